@@ -1,0 +1,362 @@
+"""Seeded synthetic workload generators shared by the oracle and the GPU path.
+
+This module only produces *descriptions*: gate lists (kind name, qubits,
+parameter slots, fixed angles), parameter arrays, Pauli structures and
+weights, and serving request streams.  It contains none of the method's
+arithmetic: no gate matrices, no contraction, no expectation values.  Both
+``oracle/`` and ``paper_2205_10091_amd`` translate these descriptions on their
+own.
+
+Conventions (paper, section "Circuits and gates / Preliminaries"):
+qubit 0 is the leftmost, most significant position of a bitstring; a Pauli
+structure is a length-n vector with 0=I, 1=X, 2=Y, 3=Z (section "Pauli
+structures and weights").
+
+Random numbers follow ``numpy.random.default_rng`` (PCG64).  Angles are drawn
+in float64 and rounded to float32; both sides consume those same rounded
+values so that input rounding does not enter parity errors.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+# Gate kinds understood by both sides.  The number of qubits and of angle
+# arguments is part of the description; the matrices are not.
+GATE_ARITY = {
+    "h": (1, 0), "x": (1, 0), "y": (1, 0), "z": (1, 0), "s": (1, 0),
+    "sqrt_x": (1, 0), "sqrt_y": (1, 0), "sqrt_w": (1, 0),
+    "rx": (1, 1), "ry": (1, 1), "rz": (1, 1),
+    "u1": (1, 0),
+    "cnot": (2, 0), "cz": (2, 0),
+    "rzz": (2, 1), "rxx": (2, 1), "ryy": (2, 1),
+    "fsim": (2, 2),
+    "u2": (2, 0),
+}
+
+
+@dataclass(frozen=True)
+class Gate:
+    """One gate application.
+
+    kind    : a key of GATE_ARITY.
+    qubits  : target qubits; for two-qubit gates qubits[0] is the more
+              significant index of the 4x4 matrix.
+    params  : one entry per angle argument: a slot of the caller's parameter
+              vector, or -1 to use the matching entry of ``fixed``.
+    fixed   : fixed angles used where ``params`` is -1.
+    matrix  : for "u1"/"u2" only, a complex 2x2 / 4x4 row-major matrix given
+              as a tuple of (re, im) pairs.
+    """
+    kind: str
+    qubits: Tuple[int, ...]
+    params: Tuple[int, ...] = ()
+    fixed: Tuple[float, ...] = ()
+    matrix: Optional[Tuple[Tuple[float, float], ...]] = None
+
+
+@dataclass
+class Circuit:
+    n_qubits: int
+    n_params: int
+    gates: List[Gate] = field(default_factory=list)
+    # optional geometry used by sweep orders: (row, col) of each qubit
+    coords: Optional[List[Tuple[int, int]]] = None
+
+    def add(self, kind, qubits, params=(), fixed=(), matrix=None):
+        nq, na = GATE_ARITY[kind]
+        qubits = tuple(int(q) for q in qubits)
+        if len(qubits) != nq:
+            raise ValueError(f"{kind} takes {nq} qubits")
+        params = tuple(int(p) for p in params) if params else (-1,) * na
+        fixed = tuple(float(f) for f in fixed) if fixed else (0.0,) * na
+        if len(params) != na or len(fixed) != na:
+            raise ValueError(f"{kind} takes {na} angles")
+        self.gates.append(Gate(kind, qubits, params, fixed, matrix))
+        return self
+
+
+@dataclass
+class Observable:
+    """Either an amplitude <bits|U|0...0> or a weighted Pauli sum."""
+    kind: str                          # "amplitude" or "pauli_sum"
+    bits: Optional[Tuple[int, ...]] = None
+    structures: Optional[np.ndarray] = None   # (n_terms, n_qubits) uint8
+    weights: Optional[np.ndarray] = None      # (n_terms,) float64
+
+
+def draw_angles(seed: int, shape, high: float = TWO_PI) -> np.ndarray:
+    """U[0, high) angles from default_rng(seed), rounded to float32."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, high, size=shape).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# 1D chains: parameters laid out as params[L][2][n] (slot 0 = the first
+# sub-layer applied in a layer, slot 1 = the second).
+# --------------------------------------------------------------------------
+
+def slot(layer: int, sub: int, i: int, n: int) -> int:
+    return (layer * 2 + sub) * n + i
+
+
+def chain_brickwork(n: int, layers: int) -> Circuit:
+    """Each layer: RX on every qubit, then RZZ on the bonds (i, i+1) with
+    i of the layer's parity (layer 0: even bonds)."""
+    c = Circuit(n, layers * 2 * n)
+    for l in range(layers):
+        for i in range(n):
+            c.add("rx", (i,), (slot(l, 0, i, n),))
+        for i in range(l % 2, n - 1, 2):
+            c.add("rzz", (i, i + 1), (slot(l, 1, i, n),))
+    return c
+
+
+def chain_ladder(n: int, layers: int) -> Circuit:
+    """Each layer: RZZ on every bond (0,1), (1,2), ..., (n-2,n-1), then RX
+    on every qubit (the Rzz-ladder + Rx ansatz of the TFIM VQE benchmark)."""
+    c = Circuit(n, layers * 2 * n)
+    for l in range(layers):
+        for i in range(n - 1):
+            c.add("rzz", (i, i + 1), (slot(l, 0, i, n),))
+        for i in range(n):
+            c.add("rx", (i,), (slot(l, 1, i, n),))
+    return c
+
+
+def tfim_zz_x(n: int, g: float = 1.0) -> Observable:
+    """E = sum_i Z_i Z_{i+1} + g sum_i X_i on an open chain.  Terms are
+    ordered ZZ bonds 0..n-2, then X sites 0..n-1 (2n-1 terms)."""
+    s = np.zeros((2 * n - 1, n), dtype=np.uint8)
+    w = np.zeros(2 * n - 1, dtype=np.float64)
+    for i in range(n - 1):
+        s[i, i] = 3
+        s[i, i + 1] = 3
+        w[i] = 1.0
+    for i in range(n):
+        s[n - 1 + i, i] = 1
+        w[n - 1 + i] = g
+    return Observable("pauli_sum", structures=s, weights=w)
+
+
+def tfim_zz_x_grid(rows: int, cols: int, g: float = 1.0) -> Observable:
+    """Nearest-neighbour ZZ on a rows x cols grid (horizontal bonds first,
+    row-major, then vertical) plus g X on every site."""
+    n = rows * cols
+    terms, wts = [], []
+    for r in range(rows):
+        for c in range(cols - 1):
+            v = np.zeros(n, np.uint8)
+            v[r * cols + c] = 3
+            v[r * cols + c + 1] = 3
+            terms.append(v)
+            wts.append(1.0)
+    for r in range(rows - 1):
+        for c in range(cols):
+            v = np.zeros(n, np.uint8)
+            v[r * cols + c] = 3
+            v[(r + 1) * cols + c] = 3
+            terms.append(v)
+            wts.append(1.0)
+    for q in range(n):
+        v = np.zeros(n, np.uint8)
+        v[q] = 1
+        terms.append(v)
+        wts.append(g)
+    return Observable("pauli_sum", structures=np.array(terms, np.uint8),
+                      weights=np.array(wts, np.float64))
+
+
+def pauli_string(n: int, x=(), y=(), z=(), weight: float = 1.0) -> Observable:
+    v = np.zeros((1, n), np.uint8)
+    for q in x:
+        v[0, q] = 1
+    for q in y:
+        v[0, q] = 2
+    for q in z:
+        v[0, q] = 3
+    return Observable("pauli_sum", structures=v, weights=np.array([weight]))
+
+
+def amplitude(n: int, bits: Optional[Sequence[int]] = None) -> Observable:
+    b = tuple(int(x) for x in bits) if bits is not None else (0,) * n
+    if len(b) != n:
+        raise ValueError("bitstring length must equal n")
+    return Observable("amplitude", bits=b)
+
+
+# --------------------------------------------------------------------------
+# 2D grid with fSim entanglers.
+# --------------------------------------------------------------------------
+
+def grid_edges(rows: int, cols: int, colouring: int):
+    """Colouring 0: horizontal (r,c)-(r,c+1), c even; 1: horizontal, c odd;
+    2: vertical (r,c)-(r+1,c), r even; 3: vertical, r odd."""
+    e = []
+    if colouring in (0, 1):
+        for r in range(rows):
+            for c in range(colouring, cols - 1, 2):
+                e.append((r * cols + c, r * cols + c + 1))
+    else:
+        par = colouring - 2
+        for r in range(par, rows - 1, 2):
+            for c in range(cols):
+                e.append((r * cols + c, (r + 1) * cols + c))
+    return e
+
+
+def grid_fsim(rows: int, cols: int, depth: int, struct_seed: int) -> Circuit:
+    """Cycle k: a random gate from {sqrt_x, sqrt_y, sqrt_w} on every qubit
+    (uniform, independent), then fSim on the edges of colouring k mod 4.
+    fSim gate number j uses parameter slots (2j, 2j+1) for (theta, phi)."""
+    n = rows * cols
+    rng = np.random.default_rng(struct_seed)
+    kinds = ("sqrt_x", "sqrt_y", "sqrt_w")
+    n_fsim = sum(len(grid_edges(rows, cols, k % 4)) for k in range(depth))
+    c = Circuit(n, 2 * n_fsim,
+                coords=[(q // cols, q % cols) for q in range(n)])
+    j = 0
+    for k in range(depth):
+        choice = rng.integers(0, 3, size=n)
+        for q in range(n):
+            c.add(kinds[int(choice[q])], (q,))
+        for (a, b) in grid_edges(rows, cols, k % 4):
+            c.add("fsim", (a, b), (2 * j, 2 * j + 1))
+            j += 1
+    return c
+
+
+def grid_ladder(rows: int, cols: int, layers: int) -> Circuit:
+    """RX/RZZ ansatz on a grid: each layer RZZ on all horizontal then all
+    vertical nearest-neighbour bonds, then RX on every qubit.  Slots:
+    one per gate, in application order."""
+    n = rows * cols
+    bonds = grid_edges(rows, cols, 0) + grid_edges(rows, cols, 1) + \
+        grid_edges(rows, cols, 2) + grid_edges(rows, cols, 3)
+    per_layer = len(bonds) + n
+    c = Circuit(n, layers * per_layer,
+                coords=[(q // cols, q % cols) for q in range(n)])
+    p = 0
+    for _ in range(layers):
+        for (a, b) in bonds:
+            c.add("rzz", (a, b), (p,))
+            p += 1
+        for q in range(n):
+            c.add("rx", (q,), (p,))
+            p += 1
+    return c
+
+
+# --------------------------------------------------------------------------
+# The five workload shapes.
+# --------------------------------------------------------------------------
+
+def workload_forward_chain(seed: int = 1):
+    """10 qubits, open chain, brickwork depth 4; outputs <Z0 Z1> and the
+    all-zeros amplitude."""
+    n, L = 10, 4
+    circ = chain_brickwork(n, L)
+    params = draw_angles(seed, (L, 2, n)).reshape(-1)
+    return circ, params, pauli_string(n, z=(0, 1)), amplitude(n)
+
+
+def workload_vqe_chain(seed: int = 2, n: int = 20, layers: int = 6,
+                       g: float = 1.0):
+    """20-qubit TFIM energy with the Rzz-ladder + Rx ansatz, 240 slots."""
+    circ = chain_ladder(n, layers)
+    params = draw_angles(seed, (layers, 2, n)).reshape(-1)
+    return circ, params, tfim_zz_x(n, g)
+
+
+def workload_grid_amplitude(rows: int = 6, cols: int = 6, depth: int = 8,
+                            struct_seed: int = 3, param_seed: int = 4):
+    """Grid of fSim cycles; amplitude <0^n|U|0^n>; fSim angles U[0, pi)."""
+    circ = grid_fsim(rows, cols, depth, struct_seed)
+    params = draw_angles(param_seed, (circ.n_params,), high=math.pi)
+    return circ, params, amplitude(circ.n_qubits)
+
+
+def workload_batched_vqe(batch: int = 1024, seed: int = 5, n: int = 20,
+                         layers: int = 6, g: float = 1.0):
+    """The VQE chain with `batch` independent parameter vectors."""
+    circ = chain_ladder(n, layers)
+    params = draw_angles(seed, (batch, layers, 2, n)).reshape(batch, -1)
+    return circ, params, tfim_zz_x(n, g)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    circuit: Circuit
+    observable: Observable
+    params: np.ndarray
+    want_grad: bool
+    shape: str            # "chain" or "grid"
+    depth: int
+
+
+def serving_requests(n_requests: int, rate_hz: float, seed: int = 6,
+                     max_width: int = 64, max_chain_shallow: int = 600,
+                     depth_range=(2, 10)) -> List[Request]:
+    """Poisson arrivals; each request a chain or grid RX/RZZ circuit with
+    seeded parameters, TFIM energy with g ~ U[0.5, 1.5], gradient with
+    probability 1/2.  Chains of depth 2 may be up to `max_chain_shallow`
+    qubits wide; everything else 8..max_width."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate_hz)
+        depth = int(rng.integers(depth_range[0], depth_range[1] + 1))
+        g = float(rng.uniform(0.5, 1.5))
+        want_grad = bool(rng.random() < 0.5)
+        if rng.random() < 0.5:
+            hi = max_chain_shallow if depth == 2 else max_width
+            n = int(rng.integers(8, hi + 1))
+            circ = chain_ladder(n, depth)
+            obs = tfim_zz_x(n, g)
+            shape = "chain"
+        else:
+            n = int(rng.integers(8, max_width + 1))
+            r = int(math.isqrt(n))
+            c = n // r
+            circ = grid_ladder(r, c, depth)
+            obs = tfim_zz_x_grid(r, c, g)
+            shape = "grid"
+        pseed = int(rng.integers(0, 2**31 - 1))
+        params = draw_angles(pseed, (circ.n_params,))
+        out.append(Request(rid, t, circ, obs, params, want_grad, shape, depth))
+    return out
+
+
+def random_circuit(n: int, n_gates: int, seed: int,
+                   kinds: Optional[Sequence[str]] = None) -> Circuit:
+    """A random circuit over the given gate kinds (default: all kinds).
+    Every parameterised angle gets its own slot; u1/u2 get random complex
+    matrices (not necessarily unitary)."""
+    rng = np.random.default_rng(seed)
+    kinds = list(kinds) if kinds is not None else list(GATE_ARITY)
+    c = Circuit(n, 0)
+    p = 0
+    for _ in range(n_gates):
+        k = kinds[int(rng.integers(0, len(kinds)))]
+        nq, na = GATE_ARITY[k]
+        if nq > n:
+            continue
+        qs = tuple(int(q) for q in rng.choice(n, size=nq, replace=False))
+        params = tuple(range(p, p + na))
+        p += na
+        mat = None
+        if k in ("u1", "u2"):
+            d = 2 ** nq
+            m = rng.normal(size=(d * d, 2)) / math.sqrt(d)
+            mat = tuple((float(a), float(b)) for a, b in m)
+        c.gates.append(Gate(k, qs, params, (0.0,) * na, mat))
+    c.n_params = p
+    return c
