@@ -1,0 +1,387 @@
+/*
+ * tcx.h - C ABI of an MI355X (gfx950) tensor-network circuit contraction
+ * executor.
+ *
+ * What it computes (arXiv:2205.10091, TensorCircuit):
+ *   - section "Tensor network engine": a parameterised circuit's diagram is a
+ *     tensor network (gate tensors plus product-state boundary vectors); an
+ *     amplitude or an expectation value is obtained by contracting its edges
+ *     until a single node remains, in an order chosen by a path finder, and
+ *     the contraction itself is a sequence of pairwise einsum/matmul steps
+ *     ("Schematic of the quantum circuit components" figure: path search
+ *     first, backend contraction second);
+ *   - section "Basic circuits and outputs": amplitudes <bits|U|0...0>;
+ *   - sections "Pauli string expectation" and "Explicit loop with
+ *     c.expectation_ps": E = sum_j alpha_j <psi|P_j|psi>, each Pauli term
+ *     contracted as one network (the reuse=False form of section "Custom
+ *     contraction settings");
+ *   - section "Gradients, optimization and variational algorithms": dE/dtheta;
+ *   - section "vmap and vectorized_value_and_grad / Batched VQE": many
+ *     parameter vectors evaluated against one compiled plan.
+ *
+ * Conventions.  Qubit 0 is the most significant position of a bitstring
+ * and of a gate's matrix index (section "Circuits and gates /
+ * Preliminaries").  Rotation gates are R_G(t) = exp(-i t G / 2).  Complex
+ * numbers crossing the ABI are pairs of doubles (re, im).
+ *
+ * Errors.  Every call returns a tc_status.  Outputs are written only when
+ * TC_OK is returned.  tc_last_error() gives a thread-local message for the
+ * most recent failure on the calling thread.  No C++ exception crosses the
+ * ABI.
+ *
+ * Ownership.  Objects returned through an out-pointer (tc_network, tc_path,
+ * tc_plan, tc_server) belong to the library and are released with the
+ * matching *_free call; freeing NULL is a no-op.  Caller arrays passed in
+ * (circuits, observables, parameters) are copied or consumed before the call
+ * returns unless stated otherwise.
+ *
+ * Threads.  Distinct objects may be used from distinct threads.  A plan
+ * accepts one contraction call at a time (TC_ERR_BUSY otherwise).
+ */
+#ifndef TCX_H
+#define TCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TC_OK = 0,
+  TC_ERR_INVALID_ARG = 1,   /* malformed input: bad qubit, size, pointer */
+  TC_ERR_UNSUPPORTED = 2,   /* unknown gate kind, option not available   */
+  TC_ERR_OUT_OF_MEMORY = 3, /* host or device allocation failed          */
+  TC_ERR_TOO_LARGE = 4,     /* plan needs more device memory than allowed */
+  TC_ERR_DEVICE = 5,        /* a HIP call failed                         */
+  TC_ERR_BUSY = 6,          /* object already has a call in flight       */
+  TC_ERR_STATE = 7          /* call not valid in the object's state      */
+} tc_status;
+
+const char* tc_status_string(tc_status s);
+const char* tc_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t tc_version(void);
+
+/* ------------------------------------------------------------------ circuit
+ * Gate kinds (section "Circuits and gates": standard gates, exp1-type
+ * rotations, arbitrary unitaries).  Matrices are indexed with q[0] the
+ * more significant qubit.  Not in the paper, standard definitions:
+ *   SQRT_X/Y/W = ((1+i)/2) I + ((1-i)/2) G with W = (X+Y)/sqrt 2;
+ *   FSIM(t, p) = [[1,0,0,0],[0,cos t,-i sin t,0],[0,-i sin t,cos t,0],
+ *                 [0,0,0,exp(-i p)]].
+ */
+typedef enum {
+  TC_GATE_H = 0, TC_GATE_X = 1, TC_GATE_Y = 2, TC_GATE_Z = 3, TC_GATE_S = 4,
+  TC_GATE_SQRT_X = 5, TC_GATE_SQRT_Y = 6, TC_GATE_SQRT_W = 7,
+  TC_GATE_RX = 8, TC_GATE_RY = 9, TC_GATE_RZ = 10,
+  TC_GATE_U1 = 11,                       /* caller 2x2 matrix             */
+  TC_GATE_CNOT = 12, TC_GATE_CZ = 13,
+  TC_GATE_RZZ = 14, TC_GATE_RXX = 15, TC_GATE_RYY = 16,
+  TC_GATE_FSIM = 17,                     /* two angles (theta, phi)       */
+  TC_GATE_U2 = 18                        /* caller 4x4 matrix             */
+} tc_gate_kind;
+
+typedef struct {
+  int32_t kind;        /* tc_gate_kind                                     */
+  int32_t q[2];        /* target qubits; q[1] ignored for 1-qubit gates    */
+  int32_t param[2];    /* slot in the parameter vector per angle, or -1    */
+  double fixed[2];     /* angle used where param[i] == -1                  */
+  const double* matrix;/* U1: 8 doubles, U2: 32 doubles, (re,im) pairs,
+                          row-major; NULL otherwise.  Copied at build.     */
+} tc_gate;
+
+typedef struct {
+  int32_t n_qubits;    /* 1 .. 4096                                        */
+  int32_t n_params;    /* length of one parameter vector (>= 0)            */
+  int32_t n_gates;
+  const tc_gate* gates;/* applied in order to |0...0>                      */
+} tc_circuit;
+
+/* --------------------------------------------------------------- observable
+ * AMPLITUDE: <bits|U|0...0> (section "Basic circuits and outputs").
+ * PAULI_SUM: sum_j weights[j] <psi|P_j|psi> with structure vectors
+ * structures[j*n_qubits + q] in {0=I,1=X,2=Y,3=Z} (section "Pauli structures
+ * and weights").  The weighted sum is reduced in FP64 in term order.
+ */
+typedef enum { TC_OBS_AMPLITUDE = 0, TC_OBS_PAULI_SUM = 1 } tc_obs_kind;
+
+typedef struct {
+  int32_t kind;               /* tc_obs_kind                               */
+  const uint8_t* bits;        /* AMPLITUDE: n_qubits entries in {0,1}, or
+                                 NULL for all zeros                        */
+  int32_t n_terms;            /* PAULI_SUM: number of terms (>= 1)         */
+  const uint8_t* structures;  /* PAULI_SUM: n_terms * n_qubits             */
+  const double* weights;      /* PAULI_SUM: n_terms                        */
+} tc_observable;
+
+/* ------------------------------------------------------------------ network
+ * tc_build_network: translate circuit + observable into one tensor network
+ * per term (section "Tensor network engine").  An expectation term is the
+ * network <0|U^dagger P_j U|0>: ket gate tensors, Pauli matrices on the
+ * measured qubits, and entrywise-conjugated gate tensors for the bra.
+ *
+ * Options:
+ *   split_2q   split RZZ/RXX/RYY/CNOT/CZ into two three-leg tensors joined
+ *              by a bond of dimension 2 (exact rank-2 operator-Schmidt
+ *              form; section "Very large circuit simulation", gate split);
+ *   lightcone  drop gates outside the backward light cone of each Pauli
+ *              term (exact: a gate that does not touch the support of the
+ *              conjugated operator cancels with its mirror image; a run of
+ *              consecutive diagonal gates (Z, S, RZ, CZ, RZZ) commutes, so
+ *              only its gates touching the support at the run's end are
+ *              kept and the support grows by their qubits only; U1/U2
+ *              matrices may be non-unitary and are always kept);
+ *   absorb_1q  before path search, contract every tensor of rank <= 2 into
+ *              a neighbour (section "Custom contraction settings",
+ *              preprocessing=True).  Applied by tc_greedy_path.
+ * A NULL opts pointer means {split_2q=1, lightcone=1, absorb_1q=1}.
+ * Errors: INVALID_ARG for out-of-range or repeated qubits, bad structure
+ * values, negative sizes, param slots >= n_params; UNSUPPORTED for unknown
+ * gate kinds.
+ */
+typedef struct tc_network tc_network;
+
+typedef struct {
+  int32_t split_2q;
+  int32_t lightcone;
+  int32_t absorb_1q;
+} tc_build_opts;
+
+tc_status tc_build_network(const tc_circuit* circuit,
+                           const tc_observable* observable,
+                           const tc_build_opts* opts, tc_network** out);
+void tc_network_free(tc_network* net);
+
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_params;
+  int32_t n_terms;        /* 1 for an amplitude                            */
+  int32_t max_leaves;     /* largest number of leaf tensors of a term      */
+  int64_t total_leaves;
+} tc_network_info;
+
+tc_status tc_network_info_get(const tc_network* net, tc_network_info* out);
+
+/* Leaf tensors of one term, for inspection and host-side checks.  For leaf
+ * i: kind[i] (0 gate, 1 |0> vector, 2 <bit| vector, 3 Pauli matrix),
+ * gate[i] (gate index, or the bit / Pauli value for kinds 1-3), part[i]
+ * (0 whole gate, 1 first split factor, 2 second split factor), conj[i] (1
+ * for bra copies), rank[i] and legs[4*i + r] (leg labels, most significant
+ * first).  Element e of a leaf is the entry whose r-th leg has value
+ * (e >> (rank-1-r)) & 1.  Whole gates have legs (out..., in...); split
+ * factors have legs (bond, out, in) and equal P_k (first) and c_k P_k
+ * (second) with P_0 = I, P_1 = the gate's Pauli (Z for CZ, X for CNOT's
+ * target) and c_k from the gate.  Arrays have max_leaves entries (legs:
+ * 4*max_leaves); *n_leaves receives the count. */
+tc_status tc_network_term_leaves(const tc_network* net, int32_t term,
+                                 int32_t* n_leaves, int32_t* kind,
+                                 int32_t* gate, int32_t* part, int32_t* conj,
+                                 int32_t* rank, int32_t* legs);
+
+/* --------------------------------------------------------------------- path
+ * tc_greedy_path: host-side pairwise greedy path per term (section "Custom
+ * contraction settings": the default greedy finder; FLOPs / WRITE / SIZE
+ * metrics).  Each step contracts the pair of tensors sharing a leg that
+ * minimises size(out) - size(a) - size(b); ties go to fewer flops, then to
+ * smaller ids.  With n_trials > 1 each further trial perturbs that cost with
+ * seeded Gumbel noise of the given temperature and the tree with the best
+ * score is kept.  Deterministic for a fixed seed.
+ *
+ * score: 0 flops, 1 write, 2 size, 3 combo = flops + 64 * write (the
+ * default combination named in the contractor table of that section).
+ * flops count 8 real operations per complex multiply-add.
+ */
+typedef struct tc_path tc_path;
+
+typedef enum { TC_SCORE_FLOPS = 0, TC_SCORE_WRITE = 1, TC_SCORE_SIZE = 2,
+               TC_SCORE_COMBO = 3 } tc_score;
+
+typedef struct {
+  uint64_t seed;
+  int32_t n_trials;      /* >= 1                                          */
+  int32_t score;         /* tc_score                                      */
+  double temperature;    /* noise scale for trials after the first        */
+} tc_path_opts;
+
+tc_status tc_greedy_path(const tc_network* net, const tc_path_opts* opts,
+                         tc_path** out);
+/* A path from caller SSA pairs for one term: pairs[2*s], pairs[2*s+1] are
+ * ids of tensors alive before step s (leaves 0..n_leaves-1, step s creates
+ * id n_leaves+s); n_steps must be n_leaves-1.  Other terms keep the greedy
+ * path of `base` (required, same network). */
+tc_status tc_path_replace_term(tc_path* base, int32_t term,
+                               const int32_t* pairs, int32_t n_steps);
+void tc_path_free(tc_path* path);
+
+typedef struct {
+  double log10_flops;    /* over all terms                                */
+  double log2_write;     /* total elements written by contraction steps   */
+  double log2_size;      /* largest intermediate (elements)               */
+  double flops;
+  double write;
+  double size;
+  int32_t n_steps;       /* pairwise contractions over all terms          */
+  int32_t max_depth;     /* deepest tree                                  */
+} tc_path_stats;
+
+tc_status tc_path_stats_get(const tc_path* path, int32_t term /* -1: all */,
+                            tc_path_stats* out);
+/* The SSA pairs of one term (2*(n_leaves-1) ints). */
+tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
+                             int32_t* pairs, int32_t* n_steps);
+
+/* --------------------------------------------------------------------- plan
+ * tc_plan_create compiles network + path into device work: leaf materialisation
+ * from parameters, the contraction tree as level-ordered batched kernels
+ * (small nodes: a gather-contraction kernel; wide nodes: coalesced permute
+ * plus MFMA complex GEMM), the FP64 root reduction and, with want_grad, the
+ * reverse sweep.  Host-only: no device memory is touched until
+ * tc_plan_bind (or the first contraction call, which binds with
+ * library-allocated memory).
+ *
+ *   precision   0 = complex64 with FP32 MFMA (default); 1 = split-BF16
+ *               (hi+lo, three BF16 MFMA products, FP32 accumulation) on
+ *               wide nodes, complex64 elsewhere;
+ *   batch       number of parameter vectors B evaluated per call (>= 1);
+ *   want_grad   keep intermediates and compile the reverse sweep;
+ *   mem_budget_bytes  0 = no limit; otherwise TOO_LARGE if the workspace
+ *               exceeds it;
+ *   stream      hipStream_t to run on (NULL = the library's own stream).
+ */
+typedef struct tc_plan tc_plan;
+
+typedef enum { TC_PREC_C64 = 0, TC_PREC_BF16X3 = 1 } tc_precision;
+
+typedef struct {
+  int32_t precision;
+  int32_t batch;
+  int32_t want_grad;
+  int32_t device;            /* HIP device ordinal                        */
+  uint64_t mem_budget_bytes;
+  void* stream;              /* hipStream_t                               */
+} tc_plan_opts;
+
+tc_status tc_plan_create(const tc_network* net, const tc_path* path,
+                         const tc_plan_opts* opts, tc_plan** out);
+void tc_plan_free(tc_plan* plan);
+
+typedef struct {
+  double flops;              /* forward contraction flops (8 per c-MAC),
+                                times batch where batched               */
+  double alg_bytes;          /* forward algorithmic bytes: operands read
+                                plus results written, once per node     */
+  double grad_flops;         /* reverse-sweep flops (0 without grad)    */
+  double grad_alg_bytes;
+  uint64_t workspace_bytes;  /* device memory the plan needs             */
+  uint64_t peak_tensor_bytes;/* largest single intermediate              */
+  int32_t n_nodes;           /* contraction steps over all terms        */
+  int32_t n_levels;          /* forward launch levels                   */
+  int32_t n_gemm_nodes;      /* nodes sent to the MFMA GEMM path         */
+  int32_t n_launches;        /* kernels per forward call                 */
+  int32_t n_grad_launches;
+  int32_t batch;
+  int32_t n_params;
+  int32_t n_terms;
+} tc_plan_info;
+
+tc_status tc_plan_info_get(const tc_plan* plan, tc_plan_info* out);
+
+/* Bind device memory: `workspace` must be a device pointer with at least
+ * workspace_bytes bytes, 256-byte aligned, owned by the caller and kept
+ * alive until tc_plan_free; NULL asks the library to allocate (hipMalloc)
+ * and own it.  Uploads the op tables and captures the launch sequence as a
+ * HIP graph.  TOO_LARGE if the budget is exceeded, DEVICE on HIP errors. */
+tc_status tc_plan_bind(tc_plan* plan, void* workspace, uint64_t bytes);
+
+/* ----------------------------------------------------------------- contract
+ * tc_contract: params is a DEVICE pointer to B*n_params floats (row b =
+ * parameter vector b).  out is a HOST pointer to 2*B doubles receiving
+ * (re, im) of sum_j alpha_j T_j for each b (the amplitude itself for
+ * AMPLITUDE).  Synchronous on the plan's stream.
+ *
+ * tc_contract_grad: requires want_grad.  value (HOST, B doubles) receives
+ * Re E; grad (HOST, B*n_params doubles) receives dE/dparams, slots no gate
+ * uses are exactly 0.  Either may be NULL to skip its copy.
+ *
+ * *_device variants write to DEVICE buffers of the same shapes (out_dev:
+ * 2*B doubles; value_dev: B doubles; grad_dev: B*n_params doubles) and do
+ * not synchronise; the caller orders later work on the plan's stream.
+ */
+tc_status tc_contract(tc_plan* plan, const float* params, double* out);
+tc_status tc_contract_grad(tc_plan* plan, const float* params, double* value,
+                           double* grad);
+tc_status tc_contract_device(tc_plan* plan, const float* params,
+                             double* out_dev);
+tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
+                                  double* value_dev, double* grad_dev);
+
+/* Profiling.  Runs the plan's launch sequence eagerly (not as a graph)
+ * `reps` times with HIP events around every launch on the plan's stream;
+ * params is a DEVICE pointer as for tc_contract.  For launch i <
+ * *n_launches (at most `cap` are written) it reports the kernel class
+ * kinds[i] (0 leaf materialisation, 1 gather contraction, 2 wavefront
+ * gather contraction, 3 MFMA GEMM, 4 FP64 root sum, 5 FP64 gradient sum),
+ * the mean duration ms[i], and the launch's algorithmic flops[i] and
+ * bytes[i] (operands read once plus results written once).  which: 0 the
+ * forward sequence, 1 forward plus reverse sweep (needs want_grad). */
+tc_status tc_plan_profile(tc_plan* plan, const float* params, int32_t which,
+                          int32_t reps, int32_t cap, int32_t* n_launches,
+                          int32_t* kinds, double* ms, double* flops,
+                          double* bytes);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous-batching request loop (not a method of the paper: a serving
+ * form of the same executor).  Requests are admitted while the sum of their
+ * workspace sizes stays within pool_bytes and fewer than max_active are
+ * live; admitted requests advance one contraction level per engine step and
+ * the steps of all live requests are launched together, so requests that
+ * arrive while others run join the next step.  Plans are cached by circuit
+ * structure and observable; each request gets its own region of the pool.
+ *
+ *   tc_serve_submit  copies the request; params are HOST floats
+ *                    (n_params); returns an id.  TOO_LARGE if the request
+ *                    alone exceeds max_request_bytes (it is not queued).
+ *   tc_serve_step    admits what fits, launches one step for every live
+ *                    request, and collects finished ones; *n_live receives
+ *                    the number still queued or running.
+ *   tc_serve_result  TC_OK with value (Re E), value_im and, if requested,
+ *                    grad (HOST, n_params doubles) once finished;
+ *                    TC_ERR_BUSY while pending.  A fetched result is
+ *                    released.
+ */
+typedef struct tc_server tc_server;
+
+typedef struct {
+  int32_t device;
+  uint64_t pool_bytes;        /* device memory shared by live requests    */
+  uint64_t max_request_bytes; /* per-request workspace cap                */
+  int32_t max_active;         /* live request slots                       */
+  int32_t path_trials;        /* greedy trials per new structure          */
+  void* stream;               /* hipStream_t, NULL = own stream           */
+} tc_serve_opts;
+
+typedef struct {
+  int64_t id;
+  double value;
+  double value_im;
+  double submit_to_done_s;    /* library-measured latency                 */
+  int32_t want_grad;
+  int32_t status;             /* tc_status of the request                 */
+} tc_serve_result;
+
+tc_status tc_serve_create(const tc_serve_opts* opts, tc_server** out);
+tc_status tc_serve_submit(tc_server* srv, const tc_circuit* circuit,
+                          const tc_observable* observable,
+                          const float* params, int32_t want_grad,
+                          int64_t* id);
+tc_status tc_serve_step(tc_server* srv, int32_t* n_live);
+tc_status tc_serve_result_get(tc_server* srv, int64_t id,
+                              tc_serve_result* out, double* grad);
+void tc_serve_free(tc_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCX_H */

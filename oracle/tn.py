@@ -16,6 +16,8 @@ never with a path finder:
   they sit on, where a two-qubit gate sits on its later qubit; a chain's
   column is its qubit index;
 * ``order="row"``: the same with rows and columns exchanged;
+* ``order="col2"``/``"row2"``: as "col"/"row", but the multi-qubit tensors
+  a qubit owns are absorbed before that qubit's single-qubit tensors;
 * ``order="time"``: tensors in the order they were created.
 
 The expectation <psi|P|psi> is built as one network: the ket (|0> vectors,
@@ -24,6 +26,12 @@ entrywise complex conjugate of the ket network whose open legs meet the
 Pauli matrices' output legs.  ``split=True`` replaces every two-qubit gate
 by the two factors of its operator-Schmidt decomposition (numpy SVD, exact
 rank), as in the paper's split option without truncation.
+
+Where a sweep's largest intermediate is too big, ``max_elements`` lets the
+fold *slice*: labels are fixed one value at a time and the sliced networks'
+scalars are summed (the plain sum over that index, written out).  Labels are
+chosen one by one, each time the one whose removal lowers the sweep's peak
+the most, until the peak fits.
 """
 from __future__ import annotations
 
@@ -128,6 +136,14 @@ class _Builder:
 
 
 def _sort_key(order):
+    # "col2"/"row2": like "col"/"row", but on each qubit the multi-qubit
+    # tensors it owns (their other legs are already in the accumulator) are
+    # absorbed before its single-qubit tensors, which keeps the growth while
+    # a qubit is processed to one leg.
+    if order == "col2":
+        return lambda t: (t.key[1], t.key[0], t.data.ndim <= 2, t.key[2], t.key[3])
+    if order == "row2":
+        return lambda t: (t.key[0], t.key[1], t.data.ndim <= 2, t.key[2], t.key[3])
     if order == "col":
         return lambda t: (t.key[1], t.key[0], t.key[2], t.key[3])
     if order == "row":
@@ -211,16 +227,78 @@ def expectation_network(circ, params, structure, split=False) -> List[T]:
     return b.tensors
 
 
+def _peak_without(tensors: List[T], removed) -> int:
+    dims = {}
+    for t in tensors:
+        for l, d in zip(t.labels, t.data.shape):
+            dims[l] = d.bit_length() - 1
+    acc = set()
+    peak = 0
+    for t in tensors:
+        ls = set(t.labels) - removed
+        shared = acc & ls
+        acc = (acc | ls) - shared
+        peak = max(peak, sum(dims[l] for l in acc))
+    return peak
+
+
+def choose_slices(tensors: List[T], max_elements: int, max_slices: int = 16):
+    """Labels to slice so that the fold's peak fits max_elements."""
+    removed = set()
+    labels = sorted({l for t in tensors for l in t.labels})
+    limit = max_elements.bit_length() - 1
+    while _peak_without(tensors, removed) > limit:
+        if len(removed) >= max_slices:
+            raise MemoryError("too many slices needed")
+        best = min((l for l in labels if l not in removed),
+                   key=lambda l: (_peak_without(tensors, removed | {l}), l))
+        removed.add(best)
+    return sorted(removed)
+
+
+def _fix(tensors: List[T], label: int, value: int) -> List[T]:
+    out = []
+    for t in tensors:
+        if label in t.labels:
+            ax = t.labels.index(label)
+            out.append(T(np.take(t.data, value, axis=ax),
+                         t.labels[:ax] + t.labels[ax + 1:], t.key))
+        else:
+            out.append(t)
+    return out
+
+
+def fold_sliced(tensors: List[T], max_elements: int, progress=None) -> complex:
+    """Sum over all values of the chosen slice labels of the left fold."""
+    sl = choose_slices(tensors, max_elements)
+    if not sl:
+        return _fold(tensors, max_elements)
+    dims = {}
+    for t in tensors:
+        for l, d in zip(t.labels, t.data.shape):
+            dims[l] = d
+    total = 0j
+    shape = [dims[l] for l in sl]
+    for idx in np.ndindex(*shape):
+        ts = tensors
+        for l, v in zip(sl, idx):
+            ts = _fix(ts, l, v)
+        total += _fold(ts, max_elements)
+        if progress is not None:
+            progress(idx, shape)
+    return total
+
+
 def amplitude(circ, params, bits=None, order="col", split=False,
-              max_elements=1 << 27) -> complex:
+              max_elements=1 << 27, progress=None) -> complex:
     ts = amplitude_network(circ, params, bits, split)
-    return _fold(sorted(ts, key=_sort_key(order)), max_elements)
+    return fold_sliced(sorted(ts, key=_sort_key(order)), max_elements, progress)
 
 
 def expectation(circ, params, structure, order="col", split=False,
                 max_elements=1 << 27) -> complex:
     ts = expectation_network(circ, params, structure, split)
-    return _fold(sorted(ts, key=_sort_key(order)), max_elements)
+    return fold_sliced(sorted(ts, key=_sort_key(order)), max_elements)
 
 
 def energy(circ, params, obs, order="col", split=False,

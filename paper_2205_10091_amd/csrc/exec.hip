@@ -1,0 +1,565 @@
+// Device executor: kernels for one plan, workspace binding, HIP-graph
+// capture, and the plan / contraction entry points of the C ABI.
+//
+// Paper, section "Tensor network engine" and the workflow figure: after the
+// path is fixed, the contraction is a sequence of pairwise tensor
+// contractions run by the backend; JIT (section "Gradients, optimization and
+// variational algorithms") compiles that sequence once and replays it.
+// Here the sequence is level-ordered launches of hand-written kernels,
+// captured once into a HIP graph and replayed per call with new
+// parameters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gates.h"
+#include "gemm.h"
+#include "plan.h"
+
+struct tc_network;
+struct tc_path;
+
+namespace tcx {
+const Network& network_of(const tc_network* n);
+const Path& path_of(const tc_path* p);
+}  // namespace tcx
+
+struct tc_plan {
+  tcx::Plan p;
+};
+
+namespace tcx {
+
+// ------------------------------------------------------------------ kernels
+
+template <typename T>
+__device__ __forceinline__ uint32_t find_item(const T* __restrict__ items, uint32_t n,
+                                              uint64_t w) {
+  // largest i with items[i].work0 <= w (items sorted by work0, items[0].work0 == 0)
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (items[mid].work0 <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
+  acc.re = fmaf(a.x, b.x, acc.re);
+  acc.re = fmaf(-a.y, b.y, acc.re);
+  acc.im = fmaf(a.x, b.y, acc.im);
+  acc.im = fmaf(a.y, b.x, acc.im);
+}
+
+// Materialise every leaf tensor (gates, boundary vectors, Pauli matrices)
+// for every batch row from the parameter vectors.
+__global__ void __launch_bounds__(256) k_leaf(const DevLeaf* __restrict__ leaves,
+                                              uint32_t n_leaves,
+                                              const float* __restrict__ ftab,
+                                              const float* __restrict__ params,
+                                              int32_t n_params, float2* __restrict__ arena,
+                                              uint64_t total) {
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+       w += (uint64_t)gridDim.x * blockDim.x) {
+    const DevLeaf& L = leaves[find_item(leaves, n_leaves, w)];
+    uint64_t l = w - L.work0;
+    int e = (int)(l & ((1u << L.rank) - 1));
+    uint64_t r = l >> L.rank;
+    const float* pr = params + r * (uint64_t)n_params;
+    float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
+    float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
+    c32 v = leaf_entry(L, e, t0, t1, ftab);
+    arena[L.out + (r << L.rank) + e] = make_float2(v.re, v.im);
+  }
+}
+
+// Gather contraction: one thread per output element (row, m, n), summing K
+// products read through the index tables.
+__global__ void __launch_bounds__(256) k_gc(const DevOp* __restrict__ ops, uint32_t n_ops,
+                                            const uint32_t* __restrict__ tab,
+                                            float2* __restrict__ arena, uint64_t total) {
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+       w += (uint64_t)gridDim.x * blockDim.x) {
+    const DevOp& op = ops[find_item(ops, n_ops, w)];
+    const uint64_t l = w - op.work0;
+    const uint32_t ln = __builtin_ctz(op.N), lm = __builtin_ctz(op.M);
+    const uint32_t n = (uint32_t)(l & (op.N - 1));
+    const uint32_t m = (uint32_t)((l >> ln) & (op.M - 1));
+    const uint64_t r = l >> (ln + lm);
+    const float2* __restrict__ A = arena + op.a + r * op.a_bs + tab[op.a_m + m];
+    const float2* __restrict__ Bp = arena + op.b + r * op.b_bs + tab[op.b_n + n];
+    const uint32_t* __restrict__ ak = tab + op.a_k;
+    const uint32_t* __restrict__ bk = tab + op.b_k;
+    c32 acc = cx(0.f, 0.f);
+    const uint32_t K = op.K;
+    for (uint32_t k = 0; k < K; ++k) cfma(acc, A[ak[k]], Bp[bk[k]]);
+    arena[op.c + r * op.c_bs + tab[op.c_m + m] + tab[op.c_n + n]] =
+        make_float2(acc.re, acc.im);
+  }
+}
+
+// Gather contraction with one wavefront per output element, for long sums
+// into few outputs; lanes stride over k and reduce by butterfly shuffles.
+__global__ void __launch_bounds__(256) k_gcw(const DevOp* __restrict__ ops, uint32_t n_ops,
+                                             const uint32_t* __restrict__ tab,
+                                             float2* __restrict__ arena, uint64_t total) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t wv = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wv * 64 < total;
+       wv += waves) {
+    const uint64_t w = wv * 64;
+    const DevOp& op = ops[find_item(ops, n_ops, w)];
+    const uint64_t l = (w - op.work0) >> 6;
+    const uint32_t ln = __builtin_ctz(op.N), lm = __builtin_ctz(op.M);
+    const uint32_t n = (uint32_t)(l & (op.N - 1));
+    const uint32_t m = (uint32_t)((l >> ln) & (op.M - 1));
+    const uint64_t r = l >> (ln + lm);
+    const float2* __restrict__ A = arena + op.a + r * op.a_bs + tab[op.a_m + m];
+    const float2* __restrict__ Bp = arena + op.b + r * op.b_bs + tab[op.b_n + n];
+    const uint32_t* __restrict__ ak = tab + op.a_k;
+    const uint32_t* __restrict__ bk = tab + op.b_k;
+    c32 acc = cx(0.f, 0.f);
+    for (uint32_t k = lane; k < op.K; k += 64) cfma(acc, A[ak[k]], Bp[bk[k]]);
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.re += __shfl_xor(acc.re, off, 64);
+      acc.im += __shfl_xor(acc.im, off, 64);
+    }
+    if (lane == 0)
+      arena[op.c + r * op.c_bs + tab[op.c_m + m] + tab[op.c_n + n]] =
+          make_float2(acc.re, acc.im);
+  }
+}
+
+// E[b] = sum_j alpha_j T_j[b] in FP64, terms in order.
+__global__ void k_root(const DevRoot* __restrict__ roots, uint32_t n_terms,
+                       const float2* __restrict__ arena, double* __restrict__ value,
+                       uint32_t batch) {
+  uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  double re = 0.0, im = 0.0;
+  for (uint32_t j = 0; j < n_terms; ++j) {
+    const DevRoot& R = roots[j];
+    double vr = 1.0, vi = 0.0;
+    if (R.present) {
+      float2 v = arena[R.val + (uint64_t)b * R.bs];
+      vr = v.x;
+      vi = v.y;
+    }
+    re += R.weight * vr;
+    im += R.weight * vi;
+  }
+  value[2 * b] = re;
+  value[2 * b + 1] = im;
+}
+
+// grad[b][slot] = Re sum_{uses of slot} sum_e adj[e] dleaf[e]/dangle, FP64.
+__global__ void k_grad(const DevGradUse* __restrict__ uses,
+                       const uint32_t* __restrict__ slot_begin,
+                       const DevLeaf* __restrict__ leaves, const float* __restrict__ params,
+                       int32_t n_params, const float2* __restrict__ arena,
+                       double* __restrict__ grad, uint64_t total) {
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+       w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t b = w / (uint32_t)n_params;
+    const uint32_t slot = (uint32_t)(w - b * (uint32_t)n_params);
+    const float* pr = params + b * (uint64_t)n_params;
+    double acc = 0.0;
+    for (uint32_t u = slot_begin[slot]; u < slot_begin[slot + 1]; ++u) {
+      const DevGradUse& U = uses[u];
+      const DevLeaf& L = leaves[U.leaf];
+      float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
+      float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
+      const float2* a = arena + U.adj + b * U.adj_bs;
+      const int ne = 1 << L.rank;
+      for (int e = 0; e < ne; ++e) {
+        c32 d = dleaf_entry(L, e, t0, t1, U.which);
+        float2 x = a[e];
+        acc += (double)x.x * d.re - (double)x.y * d.im;
+      }
+    }
+    grad[w] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ device state
+
+struct DeviceState {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* ws = nullptr;
+  bool ws_owned = false;
+  uint64_t ws_bytes = 0;
+  WorkspaceLayout lay{};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int n_cu = 256;
+};
+
+#define HIP_CHECK(x)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) fail(TC_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static unsigned grid_for(uint64_t work, int threads, int n_cu) {
+  uint64_t g = (work + threads - 1) / threads;
+  uint64_t cap = (uint64_t)n_cu * 64;  // grid-stride beyond this
+  return (unsigned)std::max<uint64_t>(1, std::min(g, cap));
+}
+
+static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& seq) {
+  char* ws = D.ws;
+  const auto& L = D.lay;
+  const DevOp* ops = (const DevOp*)(ws + L.ops);
+  const uint32_t* tabs = (const uint32_t*)(ws + L.tabs);
+  const DevLeaf* leaves = (const DevLeaf*)(ws + L.leaves);
+  const float* ftab = (const float*)(ws + L.ftab);
+  const DevGradUse* uses = (const DevGradUse*)(ws + L.uses);
+  const uint32_t* slot_begin = (const uint32_t*)(ws + L.slot_begin);
+  const DevRoot* roots = (const DevRoot*)(ws + L.roots);
+  const float* params = (const float*)(ws + L.params);
+  double* value = (double*)(ws + L.value);
+  double* grad = (double*)(ws + L.grad);
+  float2* arena = (float2*)(ws + L.arena);
+  for (const Launch& x : seq) {
+    if (x.work == 0) continue;
+    switch (x.kind) {
+      case L_LEAF:
+        hipLaunchKernelGGL(k_leaf, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
+                           leaves, (uint32_t)P.leaves.size(), ftab, params, P.n_params, arena,
+                           x.work);
+        break;
+      case L_GC:
+        hipLaunchKernelGGL(k_gc, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
+                           ops + x.begin, x.end - x.begin, tabs, arena, x.work);
+        break;
+      case L_GCW:
+        hipLaunchKernelGGL(k_gcw, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
+                           ops + x.begin, x.end - x.begin, tabs, arena, x.work);
+        break;
+      case L_GEMM:
+        launch_gemm(ops + x.begin, x.end - x.begin, tabs, arena, x.work, P.precision,
+                    D.stream);
+        break;
+      case L_ROOT:
+        hipLaunchKernelGGL(k_root, dim3((unsigned)((x.work + 255) / 256)), dim3(256), 0,
+                           D.stream, roots, (uint32_t)P.roots.size(), arena, value,
+                           (uint32_t)P.batch);
+        break;
+      case L_GRAD:
+        hipLaunchKernelGGL(k_grad, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
+                           uses, slot_begin, leaves, params, P.n_params, arena, grad, x.work);
+        break;
+    }
+    HIP_CHECK(hipGetLastError());
+  }
+}
+
+template <typename T>
+static void upload(DeviceState& D, uint64_t off, const std::vector<T>& v) {
+  if (v.empty()) return;
+  HIP_CHECK(hipMemcpyAsync(D.ws + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice,
+                           D.stream));
+}
+
+static void release(DeviceState* D) {
+  if (!D) return;
+  // teardown: errors here cannot be reported to anyone, so they are dropped
+  (void)hipSetDevice(D->device);
+  if (D->stream) (void)hipStreamSynchronize(D->stream);
+  for (int i = 0; i < 2; ++i) {
+    if (D->exec[i]) (void)hipGraphExecDestroy(D->exec[i]);
+    if (D->graph[i]) (void)hipGraphDestroy(D->graph[i]);
+  }
+  if (D->ws_owned && D->ws) (void)hipFree(D->ws);
+  if (D->own_stream && D->stream) (void)hipStreamDestroy(D->stream);
+  delete D;
+}
+
+static void capture(const Plan& P, DeviceState& D, int which) {
+  std::vector<Launch> seq = P.fwd;
+  if (which == 1) seq.insert(seq.end(), P.bwd.begin(), P.bwd.end());
+  HIP_CHECK(hipStreamBeginCapture(D.stream, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue(P, D, seq);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(D.stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIP_CHECK(hipStreamEndCapture(D.stream, &D.graph[which]));
+  HIP_CHECK(hipGraphInstantiate(&D.exec[which], D.graph[which], nullptr, nullptr, 0));
+}
+
+void bind_plan(Plan& P, void* workspace, uint64_t bytes) {
+  if (P.dev) fail(TC_ERR_STATE, "plan is already bound");
+  auto* D = new DeviceState;
+  try {
+    D->device = P.device;
+    HIP_CHECK(hipSetDevice(P.device));
+    hipDeviceProp_t prop;
+    HIP_CHECK(hipGetDeviceProperties(&prop, P.device));
+    D->n_cu = prop.multiProcessorCount;
+    if (P.user_stream) {
+      D->stream = (hipStream_t)P.user_stream;
+    } else {
+      HIP_CHECK(hipStreamCreateWithFlags(&D->stream, hipStreamNonBlocking));
+      D->own_stream = true;
+    }
+    D->lay = workspace_layout(P);
+    if (workspace) {
+      if (bytes < D->lay.total)
+        fail(TC_ERR_INVALID_ARG, "workspace smaller than workspace_bytes");
+      if (((uintptr_t)workspace & 255) != 0) fail(TC_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+      D->ws = (char*)workspace;
+      D->ws_bytes = bytes;
+    } else {
+      hipError_t e = hipMalloc(&D->ws, D->lay.total);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(TC_ERR_OUT_OF_MEMORY, "hipMalloc of the workspace failed");
+      }
+      D->ws_owned = true;
+      D->ws_bytes = D->lay.total;
+    }
+    upload(*D, D->lay.ops, P.ops);
+    upload(*D, D->lay.tabs, P.tabs);
+    upload(*D, D->lay.leaves, P.leaves);
+    upload(*D, D->lay.ftab, P.ftab);
+    upload(*D, D->lay.uses, P.uses);
+    upload(*D, D->lay.slot_begin, P.slot_begin);
+    upload(*D, D->lay.roots, P.roots);
+    upload(*D, D->lay.arena, P.seeds);  // seeds sit at arena offset 0
+    HIP_CHECK(hipStreamSynchronize(D->stream));
+    capture(P, *D, 0);
+    if (P.want_grad) capture(P, *D, 1);
+  } catch (...) {
+    release(D);
+    throw;
+  }
+  P.dev = D;
+}
+
+struct BusyGuard {
+  std::atomic<int>& f;
+  explicit BusyGuard(std::atomic<int>& x) : f(x) {
+    int expect = 0;
+    if (!f.compare_exchange_strong(expect, 1)) fail(TC_ERR_BUSY, "plan has a call in flight");
+  }
+  ~BusyGuard() { f.store(0); }
+};
+
+static void run(Plan& P, const float* params, int which) {
+  if (!params) fail(TC_ERR_INVALID_ARG, "params is NULL");
+  if (!P.dev) bind_plan(P, nullptr, 0);
+  DeviceState& D = *P.dev;
+  HIP_CHECK(hipSetDevice(D.device));
+  uint64_t pbytes = (uint64_t)P.batch * P.n_params * sizeof(float);
+  if (pbytes)
+    HIP_CHECK(hipMemcpyAsync(D.ws + D.lay.params, params, pbytes, hipMemcpyDeviceToDevice,
+                             D.stream));
+  HIP_CHECK(hipGraphLaunch(D.exec[which], D.stream));
+}
+
+void contract(Plan& P, const float* params, double* out_host, bool device_out) {
+  BusyGuard g(P.busy);
+  run(P, params, 0);
+  DeviceState& D = *P.dev;
+  if (out_host) {
+    HIP_CHECK(hipMemcpyAsync(out_host, D.ws + D.lay.value, (uint64_t)P.batch * 16,
+                             device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             D.stream));
+  }
+  if (!device_out) HIP_CHECK(hipStreamSynchronize(D.stream));
+}
+
+void contract_grad(Plan& P, const float* params, double* value, double* grad,
+                   bool device_out) {
+  if (!P.want_grad) fail(TC_ERR_STATE, "plan was compiled without want_grad");
+  BusyGuard g(P.busy);
+  run(P, params, 1);
+  DeviceState& D = *P.dev;
+  hipMemcpyKind kind = device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (value)
+    HIP_CHECK(hipMemcpy2DAsync(value, sizeof(double), D.ws + D.lay.value, 2 * sizeof(double),
+                               sizeof(double), (size_t)P.batch, kind, D.stream));
+  if (grad && P.n_params)
+    HIP_CHECK(hipMemcpyAsync(grad, D.ws + D.lay.grad,
+                             (uint64_t)P.batch * P.n_params * sizeof(double), kind, D.stream));
+  if (!device_out) HIP_CHECK(hipStreamSynchronize(D.stream));
+}
+
+void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_out,
+             int* kinds, double* ms, double* flops, double* bytes) {
+  if (which == 1 && !P.want_grad) fail(TC_ERR_STATE, "plan was compiled without want_grad");
+  if (reps < 1) fail(TC_ERR_INVALID_ARG, "reps must be >= 1");
+  BusyGuard g(P.busy);
+  if (!P.dev) bind_plan(P, nullptr, 0);
+  DeviceState& D = *P.dev;
+  HIP_CHECK(hipSetDevice(D.device));
+  std::vector<Launch> seq = P.fwd;
+  if (which == 1) seq.insert(seq.end(), P.bwd.begin(), P.bwd.end());
+  uint64_t pbytes = (uint64_t)P.batch * P.n_params * sizeof(float);
+  if (pbytes)
+    HIP_CHECK(hipMemcpyAsync(D.ws + D.lay.params, params, pbytes, hipMemcpyDeviceToDevice,
+                             D.stream));
+  std::vector<hipEvent_t> ev(seq.size() + 1);
+  for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
+  std::vector<double> acc(seq.size(), 0.0);
+  try {
+    for (int r = 0; r < reps; ++r) {
+      HIP_CHECK(hipEventRecord(ev[0], D.stream));
+      for (size_t i = 0; i < seq.size(); ++i) {
+        enqueue(P, D, std::vector<Launch>{seq[i]});
+        HIP_CHECK(hipEventRecord(ev[i + 1], D.stream));
+      }
+      HIP_CHECK(hipStreamSynchronize(D.stream));
+      for (size_t i = 0; i < seq.size(); ++i) {
+        float t = 0;
+        HIP_CHECK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+        acc[i] += t;
+      }
+    }
+  } catch (...) {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    throw;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  *n_out = (int)seq.size();
+  for (size_t i = 0; i < seq.size() && (int)i < cap; ++i) {
+    if (kinds) kinds[i] = seq[i].kind;
+    if (ms) ms[i] = acc[i] / reps;
+    if (flops) flops[i] = seq[i].flops;
+    if (bytes) bytes[i] = seq[i].bytes;
+  }
+}
+
+void free_device(Plan& P) {
+  release(P.dev);
+  P.dev = nullptr;
+}
+
+}  // namespace tcx
+
+// ------------------------------------------------------------------ C ABI
+
+#define TC_GUARD_BEGIN try {
+#define TC_GUARD_END                                               \
+  }                                                                \
+  catch (const tcx::Error& e) {                                    \
+    tcx::set_error(e.msg);                                         \
+    return e.status;                                               \
+  }                                                                \
+  catch (const std::bad_alloc&) {                                  \
+    tcx::set_error("host allocation failed");                      \
+    return TC_ERR_OUT_OF_MEMORY;                                   \
+  }                                                                \
+  catch (const std::exception& e) {                                \
+    tcx::set_error(std::string("internal error: ") + e.what());    \
+    return TC_ERR_INVALID_ARG;                                     \
+  }
+
+extern "C" {
+
+tc_status tc_plan_create(const tc_network* net, const tc_path* path,
+                         const tc_plan_opts* opts, tc_plan** out) {
+  TC_GUARD_BEGIN
+  if (!net || !path || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tc_plan_opts o{0, 1, 0, 0, 0, nullptr};
+  if (opts) o = *opts;
+  if (o.batch < 1 || o.batch > (1 << 20)) tcx::fail(TC_ERR_INVALID_ARG, "batch must be in 1..2^20");
+  if (o.precision != TC_PREC_C64 && o.precision != TC_PREC_BF16X3)
+    tcx::fail(TC_ERR_UNSUPPORTED, "unknown precision");
+  auto* p = new tc_plan;
+  p->p.precision = o.precision;
+  p->p.batch = o.batch;
+  p->p.want_grad = o.want_grad ? 1 : 0;
+  p->p.device = o.device;
+  p->p.budget = o.mem_budget_bytes;
+  p->p.user_stream = o.stream;
+  try {
+    tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  *out = p;
+  return TC_OK;
+  TC_GUARD_END
+}
+
+void tc_plan_free(tc_plan* plan) {
+  if (!plan) return;
+  tcx::free_device(plan->p);
+  delete plan;
+}
+
+tc_status tc_plan_info_get(const tc_plan* plan, tc_plan_info* out) {
+  TC_GUARD_BEGIN
+  if (!plan || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  *out = plan->p.info;
+  return TC_OK;
+  TC_GUARD_END
+}
+
+tc_status tc_plan_bind(tc_plan* plan, void* workspace, uint64_t bytes) {
+  TC_GUARD_BEGIN
+  if (!plan) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tcx::bind_plan(plan->p, workspace, bytes);
+  return TC_OK;
+  TC_GUARD_END
+}
+
+tc_status tc_contract(tc_plan* plan, const float* params, double* out) {
+  TC_GUARD_BEGIN
+  if (!plan || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tcx::contract(plan->p, params, out, false);
+  return TC_OK;
+  TC_GUARD_END
+}
+
+tc_status tc_contract_grad(tc_plan* plan, const float* params, double* value, double* grad) {
+  TC_GUARD_BEGIN
+  if (!plan) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tcx::contract_grad(plan->p, params, value, grad, false);
+  return TC_OK;
+  TC_GUARD_END
+}
+
+tc_status tc_contract_device(tc_plan* plan, const float* params, double* out_dev) {
+  TC_GUARD_BEGIN
+  if (!plan || !out_dev) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tcx::contract(plan->p, params, out_dev, true);
+  return TC_OK;
+  TC_GUARD_END
+}
+
+tc_status tc_contract_grad_device(tc_plan* plan, const float* params, double* value_dev,
+                                  double* grad_dev) {
+  TC_GUARD_BEGIN
+  if (!plan) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tcx::contract_grad(plan->p, params, value_dev, grad_dev, true);
+  return TC_OK;
+  TC_GUARD_END
+}
+
+tc_status tc_plan_profile(tc_plan* plan, const float* params, int32_t which, int32_t reps,
+                          int32_t cap, int32_t* n_launches, int32_t* kinds, double* ms,
+                          double* flops, double* bytes) {
+  TC_GUARD_BEGIN
+  if (!plan || !params || !n_launches) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tcx::profile(plan->p, params, which, reps, cap, n_launches, kinds, ms, flops, bytes);
+  return TC_OK;
+  TC_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Plain-data descriptors shared by the host planner and the HIP kernels.
+//
+// Tensor storage: complex64 (float2) elements; a tensor of rank r holds 2^r
+// entries whose index bits follow its leg list (first leg = most
+// significant bit).  A batched tensor is stored as [batch][2^r]; an
+// unbatched one holds one copy that every batch row reads (batch stride 0).
+// Offsets are in complex64 elements from the arena base.
+#pragma once
+#include <stdint.h>
+
+namespace tcx {
+
+// One pairwise contraction C[m, n] = sum_k A[m, k] B[k, n] over index-
+// permuted operands: element (m, k) of A lives at A + tab[a_m + m] +
+// tab[a_k + k]; element (k, n) of B at B + tab[b_k + k] + tab[b_n + n];
+// element (m, n) of C at C + tab[c_m + m] + tab[c_n + n].  Batch row r adds
+// r * a_bs, r * b_bs, r * c_bs.
+struct DevOp {
+  uint64_t a, b, c;        // arena element offsets
+  uint64_t work0;          // first work item of this op inside its launch
+  uint32_t a_bs, b_bs, c_bs;  // batch strides in elements (0 = shared)
+  uint32_t M, N, K;
+  uint32_t a_m, a_k, b_k, b_n, c_m, c_n;  // offsets into the table area
+  uint32_t rows;           // batch rows covered (1 if nothing is batched)
+  uint32_t tiles_m, tiles_n;  // GEMM path: tile grid per batch row
+};
+
+enum : int32_t {
+  DLEAF_GATE = 0, DLEAF_KET0 = 1, DLEAF_BRA = 2, DLEAF_PAULI = 3
+};
+
+struct DevLeaf {
+  uint64_t out;            // arena element offset
+  uint64_t work0;          // first work item (batch row * elems + e)
+  int32_t kind;            // DLEAF_*
+  int32_t gkind;           // tc_gate_kind for gate leaves
+  int32_t part;            // 0 whole, 1/2 split factors
+  int32_t conj;
+  int32_t value;           // bit for BRA, Pauli for PAULI
+  int32_t rank;
+  int32_t param[2];        // parameter slots, -1 = fixed
+  float fixed[2];
+  uint32_t rows;           // batch rows written (1 = shared)
+  uint32_t mat;            // offset of 32 floats (U1/U2) in the float table
+};
+
+// d(term root)/d(angle) for one leaf use: sum_e adj[e] * dleaf[e]/dangle
+struct DevGradUse {
+  uint64_t adj;            // arena element offset of the leaf's adjoint
+  uint32_t adj_bs;         // batch stride of the adjoint
+  uint32_t leaf;           // index into the leaf table
+  int32_t which;           // angle number (0 or 1)
+  int32_t slot;            // parameter slot
+};
+
+struct DevRoot {
+  uint64_t val;            // arena element offset of the term's scalar
+  uint32_t bs;             // batch stride (0 = shared)
+  int32_t present;         // 0: empty network, value 1
+  double weight;
+};
+
+}  // namespace tcx

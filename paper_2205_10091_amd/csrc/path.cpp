@@ -1,0 +1,297 @@
+// Host-side contraction path: preprocessing by absorption, then a pairwise
+// greedy search, per term.
+//
+// Paper, section "Custom contraction settings": the default path finder is a
+// pairwise greedy; preprocessing absorbs single-qubit gates into two-qubit
+// gates before the search; path quality is measured by FLOPs, WRITE (all
+// elements written, intermediates included) and SIZE (largest
+// intermediate); the contractor table combines flops and write as
+// flops + 64 * write.  The greedy rule used here is the size-reduction rule
+// of Gray & Kourtis (Quantum 5, 410 (2021), cited in section "Tensor network
+// engine"): contract the connected pair minimising
+// size(out) - size(a) - size(b).
+#include <algorithm>
+#include <cmath>
+#include <queue>
+#include <random>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace tcx {
+
+namespace {
+
+// legs of a contraction result: symmetric difference, keeping a's order
+// then b's order
+std::vector<int32_t> result_legs(const std::vector<int32_t>& a,
+                                 const std::vector<int32_t>& b) {
+  std::vector<int32_t> out;
+  out.reserve(a.size() + b.size());
+  for (int32_t l : a)
+    if (std::find(b.begin(), b.end(), l) == b.end()) out.push_back(l);
+  for (int32_t l : b)
+    if (std::find(a.begin(), a.end(), l) == a.end()) out.push_back(l);
+  return out;
+}
+
+int union_rank(const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+  int shared = 0;
+  for (int32_t l : a)
+    if (std::find(b.begin(), b.end(), l) != b.end()) ++shared;
+  return (int)(a.size() + b.size()) - shared;
+}
+
+struct Cand {
+  double cost;
+  double flops;
+  int32_t i, j;
+};
+struct CandCmp {
+  bool operator()(const Cand& x, const Cand& y) const {
+    if (x.cost != y.cost) return x.cost > y.cost;
+    if (x.flops != y.flops) return x.flops > y.flops;
+    if (x.i != y.i) return x.i > y.i;
+    return x.j > y.j;
+  }
+};
+
+struct Search {
+  std::vector<std::vector<int32_t>> legs;  // per SSA id
+  std::vector<char> alive;
+  std::unordered_map<int32_t, std::pair<int32_t, int32_t>> owner;  // leg -> ids
+  std::vector<std::pair<int32_t, int32_t>> pairs;
+  int32_t n_alive = 0;
+
+  void init(const Term& t) {
+    for (const Leaf& lf : t.leaves) {
+      legs.emplace_back(lf.legs, lf.legs + lf.rank);
+      alive.push_back(1);
+    }
+    n_alive = (int32_t)legs.size();
+    for (int32_t id = 0; id < (int32_t)legs.size(); ++id)
+      for (int32_t l : legs[id]) {
+        auto it = owner.find(l);
+        if (it == owner.end())
+          owner[l] = {id, -1};
+        else
+          it->second.second = id;
+      }
+  }
+
+  int32_t other(int32_t leg, int32_t id) const {
+    auto it = owner.find(leg);
+    if (it == owner.end()) return -1;
+    if (it->second.first == id) return it->second.second;
+    return it->second.first;
+  }
+
+  int32_t contract(int32_t i, int32_t j) {
+    int32_t k = (int32_t)legs.size();
+    std::vector<int32_t> out = result_legs(legs[i], legs[j]);
+    for (int32_t l : legs[i])
+      if (std::find(out.begin(), out.end(), l) == out.end()) owner.erase(l);
+    for (int32_t l : out) {
+      auto& o = owner[l];
+      if (o.first == i || o.first == j) o.first = k;
+      if (o.second == i || o.second == j) o.second = k;
+    }
+    legs.push_back(std::move(out));
+    alive.push_back(1);
+    alive[i] = alive[j] = 0;
+    --n_alive;
+    pairs.emplace_back(i, j);
+    return k;
+  }
+
+  std::vector<int32_t> neighbours(int32_t id) const {
+    std::vector<int32_t> nb;
+    for (int32_t l : legs[id]) {
+      int32_t o = other(l, id);
+      if (o >= 0 && std::find(nb.begin(), nb.end(), o) == nb.end()) nb.push_back(o);
+    }
+    return nb;
+  }
+
+  // preprocessing: tensors of rank <= 2 go into their largest neighbour
+  void absorb_small() {
+    bool changed = true;
+    while (changed) {
+      changed = false;
+      for (int32_t id = 0; id < (int32_t)legs.size(); ++id) {
+        if (!alive[id] || legs[id].size() > 2) continue;
+        std::vector<int32_t> nb = neighbours(id);
+        if (nb.empty()) continue;
+        int32_t best = nb[0];
+        for (int32_t x : nb)
+          if (legs[x].size() > legs[best].size() ||
+              (legs[x].size() == legs[best].size() && x < best))
+            best = x;
+        int32_t a = std::min(id, best), b = std::max(id, best);
+        contract(a, b);
+        changed = true;
+      }
+    }
+  }
+
+  double costmod = 1.0;
+
+  Cand cand(int32_t i, int32_t j) const {
+    int ra = (int)legs[i].size(), rb = (int)legs[j].size();
+    int ru = union_rank(legs[i], legs[j]);
+    int shared = ra + rb - ru;
+    int rc = ra + rb - 2 * shared;
+    double cost = std::ldexp(1.0, rc) -
+                  costmod * (std::ldexp(1.0, ra) + std::ldexp(1.0, rb));
+    double flops = 8.0 * std::ldexp(1.0, ru);
+    return Cand{cost, flops, std::min(i, j), std::max(i, j)};
+  }
+
+  void greedy(std::mt19937_64* rng, double temperature) {
+    std::priority_queue<Cand, std::vector<Cand>, CandCmp> heap;
+    for (int32_t id = 0; id < (int32_t)legs.size(); ++id) {
+      if (!alive[id]) continue;
+      for (int32_t o : neighbours(id))
+        if (o > id && alive[o]) heap.push(cand(id, o));
+    }
+    std::uniform_real_distribution<double> U(1e-12, 1.0);
+    while (!heap.empty()) {
+      Cand c = heap.top();
+      heap.pop();
+      if (!alive[c.i] || !alive[c.j]) continue;
+      if (rng && temperature > 0) {
+        // thermal choice among up to 8 live candidates
+        std::vector<Cand> pool{c};
+        while (!heap.empty() && pool.size() < 8) {
+          Cand d = heap.top();
+          heap.pop();
+          if (alive[d.i] && alive[d.j]) pool.push_back(d);
+        }
+        double c0 = pool[0].cost;
+        double scale = temperature * std::max(std::fabs(c0), 1.0);
+        size_t pick = 0;
+        double best = 0;
+        for (size_t k = 0; k < pool.size(); ++k) {
+          // Gumbel-max sampling of exp(-(cost - c0) / scale)
+          double g = -std::log(-std::log(U(*rng)));
+          double v = -(pool[k].cost - c0) / scale + g;
+          if (k == 0 || v > best) {
+            best = v;
+            pick = k;
+          }
+        }
+        for (size_t k = 0; k < pool.size(); ++k)
+          if (k != pick) heap.push(pool[k]);
+        c = pool[pick];
+      }
+      int32_t k = contract(c.i, c.j);
+      for (int32_t o : neighbours(k))
+        if (alive[o]) heap.push(cand(k, o));
+    }
+    // disconnected pieces (scalars, separate components): join by id
+    std::vector<int32_t> rest;
+    for (int32_t id = 0; id < (int32_t)legs.size(); ++id)
+      if (alive[id]) rest.push_back(id);
+    while (rest.size() > 1) {
+      int32_t a = rest[0], b = rest[1];
+      int32_t k = contract(a, b);
+      rest.erase(rest.begin(), rest.begin() + 2);
+      rest.insert(rest.begin(), k);
+    }
+  }
+};
+
+double score_of(const TreeStats& s, int score) {
+  switch (score) {
+    case TC_SCORE_FLOPS: return s.flops;
+    case TC_SCORE_WRITE: return s.write;
+    case TC_SCORE_SIZE: return s.size * 1e6 + s.flops * 1e-12;
+    default: return s.flops / 8.0 + 64.0 * s.write;
+  }
+}
+
+}  // namespace
+
+std::vector<std::vector<int32_t>> ssa_legs(const Term& term, const TermPath& tp) {
+  std::vector<std::vector<int32_t>> legs;
+  for (const Leaf& lf : term.leaves) legs.emplace_back(lf.legs, lf.legs + lf.rank);
+  for (auto& p : tp.pairs) legs.push_back(result_legs(legs[p.first], legs[p.second]));
+  return legs;
+}
+
+void validate_term_path(const Term& term, const TermPath& tp) {
+  int32_t n = (int32_t)term.leaves.size();
+  if (tp.n_leaves != n) fail(TC_ERR_INVALID_ARG, "path does not match the network");
+  if (n == 0) {
+    if (!tp.pairs.empty()) fail(TC_ERR_INVALID_ARG, "path has steps for an empty term");
+    return;
+  }
+  if ((int32_t)tp.pairs.size() != n - 1)
+    fail(TC_ERR_INVALID_ARG, "path must have n_leaves - 1 steps");
+  std::vector<char> used(2 * n, 0);
+  for (size_t s = 0; s < tp.pairs.size(); ++s) {
+    int32_t a = tp.pairs[s].first, b = tp.pairs[s].second;
+    int32_t limit = n + (int32_t)s;
+    if (a < 0 || b < 0 || a >= limit || b >= limit || a == b)
+      fail(TC_ERR_INVALID_ARG, "path step refers to a tensor that does not exist yet");
+    if (used[a] || used[b]) fail(TC_ERR_INVALID_ARG, "path uses a tensor twice");
+    used[a] = used[b] = 1;
+  }
+}
+
+TreeStats tree_stats(const Term& term, const TermPath& tp) {
+  TreeStats st;
+  std::vector<std::vector<int32_t>> legs = ssa_legs(term, tp);
+  int32_t n = (int32_t)term.leaves.size();
+  std::vector<int32_t> depth(legs.size(), 0);
+  for (size_t s = 0; s < tp.pairs.size(); ++s) {
+    int32_t a = tp.pairs[s].first, b = tp.pairs[s].second;
+    int ru = union_rank(legs[a], legs[b]);
+    st.flops += 8.0 * std::ldexp(1.0, ru);
+    double sz = std::ldexp(1.0, (int)legs[n + s].size());
+    st.write += sz;
+    st.size = std::max(st.size, sz);
+    depth[n + s] = 1 + std::max(depth[a], depth[b]);
+    st.depth = std::max(st.depth, depth[n + s]);
+  }
+  return st;
+}
+
+Path greedy_path(const Network& net, const tc_path_opts& opts) {
+  Path path;
+  path.opts = opts;
+  int trials = std::max(1, opts.n_trials);
+  for (size_t t = 0; t < net.terms.size(); ++t) {
+    const Term& term = net.terms[t];
+    TermPath best;
+    double best_score = 0;
+    for (int trial = 0; trial < trials; ++trial) {
+      Search s;
+      s.init(term);
+      if (net.opts.absorb_1q) s.absorb_small();
+      std::mt19937_64 rng(hash_mix(opts.seed, (uint64_t)(t * 1000003u + trial)));
+      if (trial == 0) {
+        s.greedy(nullptr, 0.0);
+      } else {
+        // later trials: random cost modifier alpha in size(ab) - alpha *
+        // (size(a) + size(b)), log-uniform in [1/4, 4], and Boltzmann
+        // choices at the given temperature
+        std::uniform_real_distribution<double> u(-2.0, 2.0);
+        s.costmod = std::exp2(u(rng));
+        s.greedy(&rng, opts.temperature > 0 ? opts.temperature : 0.1);
+      }
+      TermPath tp;
+      tp.n_leaves = (int32_t)term.leaves.size();
+      tp.pairs = std::move(s.pairs);
+      double sc = score_of(tree_stats(term, tp), opts.score);
+      if (trial == 0 || sc < best_score) {
+        best_score = sc;
+        best = std::move(tp);
+      }
+    }
+    path.terms.push_back(std::move(best));
+  }
+  return path;
+}
+
+}  // namespace tcx

@@ -1,0 +1,569 @@
+// Plan compilation (host only): contraction trees -> level-ordered batched
+// launches, index tables, leaf / root / gradient tables, and a
+// liveness-based arena.
+//
+// Paper: section "Tensor network engine" (the contraction itself is a
+// sequence of pairwise einsum/matmul steps chosen by the path), section
+// "Gradients, optimization and variational algorithms" (reverse-mode
+// gradient; section "Custom contraction settings" notes that AD keeps every
+// intermediate, which is why WRITE rather than SIZE bounds its memory), and
+// section "vmap and vectorized_value_and_grad" (one compiled plan evaluated
+// for a batch of parameter vectors).
+//
+// Execution model.  Tree nodes of all terms are grouped by level (longest
+// path from the leaves); each level is one launch per kernel class.  The
+// reverse sweep seeds each term's root with its weight alpha_j; for a node
+// C = A.B it computes dA = dC.B and dB = dC.A with the same contraction
+// kernels (the network is holomorphic in its leaf entries, so no
+// conjugation appears; bra leaves already hold conjugated entries), grouped
+// by depth below the root.  Leaf adjoints are written in their leaf's leg
+// order and dotted with dLeaf/dangle in FP64.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <string>
+#include <unordered_map>
+
+#include "plan.h"
+
+namespace tcx {
+
+namespace {
+
+struct PT {                       // a tensor of the plan
+  std::vector<int32_t> legs;      // storage order, most significant first
+  bool batched = false;
+  uint64_t elems = 1;
+  int64_t off = -1;
+  int32_t first = 0, last = 0;    // timeline steps of production / last use
+  bool fixed = false;             // preallocated constant (seeds)
+};
+
+struct Tables {
+  std::vector<uint32_t>& tabs;
+  std::unordered_map<std::string, uint32_t> memo;
+  explicit Tables(std::vector<uint32_t>& t) : tabs(t) {}
+
+  // offsets of index i over the ordered sub-legs `sub` of a tensor with
+  // legs `xl`: sum_j bit_j(i) * 2^pos(sub[j]), sub[0] most significant
+  uint32_t gather(const std::vector<int32_t>& xl, const std::vector<int32_t>& sub) {
+    std::vector<uint32_t> stride(sub.size());
+    const int r = (int)xl.size();
+    std::string key;
+    for (size_t j = 0; j < sub.size(); ++j) {
+      int idx = (int)(std::find(xl.begin(), xl.end(), sub[j]) - xl.begin());
+      if (idx >= r) fail(TC_ERR_INVALID_ARG, "internal: leg missing from tensor");
+      stride[j] = 1u << (r - 1 - idx);
+      key += std::to_string(stride[j]);
+      key += ',';
+    }
+    return put(key, stride);
+  }
+  // dense strides: index i over n_bits bits times `scale`
+  uint32_t dense(int n_bits, uint32_t scale) {
+    std::vector<uint32_t> stride(n_bits);
+    std::string key;
+    for (int j = 0; j < n_bits; ++j) {
+      stride[j] = scale << (n_bits - 1 - j);
+      key += std::to_string(stride[j]);
+      key += ',';
+    }
+    return put(key, stride);
+  }
+  uint32_t put(const std::string& key, const std::vector<uint32_t>& stride) {
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+    const size_t nb = stride.size();
+    const uint64_t n = 1ull << nb;
+    if (tabs.size() + n > 0xFFFFFFFFull) fail(TC_ERR_TOO_LARGE, "index tables exceed 2^32 entries");
+    uint32_t base = (uint32_t)tabs.size();
+    tabs.resize(tabs.size() + n);
+    for (uint64_t i = 0; i < n; ++i) {
+      uint32_t off = 0;
+      for (size_t j = 0; j < nb; ++j)
+        if ((i >> (nb - 1 - j)) & 1) off += stride[j];
+      tabs[base + i] = off;
+    }
+    memo.emplace(key, base);
+    return base;
+  }
+};
+
+struct Arena {
+  std::map<uint64_t, uint64_t> free_;  // offset -> size (elements)
+  uint64_t top = 0;
+  static uint64_t align(uint64_t x) { return (x + 31) & ~uint64_t(31); }  // 256 B
+  uint64_t alloc(uint64_t n) {
+    n = align(std::max<uint64_t>(n, 1));
+    auto best = free_.end();
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n && (best == free_.end() || it->second < best->second)) best = it;
+    if (best != free_.end()) {
+      uint64_t off = best->first, sz = best->second;
+      free_.erase(best);
+      if (sz > n) free_[off + n] = sz - n;
+      return off;
+    }
+    uint64_t off = top;
+    top += n;
+    return off;
+  }
+  void release(uint64_t off, uint64_t n) {
+    n = align(std::max<uint64_t>(n, 1));
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+        it = pv;
+      }
+    }
+    if (it->first + it->second == top) {
+      top = it->first;
+      free_.erase(it);
+    }
+  }
+};
+
+struct PendingOp {
+  int32_t a, b, c;   // tensor ids
+  int32_t step;
+  bool bwd;
+};
+
+}  // namespace
+
+WorkspaceLayout workspace_layout(const Plan& p) {
+  auto al = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  WorkspaceLayout w{};
+  uint64_t o = 0;
+  w.ops = o; o = al(o + p.ops.size() * sizeof(DevOp));
+  w.tabs = o; o = al(o + p.tabs.size() * sizeof(uint32_t));
+  w.leaves = o; o = al(o + p.leaves.size() * sizeof(DevLeaf));
+  w.ftab = o; o = al(o + p.ftab.size() * sizeof(float));
+  w.uses = o; o = al(o + p.uses.size() * sizeof(DevGradUse));
+  w.slot_begin = o; o = al(o + p.slot_begin.size() * sizeof(uint32_t));
+  w.roots = o; o = al(o + p.roots.size() * sizeof(DevRoot));
+  w.params = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(float));
+  w.value = o; o = al(o + (uint64_t)p.batch * 2 * sizeof(double));
+  w.grad = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(double));
+  w.arena = o; o = al(o + p.arena_elems * 8);
+  w.total = o;
+  return w;
+}
+
+void build_plan(Plan& plan, const Network& net, const Path& path) {
+  const int B = plan.batch;
+  const bool grad = plan.want_grad != 0;
+  plan.n_params = net.n_params;
+  plan.n_terms = (int32_t)net.terms.size();
+  if (path.terms.size() != net.terms.size()) fail(TC_ERR_INVALID_ARG, "path does not match network");
+
+  std::vector<PT> T;            // all tensors
+  std::vector<PendingOp> pend;  // all contraction ops
+  Tables tables(plan.tabs);
+
+  // seeds: one rank-0 constant per term, value alpha_j
+  for (size_t t = 0; t < net.terms.size(); ++t) {
+    PT s;
+    s.fixed = true;
+    s.off = (int64_t)t;
+    T.push_back(s);
+    plan.seeds.push_back((float)net.terms[t].weight);
+    plan.seeds.push_back(0.0f);
+  }
+  const uint64_t seed_elems = Arena::align(net.terms.size());
+
+  struct TermInfo {
+    std::vector<int32_t> tid;     // SSA id -> tensor id
+    std::vector<int32_t> level;   // SSA id -> forward level
+    std::vector<int32_t> parent;  // SSA id -> SSA id of consumer (-1 root)
+    std::vector<char> needs;      // subtree holds a parameter-dependent leaf
+    int32_t root = -1;
+  };
+  std::vector<TermInfo> ti(net.terms.size());
+  int32_t max_level = 0;
+
+  // ---- forward structure
+  for (size_t t = 0; t < net.terms.size(); ++t) {
+    const Term& term = net.terms[t];
+    const TermPath& tp = path.terms[t];
+    validate_term_path(term, tp);
+    TermInfo& I = ti[t];
+    const int32_t nl = (int32_t)term.leaves.size();
+    const int32_t ns = nl + (int32_t)tp.pairs.size();
+    I.tid.assign(ns, -1);
+    I.level.assign(ns, 0);
+    I.parent.assign(ns, -1);
+    I.needs.assign(ns, 0);
+    std::vector<std::vector<int32_t>> legs = ssa_legs(term, tp);
+    for (int32_t i = 0; i < nl; ++i) {
+      PT x;
+      x.legs = legs[i];
+      x.elems = 1ull << x.legs.size();
+      x.batched = leaf_param_dependent(net, term.leaves[i]);
+      I.needs[i] = x.batched;
+      x.first = 0;
+      I.tid[i] = (int32_t)T.size();
+      T.push_back(x);
+    }
+    for (size_t s = 0; s < tp.pairs.size(); ++s) {
+      int32_t a = tp.pairs[s].first, b = tp.pairs[s].second, c = nl + (int32_t)s;
+      PT x;
+      x.legs = legs[c];
+      if (x.legs.size() > 31) fail(TC_ERR_TOO_LARGE, "intermediate of rank > 31");
+      x.elems = 1ull << x.legs.size();
+      x.batched = T[I.tid[a]].batched || T[I.tid[b]].batched;
+      I.needs[c] = I.needs[a] || I.needs[b];
+      I.level[c] = 1 + std::max(I.level[a], I.level[b]);
+      x.first = I.level[c];
+      I.parent[a] = I.parent[b] = c;
+      I.tid[c] = (int32_t)T.size();
+      T.push_back(x);
+      max_level = std::max(max_level, I.level[c]);
+    }
+    if (ns > 0) {
+      I.root = ns - 1;
+      if (!T[I.tid[I.root]].legs.empty()) fail(TC_ERR_INVALID_ARG, "network is not closed");
+    }
+  }
+  const int32_t root_step = max_level + 1;
+
+  // ---- forward ops and last uses
+  for (size_t t = 0; t < net.terms.size(); ++t) {
+    const TermPath& tp = path.terms[t];
+    TermInfo& I = ti[t];
+    const int32_t nl = (int32_t)net.terms[t].leaves.size();
+    for (size_t s = 0; s < tp.pairs.size(); ++s) {
+      int32_t a = tp.pairs[s].first, b = tp.pairs[s].second, c = nl + (int32_t)s;
+      int32_t step = I.level[c];
+      pend.push_back({I.tid[a], I.tid[b], I.tid[c], step, false});
+      T[I.tid[a]].last = std::max(T[I.tid[a]].last, step);
+      T[I.tid[b]].last = std::max(T[I.tid[b]].last, step);
+    }
+    if (I.root >= 0) T[I.tid[I.root]].last = root_step;
+  }
+
+  // ---- reverse sweep
+  int32_t max_bstep = root_step;
+  std::vector<std::pair<int32_t, int32_t>> leaf_adj;  // (leaf tensor, adj tensor) per use
+  std::vector<std::pair<size_t, int32_t>> leaf_adj_term;  // (term, leaf index)
+  if (grad) {
+    for (size_t t = 0; t < net.terms.size(); ++t) {
+      const TermPath& tp = path.terms[t];
+      TermInfo& I = ti[t];
+      if (I.root < 0 || !I.needs[I.root]) continue;
+      const int32_t nl = (int32_t)net.terms[t].leaves.size();
+      const int32_t ns = (int32_t)I.tid.size();
+      std::vector<int32_t> adj(ns, -1), depth(ns, 0);
+      adj[I.root] = (int32_t)t;  // seed tensor
+      for (int32_t c = ns - 1; c >= nl; --c) {
+        if (adj[c] < 0) continue;
+        int32_t a = tp.pairs[c - nl].first, b = tp.pairs[c - nl].second;
+        int32_t step = root_step + 1 + depth[c];
+        max_bstep = std::max(max_bstep, step);
+        for (int side = 0; side < 2; ++side) {
+          int32_t x = side == 0 ? a : b, other = side == 0 ? b : a;
+          if (!I.needs[x]) continue;
+          PT d;
+          if (x < nl) {
+            d.legs = T[I.tid[x]].legs;  // leaf order for the gradient dot
+          } else {
+            // natural order of contract(dC, other): dC's free legs then other's
+            const auto& cl = T[adj[c]].legs;
+            const auto& ol = T[I.tid[other]].legs;
+            for (int32_t l : cl)
+              if (std::find(ol.begin(), ol.end(), l) == ol.end()) d.legs.push_back(l);
+            for (int32_t l : ol)
+              if (std::find(cl.begin(), cl.end(), l) == cl.end()) d.legs.push_back(l);
+          }
+          d.elems = 1ull << d.legs.size();
+          d.batched = T[adj[c]].batched || T[I.tid[other]].batched;
+          d.first = step;
+          d.last = step;  // extended below
+          int32_t did = (int32_t)T.size();
+          T.push_back(d);
+          pend.push_back({adj[c], I.tid[other], did, step, true});
+          T[adj[c]].last = std::max(T[adj[c]].last, step);
+          T[I.tid[other]].last = std::max(T[I.tid[other]].last, step);
+          adj[x] = did;
+          depth[x] = depth[c] + 1;
+          if (x < nl) {
+            leaf_adj.push_back({I.tid[x], did});
+            leaf_adj_term.push_back({t, x});
+          }
+        }
+      }
+    }
+  }
+  const int32_t grad_step = max_bstep + 1;
+  for (auto& la : leaf_adj) T[la.second].last = grad_step;
+
+  // ---- arena: allocate in step order, release after last use
+  {
+    Arena ar;
+    ar.top = seed_elems;
+    const int32_t n_steps = grad_step + 1;
+    std::vector<std::vector<int32_t>> born(n_steps + 1), dies(n_steps + 2);
+    for (int32_t i = 0; i < (int32_t)T.size(); ++i) {
+      if (T[i].fixed) continue;
+      born[T[i].first].push_back(i);
+      dies[std::max(T[i].last, T[i].first) + 1].push_back(i);
+    }
+    for (int32_t s = 0; s < n_steps; ++s) {
+      for (int32_t i : dies[s]) {
+        uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
+        ar.release((uint64_t)T[i].off, n);
+      }
+      // big tensors first keeps the best-fit layout compact
+      std::sort(born[s].begin(), born[s].end(),
+                [&](int32_t x, int32_t y) { return T[x].elems > T[y].elems; });
+      for (int32_t i : born[s]) {
+        uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
+        T[i].off = (int64_t)ar.alloc(n);
+        plan.arena_elems = std::max(plan.arena_elems, ar.top);
+        plan.peak_tensor_elems = std::max(plan.peak_tensor_elems, n);
+      }
+    }
+    plan.arena_elems = std::max(plan.arena_elems, seed_elems);
+  }
+
+  // ---- contraction ops, grouped into launches by step
+  std::stable_sort(pend.begin(), pend.end(),
+                   [](const PendingOp& x, const PendingOp& y) { return x.step < y.step; });
+  double flops = 0, bytes = 0, gflops = 0, gbytes = 0;
+  size_t i = 0;
+  while (i < pend.size()) {
+    size_t j = i;
+    while (j < pend.size() && pend[j].step == pend[i].step) ++j;
+    // classify: wave kernel for long sums into few outputs, else gather
+    std::vector<DevOp> gc, gcw;
+    std::vector<double> gc_fb(2, 0.0), gcw_fb(2, 0.0);
+    for (size_t k = i; k < j; ++k) {
+      const PT& A = T[pend[k].a];
+      const PT& Bt = T[pend[k].b];
+      const PT& C = T[pend[k].c];
+      std::vector<int32_t> S, FA, FB;
+      for (int32_t l : A.legs)
+        (std::find(Bt.legs.begin(), Bt.legs.end(), l) != Bt.legs.end() ? S : FA).push_back(l);
+      for (int32_t l : Bt.legs)
+        if (std::find(A.legs.begin(), A.legs.end(), l) == A.legs.end()) FB.push_back(l);
+      DevOp op{};
+      op.a = (uint64_t)A.off;
+      op.b = (uint64_t)Bt.off;
+      op.c = (uint64_t)C.off;
+      op.M = 1u << FA.size();
+      op.N = 1u << FB.size();
+      op.K = 1u << S.size();
+      op.a_m = tables.gather(A.legs, FA);
+      op.a_k = tables.gather(A.legs, S);
+      op.b_k = tables.gather(Bt.legs, S);
+      op.b_n = tables.gather(Bt.legs, FB);
+      op.c_m = tables.gather(C.legs, FA);
+      op.c_n = tables.gather(C.legs, FB);
+      bool rowsB = (A.batched || Bt.batched) && B > 1;
+      op.rows = rowsB ? (uint32_t)B : 1u;
+      op.a_bs = (A.batched && B > 1) ? (uint32_t)A.elems : 0u;
+      op.b_bs = (Bt.batched && B > 1) ? (uint32_t)Bt.elems : 0u;
+      op.c_bs = rowsB ? (uint32_t)C.elems : 0u;
+      double f = 8.0 * op.M * op.N * op.K * op.rows;
+      double by = 8.0 * (A.elems * (A.batched ? op.rows : 1) +
+                         Bt.elems * (Bt.batched ? op.rows : 1) + C.elems * op.rows);
+      if (pend[k].bwd) {
+        gflops += f;
+        gbytes += by;
+      } else {
+        flops += f;
+        bytes += by;
+      }
+      if (op.K >= 256 && (uint64_t)op.M * op.N * op.rows <= 8192) {
+        gcw.push_back(op);
+        gcw_fb[0] += f;
+        gcw_fb[1] += by;
+      } else {
+        gc.push_back(op);
+        gc_fb[0] += f;
+        gc_fb[1] += by;
+      }
+    }
+    auto emit = [&](std::vector<DevOp>& v, int32_t kind, uint64_t lanes,
+                    const std::vector<double>& fb) {
+      if (v.empty()) return;
+      Launch L;
+      L.kind = kind;
+      L.flops = fb[0];
+      L.bytes = fb[1];
+      L.begin = (uint32_t)plan.ops.size();
+      uint64_t w = 0;
+      for (DevOp& op : v) {
+        op.work0 = w;
+        w += (uint64_t)op.rows * op.M * op.N * lanes;
+        plan.ops.push_back(op);
+      }
+      L.end = (uint32_t)plan.ops.size();
+      L.work = w;
+      (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
+    };
+    if (!pend[i].bwd && plan.fwd.empty()) {
+      Launch L{L_LEAF, 0, 0, 0};
+      plan.fwd.push_back(L);  // leaf launch first; filled below
+    }
+    emit(gcw, L_GCW, 64, gcw_fb);
+    emit(gc, L_GC, 1, gc_fb);
+    i = j;
+  }
+  if (plan.fwd.empty() || plan.fwd[0].kind != L_LEAF) {
+    Launch L{L_LEAF, 0, 0, 0};
+    plan.fwd.insert(plan.fwd.begin(), L);
+  }
+
+  // ---- leaves
+  uint64_t lw = 0;
+  for (size_t t = 0; t < net.terms.size(); ++t) {
+    const Term& term = net.terms[t];
+    for (size_t li = 0; li < term.leaves.size(); ++li) {
+      const Leaf& lf = term.leaves[li];
+      const PT& x = T[ti[t].tid[li]];
+      DevLeaf d{};
+      d.out = (uint64_t)x.off;
+      d.work0 = lw;
+      d.kind = lf.kind;
+      d.part = lf.part;
+      d.conj = lf.conj;
+      d.rank = lf.rank;
+      d.rows = (x.batched && B > 1) ? (uint32_t)B : 1u;
+      d.param[0] = d.param[1] = -1;
+      if (lf.kind == LEAF_GATE) {
+        const GateRec& g = net.gates[lf.gate];
+        d.gkind = g.kind;
+        for (int a = 0; a < g.n_angles; ++a) {
+          d.param[a] = g.param[a];
+          d.fixed[a] = (float)g.fixed[a];
+        }
+        if (g.kind == TC_GATE_U1 || g.kind == TC_GATE_U2) {
+          d.mat = (uint32_t)plan.ftab.size();
+          for (int k = 0; k < 32; ++k) plan.ftab.push_back((float)g.mat[k]);
+        }
+      } else {
+        d.value = lf.gate;
+      }
+      lw += (uint64_t)d.rows << lf.rank;
+      plan.leaves.push_back(d);
+    }
+  }
+  plan.leaf_work = lw;
+  plan.fwd[0].work = lw;
+  plan.fwd[0].bytes = 8.0 * (double)lw;  // every leaf entry written once
+
+  // ---- roots
+  for (size_t t = 0; t < net.terms.size(); ++t) {
+    DevRoot r{};
+    r.weight = net.terms[t].weight;
+    if (ti[t].root >= 0) {
+      const PT& x = T[ti[t].tid[ti[t].root]];
+      r.present = 1;
+      r.val = (uint64_t)x.off;
+      r.bs = (x.batched && B > 1) ? 1u : 0u;
+    }
+    plan.roots.push_back(r);
+  }
+  plan.fwd.push_back(Launch{L_ROOT, 0, 0, (uint64_t)B});
+
+  // ---- gradient uses, sorted by slot then creation order
+  if (grad) {
+    // leaf table index of (term, leaf)
+    std::vector<uint32_t> leaf_base(net.terms.size() + 1, 0);
+    for (size_t t = 0; t < net.terms.size(); ++t)
+      leaf_base[t + 1] = leaf_base[t] + (uint32_t)net.terms[t].leaves.size();
+    std::vector<DevGradUse> uses;
+    for (size_t u = 0; u < leaf_adj.size(); ++u) {
+      size_t t = leaf_adj_term[u].first;
+      int32_t li = leaf_adj_term[u].second;
+      const Leaf& lf = net.terms[t].leaves[li];
+      const GateRec& g = net.gates[lf.gate];
+      const PT& d = T[leaf_adj[u].second];
+      for (int a = 0; a < g.n_angles; ++a) {
+        if (g.param[a] < 0) continue;
+        DevGradUse gu{};
+        gu.adj = (uint64_t)d.off;
+        gu.adj_bs = (d.batched && B > 1) ? (uint32_t)d.elems : 0u;
+        gu.leaf = leaf_base[t] + (uint32_t)li;
+        gu.which = a;
+        gu.slot = g.param[a];
+        uses.push_back(gu);
+      }
+    }
+    std::stable_sort(uses.begin(), uses.end(),
+                     [](const DevGradUse& x, const DevGradUse& y) { return x.slot < y.slot; });
+    plan.uses = uses;
+    plan.slot_begin.assign(net.n_params + 1, 0);
+    for (const auto& gu : uses) plan.slot_begin[gu.slot + 1]++;
+    for (int p = 0; p < net.n_params; ++p) plan.slot_begin[p + 1] += plan.slot_begin[p];
+    if (net.n_params > 0)
+      plan.bwd.push_back(Launch{L_GRAD, 0, 0, (uint64_t)B * net.n_params});
+  }
+
+  // ---- every device access in bounds (checked here, before any launch)
+  {
+    const uint64_t AE = plan.arena_elems;
+    const uint64_t NT = plan.tabs.size();
+    auto tmax = [&](uint32_t base, uint32_t n) {
+      if ((uint64_t)base + n > NT) fail(TC_ERR_INVALID_ARG, "internal: table out of range");
+      uint32_t m = 0;
+      for (uint32_t x = 0; x < n; ++x) m = std::max(m, plan.tabs[base + x]);
+      return (uint64_t)m;
+    };
+    for (const DevOp& op : plan.ops) {
+      uint64_t r1 = op.rows - 1;
+      uint64_t a_end = op.a + r1 * op.a_bs + tmax(op.a_m, op.M) + tmax(op.a_k, op.K);
+      uint64_t b_end = op.b + r1 * op.b_bs + tmax(op.b_k, op.K) + tmax(op.b_n, op.N);
+      uint64_t c_end = op.c + r1 * op.c_bs + tmax(op.c_m, op.M) + tmax(op.c_n, op.N);
+      if (a_end >= AE || b_end >= AE || c_end >= AE)
+        fail(TC_ERR_INVALID_ARG, "internal: contraction op out of the arena");
+      if (op.c < seed_elems) fail(TC_ERR_INVALID_ARG, "internal: op writes over the seeds");
+    }
+    for (const DevLeaf& d : plan.leaves)
+      if (d.out + ((uint64_t)d.rows << d.rank) > AE || d.out < seed_elems ||
+          (d.param[0] >= plan.n_params) || (d.param[1] >= plan.n_params))
+        fail(TC_ERR_INVALID_ARG, "internal: leaf out of range");
+    for (const DevGradUse& u : plan.uses)
+      if (u.adj + (uint64_t)(B - 1) * u.adj_bs + (1ull << plan.leaves[u.leaf].rank) > AE ||
+          u.leaf >= plan.leaves.size())
+        fail(TC_ERR_INVALID_ARG, "internal: gradient use out of range");
+    for (const DevRoot& r : plan.roots)
+      if (r.present && r.val + (uint64_t)(B - 1) * r.bs >= AE)
+        fail(TC_ERR_INVALID_ARG, "internal: root out of range");
+  }
+
+  // ---- info
+  tc_plan_info& info = plan.info;
+  info = tc_plan_info{};
+  info.flops = flops;
+  info.alg_bytes = bytes;
+  info.grad_flops = gflops;
+  info.grad_alg_bytes = gbytes;
+  info.workspace_bytes = workspace_layout(plan).total;
+  info.peak_tensor_bytes = plan.peak_tensor_elems * 8;
+  int32_t nn = 0;
+  for (const auto& p : pend)
+    if (!p.bwd) ++nn;
+  info.n_nodes = nn;
+  info.n_levels = max_level;
+  info.n_gemm_nodes = 0;
+  info.n_launches = (int32_t)plan.fwd.size();
+  info.n_grad_launches = (int32_t)plan.bwd.size();
+  info.batch = B;
+  info.n_params = net.n_params;
+  info.n_terms = plan.n_terms;
+  if (plan.budget && info.workspace_bytes > plan.budget)
+    fail(TC_ERR_TOO_LARGE, "workspace of " + std::to_string(info.workspace_bytes) +
+                               " bytes exceeds the memory budget");
+}
+
+}  // namespace tcx

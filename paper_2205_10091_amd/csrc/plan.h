@@ -1,0 +1,71 @@
+// Host-side plan: everything the device executor needs, as flat tables.
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+#include "ops.h"
+
+namespace tcx {
+
+enum LaunchKind : int32_t {
+  L_LEAF = 0,   // materialise leaf tensors from parameters
+  L_GC = 1,     // gather contraction, one thread per output element
+  L_GCW = 2,    // gather contraction, one wavefront per output element
+  L_GEMM = 3,   // LDS-tiled MFMA complex GEMM over gathered operands
+  L_ROOT = 4,   // FP64 weighted sum of the term roots
+  L_GRAD = 5    // FP64 leaf-gradient reduction
+};
+
+struct Launch {
+  int32_t kind;
+  uint32_t begin, end;  // op range (contraction kinds) in Plan::ops
+  uint64_t work;        // threads (GC/leaf/root/grad) or tiles (GEMM)
+  double flops = 0;     // algorithmic flops of the launch (8 per complex MAC)
+  double bytes = 0;     // algorithmic bytes: operands read + results written
+};
+
+struct DeviceState;  // defined by the executor
+
+struct Plan {
+  // options
+  int32_t precision = 0, batch = 1, want_grad = 0, device = 0;
+  uint64_t budget = 0;
+  void* user_stream = nullptr;
+  int32_t n_params = 0, n_terms = 0;
+
+  // tables uploaded once
+  std::vector<DevOp> ops;
+  std::vector<uint32_t> tabs;
+  std::vector<DevLeaf> leaves;
+  std::vector<float> ftab;
+  std::vector<DevGradUse> uses;       // sorted by slot
+  std::vector<uint32_t> slot_begin;   // n_params + 1
+  std::vector<DevRoot> roots;
+  std::vector<float> seeds;           // (re, im) per term, arena offset 0
+  uint64_t leaf_work = 0;
+
+  std::vector<Launch> fwd;            // leaf, levels, root
+  std::vector<Launch> bwd;            // adjoint levels, grad
+  uint64_t arena_elems = 0;           // complex64 elements
+  uint64_t peak_tensor_elems = 0;
+
+  tc_plan_info info{};
+
+  // device side
+  DeviceState* dev = nullptr;
+  std::atomic<int> busy{0};
+};
+
+void build_plan(Plan& plan, const Network& net, const Path& path);
+
+// Byte layout of the workspace: [tables][params][values][grad][arena]
+struct WorkspaceLayout {
+  uint64_t ops, tabs, leaves, ftab, uses, slot_begin, roots;
+  uint64_t params, value, grad, arena, total;
+};
+WorkspaceLayout workspace_layout(const Plan& p);
+
+}  // namespace tcx

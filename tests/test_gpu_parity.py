@@ -1,0 +1,230 @@
+"""GPU parity: the HIP contraction path against the CPU oracle.
+
+Every value is computed by libtcx.so through the C ABI (the Python binding
+only marshals arguments) and compared with the oracle on the same seeded
+inputs, at the tolerance of the plain complex64 form (1e-5 relative with the
+amplitude floor 2^(-n/2), energies and expectations floored at 1)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import tcgen
+from oracle import statevector as sv
+from paper_2205_10091_amd import _lib as L
+from paper_2205_10091_amd import api
+from gpu_common import TOL_C64, device_params, grad_err, rel_err
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def one(circ, obs, params, **kw):
+    plan = api.compile(circ, obs, **kw)
+    return plan, plan.contract(device_params(params))[0]
+
+
+def test_library_is_the_native_build():
+    lib = L.load()
+    assert os.path.basename(lib._name) == "libtcx.so"
+
+
+# ------------------------------------------------------------ forward chain
+
+def test_forward_chain_amplitude_and_zz():
+    circ, p, zz, amp = tcgen.workload_forward_chain()
+    n = circ.n_qubits
+    _, a = one(circ, amp, p)
+    assert rel_err(a, sv.amplitude(circ, p), 2 ** (-n / 2)) < TOL_C64
+    _, z = one(circ, zz, p)
+    ref = sv.energy(circ, p, zz)
+    assert rel_err(z, ref, 1.0) < TOL_C64
+    assert abs(z.imag) < TOL_C64
+
+
+@pytest.mark.parametrize("split,lightcone", [(0, 0), (1, 0), (0, 1)])
+def test_forward_chain_network_options(split, lightcone):
+    circ, p, zz, amp = tcgen.workload_forward_chain()
+    _, z = one(circ, zz, p, split_2q=split, lightcone=lightcone)
+    assert rel_err(z, sv.energy(circ, p, zz), 1.0) < TOL_C64
+
+
+def test_amplitudes_of_several_bitstrings():
+    circ, p, _, _ = tcgen.workload_forward_chain()
+    n = circ.n_qubits
+    rng = np.random.default_rng(0)
+    for _ in range(4):
+        bits = tuple(int(b) for b in rng.integers(0, 2, n))
+        _, a = one(circ, tcgen.amplitude(n, bits), p)
+        assert rel_err(a, sv.amplitude(circ, p, bits), 2 ** (-n / 2)) < TOL_C64
+
+
+# ------------------------------------------------------------ VQE energy + gradient
+
+def test_vqe_chain_energy_and_gradient():
+    circ, p, obs = tcgen.workload_vqe_chain()
+    plan = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1)
+    e, g = plan.contract_grad(device_params(p))
+    e_ref, g_ref = sv.energy_grad(circ, p, obs)
+    assert rel_err(e[0], e_ref, 1.0) < TOL_C64
+    assert grad_err(g[0], g_ref) < TOL_C64
+    # slots no gate reaches are exactly zero; the first RZZ layer has zero
+    # gradient up to rounding
+    gg = g[0].reshape(6, 2, 20)
+    assert np.all(gg[:, 0, 19] == 0.0)
+    assert np.max(np.abs(gg[0, 0, :])) < 1e-5
+    # forward-only call of the same plan agrees with the gradient call
+    v = plan.contract(device_params(p))[0]
+    assert abs(v.real - e[0]) < 1e-6 and abs(v.imag) < TOL_C64
+
+
+def test_vqe_gradient_vs_parameter_shift_and_fd_on_gpu():
+    """The GPU gradient against the GPU's own energies at shifted angles:
+    the exact two-point shift rule and central differences (h = 1e-3)."""
+    n, Ld = 8, 3
+    circ = tcgen.chain_ladder(n, Ld)
+    obs = tcgen.tfim_zz_x(n, 1.0)
+    p = tcgen.draw_angles(31, (Ld, 2, n)).reshape(-1)
+    gplan = api.compile(circ, obs, want_grad=True)
+    _, g = gplan.contract_grad(device_params(p))
+    P = len(p)
+    shifts = []
+    for s in range(P):
+        for d in (math.pi / 2, -math.pi / 2, 1e-3, -1e-3):
+            q = p.astype(np.float64).copy()
+            q[s] += d
+            shifts.append(q)
+    B = len(shifts)
+    fplan = api.compile(circ, obs, batch=B)
+    vals = fplan.contract(device_params(np.array(shifts, np.float32), B)).real.reshape(P, 4)
+    ps = 0.5 * (vals[:, 0] - vals[:, 1])
+    fd = (vals[:, 2] - vals[:, 3]) / 2e-3
+    assert grad_err(g[0], ps) < 1e-5
+    # fp32 energies limit central differences to ~1e-7/1e-3 per slot
+    assert grad_err(g[0], fd) < 2e-3
+    # and both against the oracle
+    _, g_ref = sv.energy_grad(circ, p, obs)
+    assert grad_err(ps, g_ref) < 1e-5
+
+
+# ------------------------------------------------------------ batched sweep
+
+def test_batched_sweep_matches_oracle_and_single_calls():
+    B = 64
+    circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=12, layers=4)
+    plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=4, seed=1)
+    e, g = plan.contract_grad(device_params(P, B))
+    single = api.compile(circ, obs, want_grad=True, n_trials=4, seed=1)
+    for b in (0, 17, 63):
+        e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
+        assert rel_err(e[b], e_ref, 1.0) < TOL_C64
+        assert grad_err(g[b], g_ref) < TOL_C64
+        e1, g1 = single.contract_grad(device_params(P[b]))
+        assert abs(e1[0] - e[b]) < 1e-6
+        assert np.max(np.abs(g1[0] - g[b])) < 1e-6
+
+
+def test_batched_sweep_full_size_sampled_rows():
+    B = 1024
+    circ, P, obs = tcgen.workload_batched_vqe(batch=B)
+    plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=8, seed=1)
+    e, g = plan.contract_grad(device_params(P, B))
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
+    for b in (0, 511, 1023):
+        e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
+        assert rel_err(e[b], e_ref, 1.0) < TOL_C64
+        assert grad_err(g[b], g_ref) < TOL_C64
+
+
+# ------------------------------------------------------------ grid amplitudes
+
+@pytest.mark.parametrize("rows,cols", [(2, 4), (3, 3), (4, 4)])
+def test_grid_amplitude_small(rows, cols):
+    circ, p, amp = tcgen.workload_grid_amplitude(rows, cols, 8)
+    n = circ.n_qubits
+    for seed in (0, 1):
+        _, a = one(circ, amp, p, n_trials=8, seed=seed)
+        assert rel_err(a, sv.amplitude(circ, p), 2 ** (-n / 2)) < TOL_C64
+
+
+def test_grid_amplitude_full_size_against_golden():
+    path = os.path.join(GOLDEN, "grid6x6_d8_amplitude.json")
+    if not os.path.exists(path):
+        pytest.skip("reference amplitude not generated")
+    ref = json.load(open(path))
+    vals = [complex(v["re"], v["im"]) for v in ref["values"].values()]
+    assert abs(vals[0] - vals[1]) <= 1e-12 * abs(vals[0])
+    circ, p, amp = tcgen.workload_grid_amplitude()
+    _, a = one(circ, amp, p, n_trials=32, seed=1)
+    assert rel_err(a, vals[0], 2 ** (-18)) < TOL_C64
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_all_gate_kinds_random_circuits():
+    for seed in range(3):
+        n = 6
+        circ = tcgen.random_circuit(n, 50, seed)
+        p = np.random.default_rng(seed).uniform(-3, 3, circ.n_params).astype(np.float32)
+        rng = np.random.default_rng(10 + seed)
+        s = rng.integers(0, 4, size=(4, n)).astype(np.uint8)
+        obs = tcgen.Observable("pauli_sum", structures=s, weights=rng.normal(size=4))
+        _, e = one(circ, obs, p)
+        ref = sv.energy(circ, p.astype(np.float64), obs)
+        scale = max(1.0, float(np.sum(np.abs(obs.weights))))
+        assert abs(e - ref) / scale < 1e-5
+
+
+def test_identity_and_norm():
+    circ, p, obs = tcgen.workload_vqe_chain(n=10, layers=3)
+    ident = tcgen.Observable("pauli_sum", structures=np.zeros((1, 10), np.uint8),
+                             weights=np.array([2.5]))
+    _, e = one(circ, ident, p)          # empty network after the light cone
+    assert e == 2.5
+    _, e = one(circ, ident, p, lightcone=False)   # <psi|psi> contracted
+    assert abs(e - 2.5) < 2.5e-5
+
+
+def test_single_qubit_and_unparameterised_terms():
+    c = tcgen.Circuit(1, 1).add("rx", (0,), (0,))
+    p = np.array([0.7], np.float32)
+    _, z = one(c, tcgen.pauli_string(1, z=(0,)), p)
+    assert abs(z - math.cos(0.7)) < 1e-6
+    # a term that sees no parameter is shared by every batch row
+    c = tcgen.Circuit(3, 1).add("h", (0,)).add("cnot", (0, 1)).add("rx", (2,), (0,))
+    obs = tcgen.Observable("pauli_sum", structures=np.array([[3, 3, 0], [0, 0, 3]], np.uint8),
+                           weights=np.array([1.0, 1.0]))
+    B = 5
+    P = np.linspace(0, 3, B).astype(np.float32).reshape(B, 1)
+    plan = api.compile(c, obs, batch=B, want_grad=True)
+    e, g = plan.contract_grad(device_params(P, B))
+    np.testing.assert_allclose(e, 1 + np.cos(P[:, 0].astype(np.float64)), atol=1e-6)
+    np.testing.assert_allclose(g[:, 0], -np.sin(P[:, 0].astype(np.float64)), atol=1e-6)
+
+
+def test_determinism_and_caller_workspace():
+    import torch
+    circ, p, obs = tcgen.workload_vqe_chain(n=12, layers=4)
+    plan = api.compile(circ, obs, want_grad=True, bind=False)
+    ws = torch.empty(int(plan.info().workspace_bytes), dtype=torch.uint8, device="cuda")
+    plan.bind(ws)
+    e1, g1 = plan.contract_grad(device_params(p))
+    e2, g2 = plan.contract_grad(device_params(p))
+    assert e1[0] == e2[0] and np.array_equal(g1, g2)
+    own = api.compile(circ, obs, want_grad=True, bind=False)
+    own.bind(None)      # library-allocated workspace
+    e3, g3 = own.contract_grad(device_params(p))
+    assert e3[0] == e1[0] and np.array_equal(g3, g1)
+
+
+def test_state_errors():
+    circ, p, obs = tcgen.workload_vqe_chain(n=6, layers=2)
+    plan = api.compile(circ, obs)
+    with pytest.raises(L.TcxError) as e:
+        plan.contract_grad(device_params(p))
+    assert e.value.status == L.TC_ERR_STATE
+    with pytest.raises(ValueError):
+        plan.contract(device_params(p[:-1]))

@@ -1,0 +1,114 @@
+"""C-ABI library: loads, exports every declared symbol, host-side calls work
+and fail cleanly (no GPU needed; no compute call is made)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import tcgen
+from paper_2205_10091_amd import _lib as L
+from paper_2205_10091_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tcx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), f"libtcx.so does not export {n}"
+    # the binding declares exactly the header's functions
+    assert sorted(s[0] for s in L.SIGNATURES) == names
+
+
+def test_status_strings_and_version():
+    lib = L.load()
+    assert lib.tc_status_string(0) == b"ok"
+    assert lib.tc_status_string(4) == b"too large"
+    assert lib.tc_version() >= 100
+
+
+def test_invalid_circuits_are_rejected():
+    c = tcgen.Circuit(3, 1)
+    c.gates.append(tcgen.Gate("rzz", (0, 0), (0,), (0.0,)))
+    with pytest.raises(L.TcxError) as e:
+        api.Network(c, tcgen.pauli_string(3, z=(0,)))
+    assert e.value.status == L.TC_ERR_INVALID_ARG
+    c = tcgen.Circuit(3, 1)
+    c.gates.append(tcgen.Gate("rx", (5,), (0,), (0.0,)))
+    with pytest.raises(L.TcxError) as e:
+        api.Network(c, tcgen.pauli_string(3, z=(0,)))
+    assert "qubit out of range" in str(e.value)
+    c = tcgen.Circuit(3, 1)
+    c.gates.append(tcgen.Gate("rx", (1,), (3,), (0.0,)))
+    with pytest.raises(L.TcxError):
+        api.Network(c, tcgen.pauli_string(3, z=(0,)))
+    obs = tcgen.Observable("pauli_sum", structures=np.array([[0, 4, 0]], np.uint8),
+                           weights=np.array([1.0]))
+    with pytest.raises(L.TcxError):
+        api.Network(tcgen.chain_ladder(3, 1), obs)
+
+
+def test_unknown_gate_kind_is_unsupported():
+    lib = L.load()
+    g = (L.Gate * 1)()
+    g[0].kind = 99
+    circ = L.Circuit(2, 0, 1, C.cast(g, C.POINTER(L.Gate)))
+    obs = L.Observable(0, None, 0, None, None)
+    h = C.c_void_p()
+    assert lib.tc_build_network(C.byref(circ), C.byref(obs), None, C.byref(h)) == \
+        L.TC_ERR_UNSUPPORTED
+    assert b"unknown kind" in lib.tc_last_error()
+
+
+def test_free_null_is_noop():
+    lib = L.load()
+    lib.tc_network_free(None)
+    lib.tc_path_free(None)
+    lib.tc_plan_free(None)
+    lib.tc_serve_free(None)
+
+
+def test_bad_path_is_rejected():
+    circ, _, _, amp = tcgen.workload_forward_chain()
+    net = api.Network(circ, amp)
+    path = api.Path(net)
+    pairs = path.pairs(0).copy()
+    bad = pairs.copy()
+    bad[3] = bad[2]
+    with pytest.raises(L.TcxError):
+        path.replace_term(0, bad)
+    with pytest.raises(L.TcxError):
+        path.replace_term(0, pairs[:-1])
+    path.replace_term(0, pairs)  # the original is accepted
+
+
+def test_plan_is_host_only_and_reports_sizes():
+    circ, p, obs = tcgen.workload_vqe_chain()
+    net = api.Network(circ, obs)
+    path = api.Path(net, n_trials=4, seed=1)
+    plan = api.Plan(net, path, batch=1, want_grad=True)
+    info = plan.info()
+    st = path.stats()
+    assert info.n_terms == 39
+    assert info.n_nodes == st.n_steps
+    assert info.n_params == 240
+    # forward flops of the plan equal the path's flops (8 per complex MAC)
+    assert abs(info.flops - st.flops) <= 1e-9 * st.flops
+    assert info.grad_flops > info.flops
+    assert info.workspace_bytes > 0
+    plan4 = api.Plan(net, path, batch=1024, want_grad=True)
+    assert plan4.info().flops > 900 * info.flops
+    with pytest.raises(L.TcxError) as e:
+        api.Plan(net, path, batch=1024, want_grad=True, mem_budget_bytes=1 << 20)
+    assert e.value.status == L.TC_ERR_TOO_LARGE

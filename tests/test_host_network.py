@@ -1,0 +1,171 @@
+"""Host-side network builder and path finder, checked on the CPU.
+
+The library exports each term's leaves (gate index, split part, conjugation,
+legs) and the greedy path.  Here the test fills the leaves with the oracle's
+gate matrices, contracts them with numpy along the library's path, and
+compares with the oracle's state-vector values.  This pins the builder's leg
+bookkeeping, the light cone, the split and the path without a GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import tcgen
+from oracle import gates as G
+from oracle import statevector as sv
+from paper_2205_10091_amd import api
+
+
+def split_factors(g, params):
+    """Rank-2 operator-Schmidt factors for the splittable gates, derived
+    from the oracle's 4x4 matrix by projecting on {I (x) I, P (x) P} (Pauli
+    rotations) or on the control projectors (CNOT, CZ)."""
+    m = G.matrix(g, params)
+    if g.kind in ("cnot", "cz"):
+        proj = [np.diag([1.0, 0.0]), np.diag([0.0, 1.0])]
+        f1 = np.stack(proj).astype(complex)
+        # second factor: block of m acting on the target for control k
+        f2 = np.stack([m.reshape(2, 2, 2, 2)[k, :, k, :] for k in range(2)])
+        return f1, f2
+    p = {"rzz": G.Z, "rxx": G.X, "ryy": G.Y}[g.kind]
+    basis = [np.eye(2, dtype=complex), p]
+    f1 = np.stack(basis)
+    coef = [np.trace(np.kron(b, b).conj().T @ m) / 4 for b in basis]
+    f2 = np.stack([c * b for c, b in zip(coef, basis)])
+    return f1, f2
+
+
+def leaf_tensor(circ, params, kind, gate, part, conj, rank):
+    if kind == 1:
+        return np.array([1.0, 0.0], complex)
+    if kind == 2:
+        v = np.zeros(2, complex)
+        v[gate] = 1
+        return v
+    if kind == 3:
+        return G.PAULI[gate].astype(complex)
+    g = circ.gates[gate]
+    if part == 0:
+        t = G.matrix(g, params).reshape((2,) * rank)
+    else:
+        t = split_factors(g, params)[part - 1]
+    return t.conj() if conj else t
+
+
+def contract_along_path(net, path, circ, params, term):
+    lv = net.term_leaves(term)
+    tensors = []
+    for i in range(len(lv["kind"])):
+        r = int(lv["rank"][i])
+        t = leaf_tensor(circ, params, int(lv["kind"][i]), int(lv["gate"][i]),
+                        int(lv["part"][i]), int(lv["conj"][i]), r)
+        tensors.append((t, [int(x) for x in lv["legs"][i][:r]]))
+    if not tensors:
+        return 1.0 + 0j
+    for a, b in path.pairs(term):
+        (ta, la), (tb, lb) = tensors[a], tensors[b]
+        sh = [x for x in la if x in lb]
+        out = np.tensordot(ta, tb, axes=([la.index(x) for x in sh], [lb.index(x) for x in sh]))
+        tensors.append((out, [x for x in la if x not in sh] + [x for x in lb if x not in sh]))
+    t, l = tensors[-1]
+    assert l == []
+    return complex(t)
+
+
+@pytest.mark.parametrize("split,lightcone,absorb", [(1, 1, 1), (0, 0, 1), (1, 0, 0), (0, 1, 0)])
+def test_vqe_chain_terms_through_exported_network(split, lightcone, absorb):
+    circ = tcgen.chain_ladder(8, 3)
+    obs = tcgen.tfim_zz_x(8, 0.8)
+    params = tcgen.draw_angles(7, (3, 2, 8)).reshape(-1).astype(np.float64)
+    net = api.Network(circ, obs, split_2q=split, lightcone=lightcone, absorb_1q=absorb)
+    path = api.Path(net, n_trials=3, seed=5)
+    want = sv.term_values(circ, params, obs)
+    for j in range(len(want)):
+        got = contract_along_path(net, path, circ, params, j)
+        assert abs(got - want[j]) < 1e-12, j
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_circuits_all_gate_kinds(seed):
+    n = 5
+    circ = tcgen.random_circuit(n, 40, seed)
+    params = np.random.default_rng(seed).uniform(-4, 4, circ.n_params)
+    rng = np.random.default_rng(50 + seed)
+    s = rng.integers(0, 4, size=(3, n)).astype(np.uint8)
+    obs = tcgen.Observable("pauli_sum", structures=s, weights=np.array([1.0, 0.5, -2.0]))
+    net = api.Network(circ, obs)
+    path = api.Path(net, n_trials=2, seed=seed)
+    want = sv.term_values(circ, params, obs)
+    for j in range(3):
+        assert abs(contract_along_path(net, path, circ, params, j) - want[j]) < 1e-12
+    bits = tuple(int(b) for b in rng.integers(0, 2, n))
+    net = api.Network(circ, tcgen.amplitude(n, bits))
+    path = api.Path(net)
+    assert abs(contract_along_path(net, path, circ, params, 0) -
+               sv.amplitude(circ, params, bits)) < 1e-12
+
+
+def test_identity_term_with_lightcone_is_empty():
+    circ = tcgen.chain_ladder(4, 2)
+    obs = tcgen.pauli_string(4)
+    net = api.Network(circ, obs)
+    assert net.info().max_leaves == 0
+    net = api.Network(circ, obs, lightcone=False)
+    assert net.info().max_leaves > 0
+    params = tcgen.draw_angles(3, (2, 2, 4)).reshape(-1).astype(np.float64)
+    path = api.Path(net)
+    assert abs(contract_along_path(net, path, circ, params, 0) - 1.0) < 1e-12
+
+
+def test_lightcone_sizes_on_the_ladder():
+    # a Z Z term in the bulk of an L-layer ladder keeps a window of about
+    # 2 + 2L qubits: ket leaves = |0> vectors + split halves + RX gates
+    n, L = 20, 6
+    circ = tcgen.chain_ladder(n, L)
+    net = api.Network(circ, tcgen.pauli_string(n, z=(9, 10)))
+    lv = net.term_leaves(0)
+    qubits_touched = set()
+    for k, gi in zip(lv["kind"], lv["gate"]):
+        if k == 0:
+            qubits_touched.update(circ.gates[gi].qubits)
+    assert len(qubits_touched) <= 2 + 2 * L
+    assert len(qubits_touched) >= 2 + 2 * (L - 1)
+
+
+def test_greedy_band_on_the_paper_testbed():
+    # section "Custom contraction settings": n = 40, d = 6 ZZ + RX layers,
+    # split gates, <Z_20> as one network.  The paper's default greedy gives
+    # log10 FLOPs 7.373, log2 SIZE 12, log2 WRITE 20.171; our finder with
+    # the exact light cone must stay within that band or better
+    # (parity unpinned: the paper's block details and FLOP convention are
+    # not given).
+    circ = tcgen.chain_ladder(40, 6)
+    net = api.Network(circ, tcgen.pauli_string(40, z=(20,)))
+    st = api.Path(net, n_trials=16, seed=1).stats()
+    assert st.log10_flops < 7.373 + 0.6
+    assert st.log2_size <= 16
+    assert st.log2_write < 20.171 + 1
+
+
+def test_path_stats_are_recomputed_independently():
+    circ, p, amp = tcgen.workload_grid_amplitude(4, 4, 8)
+    net = api.Network(circ, amp)
+    path = api.Path(net, n_trials=8, seed=2)
+    lv = net.term_leaves(0)
+    legs = [set(int(x) for x in lv["legs"][i][:lv["rank"][i]]) for i in range(len(lv["rank"]))]
+    fl = wr = 0.0
+    mx = 0
+    used = set()
+    for a, b in path.pairs(0):
+        assert a not in used and b not in used
+        used.update((a, b))
+        out = legs[a] ^ legs[b]
+        legs.append(out)
+        fl += 8 * 2.0 ** len(legs[a] | legs[b])
+        wr += 2.0 ** len(out)
+        mx = max(mx, len(out))
+    st = path.stats()
+    assert math.isclose(st.flops, fl) and math.isclose(st.write, wr)
+    assert st.log2_size == mx
+    assert len(used) == 2 * len(lv["rank"]) - 2
