@@ -248,7 +248,11 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *   want_grad   keep intermediates and compile the reverse sweep;
  *   mem_budget_bytes  0 = no limit; otherwise TOO_LARGE if the workspace
  *               exceeds it;
- *   stream      hipStream_t to run on (NULL = the library's own stream).
+ *   stream      hipStream_t to run on (NULL = the library's own stream);
+ *   gemm_min_k  nodes with K >= gemm_min_k contracted indices (K = product
+ *               of their dimensions) and M, N >= 16 run on the MFMA GEMM,
+ *               the rest on the gather kernels; 0 = default (8), a value
+ *               above every K keeps all nodes on the gather kernels.
  */
 typedef struct tc_plan tc_plan;
 
@@ -261,6 +265,7 @@ typedef struct {
   int32_t device;            /* HIP device ordinal                        */
   uint64_t mem_budget_bytes;
   void* stream;              /* hipStream_t                               */
+  int32_t gemm_min_k;
 } tc_plan_opts;
 
 tc_status tc_plan_create(const tc_network* net, const tc_path* path,

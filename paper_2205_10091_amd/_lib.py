@@ -68,7 +68,8 @@ class PathStats(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("batch", C.c_int32),
                 ("want_grad", C.c_int32), ("device", C.c_int32),
-                ("mem_budget_bytes", C.c_uint64), ("stream", C.c_void_p)]
+                ("mem_budget_bytes", C.c_uint64), ("stream", C.c_void_p),
+                ("gemm_min_k", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -147,6 +148,15 @@ def load(path: str = LIB_PATH, strict: bool = True):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build the HIP library first "
                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    # One HIP runtime per process: torch's bundled libamdhip64 carries the
+    # same SONAME as the system one, so loading torch first makes this
+    # library bind to it instead of starting a second runtime (which would
+    # find no device) and lets torch tensors and this library share memory
+    # and streams.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name, None)

@@ -247,7 +247,7 @@ static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& se
         break;
       case L_GEMM:
         launch_gemm(ops + x.begin, x.end - x.begin, tabs, arena, x.work, P.precision,
-                    D.stream);
+                    D.stream, D.n_cu);
         break;
       case L_ROOT:
         hipLaunchKernelGGL(k_root, dim3((unsigned)((x.work + 255) / 256)), dim3(256), 0,
@@ -474,8 +474,9 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
                          const tc_plan_opts* opts, tc_plan** out) {
   TC_GUARD_BEGIN
   if (!net || !path || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
-  tc_plan_opts o{0, 1, 0, 0, 0, nullptr};
+  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0};
   if (opts) o = *opts;
+  if (o.gemm_min_k < 0) tcx::fail(TC_ERR_INVALID_ARG, "gemm_min_k must be >= 0");
   if (o.batch < 1 || o.batch > (1 << 20)) tcx::fail(TC_ERR_INVALID_ARG, "batch must be in 1..2^20");
   if (o.precision != TC_PREC_C64 && o.precision != TC_PREC_BF16X3)
     tcx::fail(TC_ERR_UNSUPPORTED, "unknown precision");
@@ -486,6 +487,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
   p->p.device = o.device;
   p->p.budget = o.mem_budget_bytes;
   p->p.user_stream = o.stream;
+  if (o.gemm_min_k > 0) p->p.gemm_min_k = o.gemm_min_k;
   try {
     tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));
   } catch (...) {

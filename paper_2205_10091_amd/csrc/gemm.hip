@@ -1,11 +1,288 @@
-// LDS-tiled MFMA complex GEMM for wide tree nodes (not yet enabled by the
-// planner).
+// LDS-tiled MFMA complex GEMM for the wider tree nodes.
+//
+// Paper, section "Tensor network engine": each pairwise contraction is
+// executed as an einsum / matmul.  A node C[m, n] = sum_k A[m, k] B[k, n]
+// is computed here directly from the operands' own layouts: tiles of A and
+// B are gathered through the per-op index tables into LDS (no separate
+// permute pass), split into real and imaginary planes, and multiplied on
+// the matrix cores:
+//   FP32:   Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br with
+//           v_mfma_f32_16x16x4_f32 (four real products, FP32 accumulate);
+//   BF16X3: every real product X Y is taken as Xh Yh + Xh Yl + Xl Yh with
+//           X = Xh + Xl split into two bfloat16 numbers (Henry, Tang &
+//           Heinecke, "Leveraging the bfloat16 artificial intelligence
+//           datatype for higher-precision computations", ARITH 2019),
+//           on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+// A workgroup of four wavefronts computes a 64 x 64 tile of C; each wave a
+// 32 x 32 quarter as 2 x 2 blocks of 16 x 16.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
 #include "gemm.h"
 #include "internal.h"
 
 namespace tcx {
-void launch_gemm(const DevOp*, uint32_t, const uint32_t*, float2*, uint64_t, int,
-                 hipStream_t) {
-  fail(TC_ERR_UNSUPPORTED, "GEMM path not built");
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 64, BN = 64;
+constexpr int BK32 = 16;   // k per LDS stage, FP32 path
+constexpr int BK16 = 32;   // k per LDS stage, split-BF16 path
+constexpr int PAD = 16;    // row padding (floats) against LDS bank conflicts
+
+__device__ __forceinline__ uint32_t find_tile(const DevOp* __restrict__ ops, uint32_t n,
+                                              uint64_t w) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (ops[mid].work0 <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
 }
+
+struct TileCtx {
+  const float2* A;
+  const float2* B;
+  uint64_t cbase;
+  uint32_t m0, n0;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const DevOp& op, uint64_t tile,
+                                            const float2* arena) {
+  uint64_t l = tile - op.work0;
+  const uint32_t tn = (uint32_t)(l % op.tiles_n);
+  l /= op.tiles_n;
+  const uint32_t tm = (uint32_t)(l % op.tiles_m);
+  const uint64_t r = l / op.tiles_m;
+  TileCtx t;
+  t.A = arena + op.a + r * op.a_bs;
+  t.B = arena + op.b + r * op.b_bs;
+  t.cbase = op.c + r * op.c_bs;
+  t.m0 = tm * BM;
+  t.n0 = tn * BN;
+  return t;
+}
+
+__device__ __forceinline__ void store_tile(const DevOp& op, const TileCtx& t,
+                                           const uint32_t* __restrict__ tab,
+                                           float2* __restrict__ arena, const f4 (&cr)[2][2],
+                                           const f4 (&ci)[2][2], int wm, int wn, int lane) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        uint32_t m = t.m0 + wm * 32 + bi * 16 + 4 * (lane >> 4) + v;
+        uint32_t n = t.n0 + wn * 32 + bj * 16 + (lane & 15);
+        if (m < op.M && n < op.N)
+          arena[t.cbase + tab[op.c_m + m] + tab[op.c_n + n]] =
+              make_float2(cr[bi][bj][v], ci[bi][bj][v]);
+      }
+}
+
+// ------------------------------------------------------------------ FP32
+
+__global__ void __launch_bounds__(256) k_gemm_f32(const DevOp* __restrict__ ops,
+                                                  uint32_t n_ops,
+                                                  const uint32_t* __restrict__ tab,
+                                                  float2* __restrict__ arena,
+                                                  uint64_t total) {
+  __shared__ float As[2][BK32][BM + PAD];  // [re/im][k][m]
+  __shared__ float Bs[2][BK32][BN + PAD];  // [re/im][k][n]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  for (uint64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const DevOp& op = ops[find_tile(ops, n_ops, tile)];
+    const TileCtx c = tile_ctx(op, tile, arena);
+    const bool akf = op.flags & 1u, bkf = op.flags & 2u;
+    // fixed row / column offsets of this thread's loads
+    uint32_t aoff[4], boff[4];
+    bool aok[4], bok[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      uint32_t m = c.m0 + (akf ? (t >> 4) + 16 * p : (t & 63));
+      aok[p] = m < op.M;
+      aoff[p] = aok[p] ? tab[op.a_m + m] : 0;
+      uint32_t n = c.n0 + (bkf ? (t >> 4) + 16 * p : (t & 63));
+      bok[p] = n < op.N;
+      boff[p] = bok[p] ? tab[op.b_n + n] : 0;
+    }
+    f4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    for (uint32_t k0 = 0; k0 < op.K; k0 += BK32) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        // A element (m, k): k fastest across threads when A is k-contiguous
+        int kk = akf ? (t & 15) : (t >> 6) + 4 * p;
+        int mm = akf ? (t >> 4) + 16 * p : (t & 63);
+        uint32_t k = k0 + kk;
+        float2 v = make_float2(0.f, 0.f);
+        if (aok[p] && k < op.K) v = c.A[aoff[p] + tab[op.a_k + k]];
+        As[0][kk][mm] = v.x;
+        As[1][kk][mm] = v.y;
+        kk = bkf ? (t & 15) : (t >> 6) + 4 * p;
+        int nn = bkf ? (t >> 4) + 16 * p : (t & 63);
+        k = k0 + kk;
+        v = make_float2(0.f, 0.f);
+        if (bok[p] && k < op.K) v = c.B[boff[p] + tab[op.b_k + k]];
+        Bs[0][kk][nn] = v.x;
+        Bs[1][kk][nn] = v.y;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < BK32; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        float ar[2], ai[2], br[2], bi_[2], nbi[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          ar[i] = As[0][kr][wm * 32 + i * 16 + (lane & 15)];
+          ai[i] = As[1][kr][wm * 32 + i * 16 + (lane & 15)];
+          br[i] = Bs[0][kr][wn * 32 + i * 16 + (lane & 15)];
+          bi_[i] = Bs[1][kr][wn * 32 + i * 16 + (lane & 15)];
+          nbi[i] = -bi_[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], cr[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], nbi[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi_[j], ci[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], ci[i][j], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+    }
+    store_tile(op, c, tab, arena, cr, ci, wm, wn, lane);
+  }
+}
+
+// ------------------------------------------------------------------ BF16X3
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+__global__ void __launch_bounds__(256) k_gemm_bf16x3(const DevOp* __restrict__ ops,
+                                                     uint32_t n_ops,
+                                                     const uint32_t* __restrict__ tab,
+                                                     float2* __restrict__ arena,
+                                                     uint64_t total) {
+  // [re/im][hi/lo][row][k], k contiguous so that a lane reads 8 k at once
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][BM][BK16 + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][BN][BK16 + 8];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  for (uint64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const DevOp& op = ops[find_tile(ops, n_ops, tile)];
+    const TileCtx c = tile_ctx(op, tile, arena);
+    const bool akf = op.flags & 1u, bkf = op.flags & 2u;
+    uint32_t aoff[8], boff[8];
+    bool aok[8], bok[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      uint32_t m = c.m0 + (akf ? (t >> 5) + 8 * p : (t & 63));
+      aok[p] = m < op.M;
+      aoff[p] = aok[p] ? tab[op.a_m + m] : 0;
+      uint32_t n = c.n0 + (bkf ? (t >> 5) + 8 * p : (t & 63));
+      bok[p] = n < op.N;
+      boff[p] = bok[p] ? tab[op.b_n + n] : 0;
+    }
+    f4 pr[2][2], pq[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        pr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        pq[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    for (uint32_t k0 = 0; k0 < op.K; k0 += BK16) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        int kk = akf ? (t & 31) : (t >> 6) + 4 * p;
+        int mm = akf ? (t >> 5) + 8 * p : (t & 63);
+        uint32_t k = k0 + kk;
+        float2 v = make_float2(0.f, 0.f);
+        if (aok[p] && k < op.K) v = c.A[aoff[p] + tab[op.a_k + k]];
+        split_bf16(v.x, As[0][0][mm][kk], As[0][1][mm][kk]);
+        split_bf16(v.y, As[1][0][mm][kk], As[1][1][mm][kk]);
+        kk = bkf ? (t & 31) : (t >> 6) + 4 * p;
+        int nn = bkf ? (t >> 5) + 8 * p : (t & 63);
+        k = k0 + kk;
+        v = make_float2(0.f, 0.f);
+        if (bok[p] && k < op.K) v = c.B[boff[p] + tab[op.b_k + k]];
+        split_bf16(v.x, Bs[0][0][nn][kk], Bs[0][1][nn][kk]);
+        split_bf16(v.y, Bs[1][0][nn][kk], Bs[1][1][nn][kk]);
+      }
+      __syncthreads();
+      const int kr = 8 * (lane >> 4);
+      bf8 a[2][2][2], b[2][2][2];  // [block][re/im][hi/lo]
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            a[i][c2][h] = *(const bf8*)&As[c2][h][wm * 32 + i * 16 + (lane & 15)][kr];
+            b[i][c2][h] = *(const bf8*)&Bs[c2][h][wn * 32 + i * 16 + (lane & 15)][kr];
+          }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          // Ar Br
+          pr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0][0], b[j][0][0], pr[i][j], 0, 0, 0);
+          pr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0][0], b[j][0][1], pr[i][j], 0, 0, 0);
+          pr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0][1], b[j][0][0], pr[i][j], 0, 0, 0);
+          // Ai Bi
+          pq[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1][0], b[j][1][0], pq[i][j], 0, 0, 0);
+          pq[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1][0], b[j][1][1], pq[i][j], 0, 0, 0);
+          pq[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1][1], b[j][1][0], pq[i][j], 0, 0, 0);
+          // Ar Bi + Ai Br
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0][0], b[j][1][0], ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0][0], b[j][1][1], ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0][1], b[j][1][0], ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1][0], b[j][0][0], ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1][0], b[j][0][1], ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1][1], b[j][0][0], ci[i][j], 0, 0, 0);
+        }
+      __syncthreads();
+    }
+    f4 cr[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) cr[i][j] = pr[i][j] - pq[i][j];
+    store_tile(op, c, tab, arena, cr, ci, wm, wn, lane);
+  }
+}
+
+void launch_gemm(const DevOp* ops, uint32_t n_ops, const uint32_t* tabs, float2* arena,
+                 uint64_t tiles, int precision, hipStream_t stream, int n_cu) {
+  uint64_t cap = (uint64_t)n_cu * 16;
+  unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
+  if (precision == TC_PREC_BF16X3)
+    hipLaunchKernelGGL(k_gemm_bf16x3, dim3(grid), dim3(256), 0, stream, ops, n_ops, tabs,
+                       arena, tiles);
+  else
+    hipLaunchKernelGGL(k_gemm_f32, dim3(grid), dim3(256), 0, stream, ops, n_ops, tabs, arena,
+                       tiles);
+}
+
 }  // namespace tcx

@@ -23,6 +23,7 @@ struct DevOp {
   uint32_t a_m, a_k, b_k, b_n, c_m, c_n;  // offsets into the table area
   uint32_t rows;           // batch rows covered (1 if nothing is batched)
   uint32_t tiles_m, tiles_n;  // GEMM path: tile grid per batch row
+  uint32_t flags;          // bit 0: A is k-contiguous; bit 1: B is k-contiguous
 };
 
 enum : int32_t {

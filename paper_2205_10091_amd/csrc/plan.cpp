@@ -343,8 +343,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     size_t j = i;
     while (j < pend.size() && pend[j].step == pend[i].step) ++j;
     // classify: wave kernel for long sums into few outputs, else gather
-    std::vector<DevOp> gc, gcw;
-    std::vector<double> gc_fb(2, 0.0), gcw_fb(2, 0.0);
+    std::vector<DevOp> gc, gcw, gm;
+    std::vector<double> gc_fb(2, 0.0), gcw_fb(2, 0.0), gm_fb(2, 0.0);
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
       const PT& Bt = T[pend[k].b];
@@ -382,7 +382,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         flops += f;
         bytes += by;
       }
-      if (op.K >= 256 && (uint64_t)op.M * op.N * op.rows <= 8192) {
+      // k-contiguity of the operands picks the GEMM's load pattern
+      if (op.K > 1 && plan.tabs[op.a_k + 1] == 1) op.flags |= 1u;
+      if (op.K > 1 && plan.tabs[op.b_k + 1] == 1) op.flags |= 2u;
+      if (op.K >= (uint32_t)plan.gemm_min_k && op.M >= (uint32_t)plan.gemm_min_mn &&
+          op.N >= (uint32_t)plan.gemm_min_mn) {
+        op.tiles_m = (op.M + 63) / 64;
+        op.tiles_n = (op.N + 63) / 64;
+        gm.push_back(op);
+        gm_fb[0] += f;
+        gm_fb[1] += by;
+      } else if (op.K >= 256 && (uint64_t)op.M * op.N * op.rows <= 8192) {
         gcw.push_back(op);
         gcw_fb[0] += f;
         gcw_fb[1] += by;
@@ -403,7 +413,10 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       uint64_t w = 0;
       for (DevOp& op : v) {
         op.work0 = w;
-        w += (uint64_t)op.rows * op.M * op.N * lanes;
+        if (kind == L_GEMM)
+          w += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+        else
+          w += (uint64_t)op.rows * op.M * op.N * lanes;
         plan.ops.push_back(op);
       }
       L.end = (uint32_t)plan.ops.size();
@@ -414,6 +427,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       Launch L{L_LEAF, 0, 0, 0};
       plan.fwd.push_back(L);  // leaf launch first; filled below
     }
+    plan.info.n_gemm_nodes += pend[i].bwd ? 0 : (int32_t)gm.size();
+    emit(gm, L_GEMM, 1, gm_fb);
     emit(gcw, L_GCW, 64, gcw_fb);
     emit(gc, L_GC, 1, gc_fb);
     i = j;
@@ -543,7 +558,9 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
 
   // ---- info
   tc_plan_info& info = plan.info;
+  const int32_t n_gemm = info.n_gemm_nodes;
   info = tc_plan_info{};
+  info.n_gemm_nodes = n_gemm;
   info.flops = flops;
   info.alg_bytes = bytes;
   info.grad_flops = gflops;
@@ -555,7 +572,6 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     if (!p.bwd) ++nn;
   info.n_nodes = nn;
   info.n_levels = max_level;
-  info.n_gemm_nodes = 0;
   info.n_launches = (int32_t)plan.fwd.size();
   info.n_grad_launches = (int32_t)plan.bwd.size();
   info.batch = B;

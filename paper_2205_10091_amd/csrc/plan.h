@@ -35,6 +35,8 @@ struct Plan {
   uint64_t budget = 0;
   void* user_stream = nullptr;
   int32_t n_params = 0, n_terms = 0;
+  // nodes with K >= gemm_min_k and M, N >= gemm_min_mn go to the MFMA GEMM
+  int32_t gemm_min_k = 8, gemm_min_mn = 16;
 
   // tables uploaded once
   std::vector<DevOp> ops;

@@ -220,6 +220,43 @@ def test_determinism_and_caller_workspace():
     assert e3[0] == e1[0] and np.array_equal(g3, g1)
 
 
+def test_gemm_path_matches_gather_path():
+    """Same trees, once with wide nodes on the MFMA GEMM and once with every
+    node on the gather kernels; both against the oracle."""
+    circ, p, obs = tcgen.workload_vqe_chain()
+    gm = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1, gemm_min_k=4)
+    gc = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1, gemm_min_k=1 << 30)
+    assert gm.info().n_gemm_nodes > 0 and gc.info().n_gemm_nodes == 0
+    e1, g1 = gm.contract_grad(device_params(p))
+    e2, g2 = gc.contract_grad(device_params(p))
+    e_ref, g_ref = sv.energy_grad(circ, p, obs)
+    for e, g in ((e1, g1), (e2, g2)):
+        assert rel_err(e[0], e_ref, 1.0) < TOL_C64
+        assert grad_err(g[0], g_ref) < TOL_C64
+    # batched rows through the GEMM tiles
+    B = 16
+    circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=14, layers=5)
+    gm = api.compile(circ, obs, batch=B, want_grad=True, gemm_min_k=4)
+    e, g = gm.contract_grad(device_params(P, B))
+    for b in (0, 9):
+        e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
+        assert rel_err(e[b], e_ref, 1.0) < TOL_C64
+        assert grad_err(g[b], g_ref) < TOL_C64
+
+
+def test_grid_gemm_nodes_fp32_and_bf16x3():
+    from gpu_common import TOL_BF16X3
+    circ, p, amp = tcgen.workload_grid_amplitude(4, 5, 8)
+    n = circ.n_qubits
+    ref = sv.amplitude(circ, p)
+    # one greedy trial leaves wide nodes in the tree
+    for prec, tol in ((0, TOL_C64), (1, TOL_BF16X3)):
+        plan = api.compile(circ, amp, n_trials=1, precision=prec, gemm_min_k=4)
+        assert plan.info().n_gemm_nodes > 0
+        a = plan.contract(device_params(p))[0]
+        assert rel_err(a, ref, 2 ** (-n / 2)) < tol, prec
+
+
 def test_state_errors():
     circ, p, obs = tcgen.workload_vqe_chain(n=6, layers=2)
     plan = api.compile(circ, obs)
