@@ -1,19 +1,25 @@
-"""Benchmark: TFIM VQE energy + gradient on a 20-qubit chain (one GPU).
+"""Benchmark of the tensor-network contraction path on one MI355X.
 
-One step = one evaluation of E = sum_i Z_i Z_{i+1} + g sum_i X_i (39 Pauli
-terms, each its own tensor network) and its 240-entry gradient, through the
-whole contraction path: leaf materialisation from the parameters, the
-level-ordered contraction of all 39 trees, the FP64 root sum, the reverse
-sweep and the FP64 gradient sum.  Parameters are resident in HBM before the
-timed region; the plan (network, greedy path, tables, HIP graph) is built
-once beforehand, as the paper excludes JIT staging from its timings.
+Default workload (--workload vqe): TFIM VQE energy + gradient on a 20-qubit
+open chain, 6 layers of [RZZ ladder, RX layer] (240 parameter slots),
+E = sum_i Z_i Z_{i+1} + g sum_i X_i with g = 1 (39 Pauli terms, each its own
+tensor network).  One step = one evaluation of E and its gradient through
+the whole path: leaf materialisation from the parameters, the level-ordered
+contraction of all 39 trees, the FP64 root sum, the reverse sweep and the
+FP64 gradient sum.  Parameters are resident in HBM before the timed region;
+the plan (network, greedy path, tables, HIP graph) is built once beforehand,
+as the paper excludes JIT staging from its timings.
 
-Prints one JSON line.  Extra fields: the batched sweep (1024 parameter
-vectors per launch) and the 10-qubit forward latency distribution.
+Other workloads: --workload batched (the same chain, 1024 parameter vectors
+per launch), forward (10-qubit brickwork: amplitude and <Z0 Z1>), grid (6x6
+fSim grid amplitude, depth 8).
+
+Prints one JSON line.  --copy-calibration BYTES also runs one plain device
+copy of that many bytes (used to scale HBM byte counters).
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -26,11 +32,36 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 KIND_NAMES = {0: "k_leaf", 1: "k_gc", 2: "k_gcw", 3: "k_gemm", 4: "k_root", 5: "k_grad"}
+KERNEL_SOURCES = ["paper_2205_10091_amd/csrc/exec.hip", "paper_2205_10091_amd/csrc/gemm.hip",
+                  "paper_2205_10091_amd/csrc/gates.h", "paper_2205_10091_amd/csrc/ops.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def roofline(profile):
-    """Dominant kernel (most time) over one step, with its algorithmic
-    bytes / flops per launch over its mean launch duration."""
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs, or
+    None if they are missing or the kernels changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload, {}).get(kernel)
+    if not e or t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
+def roofline(profile, workload):
+    """Dominant kernel (most time over a step) with its algorithmic bytes /
+    flops per launch over its mean launch duration."""
     kinds, ms, flops, by = profile
     agg = {}
     for k, t, f, b in zip(kinds, ms, flops, by):
@@ -42,21 +73,18 @@ def roofline(profile):
     k, (t, f, b, n) = max(agg.items(), key=lambda kv: kv[1][0])
     secs = t / 1e3
     ai = f / b if b else 0.0
+    name = KIND_NAMES[k]
     if ai > PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
-        ach = f / secs / 1e12
-        rl = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
+        rl = {"bound": "alu" if name != "k_gemm" else "mfma",
+              "achieved": f / secs / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
     else:
-        ach = b / secs / 1e9
-        rl = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        rl = {"bound": "hbm", "achieved": b / secs / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     rl["frac"] = rl["achieved"] / rl["peak"]
-    rl["traffic"] = None
-    rl["kernel"] = KIND_NAMES[k]
-    rl["launches_per_step"] = n
-    rl["mean_launch_us"] = t / n * 1e3
-    rl["alg_bytes_per_launch"] = b / n
-    rl["alg_flops_per_launch"] = f / n
-    share = {KIND_NAMES[kk]: round(v[0] / sum(x[0] for x in agg.values()), 4)
-             for kk, v in agg.items()}
+    rl["traffic"] = measured_traffic(workload, name)
+    rl.update({"kernel": name, "launches_per_step": n, "mean_launch_us": t / n * 1e3,
+               "alg_bytes_per_launch": b / n, "alg_flops_per_launch": f / n})
+    tot = sum(x[0] for x in agg.values())
+    share = {KIND_NAMES[kk]: round(v[0] / tot, 4) for kk, v in agg.items()}
     return rl, share
 
 
@@ -78,14 +106,28 @@ def cpu_baseline(circ, p, obs, budget_s=15.0):
                       f"({dt:.1f} s)"}
 
 
+def timed(step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--workload", default="vqe", choices=["vqe", "batched", "forward", "grid"])
     ap.add_argument("--trials", type=int, default=32, help="greedy path trials")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the contraction path is built and "
@@ -95,79 +137,105 @@ def main():
 
     import torch
     import tcgen
+    from oracle import statevector as sv
     from paper_2205_10091_amd import api
 
     dev = torch.device("cuda:0")
-    circ, p, obs = tcgen.workload_vqe_chain()
-    t0 = time.perf_counter()
-    plan = api.compile(circ, obs, want_grad=True, n_trials=args.trials, seed=1)
-    plan_s = time.perf_counter() - t0
-    info = plan.info()
-    params = torch.from_numpy(p).to(dev)
+    out = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic (seeded angles)"}
 
-    for _ in range(args.warmup):
-        e, g = plan.contract_grad(params)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e, g = plan.contract_grad(params)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt / args.steps * 1e3
-    value = args.steps / dt
+    if args.workload in ("vqe", "batched"):
+        B = 1 if args.workload == "vqe" else 1024
+        if B == 1:
+            circ, p, obs = tcgen.workload_vqe_chain()
+            P = p
+        else:
+            circ, P, obs = tcgen.workload_batched_vqe(batch=B)
+        t0 = time.perf_counter()
+        plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=args.trials, seed=1)
+        plan_s = time.perf_counter() - t0
+        params = torch.from_numpy(np.ascontiguousarray(P.reshape(-1))).to(dev)
+        dt, (e, g) = timed(lambda: plan.contract_grad(params), args.steps, args.warmup)
+        info = plan.info()
+        out.update({
+            "metric": "circuit evals/s (TFIM energy + 240-entry gradient, 20-qubit chain, "
+                      "39 Pauli-term networks)",
+            "value": B * args.steps / dt, "unit": "evals/s", "ms_per_step": dt / args.steps * 1e3,
+            "dtype": "c64 (fp32) + fp64 sums",
+            "config": {"workload": f"vqe_chain_n20_L6_tfim_energy_grad_batch{B}",
+                       "n_qubits": 20, "layers": 6, "n_params": 240, "n_terms": 39,
+                       "batch": B, "path_trials": args.trials},
+            "achieved_tflops": (info.flops + info.grad_flops) / (dt / args.steps) / 1e12})
+        prof = plan.profile(params, which=1, reps=20 if B == 1 else 2)
+        rl, share = roofline(prof, args.workload)
+        b0 = 7 if B > 1 else 0
+        e_ref, g_ref = sv.energy_grad(circ, P.reshape(B, -1)[b0], obs)
+        out["rel_err_energy"] = abs(e[b0] - e_ref) / max(abs(e_ref), 1.0)
+        out["rel_err_grad"] = float(np.linalg.norm(g[b0] - g_ref) /
+                                    max(np.linalg.norm(g_ref), 1.0))
+    elif args.workload == "forward":
+        circ, p, zz, amp = tcgen.workload_forward_chain()
+        t0 = time.perf_counter()
+        pa = api.compile(circ, amp, n_trials=args.trials, seed=1)
+        pz = api.compile(circ, zz, n_trials=args.trials, seed=1)
+        plan_s = time.perf_counter() - t0
+        params = torch.from_numpy(p).to(dev)
+        dt, _ = timed(lambda: (pa.contract(params), pz.contract(params)), args.steps,
+                      args.warmup)
+        a, z = pa.contract(params)[0], pz.contract(params)[0]
+        info = pz.info()
+        out.update({"metric": "circuit evals/s (10-qubit brickwork: amplitude and <Z0 Z1>)",
+                    "value": args.steps / dt, "unit": "evals/s",
+                    "ms_per_step": dt / args.steps * 1e3, "dtype": "c64 (fp32)",
+                    "config": {"workload": "brickwork_n10_L4_amp_zz", "batch": 1}})
+        prof = pz.profile(params, which=0, reps=20)
+        rl, share = roofline(prof, args.workload)
+        out["rel_err_amplitude"] = abs(a - sv.amplitude(circ, p)) / max(abs(sv.amplitude(circ, p)), 2 ** -5)
+        out["rel_err_zz"] = abs(z - sv.energy(circ, p, zz))
+    else:
+        circ, p, amp = tcgen.workload_grid_amplitude()
+        t0 = time.perf_counter()
+        plan = api.compile(circ, amp, n_trials=args.trials, seed=1)
+        plan_s = time.perf_counter() - t0
+        params = torch.from_numpy(p).to(dev)
+        dt, v = timed(lambda: plan.contract(params), args.steps, args.warmup)
+        info = plan.info()
+        out.update({"metric": "circuit evals/s (6x6 fSim grid amplitude, depth 8)",
+                    "value": args.steps / dt, "unit": "evals/s",
+                    "ms_per_step": dt / args.steps * 1e3, "dtype": "c64 (fp32)",
+                    "config": {"workload": "grid6x6_d8_amplitude", "batch": 1},
+                    "achieved_tflops": info.flops / (dt / args.steps) / 1e12})
+        prof = plan.profile(params, which=0, reps=20)
+        rl, share = roofline(prof, args.workload)
+        ref = json.load(open(os.path.join(ROOT, "tests/golden/grid6x6_d8_amplitude.json")))
+        r = complex(ref["values"]["col2"]["re"], ref["values"]["col2"]["im"])
+        out["rel_err_amplitude"] = abs(v[0] - r) / max(abs(r), 2 ** -18)
 
-    # live per-launch timing (HIP events on the plan's stream, eager replay)
-    prof = plan.profile(params, which=1, reps=20)
-    rl, share = roofline(prof)
+    out["plan"] = {"flops": info.flops, "grad_flops": info.grad_flops,
+                   "alg_bytes": info.alg_bytes + info.grad_alg_bytes,
+                   "workspace_bytes": int(info.workspace_bytes), "nodes": info.n_nodes,
+                   "gemm_nodes": info.n_gemm_nodes, "levels": info.n_levels,
+                   "launches_per_step": info.n_launches + info.n_grad_launches,
+                   "plan_seconds": plan_s}
+    out["roofline"] = rl
+    out["time_share_by_kernel"] = share
+    out["kernel_source_hash"] = kernel_source_hash()
 
-    out = {
-        "metric": "circuit evals/s (TFIM energy + 240-entry gradient, 20-qubit chain, "
-                  "39 Pauli-term networks)",
-        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32) + fp64 sums",
-        "data": "synthetic (seeded angles)",
-        "config": {"workload": "vqe_chain_n20_L6_tfim_energy_grad", "n_qubits": 20,
-                   "layers": 6, "n_params": 240, "n_terms": 39, "batch": 1,
-                   "path_trials": args.trials},
-        "achieved_tflops": (info.flops + info.grad_flops) / (dt / args.steps) / 1e12,
-        "plan": {"flops": info.flops, "grad_flops": info.grad_flops,
-                 "alg_bytes": info.alg_bytes + info.grad_alg_bytes,
-                 "workspace_bytes": int(info.workspace_bytes), "nodes": info.n_nodes,
-                 "levels": info.n_levels,
-                 "launches_per_step": info.n_launches + info.n_grad_launches,
-                 "plan_seconds": plan_s},
-        "roofline": rl, "time_share_by_kernel": share,
-    }
-
-    # error of the timed result against the oracle
-    from oracle import statevector as sv
-    e_ref, g_ref = sv.energy_grad(circ, p, obs)
-    out["rel_err_energy"] = abs(e[0] - e_ref) / max(abs(e_ref), 1.0)
-    out["rel_err_grad"] = float(np.linalg.norm(g[0] - g_ref) / max(np.linalg.norm(g_ref), 1.0))
-
-    if not args.no_extras:
-        # batched sweep: 1024 parameter vectors per launch
+    if args.workload == "vqe" and not args.no_extras:
+        # batched sweep: 1024 parameter vectors per launch vs the plain form
         B = 1024
         circ4, P4, obs4 = tcgen.workload_batched_vqe(batch=B)
         plan4 = api.compile(circ4, obs4, batch=B, want_grad=True, n_trials=args.trials, seed=1)
         par4 = torch.from_numpy(P4.reshape(-1)).to(dev)
-        plan4.contract_grad(par4)
-        torch.cuda.synchronize()
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            e4, g4 = plan4.contract_grad(par4)
-        torch.cuda.synchronize()
-        d4 = (time.perf_counter() - t0) / reps
+        d4, (e4, g4) = timed(lambda: plan4.contract_grad(par4), 3, 1)
         i4 = plan4.info()
-        rl4, share4 = roofline(plan4.profile(par4, which=1, reps=1))
-        e4_ref, g4_ref = sv.energy_grad(circ4, P4[7], obs4)
+        rl4, share4 = roofline(plan4.profile(par4, which=1, reps=1), "batched")
+        e4_ref, _ = sv.energy_grad(circ4, P4[7], obs4)
         out["batched"] = {
-            "workload": "vqe_chain_n20_L6_batch1024", "evals_per_s": B / d4,
-            "ms_per_launch": d4 * 1e3,
-            "vs_plain_per_circuit": (B / d4) / value,
-            "achieved_tflops": (i4.flops + i4.grad_flops) / d4 / 1e12,
+            "workload": "vqe_chain_n20_L6_batch1024", "evals_per_s": 3 * B / d4,
+            "ms_per_launch": d4 / 3 * 1e3, "vs_plain_per_circuit": (3 * B / d4) / out["value"],
+            "achieved_tflops": (i4.flops + i4.grad_flops) / (d4 / 3) / 1e12,
             "roofline": rl4, "time_share_by_kernel": share4,
             "rel_err_row7": abs(e4[7] - e4_ref) / max(abs(e4_ref), 1.0)}
         del plan4
@@ -188,9 +256,24 @@ def main():
                                            "p99": float(np.percentile(lat, 99)),
                                            "evals_per_s": 1e6 / float(np.mean(lat))}
 
-    if not args.no_cpu_baseline:
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 4 * n
+
+    if args.workload == "vqe" and not args.no_cpu_baseline:
+        circ, p, obs = tcgen.workload_vqe_chain()
         out["cpu_baseline"] = cpu_baseline(circ, p, obs)
-    print(json.dumps(out), flush=True)
+    order = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+             "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+             "roofline", "cpu_baseline"]
+    line = {k: out[k] for k in order if k in out}
+    line.update({k: v for k, v in out.items() if k not in line})
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
