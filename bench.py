@@ -31,8 +31,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
-KIND_NAMES = {0: "k_leaf", 1: "k_gc", 2: "k_gcw", 3: "k_gemm", 4: "k_root", 5: "k_grad"}
-KERNEL_SOURCES = ["paper_2205_10091_amd/csrc/exec.hip", "paper_2205_10091_amd/csrc/gemm.hip",
+KIND_NAMES = {0: "k_leaf", 1: "k_level", 4: "k_root", 5: "k_grad"}
+KERNEL_SOURCES = ["paper_2205_10091_amd/csrc/exec.hip", "paper_2205_10091_amd/csrc/gemm_tile.h",
                   "paper_2205_10091_amd/csrc/gates.h", "paper_2205_10091_amd/csrc/ops.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -75,7 +75,7 @@ def roofline(profile, workload):
     ai = f / b if b else 0.0
     name = KIND_NAMES[k]
     if ai > PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
-        rl = {"bound": "alu" if name != "k_gemm" else "mfma",
+        rl = {"bound": "alu",
               "achieved": f / secs / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
     else:
         rl = {"bound": "hbm", "achieved": b / secs / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}

@@ -103,7 +103,7 @@ typedef struct {
  * AMPLITUDE: <bits|U|0...0> (section "Basic circuits and outputs").
  * PAULI_SUM: sum_j weights[j] <psi|P_j|psi> with structure vectors
  * structures[j*n_qubits + q] in {0=I,1=X,2=Y,3=Z} (section "Pauli structures
- * and weights").  The weighted sum is reduced in FP64 in term order.
+ * and weights").  The weighted sum is reduced in FP64 in a fixed order.
  */
 typedef enum { TC_OBS_AMPLITUDE = 0, TC_OBS_PAULI_SUM = 1 } tc_obs_kind;
 
@@ -326,8 +326,9 @@ tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
  * `reps` times with HIP events around every launch on the plan's stream;
  * params is a DEVICE pointer as for tc_contract.  For launch i <
  * *n_launches (at most `cap` are written) it reports the kernel class
- * kinds[i] (0 leaf materialisation, 1 gather contraction, 2 wavefront
- * gather contraction, 3 MFMA GEMM, 4 FP64 root sum, 5 FP64 gradient sum),
+ * kinds[i] (0 leaf materialisation, 1 contraction level: MFMA GEMM tiles
+ * and gather contractions of one tree level, 4 FP64 root sum, 5 FP64
+ * gradient sum),
  * the mean duration ms[i], and the launch's algorithmic flops[i] and
  * bytes[i] (operands read once plus results written once).  which: 0 the
  * forward sequence, 1 forward plus reverse sweep (needs want_grad). */

@@ -79,9 +79,12 @@ class Network:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None) and L._lib is not None:
-            L._lib.tc_network_free(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None) and L._lib is not None:
+                L._lib.tc_network_free(self.h)
+                self.h = None
+        except (AttributeError, TypeError):  # interpreter shutdown
+            pass
 
     def info(self) -> L.NetworkInfo:
         out = L.NetworkInfo()
@@ -114,9 +117,12 @@ class Path:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None) and L._lib is not None:
-            L._lib.tc_path_free(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None) and L._lib is not None:
+                L._lib.tc_path_free(self.h)
+                self.h = None
+        except (AttributeError, TypeError):  # interpreter shutdown
+            pass
 
     def stats(self, term: int = -1) -> L.PathStats:
         out = L.PathStats()
@@ -151,12 +157,16 @@ class Plan:
         L.check(lib().tc_plan_create(net.h, path.h, C.byref(opts), C.byref(h)))
         self.h = h
         self.workspace = None
+        self.torch_stream = None
         self.n_params = net.circ.n_params
 
     def __del__(self):
-        if getattr(self, "h", None) and L._lib is not None:
-            L._lib.tc_plan_free(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None) and L._lib is not None:
+                L._lib.tc_plan_free(self.h)
+                self.h = None
+        except (AttributeError, TypeError):  # interpreter shutdown
+            pass
 
     def info(self) -> L.PlanInfo:
         out = L.PlanInfo()
@@ -189,6 +199,9 @@ class Plan:
         if params.numel() != self.batch * self.n_params:
             raise ValueError(f"params must hold batch*n_params = "
                              f"{self.batch * self.n_params} floats")
+        if self.torch_stream is not None:
+            # parameters written on torch's current stream are visible to the plan
+            self.torch_stream.wait_stream(torch.cuda.current_stream(params.device))
         return C.c_void_p(params.data_ptr())
 
     def contract(self, params) -> np.ndarray:
@@ -238,8 +251,68 @@ def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
     """Network + greedy path + plan (+ bind with a torch workspace)."""
     net = Network(circ, obs, split_2q, lightcone, absorb_1q)
     path = Path(net, seed=seed, n_trials=n_trials)
+    torch_stream = None
+    if stream is None and bind:
+        # a dedicated torch stream (default priority): torch work orders
+        # around the plan with wait_stream, and the plan's HIP graph is
+        # captured on a real stream rather than the null stream
+        import torch
+        torch_stream = torch.cuda.Stream(device=f"cuda:{device}")
+        stream = torch_stream.cuda_stream
     plan = Plan(net, path, batch, want_grad, precision, device, mem_budget_bytes,
                 stream, gemm_min_k)
+    plan.torch_stream = torch_stream
     if bind:
         plan.bind_torch(f"cuda:{device}")
     return plan
+
+
+def _make_function():
+    import torch
+
+    class TCContract(torch.autograd.Function):
+        """E(params) = Re sum_j alpha_j <P_j> through the HIP plan.
+
+        forward runs the plan's forward sweep and reverse sweep in one call
+        (tc_contract_grad_device: values and dE/dparams land in device
+        buffers on the plan's stream); backward scales the stored gradient by
+        the incoming gradient.  params: [batch, n_params] float32 on the GPU;
+        returns [batch] float64.  The plan must be compiled with
+        want_grad=True and bound to the current stream's device."""
+
+        @staticmethod
+        def forward(ctx, params, plan):
+            p = params.detach().contiguous()
+            if p.dtype != torch.float32:
+                p = p.float()
+            value = torch.empty(plan.batch, dtype=torch.float64, device=p.device)
+            grad = torch.empty(plan.batch, plan.n_params, dtype=torch.float64, device=p.device)
+            cur = torch.cuda.current_stream(p.device)
+            ps = getattr(plan, "torch_stream", None)
+            if ps is None:
+                raise ValueError("compile the plan with api.compile(..., bind=True) so that it "
+                                 "runs on a torch stream")
+            ps.wait_stream(cur)           # params ready before the plan reads them
+            plan.contract_grad_device(p, value, grad)
+            cur.wait_stream(ps)           # results ready before torch reads them
+            ctx.save_for_backward(grad)
+            ctx.in_dtype = params.dtype
+            return value
+
+        @staticmethod
+        def backward(ctx, g_out):
+            (grad,) = ctx.saved_tensors
+            return (g_out.to(grad.dtype)[:, None] * grad).to(ctx.in_dtype), None
+
+    return TCContract
+
+
+_TCContract = None
+
+
+def tc_contract(params, plan):
+    """Differentiable energy: torch.autograd.Function over the reverse sweep."""
+    global _TCContract
+    if _TCContract is None:
+        _TCContract = _make_function()
+    return _TCContract.apply(params, plan)

@@ -16,7 +16,7 @@ OUT = os.path.join(PKG, "libtcx.so")
 BUILD = os.path.join(ROOT, "_build")
 
 HOST = ["network.cpp", "path.cpp", "plan.cpp", "capi_host.cpp", "serve.cpp"]
-DEVICE = ["exec.hip", "gemm.hip"]
+DEVICE = ["exec.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", os.path.join(ROOT, "include"),

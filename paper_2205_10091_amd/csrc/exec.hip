@@ -17,7 +17,7 @@
 #include <vector>
 
 #include "gates.h"
-#include "gemm.h"
+#include "gemm_tile.h"
 #include "plan.h"
 
 struct tc_network;
@@ -80,111 +80,167 @@ __global__ void __launch_bounds__(256) k_leaf(const DevLeaf* __restrict__ leaves
   }
 }
 
-// Gather contraction: one thread per output element (row, m, n), summing K
-// products read through the index tables.
-__global__ void __launch_bounds__(256) k_gc(const DevOp* __restrict__ ops, uint32_t n_ops,
-                                            const uint32_t* __restrict__ tab,
-                                            float2* __restrict__ arena, uint64_t total) {
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
-       w += (uint64_t)gridDim.x * blockDim.x) {
-    const DevOp& op = ops[find_item(ops, n_ops, w)];
-    const uint64_t l = w - op.work0;
-    const uint32_t ln = __builtin_ctz(op.N), lm = __builtin_ctz(op.M);
-    const uint32_t n = (uint32_t)(l & (op.N - 1));
-    const uint32_t m = (uint32_t)((l >> ln) & (op.M - 1));
-    const uint64_t r = l >> (ln + lm);
-    const float2* __restrict__ A = arena + op.a + r * op.a_bs + tab[op.a_m + m];
-    const float2* __restrict__ Bp = arena + op.b + r * op.b_bs + tab[op.b_n + n];
-    const uint32_t* __restrict__ ak = tab + op.a_k;
-    const uint32_t* __restrict__ bk = tab + op.b_k;
-    c32 acc = cx(0.f, 0.f);
-    const uint32_t K = op.K;
-    for (uint32_t k = 0; k < K; ++k) cfma(acc, A[ak[k]], Bp[bk[k]]);
-    arena[op.c + r * op.c_bs + tab[op.c_m + m] + tab[op.c_n + n]] =
-        make_float2(acc.re, acc.im);
-  }
-}
+// One contraction level: blocks [0, gemm_blocks) run 64 x 64 MFMA GEMM tiles,
+// the remaining blocks run the gather contractions of the same level.
+//
+// Gather item: an op with k-split S = 2^ls and n-vector V = 2^lv assigns S
+// consecutive lanes to a group of V outputs (row, m, n0 .. n0+V-1); lane
+// `sub` sums k = sub, sub + S, ... and the S lanes combine by butterfly
+// shuffles.  Ops with S > 1 start and end on wavefront boundaries (the
+// planner pads them), so every lane of such a wave runs the same shuffles.
+struct LevelArgs {
+  const DevOp* gemm_ops;
+  uint32_t n_gemm;
+  uint32_t gemm_blocks;
+  uint64_t gemm_tiles;
+  const DevOp* gc_ops;
+  uint32_t n_gc;
+  uint64_t gc_work;
+  const uint32_t* tab;
+  float2* arena;
+};
 
-// Gather contraction with one wavefront per output element, for long sums
-// into few outputs; lanes stride over k and reduce by butterfly shuffles.
-__global__ void __launch_bounds__(256) k_gcw(const DevOp* __restrict__ ops, uint32_t n_ops,
-                                             const uint32_t* __restrict__ tab,
-                                             float2* __restrict__ arena, uint64_t total) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t wv = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wv * 64 < total;
-       wv += waves) {
-    const uint64_t w = wv * 64;
-    const DevOp& op = ops[find_item(ops, n_ops, w)];
-    const uint64_t l = (w - op.work0) >> 6;
-    const uint32_t ln = __builtin_ctz(op.N), lm = __builtin_ctz(op.M);
-    const uint32_t n = (uint32_t)(l & (op.N - 1));
-    const uint32_t m = (uint32_t)((l >> ln) & (op.M - 1));
-    const uint64_t r = l >> (ln + lm);
-    const float2* __restrict__ A = arena + op.a + r * op.a_bs + tab[op.a_m + m];
-    const float2* __restrict__ Bp = arena + op.b + r * op.b_bs + tab[op.b_n + n];
-    const uint32_t* __restrict__ ak = tab + op.a_k;
-    const uint32_t* __restrict__ bk = tab + op.b_k;
-    c32 acc = cx(0.f, 0.f);
-    for (uint32_t k = lane; k < op.K; k += 64) cfma(acc, A[ak[k]], Bp[bk[k]]);
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.re += __shfl_xor(acc.re, off, 64);
-      acc.im += __shfl_xor(acc.im, off, 64);
+template <int PREC>
+__global__ void __launch_bounds__(256) k_level(LevelArgs a) {
+  if (blockIdx.x < a.gemm_blocks) {
+    if constexpr (PREC == TC_PREC_BF16X3) {
+      __shared__ SmemBF16 smem;
+      for (uint64_t tile = blockIdx.x; tile < a.gemm_tiles; tile += a.gemm_blocks) {
+        const DevOp& op = a.gemm_ops[find_item(a.gemm_ops, a.n_gemm, tile)];
+        gemm_tile_bf16x3(op, tile, a.tab, a.arena, smem);
+      }
+    } else {
+      __shared__ SmemF32 smem;
+      for (uint64_t tile = blockIdx.x; tile < a.gemm_tiles; tile += a.gemm_blocks) {
+        const DevOp& op = a.gemm_ops[find_item(a.gemm_ops, a.n_gemm, tile)];
+        gemm_tile_f32(op, tile, a.tab, a.arena, smem);
+      }
     }
-    if (lane == 0)
-      arena[op.c + r * op.c_bs + tab[op.c_m + m] + tab[op.c_n + n]] =
-          make_float2(acc.re, acc.im);
+    return;
+  }
+  const uint32_t* __restrict__ tab = a.tab;
+  float2* __restrict__ arena = a.arena;
+  const uint64_t stride = (uint64_t)(gridDim.x - a.gemm_blocks) * blockDim.x;
+  for (uint64_t w = (uint64_t)(blockIdx.x - a.gemm_blocks) * blockDim.x + threadIdx.x;
+       w < a.gc_work; w += stride) {
+    const DevOp& op = a.gc_ops[find_item(a.gc_ops, a.n_gc, w)];
+    const uint32_t ls = (op.flags >> 4) & 7u, lv = (op.flags >> 8) & 3u;
+    const uint32_t S = 1u << ls, V = 1u << lv;
+    const uint64_t l = w - op.work0;
+    const uint32_t ln = __builtin_ctz(op.N) - lv, lm = __builtin_ctz(op.M);
+    const uint64_t e = l >> ls;
+    const uint32_t sub = (uint32_t)(l & (S - 1));
+    const bool valid = e < ((uint64_t)op.rows << (ln + lm));
+    c32 acc[4] = {cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f)};
+    uint32_t m = 0, n0 = 0;
+    uint64_t r = 0;
+    if (valid) {
+      n0 = (uint32_t)(e & ((1u << ln) - 1)) << lv;
+      m = (uint32_t)((e >> ln) & (op.M - 1));
+      r = e >> (ln + lm);
+      const float2* __restrict__ A = arena + op.a + r * op.a_bs + tab[op.a_m + m];
+      const float2* __restrict__ Bp = arena + op.b + r * op.b_bs;
+      const uint32_t* __restrict__ ak = tab + op.a_k;
+      const uint32_t* __restrict__ bk = tab + op.b_k;
+      uint32_t bn[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? tab[op.b_n + n0 + j] : 0u;
+      const uint32_t K = op.K;
+      if (V == 4) {
+        for (uint32_t k = sub; k < K; k += S) {
+          const float2 av = A[ak[k]];
+          const float2* __restrict__ bb = Bp + bk[k];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cfma(acc[j], av, bb[bn[j]]);
+        }
+      } else {
+        for (uint32_t k = sub; k < K; k += S) {
+          const float2 av = A[ak[k]];
+          const float2* __restrict__ bb = Bp + bk[k];
+          for (uint32_t j = 0; j < V; ++j) cfma(acc[j], av, bb[bn[j]]);
+        }
+      }
+    }
+    if (S > 1) {
+      // V == 1 whenever S > 1
+      for (uint32_t off = S >> 1; off > 0; off >>= 1) {
+        acc[0].re += __shfl_xor(acc[0].re, (int)off, 64);
+        acc[0].im += __shfl_xor(acc[0].im, (int)off, 64);
+      }
+    }
+    if (valid && sub == 0) {
+      const uint64_t cb = op.c + r * op.c_bs + tab[op.c_m + m];
+      for (uint32_t j = 0; j < V; ++j)
+        arena[cb + tab[op.c_n + n0 + j]] = make_float2(acc[j].re, acc[j].im);
+    }
   }
 }
 
-// E[b] = sum_j alpha_j T_j[b] in FP64, terms in order.
-__global__ void k_root(const DevRoot* __restrict__ roots, uint32_t n_terms,
-                       const float2* __restrict__ arena, double* __restrict__ value,
-                       uint32_t batch) {
-  uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
+// E[b] = sum_j alpha_j T_j[b] in FP64: one wavefront per batch row, lane l
+// takes terms l, l + 64, ...; the 64 partial sums combine in a fixed
+// butterfly order (deterministic).
+__global__ void __launch_bounds__(256) k_root(const DevRoot* __restrict__ roots,
+                                              uint32_t n_terms,
+                                              const float2* __restrict__ arena,
+                                              double* __restrict__ value, uint32_t batch) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (b >= batch) return;  // whole wavefronts leave together
   double re = 0.0, im = 0.0;
-  for (uint32_t j = 0; j < n_terms; ++j) {
+  for (uint32_t j = lane; j < n_terms; j += 64) {
     const DevRoot& R = roots[j];
     double vr = 1.0, vi = 0.0;
     if (R.present) {
-      float2 v = arena[R.val + (uint64_t)b * R.bs];
+      float2 v = arena[R.val + b * R.bs];
       vr = v.x;
       vi = v.y;
     }
     re += R.weight * vr;
     im += R.weight * vi;
   }
-  value[2 * b] = re;
-  value[2 * b + 1] = im;
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (lane == 0) {
+    value[2 * b] = re;
+    value[2 * b + 1] = im;
+  }
 }
 
-// grad[b][slot] = Re sum_{uses of slot} sum_e adj[e] dleaf[e]/dangle, FP64.
-__global__ void k_grad(const DevGradUse* __restrict__ uses,
-                       const uint32_t* __restrict__ slot_begin,
-                       const DevLeaf* __restrict__ leaves, const float* __restrict__ params,
-                       int32_t n_params, const float2* __restrict__ arena,
-                       double* __restrict__ grad, uint64_t total) {
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
-       w += (uint64_t)gridDim.x * blockDim.x) {
+// grad[b][slot] = Re sum_{uses of slot} sum_e adj[e] dleaf[e]/dangle in FP64:
+// one wavefront per (row, slot), lanes over the slot's uses, fixed-order
+// butterfly combination.
+__global__ void __launch_bounds__(256) k_grad(const DevGradUse* __restrict__ uses,
+                                              const uint32_t* __restrict__ slot_begin,
+                                              const DevLeaf* __restrict__ leaves,
+                                              const float* __restrict__ params,
+                                              int32_t n_params,
+                                              const float2* __restrict__ arena,
+                                              double* __restrict__ grad, uint64_t total) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < total;
+       w += waves) {
     const uint64_t b = w / (uint32_t)n_params;
     const uint32_t slot = (uint32_t)(w - b * (uint32_t)n_params);
     const float* pr = params + b * (uint64_t)n_params;
     double acc = 0.0;
-    for (uint32_t u = slot_begin[slot]; u < slot_begin[slot + 1]; ++u) {
+    for (uint32_t u = slot_begin[slot] + lane; u < slot_begin[slot + 1]; u += 64) {
       const DevGradUse& U = uses[u];
       const DevLeaf& L = leaves[U.leaf];
       float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
       float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
-      const float2* a = arena + U.adj + b * U.adj_bs;
+      const float2* ad = arena + U.adj + b * U.adj_bs;
       const int ne = 1 << L.rank;
       for (int e = 0; e < ne; ++e) {
         c32 d = dleaf_entry(L, e, t0, t1, U.which);
-        float2 x = a[e];
+        float2 x = ad[e];
         acc += (double)x.x * d.re - (double)x.y * d.im;
       }
     }
-    grad[w] = acc;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) grad[w] = acc;
   }
 }
 
@@ -230,33 +286,43 @@ static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& se
   double* grad = (double*)(ws + L.grad);
   float2* arena = (float2*)(ws + L.arena);
   for (const Launch& x : seq) {
-    if (x.work == 0) continue;
     switch (x.kind) {
       case L_LEAF:
+        if (x.work == 0) continue;
         hipLaunchKernelGGL(k_leaf, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
                            leaves, (uint32_t)P.leaves.size(), ftab, params, P.n_params, arena,
                            x.work);
         break;
-      case L_GC:
-        hipLaunchKernelGGL(k_gc, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
-                           ops + x.begin, x.end - x.begin, tabs, arena, x.work);
+      case L_LEVEL: {
+        LevelArgs a;
+        a.gemm_ops = ops + x.gbegin;
+        a.n_gemm = x.gend - x.gbegin;
+        a.gemm_tiles = x.tiles;
+        a.gemm_blocks = (uint32_t)std::min<uint64_t>(x.tiles, (uint64_t)D.n_cu * 8);
+        a.gc_ops = ops + x.begin;
+        a.n_gc = x.end - x.begin;
+        a.gc_work = x.work;
+        a.tab = tabs;
+        a.arena = arena;
+        unsigned gcb = x.work ? grid_for(x.work, 256, D.n_cu) : 0u;
+        unsigned grid = a.gemm_blocks + gcb;
+        if (grid == 0) continue;
+        if (P.precision == TC_PREC_BF16X3)
+          hipLaunchKernelGGL(k_level<TC_PREC_BF16X3>, dim3(grid), dim3(256), 0, D.stream, a);
+        else
+          hipLaunchKernelGGL(k_level<TC_PREC_C64>, dim3(grid), dim3(256), 0, D.stream, a);
         break;
-      case L_GCW:
-        hipLaunchKernelGGL(k_gcw, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
-                           ops + x.begin, x.end - x.begin, tabs, arena, x.work);
-        break;
-      case L_GEMM:
-        launch_gemm(ops + x.begin, x.end - x.begin, tabs, arena, x.work, P.precision,
-                    D.stream, D.n_cu);
-        break;
+      }
       case L_ROOT:
-        hipLaunchKernelGGL(k_root, dim3((unsigned)((x.work + 255) / 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_root, dim3((unsigned)((x.work * 64 + 255) / 256)), dim3(256), 0,
                            D.stream, roots, (uint32_t)P.roots.size(), arena, value,
                            (uint32_t)P.batch);
         break;
       case L_GRAD:
-        hipLaunchKernelGGL(k_grad, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
-                           uses, slot_begin, leaves, params, P.n_params, arena, grad, x.work);
+        if (x.work == 0) continue;
+        hipLaunchKernelGGL(k_grad, dim3(grid_for(x.work * 64, 256, D.n_cu)), dim3(256), 0,
+                           D.stream, uses, slot_begin, leaves, params, P.n_params, arena, grad,
+                           x.work);
         break;
     }
     HIP_CHECK(hipGetLastError());

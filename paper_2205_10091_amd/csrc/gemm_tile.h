@@ -1,4 +1,5 @@
-// LDS-tiled MFMA complex GEMM for the wider tree nodes.
+// LDS-tiled MFMA complex GEMM tiles for the wider tree nodes (device code,
+// included by the executor).
 //
 // Paper, section "Tensor network engine": each pairwise contraction is
 // executed as an einsum / matmul.  A node C[m, n] = sum_k A[m, k] B[k, n]
@@ -15,12 +16,10 @@
 //           on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
 // A workgroup of four wavefronts computes a 64 x 64 tile of C; each wave a
 // 32 x 32 quarter as 2 x 2 blocks of 16 x 16.
+#pragma once
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-
-#include "gemm.h"
-#include "internal.h"
+#include "ops.h"
 
 namespace tcx {
 
@@ -31,19 +30,6 @@ constexpr int BM = 64, BN = 64;
 constexpr int BK32 = 16;   // k per LDS stage, FP32 path
 constexpr int BK16 = 32;   // k per LDS stage, split-BF16 path
 constexpr int PAD = 16;    // row padding (floats) against LDS bank conflicts
-
-__device__ __forceinline__ uint32_t find_tile(const DevOp* __restrict__ ops, uint32_t n,
-                                              uint64_t w) {
-  uint32_t lo = 0, hi = n;
-  while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (ops[mid].work0 <= w)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
 
 struct TileCtx {
   const float2* A;
@@ -88,18 +74,21 @@ __device__ __forceinline__ void store_tile(const DevOp& op, const TileCtx& t,
 
 // ------------------------------------------------------------------ FP32
 
-__global__ void __launch_bounds__(256) k_gemm_f32(const DevOp* __restrict__ ops,
-                                                  uint32_t n_ops,
-                                                  const uint32_t* __restrict__ tab,
-                                                  float2* __restrict__ arena,
-                                                  uint64_t total) {
-  __shared__ float As[2][BK32][BM + PAD];  // [re/im][k][m]
-  __shared__ float Bs[2][BK32][BN + PAD];  // [re/im][k][n]
+struct SmemF32 {
+  float A[2][BK32][BM + PAD];  // [re/im][k][m]
+  float B[2][BK32][BN + PAD];  // [re/im][k][n]
+};
+
+// One 64 x 64 tile of C for the FP32 path; called by all 256 threads.
+__device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
+                                              const uint32_t* __restrict__ tab,
+                                              float2* __restrict__ arena, SmemF32& S) {
+  auto& As = S.A;
+  auto& Bs = S.B;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  for (uint64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-    const DevOp& op = ops[find_tile(ops, n_ops, tile)];
+  {
     const TileCtx c = tile_ctx(op, tile, arena);
     const bool akf = op.flags & 1u, bkf = op.flags & 2u;
     // fixed row / column offsets of this thread's loads
@@ -177,19 +166,22 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-__global__ void __launch_bounds__(256) k_gemm_bf16x3(const DevOp* __restrict__ ops,
-                                                     uint32_t n_ops,
-                                                     const uint32_t* __restrict__ tab,
-                                                     float2* __restrict__ arena,
-                                                     uint64_t total) {
+struct SmemBF16 {
   // [re/im][hi/lo][row][k], k contiguous so that a lane reads 8 k at once
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][BM][BK16 + 8];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][BN][BK16 + 8];
+  __attribute__((aligned(16))) __bf16 A[2][2][BM][BK16 + 8];
+  __attribute__((aligned(16))) __bf16 B[2][2][BN][BK16 + 8];
+};
+
+// One 64 x 64 tile of C for the split-BF16 path; called by all 256 threads.
+__device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
+                                                 const uint32_t* __restrict__ tab,
+                                                 float2* __restrict__ arena, SmemBF16& S) {
+  auto& As = S.A;
+  auto& Bs = S.B;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  for (uint64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-    const DevOp& op = ops[find_tile(ops, n_ops, tile)];
+  {
     const TileCtx c = tile_ctx(op, tile, arena);
     const bool akf = op.flags & 1u, bkf = op.flags & 2u;
     uint32_t aoff[8], boff[8];
@@ -271,18 +263,6 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const DevOp* __restrict__ o
       for (int j = 0; j < 2; ++j) cr[i][j] = pr[i][j] - pq[i][j];
     store_tile(op, c, tab, arena, cr, ci, wm, wn, lane);
   }
-}
-
-void launch_gemm(const DevOp* ops, uint32_t n_ops, const uint32_t* tabs, float2* arena,
-                 uint64_t tiles, int precision, hipStream_t stream, int n_cu) {
-  uint64_t cap = (uint64_t)n_cu * 16;
-  unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
-  if (precision == TC_PREC_BF16X3)
-    hipLaunchKernelGGL(k_gemm_bf16x3, dim3(grid), dim3(256), 0, stream, ops, n_ops, tabs,
-                       arena, tiles);
-  else
-    hipLaunchKernelGGL(k_gemm_f32, dim3(grid), dim3(256), 0, stream, ops, n_ops, tabs, arena,
-                       tiles);
 }
 
 }  // namespace tcx

@@ -343,8 +343,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     size_t j = i;
     while (j < pend.size() && pend[j].step == pend[i].step) ++j;
     // classify: wave kernel for long sums into few outputs, else gather
-    std::vector<DevOp> gc, gcw, gm;
-    std::vector<double> gc_fb(2, 0.0), gcw_fb(2, 0.0), gm_fb(2, 0.0);
+    std::vector<DevOp> gc, gm;
+    double lf = 0, lb = 0;
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
       const PT& Bt = T[pend[k].b];
@@ -382,6 +382,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         flops += f;
         bytes += by;
       }
+      lf += f;
+      lb += by;
       // k-contiguity of the operands picks the GEMM's load pattern
       if (op.K > 1 && plan.tabs[op.a_k + 1] == 1) op.flags |= 1u;
       if (op.K > 1 && plan.tabs[op.b_k + 1] == 1) op.flags |= 2u;
@@ -390,51 +392,59 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         op.tiles_m = (op.M + 63) / 64;
         op.tiles_n = (op.N + 63) / 64;
         gm.push_back(op);
-        gm_fb[0] += f;
-        gm_fb[1] += by;
-      } else if (op.K >= 256 && (uint64_t)op.M * op.N * op.rows <= 8192) {
-        gcw.push_back(op);
-        gcw_fb[0] += f;
-        gcw_fb[1] += by;
       } else {
+        // gather: split long sums over up to 64 lanes while the op is small,
+        // else 4 outputs per thread along n
+        const uint64_t outs = (uint64_t)op.rows * op.M * op.N;
+        uint32_t ls = 0;
+        while (ls < 6 && (op.K >> ls) > 4 && (outs << (ls + 1)) <= 65536) ++ls;
+        while (ls < 6 && (op.K >> ls) > 256) ++ls;
+        uint32_t lv = 0;
+        if (ls == 0) lv = op.N >= 4 ? 2 : (op.N == 2 ? 1 : 0);
+        op.flags |= (ls << 4) | (lv << 8);
         gc.push_back(op);
-        gc_fb[0] += f;
-        gc_fb[1] += by;
       }
     }
-    auto emit = [&](std::vector<DevOp>& v, int32_t kind, uint64_t lanes,
-                    const std::vector<double>& fb) {
-      if (v.empty()) return;
-      Launch L;
-      L.kind = kind;
-      L.flops = fb[0];
-      L.bytes = fb[1];
-      L.begin = (uint32_t)plan.ops.size();
-      uint64_t w = 0;
-      for (DevOp& op : v) {
-        op.work0 = w;
-        if (kind == L_GEMM)
-          w += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
-        else
-          w += (uint64_t)op.rows * op.M * op.N * lanes;
-        plan.ops.push_back(op);
-      }
-      L.end = (uint32_t)plan.ops.size();
-      L.work = w;
-      (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
-    };
-    if (!pend[i].bwd && plan.fwd.empty()) {
-      Launch L{L_LEAF, 0, 0, 0};
-      plan.fwd.push_back(L);  // leaf launch first; filled below
+    Launch L;
+    L.kind = L_LEVEL;
+    L.flops = lf;
+    L.bytes = lb;
+    L.gbegin = (uint32_t)plan.ops.size();
+    uint64_t tiles = 0;
+    for (DevOp& op : gm) {
+      op.work0 = tiles;
+      tiles += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+      plan.ops.push_back(op);
     }
+    L.gend = (uint32_t)plan.ops.size();
+    L.tiles = tiles;
+    L.begin = (uint32_t)plan.ops.size();
+    uint64_t w = 0;
+    for (DevOp& op : gc) {
+      const uint32_t ls = (op.flags >> 4) & 7u, lv = (op.flags >> 8) & 3u;
+      uint64_t items = ((uint64_t)op.rows * op.M * (op.N >> lv)) << ls;
+      if (ls) {  // whole wavefronts: aligned start, padded length
+        w = (w + 63) & ~uint64_t(63);
+        items = (items + 63) & ~uint64_t(63);
+      }
+      op.work0 = w;
+      w += items;
+      plan.ops.push_back(op);
+    }
+    L.end = (uint32_t)plan.ops.size();
+    L.work = (w + 63) & ~uint64_t(63);
     plan.info.n_gemm_nodes += pend[i].bwd ? 0 : (int32_t)gm.size();
-    emit(gm, L_GEMM, 1, gm_fb);
-    emit(gcw, L_GCW, 64, gcw_fb);
-    emit(gc, L_GC, 1, gc_fb);
+    if (!pend[i].bwd && plan.fwd.empty()) {
+      Launch LL;
+      LL.kind = L_LEAF;
+      plan.fwd.push_back(LL);  // leaf launch first; filled below
+    }
+    (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
     i = j;
   }
   if (plan.fwd.empty() || plan.fwd[0].kind != L_LEAF) {
-    Launch L{L_LEAF, 0, 0, 0};
+    Launch L;
+    L.kind = L_LEAF;
     plan.fwd.insert(plan.fwd.begin(), L);
   }
 
@@ -488,7 +498,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     plan.roots.push_back(r);
   }
-  plan.fwd.push_back(Launch{L_ROOT, 0, 0, (uint64_t)B});
+  {
+    Launch L;
+    L.kind = L_ROOT;
+    L.work = (uint64_t)B;
+    plan.fwd.push_back(L);
+  }
 
   // ---- gradient uses, sorted by slot then creation order
   if (grad) {
@@ -520,8 +535,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     plan.slot_begin.assign(net.n_params + 1, 0);
     for (const auto& gu : uses) plan.slot_begin[gu.slot + 1]++;
     for (int p = 0; p < net.n_params; ++p) plan.slot_begin[p + 1] += plan.slot_begin[p];
-    if (net.n_params > 0)
-      plan.bwd.push_back(Launch{L_GRAD, 0, 0, (uint64_t)B * net.n_params});
+    if (net.n_params > 0) {
+      Launch L;
+      L.kind = L_GRAD;
+      L.work = (uint64_t)B * net.n_params;
+      plan.bwd.push_back(L);
+    }
   }
 
   // ---- every device access in bounds (checked here, before any launch)

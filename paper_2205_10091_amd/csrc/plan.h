@@ -12,19 +12,19 @@ namespace tcx {
 
 enum LaunchKind : int32_t {
   L_LEAF = 0,   // materialise leaf tensors from parameters
-  L_GC = 1,     // gather contraction, one thread per output element
-  L_GCW = 2,    // gather contraction, one wavefront per output element
-  L_GEMM = 3,   // LDS-tiled MFMA complex GEMM over gathered operands
+  L_LEVEL = 1,  // one contraction level: MFMA GEMM tiles + gather contractions
   L_ROOT = 4,   // FP64 weighted sum of the term roots
   L_GRAD = 5    // FP64 leaf-gradient reduction
 };
 
 struct Launch {
   int32_t kind;
-  uint32_t begin, end;  // op range (contraction kinds) in Plan::ops
-  uint64_t work;        // threads (GC/leaf/root/grad) or tiles (GEMM)
-  double flops = 0;     // algorithmic flops of the launch (8 per complex MAC)
-  double bytes = 0;     // algorithmic bytes: operands read + results written
+  uint32_t begin = 0, end = 0;    // gather ops in Plan::ops
+  uint64_t work = 0;              // gather work items / leaf, root, grad items
+  uint32_t gbegin = 0, gend = 0;  // GEMM ops in Plan::ops
+  uint64_t tiles = 0;             // GEMM tiles
+  double flops = 0;               // algorithmic flops (8 per complex MAC)
+  double bytes = 0;               // algorithmic bytes: operands read + results written
 };
 
 struct DeviceState;  // defined by the executor

@@ -257,6 +257,22 @@ def test_grid_gemm_nodes_fp32_and_bf16x3():
         assert rel_err(a, ref, 2 ** (-n / 2)) < tol, prec
 
 
+def test_autograd_function_matches_oracle():
+    import torch
+    B = 4
+    circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=10, layers=3)
+    plan = api.compile(circ, obs, batch=B, want_grad=True)
+    x = torch.from_numpy(P.copy()).cuda().requires_grad_(True)
+    e = api.tc_contract(x, plan)
+    w = torch.tensor([1.0, -2.0, 0.5, 3.0], dtype=torch.float64, device="cuda")
+    loss = (w * e).sum()
+    (gx,) = torch.autograd.grad(loss, x)
+    for b in range(B):
+        e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
+        assert abs(e[b].item() - e_ref) < TOL_C64
+        assert grad_err(gx[b].cpu().numpy() / w[b].item(), g_ref) < TOL_C64
+
+
 def test_state_errors():
     circ, p, obs = tcgen.workload_vqe_chain(n=6, layers=2)
     plan = api.compile(circ, obs)
