@@ -15,8 +15,8 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libtcx.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HOST = ["network.cpp", "path.cpp", "plan.cpp", "capi_host.cpp", "serve.cpp"]
-DEVICE = ["exec.hip"]
+HOST = ["network.cpp", "path.cpp", "plan.cpp", "capi_host.cpp"]
+DEVICE = ["exec.hip", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", os.path.join(ROOT, "include"),

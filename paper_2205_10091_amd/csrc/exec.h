@@ -1,0 +1,54 @@
+// Internal interface of the device executor (shared by the single-plan path
+// and the serving engine).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+namespace tcx {
+
+#define HIP_CHECK(x)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      ::tcx::fail(TC_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+struct DeviceState {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* ws = nullptr;
+  bool ws_owned = false;
+  uint64_t ws_bytes = 0;
+  WorkspaceLayout lay{};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int n_cu = 256;
+};
+
+// One plan's launch, located in that plan's workspace.
+struct SegRef {
+  const Plan* plan;
+  const char* ws;               // workspace base of this plan
+  const WorkspaceLayout* lay;
+  const Launch* launch;
+};
+
+// Largest number of plans one merged launch carries (kernel-argument space).
+constexpr int MAX_SEG = 24;
+
+// Enqueue one launch of `kind` covering all `segs` (at most MAX_SEG, all of
+// that kind) on `stream`.
+void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
+                     int precision);
+
+// Asynchronous upload of a plan's tables and seeds into a workspace.
+void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStream_t stream);
+
+int device_cu_count(int device);
+
+}  // namespace tcx

@@ -1,5 +1,5 @@
-// Device executor: kernels for one plan, workspace binding, HIP-graph
-// capture, and the plan / contraction entry points of the C ABI.
+// Device executor: kernels, workspace binding, HIP-graph capture, and the
+// plan / contraction entry points of the C ABI.
 //
 // Paper, section "Tensor network engine" and the workflow figure: after the
 // path is fixed, the contraction is a sequence of pairwise tensor
@@ -8,6 +8,11 @@
 // Here the sequence is level-ordered launches of hand-written kernels,
 // captured once into a HIP graph and replayed per call with new
 // parameters.
+//
+// Every kernel takes a small table of segments by value: one segment per
+// plan, each pointing at that plan's own tables and workspace.  A single
+// plan is one segment; the serving engine merges the current launch of
+// every live request into one launch per kernel class.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,9 +21,9 @@
 #include <string>
 #include <vector>
 
+#include "exec.h"
 #include "gates.h"
 #include "gemm_tile.h"
-#include "plan.h"
 
 struct tc_network;
 struct tc_path;
@@ -33,6 +38,80 @@ struct tc_plan {
 };
 
 namespace tcx {
+
+// ------------------------------------------------------------------ segments
+
+struct LeafSeg {
+  const DevLeaf* leaves;
+  const float* ftab;
+  const float* params;
+  float2* arena;
+  uint64_t start;  // first work item of this segment in the launch
+  uint32_t n;
+  int32_t n_params;
+};
+struct LeafArgs {
+  LeafSeg seg[MAX_SEG];
+  uint32_t nseg;
+  uint64_t total;
+};
+
+struct LevelSeg {
+  const DevOp* gemm_ops;
+  const DevOp* gc_ops;
+  const uint32_t* tab;
+  float2* arena;
+  uint64_t gemm_start;  // first GEMM tile of this segment
+  uint64_t gc_start;    // first gather item (a multiple of 64)
+  uint32_t n_gemm;
+  uint32_t n_gc;
+};
+struct LevelArgs {
+  LevelSeg seg[MAX_SEG];
+  uint32_t nseg;
+  uint32_t gemm_blocks;
+  uint64_t gemm_tiles;
+  uint64_t gc_work;
+};
+
+struct RootSeg {
+  const DevRoot* roots;
+  const float2* arena;
+  double* value;
+  uint64_t start;  // first wavefront (batch row) of this segment
+  uint32_t n_terms;
+  uint32_t batch;
+};
+struct RootArgs {
+  RootSeg seg[MAX_SEG];
+  uint32_t nseg;
+  uint64_t total;  // wavefronts
+};
+
+struct GradSeg {
+  const DevGradUse* uses;
+  const uint32_t* slot_begin;
+  const DevLeaf* leaves;
+  const float* params;
+  const float2* arena;
+  double* grad;
+  uint64_t start;  // first wavefront (row, slot) of this segment
+  int32_t n_params;
+};
+struct GradArgs {
+  GradSeg seg[MAX_SEG];
+  uint32_t nseg;
+  uint64_t total;  // wavefronts
+};
+
+// last segment whose start is <= w (an empty segment shares the next start)
+template <typename A, typename F>
+__device__ __forceinline__ uint32_t find_seg(const A& args, uint64_t w, F start) {
+  uint32_t s = 0;
+  for (uint32_t i = 1; i < args.nseg; ++i)
+    if (start(args.seg[i]) <= w) s = i;
+  return s;
+}
 
 // ------------------------------------------------------------------ kernels
 
@@ -60,23 +139,20 @@ __device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
 
 // Materialise every leaf tensor (gates, boundary vectors, Pauli matrices)
 // for every batch row from the parameter vectors.
-__global__ void __launch_bounds__(256) k_leaf(const DevLeaf* __restrict__ leaves,
-                                              uint32_t n_leaves,
-                                              const float* __restrict__ ftab,
-                                              const float* __restrict__ params,
-                                              int32_t n_params, float2* __restrict__ arena,
-                                              uint64_t total) {
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+__global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.total;
        w += (uint64_t)gridDim.x * blockDim.x) {
-    const DevLeaf& L = leaves[find_item(leaves, n_leaves, w)];
-    uint64_t l = w - L.work0;
-    int e = (int)(l & ((1u << L.rank) - 1));
-    uint64_t r = l >> L.rank;
-    const float* pr = params + r * (uint64_t)n_params;
-    float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
-    float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
-    c32 v = leaf_entry(L, e, t0, t1, ftab);
-    arena[L.out + (r << L.rank) + e] = make_float2(v.re, v.im);
+    const LeafSeg& S = a.seg[find_seg(a, w, [](const LeafSeg& s) { return s.start; })];
+    const uint64_t ws = w - S.start;
+    const DevLeaf& L = S.leaves[find_item(S.leaves, S.n, ws)];
+    const uint64_t l = ws - L.work0;
+    const int e = (int)(l & ((1u << L.rank) - 1));
+    const uint64_t r = l >> L.rank;
+    const float* pr = S.params + r * (uint64_t)S.n_params;
+    const float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
+    const float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
+    const c32 v = leaf_entry(L, e, t0, t1, S.ftab);
+    S.arena[L.out + (r << L.rank) + e] = make_float2(v.re, v.im);
   }
 }
 
@@ -87,50 +163,55 @@ __global__ void __launch_bounds__(256) k_leaf(const DevLeaf* __restrict__ leaves
 // consecutive lanes to a group of V outputs (row, m, n0 .. n0+V-1); lane
 // `sub` sums k = sub, sub + S, ... and the S lanes combine by butterfly
 // shuffles.  Ops with S > 1 start and end on wavefront boundaries (the
-// planner pads them), so every lane of such a wave runs the same shuffles.
-struct LevelArgs {
-  const DevOp* gemm_ops;
-  uint32_t n_gemm;
-  uint32_t gemm_blocks;
-  uint64_t gemm_tiles;
-  const DevOp* gc_ops;
-  uint32_t n_gc;
-  uint64_t gc_work;
-  const uint32_t* tab;
-  float2* arena;
-};
-
+// planner pads them, and segments start on multiples of 64), so every lane
+// of such a wave runs the same shuffles.
 template <int PREC>
 __global__ void __launch_bounds__(256) k_level(LevelArgs a) {
   if (blockIdx.x < a.gemm_blocks) {
     if constexpr (PREC == TC_PREC_BF16X3) {
       __shared__ SmemBF16 smem;
       for (uint64_t tile = blockIdx.x; tile < a.gemm_tiles; tile += a.gemm_blocks) {
-        const DevOp& op = a.gemm_ops[find_item(a.gemm_ops, a.n_gemm, tile)];
-        gemm_tile_bf16x3(op, tile, a.tab, a.arena, smem);
+        const LevelSeg& S =
+            a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
+        const uint64_t lt = tile - S.gemm_start;
+        const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
+        gemm_tile_bf16x3(op, lt, S.tab, S.arena, smem);
       }
     } else {
       __shared__ SmemF32 smem;
       for (uint64_t tile = blockIdx.x; tile < a.gemm_tiles; tile += a.gemm_blocks) {
-        const DevOp& op = a.gemm_ops[find_item(a.gemm_ops, a.n_gemm, tile)];
-        gemm_tile_f32(op, tile, a.tab, a.arena, smem);
+        const LevelSeg& S =
+            a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
+        const uint64_t lt = tile - S.gemm_start;
+        const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
+        gemm_tile_f32(op, lt, S.tab, S.arena, smem);
       }
     }
     return;
   }
-  const uint32_t* __restrict__ tab = a.tab;
-  float2* __restrict__ arena = a.arena;
   const uint64_t stride = (uint64_t)(gridDim.x - a.gemm_blocks) * blockDim.x;
   for (uint64_t w = (uint64_t)(blockIdx.x - a.gemm_blocks) * blockDim.x + threadIdx.x;
        w < a.gc_work; w += stride) {
-    const DevOp& op = a.gc_ops[find_item(a.gc_ops, a.n_gc, w)];
-    const uint32_t ls = (op.flags >> 4) & 7u, lv = (op.flags >> 8) & 3u;
+    const LevelSeg& Sg = a.seg[find_seg(a, w, [](const LevelSeg& s) { return s.gc_start; })];
+    const uint32_t* __restrict__ tab = Sg.tab;
+    float2* __restrict__ arena = Sg.arena;
+    const uint64_t ws = w - Sg.gc_start;
+    const bool has = Sg.n_gc > 0;
+    const DevOp& op = Sg.gc_ops[has ? find_item(Sg.gc_ops, Sg.n_gc, ws) : 0];
+    const uint32_t ls = has ? (op.flags >> 4) & 7u : 0u;
+    const uint32_t lv = has ? (op.flags >> 8) & 3u : 0u;
     const uint32_t S = 1u << ls, V = 1u << lv;
-    const uint64_t l = w - op.work0;
-    const uint32_t ln = __builtin_ctz(op.N) - lv, lm = __builtin_ctz(op.M);
-    const uint64_t e = l >> ls;
-    const uint32_t sub = (uint32_t)(l & (S - 1));
-    const bool valid = e < ((uint64_t)op.rows << (ln + lm));
+    bool valid = false;
+    uint64_t e = 0;
+    uint32_t sub = 0, ln = 0, lm = 0;
+    if (has) {
+      const uint64_t l = ws - op.work0;
+      ln = __builtin_ctz(op.N) - lv;
+      lm = __builtin_ctz(op.M);
+      e = l >> ls;
+      sub = (uint32_t)(l & (S - 1));
+      valid = e < ((uint64_t)op.rows << (ln + lm));
+    }
     c32 acc[4] = {cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f)};
     uint32_t m = 0, n0 = 0;
     uint64_t r = 0;
@@ -179,19 +260,18 @@ __global__ void __launch_bounds__(256) k_level(LevelArgs a) {
 // E[b] = sum_j alpha_j T_j[b] in FP64: one wavefront per batch row, lane l
 // takes terms l, l + 64, ...; the 64 partial sums combine in a fixed
 // butterfly order (deterministic).
-__global__ void __launch_bounds__(256) k_root(const DevRoot* __restrict__ roots,
-                                              uint32_t n_terms,
-                                              const float2* __restrict__ arena,
-                                              double* __restrict__ value, uint32_t batch) {
+__global__ void __launch_bounds__(256) k_root(RootArgs a) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (b >= batch) return;  // whole wavefronts leave together
+  const uint64_t wv = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wv >= a.total) return;  // whole wavefronts leave together
+  const RootSeg& S = a.seg[find_seg(a, wv, [](const RootSeg& s) { return s.start; })];
+  const uint64_t b = wv - S.start;
   double re = 0.0, im = 0.0;
-  for (uint32_t j = lane; j < n_terms; j += 64) {
-    const DevRoot& R = roots[j];
+  for (uint32_t j = lane; j < S.n_terms; j += 64) {
+    const DevRoot& R = S.roots[j];
     double vr = 1.0, vi = 0.0;
     if (R.present) {
-      float2 v = arena[R.val + b * R.bs];
+      const float2 v = S.arena[R.val + b * R.bs];
       vr = v.x;
       vi = v.y;
     }
@@ -203,67 +283,44 @@ __global__ void __launch_bounds__(256) k_root(const DevRoot* __restrict__ roots,
     im += __shfl_xor(im, off, 64);
   }
   if (lane == 0) {
-    value[2 * b] = re;
-    value[2 * b + 1] = im;
+    S.value[2 * b] = re;
+    S.value[2 * b + 1] = im;
   }
 }
 
 // grad[b][slot] = Re sum_{uses of slot} sum_e adj[e] dleaf[e]/dangle in FP64:
 // one wavefront per (row, slot), lanes over the slot's uses, fixed-order
 // butterfly combination.
-__global__ void __launch_bounds__(256) k_grad(const DevGradUse* __restrict__ uses,
-                                              const uint32_t* __restrict__ slot_begin,
-                                              const DevLeaf* __restrict__ leaves,
-                                              const float* __restrict__ params,
-                                              int32_t n_params,
-                                              const float2* __restrict__ arena,
-                                              double* __restrict__ grad, uint64_t total) {
+__global__ void __launch_bounds__(256) k_grad(GradArgs a) {
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < total;
-       w += waves) {
-    const uint64_t b = w / (uint32_t)n_params;
-    const uint32_t slot = (uint32_t)(w - b * (uint32_t)n_params);
-    const float* pr = params + b * (uint64_t)n_params;
+  for (uint64_t wv = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wv < a.total;
+       wv += waves) {
+    const GradSeg& S = a.seg[find_seg(a, wv, [](const GradSeg& s) { return s.start; })];
+    const uint64_t w = wv - S.start;
+    const uint64_t b = w / (uint32_t)S.n_params;
+    const uint32_t slot = (uint32_t)(w - b * (uint32_t)S.n_params);
+    const float* pr = S.params + b * (uint64_t)S.n_params;
     double acc = 0.0;
-    for (uint32_t u = slot_begin[slot] + lane; u < slot_begin[slot + 1]; u += 64) {
-      const DevGradUse& U = uses[u];
-      const DevLeaf& L = leaves[U.leaf];
-      float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
-      float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
-      const float2* ad = arena + U.adj + b * U.adj_bs;
+    for (uint32_t u = S.slot_begin[slot] + lane; u < S.slot_begin[slot + 1]; u += 64) {
+      const DevGradUse& U = S.uses[u];
+      const DevLeaf& L = S.leaves[U.leaf];
+      const float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
+      const float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
+      const float2* ad = S.arena + U.adj + b * U.adj_bs;
       const int ne = 1 << L.rank;
       for (int e = 0; e < ne; ++e) {
-        c32 d = dleaf_entry(L, e, t0, t1, U.which);
-        float2 x = ad[e];
+        const c32 d = dleaf_entry(L, e, t0, t1, U.which);
+        const float2 x = ad[e];
         acc += (double)x.x * d.re - (double)x.y * d.im;
       }
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) grad[w] = acc;
+    if (lane == 0) S.grad[w] = acc;
   }
 }
 
-// ------------------------------------------------------------------ device state
-
-struct DeviceState {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  char* ws = nullptr;
-  bool ws_owned = false;
-  uint64_t ws_bytes = 0;
-  WorkspaceLayout lay{};
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
-  int n_cu = 256;
-};
-
-#define HIP_CHECK(x)                                                              \
-  do {                                                                            \
-    hipError_t e_ = (x);                                                          \
-    if (e_ != hipSuccess) fail(TC_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+// ------------------------------------------------------------------ launching
 
 static unsigned grid_for(uint64_t work, int threads, int n_cu) {
   uint64_t g = (work + threads - 1) / threads;
@@ -271,70 +328,147 @@ static unsigned grid_for(uint64_t work, int threads, int n_cu) {
   return (unsigned)std::max<uint64_t>(1, std::min(g, cap));
 }
 
-static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& seq) {
-  char* ws = D.ws;
-  const auto& L = D.lay;
-  const DevOp* ops = (const DevOp*)(ws + L.ops);
-  const uint32_t* tabs = (const uint32_t*)(ws + L.tabs);
-  const DevLeaf* leaves = (const DevLeaf*)(ws + L.leaves);
-  const float* ftab = (const float*)(ws + L.ftab);
-  const DevGradUse* uses = (const DevGradUse*)(ws + L.uses);
-  const uint32_t* slot_begin = (const uint32_t*)(ws + L.slot_begin);
-  const DevRoot* roots = (const DevRoot*)(ws + L.roots);
-  const float* params = (const float*)(ws + L.params);
-  double* value = (double*)(ws + L.value);
-  double* grad = (double*)(ws + L.grad);
-  float2* arena = (float2*)(ws + L.arena);
-  for (const Launch& x : seq) {
-    switch (x.kind) {
-      case L_LEAF:
-        if (x.work == 0) continue;
-        hipLaunchKernelGGL(k_leaf, dim3(grid_for(x.work, 256, D.n_cu)), dim3(256), 0, D.stream,
-                           leaves, (uint32_t)P.leaves.size(), ftab, params, P.n_params, arena,
-                           x.work);
-        break;
-      case L_LEVEL: {
-        LevelArgs a;
-        a.gemm_ops = ops + x.gbegin;
-        a.n_gemm = x.gend - x.gbegin;
-        a.gemm_tiles = x.tiles;
-        a.gemm_blocks = (uint32_t)std::min<uint64_t>(x.tiles, (uint64_t)D.n_cu * 8);
-        a.gc_ops = ops + x.begin;
-        a.n_gc = x.end - x.begin;
-        a.gc_work = x.work;
-        a.tab = tabs;
-        a.arena = arena;
-        unsigned gcb = x.work ? grid_for(x.work, 256, D.n_cu) : 0u;
-        unsigned grid = a.gemm_blocks + gcb;
-        if (grid == 0) continue;
-        if (P.precision == TC_PREC_BF16X3)
-          hipLaunchKernelGGL(k_level<TC_PREC_BF16X3>, dim3(grid), dim3(256), 0, D.stream, a);
-        else
-          hipLaunchKernelGGL(k_level<TC_PREC_C64>, dim3(grid), dim3(256), 0, D.stream, a);
-        break;
+int device_cu_count(int device) {
+  hipDeviceProp_t prop;
+  HIP_CHECK(hipGetDeviceProperties(&prop, device));
+  return prop.multiProcessorCount;
+}
+
+void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
+                     int precision) {
+  if (nseg <= 0) return;
+  if (nseg > MAX_SEG) fail(TC_ERR_INVALID_ARG, "internal: too many segments");
+  switch (kind) {
+    case L_LEAF: {
+      LeafArgs a{};
+      uint64_t w = 0;
+      for (int i = 0; i < nseg; ++i) {
+        const SegRef& s = segs[i];
+        const WorkspaceLayout& L = *s.lay;
+        LeafSeg& g = a.seg[i];
+        g.leaves = (const DevLeaf*)(s.ws + L.leaves);
+        g.ftab = (const float*)(s.ws + L.ftab);
+        g.params = (const float*)(s.ws + L.params);
+        g.arena = (float2*)(s.ws + L.arena);
+        g.n = (uint32_t)s.plan->leaves.size();
+        g.n_params = s.plan->n_params;
+        g.start = w;
+        w += s.launch->work;
       }
-      case L_ROOT:
-        hipLaunchKernelGGL(k_root, dim3((unsigned)((x.work * 64 + 255) / 256)), dim3(256), 0,
-                           D.stream, roots, (uint32_t)P.roots.size(), arena, value,
-                           (uint32_t)P.batch);
-        break;
-      case L_GRAD:
-        if (x.work == 0) continue;
-        hipLaunchKernelGGL(k_grad, dim3(grid_for(x.work * 64, 256, D.n_cu)), dim3(256), 0,
-                           D.stream, uses, slot_begin, leaves, params, P.n_params, arena, grad,
-                           x.work);
-        break;
+      a.nseg = (uint32_t)nseg;
+      a.total = w;
+      if (w == 0) return;
+      hipLaunchKernelGGL(k_leaf, dim3(grid_for(w, 256, n_cu)), dim3(256), 0, stream, a);
+      break;
     }
-    HIP_CHECK(hipGetLastError());
+    case L_LEVEL: {
+      LevelArgs a{};
+      uint64_t tiles = 0, work = 0;
+      for (int i = 0; i < nseg; ++i) {
+        const SegRef& s = segs[i];
+        const WorkspaceLayout& L = *s.lay;
+        const DevOp* ops = (const DevOp*)(s.ws + L.ops);
+        LevelSeg& g = a.seg[i];
+        g.gemm_ops = ops + s.launch->gbegin;
+        g.n_gemm = s.launch->gend - s.launch->gbegin;
+        g.gc_ops = ops + s.launch->begin;
+        g.n_gc = s.launch->end - s.launch->begin;
+        g.tab = (const uint32_t*)(s.ws + L.tabs);
+        g.arena = (float2*)(s.ws + L.arena);
+        g.gemm_start = tiles;
+        g.gc_start = work;
+        tiles += s.launch->tiles;
+        work += (s.launch->work + 63) & ~uint64_t(63);
+      }
+      a.nseg = (uint32_t)nseg;
+      a.gemm_tiles = tiles;
+      a.gc_work = work;
+      a.gemm_blocks = (uint32_t)std::min<uint64_t>(tiles, (uint64_t)n_cu * 8);
+      const unsigned gcb = work ? grid_for(work, 256, n_cu) : 0u;
+      const unsigned grid = a.gemm_blocks + gcb;
+      if (grid == 0) return;
+      if (precision == TC_PREC_BF16X3)
+        hipLaunchKernelGGL(k_level<TC_PREC_BF16X3>, dim3(grid), dim3(256), 0, stream, a);
+      else
+        hipLaunchKernelGGL(k_level<TC_PREC_C64>, dim3(grid), dim3(256), 0, stream, a);
+      break;
+    }
+    case L_ROOT: {
+      RootArgs a{};
+      uint64_t w = 0;
+      for (int i = 0; i < nseg; ++i) {
+        const SegRef& s = segs[i];
+        const WorkspaceLayout& L = *s.lay;
+        RootSeg& g = a.seg[i];
+        g.roots = (const DevRoot*)(s.ws + L.roots);
+        g.arena = (const float2*)(s.ws + L.arena);
+        g.value = (double*)(s.ws + L.value);
+        g.n_terms = (uint32_t)s.plan->roots.size();
+        g.batch = (uint32_t)s.plan->batch;
+        g.start = w;
+        w += (uint64_t)s.plan->batch;
+      }
+      a.nseg = (uint32_t)nseg;
+      a.total = w;
+      hipLaunchKernelGGL(k_root, dim3((unsigned)((w * 64 + 255) / 256)), dim3(256), 0, stream,
+                         a);
+      break;
+    }
+    case L_GRAD: {
+      GradArgs a{};
+      uint64_t w = 0;
+      for (int i = 0; i < nseg; ++i) {
+        const SegRef& s = segs[i];
+        const WorkspaceLayout& L = *s.lay;
+        GradSeg& g = a.seg[i];
+        g.uses = (const DevGradUse*)(s.ws + L.uses);
+        g.slot_begin = (const uint32_t*)(s.ws + L.slot_begin);
+        g.leaves = (const DevLeaf*)(s.ws + L.leaves);
+        g.params = (const float*)(s.ws + L.params);
+        g.arena = (const float2*)(s.ws + L.arena);
+        g.grad = (double*)(s.ws + L.grad);
+        g.n_params = s.plan->n_params;
+        g.start = w;
+        w += s.launch->work;
+      }
+      a.nseg = (uint32_t)nseg;
+      a.total = w;
+      if (w == 0) return;
+      hipLaunchKernelGGL(k_grad, dim3(grid_for(w * 64, 256, n_cu)), dim3(256), 0, stream, a);
+      break;
+    }
+    default:
+      fail(TC_ERR_INVALID_ARG, "internal: unknown launch kind");
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& seq) {
+  for (const Launch& x : seq) {
+    SegRef s{&P, D.ws, &D.lay, &x};
+    launch_segments(x.kind, &s, 1, D.stream, D.n_cu, P.precision);
   }
 }
 
 template <typename T>
-static void upload(DeviceState& D, uint64_t off, const std::vector<T>& v) {
+static void upload(char* ws, uint64_t off, const std::vector<T>& v, hipStream_t stream) {
   if (v.empty()) return;
-  HIP_CHECK(hipMemcpyAsync(D.ws + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice,
-                           D.stream));
+  HIP_CHECK(hipMemcpyAsync(ws + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice,
+                           stream));
 }
+
+void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStream_t stream) {
+  upload(ws, lay.ops, P.ops, stream);
+  upload(ws, lay.tabs, P.tabs, stream);
+  upload(ws, lay.leaves, P.leaves, stream);
+  upload(ws, lay.ftab, P.ftab, stream);
+  upload(ws, lay.uses, P.uses, stream);
+  upload(ws, lay.slot_begin, P.slot_begin, stream);
+  upload(ws, lay.roots, P.roots, stream);
+  upload(ws, lay.arena, P.seeds, stream);  // seeds sit at arena offset 0
+}
+
+// ------------------------------------------------------------------ device state
 
 static void release(DeviceState* D) {
   if (!D) return;
@@ -372,9 +506,7 @@ void bind_plan(Plan& P, void* workspace, uint64_t bytes) {
   try {
     D->device = P.device;
     HIP_CHECK(hipSetDevice(P.device));
-    hipDeviceProp_t prop;
-    HIP_CHECK(hipGetDeviceProperties(&prop, P.device));
-    D->n_cu = prop.multiProcessorCount;
+    D->n_cu = device_cu_count(P.device);
     if (P.user_stream) {
       D->stream = (hipStream_t)P.user_stream;
     } else {
@@ -397,14 +529,7 @@ void bind_plan(Plan& P, void* workspace, uint64_t bytes) {
       D->ws_owned = true;
       D->ws_bytes = D->lay.total;
     }
-    upload(*D, D->lay.ops, P.ops);
-    upload(*D, D->lay.tabs, P.tabs);
-    upload(*D, D->lay.leaves, P.leaves);
-    upload(*D, D->lay.ftab, P.ftab);
-    upload(*D, D->lay.uses, P.uses);
-    upload(*D, D->lay.slot_begin, P.slot_begin);
-    upload(*D, D->lay.roots, P.roots);
-    upload(*D, D->lay.arena, P.seeds);  // seeds sit at arena offset 0
+    upload_tables(P, D->ws, D->lay, D->stream);
     HIP_CHECK(hipStreamSynchronize(D->stream));
     capture(P, *D, 0);
     if (P.want_grad) capture(P, *D, 1);
@@ -424,7 +549,7 @@ struct BusyGuard {
   ~BusyGuard() { f.store(0); }
 };
 
-static void run(Plan& P, const float* params, int which) {
+static void stage_params(Plan& P, const float* params) {
   if (!params) fail(TC_ERR_INVALID_ARG, "params is NULL");
   if (!P.dev) bind_plan(P, nullptr, 0);
   DeviceState& D = *P.dev;
@@ -433,18 +558,16 @@ static void run(Plan& P, const float* params, int which) {
   if (pbytes)
     HIP_CHECK(hipMemcpyAsync(D.ws + D.lay.params, params, pbytes, hipMemcpyDeviceToDevice,
                              D.stream));
-  HIP_CHECK(hipGraphLaunch(D.exec[which], D.stream));
 }
 
-void contract(Plan& P, const float* params, double* out_host, bool device_out) {
+void contract(Plan& P, const float* params, double* out, bool device_out) {
   BusyGuard g(P.busy);
-  run(P, params, 0);
+  stage_params(P, params);
   DeviceState& D = *P.dev;
-  if (out_host) {
-    HIP_CHECK(hipMemcpyAsync(out_host, D.ws + D.lay.value, (uint64_t)P.batch * 16,
-                             device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                             D.stream));
-  }
+  HIP_CHECK(hipGraphLaunch(D.exec[0], D.stream));
+  HIP_CHECK(hipMemcpyAsync(out, D.ws + D.lay.value, (uint64_t)P.batch * 16,
+                           device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           D.stream));
   if (!device_out) HIP_CHECK(hipStreamSynchronize(D.stream));
 }
 
@@ -452,8 +575,9 @@ void contract_grad(Plan& P, const float* params, double* value, double* grad,
                    bool device_out) {
   if (!P.want_grad) fail(TC_ERR_STATE, "plan was compiled without want_grad");
   BusyGuard g(P.busy);
-  run(P, params, 1);
+  stage_params(P, params);
   DeviceState& D = *P.dev;
+  HIP_CHECK(hipGraphLaunch(D.exec[1], D.stream));
   hipMemcpyKind kind = device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (value)
     HIP_CHECK(hipMemcpy2DAsync(value, sizeof(double), D.ws + D.lay.value, 2 * sizeof(double),
@@ -469,19 +593,14 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
   if (which == 1 && !P.want_grad) fail(TC_ERR_STATE, "plan was compiled without want_grad");
   if (reps < 1) fail(TC_ERR_INVALID_ARG, "reps must be >= 1");
   BusyGuard g(P.busy);
-  if (!P.dev) bind_plan(P, nullptr, 0);
+  stage_params(P, params);
   DeviceState& D = *P.dev;
-  HIP_CHECK(hipSetDevice(D.device));
   std::vector<Launch> seq = P.fwd;
   if (which == 1) seq.insert(seq.end(), P.bwd.begin(), P.bwd.end());
-  uint64_t pbytes = (uint64_t)P.batch * P.n_params * sizeof(float);
-  if (pbytes)
-    HIP_CHECK(hipMemcpyAsync(D.ws + D.lay.params, params, pbytes, hipMemcpyDeviceToDevice,
-                             D.stream));
-  std::vector<hipEvent_t> ev(seq.size() + 1);
-  for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
+  std::vector<hipEvent_t> ev(seq.size() + 1, nullptr);
   std::vector<double> acc(seq.size(), 0.0);
   try {
+    for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
     for (int r = 0; r < reps; ++r) {
       HIP_CHECK(hipEventRecord(ev[0], D.stream));
       for (size_t i = 0; i < seq.size(); ++i) {
@@ -496,7 +615,8 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
       }
     }
   } catch (...) {
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
     throw;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);

@@ -333,6 +333,10 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     plan.arena_elems = std::max(plan.arena_elems, seed_elems);
   }
+  // the arena alone already exceeds the budget: stop before building tables
+  if (plan.budget && plan.arena_elems * 8 > plan.budget)
+    fail(TC_ERR_TOO_LARGE, "live intermediates need " + std::to_string(plan.arena_elems * 8) +
+                               " bytes, more than the memory budget");
 
   // ---- contraction ops, grouped into launches by step
   std::stable_sort(pend.begin(), pend.end(),

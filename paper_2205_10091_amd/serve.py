@@ -1,0 +1,155 @@
+"""Python driver of the serving engine (tc_serve_* in include/tcx.h).
+
+The engine itself (admission by HBM footprint, plan cache, merged launches
+across live requests) is native; this module marshals requests, runs the
+Poisson arrival clock in a submitter thread and the engine loop in the
+caller's thread, and collects per-request latencies.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import _lib as L
+from .api import _CCircuit, _CObservable, lib
+
+
+@dataclass
+class Result:
+    rid: int
+    value: float
+    value_im: float
+    latency_s: float
+    grad: Optional[np.ndarray]
+    status: int
+
+
+class Server:
+    def __init__(self, pool_bytes=16 << 30, max_request_bytes=4 << 30, max_active=64,
+                 path_trials=4, device=0):
+        opts = L.ServeOpts(device, pool_bytes, max_request_bytes, max_active, path_trials, None)
+        h = C.c_void_p()
+        L.check(lib().tc_serve_create(C.byref(opts), C.byref(h)))
+        self.h = h
+        self.n_params: Dict[int, int] = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tc_serve_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except (AttributeError, TypeError):  # interpreter shutdown
+            pass
+
+    def submit(self, circ, obs, params, want_grad: bool) -> int:
+        """Returns the engine's request id; raises TcxError (TOO_LARGE for
+        requests over the per-request memory cap)."""
+        cc = _CCircuit(circ)
+        co = _CObservable(obs, circ.n_qubits)
+        p = np.ascontiguousarray(np.asarray(params, np.float32).reshape(-1))
+        rid = C.c_int64()
+        L.check(lib().tc_serve_submit(self.h, C.byref(cc.c), C.byref(co.o),
+                                      p.ctypes.data_as(L.F32P), int(want_grad), C.byref(rid)))
+        self.n_params[rid.value] = circ.n_params
+        return rid.value
+
+    def step(self) -> int:
+        n = C.c_int32()
+        L.check(lib().tc_serve_step(self.h, C.byref(n)))
+        return n.value
+
+    def result(self, rid: int) -> Optional[Result]:
+        out = L.ServeResult()
+        g = np.zeros(max(self.n_params.get(rid, 0), 1), np.float64)
+        st = lib().tc_serve_result_get(self.h, rid, C.byref(out), g.ctypes.data_as(L.F64P))
+        if st == L.TC_ERR_BUSY:
+            return None
+        L.check(st)
+        npar = self.n_params.pop(rid, 0)
+        return Result(rid, out.value, out.value_im, out.submit_to_done_s,
+                      g[:npar].copy() if out.want_grad else None, out.status)
+
+
+@dataclass
+class ServeReport:
+    results: Dict[int, Result] = field(default_factory=dict)   # keyed by request index
+    rejected: List[int] = field(default_factory=list)
+    wall_s: float = 0.0
+
+    def latencies(self):
+        return np.array([r.latency_s for r in self.results.values()])
+
+    def summary(self):
+        lat = self.latencies()
+        n = len(lat)
+        return {"completed": n, "rejected": len(self.rejected), "wall_s": self.wall_s,
+                "evals_per_s": n / self.wall_s if self.wall_s else 0.0,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3) if n else None,
+                "p99_ms": float(np.percentile(lat, 99) * 1e3) if n else None}
+
+
+def run(server: Server, requests, realtime: bool = True, poll_sleep: float = 0.0) -> ServeReport:
+    """Submit `requests` (objects with circuit, observable, params,
+    want_grad, arrival_s) at their arrival times (realtime) or all at once,
+    and step the engine until every accepted request finished."""
+    rep = ServeReport()
+    ids: Dict[int, int] = {}
+    lock = threading.Lock()
+    done_submitting = threading.Event()
+    errors = []
+
+    def submitter():
+        t0 = time.perf_counter()
+        try:
+            for i, rq in enumerate(requests):
+                if realtime:
+                    dt = rq.arrival_s - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                try:
+                    rid = server.submit(rq.circuit, rq.observable, rq.params, rq.want_grad)
+                    with lock:
+                        ids[rid] = i
+                except L.TcxError as e:
+                    if e.status == L.TC_ERR_TOO_LARGE:
+                        with lock:
+                            rep.rejected.append(i)
+                    else:
+                        raise
+        except Exception as e:  # surfaced in the engine thread
+            errors.append(e)
+        finally:
+            done_submitting.set()
+
+    t0 = time.perf_counter()
+    th = threading.Thread(target=submitter, daemon=True)
+    th.start()
+    while True:
+        live = server.step()
+        with lock:
+            pending = list(ids.items())
+        for rid, i in pending:
+            r = server.result(rid)
+            if r is not None:
+                rep.results[i] = r
+                with lock:
+                    del ids[rid]
+        if errors:
+            raise errors[0]
+        if done_submitting.is_set() and live == 0:
+            with lock:
+                if not ids:
+                    break
+        if poll_sleep:
+            time.sleep(poll_sleep)
+    th.join()
+    rep.wall_s = time.perf_counter() - t0
+    return rep
