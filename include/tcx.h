@@ -252,7 +252,14 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *   gemm_min_k  nodes with K >= gemm_min_k contracted indices (K = product
  *               of their dimensions) and M, N >= 16 run on the MFMA GEMM,
  *               the rest on the gather kernels; 0 = default (8), a value
- *               above every K keeps all nodes on the gather kernels.
+ *               above every K keeps all nodes on the gather kernels;
+ *   checkpoint_every  with want_grad: 0 = keep every intermediate for the
+ *               reverse sweep unless mem_budget_bytes is exceeded, in which
+ *               case the segment length with the smallest workspace is
+ *               chosen; c >= 2 = always checkpoint with segments of c tree
+ *               levels (values consumed inside their own segment are freed
+ *               after the forward pass and recomputed segment by segment
+ *               during the reverse sweep); -1 = never.
  */
 typedef struct tc_plan tc_plan;
 
@@ -266,6 +273,7 @@ typedef struct {
   uint64_t mem_budget_bytes;
   void* stream;              /* hipStream_t                               */
   int32_t gemm_min_k;
+  int32_t checkpoint_every;
 } tc_plan_opts;
 
 tc_status tc_plan_create(const tc_network* net, const tc_path* path,
@@ -289,6 +297,7 @@ typedef struct {
   int32_t batch;
   int32_t n_params;
   int32_t n_terms;
+  int32_t checkpoint_every;  /* segment length used, 0 = none            */
 } tc_plan_info;
 
 tc_status tc_plan_info_get(const tc_plan* plan, tc_plan_info* out);

@@ -69,7 +69,7 @@ class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("batch", C.c_int32),
                 ("want_grad", C.c_int32), ("device", C.c_int32),
                 ("mem_budget_bytes", C.c_uint64), ("stream", C.c_void_p),
-                ("gemm_min_k", C.c_int32)]
+                ("gemm_min_k", C.c_int32), ("checkpoint_every", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -80,7 +80,8 @@ class PlanInfo(C.Structure):
                 ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
                 ("n_gemm_nodes", C.c_int32), ("n_launches", C.c_int32),
                 ("n_grad_launches", C.c_int32), ("batch", C.c_int32),
-                ("n_params", C.c_int32), ("n_terms", C.c_int32)]
+                ("n_params", C.c_int32), ("n_terms", C.c_int32),
+                ("checkpoint_every", C.c_int32)]
 
 
 class ServeOpts(C.Structure):

@@ -660,9 +660,11 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
                          const tc_plan_opts* opts, tc_plan** out) {
   TC_GUARD_BEGIN
   if (!net || !path || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
-  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0};
+  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0};
   if (opts) o = *opts;
   if (o.gemm_min_k < 0) tcx::fail(TC_ERR_INVALID_ARG, "gemm_min_k must be >= 0");
+  if (o.checkpoint_every < -1 || o.checkpoint_every == 1)
+    tcx::fail(TC_ERR_INVALID_ARG, "checkpoint_every must be -1, 0 or >= 2");
   if (o.batch < 1 || o.batch > (1 << 20)) tcx::fail(TC_ERR_INVALID_ARG, "batch must be in 1..2^20");
   if (o.precision != TC_PREC_C64 && o.precision != TC_PREC_BF16X3)
     tcx::fail(TC_ERR_UNSUPPORTED, "unknown precision");
@@ -674,6 +676,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
   p->p.budget = o.mem_budget_bytes;
   p->p.user_stream = o.stream;
   if (o.gemm_min_k > 0) p->p.gemm_min_k = o.gemm_min_k;
+  p->p.checkpoint = o.checkpoint_every;
   try {
     tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));
   } catch (...) {

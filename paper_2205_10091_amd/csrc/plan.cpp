@@ -11,13 +11,20 @@
 // for a batch of parameter vectors).
 //
 // Execution model.  Tree nodes of all terms are grouped by level (longest
-// path from the leaves); each level is one launch per kernel class.  The
-// reverse sweep seeds each term's root with its weight alpha_j; for a node
-// C = A.B it computes dA = dC.B and dB = dC.A with the same contraction
-// kernels (the network is holomorphic in its leaf entries, so no
-// conjugation appears; bra leaves already hold conjugated entries), grouped
-// by depth below the root.  Leaf adjoints are written in their leaf's leg
+// path from the leaves); each level is one launch.  The reverse sweep seeds
+// each term's root with its weight alpha_j; for a node C = A.B it computes
+// dA = dC.B and dB = dC.A with the same contraction kernels (the network is
+// holomorphic in its leaf entries, so no conjugation appears; bra leaves
+// already hold conjugated entries).  Adjoint launches visit the forward
+// levels from the top down.  Leaf adjoints are written in their leaf's leg
 // order and dotted with dLeaf/dangle in FP64.
+//
+// Checkpointing.  With segment length c, forward levels are cut into
+// segments of c levels.  A node's value is kept for the reverse sweep only
+// if its consumer lies in another segment; the others are freed after the
+// forward pass.  The reverse sweep handles segments from the top: it first
+// recomputes the segment's dropped values from kept ones (a second forward
+// pass over that segment), then runs the segment's adjoint launches.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -57,20 +64,6 @@ struct Tables {
       key += std::to_string(stride[j]);
       key += ',';
     }
-    return put(key, stride);
-  }
-  // dense strides: index i over n_bits bits times `scale`
-  uint32_t dense(int n_bits, uint32_t scale) {
-    std::vector<uint32_t> stride(n_bits);
-    std::string key;
-    for (int j = 0; j < n_bits; ++j) {
-      stride[j] = scale << (n_bits - 1 - j);
-      key += std::to_string(stride[j]);
-      key += ',';
-    }
-    return put(key, stride);
-  }
-  uint32_t put(const std::string& key, const std::vector<uint32_t>& stride) {
     auto it = memo.find(key);
     if (it != memo.end()) return it->second;
     const size_t nb = stride.size();
@@ -134,68 +127,50 @@ struct Arena {
 struct PendingOp {
   int32_t a, b, c;   // tensor ids
   int32_t step;
-  bool bwd;
+  bool bwd;          // part of the reverse-sweep launch list
+  bool recompute;    // forward op re-run by checkpointing
 };
 
-}  // namespace
+struct TermInfo {
+  std::vector<int32_t> tid;     // SSA id -> tensor id
+  std::vector<int32_t> level;   // SSA id -> forward level
+  std::vector<int32_t> parent;  // SSA id -> SSA id of consumer (-1 root)
+  std::vector<char> needs;      // subtree holds a parameter-dependent leaf
+  int32_t root = -1;
+};
 
-WorkspaceLayout workspace_layout(const Plan& p) {
-  auto al = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
-  WorkspaceLayout w{};
-  uint64_t o = 0;
-  w.ops = o; o = al(o + p.ops.size() * sizeof(DevOp));
-  w.tabs = o; o = al(o + p.tabs.size() * sizeof(uint32_t));
-  w.leaves = o; o = al(o + p.leaves.size() * sizeof(DevLeaf));
-  w.ftab = o; o = al(o + p.ftab.size() * sizeof(float));
-  w.uses = o; o = al(o + p.uses.size() * sizeof(DevGradUse));
-  w.slot_begin = o; o = al(o + p.slot_begin.size() * sizeof(uint32_t));
-  w.roots = o; o = al(o + p.roots.size() * sizeof(DevRoot));
-  w.params = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(float));
-  w.value = o; o = al(o + (uint64_t)p.batch * 2 * sizeof(double));
-  w.grad = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(double));
-  w.arena = o; o = al(o + p.arena_elems * 8);
-  w.total = o;
-  return w;
-}
+struct Schedule {
+  std::vector<PT> T;
+  std::vector<PendingOp> pend;
+  std::vector<TermInfo> ti;
+  std::vector<std::pair<int32_t, int32_t>> leaf_adj;      // (leaf tensor, adj tensor)
+  std::vector<std::pair<size_t, int32_t>> leaf_adj_term;  // (term, leaf index)
+  int32_t max_level = 0, root_step = 0, grad_step = 0;
+  uint64_t seed_elems = 0, arena_elems = 0, peak_tensor_elems = 0;
+};
 
-void build_plan(Plan& plan, const Network& net, const Path& path) {
-  const int B = plan.batch;
-  const bool grad = plan.want_grad != 0;
-  plan.n_params = net.n_params;
-  plan.n_terms = (int32_t)net.terms.size();
-  if (path.terms.size() != net.terms.size()) fail(TC_ERR_INVALID_ARG, "path does not match network");
+// Builds tensors, ops with their steps, lifetimes and arena offsets.
+// ckpt = 0: keep every intermediate for the reverse sweep; ckpt >= 2:
+// checkpoint segments of that many levels.
+void schedule(Schedule& S, const Network& net, const Path& path, int B, bool grad, int ckpt) {
+  std::vector<PT>& T = S.T;
+  S.ti.assign(net.terms.size(), TermInfo{});
 
-  std::vector<PT> T;            // all tensors
-  std::vector<PendingOp> pend;  // all contraction ops
-  Tables tables(plan.tabs);
-
-  // seeds: one rank-0 constant per term, value alpha_j
+  // seeds: one rank-0 constant per term, value alpha_j (arena offset t)
   for (size_t t = 0; t < net.terms.size(); ++t) {
     PT s;
     s.fixed = true;
     s.off = (int64_t)t;
     T.push_back(s);
-    plan.seeds.push_back((float)net.terms[t].weight);
-    plan.seeds.push_back(0.0f);
   }
-  const uint64_t seed_elems = Arena::align(net.terms.size());
-
-  struct TermInfo {
-    std::vector<int32_t> tid;     // SSA id -> tensor id
-    std::vector<int32_t> level;   // SSA id -> forward level
-    std::vector<int32_t> parent;  // SSA id -> SSA id of consumer (-1 root)
-    std::vector<char> needs;      // subtree holds a parameter-dependent leaf
-    int32_t root = -1;
-  };
-  std::vector<TermInfo> ti(net.terms.size());
-  int32_t max_level = 0;
+  S.seed_elems = Arena::align(net.terms.size());
 
   // ---- forward structure
   for (size_t t = 0; t < net.terms.size(); ++t) {
     const Term& term = net.terms[t];
     const TermPath& tp = path.terms[t];
     validate_term_path(term, tp);
-    TermInfo& I = ti[t];
+    TermInfo& I = S.ti[t];
     const int32_t nl = (int32_t)term.leaves.size();
     const int32_t ns = nl + (int32_t)tp.pairs.size();
     I.tid.assign(ns, -1);
@@ -226,136 +201,242 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       I.parent[a] = I.parent[b] = c;
       I.tid[c] = (int32_t)T.size();
       T.push_back(x);
-      max_level = std::max(max_level, I.level[c]);
+      S.max_level = std::max(S.max_level, I.level[c]);
     }
     if (ns > 0) {
       I.root = ns - 1;
       if (!T[I.tid[I.root]].legs.empty()) fail(TC_ERR_INVALID_ARG, "network is not closed");
     }
   }
-  const int32_t root_step = max_level + 1;
+  const int32_t Lf = S.max_level;
+  S.root_step = Lf + 1;
+  const bool ck = grad && ckpt >= 2;
+  auto seg_of = [&](int32_t level) { return level <= 0 ? -1 : (level - 1) / ckpt; };
 
   // ---- forward ops and last uses
   for (size_t t = 0; t < net.terms.size(); ++t) {
     const TermPath& tp = path.terms[t];
-    TermInfo& I = ti[t];
+    TermInfo& I = S.ti[t];
     const int32_t nl = (int32_t)net.terms[t].leaves.size();
     for (size_t s = 0; s < tp.pairs.size(); ++s) {
       int32_t a = tp.pairs[s].first, b = tp.pairs[s].second, c = nl + (int32_t)s;
       int32_t step = I.level[c];
-      pend.push_back({I.tid[a], I.tid[b], I.tid[c], step, false});
+      S.pend.push_back({I.tid[a], I.tid[b], I.tid[c], step, false, false});
       T[I.tid[a]].last = std::max(T[I.tid[a]].last, step);
       T[I.tid[b]].last = std::max(T[I.tid[b]].last, step);
     }
-    if (I.root >= 0) T[I.tid[I.root]].last = root_step;
+    if (I.root >= 0) T[I.tid[I.root]].last = S.root_step;
   }
 
-  // ---- reverse sweep
-  int32_t max_bstep = root_step;
-  std::vector<std::pair<int32_t, int32_t>> leaf_adj;  // (leaf tensor, adj tensor) per use
-  std::vector<std::pair<size_t, int32_t>> leaf_adj_term;  // (term, leaf index)
+  // ---- reverse sweep (and recomputation under checkpointing)
+  // Timeline after the root step: for each segment from the top, its
+  // recompute steps (ascending levels), then its adjoint steps (descending).
+  const int32_t nseg = ck ? seg_of(Lf) + 1 : 1;
+  std::vector<int32_t> recompute_step(Lf + 2, -1), adjoint_step(Lf + 2, -1);
+  {
+    int32_t st = S.root_step + 1;
+    for (int32_t sg = nseg - 1; sg >= 0; --sg) {
+      const int32_t lo = ck ? sg * ckpt + 1 : 1;
+      const int32_t hi = ck ? std::min((sg + 1) * ckpt, Lf) : Lf;
+      if (ck)
+        for (int32_t l = lo; l < hi; ++l) recompute_step[l] = st++;
+      for (int32_t l = hi; l >= lo; --l) adjoint_step[l] = st++;
+    }
+    S.grad_step = st;
+  }
   if (grad) {
     for (size_t t = 0; t < net.terms.size(); ++t) {
       const TermPath& tp = path.terms[t];
-      TermInfo& I = ti[t];
+      TermInfo& I = S.ti[t];
       if (I.root < 0 || !I.needs[I.root]) continue;
       const int32_t nl = (int32_t)net.terms[t].leaves.size();
       const int32_t ns = (int32_t)I.tid.size();
-      std::vector<int32_t> adj(ns, -1), depth(ns, 0);
+      // value instance used by the reverse sweep for each SSA id
+      std::vector<int32_t> val(ns);
+      for (int32_t x = 0; x < ns; ++x) val[x] = I.tid[x];
+      if (ck) {
+        // dropped: a node whose consumer sits in the same segment
+        std::vector<char> dropped(ns, 0);
+        for (int32_t x = nl; x < ns; ++x)
+          if (I.parent[x] >= 0 && seg_of(I.level[x]) == seg_of(I.level[I.parent[x]]))
+            dropped[x] = 1;
+        // recompute dropped nodes whose subtree matters for the gradient
+        // (their values are operands of adjoint ops), in level order
+        std::vector<int32_t> order;
+        for (int32_t x = nl; x < ns; ++x)
+          if (dropped[x]) order.push_back(x);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t u, int32_t v) { return I.level[u] < I.level[v]; });
+        for (int32_t x : order) {
+          int32_t a = tp.pairs[x - nl].first, b = tp.pairs[x - nl].second;
+          int32_t step = recompute_step[I.level[x]];
+          PT r = T[I.tid[x]];
+          r.off = -1;
+          r.first = step;
+          r.last = step;
+          int32_t rid = (int32_t)T.size();
+          T.push_back(r);
+          S.pend.push_back({val[a], val[b], rid, step, true, true});
+          T[val[a]].last = std::max(T[val[a]].last, step);
+          T[val[b]].last = std::max(T[val[b]].last, step);
+          val[x] = rid;
+        }
+      }
+      std::vector<int32_t> adj(ns, -1);
       adj[I.root] = (int32_t)t;  // seed tensor
       for (int32_t c = ns - 1; c >= nl; --c) {
         if (adj[c] < 0) continue;
         int32_t a = tp.pairs[c - nl].first, b = tp.pairs[c - nl].second;
-        int32_t step = root_step + 1 + depth[c];
-        max_bstep = std::max(max_bstep, step);
+        int32_t step = adjoint_step[I.level[c]];
         for (int side = 0; side < 2; ++side) {
           int32_t x = side == 0 ? a : b, other = side == 0 ? b : a;
           if (!I.needs[x]) continue;
+          const int32_t ov = val[other];
           PT d;
           if (x < nl) {
             d.legs = T[I.tid[x]].legs;  // leaf order for the gradient dot
           } else {
             // natural order of contract(dC, other): dC's free legs then other's
             const auto& cl = T[adj[c]].legs;
-            const auto& ol = T[I.tid[other]].legs;
+            const auto& ol = T[ov].legs;
             for (int32_t l : cl)
               if (std::find(ol.begin(), ol.end(), l) == ol.end()) d.legs.push_back(l);
             for (int32_t l : ol)
               if (std::find(cl.begin(), cl.end(), l) == cl.end()) d.legs.push_back(l);
           }
           d.elems = 1ull << d.legs.size();
-          d.batched = T[adj[c]].batched || T[I.tid[other]].batched;
+          d.batched = T[adj[c]].batched || T[ov].batched;
           d.first = step;
-          d.last = step;  // extended below
+          d.last = step;  // extended when consumed
           int32_t did = (int32_t)T.size();
           T.push_back(d);
-          pend.push_back({adj[c], I.tid[other], did, step, true});
+          S.pend.push_back({adj[c], ov, did, step, true, false});
           T[adj[c]].last = std::max(T[adj[c]].last, step);
-          T[I.tid[other]].last = std::max(T[I.tid[other]].last, step);
+          T[ov].last = std::max(T[ov].last, step);
           adj[x] = did;
-          depth[x] = depth[c] + 1;
           if (x < nl) {
-            leaf_adj.push_back({I.tid[x], did});
-            leaf_adj_term.push_back({t, x});
+            S.leaf_adj.push_back({I.tid[x], did});
+            S.leaf_adj_term.push_back({t, x});
           }
         }
       }
     }
   }
-  const int32_t grad_step = max_bstep + 1;
-  for (auto& la : leaf_adj) T[la.second].last = grad_step;
+  for (auto& la : S.leaf_adj) T[la.second].last = S.grad_step;
 
   // ---- arena: allocate in step order, release after last use
-  {
-    Arena ar;
-    ar.top = seed_elems;
-    const int32_t n_steps = grad_step + 1;
-    std::vector<std::vector<int32_t>> born(n_steps + 1), dies(n_steps + 2);
-    for (int32_t i = 0; i < (int32_t)T.size(); ++i) {
-      if (T[i].fixed) continue;
-      born[T[i].first].push_back(i);
-      dies[std::max(T[i].last, T[i].first) + 1].push_back(i);
-    }
-    for (int32_t s = 0; s < n_steps; ++s) {
-      for (int32_t i : dies[s]) {
-        uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
-        ar.release((uint64_t)T[i].off, n);
-      }
-      // big tensors first keeps the best-fit layout compact
-      std::sort(born[s].begin(), born[s].end(),
-                [&](int32_t x, int32_t y) { return T[x].elems > T[y].elems; });
-      for (int32_t i : born[s]) {
-        uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
-        T[i].off = (int64_t)ar.alloc(n);
-        plan.arena_elems = std::max(plan.arena_elems, ar.top);
-        plan.peak_tensor_elems = std::max(plan.peak_tensor_elems, n);
-      }
-    }
-    plan.arena_elems = std::max(plan.arena_elems, seed_elems);
+  Arena ar;
+  ar.top = S.seed_elems;
+  const int32_t n_steps = S.grad_step + 1;
+  std::vector<std::vector<int32_t>> born(n_steps + 1), dies(n_steps + 2);
+  for (int32_t i = 0; i < (int32_t)T.size(); ++i) {
+    if (T[i].fixed) continue;
+    born[T[i].first].push_back(i);
+    dies[std::max(T[i].last, T[i].first) + 1].push_back(i);
   }
+  for (int32_t s = 0; s < n_steps; ++s) {
+    for (int32_t i : dies[s]) {
+      uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
+      ar.release((uint64_t)T[i].off, n);
+    }
+    // big tensors first keeps the best-fit layout compact
+    std::sort(born[s].begin(), born[s].end(),
+              [&](int32_t x, int32_t y) { return T[x].elems > T[y].elems; });
+    for (int32_t i : born[s]) {
+      uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
+      T[i].off = (int64_t)ar.alloc(n);
+      S.arena_elems = std::max(S.arena_elems, ar.top);
+      S.peak_tensor_elems = std::max(S.peak_tensor_elems, n);
+    }
+  }
+  S.arena_elems = std::max(S.arena_elems, S.seed_elems);
+}
+
+}  // namespace
+
+WorkspaceLayout workspace_layout(const Plan& p) {
+  auto al = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  WorkspaceLayout w{};
+  uint64_t o = 0;
+  w.ops = o; o = al(o + p.ops.size() * sizeof(DevOp));
+  w.tabs = o; o = al(o + p.tabs.size() * sizeof(uint32_t));
+  w.leaves = o; o = al(o + p.leaves.size() * sizeof(DevLeaf));
+  w.ftab = o; o = al(o + p.ftab.size() * sizeof(float));
+  w.uses = o; o = al(o + p.uses.size() * sizeof(DevGradUse));
+  w.slot_begin = o; o = al(o + p.slot_begin.size() * sizeof(uint32_t));
+  w.roots = o; o = al(o + p.roots.size() * sizeof(DevRoot));
+  w.params = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(float));
+  w.value = o; o = al(o + (uint64_t)p.batch * 2 * sizeof(double));
+  w.grad = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(double));
+  w.arena = o; o = al(o + p.arena_elems * 8);
+  w.total = o;
+  return w;
+}
+
+void build_plan(Plan& plan, const Network& net, const Path& path) {
+  const int B = plan.batch;
+  const bool grad = plan.want_grad != 0;
+  plan.n_params = net.n_params;
+  plan.n_terms = (int32_t)net.terms.size();
+  if (path.terms.size() != net.terms.size()) fail(TC_ERR_INVALID_ARG, "path does not match network");
+
+  // ---- schedule, with checkpointing when the budget asks for it
+  Schedule S;
+  int ckpt = plan.checkpoint > 0 ? plan.checkpoint : 0;
+  schedule(S, net, path, B, grad, ckpt);
+  if (grad && plan.checkpoint == 0 && plan.budget && S.arena_elems * 8 > plan.budget &&
+      S.max_level >= 4) {
+    // smallest arena over segment lengths 2 .. max_level / 2
+    Schedule best;
+    int best_c = 0;
+    for (int c = 2; c <= std::max(2, S.max_level / 2); ++c) {
+      Schedule t;
+      schedule(t, net, path, B, grad, c);
+      if (!best_c || t.arena_elems < best.arena_elems) {
+        best = std::move(t);
+        best_c = c;
+      }
+    }
+    if (best.arena_elems < S.arena_elems) {
+      S = std::move(best);
+      ckpt = best_c;
+    }
+  }
+  plan.checkpoint_used = grad ? ckpt : 0;
+  plan.arena_elems = S.arena_elems;
+  plan.peak_tensor_elems = S.peak_tensor_elems;
   // the arena alone already exceeds the budget: stop before building tables
   if (plan.budget && plan.arena_elems * 8 > plan.budget)
     fail(TC_ERR_TOO_LARGE, "live intermediates need " + std::to_string(plan.arena_elems * 8) +
                                " bytes, more than the memory budget");
+  std::vector<PT>& T = S.T;
+  std::vector<PendingOp>& pend = S.pend;
+  std::vector<TermInfo>& ti = S.ti;
+  const uint64_t seed_elems = S.seed_elems;
+  for (size_t t = 0; t < net.terms.size(); ++t) {
+    plan.seeds.push_back((float)net.terms[t].weight);
+    plan.seeds.push_back(0.0f);
+  }
+  Tables tables(plan.tabs);
 
   // ---- contraction ops, grouped into launches by step
   std::stable_sort(pend.begin(), pend.end(),
                    [](const PendingOp& x, const PendingOp& y) { return x.step < y.step; });
   double flops = 0, bytes = 0, gflops = 0, gbytes = 0;
+  int32_t n_gemm_nodes = 0;
   size_t i = 0;
   while (i < pend.size()) {
     size_t j = i;
     while (j < pend.size() && pend[j].step == pend[i].step) ++j;
-    // classify: wave kernel for long sums into few outputs, else gather
     std::vector<DevOp> gc, gm;
     double lf = 0, lb = 0;
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
       const PT& Bt = T[pend[k].b];
       const PT& C = T[pend[k].c];
-      std::vector<int32_t> S, FA, FB;
+      std::vector<int32_t> Sh, FA, FB;
       for (int32_t l : A.legs)
-        (std::find(Bt.legs.begin(), Bt.legs.end(), l) != Bt.legs.end() ? S : FA).push_back(l);
+        (std::find(Bt.legs.begin(), Bt.legs.end(), l) != Bt.legs.end() ? Sh : FA).push_back(l);
       for (int32_t l : Bt.legs)
         if (std::find(A.legs.begin(), A.legs.end(), l) == A.legs.end()) FB.push_back(l);
       DevOp op{};
@@ -364,10 +445,10 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       op.c = (uint64_t)C.off;
       op.M = 1u << FA.size();
       op.N = 1u << FB.size();
-      op.K = 1u << S.size();
+      op.K = 1u << Sh.size();
       op.a_m = tables.gather(A.legs, FA);
-      op.a_k = tables.gather(A.legs, S);
-      op.b_k = tables.gather(Bt.legs, S);
+      op.a_k = tables.gather(A.legs, Sh);
+      op.b_k = tables.gather(Bt.legs, Sh);
       op.b_n = tables.gather(Bt.legs, FB);
       op.c_m = tables.gather(C.legs, FA);
       op.c_n = tables.gather(C.legs, FB);
@@ -396,6 +477,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         op.tiles_m = (op.M + 63) / 64;
         op.tiles_n = (op.N + 63) / 64;
         gm.push_back(op);
+        if (!pend[k].bwd) ++n_gemm_nodes;
       } else {
         // gather: split long sums over up to 64 lanes while the op is small,
         // else 4 outputs per thread along n
@@ -437,19 +519,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     L.end = (uint32_t)plan.ops.size();
     L.work = (w + 63) & ~uint64_t(63);
-    plan.info.n_gemm_nodes += pend[i].bwd ? 0 : (int32_t)gm.size();
-    if (!pend[i].bwd && plan.fwd.empty()) {
-      Launch LL;
-      LL.kind = L_LEAF;
-      plan.fwd.push_back(LL);  // leaf launch first; filled below
-    }
     (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
     i = j;
   }
-  if (plan.fwd.empty() || plan.fwd[0].kind != L_LEAF) {
+  {
     Launch L;
     L.kind = L_LEAF;
-    plan.fwd.insert(plan.fwd.begin(), L);
+    plan.fwd.insert(plan.fwd.begin(), L);  // filled below
   }
 
   // ---- leaves
@@ -511,17 +587,16 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
 
   // ---- gradient uses, sorted by slot then creation order
   if (grad) {
-    // leaf table index of (term, leaf)
     std::vector<uint32_t> leaf_base(net.terms.size() + 1, 0);
     for (size_t t = 0; t < net.terms.size(); ++t)
       leaf_base[t + 1] = leaf_base[t] + (uint32_t)net.terms[t].leaves.size();
     std::vector<DevGradUse> uses;
-    for (size_t u = 0; u < leaf_adj.size(); ++u) {
-      size_t t = leaf_adj_term[u].first;
-      int32_t li = leaf_adj_term[u].second;
+    for (size_t u = 0; u < S.leaf_adj.size(); ++u) {
+      size_t t = S.leaf_adj_term[u].first;
+      int32_t li = S.leaf_adj_term[u].second;
       const Leaf& lf = net.terms[t].leaves[li];
       const GateRec& g = net.gates[lf.gate];
-      const PT& d = T[leaf_adj[u].second];
+      const PT& d = T[S.leaf_adj[u].second];
       for (int a = 0; a < g.n_angles; ++a) {
         if (g.param[a] < 0) continue;
         DevGradUse gu{};
@@ -571,8 +646,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           (d.param[0] >= plan.n_params) || (d.param[1] >= plan.n_params))
         fail(TC_ERR_INVALID_ARG, "internal: leaf out of range");
     for (const DevGradUse& u : plan.uses)
-      if (u.adj + (uint64_t)(B - 1) * u.adj_bs + (1ull << plan.leaves[u.leaf].rank) > AE ||
-          u.leaf >= plan.leaves.size())
+      if (u.leaf >= plan.leaves.size() ||
+          u.adj + (uint64_t)(B - 1) * u.adj_bs + (1ull << plan.leaves[u.leaf].rank) > AE)
         fail(TC_ERR_INVALID_ARG, "internal: gradient use out of range");
     for (const DevRoot& r : plan.roots)
       if (r.present && r.val + (uint64_t)(B - 1) * r.bs >= AE)
@@ -581,9 +656,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
 
   // ---- info
   tc_plan_info& info = plan.info;
-  const int32_t n_gemm = info.n_gemm_nodes;
   info = tc_plan_info{};
-  info.n_gemm_nodes = n_gemm;
+  info.n_gemm_nodes = n_gemm_nodes;
   info.flops = flops;
   info.alg_bytes = bytes;
   info.grad_flops = gflops;
@@ -594,12 +668,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   for (const auto& p : pend)
     if (!p.bwd) ++nn;
   info.n_nodes = nn;
-  info.n_levels = max_level;
+  info.n_levels = S.max_level;
   info.n_launches = (int32_t)plan.fwd.size();
   info.n_grad_launches = (int32_t)plan.bwd.size();
   info.batch = B;
   info.n_params = net.n_params;
   info.n_terms = plan.n_terms;
+  info.checkpoint_every = plan.checkpoint_used;
   if (plan.budget && info.workspace_bytes > plan.budget)
     fail(TC_ERR_TOO_LARGE, "workspace of " + std::to_string(info.workspace_bytes) +
                                " bytes exceeds the memory budget");

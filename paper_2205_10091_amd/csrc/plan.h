@@ -37,6 +37,10 @@ struct Plan {
   int32_t n_params = 0, n_terms = 0;
   // nodes with K >= gemm_min_k and M, N >= gemm_min_mn go to the MFMA GEMM
   int32_t gemm_min_k = 8, gemm_min_mn = 16;
+  // checkpoint segment length: 0 = only when the budget requires it,
+  // >= 2 = always with that length, -1 = never
+  int32_t checkpoint = 0;
+  int32_t checkpoint_used = 0;
 
   // tables uploaded once
   std::vector<DevOp> ops;

@@ -257,6 +257,22 @@ def test_grid_gemm_nodes_fp32_and_bf16x3():
         assert rel_err(a, ref, 2 ** (-n / 2)) < tol, prec
 
 
+@pytest.mark.parametrize("ckpt", [2, 3, 5])
+def test_checkpointed_gradient_matches(ckpt):
+    B = 8
+    circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=14, layers=5)
+    full = api.compile(circ, obs, batch=B, want_grad=True, checkpoint_every=-1)
+    ck = api.compile(circ, obs, batch=B, want_grad=True, checkpoint_every=ckpt)
+    assert ck.info().checkpoint_every == ckpt
+    assert ck.info().workspace_bytes < full.info().workspace_bytes
+    e1, g1 = full.contract_grad(device_params(P, B))
+    e2, g2 = ck.contract_grad(device_params(P, B))
+    assert np.max(np.abs(e1 - e2)) < 1e-6
+    assert np.max(np.abs(g1 - g2)) < 1e-6
+    e_ref, g_ref = sv.energy_grad(circ, P[3], obs)
+    assert grad_err(g2[3], g_ref) < TOL_C64
+
+
 def test_autograd_function_matches_oracle():
     import torch
     B = 4

@@ -93,6 +93,24 @@ def test_bad_path_is_rejected():
     path.replace_term(0, pairs)  # the original is accepted
 
 
+def test_checkpointing_shrinks_the_workspace_under_a_budget():
+    circ, p, obs = tcgen.workload_vqe_chain()
+    net = api.Network(circ, obs)
+    path = api.Path(net, n_trials=8, seed=1)
+    full = api.Plan(net, path, batch=256, want_grad=True, checkpoint_every=-1).info()
+    forced = api.Plan(net, path, batch=256, want_grad=True, checkpoint_every=3).info()
+    assert full.checkpoint_every == 0 and forced.checkpoint_every == 3
+    assert forced.workspace_bytes < full.workspace_bytes
+    assert forced.grad_flops > full.grad_flops          # recomputation
+    assert forced.flops == full.flops
+    budget = (full.workspace_bytes + forced.workspace_bytes) // 2
+    auto = api.Plan(net, path, batch=256, want_grad=True, mem_budget_bytes=budget).info()
+    assert auto.checkpoint_every >= 2 and auto.workspace_bytes <= budget
+    with pytest.raises(L.TcxError) as e:
+        api.Plan(net, path, batch=256, want_grad=True, checkpoint_every=1)
+    assert e.value.status == L.TC_ERR_INVALID_ARG
+
+
 def test_plan_is_host_only_and_reports_sizes():
     circ, p, obs = tcgen.workload_vqe_chain()
     net = api.Network(circ, obs)
