@@ -140,11 +140,26 @@ __device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
 // Materialise every leaf tensor (gates, boundary vectors, Pauli matrices)
 // for every batch row from the parameter vectors.
 __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.total;
-       w += (uint64_t)gridDim.x * blockDim.x) {
-    const LeafSeg& S = a.seg[find_seg(a, w, [](const LeafSeg& s) { return s.start; })];
+  // contiguous chunk per block; the leaf index only walks forward
+  const uint64_t chunk = (((a.total + gridDim.x - 1) / gridDim.x) + 255) & ~uint64_t(255);
+  const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+  const uint64_t end = begin + chunk < a.total ? begin + chunk : a.total;
+  uint32_t si = 0xffffffffu, li = 0;
+  for (uint64_t w = begin + threadIdx.x; w < end; w += blockDim.x) {
+    if (si == 0xffffffffu) {
+      si = find_seg(a, w, [](const LeafSeg& s) { return s.start; });
+      li = find_item(a.seg[si].leaves, a.seg[si].n, w - a.seg[si].start);
+    } else {
+      while (si + 1 < a.nseg && a.seg[si + 1].start <= w) {
+        ++si;
+        li = 0;
+      }
+      const LeafSeg& s0 = a.seg[si];
+      while (li + 1 < s0.n && s0.leaves[li + 1].work0 <= w - s0.start) ++li;
+    }
+    const LeafSeg& S = a.seg[si];
     const uint64_t ws = w - S.start;
-    const DevLeaf& L = S.leaves[find_item(S.leaves, S.n, ws)];
+    const DevLeaf& L = S.leaves[li];
     const uint64_t l = ws - L.work0;
     const int e = (int)(l & ((1u << L.rank) - 1));
     const uint64_t r = l >> L.rank;
@@ -189,15 +204,33 @@ __global__ void __launch_bounds__(256) k_level(LevelArgs a) {
     }
     return;
   }
-  const uint64_t stride = (uint64_t)(gridDim.x - a.gemm_blocks) * blockDim.x;
-  for (uint64_t w = (uint64_t)(blockIdx.x - a.gemm_blocks) * blockDim.x + threadIdx.x;
-       w < a.gc_work; w += stride) {
-    const LevelSeg& Sg = a.seg[find_seg(a, w, [](const LevelSeg& s) { return s.gc_start; })];
+  // each block takes one contiguous chunk (a multiple of 256 items, so
+  // wavefronts never straddle its end); a thread finds its segment and op
+  // once and then only walks forward
+  const uint64_t nblk = gridDim.x - a.gemm_blocks;
+  const uint64_t chunk = (((a.gc_work + nblk - 1) / nblk) + 255) & ~uint64_t(255);
+  const uint64_t begin = (uint64_t)(blockIdx.x - a.gemm_blocks) * chunk;
+  const uint64_t end = begin + chunk < a.gc_work ? begin + chunk : a.gc_work;
+  uint32_t si = 0xffffffffu, oi = 0;
+  for (uint64_t w = begin + threadIdx.x; w < end; w += blockDim.x) {
+    if (si == 0xffffffffu) {
+      si = find_seg(a, w, [](const LevelSeg& s) { return s.gc_start; });
+      oi = a.seg[si].n_gc ? find_item(a.seg[si].gc_ops, a.seg[si].n_gc, w - a.seg[si].gc_start)
+                          : 0u;
+    } else {
+      while (si + 1 < a.nseg && a.seg[si + 1].gc_start <= w) {
+        ++si;
+        oi = 0;
+      }
+      const LevelSeg& s0 = a.seg[si];
+      while (oi + 1 < s0.n_gc && s0.gc_ops[oi + 1].work0 <= w - s0.gc_start) ++oi;
+    }
+    const LevelSeg& Sg = a.seg[si];
     const uint32_t* __restrict__ tab = Sg.tab;
     float2* __restrict__ arena = Sg.arena;
     const uint64_t ws = w - Sg.gc_start;
     const bool has = Sg.n_gc > 0;
-    const DevOp& op = Sg.gc_ops[has ? find_item(Sg.gc_ops, Sg.n_gc, ws) : 0];
+    const DevOp& op = Sg.gc_ops[oi];
     const uint32_t ls = has ? (op.flags >> 4) & 7u : 0u;
     const uint32_t lv = has ? (op.flags >> 8) & 3u : 0u;
     const uint32_t S = 1u << ls, V = 1u << lv;
