@@ -106,6 +106,63 @@ def cpu_baseline(circ, p, obs, budget_s=15.0):
                       f"({dt:.1f} s)"}
 
 
+def serve_workload(args, out):
+    """Serving mix: chains and grids of 8-64 qubits (chains up to 600 at
+    depth 2), depth 2-10, TFIM energy (g ~ U[0.5, 1.5]) with gradient for
+    half of them, Poisson arrivals.  The plain per-circuit form (plan +
+    contract each request alone, one after another) sets the saturated
+    rate; the engine is then driven at 0.5, 0.8 and 0.95 of it."""
+    import tcgen
+    from paper_2205_10091_amd import _lib as L
+    from paper_2205_10091_amd import api, serve
+    import torch
+    n_req = max(args.steps, 20)
+    reqs = tcgen.serving_requests(n_req, 1.0, seed=6)
+    # plain per-circuit form on the first requests
+    t0 = time.perf_counter()
+    done = rejected = 0
+    for rq in reqs[:min(40, n_req)]:
+        try:
+            plan = api.compile(rq.circuit, rq.observable, want_grad=rq.want_grad, n_trials=1,
+                               mem_budget_bytes=4 << 30)
+        except L.TcxError as e:
+            if e.status != L.TC_ERR_TOO_LARGE:
+                raise
+            rejected += 1
+            continue
+        par = torch.from_numpy(rq.params).cuda()
+        if rq.want_grad:
+            plan.contract_grad(par)
+        else:
+            plan.contract(par)
+        done += 1
+    plain_s = time.perf_counter() - t0
+    lam_sat = (done + rejected) / plain_s
+    out["plain_per_circuit"] = {"requests": done + rejected, "rejected": rejected,
+                                "requests_per_s": lam_sat}
+    runs = []
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * lam_sat
+        rs = tcgen.serving_requests(n_req, rate, seed=6)
+        srv = serve.Server(pool_bytes=64 << 30, max_request_bytes=4 << 30, max_active=64,
+                           path_trials=1)
+        rep = serve.run(srv, rs, realtime=True)
+        srv.close()
+        s = rep.summary()
+        s["rate_per_s"] = rate
+        s["rate_frac_of_plain"] = frac
+        s["rejected_frac"] = len(rep.rejected) / n_req
+        runs.append(s)
+    best = runs[-1]
+    out.update({"metric": "circuit evals/s under Poisson arrivals (serving mix), p50/p99 latency",
+                "value": best["evals_per_s"], "unit": "evals/s",
+                "ms_per_step": 1e3 / best["evals_per_s"] if best["evals_per_s"] else None,
+                "dtype": "c64 (fp32) + fp64 sums",
+                "config": {"workload": "serving_mix_chain_grid_8_64_depth_2_10", "requests": n_req,
+                           "max_active": 64, "path_trials": 1},
+                "serving": runs})
+
+
 def timed(step, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -123,7 +180,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="vqe", choices=["vqe", "batched", "forward", "grid"])
+    ap.add_argument("--workload", default="vqe",
+                    choices=["vqe", "batched", "forward", "grid", "serve"])
     ap.add_argument("--trials", type=int, default=32, help="greedy path trials")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -193,6 +251,8 @@ def main():
         rl, share = roofline(prof, args.workload)
         out["rel_err_amplitude"] = abs(a - sv.amplitude(circ, p)) / max(abs(sv.amplitude(circ, p)), 2 ** -5)
         out["rel_err_zz"] = abs(z - sv.energy(circ, p, zz))
+    elif args.workload == "serve":
+        pass  # handled below
     else:
         circ, p, amp = tcgen.workload_grid_amplitude()
         t0 = time.perf_counter()
@@ -212,14 +272,18 @@ def main():
         r = complex(ref["values"]["col2"]["re"], ref["values"]["col2"]["im"])
         out["rel_err_amplitude"] = abs(v[0] - r) / max(abs(r), 2 ** -18)
 
-    out["plan"] = {"flops": info.flops, "grad_flops": info.grad_flops,
-                   "alg_bytes": info.alg_bytes + info.grad_alg_bytes,
-                   "workspace_bytes": int(info.workspace_bytes), "nodes": info.n_nodes,
-                   "gemm_nodes": info.n_gemm_nodes, "levels": info.n_levels,
-                   "launches_per_step": info.n_launches + info.n_grad_launches,
-                   "plan_seconds": plan_s}
-    out["roofline"] = rl
-    out["time_share_by_kernel"] = share
+    if args.workload == "serve":
+        serve_workload(args, out)
+        out["roofline"] = None   # a mix of plans: see the per-workload runs
+    else:
+        out["plan"] = {"flops": info.flops, "grad_flops": info.grad_flops,
+                       "alg_bytes": info.alg_bytes + info.grad_alg_bytes,
+                       "workspace_bytes": int(info.workspace_bytes), "nodes": info.n_nodes,
+                       "gemm_nodes": info.n_gemm_nodes, "levels": info.n_levels,
+                       "launches_per_step": info.n_launches + info.n_grad_launches,
+                       "checkpoint_every": info.checkpoint_every, "plan_seconds": plan_s}
+        out["roofline"] = rl
+        out["time_share_by_kernel"] = share
     out["kernel_source_hash"] = kernel_source_hash()
 
     if args.workload == "vqe" and not args.no_extras:

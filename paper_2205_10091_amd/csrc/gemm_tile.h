@@ -111,26 +111,34 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
         cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       }
-    for (uint32_t k0 = 0; k0 < op.K; k0 += BK32) {
+    // register prefetch: the next k-tile's global loads are in flight while
+    // the current tile's MFMAs run
+    float2 pa[4], pb[4];
+    auto fetch = [&](uint32_t k0) {
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         // A element (m, k): k fastest across threads when A is k-contiguous
+        uint32_t k = k0 + (akf ? (t & 15) : (t >> 6) + 4 * p);
+        pa[p] = (aok[p] && k < op.K) ? c.A[aoff[p] + tab[op.a_k + k]] : make_float2(0.f, 0.f);
+        k = k0 + (bkf ? (t & 15) : (t >> 6) + 4 * p);
+        pb[p] = (bok[p] && k < op.K) ? c.B[boff[p] + tab[op.b_k + k]] : make_float2(0.f, 0.f);
+      }
+    };
+    fetch(0);
+    for (uint32_t k0 = 0; k0 < op.K; k0 += BK32) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
         int kk = akf ? (t & 15) : (t >> 6) + 4 * p;
         int mm = akf ? (t >> 4) + 16 * p : (t & 63);
-        uint32_t k = k0 + kk;
-        float2 v = make_float2(0.f, 0.f);
-        if (aok[p] && k < op.K) v = c.A[aoff[p] + tab[op.a_k + k]];
-        As[0][kk][mm] = v.x;
-        As[1][kk][mm] = v.y;
+        As[0][kk][mm] = pa[p].x;
+        As[1][kk][mm] = pa[p].y;
         kk = bkf ? (t & 15) : (t >> 6) + 4 * p;
         int nn = bkf ? (t >> 4) + 16 * p : (t & 63);
-        k = k0 + kk;
-        v = make_float2(0.f, 0.f);
-        if (bok[p] && k < op.K) v = c.B[boff[p] + tab[op.b_k + k]];
-        Bs[0][kk][nn] = v.x;
-        Bs[1][kk][nn] = v.y;
+        Bs[0][kk][nn] = pb[p].x;
+        Bs[1][kk][nn] = pb[p].y;
       }
       __syncthreads();
+      if (k0 + BK32 < op.K) fetch(k0 + BK32);
 #pragma unroll
       for (int kk = 0; kk < BK32; kk += 4) {
         const int kr = kk + (lane >> 4);
