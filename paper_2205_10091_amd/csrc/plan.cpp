@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <set>
 #include <string>
 #include <unordered_map>
 
@@ -49,52 +50,68 @@ struct PT {                       // a tensor of the plan
 struct Tables {
   std::vector<uint32_t>& tabs;
   std::unordered_map<std::string, uint32_t> memo;
+  std::unordered_map<uint32_t, uint32_t> maxv;  // table base -> largest entry
   explicit Tables(std::vector<uint32_t>& t) : tabs(t) {}
 
-  // offsets of index i over the ordered sub-legs `sub` of a tensor with
-  // legs `xl`: sum_j bit_j(i) * 2^pos(sub[j]), sub[0] most significant
-  uint32_t gather(const std::vector<int32_t>& xl, const std::vector<int32_t>& sub) {
-    std::vector<uint32_t> stride(sub.size());
-    const int r = (int)xl.size();
-    std::string key;
-    for (size_t j = 0; j < sub.size(); ++j) {
-      int idx = (int)(std::find(xl.begin(), xl.end(), sub[j]) - xl.begin());
-      if (idx >= r) fail(TC_ERR_INVALID_ARG, "internal: leg missing from tensor");
+  // offsets of index i over the ordered sub-legs `sub` of a rank-r tensor
+  // whose leg l sits at position pos[l]: sum_j bit_j(i) * 2^(r-1-pos[sub[j]]),
+  // sub[0] most significant
+  uint32_t gather(const std::vector<int8_t>& pos, int r, const std::vector<int32_t>& sub) {
+    uint32_t stride[32];
+    char sh[32];
+    const size_t nb = sub.size();
+    for (size_t j = 0; j < nb; ++j) {
+      const int idx = pos[sub[j]];
+      if (idx < 0) fail(TC_ERR_INVALID_ARG, "internal: leg missing from tensor");
+      sh[j] = (char)(r - 1 - idx);
       stride[j] = 1u << (r - 1 - idx);
-      key += std::to_string(stride[j]);
-      key += ',';
     }
+    std::string key(sh, nb);
     auto it = memo.find(key);
     if (it != memo.end()) return it->second;
-    const size_t nb = stride.size();
     const uint64_t n = 1ull << nb;
     if (tabs.size() + n > 0xFFFFFFFFull) fail(TC_ERR_TOO_LARGE, "index tables exceed 2^32 entries");
     uint32_t base = (uint32_t)tabs.size();
     tabs.resize(tabs.size() + n);
-    for (uint64_t i = 0; i < n; ++i) {
-      uint32_t off = 0;
-      for (size_t j = 0; j < nb; ++j)
-        if ((i >> (nb - 1 - j)) & 1) off += stride[j];
-      tabs[base + i] = off;
+    // entry i = entry(i without its lowest set bit) + stride of that bit
+    tabs[base] = 0;
+    uint32_t mx = 0;
+    for (uint64_t i = 1; i < n; ++i) {
+      const int low = __builtin_ctzll(i);
+      const uint32_t v = tabs[base + (i & (i - 1))] + stride[nb - 1 - low];
+      tabs[base + i] = v;
+      mx = std::max(mx, v);
     }
     memo.emplace(key, base);
+    maxv.emplace(base, mx);
     return base;
   }
+  uint32_t max_of(uint32_t base) const { return maxv.at(base); }
 };
 
+// Best-fit allocator over element offsets: free blocks indexed both by
+// offset (to coalesce neighbours) and by size (to find the best fit).
 struct Arena {
-  std::map<uint64_t, uint64_t> free_;  // offset -> size (elements)
+  std::map<uint64_t, uint64_t> free_;             // offset -> size (elements)
+  std::set<std::pair<uint64_t, uint64_t>> by_size_;  // (size, offset)
   uint64_t top = 0;
   static uint64_t align(uint64_t x) { return (x + 31) & ~uint64_t(31); }  // 256 B
+  void add_free(uint64_t off, uint64_t n) {
+    free_[off] = n;
+    by_size_.emplace(n, off);
+  }
+  void drop_free(std::map<uint64_t, uint64_t>::iterator it) {
+    by_size_.erase({it->second, it->first});
+    free_.erase(it);
+  }
   uint64_t alloc(uint64_t n) {
     n = align(std::max<uint64_t>(n, 1));
-    auto best = free_.end();
-    for (auto it = free_.begin(); it != free_.end(); ++it)
-      if (it->second >= n && (best == free_.end() || it->second < best->second)) best = it;
-    if (best != free_.end()) {
-      uint64_t off = best->first, sz = best->second;
-      free_.erase(best);
-      if (sz > n) free_[off + n] = sz - n;
+    auto b = by_size_.lower_bound({n, 0});
+    if (b != by_size_.end()) {
+      uint64_t sz = b->first, off = b->second;
+      by_size_.erase(b);
+      free_.erase(off);
+      if (sz > n) add_free(off + n, sz - n);
       return off;
     }
     uint64_t off = top;
@@ -103,24 +120,24 @@ struct Arena {
   }
   void release(uint64_t off, uint64_t n) {
     n = align(std::max<uint64_t>(n, 1));
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + n == nx->first) {  // merge the next block
+      n += nx->second;
+      auto tmp = nx++;
+      drop_free(tmp);
     }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-        it = pv;
+    if (nx != free_.begin()) {                        // merge the previous block
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        n += pv->second;
+        drop_free(pv);
       }
     }
-    if (it->first + it->second == top) {
-      top = it->first;
-      free_.erase(it);
-    }
+    if (off + n == top)
+      top = off;
+    else
+      add_free(off, n);
   }
 };
 
@@ -386,10 +403,11 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   schedule(S, net, path, B, grad, ckpt);
   if (grad && plan.checkpoint == 0 && plan.budget && S.arena_elems * 8 > plan.budget &&
       S.max_level >= 4) {
-    // smallest arena over segment lengths 2 .. max_level / 2
+    // smallest arena over a few segment lengths
     Schedule best;
     int best_c = 0;
-    for (int c = 2; c <= std::max(2, S.max_level / 2); ++c) {
+    for (int c : {2, 3, 4, 6, 8, 12}) {
+      if (c > std::max(2, S.max_level / 2)) break;
       Schedule t;
       schedule(t, net, path, B, grad, c);
       if (!best_c || t.arena_elems < best.arena_elems) {
@@ -424,6 +442,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
                    [](const PendingOp& x, const PendingOp& y) { return x.step < y.step; });
   double flops = 0, bytes = 0, gflops = 0, gbytes = 0;
   int32_t n_gemm_nodes = 0;
+  // leg label -> position in one operand's storage order (-1: absent)
+  int32_t n_labels = 0;
+  for (const Term& term : net.terms) n_labels = std::max(n_labels, term.n_labels);
+  std::vector<int8_t> pa(n_labels, -1), pb(n_labels, -1), pc(n_labels, -1);
+  auto mark = [&](std::vector<int8_t>& pos, const std::vector<int32_t>& legs, bool on) {
+    for (size_t x = 0; x < legs.size(); ++x) {
+      if (legs[x] < 0 || legs[x] >= n_labels) fail(TC_ERR_INVALID_ARG, "internal: leg label out of range");
+      pos[legs[x]] = on ? (int8_t)x : (int8_t)-1;
+    }
+  };
+  std::vector<int32_t> Sh, FA, FB;
   size_t i = 0;
   while (i < pend.size()) {
     size_t j = i;
@@ -434,11 +463,15 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       const PT& A = T[pend[k].a];
       const PT& Bt = T[pend[k].b];
       const PT& C = T[pend[k].c];
-      std::vector<int32_t> Sh, FA, FB;
-      for (int32_t l : A.legs)
-        (std::find(Bt.legs.begin(), Bt.legs.end(), l) != Bt.legs.end() ? Sh : FA).push_back(l);
+      mark(pa, A.legs, true);
+      mark(pb, Bt.legs, true);
+      mark(pc, C.legs, true);
+      Sh.clear();
+      FA.clear();
+      FB.clear();
+      for (int32_t l : A.legs) (pb[l] >= 0 ? Sh : FA).push_back(l);
       for (int32_t l : Bt.legs)
-        if (std::find(A.legs.begin(), A.legs.end(), l) == A.legs.end()) FB.push_back(l);
+        if (pa[l] < 0) FB.push_back(l);
       DevOp op{};
       op.a = (uint64_t)A.off;
       op.b = (uint64_t)Bt.off;
@@ -446,12 +479,16 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       op.M = 1u << FA.size();
       op.N = 1u << FB.size();
       op.K = 1u << Sh.size();
-      op.a_m = tables.gather(A.legs, FA);
-      op.a_k = tables.gather(A.legs, Sh);
-      op.b_k = tables.gather(Bt.legs, Sh);
-      op.b_n = tables.gather(Bt.legs, FB);
-      op.c_m = tables.gather(C.legs, FA);
-      op.c_n = tables.gather(C.legs, FB);
+      const int ra = (int)A.legs.size(), rb = (int)Bt.legs.size(), rc = (int)C.legs.size();
+      op.a_m = tables.gather(pa, ra, FA);
+      op.a_k = tables.gather(pa, ra, Sh);
+      op.b_k = tables.gather(pb, rb, Sh);
+      op.b_n = tables.gather(pb, rb, FB);
+      op.c_m = tables.gather(pc, rc, FA);
+      op.c_n = tables.gather(pc, rc, FB);
+      mark(pa, A.legs, false);
+      mark(pb, Bt.legs, false);
+      mark(pc, C.legs, false);
       bool rowsB = (A.batched || Bt.batched) && B > 1;
       op.rows = rowsB ? (uint32_t)B : 1u;
       op.a_bs = (A.batched && B > 1) ? (uint32_t)A.elems : 0u;
@@ -628,9 +665,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     const uint64_t NT = plan.tabs.size();
     auto tmax = [&](uint32_t base, uint32_t n) {
       if ((uint64_t)base + n > NT) fail(TC_ERR_INVALID_ARG, "internal: table out of range");
-      uint32_t m = 0;
-      for (uint32_t x = 0; x < n; ++x) m = std::max(m, plan.tabs[base + x]);
-      return (uint64_t)m;
+      return (uint64_t)tables.max_of(base);  // a table of n = 2^b entries
     };
     for (const DevOp& op : plan.ops) {
       uint64_t r1 = op.rows - 1;
