@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
-KIND_NAMES = {0: "k_leaf", 1: "k_level", 4: "k_root", 5: "k_grad"}
+KIND_NAMES = {0: "k_leaf", 2: "k_gemm", 3: "k_gather", 4: "k_root", 5: "k_grad"}
 KERNEL_SOURCES = ["paper_2205_10091_amd/csrc/exec.hip", "paper_2205_10091_amd/csrc/gemm_tile.h",
                   "paper_2205_10091_amd/csrc/gates.h", "paper_2205_10091_amd/csrc/ops.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -75,7 +75,8 @@ def roofline(profile, workload):
     ai = f / b if b else 0.0
     name = KIND_NAMES[k]
     if ai > PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
-        rl = {"bound": "alu",
+        # above the ridge: FP32 MFMA for the GEMM tiles, FP32 vector ALU else
+        rl = {"bound": "mfma" if name == "k_gemm" else "alu",
               "achieved": f / secs / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
     else:
         rl = {"bound": "hbm", "achieved": b / secs / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
@@ -121,7 +122,11 @@ def serve_workload(args, out):
     # plain per-circuit form on the first requests
     t0 = time.perf_counter()
     done = rejected = 0
-    for rq in reqs[:min(40, n_req)]:
+    n_plain = min(40, n_req)
+    for k, rq in enumerate(reqs[:n_plain]):
+        if k % 10 == 0:
+            print(f"[serve] plain per-circuit {k}/{n_plain} t={time.perf_counter() - t0:.1f}s",
+                  file=sys.stderr, flush=True)
         try:
             plan = api.compile(rq.circuit, rq.observable, want_grad=rq.want_grad, n_trials=1,
                                mem_budget_bytes=4 << 30)
@@ -146,7 +151,10 @@ def serve_workload(args, out):
         rs = tcgen.serving_requests(n_req, rate, seed=6)
         srv = serve.Server(pool_bytes=64 << 30, max_request_bytes=4 << 30, max_active=64,
                            path_trials=1)
-        rep = serve.run(srv, rs, realtime=True)
+        print(f"[serve] engine at {frac:.2f} of plain rate ({rate:.2f} req/s)",
+              file=sys.stderr, flush=True)
+        rep = serve.run(srv, rs, realtime=True, progress=lambda t, d, r, p: print(
+            f"[serve]   t={t:.1f}s done={d} rejected={r} pending={p}", file=sys.stderr, flush=True))
         srv.close()
         s = rep.summary()
         s["rate_per_s"] = rate
@@ -271,6 +279,13 @@ def main():
         ref = json.load(open(os.path.join(ROOT, "tests/golden/grid6x6_d8_amplitude.json")))
         r = complex(ref["values"]["col2"]["re"], ref["values"]["col2"]["im"])
         out["rel_err_amplitude"] = abs(v[0] - r) / max(abs(r), 2 ** -18)
+        # the same tree with the wide nodes in split-BF16 (hi + lo) MFMA
+        plan16 = api.compile(circ, amp, n_trials=args.trials, seed=1, precision=1)
+        dt16, v16 = timed(lambda: plan16.contract(params), args.steps, args.warmup)
+        rl16, _ = roofline(plan16.profile(params, which=0, reps=5), args.workload)
+        out["bf16x3"] = {"evals_per_s": args.steps / dt16, "ms_per_step": dt16 / args.steps * 1e3,
+                         "rel_err_amplitude": abs(v16[0] - r) / max(abs(r), 2 ** -18),
+                         "dominant_kernel": rl16}
 
     if args.workload == "serve":
         serve_workload(args, out)

@@ -253,6 +253,10 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *               of their dimensions) and M, N >= 16 run on the MFMA GEMM,
  *               the rest on the gather kernels; 0 = default (8), a value
  *               above every K keeps all nodes on the gather kernels;
+ *   gemm_min_macs  a node also needs at least this many complex
+ *               multiply-adds (M N K times its batch rows) to go to the GEMM:
+ *               below it the gather kernels finish sooner; 0 = default
+ *               (2^20), 1 = no floor;
  *   checkpoint_every  with want_grad: 0 = keep every intermediate for the
  *               reverse sweep unless mem_budget_bytes is exceeded, in which
  *               case the segment length with the smallest workspace is
@@ -274,6 +278,7 @@ typedef struct {
   void* stream;              /* hipStream_t                               */
   int32_t gemm_min_k;
   int32_t checkpoint_every;
+  uint64_t gemm_min_macs;
 } tc_plan_opts;
 
 tc_status tc_plan_create(const tc_network* net, const tc_path* path,
@@ -331,16 +336,16 @@ tc_status tc_contract_device(tc_plan* plan, const float* params,
 tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
                                   double* value_dev, double* grad_dev);
 
-/* Profiling.  Runs the plan's launch sequence eagerly (not as a graph)
- * `reps` times with HIP events around every launch on the plan's stream;
- * params is a DEVICE pointer as for tc_contract.  For launch i <
+/* Profiling.  Runs the plan's kernels eagerly (not as a graph), one after
+ * another on the plan's stream, `reps` times with HIP events around every
+ * kernel; params is a DEVICE pointer as for tc_contract.  For kernel i <
  * *n_launches (at most `cap` are written) it reports the kernel class
- * kinds[i] (0 leaf materialisation, 1 contraction level: MFMA GEMM tiles
- * and gather contractions of one tree level, 4 FP64 root sum, 5 FP64
- * gradient sum),
- * the mean duration ms[i], and the launch's algorithmic flops[i] and
- * bytes[i] (operands read once plus results written once).  which: 0 the
- * forward sequence, 1 forward plus reverse sweep (needs want_grad). */
+ * kinds[i] (0 leaf materialisation, 2 MFMA GEMM tiles of one tree level,
+ * 3 gather contractions of one tree level, 4 FP64 root sum, 5 FP64
+ * gradient sum), the mean duration ms[i], and the kernel's algorithmic
+ * flops[i] and bytes[i] (operands read once plus results written once).
+ * which: 0 the forward sequence, 1 forward plus reverse sweep (needs
+ * want_grad).  In contractions the two kernels of a level may overlap. */
 tc_status tc_plan_profile(tc_plan* plan, const float* params, int32_t which,
                           int32_t reps, int32_t cap, int32_t* n_launches,
                           int32_t* kinds, double* ms, double* flops,

@@ -69,7 +69,8 @@ class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("batch", C.c_int32),
                 ("want_grad", C.c_int32), ("device", C.c_int32),
                 ("mem_budget_bytes", C.c_uint64), ("stream", C.c_void_p),
-                ("gemm_min_k", C.c_int32), ("checkpoint_every", C.c_int32)]
+                ("gemm_min_k", C.c_int32), ("checkpoint_every", C.c_int32),
+                ("gemm_min_macs", C.c_uint64)]
 
 
 class PlanInfo(C.Structure):

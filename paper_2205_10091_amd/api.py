@@ -148,12 +148,13 @@ class Plan:
 
     def __init__(self, net: Network, path: Path, batch=1, want_grad=False,
                  precision=0, device=0, mem_budget_bytes=0, stream=None, gemm_min_k=0,
-                 checkpoint_every=0):
+                 checkpoint_every=0, gemm_min_macs=0):
         self.net, self.path = net, path
         self.batch = batch
         self.want_grad = want_grad
         opts = L.PlanOpts(precision, batch, int(want_grad), device,
-                          mem_budget_bytes, stream, gemm_min_k, checkpoint_every)
+                          mem_budget_bytes, stream, gemm_min_k, checkpoint_every,
+                          gemm_min_macs)
         h = C.c_void_p()
         L.check(lib().tc_plan_create(net.h, path.h, C.byref(opts), C.byref(h)))
         self.h = h
@@ -222,10 +223,11 @@ class Plan:
         return val, grad.reshape(self.batch, self.n_params)
 
     def profile(self, params, which=0, reps=10):
-        """Per-launch (kind, mean ms, algorithmic flops, bytes) arrays from an
-        eager replay with HIP events around each launch."""
+        """Per-kernel (kind, mean ms, algorithmic flops, bytes) arrays from an
+        eager replay with HIP events around each kernel (a level has a GEMM
+        and a gather kernel)."""
         info = self.info()
-        cap = info.n_launches + info.n_grad_launches + 8
+        cap = 2 * (info.n_launches + info.n_grad_launches) + 8
         kinds = np.zeros(cap, np.int32)
         ms, fl, by = (np.zeros(cap, np.float64) for _ in range(3))
         n = C.c_int32()
@@ -233,7 +235,9 @@ class Plan:
                                       C.byref(n), kinds.ctypes.data_as(L.I32P),
                                       ms.ctypes.data_as(L.F64P), fl.ctypes.data_as(L.F64P),
                                       by.ctypes.data_as(L.F64P)))
-        k = min(n.value, cap)
+        if n.value > cap:
+            raise RuntimeError(f"profile reported {n.value} kernels, more than {cap}")
+        k = n.value
         return kinds[:k], ms[:k], fl[:k], by[:k]
 
     def contract_device(self, params, out_dev):
@@ -249,7 +253,7 @@ class Plan:
 def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
             lightcone=True, absorb_1q=True, seed=0, n_trials=8,
             mem_budget_bytes=0, device=0, bind=True, gemm_min_k=0, stream=None,
-            checkpoint_every=0) -> Plan:
+            checkpoint_every=0, gemm_min_macs=0) -> Plan:
     """Network + greedy path + plan (+ bind with a torch workspace)."""
     net = Network(circ, obs, split_2q, lightcone, absorb_1q)
     path = Path(net, seed=seed, n_trials=n_trials)
@@ -262,7 +266,7 @@ def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
         torch_stream = torch.cuda.Stream(device=f"cuda:{device}")
         stream = torch_stream.cuda_stream
     plan = Plan(net, path, batch, want_grad, precision, device, mem_budget_bytes,
-                stream, gemm_min_k, checkpoint_every)
+                stream, gemm_min_k, checkpoint_every, gemm_min_macs)
     plan.torch_stream = torch_stream
     if bind:
         plan.bind_torch(f"cuda:{device}")

@@ -28,6 +28,8 @@ struct DeviceState {
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   int n_cu = 256;
+  hipStream_t side = nullptr;               // GEMM half of forked level launches
+  hipEvent_t fork_start = nullptr, fork_done = nullptr;
 };
 
 // One plan's launch, located in that plan's workspace.
@@ -41,10 +43,23 @@ struct SegRef {
 // Largest number of plans one merged launch carries (kernel-argument space).
 constexpr int MAX_SEG = 24;
 
+// A level launch with both GEMM tiles and gather work may fork: its GEMM
+// kernel runs on `side` (after `start` is recorded on the main stream) and
+// the main stream waits for `done` before the next launch.
+struct Fork {
+  hipStream_t side;
+  hipEvent_t start, done;
+};
+
+// Launch parts of a level: GEMM tiles, gather items.
+constexpr int PART_GEMM = 1, PART_GATHER = 2;
+
 // Enqueue one launch of `kind` covering all `segs` (at most MAX_SEG, all of
-// that kind) on `stream`.
+// that kind) on `stream`; for levels, only the kernels named in `parts`,
+// forked as above when `fork` is given.
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
-                     int precision);
+                     int precision, const Fork* fork = nullptr,
+                     int parts = PART_GEMM | PART_GATHER);
 
 // Asynchronous upload of a plan's tables and seeds into a workspace.
 void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStream_t stream);

@@ -43,6 +43,7 @@ namespace tcx {
 
 struct LeafSeg {
   const DevLeaf* leaves;
+  const uint32_t* item_leaf;  // leaf entry -> leaf index, or null (search)
   const float* ftab;
   const float* params;
   float2* arena;
@@ -58,19 +59,24 @@ struct LeafArgs {
 
 struct LevelSeg {
   const DevOp* gemm_ops;
+  const DevOp* wave_ops;
   const DevOp* gc_ops;
   const uint32_t* tab;
+  const uint32_t* item_op;  // gather item -> op index, or null (search)
   float2* arena;
   uint64_t gemm_start;  // first GEMM tile of this segment
+  uint64_t wave_start;  // first wave tile of this segment
   uint64_t gc_start;    // first gather item (a multiple of 64)
   uint32_t n_gemm;
+  uint32_t n_wave;
   uint32_t n_gc;
 };
 struct LevelArgs {
   LevelSeg seg[MAX_SEG];
   uint32_t nseg;
-  uint32_t gemm_blocks;
+  uint32_t tile_blocks;  // k_gemm blocks [0, tile_blocks) run 64 x 64 tiles
   uint64_t gemm_tiles;
+  uint64_t wave_tiles;
   uint64_t gc_work;
 };
 
@@ -137,6 +143,46 @@ __device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
   acc.im = fmaf(a.y, b.x, acc.im);
 }
 
+// acc[j] += sum over k = sub, sub + S, ... < K of A[ak[k]] * B[bk[k] + bn[j]],
+// j < V, accumulated in increasing k.  U steps are issued together so that
+// their table and operand loads overlap instead of forming one dependent
+// chain per step.
+template <int V>
+__device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restrict__ A,
+                                           const float2* __restrict__ Bp,
+                                           const uint32_t* __restrict__ ak,
+                                           const uint32_t* __restrict__ bk,
+                                           const uint32_t (&bn)[4], uint32_t sub, uint32_t S,
+                                           uint32_t K) {
+  constexpr int U = V == 4 ? 2 : (V == 2 ? 4 : 8);  // about 90 VGPRs: 5 waves per SIMD
+  uint32_t k = sub;
+  for (; k + (U - 1) * S < K; k += U * S) {
+    uint32_t ia[U], ib[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ia[u] = ak[k + u * S];
+      ib[u] = bk[k + u * S];
+    }
+    float2 av[U], bv[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      av[u] = A[ia[u]];
+#pragma unroll
+      for (int j = 0; j < V; ++j) bv[u][j] = Bp[ib[u] + bn[j]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < V; ++j) cfma(acc[j], av[u], bv[u][j]);
+  }
+  for (; k < K; k += S) {
+    const float2 av = A[ak[k]];
+    const float2* __restrict__ bb = Bp + bk[k];
+#pragma unroll
+    for (int j = 0; j < V; ++j) cfma(acc[j], av, bb[bn[j]]);
+  }
+}
+
 // Materialise every leaf tensor (gates, boundary vectors, Pauli matrices)
 // for every batch row from the parameter vectors.
 __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
@@ -144,21 +190,24 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
   const uint64_t chunk = (((a.total + gridDim.x - 1) / gridDim.x) + 255) & ~uint64_t(255);
   const uint64_t begin = (uint64_t)blockIdx.x * chunk;
   const uint64_t end = begin + chunk < a.total ? begin + chunk : a.total;
-  uint32_t si = 0xffffffffu, li = 0;
+  uint32_t si = 0xffffffffu, li = 0xffffffffu;
   for (uint64_t w = begin + threadIdx.x; w < end; w += blockDim.x) {
     if (si == 0xffffffffu) {
       si = find_seg(a, w, [](const LeafSeg& s) { return s.start; });
-      li = find_item(a.seg[si].leaves, a.seg[si].n, w - a.seg[si].start);
     } else {
       while (si + 1 < a.nseg && a.seg[si + 1].start <= w) {
         ++si;
-        li = 0;
+        li = 0xffffffffu;
       }
-      const LeafSeg& s0 = a.seg[si];
-      while (li + 1 < s0.n && s0.leaves[li + 1].work0 <= w - s0.start) ++li;
     }
     const LeafSeg& S = a.seg[si];
     const uint64_t ws = w - S.start;
+    if (S.item_leaf)
+      li = S.item_leaf[ws];
+    else if (li == 0xffffffffu)
+      li = find_item(S.leaves, S.n, ws);
+    else
+      while (li + 1 < S.n && S.leaves[li + 1].work0 <= ws) ++li;
     const DevLeaf& L = S.leaves[li];
     const uint64_t l = ws - L.work0;
     const int e = (int)(l & ((1u << L.rank) - 1));
@@ -171,65 +220,93 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
   }
 }
 
-// One contraction level: blocks [0, gemm_blocks) run 64 x 64 MFMA GEMM tiles,
-// the remaining blocks run the gather contractions of the same level.
-//
+// One contraction level is two kernels over the same arguments: k_gemm runs
+// the level's wide nodes as 64 x 64 MFMA GEMM tiles, k_gather its other
+// nodes.  They touch disjoint outputs, so they may run concurrently, and
+// each keeps its own register budget (the GEMM tiles' accumulators would
+// otherwise cap the gather waves' occupancy).
+template <int PREC>
+__global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
+  if (blockIdx.x >= a.tile_blocks) {
+    // wave tiles: one unit per wavefront, grid-stride over the units
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)(gridDim.x - a.tile_blocks) * (blockDim.x >> 6);
+    for (uint64_t u = (uint64_t)(blockIdx.x - a.tile_blocks) * (blockDim.x >> 6) +
+                      (threadIdx.x >> 6);
+         u < a.wave_tiles; u += waves) {
+      const LevelSeg& S = a.seg[find_seg(a, u, [](const LevelSeg& s) { return s.wave_start; })];
+      const uint64_t lu = u - S.wave_start;
+      const DevOp& op = S.wave_ops[find_item(S.wave_ops, S.n_wave, lu)];
+      switch ((op.flags >> 12) & 3u) {
+        case 0: wave_tile_f32<1, 1>(op, lu, S.tab, S.arena, lane); break;
+        case 1: wave_tile_f32<2, 1>(op, lu, S.tab, S.arena, lane); break;
+        case 2: wave_tile_f32<1, 2>(op, lu, S.tab, S.arena, lane); break;
+        default: wave_tile_f32<2, 2>(op, lu, S.tab, S.arena, lane); break;
+      }
+    }
+    return;
+  }
+  if constexpr (PREC == TC_PREC_BF16X3) {
+    __shared__ SmemBF16 smem;
+    for (uint64_t tile = blockIdx.x; tile < a.gemm_tiles; tile += a.tile_blocks) {
+      const LevelSeg& S =
+          a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
+      const uint64_t lt = tile - S.gemm_start;
+      const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
+      gemm_tile_bf16x3(op, lt, S.tab, S.arena, smem);
+    }
+  } else {
+    __shared__ SmemF32 smem;
+    for (uint64_t tile = blockIdx.x; tile < a.gemm_tiles; tile += a.tile_blocks) {
+      const LevelSeg& S =
+          a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
+      const uint64_t lt = tile - S.gemm_start;
+      const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
+      gemm_tile_f32(op, lt, S.tab, S.arena, smem);
+    }
+  }
+}
+
 // Gather item: an op with k-split S = 2^ls and n-vector V = 2^lv assigns S
 // consecutive lanes to a group of V outputs (row, m, n0 .. n0+V-1); lane
 // `sub` sums k = sub, sub + S, ... and the S lanes combine by butterfly
 // shuffles.  Ops with S > 1 start and end on wavefront boundaries (the
 // planner pads them, and segments start on multiples of 64), so every lane
 // of such a wave runs the same shuffles.
-template <int PREC>
-__global__ void __launch_bounds__(256) k_level(LevelArgs a) {
-  if (blockIdx.x < a.gemm_blocks) {
-    if constexpr (PREC == TC_PREC_BF16X3) {
-      __shared__ SmemBF16 smem;
-      for (uint64_t tile = blockIdx.x; tile < a.gemm_tiles; tile += a.gemm_blocks) {
-        const LevelSeg& S =
-            a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
-        const uint64_t lt = tile - S.gemm_start;
-        const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
-        gemm_tile_bf16x3(op, lt, S.tab, S.arena, smem);
-      }
-    } else {
-      __shared__ SmemF32 smem;
-      for (uint64_t tile = blockIdx.x; tile < a.gemm_tiles; tile += a.gemm_blocks) {
-        const LevelSeg& S =
-            a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
-        const uint64_t lt = tile - S.gemm_start;
-        const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
-        gemm_tile_f32(op, lt, S.tab, S.arena, smem);
-      }
-    }
-    return;
-  }
+__global__ void __launch_bounds__(256) k_gather(LevelArgs a) {
   // each block takes one contiguous chunk (a multiple of 256 items, so
   // wavefronts never straddle its end); a thread finds its segment and op
-  // once and then only walks forward
-  const uint64_t nblk = gridDim.x - a.gemm_blocks;
+  // once (or reads it from the per-item table) and then only walks forward
+  const uint64_t nblk = gridDim.x;
   const uint64_t chunk = (((a.gc_work + nblk - 1) / nblk) + 255) & ~uint64_t(255);
-  const uint64_t begin = (uint64_t)(blockIdx.x - a.gemm_blocks) * chunk;
+  const uint64_t begin = (uint64_t)blockIdx.x * chunk;
   const uint64_t end = begin + chunk < a.gc_work ? begin + chunk : a.gc_work;
-  uint32_t si = 0xffffffffu, oi = 0;
+  uint32_t si = 0xffffffffu, oi = 0xffffffffu;
   for (uint64_t w = begin + threadIdx.x; w < end; w += blockDim.x) {
     if (si == 0xffffffffu) {
       si = find_seg(a, w, [](const LevelSeg& s) { return s.gc_start; });
-      oi = a.seg[si].n_gc ? find_item(a.seg[si].gc_ops, a.seg[si].n_gc, w - a.seg[si].gc_start)
-                          : 0u;
     } else {
       while (si + 1 < a.nseg && a.seg[si + 1].gc_start <= w) {
         ++si;
-        oi = 0;
+        oi = 0xffffffffu;
       }
-      const LevelSeg& s0 = a.seg[si];
-      while (oi + 1 < s0.n_gc && s0.gc_ops[oi + 1].work0 <= w - s0.gc_start) ++oi;
     }
     const LevelSeg& Sg = a.seg[si];
-    const uint32_t* __restrict__ tab = Sg.tab;
-    float2* __restrict__ arena = Sg.arena;
     const uint64_t ws = w - Sg.gc_start;
     const bool has = Sg.n_gc > 0;
+    if (has) {
+      if (Sg.item_op) {
+        oi = Sg.item_op[ws];
+      } else if (oi == 0xffffffffu) {
+        oi = find_item(Sg.gc_ops, Sg.n_gc, ws);
+      } else {
+        while (oi + 1 < Sg.n_gc && Sg.gc_ops[oi + 1].work0 <= ws) ++oi;
+      }
+    } else {
+      oi = 0;
+    }
+    const uint32_t* __restrict__ tab = Sg.tab;
+    float2* __restrict__ arena = Sg.arena;
     const DevOp& op = Sg.gc_ops[oi];
     const uint32_t ls = has ? (op.flags >> 4) & 7u : 0u;
     const uint32_t lv = has ? (op.flags >> 8) & 3u : 0u;
@@ -259,21 +336,12 @@ __global__ void __launch_bounds__(256) k_level(LevelArgs a) {
       uint32_t bn[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? tab[op.b_n + n0 + j] : 0u;
-      const uint32_t K = op.K;
-      if (V == 4) {
-        for (uint32_t k = sub; k < K; k += S) {
-          const float2 av = A[ak[k]];
-          const float2* __restrict__ bb = Bp + bk[k];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) cfma(acc[j], av, bb[bn[j]]);
-        }
-      } else {
-        for (uint32_t k = sub; k < K; k += S) {
-          const float2 av = A[ak[k]];
-          const float2* __restrict__ bb = Bp + bk[k];
-          for (uint32_t j = 0; j < V; ++j) cfma(acc[j], av, bb[bn[j]]);
-        }
-      }
+      if (V == 4)
+        gather_dot<4>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+      else if (V == 2)
+        gather_dot<2>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+      else
+        gather_dot<1>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
     }
     if (S > 1) {
       // V == 1 whenever S > 1
@@ -284,8 +352,9 @@ __global__ void __launch_bounds__(256) k_level(LevelArgs a) {
     }
     if (valid && sub == 0) {
       const uint64_t cb = op.c + r * op.c_bs + tab[op.c_m + m];
-      for (uint32_t j = 0; j < V; ++j)
-        arena[cb + tab[op.c_n + n0 + j]] = make_float2(acc[j].re, acc[j].im);
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)
+        if (j < V) arena[cb + tab[op.c_n + n0 + j]] = make_float2(acc[j].re, acc[j].im);
     }
   }
 }
@@ -368,7 +437,7 @@ int device_cu_count(int device) {
 }
 
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
-                     int precision) {
+                     int precision, const Fork* fork, int parts) {
   if (nseg <= 0) return;
   if (nseg > MAX_SEG) fail(TC_ERR_INVALID_ARG, "internal: too many segments");
   switch (kind) {
@@ -380,6 +449,9 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         const WorkspaceLayout& L = *s.lay;
         LeafSeg& g = a.seg[i];
         g.leaves = (const DevLeaf*)(s.ws + L.leaves);
+        g.item_leaf = s.launch->item_begin != NO_ITEMS
+                          ? (const uint32_t*)(s.ws + L.item_op) + s.launch->item_begin
+                          : nullptr;
         g.ftab = (const float*)(s.ws + L.ftab);
         g.params = (const float*)(s.ws + L.params);
         g.arena = (float2*)(s.ws + L.arena);
@@ -396,7 +468,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
     }
     case L_LEVEL: {
       LevelArgs a{};
-      uint64_t tiles = 0, work = 0;
+      uint64_t tiles = 0, wtiles = 0, work = 0;
       for (int i = 0; i < nseg; ++i) {
         const SegRef& s = segs[i];
         const WorkspaceLayout& L = *s.lay;
@@ -404,26 +476,48 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         LevelSeg& g = a.seg[i];
         g.gemm_ops = ops + s.launch->gbegin;
         g.n_gemm = s.launch->gend - s.launch->gbegin;
+        g.wave_ops = ops + s.launch->wbegin;
+        g.n_wave = s.launch->wend - s.launch->wbegin;
         g.gc_ops = ops + s.launch->begin;
         g.n_gc = s.launch->end - s.launch->begin;
         g.tab = (const uint32_t*)(s.ws + L.tabs);
+        g.item_op = s.launch->item_begin != NO_ITEMS
+                        ? (const uint32_t*)(s.ws + L.item_op) + s.launch->item_begin
+                        : nullptr;
         g.arena = (float2*)(s.ws + L.arena);
         g.gemm_start = tiles;
+        g.wave_start = wtiles;
         g.gc_start = work;
         tiles += s.launch->tiles;
+        wtiles += s.launch->wtiles;
         work += (s.launch->work + 63) & ~uint64_t(63);
       }
       a.nseg = (uint32_t)nseg;
       a.gemm_tiles = tiles;
+      a.wave_tiles = wtiles;
       a.gc_work = work;
-      a.gemm_blocks = (uint32_t)std::min<uint64_t>(tiles, (uint64_t)n_cu * 8);
-      const unsigned gcb = work ? grid_for(work, 256, n_cu) : 0u;
-      const unsigned grid = a.gemm_blocks + gcb;
-      if (grid == 0) return;
-      if (precision == TC_PREC_BF16X3)
-        hipLaunchKernelGGL(k_level<TC_PREC_BF16X3>, dim3(grid), dim3(256), 0, stream, a);
-      else
-        hipLaunchKernelGGL(k_level<TC_PREC_C64>, dim3(grid), dim3(256), 0, stream, a);
+      a.tile_blocks = (unsigned)std::min<uint64_t>(tiles, (uint64_t)n_cu * 8);
+      const unsigned wvb = (unsigned)std::min<uint64_t>((wtiles + 3) / 4, (uint64_t)n_cu * 16);
+      const unsigned gmb = (parts & PART_GEMM) ? a.tile_blocks + wvb : 0u;
+      const unsigned gcb = (parts & PART_GATHER) && work ? grid_for(work, 256, n_cu) : 0u;
+      auto gemm = [&](hipStream_t st) {
+        if (precision == TC_PREC_BF16X3)
+          hipLaunchKernelGGL(k_gemm<TC_PREC_BF16X3>, dim3(gmb), dim3(256), 0, st, a);
+        else
+          hipLaunchKernelGGL(k_gemm<TC_PREC_C64>, dim3(gmb), dim3(256), 0, st, a);
+      };
+      if (gmb && gcb && fork) {
+        // GEMM tiles on the side stream, concurrent with the gather kernel
+        HIP_CHECK(hipEventRecord(fork->start, stream));
+        HIP_CHECK(hipStreamWaitEvent(fork->side, fork->start, 0));
+        gemm(fork->side);
+        hipLaunchKernelGGL(k_gather, dim3(gcb), dim3(256), 0, stream, a);
+        HIP_CHECK(hipEventRecord(fork->done, fork->side));
+        HIP_CHECK(hipStreamWaitEvent(stream, fork->done, 0));
+      } else {
+        if (gmb) gemm(stream);
+        if (gcb) hipLaunchKernelGGL(k_gather, dim3(gcb), dim3(256), 0, stream, a);
+      }
       break;
     }
     case L_ROOT: {
@@ -476,10 +570,12 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
   HIP_CHECK(hipGetLastError());
 }
 
-static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& seq) {
+static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& seq,
+                    int parts = PART_GEMM | PART_GATHER) {
+  const Fork fork{D.side, D.fork_start, D.fork_done};
   for (const Launch& x : seq) {
     SegRef s{&P, D.ws, &D.lay, &x};
-    launch_segments(x.kind, &s, 1, D.stream, D.n_cu, P.precision);
+    launch_segments(x.kind, &s, 1, D.stream, D.n_cu, P.precision, &fork, parts);
   }
 }
 
@@ -493,6 +589,7 @@ static void upload(char* ws, uint64_t off, const std::vector<T>& v, hipStream_t 
 void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStream_t stream) {
   upload(ws, lay.ops, P.ops, stream);
   upload(ws, lay.tabs, P.tabs, stream);
+  upload(ws, lay.item_op, P.item_op, stream);
   upload(ws, lay.leaves, P.leaves, stream);
   upload(ws, lay.ftab, P.ftab, stream);
   upload(ws, lay.uses, P.uses, stream);
@@ -512,7 +609,11 @@ static void release(DeviceState* D) {
     if (D->exec[i]) (void)hipGraphExecDestroy(D->exec[i]);
     if (D->graph[i]) (void)hipGraphDestroy(D->graph[i]);
   }
+  if (D->side) (void)hipStreamSynchronize(D->side);
   if (D->ws_owned && D->ws) (void)hipFree(D->ws);
+  if (D->fork_start) (void)hipEventDestroy(D->fork_start);
+  if (D->fork_done) (void)hipEventDestroy(D->fork_done);
+  if (D->side) (void)hipStreamDestroy(D->side);
   if (D->own_stream && D->stream) (void)hipStreamDestroy(D->stream);
   delete D;
 }
@@ -546,6 +647,9 @@ void bind_plan(Plan& P, void* workspace, uint64_t bytes) {
       HIP_CHECK(hipStreamCreateWithFlags(&D->stream, hipStreamNonBlocking));
       D->own_stream = true;
     }
+    HIP_CHECK(hipStreamCreateWithFlags(&D->side, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&D->fork_start, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&D->fork_done, hipEventDisableTiming));
     D->lay = workspace_layout(P);
     if (workspace) {
       if (bytes < D->lay.total)
@@ -628,8 +732,24 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
   BusyGuard g(P.busy);
   stage_params(P, params);
   DeviceState& D = *P.dev;
-  std::vector<Launch> seq = P.fwd;
-  if (which == 1) seq.insert(seq.end(), P.bwd.begin(), P.bwd.end());
+  std::vector<Launch> all = P.fwd;
+  if (which == 1) all.insert(all.end(), P.bwd.begin(), P.bwd.end());
+  // one entry per kernel: a level contributes its GEMM and gather kernels
+  struct Entry {
+    Launch L;
+    int kind, parts;
+    double flops, bytes;
+  };
+  std::vector<Entry> seq;
+  for (const Launch& L : all) {
+    if (L.kind != L_LEVEL) {
+      seq.push_back({L, L.kind, PART_GEMM | PART_GATHER, L.flops, L.bytes});
+      continue;
+    }
+    if (L.tiles || L.wtiles) seq.push_back({L, PROF_GEMM, PART_GEMM, L.gemm_flops, L.gemm_bytes});
+    if (L.work)
+      seq.push_back({L, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops, L.bytes - L.gemm_bytes});
+  }
   std::vector<hipEvent_t> ev(seq.size() + 1, nullptr);
   std::vector<double> acc(seq.size(), 0.0);
   try {
@@ -637,7 +757,7 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
     for (int r = 0; r < reps; ++r) {
       HIP_CHECK(hipEventRecord(ev[0], D.stream));
       for (size_t i = 0; i < seq.size(); ++i) {
-        enqueue(P, D, std::vector<Launch>{seq[i]});
+        enqueue(P, D, std::vector<Launch>{seq[i].L}, seq[i].parts);
         HIP_CHECK(hipEventRecord(ev[i + 1], D.stream));
       }
       HIP_CHECK(hipStreamSynchronize(D.stream));
@@ -693,7 +813,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
                          const tc_plan_opts* opts, tc_plan** out) {
   TC_GUARD_BEGIN
   if (!net || !path || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
-  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0};
+  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0, 0};
   if (opts) o = *opts;
   if (o.gemm_min_k < 0) tcx::fail(TC_ERR_INVALID_ARG, "gemm_min_k must be >= 0");
   if (o.checkpoint_every < -1 || o.checkpoint_every == 1)
@@ -709,6 +829,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
   p->p.budget = o.mem_budget_bytes;
   p->p.user_stream = o.stream;
   if (o.gemm_min_k > 0) p->p.gemm_min_k = o.gemm_min_k;
+  if (o.gemm_min_macs > 0) p->p.gemm_min_macs = o.gemm_min_macs;
   p->p.checkpoint = o.checkpoint_every;
   try {
     tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));

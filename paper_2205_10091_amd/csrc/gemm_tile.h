@@ -167,6 +167,96 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
   }
 }
 
+// ------------------------------------------------------------------ wave tiles
+
+// One (16 BI) x (16 BJ) block of C for one batch row, computed by a single
+// wavefront with FP32 MFMA straight from the arena: the operands are read
+// in the matrix cores' register layout (lane l holds A[m0 + l % 16][k + l / 16]
+// and B[k + l / 16][n0 + l % 16]), so there is no LDS staging and no
+// barrier.  This is the form for nodes too narrow for 64 x 64 tiles (M or
+// N below 64, as in per-row batched contractions), where a block tile
+// would mostly multiply padding.  K is a power of two >= 4.
+template <int BI, int BJ>
+__device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
+                                              const uint32_t* __restrict__ tab,
+                                              float2* __restrict__ arena, int lane) {
+  uint64_t l = unit - op.work0;
+  const uint32_t tn = (uint32_t)(l % op.tiles_n);
+  l /= op.tiles_n;
+  const uint32_t tm = (uint32_t)(l % op.tiles_m);
+  const uint64_t r = l / op.tiles_m;
+  const float2* __restrict__ A = arena + op.a + r * op.a_bs;
+  const float2* __restrict__ B = arena + op.b + r * op.b_bs;
+  const uint32_t m0 = tm * 16 * BI, n0 = tn * 16 * BJ;
+  const int i = lane & 15, kq = lane >> 4;
+  uint32_t am[BI], bn[BJ];
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi) am[bi] = tab[op.a_m + m0 + bi * 16 + i];
+#pragma unroll
+  for (int bj = 0; bj < BJ; ++bj) bn[bj] = tab[op.b_n + n0 + bj * 16 + i];
+  f4 cr[BI][BJ], ci[BI][BJ];
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+      cr[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+      ci[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  auto step = [&](const float2 (&av)[BI], const float2 (&bv)[BJ]) {
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) {
+        cr[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi].x, bv[bj].x, cr[bi][bj], 0, 0, 0);
+        cr[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi].y, -bv[bj].y, cr[bi][bj], 0, 0, 0);
+        ci[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi].x, bv[bj].y, ci[bi][bj], 0, 0, 0);
+        ci[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi].y, bv[bj].x, ci[bi][bj], 0, 0, 0);
+      }
+  };
+  const uint32_t steps = op.K >> 2;
+  uint32_t s = 0;
+  // U k-steps issued together: their table and operand loads overlap
+  constexpr int U = 4;
+  for (; s + U <= steps; s += U) {
+    uint32_t ka[U], kb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ka[u] = tab[op.a_k + 4 * (s + u) + kq];
+      kb[u] = tab[op.b_k + 4 * (s + u) + kq];
+    }
+    float2 av[U][BI], bv[U][BJ];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int bi = 0; bi < BI; ++bi) av[u][bi] = A[am[bi] + ka[u]];
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = B[kb[u] + bn[bj]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) step(av[u], bv[u]);
+  }
+  for (; s < steps; ++s) {
+    const uint32_t ka = tab[op.a_k + 4 * s + kq], kb = tab[op.b_k + 4 * s + kq];
+    float2 av[BI], bv[BJ];
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi) av[bi] = A[am[bi] + ka];
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) bv[bj] = B[kb + bn[bj]];
+    step(av, bv);
+  }
+  const uint64_t cb = op.c + r * op.c_bs;
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t cm = tab[op.c_m + m0 + bi * 16 + 4 * kq + v];
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj)
+        arena[cb + cm + tab[op.c_n + n0 + bj * 16 + i]] =
+            make_float2(cr[bi][bj][v], ci[bi][bj][v]);
+    }
+}
+
 // ------------------------------------------------------------------ BF16X3
 
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {

@@ -377,6 +377,7 @@ WorkspaceLayout workspace_layout(const Plan& p) {
   uint64_t o = 0;
   w.ops = o; o = al(o + p.ops.size() * sizeof(DevOp));
   w.tabs = o; o = al(o + p.tabs.size() * sizeof(uint32_t));
+  w.item_op = o; o = al(o + p.item_op.size() * sizeof(uint32_t));
   w.leaves = o; o = al(o + p.leaves.size() * sizeof(DevLeaf));
   w.ftab = o; o = al(o + p.ftab.size() * sizeof(float));
   w.uses = o; o = al(o + p.uses.size() * sizeof(DevGradUse));
@@ -457,8 +458,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   while (i < pend.size()) {
     size_t j = i;
     while (j < pend.size() && pend[j].step == pend[i].step) ++j;
-    std::vector<DevOp> gc, gm;
-    double lf = 0, lb = 0;
+    std::vector<DevOp> gc, gm, wv;
+    double lf = 0, lb = 0, gf = 0, gb = 0;
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
       const PT& Bt = T[pend[k].b];
@@ -506,14 +507,31 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       }
       lf += f;
       lb += by;
+      const bool to_gemm = op.K >= (uint32_t)plan.gemm_min_k && op.M >= (uint32_t)plan.gemm_min_mn &&
+                           op.N >= (uint32_t)plan.gemm_min_mn &&
+                           (uint64_t)op.rows * op.M * op.N * op.K >= plan.gemm_min_macs;
+      if (to_gemm) {
+        gf += f;
+        gb += by;
+      }
       // k-contiguity of the operands picks the GEMM's load pattern
       if (op.K > 1 && plan.tabs[op.a_k + 1] == 1) op.flags |= 1u;
       if (op.K > 1 && plan.tabs[op.b_k + 1] == 1) op.flags |= 2u;
-      if (op.K >= (uint32_t)plan.gemm_min_k && op.M >= (uint32_t)plan.gemm_min_mn &&
-          op.N >= (uint32_t)plan.gemm_min_mn) {
+      const bool block_tile = op.M >= (uint32_t)plan.block_tile_min_mn &&
+                              op.N >= (uint32_t)plan.block_tile_min_mn &&
+                              op.K >= (uint32_t)plan.block_tile_min_k;
+      if (to_gemm && block_tile) {
         op.tiles_m = (op.M + 63) / 64;
         op.tiles_n = (op.N + 63) / 64;
         gm.push_back(op);
+        if (!pend[k].bwd) ++n_gemm_nodes;
+      } else if (to_gemm && op.K >= 4) {
+        // one wavefront per (16 BI) x (16 BJ) block of one row
+        const uint32_t bi = op.M >= 32 ? 2 : 1, bj = op.N >= 32 ? 2 : 1;
+        op.tiles_m = op.M / (16 * bi);
+        op.tiles_n = op.N / (16 * bj);
+        op.flags |= ((bi - 1) << 12) | ((bj - 1) << 13);
+        wv.push_back(op);
         if (!pend[k].bwd) ++n_gemm_nodes;
       } else {
         // gather: split long sums over up to 64 lanes while the op is small,
@@ -532,6 +550,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.kind = L_LEVEL;
     L.flops = lf;
     L.bytes = lb;
+    L.gemm_flops = gf;
+    L.gemm_bytes = gb;
     L.gbegin = (uint32_t)plan.ops.size();
     uint64_t tiles = 0;
     for (DevOp& op : gm) {
@@ -541,6 +561,15 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     L.gend = (uint32_t)plan.ops.size();
     L.tiles = tiles;
+    L.wbegin = (uint32_t)plan.ops.size();
+    uint64_t wtiles = 0;
+    for (DevOp& op : wv) {
+      op.work0 = wtiles;
+      wtiles += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+      plan.ops.push_back(op);
+    }
+    L.wend = (uint32_t)plan.ops.size();
+    L.wtiles = wtiles;
     L.begin = (uint32_t)plan.ops.size();
     uint64_t w = 0;
     for (DevOp& op : gc) {
@@ -556,6 +585,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     L.end = (uint32_t)plan.ops.size();
     L.work = (w + 63) & ~uint64_t(63);
+    if (L.end > L.begin && L.work <= ITEM_TABLE_MAX) {
+      // item -> op (relative to L.begin); pad items map to the op before them
+      L.item_begin = plan.item_op.size();
+      plan.item_op.resize(plan.item_op.size() + L.work);
+      uint32_t* it = plan.item_op.data() + L.item_begin;
+      for (uint32_t o = L.begin; o < L.end; ++o) {
+        const uint64_t lo = plan.ops[o].work0;
+        const uint64_t hi = o + 1 < L.end ? plan.ops[o + 1].work0 : L.work;
+        for (uint64_t x = lo; x < hi; ++x) it[x] = o - L.begin;
+      }
+    }
     (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
     i = j;
   }
@@ -601,6 +641,14 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   }
   plan.leaf_work = lw;
   plan.fwd[0].work = lw;
+  if (lw > 0 && lw <= ITEM_TABLE_MAX) {  // leaf entry -> leaf index
+    plan.fwd[0].item_begin = plan.item_op.size();
+    plan.item_op.reserve(plan.item_op.size() + lw);
+    for (uint32_t i = 0; i < (uint32_t)plan.leaves.size(); ++i) {
+      const DevLeaf& d = plan.leaves[i];
+      plan.item_op.insert(plan.item_op.end(), (uint64_t)d.rows << d.rank, i);
+    }
+  }
   plan.fwd[0].bytes = 8.0 * (double)lw;  // every leaf entry written once
 
   // ---- roots
@@ -687,6 +735,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     for (const DevRoot& r : plan.roots)
       if (r.present && r.val + (uint64_t)(B - 1) * r.bs >= AE)
         fail(TC_ERR_INVALID_ARG, "internal: root out of range");
+    // per-item tables: one entry per work item, naming an item of the launch
+    for (const auto* seq : {&plan.fwd, &plan.bwd})
+      for (const Launch& L : *seq) {
+        if (L.item_begin == NO_ITEMS) continue;
+        const uint64_t n_items = L.kind == L_LEAF ? plan.leaves.size() : L.end - L.begin;
+        if (L.item_begin + L.work > plan.item_op.size())
+          fail(TC_ERR_INVALID_ARG, "internal: item table out of range");
+        for (uint64_t x = 0; x < L.work; ++x)
+          if (plan.item_op[L.item_begin + x] >= n_items)
+            fail(TC_ERR_INVALID_ARG, "internal: item table names a missing op");
+      }
   }
 
   // ---- info

@@ -16,15 +16,26 @@ enum LaunchKind : int32_t {
   L_ROOT = 4,   // FP64 weighted sum of the term roots
   L_GRAD = 5    // FP64 leaf-gradient reduction
 };
+// kernel kinds reported by profiling: a level's two kernels
+constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3;
+
+constexpr uint64_t NO_ITEMS = ~uint64_t(0);
+// levels with at most this many gather items get a per-item op index table
+constexpr uint64_t ITEM_TABLE_MAX = uint64_t(1) << 18;
 
 struct Launch {
   int32_t kind;
   uint32_t begin = 0, end = 0;    // gather ops in Plan::ops
   uint64_t work = 0;              // gather work items / leaf, root, grad items
-  uint32_t gbegin = 0, gend = 0;  // GEMM ops in Plan::ops
-  uint64_t tiles = 0;             // GEMM tiles
+  uint32_t gbegin = 0, gend = 0;  // GEMM ops in 64 x 64 tiles, in Plan::ops
+  uint64_t tiles = 0;             // 64 x 64 GEMM tiles
+  uint32_t wbegin = 0, wend = 0;  // GEMM ops in wave tiles, in Plan::ops
+  uint64_t wtiles = 0;            // wave tiles
+  uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
   double flops = 0;               // algorithmic flops (8 per complex MAC)
   double bytes = 0;               // algorithmic bytes: operands read + results written
+  double gemm_flops = 0;          // the part of flops / bytes in GEMM tiles
+  double gemm_bytes = 0;
 };
 
 struct DeviceState;  // defined by the executor
@@ -35,8 +46,14 @@ struct Plan {
   uint64_t budget = 0;
   void* user_stream = nullptr;
   int32_t n_params = 0, n_terms = 0;
-  // nodes with K >= gemm_min_k and M, N >= gemm_min_mn go to the MFMA GEMM
+  // nodes with K >= gemm_min_k, M, N >= gemm_min_mn and at least
+  // gemm_min_macs complex multiply-adds (over their batch rows) go to the
+  // MFMA GEMM; smaller ones finish sooner on the gather path
   int32_t gemm_min_k = 8, gemm_min_mn = 16;
+  uint64_t gemm_min_macs = uint64_t(1) << 20;
+  // GEMM nodes with M, N >= 64 and K >= 16 use 64 x 64 LDS tiles; the
+  // narrower ones run as one-wavefront MFMA tiles
+  int32_t block_tile_min_mn = 64, block_tile_min_k = 16;
   // checkpoint segment length: 0 = only when the budget requires it,
   // >= 2 = always with that length, -1 = never
   int32_t checkpoint = 0;
@@ -45,6 +62,7 @@ struct Plan {
   // tables uploaded once
   std::vector<DevOp> ops;
   std::vector<uint32_t> tabs;
+  std::vector<uint32_t> item_op;      // gather item -> op index, per small level
   std::vector<DevLeaf> leaves;
   std::vector<float> ftab;
   std::vector<DevGradUse> uses;       // sorted by slot
@@ -69,7 +87,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path);
 
 // Byte layout of the workspace: [tables][params][values][grad][arena]
 struct WorkspaceLayout {
-  uint64_t ops, tabs, leaves, ftab, uses, slot_begin, roots;
+  uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots;
   uint64_t params, value, grad, arena, total;
 };
 WorkspaceLayout workspace_layout(const Plan& p);

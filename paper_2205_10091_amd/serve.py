@@ -96,10 +96,13 @@ class ServeReport:
                 "p99_ms": float(np.percentile(lat, 99) * 1e3) if n else None}
 
 
-def run(server: Server, requests, realtime: bool = True, poll_sleep: float = 0.0) -> ServeReport:
+def run(server: Server, requests, realtime: bool = True, poll_sleep: float = 0.0,
+        progress=None, progress_every_s: float = 10.0) -> ServeReport:
     """Submit `requests` (objects with circuit, observable, params,
     want_grad, arrival_s) at their arrival times (realtime) or all at once,
-    and step the engine until every accepted request finished."""
+    and step the engine until every accepted request finished.  If given,
+    `progress(elapsed_s, n_done, n_rejected, n_pending)` is called about
+    every `progress_every_s` seconds."""
     rep = ServeReport()
     ids: Dict[int, int] = {}
     lock = threading.Lock()
@@ -130,6 +133,7 @@ def run(server: Server, requests, realtime: bool = True, poll_sleep: float = 0.0
             done_submitting.set()
 
     t0 = time.perf_counter()
+    last_report = t0
     th = threading.Thread(target=submitter, daemon=True)
     th.start()
     while True:
@@ -148,6 +152,10 @@ def run(server: Server, requests, realtime: bool = True, poll_sleep: float = 0.0
             with lock:
                 if not ids:
                     break
+        if progress is not None and time.perf_counter() - last_report >= progress_every_s:
+            last_report = time.perf_counter()
+            with lock:
+                progress(last_report - t0, len(rep.results), len(rep.rejected), len(ids))
         if poll_sleep:
             time.sleep(poll_sleep)
     th.join()

@@ -224,7 +224,8 @@ def test_gemm_path_matches_gather_path():
     """Same trees, once with wide nodes on the MFMA GEMM and once with every
     node on the gather kernels; both against the oracle."""
     circ, p, obs = tcgen.workload_vqe_chain()
-    gm = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1, gemm_min_k=4)
+    gm = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1, gemm_min_k=4,
+                     gemm_min_macs=1)
     gc = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1, gemm_min_k=1 << 30)
     assert gm.info().n_gemm_nodes > 0 and gc.info().n_gemm_nodes == 0
     e1, g1 = gm.contract_grad(device_params(p))
@@ -236,7 +237,7 @@ def test_gemm_path_matches_gather_path():
     # batched rows through the GEMM tiles
     B = 16
     circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=14, layers=5)
-    gm = api.compile(circ, obs, batch=B, want_grad=True, gemm_min_k=4)
+    gm = api.compile(circ, obs, batch=B, want_grad=True, gemm_min_k=4, gemm_min_macs=1)
     e, g = gm.contract_grad(device_params(P, B))
     for b in (0, 9):
         e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
@@ -251,7 +252,8 @@ def test_grid_gemm_nodes_fp32_and_bf16x3():
     ref = sv.amplitude(circ, p)
     # one greedy trial leaves wide nodes in the tree
     for prec, tol in ((0, TOL_C64), (1, TOL_BF16X3)):
-        plan = api.compile(circ, amp, n_trials=1, precision=prec, gemm_min_k=4)
+        plan = api.compile(circ, amp, n_trials=1, precision=prec, gemm_min_k=4,
+                           gemm_min_macs=1)
         assert plan.info().n_gemm_nodes > 0
         a = plan.contract(device_params(p))[0]
         assert rel_err(a, ref, 2 ** (-n / 2)) < tol, prec
