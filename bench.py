@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
-KIND_NAMES = {0: "k_leaf", 2: "k_gemm", 3: "k_gather", 4: "k_root", 5: "k_grad"}
+KIND_NAMES = {0: "k_leaf", 2: "k_gemm", 3: "k_gather", 4: "k_root", 5: "k_grad", 6: "k_term"}
 KERNEL_SOURCES = ["paper_2205_10091_amd/csrc/exec.hip", "paper_2205_10091_amd/csrc/gemm_tile.h",
                   "paper_2205_10091_amd/csrc/gates.h", "paper_2205_10091_amd/csrc/ops.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")

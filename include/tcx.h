@@ -257,6 +257,18 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *               multiply-adds (M N K times its batch rows) to go to the GEMM:
  *               below it the gather kernels finish sooner; 0 = default
  *               (2^20), 1 = no floor;
+ *   exec_mode   1 = level-synchronous: every tree level (of all terms) is a
+ *               GEMM kernel and a gather kernel; 2 = term mode: one
+ *               workgroup per term runs the term's leaves and all its levels
+ *               with workgroup barriers in between (one kernel for the
+ *               forward pass and one for the reverse sweep; every node on
+ *               the gather path; each term gets its own arena region);
+ *               0 = term mode when batch is 1 and no node qualifies for the
+ *               GEMM path, level-synchronous otherwise.
+ * GEMM nodes whose output tiles cannot fill the chip have K cut into
+ * slices (split-K): every slice writes a partial tile to the workspace and
+ * the last slice of a tile to arrive adds the slices in slice order, so
+ * results do not depend on the order in which slices finish.
  *   checkpoint_every  with want_grad: 0 = keep every intermediate for the
  *               reverse sweep unless mem_budget_bytes is exceeded, in which
  *               case the segment length with the smallest workspace is
@@ -279,6 +291,7 @@ typedef struct {
   int32_t gemm_min_k;
   int32_t checkpoint_every;
   uint64_t gemm_min_macs;
+  int32_t exec_mode;
 } tc_plan_opts;
 
 tc_status tc_plan_create(const tc_network* net, const tc_path* path,
@@ -303,6 +316,8 @@ typedef struct {
   int32_t n_params;
   int32_t n_terms;
   int32_t checkpoint_every;  /* segment length used, 0 = none            */
+  int32_t exec_mode;         /* 1 level launches, 2 term mode            */
+  int32_t n_split_nodes;     /* GEMM nodes whose K is cut into slices    */
 } tc_plan_info;
 
 tc_status tc_plan_info_get(const tc_plan* plan, tc_plan_info* out);
@@ -342,7 +357,8 @@ tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
  * *n_launches (at most `cap` are written) it reports the kernel class
  * kinds[i] (0 leaf materialisation, 2 MFMA GEMM tiles of one tree level,
  * 3 gather contractions of one tree level, 4 FP64 root sum, 5 FP64
- * gradient sum), the mean duration ms[i], and the kernel's algorithmic
+ * gradient sum, 6 term mode: all terms' trees, forward pass with the leaves
+ * or reverse sweep), the mean duration ms[i], and the kernel's algorithmic
  * flops[i] and bytes[i] (operands read once plus results written once).
  * which: 0 the forward sequence, 1 forward plus reverse sweep (needs
  * want_grad).  In contractions the two kernels of a level may overlap. */

@@ -64,6 +64,7 @@ struct LevelSeg {
   const uint32_t* tab;
   const uint32_t* item_op;  // gather item -> op index, or null (search)
   float2* arena;
+  SplitK split;             // split-K partial tiles and counters
   uint64_t gemm_start;  // first GEMM tile of this segment
   uint64_t wave_start;  // first wave tile of this segment
   uint64_t gc_start;    // first gather item (a multiple of 64)
@@ -92,6 +93,21 @@ struct RootArgs {
   RootSeg seg[MAX_SEG];
   uint32_t nseg;
   uint64_t total;  // wavefronts
+};
+
+struct TermArgs {
+  const DevTerm* terms;
+  const DevGroup* groups;
+  const DevOp* ops;
+  const uint32_t* tab;
+  const uint32_t* item_op;    // per-item op tables (groups hold their base)
+  const uint32_t* item_leaf;  // leaf entry -> leaf index, or null (search)
+  const DevLeaf* leaves;
+  const float* ftab;
+  const float* params;
+  float2* arena;
+  int32_t n_params;
+  int32_t phase;              // 0: leaves and forward groups, 1: reverse sweep
 };
 
 struct GradSeg {
@@ -183,6 +199,22 @@ __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restri
   }
 }
 
+// Leaf work item w (row-major over the leaf's rows and entries): one entry
+// of one leaf tensor for one batch row.
+__device__ __forceinline__ void leaf_item(const DevLeaf& L, uint64_t w,
+                                          const float* __restrict__ params, int32_t n_params,
+                                          const float* __restrict__ ftab,
+                                          float2* __restrict__ arena) {
+  const uint64_t l = w - L.work0;
+  const int e = (int)(l & ((1u << L.rank) - 1));
+  const uint64_t r = l >> L.rank;
+  const float* pr = params + r * (uint64_t)n_params;
+  const float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
+  const float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
+  const c32 v = leaf_entry(L, e, t0, t1, ftab);
+  arena[L.out + (r << L.rank) + e] = make_float2(v.re, v.im);
+}
+
 // Materialise every leaf tensor (gates, boundary vectors, Pauli matrices)
 // for every batch row from the parameter vectors.
 __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
@@ -208,15 +240,7 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
       li = find_item(S.leaves, S.n, ws);
     else
       while (li + 1 < S.n && S.leaves[li + 1].work0 <= ws) ++li;
-    const DevLeaf& L = S.leaves[li];
-    const uint64_t l = ws - L.work0;
-    const int e = (int)(l & ((1u << L.rank) - 1));
-    const uint64_t r = l >> L.rank;
-    const float* pr = S.params + r * (uint64_t)S.n_params;
-    const float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
-    const float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
-    const c32 v = leaf_entry(L, e, t0, t1, S.ftab);
-    S.arena[L.out + (r << L.rank) + e] = make_float2(v.re, v.im);
+    leaf_item(S.leaves[li], ws, S.params, S.n_params, S.ftab, S.arena);
   }
 }
 
@@ -226,7 +250,7 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
 // each keeps its own register budget (the GEMM tiles' accumulators would
 // otherwise cap the gather waves' occupancy).
 template <int PREC>
-__global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gemm(LevelArgs a) {
   if (blockIdx.x >= a.tile_blocks) {
     // wave tiles: one unit per wavefront, grid-stride over the units
     const int lane = threadIdx.x & 63;
@@ -238,10 +262,10 @@ __global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
       const uint64_t lu = u - S.wave_start;
       const DevOp& op = S.wave_ops[find_item(S.wave_ops, S.n_wave, lu)];
       switch ((op.flags >> 12) & 3u) {
-        case 0: wave_tile_f32<1, 1>(op, lu, S.tab, S.arena, lane); break;
-        case 1: wave_tile_f32<2, 1>(op, lu, S.tab, S.arena, lane); break;
-        case 2: wave_tile_f32<1, 2>(op, lu, S.tab, S.arena, lane); break;
-        default: wave_tile_f32<2, 2>(op, lu, S.tab, S.arena, lane); break;
+        case 0: wave_tile_f32<1, 1>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 1: wave_tile_f32<2, 1>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 2: wave_tile_f32<1, 2>(op, lu, S.tab, S.arena, lane, S.split); break;
+        default: wave_tile_f32<2, 2>(op, lu, S.tab, S.arena, lane, S.split); break;
       }
     }
     return;
@@ -253,7 +277,7 @@ __global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
           a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
       const uint64_t lt = tile - S.gemm_start;
       const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
-      gemm_tile_bf16x3(op, lt, S.tab, S.arena, smem);
+      gemm_tile_bf16x3(op, lt, S.tab, S.arena, smem, S.split);
     }
   } else {
     __shared__ SmemF32 smem;
@@ -262,7 +286,7 @@ __global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
           a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
       const uint64_t lt = tile - S.gemm_start;
       const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
-      gemm_tile_f32(op, lt, S.tab, S.arena, smem);
+      gemm_tile_f32(op, lt, S.tab, S.arena, smem, S.split);
     }
   }
 }
@@ -273,6 +297,61 @@ __global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
 // shuffles.  Ops with S > 1 start and end on wavefront boundaries (the
 // planner pads them, and segments start on multiples of 64), so every lane
 // of such a wave runs the same shuffles.
+// Gather item l of op (item layout above).  All lanes of a wavefront call
+// this together (the k-split combines across lanes); `has` = false makes
+// the call a no-op that still joins the shuffles.
+__device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool has,
+                                            const uint32_t* __restrict__ tab,
+                                            float2* __restrict__ arena) {
+  const uint32_t ls = has ? (op.flags >> 4) & 7u : 0u;
+  const uint32_t lv = has ? (op.flags >> 8) & 3u : 0u;
+  const uint32_t S = 1u << ls, V = 1u << lv;
+  bool valid = false;
+  uint64_t e = 0;
+  uint32_t sub = 0, ln = 0, lm = 0;
+  if (has) {
+    ln = __builtin_ctz(op.N) - lv;
+    lm = __builtin_ctz(op.M);
+    e = l >> ls;
+    sub = (uint32_t)(l & (S - 1));
+    valid = e < ((uint64_t)op.rows << (ln + lm));
+  }
+  c32 acc[4] = {cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f)};
+  uint32_t m = 0, n0 = 0;
+  uint64_t r = 0;
+  if (valid) {
+    n0 = (uint32_t)(e & ((1u << ln) - 1)) << lv;
+    m = (uint32_t)((e >> ln) & (op.M - 1));
+    r = e >> (ln + lm);
+    const float2* __restrict__ A = arena + op.a + r * op.a_bs + tab[op.a_m + m];
+    const float2* __restrict__ Bp = arena + op.b + r * op.b_bs;
+    const uint32_t* __restrict__ ak = tab + op.a_k;
+    const uint32_t* __restrict__ bk = tab + op.b_k;
+    uint32_t bn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? tab[op.b_n + n0 + j] : 0u;
+    if (V == 4)
+      gather_dot<4>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+    else if (V == 2)
+      gather_dot<2>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+    else
+      gather_dot<1>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+  }
+  if (S > 1) {
+    // V == 1 whenever S > 1
+    for (uint32_t off = S >> 1; off > 0; off >>= 1) {
+      acc[0].re += __shfl_xor(acc[0].re, (int)off, 64);
+      acc[0].im += __shfl_xor(acc[0].im, (int)off, 64);
+    }
+  }
+  if (valid && sub == 0) {
+    const uint64_t cb = op.c + r * op.c_bs + tab[op.c_m + m];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j < V) arena[cb + tab[op.c_n + n0 + j]] = make_float2(acc[j].re, acc[j].im);
+  }
+}
+
 __global__ void __launch_bounds__(256) k_gather(LevelArgs a) {
   // each block takes one contiguous chunk (a multiple of 256 items, so
   // wavefronts never straddle its end); a thread finds its segment and op
@@ -305,57 +384,59 @@ __global__ void __launch_bounds__(256) k_gather(LevelArgs a) {
     } else {
       oi = 0;
     }
-    const uint32_t* __restrict__ tab = Sg.tab;
-    float2* __restrict__ arena = Sg.arena;
     const DevOp& op = Sg.gc_ops[oi];
-    const uint32_t ls = has ? (op.flags >> 4) & 7u : 0u;
-    const uint32_t lv = has ? (op.flags >> 8) & 3u : 0u;
-    const uint32_t S = 1u << ls, V = 1u << lv;
-    bool valid = false;
-    uint64_t e = 0;
-    uint32_t sub = 0, ln = 0, lm = 0;
-    if (has) {
-      const uint64_t l = ws - op.work0;
-      ln = __builtin_ctz(op.N) - lv;
-      lm = __builtin_ctz(op.M);
-      e = l >> ls;
-      sub = (uint32_t)(l & (S - 1));
-      valid = e < ((uint64_t)op.rows << (ln + lm));
+    gather_item(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena);
+  }
+}
+
+// largest i in [lo, hi) with items[i].work0 <= w (items[lo].work0 <= w)
+template <typename T>
+__device__ __forceinline__ uint32_t find_in(const T* __restrict__ items, uint32_t lo, uint32_t hi,
+                                            uint64_t w) {
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (items[mid].work0 <= w)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Term mode: workgroup t runs term t alone, its leaves and then each of its
+// groups (its nodes at one step) with a workgroup barrier in between; the
+// terms' trees advance independently, each in its own arena region, so a
+// deep tree costs barriers instead of kernel launches.  Group items are
+// whole wavefronts (a multiple of 64) and the block strides over them in
+// steps of 1024, so the lanes of a wavefront always share one op.
+__global__ void __launch_bounds__(1024) k_term(TermArgs a) {
+  const DevTerm T = a.terms[blockIdx.x];
+  if (a.phase == 0) {
+    for (uint64_t w = T.leaf_work0 + threadIdx.x; w < T.leaf_work_end; w += blockDim.x) {
+      const uint32_t li =
+          a.item_leaf ? a.item_leaf[w] : find_in(a.leaves, T.leaf_begin, T.leaf_end, w);
+      leaf_item(a.leaves[li], w, a.params, a.n_params, a.ftab, a.arena);
     }
-    c32 acc[4] = {cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f)};
-    uint32_t m = 0, n0 = 0;
-    uint64_t r = 0;
-    if (valid) {
-      n0 = (uint32_t)(e & ((1u << ln) - 1)) << lv;
-      m = (uint32_t)((e >> ln) & (op.M - 1));
-      r = e >> (ln + lm);
-      const float2* __restrict__ A = arena + op.a + r * op.a_bs + tab[op.a_m + m];
-      const float2* __restrict__ Bp = arena + op.b + r * op.b_bs;
-      const uint32_t* __restrict__ ak = tab + op.a_k;
-      const uint32_t* __restrict__ bk = tab + op.b_k;
-      uint32_t bn[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? tab[op.b_n + n0 + j] : 0u;
-      if (V == 4)
-        gather_dot<4>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
-      else if (V == 2)
-        gather_dot<2>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+    __syncthreads();
+  }
+  const uint32_t g0 = a.phase == 0 ? T.fwd_begin : T.bwd_begin;
+  const uint32_t g1 = a.phase == 0 ? T.fwd_end : T.bwd_end;
+  for (uint32_t g = g0; g < g1; ++g) {
+    const DevGroup G = a.groups[g];
+    const DevOp* __restrict__ ops = a.ops + G.op_begin;
+    const uint32_t n = G.op_end - G.op_begin;
+    uint32_t oi = 0xffffffffu;
+    for (uint64_t w = threadIdx.x; w < G.items; w += blockDim.x) {
+      if (G.item_base != NO_ITEMS)
+        oi = a.item_op[G.item_base + w];
+      else if (oi == 0xffffffffu)
+        oi = find_item(ops, n, w);
       else
-        gather_dot<1>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+        while (oi + 1 < n && ops[oi + 1].work0 <= w) ++oi;
+      const DevOp& op = ops[oi];
+      gather_item(op, w - op.work0, true, a.tab, a.arena);
     }
-    if (S > 1) {
-      // V == 1 whenever S > 1
-      for (uint32_t off = S >> 1; off > 0; off >>= 1) {
-        acc[0].re += __shfl_xor(acc[0].re, (int)off, 64);
-        acc[0].im += __shfl_xor(acc[0].im, (int)off, 64);
-      }
-    }
-    if (valid && sub == 0) {
-      const uint64_t cb = op.c + r * op.c_bs + tab[op.c_m + m];
-#pragma unroll
-      for (uint32_t j = 0; j < 4; ++j)
-        if (j < V) arena[cb + tab[op.c_n + n0 + j]] = make_float2(acc[j].re, acc[j].im);
-    }
+    __syncthreads();
   }
 }
 
@@ -485,6 +566,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
                         ? (const uint32_t*)(s.ws + L.item_op) + s.launch->item_begin
                         : nullptr;
         g.arena = (float2*)(s.ws + L.arena);
+        g.split = SplitK{(float*)(s.ws + L.split), (uint32_t*)(s.ws + L.splitcnt)};
         g.gemm_start = tiles;
         g.wave_start = wtiles;
         g.gc_start = work;
@@ -518,6 +600,30 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         if (gmb) gemm(stream);
         if (gcb) hipLaunchKernelGGL(k_gather, dim3(gcb), dim3(256), 0, stream, a);
       }
+      break;
+    }
+    case L_TERM: {
+      if (nseg != 1) fail(TC_ERR_INVALID_ARG, "internal: term mode runs one plan per launch");
+      const SegRef& s = segs[0];
+      const WorkspaceLayout& L = *s.lay;
+      const Plan& P = *s.plan;
+      if (P.terms.empty()) return;
+      TermArgs a{};
+      a.terms = (const DevTerm*)(s.ws + L.terms);
+      a.groups = (const DevGroup*)(s.ws + L.groups);
+      a.ops = (const DevOp*)(s.ws + L.ops);
+      a.tab = (const uint32_t*)(s.ws + L.tabs);
+      a.item_op = (const uint32_t*)(s.ws + L.item_op);
+      a.item_leaf = s.launch->item_begin != NO_ITEMS
+                        ? (const uint32_t*)(s.ws + L.item_op) + s.launch->item_begin
+                        : nullptr;
+      a.leaves = (const DevLeaf*)(s.ws + L.leaves);
+      a.ftab = (const float*)(s.ws + L.ftab);
+      a.params = (const float*)(s.ws + L.params);
+      a.arena = (float2*)(s.ws + L.arena);
+      a.n_params = P.n_params;
+      a.phase = s.launch->phase;
+      hipLaunchKernelGGL(k_term, dim3((unsigned)P.terms.size()), dim3(1024), 0, stream, a);
       break;
     }
     case L_ROOT: {
@@ -595,6 +701,12 @@ void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStrea
   upload(ws, lay.uses, P.uses, stream);
   upload(ws, lay.slot_begin, P.slot_begin, stream);
   upload(ws, lay.roots, P.roots, stream);
+  upload(ws, lay.terms, P.terms, stream);
+  upload(ws, lay.groups, P.groups, stream);
+  // split-K arrival counters start at zero; each tile's last slice resets
+  // its counter, so they are zero again after every launch
+  if (P.split_counters)
+    HIP_CHECK(hipMemsetAsync(ws + lay.splitcnt, 0, P.split_counters * sizeof(uint32_t), stream));
   upload(ws, lay.arena, P.seeds, stream);  // seeds sit at arena offset 0
 }
 
@@ -813,9 +925,10 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
                          const tc_plan_opts* opts, tc_plan** out) {
   TC_GUARD_BEGIN
   if (!net || !path || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
-  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0, 0};
+  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.gemm_min_k < 0) tcx::fail(TC_ERR_INVALID_ARG, "gemm_min_k must be >= 0");
+  if (o.exec_mode < 0 || o.exec_mode > 2) tcx::fail(TC_ERR_INVALID_ARG, "exec_mode must be 0, 1 or 2");
   if (o.checkpoint_every < -1 || o.checkpoint_every == 1)
     tcx::fail(TC_ERR_INVALID_ARG, "checkpoint_every must be -1, 0 or >= 2");
   if (o.batch < 1 || o.batch > (1 << 20)) tcx::fail(TC_ERR_INVALID_ARG, "batch must be in 1..2^20");
@@ -830,6 +943,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
   p->p.user_stream = o.stream;
   if (o.gemm_min_k > 0) p->p.gemm_min_k = o.gemm_min_k;
   if (o.gemm_min_macs > 0) p->p.gemm_min_macs = o.gemm_min_macs;
+  p->p.exec_mode = o.exec_mode;
   p->p.checkpoint = o.checkpoint_every;
   try {
     tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));

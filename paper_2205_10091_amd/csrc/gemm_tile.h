@@ -36,22 +36,96 @@ struct TileCtx {
   const float2* B;
   uint64_t cbase;
   uint32_t m0, n0;
+  uint32_t kb, ke;   // this unit's K slice
+  uint32_t slice;    // p of ksplit
+  uint64_t tile;     // output tile index within the op (row-major over rows, m, n)
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const DevOp& op, uint64_t tile,
-                                            const float2* arena) {
-  uint64_t l = tile - op.work0;
+// Unit u of op (relative to op.work0): slice p fastest, then the tile grid
+// (n fastest, then m, then batch row); tile edges tm x tn in elements.
+__device__ __forceinline__ TileCtx unit_ctx(const DevOp& op, uint64_t u, const float2* arena,
+                                            uint32_t tm_size, uint32_t tn_size) {
+  const uint32_t P = op.ksplit;
+  TileCtx t;
+  t.slice = (uint32_t)(u % P);
+  uint64_t l = u / P;
+  t.tile = l;
   const uint32_t tn = (uint32_t)(l % op.tiles_n);
   l /= op.tiles_n;
   const uint32_t tm = (uint32_t)(l % op.tiles_m);
   const uint64_t r = l / op.tiles_m;
-  TileCtx t;
   t.A = arena + op.a + r * op.a_bs;
   t.B = arena + op.b + r * op.b_bs;
   t.cbase = op.c + r * op.c_bs;
-  t.m0 = tm * BM;
-  t.n0 = tn * BN;
+  t.m0 = tm * tm_size;
+  t.n0 = tn * tn_size;
+  const uint32_t ks = op.K / P;
+  t.kb = t.slice * ks;
+  t.ke = t.kb + ks;
   return t;
+}
+
+__device__ __forceinline__ TileCtx tile_ctx(const DevOp& op, uint64_t tile,
+                                            const float2* arena) {
+  return unit_ctx(op, tile - op.work0, arena, BM, BN);
+}
+
+// Split-K scratch of one launch: partial tiles and per-tile arrival counters.
+struct SplitK {
+  float* part;
+  uint32_t* cnt;
+};
+
+// Split-K epilogue of a 64 x 64 block tile (all 256 threads): the slice's
+// accumulators go to its partial tile (element j of thread t at j * 256 + t,
+// so every store is coalesced); the last slice of the tile to arrive adds
+// all slices in slice order (a fixed order: the result does not depend on
+// which slice came last), leaves the sum in cr / ci, resets the counter and
+// returns true.
+__device__ __forceinline__ bool split_block(const DevOp& op, const TileCtx& c, const SplitK& sk,
+                                            f4 (&cr)[2][2], f4 (&ci)[2][2], uint32_t& flag) {
+  const int t = threadIdx.x;
+  const uint32_t P = op.ksplit;
+  float* tile_part = sk.part + op.part + c.tile * P * (32 * 256);
+  float* mine = tile_part + (uint64_t)c.slice * (32 * 256);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        mine[((i * 2 + j) * 8 + v) * 256 + t] = cr[i][j][v];
+        mine[((i * 2 + j) * 8 + 4 + v) * 256 + t] = ci[i][j][v];
+      }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) flag = atomicAdd(sk.cnt + op.cnt + c.tile, 1u) == P - 1 ? 1u : 0u;
+  __syncthreads();
+  const bool last = flag != 0;
+  __syncthreads();  // every thread has read the flag before it is reused
+  if (!last) return false;
+  __threadfence();
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (uint32_t q = 0; q < P; ++q) {
+    const float* src = tile_part + (uint64_t)q * (32 * 256);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cr[i][j][v] += src[((i * 2 + j) * 8 + v) * 256 + t];
+          ci[i][j][v] += src[((i * 2 + j) * 8 + 4 + v) * 256 + t];
+        }
+  }
+  if (t == 0) sk.cnt[op.cnt + c.tile] = 0;
+  return true;
 }
 
 __device__ __forceinline__ void store_tile(const DevOp& op, const TileCtx& t,
@@ -77,12 +151,15 @@ __device__ __forceinline__ void store_tile(const DevOp& op, const TileCtx& t,
 struct SmemF32 {
   float A[2][BK32][BM + PAD];  // [re/im][k][m]
   float B[2][BK32][BN + PAD];  // [re/im][k][n]
+  uint32_t flag;               // split-K: this block holds the tile's last slice
 };
 
-// One 64 x 64 tile of C for the FP32 path; called by all 256 threads.
+// One 64 x 64 tile of C (or one K slice of it) for the FP32 path; called by
+// all 256 threads.
 __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
                                               const uint32_t* __restrict__ tab,
-                                              float2* __restrict__ arena, SmemF32& S) {
+                                              float2* __restrict__ arena, SmemF32& S,
+                                              const SplitK& sk) {
   auto& As = S.A;
   auto& Bs = S.B;
   const int t = threadIdx.x;
@@ -119,13 +196,13 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
       for (int p = 0; p < 4; ++p) {
         // A element (m, k): k fastest across threads when A is k-contiguous
         uint32_t k = k0 + (akf ? (t & 15) : (t >> 6) + 4 * p);
-        pa[p] = (aok[p] && k < op.K) ? c.A[aoff[p] + tab[op.a_k + k]] : make_float2(0.f, 0.f);
+        pa[p] = (aok[p] && k < c.ke) ? c.A[aoff[p] + tab[op.a_k + k]] : make_float2(0.f, 0.f);
         k = k0 + (bkf ? (t & 15) : (t >> 6) + 4 * p);
-        pb[p] = (bok[p] && k < op.K) ? c.B[boff[p] + tab[op.b_k + k]] : make_float2(0.f, 0.f);
+        pb[p] = (bok[p] && k < c.ke) ? c.B[boff[p] + tab[op.b_k + k]] : make_float2(0.f, 0.f);
       }
     };
-    fetch(0);
-    for (uint32_t k0 = 0; k0 < op.K; k0 += BK32) {
+    fetch(c.kb);
+    for (uint32_t k0 = c.kb; k0 < c.ke; k0 += BK32) {
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         int kk = akf ? (t & 15) : (t >> 6) + 4 * p;
@@ -138,7 +215,7 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
         Bs[1][kk][nn] = pb[p].y;
       }
       __syncthreads();
-      if (k0 + BK32 < op.K) fetch(k0 + BK32);
+      if (k0 + BK32 < c.ke) fetch(k0 + BK32);
 #pragma unroll
       for (int kk = 0; kk < BK32; kk += 4) {
         const int kr = kk + (lane >> 4);
@@ -163,6 +240,7 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
       }
       __syncthreads();
     }
+    if (op.ksplit > 1 && !split_block(op, c, sk, cr, ci, S.flag)) return;
     store_tile(op, c, tab, arena, cr, ci, wm, wn, lane);
   }
 }
@@ -179,15 +257,12 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
 template <int BI, int BJ>
 __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
                                               const uint32_t* __restrict__ tab,
-                                              float2* __restrict__ arena, int lane) {
-  uint64_t l = unit - op.work0;
-  const uint32_t tn = (uint32_t)(l % op.tiles_n);
-  l /= op.tiles_n;
-  const uint32_t tm = (uint32_t)(l % op.tiles_m);
-  const uint64_t r = l / op.tiles_m;
-  const float2* __restrict__ A = arena + op.a + r * op.a_bs;
-  const float2* __restrict__ B = arena + op.b + r * op.b_bs;
-  const uint32_t m0 = tm * 16 * BI, n0 = tn * 16 * BJ;
+                                              float2* __restrict__ arena, int lane,
+                                              const SplitK& sk) {
+  const TileCtx c = unit_ctx(op, unit - op.work0, arena, 16 * BI, 16 * BJ);
+  const float2* __restrict__ A = c.A;
+  const float2* __restrict__ B = c.B;
+  const uint32_t m0 = c.m0, n0 = c.n0;
   const int i = lane & 15, kq = lane >> 4;
   uint32_t am[BI], bn[BJ];
 #pragma unroll
@@ -213,8 +288,8 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
         ci[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi].y, bv[bj].x, ci[bi][bj], 0, 0, 0);
       }
   };
-  const uint32_t steps = op.K >> 2;
-  uint32_t s = 0;
+  const uint32_t steps = c.ke >> 2;
+  uint32_t s = c.kb >> 2;
   // U k-steps issued together: their table and operand loads overlap
   constexpr int U = 4;
   for (; s + U <= steps; s += U) {
@@ -244,7 +319,51 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
     for (int bj = 0; bj < BJ; ++bj) bv[bj] = B[kb + bn[bj]];
     step(av, bv);
   }
-  const uint64_t cb = op.c + r * op.c_bs;
+  if (op.ksplit > 1) {
+    // split-K epilogue of one wavefront: element j of lane l at j * 64 + l
+    // of the slice's partial tile; the last slice of the tile to arrive adds
+    // all slices in slice order and stores
+    constexpr int NF = 8 * BI * BJ;
+    const uint32_t P = op.ksplit;
+    float* tile_part = sk.part + op.part + c.tile * P * (NF * 64);
+    float* mine = tile_part + (uint64_t)c.slice * (NF * 64);
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          mine[((bi * BJ + bj) * 8 + v) * 64 + lane] = cr[bi][bj][v];
+          mine[((bi * BJ + bj) * 8 + 4 + v) * 64 + lane] = ci[bi][bj][v];
+        }
+    __threadfence();
+    uint32_t prev = 0;
+    if (lane == 0) prev = atomicAdd(sk.cnt + op.cnt + c.tile, 1u);
+    prev = __shfl(prev, 0, 64);
+    if (prev != P - 1) return;
+    __threadfence();
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) {
+        cr[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+        ci[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    for (uint32_t q = 0; q < P; ++q) {
+      const float* src = tile_part + (uint64_t)q * (NF * 64);
+#pragma unroll
+      for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            cr[bi][bj][v] += src[((bi * BJ + bj) * 8 + v) * 64 + lane];
+            ci[bi][bj][v] += src[((bi * BJ + bj) * 8 + 4 + v) * 64 + lane];
+          }
+    }
+    if (lane == 0) sk.cnt[op.cnt + c.tile] = 0;
+  }
+  const uint64_t cb = c.cbase;
 #pragma unroll
   for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
@@ -268,12 +387,15 @@ struct SmemBF16 {
   // [re/im][hi/lo][row][k], k contiguous so that a lane reads 8 k at once
   __attribute__((aligned(16))) __bf16 A[2][2][BM][BK16 + 8];
   __attribute__((aligned(16))) __bf16 B[2][2][BN][BK16 + 8];
+  uint32_t flag;  // split-K: this block holds the tile's last slice
 };
 
-// One 64 x 64 tile of C for the split-BF16 path; called by all 256 threads.
+// One 64 x 64 tile of C (or one K slice of it) for the split-BF16 path;
+// called by all 256 threads.
 __device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
                                                  const uint32_t* __restrict__ tab,
-                                                 float2* __restrict__ arena, SmemBF16& S) {
+                                                 float2* __restrict__ arena, SmemBF16& S,
+                                                 const SplitK& sk) {
   auto& As = S.A;
   auto& Bs = S.B;
   const int t = threadIdx.x;
@@ -302,21 +424,21 @@ __device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
         pq[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       }
-    for (uint32_t k0 = 0; k0 < op.K; k0 += BK16) {
+    for (uint32_t k0 = c.kb; k0 < c.ke; k0 += BK16) {
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         int kk = akf ? (t & 31) : (t >> 6) + 4 * p;
         int mm = akf ? (t >> 5) + 8 * p : (t & 63);
         uint32_t k = k0 + kk;
         float2 v = make_float2(0.f, 0.f);
-        if (aok[p] && k < op.K) v = c.A[aoff[p] + tab[op.a_k + k]];
+        if (aok[p] && k < c.ke) v = c.A[aoff[p] + tab[op.a_k + k]];
         split_bf16(v.x, As[0][0][mm][kk], As[0][1][mm][kk]);
         split_bf16(v.y, As[1][0][mm][kk], As[1][1][mm][kk]);
         kk = bkf ? (t & 31) : (t >> 6) + 4 * p;
         int nn = bkf ? (t >> 5) + 8 * p : (t & 63);
         k = k0 + kk;
         v = make_float2(0.f, 0.f);
-        if (bok[p] && k < op.K) v = c.B[boff[p] + tab[op.b_k + k]];
+        if (bok[p] && k < c.ke) v = c.B[boff[p] + tab[op.b_k + k]];
         split_bf16(v.x, Bs[0][0][nn][kk], Bs[0][1][nn][kk]);
         split_bf16(v.y, Bs[1][0][nn][kk], Bs[1][1][nn][kk]);
       }
@@ -359,6 +481,7 @@ __device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) cr[i][j] = pr[i][j] - pq[i][j];
+    if (op.ksplit > 1 && !split_block(op, c, sk, cr, ci, S.flag)) return;
     store_tile(op, c, tab, arena, cr, ci, wm, wn, lane);
   }
 }

@@ -24,6 +24,27 @@ struct DevOp {
   uint32_t rows;           // batch rows covered (1 if nothing is batched)
   uint32_t tiles_m, tiles_n;  // GEMM path: tile grid per batch row
   uint32_t flags;          // bit 0: A is k-contiguous; bit 1: B is k-contiguous
+  // GEMM split-K: K is cut into ksplit slices (1 = none); slice results go
+  // to partial tiles from float `part` of the split region, and the tiles'
+  // arrival counters start at `cnt` in the counter region
+  uint64_t part;
+  uint32_t cnt;
+  uint32_t ksplit;
+};
+
+// Term mode: one workgroup runs one term's whole tree.  A group is the
+// term's gather ops at one step (run between two workgroup barriers).
+struct DevGroup {
+  uint32_t op_begin, op_end;  // ops in the op table, work0 relative to the group
+  uint64_t items;             // gather items (a multiple of 64)
+  uint64_t item_base;         // first entry in the per-item op table
+};
+
+struct DevTerm {
+  uint64_t leaf_work0, leaf_work_end;  // the term's leaf entries (leaf work items)
+  uint32_t leaf_begin, leaf_end;       // the term's leaves
+  uint32_t fwd_begin, fwd_end;         // forward groups
+  uint32_t bwd_begin, bwd_end;         // reverse-sweep groups
 };
 
 enum : int32_t {

@@ -289,6 +289,31 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
         best = std::move(tp);
       }
     }
+    // One more candidate: the time-ordered sweep of a state-vector
+    // simulation, kept when it scores better.  The unconjugated leaves
+    // (boundary vectors, gates in circuit order, Pauli matrices or output
+    // bras) are absorbed one by one into a single growing tensor, then the
+    // conjugated copy from its last gate back to its boundary vectors, so
+    // the tensor never holds more than the light cone's open wires (plus a
+    // split gate's bond).  On two-dimensional circuits, where greedy merging
+    // of the doubled network can open far more legs, this bounds the largest
+    // intermediate by 2^(qubits in the light cone).
+    if (term.leaves.size() > 1) {
+      std::vector<int32_t> order;
+      for (int32_t i = 0; i < (int32_t)term.leaves.size(); ++i)
+        if (!term.leaves[i].conj) order.push_back(i);
+      for (int32_t i = (int32_t)term.leaves.size() - 1; i >= 0; --i)
+        if (term.leaves[i].conj) order.push_back(i);
+      TermPath tp;
+      tp.n_leaves = (int32_t)term.leaves.size();
+      int32_t cur = order[0];
+      for (size_t k = 1; k < order.size(); ++k) {
+        tp.pairs.push_back({cur, order[k]});
+        cur = tp.n_leaves + (int32_t)tp.pairs.size() - 1;
+      }
+      const double sc = score_of(tree_stats(term, tp), opts.score);
+      if (sc < best_score) best = std::move(tp);
+    }
     path.terms.push_back(std::move(best));
   }
   return path;

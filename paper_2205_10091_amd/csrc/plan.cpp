@@ -45,6 +45,7 @@ struct PT {                       // a tensor of the plan
   int64_t off = -1;
   int32_t first = 0, last = 0;    // timeline steps of production / last use
   bool fixed = false;             // preallocated constant (seeds)
+  int32_t term = -1;              // owning term
 };
 
 struct Tables {
@@ -70,7 +71,10 @@ struct Tables {
     auto it = memo.find(key);
     if (it != memo.end()) return it->second;
     const uint64_t n = 1ull << nb;
-    if (tabs.size() + n > 0xFFFFFFFFull) fail(TC_ERR_TOO_LARGE, "index tables exceed 2^32 entries");
+    // checked before building: a plan whose tables would pass the budget is
+    // rejected at once instead of after filling them
+    if (tabs.size() + n > TABLE_MAX_ENTRIES)
+      fail(TC_ERR_TOO_LARGE, "index tables would exceed 2^27 entries (512 MiB)");
     uint32_t base = (uint32_t)tabs.size();
     tabs.resize(tabs.size() + n);
     // entry i = entry(i without its lowest set bit) + stride of that bit
@@ -141,9 +145,31 @@ struct Arena {
   }
 };
 
+// Gather layout of a node: k-split S = 2^ls lanes per output group (long
+// sums of small nodes, while the node stays within `lanes` lanes), else
+// V = 2^lv outputs per thread along n.  Level launches spread a node over
+// the whole chip (65536 lanes); term mode over one 1024-thread workgroup.
+void gather_shape(uint32_t M, uint32_t N, uint32_t K, uint32_t rows, uint64_t lanes,
+                  uint32_t& ls, uint32_t& lv) {
+  const uint64_t outs = (uint64_t)rows * M * N;
+  ls = 0;
+  while (ls < 6 && (K >> ls) > 4 && (outs << (ls + 1)) <= lanes) ++ls;
+  while (ls < 6 && (K >> ls) > 256) ++ls;
+  lv = 0;
+  if (ls == 0) lv = N >= 4 ? 2 : (N == 2 ? 1 : 0);
+}
+
+uint64_t gather_items(uint32_t M, uint32_t N, uint32_t K, uint32_t rows, uint64_t lanes) {
+  uint32_t ls, lv;
+  gather_shape(M, N, K, rows, lanes, ls, lv);
+  uint64_t items = ((uint64_t)rows * M * (N >> lv)) << ls;
+  return ls ? (items + 63) & ~uint64_t(63) : items;
+}
+
 struct PendingOp {
   int32_t a, b, c;   // tensor ids
   int32_t step;
+  int32_t term;
   bool bwd;          // part of the reverse-sweep launch list
   bool recompute;    // forward op re-run by checkpointing
 };
@@ -169,7 +195,8 @@ struct Schedule {
 // Builds tensors, ops with their steps, lifetimes and arena offsets.
 // ckpt = 0: keep every intermediate for the reverse sweep; ckpt >= 2:
 // checkpoint segments of that many levels.
-void schedule(Schedule& S, const Network& net, const Path& path, int B, bool grad, int ckpt) {
+void schedule(Schedule& S, const Network& net, const Path& path, int B, bool grad, int ckpt,
+              bool per_term_arena) {
   std::vector<PT>& T = S.T;
   S.ti.assign(net.terms.size(), TermInfo{});
 
@@ -200,6 +227,7 @@ void schedule(Schedule& S, const Network& net, const Path& path, int B, bool gra
       x.legs = legs[i];
       x.elems = 1ull << x.legs.size();
       x.batched = leaf_param_dependent(net, term.leaves[i]);
+      x.term = (int32_t)t;
       I.needs[i] = x.batched;
       x.first = 0;
       I.tid[i] = (int32_t)T.size();
@@ -212,6 +240,7 @@ void schedule(Schedule& S, const Network& net, const Path& path, int B, bool gra
       if (x.legs.size() > 31) fail(TC_ERR_TOO_LARGE, "intermediate of rank > 31");
       x.elems = 1ull << x.legs.size();
       x.batched = T[I.tid[a]].batched || T[I.tid[b]].batched;
+      x.term = (int32_t)t;
       I.needs[c] = I.needs[a] || I.needs[b];
       I.level[c] = 1 + std::max(I.level[a], I.level[b]);
       x.first = I.level[c];
@@ -238,7 +267,7 @@ void schedule(Schedule& S, const Network& net, const Path& path, int B, bool gra
     for (size_t s = 0; s < tp.pairs.size(); ++s) {
       int32_t a = tp.pairs[s].first, b = tp.pairs[s].second, c = nl + (int32_t)s;
       int32_t step = I.level[c];
-      S.pend.push_back({I.tid[a], I.tid[b], I.tid[c], step, false, false});
+      S.pend.push_back({I.tid[a], I.tid[b], I.tid[c], step, (int32_t)t, false, false});
       T[I.tid[a]].last = std::max(T[I.tid[a]].last, step);
       T[I.tid[b]].last = std::max(T[I.tid[b]].last, step);
     }
@@ -293,7 +322,7 @@ void schedule(Schedule& S, const Network& net, const Path& path, int B, bool gra
           r.last = step;
           int32_t rid = (int32_t)T.size();
           T.push_back(r);
-          S.pend.push_back({val[a], val[b], rid, step, true, true});
+          S.pend.push_back({val[a], val[b], rid, step, (int32_t)t, true, true});
           T[val[a]].last = std::max(T[val[a]].last, step);
           T[val[b]].last = std::max(T[val[b]].last, step);
           val[x] = rid;
@@ -322,12 +351,13 @@ void schedule(Schedule& S, const Network& net, const Path& path, int B, bool gra
               if (std::find(cl.begin(), cl.end(), l) == cl.end()) d.legs.push_back(l);
           }
           d.elems = 1ull << d.legs.size();
+          d.term = (int32_t)t;
           d.batched = T[adj[c]].batched || T[ov].batched;
           d.first = step;
           d.last = step;  // extended when consumed
           int32_t did = (int32_t)T.size();
           T.push_back(d);
-          S.pend.push_back({adj[c], ov, did, step, true, false});
+          S.pend.push_back({adj[c], ov, did, step, (int32_t)t, true, false});
           T[adj[c]].last = std::max(T[adj[c]].last, step);
           T[ov].last = std::max(T[ov].last, step);
           adj[x] = did;
@@ -341,32 +371,41 @@ void schedule(Schedule& S, const Network& net, const Path& path, int B, bool gra
   }
   for (auto& la : S.leaf_adj) T[la.second].last = S.grad_step;
 
-  // ---- arena: allocate in step order, release after last use
-  Arena ar;
-  ar.top = S.seed_elems;
+  // ---- arena: allocate in step order, release after last use.  One arena
+  // over all terms (level-synchronous launches order every term's steps), or
+  // one region per term when terms run independently (term mode).
   const int32_t n_steps = S.grad_step + 1;
-  std::vector<std::vector<int32_t>> born(n_steps + 1), dies(n_steps + 2);
-  for (int32_t i = 0; i < (int32_t)T.size(); ++i) {
-    if (T[i].fixed) continue;
-    born[T[i].first].push_back(i);
-    dies[std::max(T[i].last, T[i].first) + 1].push_back(i);
-  }
-  for (int32_t s = 0; s < n_steps; ++s) {
-    for (int32_t i : dies[s]) {
-      uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
-      ar.release((uint64_t)T[i].off, n);
+  std::vector<std::vector<int32_t>> members(per_term_arena ? net.terms.size() : 1);
+  for (int32_t i = 0; i < (int32_t)T.size(); ++i)
+    if (!T[i].fixed) members[per_term_arena ? T[i].term : 0].push_back(i);
+  uint64_t base = S.seed_elems;
+  for (const auto& mem : members) {
+    Arena ar;
+    ar.top = base;
+    uint64_t top = base;
+    std::vector<std::vector<int32_t>> born(n_steps + 1), dies(n_steps + 2);
+    for (int32_t i : mem) {
+      born[T[i].first].push_back(i);
+      dies[std::max(T[i].last, T[i].first) + 1].push_back(i);
     }
-    // big tensors first keeps the best-fit layout compact
-    std::sort(born[s].begin(), born[s].end(),
-              [&](int32_t x, int32_t y) { return T[x].elems > T[y].elems; });
-    for (int32_t i : born[s]) {
-      uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
-      T[i].off = (int64_t)ar.alloc(n);
-      S.arena_elems = std::max(S.arena_elems, ar.top);
-      S.peak_tensor_elems = std::max(S.peak_tensor_elems, n);
+    for (int32_t s = 0; s < n_steps; ++s) {
+      for (int32_t i : dies[s]) {
+        uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
+        ar.release((uint64_t)T[i].off, n);
+      }
+      // big tensors first keeps the best-fit layout compact
+      std::sort(born[s].begin(), born[s].end(),
+                [&](int32_t x, int32_t y) { return T[x].elems > T[y].elems; });
+      for (int32_t i : born[s]) {
+        uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
+        T[i].off = (int64_t)ar.alloc(n);
+        top = std::max(top, ar.top);
+        S.peak_tensor_elems = std::max(S.peak_tensor_elems, n);
+      }
     }
+    base = Arena::align(top);
   }
-  S.arena_elems = std::max(S.arena_elems, S.seed_elems);
+  S.arena_elems = std::max(base, S.seed_elems);
 }
 
 }  // namespace
@@ -383,6 +422,10 @@ WorkspaceLayout workspace_layout(const Plan& p) {
   w.uses = o; o = al(o + p.uses.size() * sizeof(DevGradUse));
   w.slot_begin = o; o = al(o + p.slot_begin.size() * sizeof(uint32_t));
   w.roots = o; o = al(o + p.roots.size() * sizeof(DevRoot));
+  w.terms = o; o = al(o + p.terms.size() * sizeof(DevTerm));
+  w.groups = o; o = al(o + p.groups.size() * sizeof(DevGroup));
+  w.split = o; o = al(o + p.split_floats * sizeof(float));
+  w.splitcnt = o; o = al(o + p.split_counters * sizeof(uint32_t));
   w.params = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(float));
   w.value = o; o = al(o + (uint64_t)p.batch * 2 * sizeof(double));
   w.grad = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(double));
@@ -401,7 +444,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   // ---- schedule, with checkpointing when the budget asks for it
   Schedule S;
   int ckpt = plan.checkpoint > 0 ? plan.checkpoint : 0;
-  schedule(S, net, path, B, grad, ckpt);
+  schedule(S, net, path, B, grad, ckpt, false);
   if (grad && plan.checkpoint == 0 && plan.budget && S.arena_elems * 8 > plan.budget &&
       S.max_level >= 4) {
     // smallest arena over a few segment lengths
@@ -410,7 +453,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     for (int c : {2, 3, 4, 6, 8, 12}) {
       if (c > std::max(2, S.max_level / 2)) break;
       Schedule t;
-      schedule(t, net, path, B, grad, c);
+      schedule(t, net, path, B, grad, c, false);
       if (!best_c || t.arena_elems < best.arena_elems) {
         best = std::move(t);
         best_c = c;
@@ -421,6 +464,64 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       ckpt = best_c;
     }
   }
+  // leg label -> position in one operand's storage order (-1: absent)
+  int32_t n_labels = 0;
+  for (const Term& term : net.terms) n_labels = std::max(n_labels, term.n_labels);
+  std::vector<int8_t> pa(n_labels, -1), pb(n_labels, -1), pc(n_labels, -1);
+  auto mark = [&](std::vector<int8_t>& pos, const std::vector<int32_t>& legs, bool on) {
+    for (size_t x = 0; x < legs.size(); ++x) {
+      if (legs[x] < 0 || legs[x] >= n_labels) fail(TC_ERR_INVALID_ARG, "internal: leg label out of range");
+      pos[legs[x]] = on ? (int8_t)x : (int8_t)-1;
+    }
+  };
+  auto gemm_node = [&](uint32_t M, uint32_t N, uint32_t K, uint32_t rows) {
+    return K >= (uint32_t)plan.gemm_min_k && M >= (uint32_t)plan.gemm_min_mn &&
+           N >= (uint32_t)plan.gemm_min_mn && (uint64_t)rows * M * N * K >= plan.gemm_min_macs;
+  };
+
+  // ---- execution mode.  Term mode runs each term's whole tree in one
+  // workgroup (workgroup barriers between its steps, one kernel for all
+  // terms): it needs every node on the gather path and gives each term its
+  // own arena region, since terms no longer advance in step.  A workgroup
+  // is one CU, so term mode only pays off for light trees: automatically it
+  // is chosen when no step of any term has more gather items than two per
+  // thread of the workgroup.
+  bool term_mode = plan.exec_mode == 2;
+  if (plan.exec_mode == 0 && B == 1) {
+    term_mode = true;
+    std::map<std::pair<int32_t, int32_t>, uint64_t> items;  // (term, step) -> items
+    for (const PendingOp& q : S.pend) {
+      const PT& A = S.T[q.a];
+      const PT& Bt = S.T[q.b];
+      mark(pb, Bt.legs, true);
+      uint32_t sh = 0;
+      for (int32_t l : A.legs) sh += pb[l] >= 0;
+      mark(pb, Bt.legs, false);
+      const uint32_t K = 1u << sh, M = 1u << (A.legs.size() - sh), N = 1u << (Bt.legs.size() - sh);
+      uint64_t& n_items = items[{q.term, q.step}];
+      uint32_t ls, lv;
+      gather_shape(M, N, K, 1, TERM_LANES, ls, lv);
+      if (ls) n_items = (n_items + 63) & ~uint64_t(63);  // k-split ops start on a wavefront
+      n_items += gather_items(M, N, K, 1, TERM_LANES);
+      if (gemm_node(M, N, K, 1) || n_items > TERM_MODE_MAX_ITEMS) {
+        term_mode = false;
+        break;
+      }
+    }
+  }
+  if (term_mode) {
+    Schedule St;
+    schedule(St, net, path, B, grad, ckpt, true);
+    // automatic choice: only while the separate regions stay modest
+    const bool fits = !plan.budget || St.arena_elems * 8 <= plan.budget;
+    const bool modest = St.arena_elems <= std::max<uint64_t>(4 * S.arena_elems, uint64_t(1) << 25);
+    if (plan.exec_mode == 2 || (fits && modest))
+      S = std::move(St);
+    else
+      term_mode = false;
+  }
+  plan.term_mode = term_mode;
+
   plan.checkpoint_used = grad ? ckpt : 0;
   plan.arena_elems = S.arena_elems;
   plan.peak_tensor_elems = S.peak_tensor_elems;
@@ -438,26 +539,26 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   }
   Tables tables(plan.tabs);
 
-  // ---- contraction ops, grouped into launches by step
-  std::stable_sort(pend.begin(), pend.end(),
-                   [](const PendingOp& x, const PendingOp& y) { return x.step < y.step; });
+  // ---- contraction ops, grouped into launches by step (term mode: into
+  // groups by term, then step)
+  if (term_mode)
+    std::stable_sort(pend.begin(), pend.end(), [](const PendingOp& x, const PendingOp& y) {
+      return x.term != y.term ? x.term < y.term : x.step < y.step;
+    });
+  else
+    std::stable_sort(pend.begin(), pend.end(),
+                     [](const PendingOp& x, const PendingOp& y) { return x.step < y.step; });
   double flops = 0, bytes = 0, gflops = 0, gbytes = 0;
+  double term_flops[2] = {0, 0}, term_bytes[2] = {0, 0};
   int32_t n_gemm_nodes = 0;
-  // leg label -> position in one operand's storage order (-1: absent)
-  int32_t n_labels = 0;
-  for (const Term& term : net.terms) n_labels = std::max(n_labels, term.n_labels);
-  std::vector<int8_t> pa(n_labels, -1), pb(n_labels, -1), pc(n_labels, -1);
-  auto mark = [&](std::vector<int8_t>& pos, const std::vector<int32_t>& legs, bool on) {
-    for (size_t x = 0; x < legs.size(); ++x) {
-      if (legs[x] < 0 || legs[x] >= n_labels) fail(TC_ERR_INVALID_ARG, "internal: leg label out of range");
-      pos[legs[x]] = on ? (int8_t)x : (int8_t)-1;
-    }
-  };
+  plan.terms.assign(net.terms.size(), DevTerm{});
   std::vector<int32_t> Sh, FA, FB;
   size_t i = 0;
   while (i < pend.size()) {
     size_t j = i;
-    while (j < pend.size() && pend[j].step == pend[i].step) ++j;
+    while (j < pend.size() && pend[j].step == pend[i].step &&
+           (!term_mode || pend[j].term == pend[i].term))
+      ++j;
     std::vector<DevOp> gc, gm, wv;
     double lf = 0, lb = 0, gf = 0, gb = 0;
     for (size_t k = i; k < j; ++k) {
@@ -474,6 +575,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       for (int32_t l : Bt.legs)
         if (pa[l] < 0) FB.push_back(l);
       DevOp op{};
+      op.ksplit = 1;
       op.a = (uint64_t)A.off;
       op.b = (uint64_t)Bt.off;
       op.c = (uint64_t)C.off;
@@ -507,9 +609,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       }
       lf += f;
       lb += by;
-      const bool to_gemm = op.K >= (uint32_t)plan.gemm_min_k && op.M >= (uint32_t)plan.gemm_min_mn &&
-                           op.N >= (uint32_t)plan.gemm_min_mn &&
-                           (uint64_t)op.rows * op.M * op.N * op.K >= plan.gemm_min_macs;
+      const bool to_gemm = !term_mode && gemm_node(op.M, op.N, op.K, op.rows);
       if (to_gemm) {
         gf += f;
         gb += by;
@@ -536,12 +636,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       } else {
         // gather: split long sums over up to 64 lanes while the op is small,
         // else 4 outputs per thread along n
-        const uint64_t outs = (uint64_t)op.rows * op.M * op.N;
-        uint32_t ls = 0;
-        while (ls < 6 && (op.K >> ls) > 4 && (outs << (ls + 1)) <= 65536) ++ls;
-        while (ls < 6 && (op.K >> ls) > 256) ++ls;
-        uint32_t lv = 0;
-        if (ls == 0) lv = op.N >= 4 ? 2 : (op.N == 2 ? 1 : 0);
+        uint32_t ls, lv;
+        gather_shape(op.M, op.N, op.K, op.rows, term_mode ? TERM_LANES : LEVEL_LANES, ls, lv);
         op.flags |= (ls << 4) | (lv << 8);
         gc.push_back(op);
       }
@@ -552,11 +648,30 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.bytes = lb;
     L.gemm_flops = gf;
     L.gemm_bytes = gb;
+    // split-K: a GEMM node with too few output tiles to fill the chip (256
+    // CUs) cuts K into slices of at least 64; each slice writes a partial
+    // tile and the last slice of a tile to arrive sums them in slice order.
+    // The partial tiles and counters of one level reuse the same regions as
+    // every other level's (levels never overlap).
+    uint64_t part = 0, cnt = 0;
+    auto split = [&](DevOp& op, uint64_t target_units, uint64_t floats_per_tile) {
+      const uint64_t base = (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+      uint32_t P = 1;
+      while (P < 64 && base * P < target_units && op.K / (2 * P) >= 64) P *= 2;
+      op.ksplit = P;
+      if (P > 1) {
+        op.part = part;
+        op.cnt = (uint32_t)cnt;
+        part += base * P * floats_per_tile;
+        cnt += base;
+      }
+      return base * P;
+    };
     L.gbegin = (uint32_t)plan.ops.size();
     uint64_t tiles = 0;
     for (DevOp& op : gm) {
       op.work0 = tiles;
-      tiles += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+      tiles += split(op, 512, 32 * 256);  // 32 accumulators per thread, 256 threads
       plan.ops.push_back(op);
     }
     L.gend = (uint32_t)plan.ops.size();
@@ -565,9 +680,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     uint64_t wtiles = 0;
     for (DevOp& op : wv) {
       op.work0 = wtiles;
-      wtiles += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+      const uint64_t blocks = (uint64_t)((op.flags >> 12) & 1u ? 2 : 1) * ((op.flags >> 13) & 1u ? 2 : 1);
+      wtiles += split(op, 2048, 8 * blocks * 64);  // 8 accumulators per 16x16 block and lane
       plan.ops.push_back(op);
     }
+    if (cnt > 0xFFFFFFFFull) fail(TC_ERR_TOO_LARGE, "too many split-K tiles in one level");
+    plan.split_floats = std::max(plan.split_floats, part);
+    plan.split_counters = std::max(plan.split_counters, cnt);
     L.wend = (uint32_t)plan.ops.size();
     L.wtiles = wtiles;
     L.begin = (uint32_t)plan.ops.size();
@@ -596,19 +715,50 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         for (uint64_t x = lo; x < hi; ++x) it[x] = o - L.begin;
       }
     }
-    (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
+    if (term_mode) {
+      // one group of the term: its ops at this step
+      const int32_t t = pend[i].term;
+      const int ph = pend[i].bwd ? 1 : 0;
+      DevGroup G{};
+      G.op_begin = L.begin;
+      G.op_end = L.end;
+      G.items = L.work;
+      G.item_base = L.item_begin;
+      DevTerm& D = plan.terms[t];
+      const uint32_t g = (uint32_t)plan.groups.size();
+      if (ph == 0) {
+        if (D.fwd_end == 0) D.fwd_begin = g;
+        D.fwd_end = g + 1;
+      } else {
+        if (D.bwd_end == 0) D.bwd_begin = g;
+        D.bwd_end = g + 1;
+      }
+      plan.groups.push_back(G);
+      term_flops[ph] += lf;
+      term_bytes[ph] += lb;
+    } else {
+      (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
+    }
     i = j;
+  }
+  for (DevTerm& D : plan.terms) {  // terms without groups: empty ranges
+    if (D.fwd_end == 0) D.fwd_begin = 0;
+    if (D.bwd_end == 0) D.bwd_begin = 0;
   }
   {
     Launch L;
-    L.kind = L_LEAF;
-    plan.fwd.insert(plan.fwd.begin(), L);  // filled below
+    L.kind = term_mode ? L_TERM : L_LEAF;
+    L.flops = term_flops[0];
+    L.bytes = term_bytes[0];
+    plan.fwd.insert(plan.fwd.begin(), L);  // leaf work filled below
   }
 
   // ---- leaves
   uint64_t lw = 0;
   for (size_t t = 0; t < net.terms.size(); ++t) {
     const Term& term = net.terms[t];
+    plan.terms[t].leaf_begin = (uint32_t)plan.leaves.size();
+    plan.terms[t].leaf_work0 = lw;
     for (size_t li = 0; li < term.leaves.size(); ++li) {
       const Leaf& lf = term.leaves[li];
       const PT& x = T[ti[t].tid[li]];
@@ -638,7 +788,10 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       lw += (uint64_t)d.rows << lf.rank;
       plan.leaves.push_back(d);
     }
+    plan.terms[t].leaf_end = (uint32_t)plan.leaves.size();
+    plan.terms[t].leaf_work_end = lw;
   }
+  if (!term_mode) plan.terms.clear();
   plan.leaf_work = lw;
   plan.fwd[0].work = lw;
   if (lw > 0 && lw <= ITEM_TABLE_MAX) {  // leaf entry -> leaf index
@@ -649,7 +802,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       plan.item_op.insert(plan.item_op.end(), (uint64_t)d.rows << d.rank, i);
     }
   }
-  plan.fwd[0].bytes = 8.0 * (double)lw;  // every leaf entry written once
+  plan.fwd[0].bytes += 8.0 * (double)lw;  // every leaf entry written once
 
   // ---- roots
   for (size_t t = 0; t < net.terms.size(); ++t) {
@@ -705,6 +858,14 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       L.work = (uint64_t)B * net.n_params;
       plan.bwd.push_back(L);
     }
+    if (term_mode) {  // the reverse sweep of every term, before the gradient sum
+      Launch L;
+      L.kind = L_TERM;
+      L.phase = 1;
+      L.flops = term_flops[1];
+      L.bytes = term_bytes[1];
+      plan.bwd.insert(plan.bwd.begin(), L);
+    }
   }
 
   // ---- every device access in bounds (checked here, before any launch)
@@ -735,11 +896,61 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     for (const DevRoot& r : plan.roots)
       if (r.present && r.val + (uint64_t)(B - 1) * r.bs >= AE)
         fail(TC_ERR_INVALID_ARG, "internal: root out of range");
+    // GEMM ops: tile grids that cover M x N, split-K partial tiles and
+    // counters inside their regions
+    for (const auto* seq : {&plan.fwd, &plan.bwd})
+      for (const Launch& L : *seq) {
+        if (L.kind != L_LEVEL) continue;
+        for (uint32_t o = L.gbegin; o < L.wend; ++o) {
+          const DevOp& op = plan.ops[o];
+          const bool wave = o >= L.wbegin;
+          const uint64_t bi = (op.flags >> 12) & 1u ? 2 : 1, bj = (op.flags >> 13) & 1u ? 2 : 1;
+          const uint64_t fpt = wave ? 8 * bi * bj * 64 : 32 * 256;
+          const bool cover = wave ? (uint64_t)op.tiles_m * 16 * bi == op.M &&
+                                        (uint64_t)op.tiles_n * 16 * bj == op.N && op.K >= 4
+                                  : (uint64_t)op.tiles_m * 64 >= op.M && (uint64_t)op.tiles_n * 64 >= op.N;
+          if (!cover || op.ksplit < 1 || op.K % op.ksplit != 0)
+            fail(TC_ERR_INVALID_ARG, "internal: GEMM tile grid does not match the node");
+          if (op.ksplit == 1) continue;
+          const uint64_t base = (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+          if (op.cnt + base > plan.split_counters ||
+              op.part + base * op.ksplit * fpt > plan.split_floats ||
+              (wave && (op.K / op.ksplit) % 4 != 0))
+            fail(TC_ERR_INVALID_ARG, "internal: split-K tiles out of range");
+        }
+      }
+    // term mode: groups name contiguous op ranges whose items cover the ops,
+    // terms name group and leaf ranges
+    for (const DevGroup& G : plan.groups) {
+      if (G.op_begin >= G.op_end || G.op_end > plan.ops.size() || (G.items & 63) != 0)
+        fail(TC_ERR_INVALID_ARG, "internal: bad group");
+      for (uint32_t o = G.op_begin; o < G.op_end; ++o) {
+        const DevOp& op = plan.ops[o];
+        const uint32_t ls = (op.flags >> 4) & 7u, lv = (op.flags >> 8) & 3u;
+        const uint64_t items = ((uint64_t)op.rows * op.M * (op.N >> lv)) << ls;
+        if (op.work0 + items > G.items || (o > G.op_begin && op.work0 < plan.ops[o - 1].work0))
+          fail(TC_ERR_INVALID_ARG, "internal: group items do not cover its ops");
+      }
+      if (G.item_base != NO_ITEMS) {
+        if (G.item_base + G.items > plan.item_op.size())
+          fail(TC_ERR_INVALID_ARG, "internal: item table out of range");
+        for (uint64_t x = 0; x < G.items; ++x)
+          if (plan.item_op[G.item_base + x] >= G.op_end - G.op_begin)
+            fail(TC_ERR_INVALID_ARG, "internal: item table names a missing op");
+      }
+    }
+    for (const DevTerm& D : plan.terms)
+      if (D.fwd_begin > D.fwd_end || D.fwd_end > plan.groups.size() ||
+          D.bwd_begin > D.bwd_end || D.bwd_end > plan.groups.size() ||
+          D.leaf_begin > D.leaf_end || D.leaf_end > plan.leaves.size() ||
+          D.leaf_work_end > plan.leaf_work || D.leaf_work0 > D.leaf_work_end)
+        fail(TC_ERR_INVALID_ARG, "internal: bad term range");
     // per-item tables: one entry per work item, naming an item of the launch
     for (const auto* seq : {&plan.fwd, &plan.bwd})
       for (const Launch& L : *seq) {
         if (L.item_begin == NO_ITEMS) continue;
-        const uint64_t n_items = L.kind == L_LEAF ? plan.leaves.size() : L.end - L.begin;
+        const uint64_t n_items =
+            (L.kind == L_LEAF || L.kind == L_TERM) ? plan.leaves.size() : L.end - L.begin;
         if (L.item_begin + L.work > plan.item_op.size())
           fail(TC_ERR_INVALID_ARG, "internal: item table out of range");
         for (uint64_t x = 0; x < L.work; ++x)
@@ -769,6 +980,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   info.n_params = net.n_params;
   info.n_terms = plan.n_terms;
   info.checkpoint_every = plan.checkpoint_used;
+  info.exec_mode = plan.term_mode ? 2 : 1;
+  for (const DevOp& op : plan.ops) info.n_split_nodes += op.ksplit > 1;
   if (plan.budget && info.workspace_bytes > plan.budget)
     fail(TC_ERR_TOO_LARGE, "workspace of " + std::to_string(info.workspace_bytes) +
                                " bytes exceeds the memory budget");

@@ -14,7 +14,8 @@ enum LaunchKind : int32_t {
   L_LEAF = 0,   // materialise leaf tensors from parameters
   L_LEVEL = 1,  // one contraction level: MFMA GEMM tiles + gather contractions
   L_ROOT = 4,   // FP64 weighted sum of the term roots
-  L_GRAD = 5    // FP64 leaf-gradient reduction
+  L_GRAD = 5,   // FP64 leaf-gradient reduction
+  L_TERM = 6    // term mode: one workgroup per term runs its leaves and levels
 };
 // kernel kinds reported by profiling: a level's two kernels
 constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3;
@@ -22,6 +23,14 @@ constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3;
 constexpr uint64_t NO_ITEMS = ~uint64_t(0);
 // levels with at most this many gather items get a per-item op index table
 constexpr uint64_t ITEM_TABLE_MAX = uint64_t(1) << 18;
+// automatic term mode: at most this many gather items per term and step
+// (two per thread of the 1024-thread workgroup)
+constexpr uint64_t TERM_MODE_MAX_ITEMS = 2048;
+// lanes a gather node may spread its k-split over: a level launch, a term's
+// workgroup
+constexpr uint64_t LEVEL_LANES = 65536, TERM_LANES = 1024;
+// index tables of one plan (uint32 entries)
+constexpr uint64_t TABLE_MAX_ENTRIES = uint64_t(1) << 27;
 
 struct Launch {
   int32_t kind;
@@ -32,6 +41,7 @@ struct Launch {
   uint32_t wbegin = 0, wend = 0;  // GEMM ops in wave tiles, in Plan::ops
   uint64_t wtiles = 0;            // wave tiles
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
+  int32_t phase = 0;              // L_TERM: 0 leaves + forward groups, 1 reverse sweep
   double flops = 0;               // algorithmic flops (8 per complex MAC)
   double bytes = 0;               // algorithmic bytes: operands read + results written
   double gemm_flops = 0;          // the part of flops / bytes in GEMM tiles
@@ -54,6 +64,10 @@ struct Plan {
   // GEMM nodes with M, N >= 64 and K >= 16 use 64 x 64 LDS tiles; the
   // narrower ones run as one-wavefront MFMA tiles
   int32_t block_tile_min_mn = 64, block_tile_min_k = 16;
+  // execution: 0 = term mode when every node is a gather and batch is 1,
+  // 1 = level-synchronous launches, 2 = term mode (all nodes as gathers)
+  int32_t exec_mode = 0;
+  bool term_mode = false;
   // checkpoint segment length: 0 = only when the budget requires it,
   // >= 2 = always with that length, -1 = never
   int32_t checkpoint = 0;
@@ -68,12 +82,16 @@ struct Plan {
   std::vector<DevGradUse> uses;       // sorted by slot
   std::vector<uint32_t> slot_begin;   // n_params + 1
   std::vector<DevRoot> roots;
+  std::vector<DevTerm> terms;         // term mode
+  std::vector<DevGroup> groups;       // term mode
   std::vector<float> seeds;           // (re, im) per term, arena offset 0
   uint64_t leaf_work = 0;
 
   std::vector<Launch> fwd;            // leaf, levels, root
   std::vector<Launch> bwd;            // adjoint levels, grad
   uint64_t arena_elems = 0;           // complex64 elements
+  uint64_t split_floats = 0;          // split-K partial tiles of the largest level
+  uint64_t split_counters = 0;        // split-K output tiles of the largest level
   uint64_t peak_tensor_elems = 0;
 
   tc_plan_info info{};
@@ -87,7 +105,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path);
 
 // Byte layout of the workspace: [tables][params][values][grad][arena]
 struct WorkspaceLayout {
-  uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots;
+  uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots, terms, groups;
+  uint64_t split, splitcnt;  // split-K partial tiles (float), arrival counters (uint32)
   uint64_t params, value, grad, arena, total;
 };
 WorkspaceLayout workspace_layout(const Plan& p);

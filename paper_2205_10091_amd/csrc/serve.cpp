@@ -334,6 +334,7 @@ tc_status tc_serve_submit(tc_server* srv, const tc_circuit* circuit,
     plan->want_grad = req->want_grad;
     plan->device = S.opts.device;
     plan->budget = S.opts.max_request_bytes;
+    plan->exec_mode = 1;  // requests advance one level per engine step
     tcx::build_plan(*plan, net, path);  // TOO_LARGE when over the per-request cap
     std::lock_guard<std::mutex> g(S.mu);
     if (S.cache.size() >= 512) S.cache.clear();

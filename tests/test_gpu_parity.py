@@ -162,6 +162,27 @@ def test_grid_amplitude_full_size_against_golden():
     assert rel_err(a, vals[0], 2 ** (-18)) < TOL_C64
 
 
+def test_split_k_wide_nodes_fp32_and_bf16x3():
+    """The 6x6 grid's widest nodes have few output tiles and deep K, so
+    their K is cut into slices; the slices' partial tiles are added in slice
+    order by whichever slice finishes last.  Both precisions against the
+    oracle's amplitude, and repeated calls bit-identical."""
+    from gpu_common import TOL_BF16X3
+    path = os.path.join(GOLDEN, "grid6x6_d8_amplitude.json")
+    if not os.path.exists(path):
+        pytest.skip("reference amplitude not generated")
+    ref = json.load(open(path))
+    r = complex(ref["values"]["col2"]["re"], ref["values"]["col2"]["im"])
+    circ, p, amp = tcgen.workload_grid_amplitude()
+    for prec, tol in ((0, TOL_C64), (1, TOL_BF16X3)):
+        plan = api.compile(circ, amp, n_trials=32, seed=1, precision=prec)
+        assert plan.info().n_split_nodes > 0
+        a1 = plan.contract(device_params(p))[0]
+        a2 = plan.contract(device_params(p))[0]
+        assert a1 == a2, prec
+        assert rel_err(a1, r, 2 ** (-18)) < tol, prec
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_all_gate_kinds_random_circuits():
@@ -273,6 +294,44 @@ def test_checkpointed_gradient_matches(ckpt):
     assert np.max(np.abs(g1 - g2)) < 1e-6
     e_ref, g_ref = sv.energy_grad(circ, P[3], obs)
     assert grad_err(g2[3], g_ref) < TOL_C64
+
+
+def test_term_mode_matches_level_mode_and_oracle():
+    """One workgroup per term (leaves and every level behind workgroup
+    barriers) against level-synchronous launches of the same trees and
+    against the oracle: the VQE chain with gradient, the same with
+    checkpointed segments, batch rows inside a term, and a forward-only
+    amplitude."""
+    circ, p, obs = tcgen.workload_vqe_chain()
+    tm = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1, exec_mode=2)
+    lev = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1, exec_mode=1)
+    ck = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1, exec_mode=2,
+                     checkpoint_every=3)
+    assert lev.info().exec_mode == 1 and ck.info().exec_mode == 2
+    assert tm.info().n_launches + tm.info().n_grad_launches == 4
+    e_ref, g_ref = sv.energy_grad(circ, p, obs)
+    results = [pl.contract_grad(device_params(p)) for pl in (tm, lev, ck)]
+    for e, g in results:
+        assert rel_err(e[0], e_ref, 1.0) < TOL_C64
+        assert grad_err(g[0], g_ref) < TOL_C64
+    # repeated calls reuse the same per-term regions
+    e2, g2 = tm.contract_grad(device_params(p))
+    assert e2[0] == results[0][0][0] and np.array_equal(g2, results[0][1])
+    # batch rows inside each term's workgroup
+    B = 6
+    circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=12, layers=4)
+    tm = api.compile(circ, obs, batch=B, want_grad=True, exec_mode=2)
+    assert tm.info().exec_mode == 2
+    e, g = tm.contract_grad(device_params(P, B))
+    for b in (0, 5):
+        e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
+        assert rel_err(e[b], e_ref, 1.0) < TOL_C64
+        assert grad_err(g[b], g_ref) < TOL_C64
+    # forward only, amplitude: a light tree, term mode chosen automatically
+    circ, p, zz, amp = tcgen.workload_forward_chain()
+    pa, a = one(circ, amp, p)
+    assert pa.info().exec_mode == 2
+    assert rel_err(a, sv.amplitude(circ, p), 2 ** (-circ.n_qubits / 2)) < TOL_C64
 
 
 def test_autograd_function_matches_oracle():
