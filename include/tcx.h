@@ -257,14 +257,18 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *               multiply-adds (M N K times its batch rows) to go to the GEMM:
  *               below it the gather kernels finish sooner; 0 = default
  *               (2^20), 1 = no floor;
- *   exec_mode   1 = level-synchronous: every tree level (of all terms) is a
- *               GEMM kernel and a gather kernel; 2 = term mode: one
- *               workgroup per term runs the term's leaves and all its levels
- *               with workgroup barriers in between (one kernel for the
- *               forward pass and one for the reverse sweep; every node on
- *               the gather path; each term gets its own arena region);
- *               0 = term mode when batch is 1 and no node qualifies for the
- *               GEMM path, level-synchronous otherwise.
+ *   exec_mode   how tree levels (steps) run.  Level launch: all terms'
+ *               nodes at one step as a GEMM kernel and a gather kernel over
+ *               the whole chip.  Term launch: one workgroup per term runs
+ *               the term's nodes of a run of consecutive steps with
+ *               workgroup barriers in between (gather path only; each term
+ *               gets its own arena region).  1 = level launches only; 2 =
+ *               term launches only (the leaves and all forward steps in
+ *               one kernel, the reverse sweep in another); 0 = term
+ *               launches for runs of at least two light steps (batch 1, no
+ *               node for the GEMM path, at most two gather items per
+ *               thread of each term's workgroup), level launches for the
+ *               other steps.
  * GEMM nodes whose output tiles cannot fill the chip have K cut into
  * slices (split-K): every slice writes a partial tile to the workspace and
  * the last slice of a tile to arrive adds the slices in slice order, so
@@ -316,7 +320,8 @@ typedef struct {
   int32_t n_params;
   int32_t n_terms;
   int32_t checkpoint_every;  /* segment length used, 0 = none            */
-  int32_t exec_mode;         /* 1 level launches, 2 term mode            */
+  int32_t exec_mode;         /* 1 level launches only, 2 term launches
+                                only, 3 both                             */
   int32_t n_split_nodes;     /* GEMM nodes whose K is cut into slices    */
 } tc_plan_info;
 

@@ -97,6 +97,7 @@ struct RootArgs {
 
 struct TermArgs {
   const DevTerm* terms;
+  const DevRange* ranges;     // this launch's range of each term
   const DevGroup* groups;
   const DevOp* ops;
   const uint32_t* tab;
@@ -107,7 +108,7 @@ struct TermArgs {
   const float* params;
   float2* arena;
   int32_t n_params;
-  int32_t phase;              // 0: leaves and forward groups, 1: reverse sweep
+  int32_t with_leaves;        // materialise the term's leaves first
 };
 
 struct GradSeg {
@@ -159,15 +160,15 @@ __device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
   acc.im = fmaf(a.y, b.x, acc.im);
 }
 
-// acc[j] += sum over k = sub, sub + S, ... < K of A[ak[k]] * B[bk[k] + bn[j]],
+// acc[j] += sum over k = sub, sub + S, ... < K of A[ak(k)] * B[bk(k) + bn[j]],
 // j < V, accumulated in increasing k.  U steps are issued together so that
 // their table and operand loads overlap instead of forming one dependent
 // chain per step.
 template <int V>
 __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restrict__ A,
                                            const float2* __restrict__ Bp,
-                                           const uint32_t* __restrict__ ak,
-                                           const uint32_t* __restrict__ bk,
+                                           const uint32_t* __restrict__ tab, uint32_t ak,
+                                           uint32_t bk,
                                            const uint32_t (&bn)[4], uint32_t sub, uint32_t S,
                                            uint32_t K) {
   constexpr int U = V == 4 ? 2 : (V == 2 ? 4 : 8);  // about 90 VGPRs: 5 waves per SIMD
@@ -176,8 +177,8 @@ __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restri
     uint32_t ia[U], ib[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ia[u] = ak[k + u * S];
-      ib[u] = bk[k + u * S];
+      ia[u] = ix(tab, ak, k + u * S);
+      ib[u] = ix(tab, bk, k + u * S);
     }
     float2 av[U], bv[U][V];
 #pragma unroll
@@ -192,8 +193,8 @@ __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restri
       for (int j = 0; j < V; ++j) cfma(acc[j], av[u], bv[u][j]);
   }
   for (; k < K; k += S) {
-    const float2 av = A[ak[k]];
-    const float2* __restrict__ bb = Bp + bk[k];
+    const float2 av = A[ix(tab, ak, k)];
+    const float2* __restrict__ bb = Bp + ix(tab, bk, k);
 #pragma unroll
     for (int j = 0; j < V; ++j) cfma(acc[j], av, bb[bn[j]]);
   }
@@ -323,19 +324,17 @@ __device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool ha
     n0 = (uint32_t)(e & ((1u << ln) - 1)) << lv;
     m = (uint32_t)((e >> ln) & (op.M - 1));
     r = e >> (ln + lm);
-    const float2* __restrict__ A = arena + op.a + r * op.a_bs + tab[op.a_m + m];
+    const float2* __restrict__ A = arena + op.a + r * op.a_bs + ix(tab, op.a_m, m);
     const float2* __restrict__ Bp = arena + op.b + r * op.b_bs;
-    const uint32_t* __restrict__ ak = tab + op.a_k;
-    const uint32_t* __restrict__ bk = tab + op.b_k;
     uint32_t bn[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? tab[op.b_n + n0 + j] : 0u;
+    for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? ix(tab, op.b_n, n0 + j) : 0u;
     if (V == 4)
-      gather_dot<4>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+      gather_dot<4>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
     else if (V == 2)
-      gather_dot<2>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+      gather_dot<2>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
     else
-      gather_dot<1>(acc, A, Bp, ak, bk, bn, sub, S, op.K);
+      gather_dot<1>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
   }
   if (S > 1) {
     // V == 1 whenever S > 1
@@ -345,14 +344,14 @@ __device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool ha
     }
   }
   if (valid && sub == 0) {
-    const uint64_t cb = op.c + r * op.c_bs + tab[op.c_m + m];
+    const uint64_t cb = op.c + r * op.c_bs + ix(tab, op.c_m, m);
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j)
-      if (j < V) arena[cb + tab[op.c_n + n0 + j]] = make_float2(acc[j].re, acc[j].im);
+      if (j < V) arena[cb + ix(tab, op.c_n, n0 + j)] = make_float2(acc[j].re, acc[j].im);
   }
 }
 
-__global__ void __launch_bounds__(256) k_gather(LevelArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_gather(LevelArgs a) {
   // each block takes one contiguous chunk (a multiple of 256 items, so
   // wavefronts never straddle its end); a thread finds its segment and op
   // once (or reads it from the per-item table) and then only walks forward
@@ -403,39 +402,105 @@ __device__ __forceinline__ uint32_t find_in(const T* __restrict__ items, uint32_
   return lo;
 }
 
-// Term mode: workgroup t runs term t alone, its leaves and then each of its
-// groups (its nodes at one step) with a workgroup barrier in between; the
-// terms' trees advance independently, each in its own arena region, so a
-// deep tree costs barriers instead of kernel launches.  Group items are
-// whole wavefronts (a multiple of 64) and the block strides over them in
-// steps of 1024, so the lanes of a wavefront always share one op.
+// Term launch: workgroup t runs term t alone over a run of steps (first
+// its leaves, if asked), each group (its nodes at one step) followed by a
+// workgroup barrier; the terms advance independently, each in its own arena
+// region, so a run of light steps costs barriers instead of kernel
+// launches.  Group items are whole wavefronts (a multiple of 64) and the
+// block strides over them in steps of 1024, so the lanes of a wavefront
+// always share one op.
+// Groups and op records of a term launch are staged in LDS: the groups of
+// the term's range once, and each group's op records (up to TERM_LDS_OPS of
+// them) double-buffered, the next group's loaded into registers while the
+// current group computes and written to the other buffer before the
+// barrier.  Reading op records and finding an item's op then costs LDS
+// accesses instead of dependent global loads on every step.
+constexpr uint32_t TERM_LDS_OPS = 128, TERM_LDS_GROUPS = 64;
+constexpr uint32_t OP_WORDS = sizeof(DevOp) / 4;
+static_assert(sizeof(DevOp) % 4 == 0, "op records are copied as 32-bit words");
+constexpr uint32_t TERM_PRE = (TERM_LDS_OPS * OP_WORDS + 1023) / 1024;  // words per thread
+
 __global__ void __launch_bounds__(1024) k_term(TermArgs a) {
+  __shared__ DevOp sops[2][TERM_LDS_OPS];
+  __shared__ DevGroup sgroups[TERM_LDS_GROUPS];
   const DevTerm T = a.terms[blockIdx.x];
-  if (a.phase == 0) {
+  const DevRange R = a.ranges[blockIdx.x];
+  const uint32_t ng = R.g_end - R.g_begin;
+  const bool groups_staged = ng <= TERM_LDS_GROUPS;
+  if (groups_staged && threadIdx.x < ng) sgroups[threadIdx.x] = a.groups[R.g_begin + threadIdx.x];
+  auto group = [&](uint32_t g) -> DevGroup {
+    return groups_staged ? sgroups[g - R.g_begin] : a.groups[g];
+  };
+  uint32_t pre[TERM_PRE];
+  auto fetch = [&](uint32_t g) {  // the op records of group g, into registers
+    if (g >= R.g_end) return;
+    const DevGroup G = a.groups[g];
+    const uint32_t n = G.op_end - G.op_begin;
+    if (n > TERM_LDS_OPS) return;
+    const uint32_t* src = (const uint32_t*)(a.ops + G.op_begin);
+#pragma unroll
+    for (uint32_t q = 0; q < TERM_PRE; ++q) {
+      const uint32_t x = threadIdx.x + q * 1024;
+      pre[q] = x < n * OP_WORDS ? src[x] : 0u;
+    }
+  };
+  auto commit = [&](uint32_t g, int buf) {  // registers -> LDS buffer
+    if (g >= R.g_end) return;
+    const DevGroup G = a.groups[g];
+    const uint32_t n = G.op_end - G.op_begin;
+    if (n > TERM_LDS_OPS) return;
+    uint32_t* dst = (uint32_t*)&sops[buf][0];
+#pragma unroll
+    for (uint32_t q = 0; q < TERM_PRE; ++q) {
+      const uint32_t x = threadIdx.x + q * 1024;
+      if (x < n * OP_WORDS) dst[x] = pre[q];
+    }
+  };
+  fetch(R.g_begin);
+  if (a.with_leaves) {
     for (uint64_t w = T.leaf_work0 + threadIdx.x; w < T.leaf_work_end; w += blockDim.x) {
       const uint32_t li =
           a.item_leaf ? a.item_leaf[w] : find_in(a.leaves, T.leaf_begin, T.leaf_end, w);
       leaf_item(a.leaves[li], w, a.params, a.n_params, a.ftab, a.arena);
     }
-    __syncthreads();
   }
-  const uint32_t g0 = a.phase == 0 ? T.fwd_begin : T.bwd_begin;
-  const uint32_t g1 = a.phase == 0 ? T.fwd_end : T.bwd_end;
-  for (uint32_t g = g0; g < g1; ++g) {
-    const DevGroup G = a.groups[g];
-    const DevOp* __restrict__ ops = a.ops + G.op_begin;
+  commit(R.g_begin, 0);
+  __syncthreads();
+  for (uint32_t g = R.g_begin; g < R.g_end; ++g) {
+    const int buf = (int)((g - R.g_begin) & 1u);
+    const DevGroup G = group(g);
     const uint32_t n = G.op_end - G.op_begin;
-    uint32_t oi = 0xffffffffu;
-    for (uint64_t w = threadIdx.x; w < G.items; w += blockDim.x) {
-      if (G.item_base != NO_ITEMS)
-        oi = a.item_op[G.item_base + w];
-      else if (oi == 0xffffffffu)
-        oi = find_item(ops, n, w);
-      else
-        while (oi + 1 < n && ops[oi + 1].work0 <= w) ++oi;
-      const DevOp& op = ops[oi];
-      gather_item(op, w - op.work0, true, a.tab, a.arena);
+    fetch(g + 1);  // in flight while this group computes
+    if (n <= TERM_LDS_OPS) {
+      const DevOp* ops = sops[buf];
+      for (uint64_t w = threadIdx.x; w < G.items; w += blockDim.x) {
+        // largest op with work0 <= w, by binary search over the LDS records
+        uint32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (ops[mid].work0 <= w)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        const DevOp& op = ops[lo];
+        gather_item(op, w - op.work0, true, a.tab, a.arena);
+      }
+    } else {
+      const DevOp* __restrict__ ops = a.ops + G.op_begin;
+      uint32_t oi = 0xffffffffu;
+      for (uint64_t w = threadIdx.x; w < G.items; w += blockDim.x) {
+        if (G.item_base != NO_ITEMS)
+          oi = a.item_op[G.item_base + w];
+        else if (oi == 0xffffffffu)
+          oi = find_item(ops, n, w);
+        else
+          while (oi + 1 < n && ops[oi + 1].work0 <= w) ++oi;
+        const DevOp& op = ops[oi];
+        gather_item(op, w - op.work0, true, a.tab, a.arena);
+      }
     }
+    commit(g + 1, buf ^ 1);
     __syncthreads();
   }
 }
@@ -610,6 +675,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       if (P.terms.empty()) return;
       TermArgs a{};
       a.terms = (const DevTerm*)(s.ws + L.terms);
+      a.ranges = (const DevRange*)(s.ws + L.ranges) + s.launch->begin;
       a.groups = (const DevGroup*)(s.ws + L.groups);
       a.ops = (const DevOp*)(s.ws + L.ops);
       a.tab = (const uint32_t*)(s.ws + L.tabs);
@@ -622,7 +688,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.params = (const float*)(s.ws + L.params);
       a.arena = (float2*)(s.ws + L.arena);
       a.n_params = P.n_params;
-      a.phase = s.launch->phase;
+      a.with_leaves = s.launch->with_leaves ? 1 : 0;
       hipLaunchKernelGGL(k_term, dim3((unsigned)P.terms.size()), dim3(1024), 0, stream, a);
       break;
     }
@@ -703,6 +769,7 @@ void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStrea
   upload(ws, lay.roots, P.roots, stream);
   upload(ws, lay.terms, P.terms, stream);
   upload(ws, lay.groups, P.groups, stream);
+  upload(ws, lay.ranges, P.ranges, stream);
   // split-K arrival counters start at zero; each tile's last slice resets
   // its counter, so they are zero again after every launch
   if (P.split_counters)

@@ -26,6 +26,20 @@ namespace tcx {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// Offset of index i of an index group under its descriptor d (layout in
+// ops.h): a table lookup, or the OR of up to IX_RUNS shifted bit fields.
+__device__ __forceinline__ uint32_t ix(const uint32_t* __restrict__ tab, uint32_t d, uint32_t i) {
+  if (d & IX_TABLE) return tab[(d & ~IX_TABLE) + i];
+  uint32_t off = 0, src = 0;
+#pragma unroll
+  for (int r = 0; r < IX_RUNS; ++r) {
+    const uint32_t len = (d >> (10 * r)) & 31u, dst = (d >> (10 * r + 5)) & 31u;
+    off |= ((i >> src) & ((1u << len) - 1u)) << dst;
+    src += len;
+  }
+  return off;
+}
+
 constexpr int BM = 64, BN = 64;
 constexpr int BK32 = 16;   // k per LDS stage, FP32 path
 constexpr int BK16 = 32;   // k per LDS stage, split-BF16 path
@@ -141,7 +155,7 @@ __device__ __forceinline__ void store_tile(const DevOp& op, const TileCtx& t,
         uint32_t m = t.m0 + wm * 32 + bi * 16 + 4 * (lane >> 4) + v;
         uint32_t n = t.n0 + wn * 32 + bj * 16 + (lane & 15);
         if (m < op.M && n < op.N)
-          arena[t.cbase + tab[op.c_m + m] + tab[op.c_n + n]] =
+          arena[t.cbase + ix(tab, op.c_m, m) + ix(tab, op.c_n, n)] =
               make_float2(cr[bi][bj][v], ci[bi][bj][v]);
       }
 }
@@ -175,10 +189,10 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
     for (int p = 0; p < 4; ++p) {
       uint32_t m = c.m0 + (akf ? (t >> 4) + 16 * p : (t & 63));
       aok[p] = m < op.M;
-      aoff[p] = aok[p] ? tab[op.a_m + m] : 0;
+      aoff[p] = aok[p] ? ix(tab, op.a_m, m) : 0;
       uint32_t n = c.n0 + (bkf ? (t >> 4) + 16 * p : (t & 63));
       bok[p] = n < op.N;
-      boff[p] = bok[p] ? tab[op.b_n + n] : 0;
+      boff[p] = bok[p] ? ix(tab, op.b_n, n) : 0;
     }
     f4 cr[2][2], ci[2][2];
 #pragma unroll
@@ -196,9 +210,9 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
       for (int p = 0; p < 4; ++p) {
         // A element (m, k): k fastest across threads when A is k-contiguous
         uint32_t k = k0 + (akf ? (t & 15) : (t >> 6) + 4 * p);
-        pa[p] = (aok[p] && k < c.ke) ? c.A[aoff[p] + tab[op.a_k + k]] : make_float2(0.f, 0.f);
+        pa[p] = (aok[p] && k < c.ke) ? c.A[aoff[p] + ix(tab, op.a_k, k)] : make_float2(0.f, 0.f);
         k = k0 + (bkf ? (t & 15) : (t >> 6) + 4 * p);
-        pb[p] = (bok[p] && k < c.ke) ? c.B[boff[p] + tab[op.b_k + k]] : make_float2(0.f, 0.f);
+        pb[p] = (bok[p] && k < c.ke) ? c.B[boff[p] + ix(tab, op.b_k, k)] : make_float2(0.f, 0.f);
       }
     };
     fetch(c.kb);
@@ -266,9 +280,9 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
   const int i = lane & 15, kq = lane >> 4;
   uint32_t am[BI], bn[BJ];
 #pragma unroll
-  for (int bi = 0; bi < BI; ++bi) am[bi] = tab[op.a_m + m0 + bi * 16 + i];
+  for (int bi = 0; bi < BI; ++bi) am[bi] = ix(tab, op.a_m, m0 + bi * 16 + i);
 #pragma unroll
-  for (int bj = 0; bj < BJ; ++bj) bn[bj] = tab[op.b_n + n0 + bj * 16 + i];
+  for (int bj = 0; bj < BJ; ++bj) bn[bj] = ix(tab, op.b_n, n0 + bj * 16 + i);
   f4 cr[BI][BJ], ci[BI][BJ];
 #pragma unroll
   for (int bi = 0; bi < BI; ++bi)
@@ -296,8 +310,8 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
     uint32_t ka[U], kb[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ka[u] = tab[op.a_k + 4 * (s + u) + kq];
-      kb[u] = tab[op.b_k + 4 * (s + u) + kq];
+      ka[u] = ix(tab, op.a_k, 4 * (s + u) + kq);
+      kb[u] = ix(tab, op.b_k, 4 * (s + u) + kq);
     }
     float2 av[U][BI], bv[U][BJ];
 #pragma unroll
@@ -311,7 +325,7 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
     for (int u = 0; u < U; ++u) step(av[u], bv[u]);
   }
   for (; s < steps; ++s) {
-    const uint32_t ka = tab[op.a_k + 4 * s + kq], kb = tab[op.b_k + 4 * s + kq];
+    const uint32_t ka = ix(tab, op.a_k, 4 * s + kq), kb = ix(tab, op.b_k, 4 * s + kq);
     float2 av[BI], bv[BJ];
 #pragma unroll
     for (int bi = 0; bi < BI; ++bi) av[bi] = A[am[bi] + ka];
@@ -368,10 +382,10 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
   for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const uint32_t cm = tab[op.c_m + m0 + bi * 16 + 4 * kq + v];
+      const uint32_t cm = ix(tab, op.c_m, m0 + bi * 16 + 4 * kq + v);
 #pragma unroll
       for (int bj = 0; bj < BJ; ++bj)
-        arena[cb + cm + tab[op.c_n + n0 + bj * 16 + i]] =
+        arena[cb + cm + ix(tab, op.c_n, n0 + bj * 16 + i)] =
             make_float2(cr[bi][bj][v], ci[bi][bj][v]);
     }
 }
@@ -410,10 +424,10 @@ __device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
     for (int p = 0; p < 8; ++p) {
       uint32_t m = c.m0 + (akf ? (t >> 5) + 8 * p : (t & 63));
       aok[p] = m < op.M;
-      aoff[p] = aok[p] ? tab[op.a_m + m] : 0;
+      aoff[p] = aok[p] ? ix(tab, op.a_m, m) : 0;
       uint32_t n = c.n0 + (bkf ? (t >> 5) + 8 * p : (t & 63));
       bok[p] = n < op.N;
-      boff[p] = bok[p] ? tab[op.b_n + n] : 0;
+      boff[p] = bok[p] ? ix(tab, op.b_n, n) : 0;
     }
     f4 pr[2][2], pq[2][2], ci[2][2];
 #pragma unroll
@@ -431,14 +445,14 @@ __device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
         int mm = akf ? (t >> 5) + 8 * p : (t & 63);
         uint32_t k = k0 + kk;
         float2 v = make_float2(0.f, 0.f);
-        if (aok[p] && k < c.ke) v = c.A[aoff[p] + tab[op.a_k + k]];
+        if (aok[p] && k < c.ke) v = c.A[aoff[p] + ix(tab, op.a_k, k)];
         split_bf16(v.x, As[0][0][mm][kk], As[0][1][mm][kk]);
         split_bf16(v.y, As[1][0][mm][kk], As[1][1][mm][kk]);
         kk = bkf ? (t & 31) : (t >> 6) + 4 * p;
         int nn = bkf ? (t >> 5) + 8 * p : (t & 63);
         k = k0 + kk;
         v = make_float2(0.f, 0.f);
-        if (bok[p] && k < c.ke) v = c.B[boff[p] + tab[op.b_k + k]];
+        if (bok[p] && k < c.ke) v = c.B[boff[p] + ix(tab, op.b_k, k)];
         split_bf16(v.x, Bs[0][0][nn][kk], Bs[0][1][nn][kk]);
         split_bf16(v.y, Bs[1][0][nn][kk], Bs[1][1][nn][kk]);
       }

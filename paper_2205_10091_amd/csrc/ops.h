@@ -15,12 +15,29 @@ namespace tcx {
 // tab[a_k + k]; element (k, n) of B at B + tab[b_k + k] + tab[b_n + n];
 // element (m, n) of C at C + tab[c_m + m] + tab[c_n + n].  Batch row r adds
 // r * a_bs, r * b_bs, r * c_bs.
+// Index descriptor of one index group (the m, k or n legs of an operand):
+// maps an index i over the group (first leg most significant) to the
+// element offset of that index inside the tensor.
+//   bit 31 set:   table; offset(i) = tab[(d & 0x7fffffff) + i]
+//   bit 31 clear: up to IX_RUNS bit-field runs, run r in bits [10 r, 10 r + 10)
+//                 as len (5 bits) | dst (5 bits) << 5, run 0 on the lowest
+//                 index bits: with s_r = len_0 + ... + len_(r-1),
+//                 offset(i) = OR_r ((i >> s_r) & (2^len_r - 1)) << dst_r
+//                 (a run of len 0 contributes nothing).
+// A run is a stretch of the group's legs that sits, in the same order, on
+// consecutive bits of the tensor.  Nearly every group needs one to three
+// runs (three when two legs are taken out of the middle of a tensor, as
+// when a gate meets a state) and no memory at all; tables remain for the
+// more permuted ones.
+constexpr int IX_RUNS = 3;
+constexpr uint32_t IX_TABLE = 0x80000000u;
+
 struct DevOp {
   uint64_t a, b, c;        // arena element offsets
   uint64_t work0;          // first work item of this op inside its launch
   uint32_t a_bs, b_bs, c_bs;  // batch strides in elements (0 = shared)
   uint32_t M, N, K;
-  uint32_t a_m, a_k, b_k, b_n, c_m, c_n;  // offsets into the table area
+  uint32_t a_m, a_k, b_k, b_n, c_m, c_n;  // index descriptors
   uint32_t rows;           // batch rows covered (1 if nothing is batched)
   uint32_t tiles_m, tiles_n;  // GEMM path: tile grid per batch row
   uint32_t flags;          // bit 0: A is k-contiguous; bit 1: B is k-contiguous
@@ -32,19 +49,22 @@ struct DevOp {
   uint32_t ksplit;
 };
 
-// Term mode: one workgroup runs one term's whole tree.  A group is the
-// term's gather ops at one step (run between two workgroup barriers).
+// Term launches: one workgroup runs one term's nodes over a run of steps.
+// A group is the term's gather ops at one step (between two workgroup
+// barriers); a range names one term's groups in one term launch.
 struct DevGroup {
   uint32_t op_begin, op_end;  // ops in the op table, work0 relative to the group
   uint64_t items;             // gather items (a multiple of 64)
   uint64_t item_base;         // first entry in the per-item op table
 };
 
+struct DevRange {
+  uint32_t g_begin, g_end;
+};
+
 struct DevTerm {
   uint64_t leaf_work0, leaf_work_end;  // the term's leaf entries (leaf work items)
   uint32_t leaf_begin, leaf_end;       // the term's leaves
-  uint32_t fwd_begin, fwd_end;         // forward groups
-  uint32_t bwd_begin, bwd_end;         // reverse-sweep groups
 };
 
 enum : int32_t {

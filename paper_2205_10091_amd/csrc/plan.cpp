@@ -48,15 +48,30 @@ struct PT {                       // a tensor of the plan
   int32_t term = -1;              // owning term
 };
 
+// offset of index i under descriptor d (see ops.h)
+uint64_t ix_host(const std::vector<uint32_t>& tabs, uint32_t d, uint64_t i) {
+  if (d & IX_TABLE) return tabs[(d & ~IX_TABLE) + i];
+  uint64_t off = 0;
+  uint32_t src = 0;
+  for (int r = 0; r < IX_RUNS; ++r) {
+    const uint32_t f = (d >> (10 * r)) & 0x3ffu;
+    const uint32_t len = f & 31, dst = f >> 5;
+    off |= ((i >> src) & ((uint64_t(1) << len) - 1)) << dst;
+    src += len;
+  }
+  return off;
+}
+
 struct Tables {
   std::vector<uint32_t>& tabs;
   std::unordered_map<std::string, uint32_t> memo;
   std::unordered_map<uint32_t, uint32_t> maxv;  // table base -> largest entry
+  uint64_t n_runs = 0, n_tables = 0;            // descriptors of each kind
   explicit Tables(std::vector<uint32_t>& t) : tabs(t) {}
 
-  // offsets of index i over the ordered sub-legs `sub` of a rank-r tensor
-  // whose leg l sits at position pos[l]: sum_j bit_j(i) * 2^(r-1-pos[sub[j]]),
-  // sub[0] most significant
+  // Descriptor of the offsets of index i over the ordered sub-legs `sub` of
+  // a rank-r tensor whose leg l sits at position pos[l]:
+  // sum_j bit_j(i) * 2^(r-1-pos[sub[j]]), sub[0] most significant.
   uint32_t gather(const std::vector<int8_t>& pos, int r, const std::vector<int32_t>& sub) {
     uint32_t stride[32];
     char sh[32];
@@ -67,9 +82,33 @@ struct Tables {
       sh[j] = (char)(r - 1 - idx);
       stride[j] = 1u << (r - 1 - idx);
     }
+    // runs: maximal stretches of legs on consecutive, descending tensor
+    // bits, found from the most significant index bit down and stored from
+    // the least significant up
+    {
+      uint32_t len[IX_RUNS + 1], dst[IX_RUNS + 1];
+      int runs = 0;
+      size_t j = 0;
+      while (j < nb && runs <= IX_RUNS) {
+        size_t e = j + 1;
+        while (e < nb && sh[e] == sh[e - 1] - 1) ++e;
+        len[runs] = (uint32_t)(e - j);
+        dst[runs] = (uint32_t)sh[e - 1];  // lowest tensor bit of the run
+        ++runs;
+        j = e;
+      }
+      if (j == nb && runs <= IX_RUNS) {
+        uint32_t d = 0;
+        for (int q = 0; q < runs; ++q)
+          d |= (len[runs - 1 - q] | (dst[runs - 1 - q] << 5)) << (10 * q);
+        ++n_runs;
+        return d;
+      }
+    }
+    ++n_tables;
     std::string key(sh, nb);
     auto it = memo.find(key);
-    if (it != memo.end()) return it->second;
+    if (it != memo.end()) return IX_TABLE | it->second;
     const uint64_t n = 1ull << nb;
     // checked before building: a plan whose tables would pass the budget is
     // rejected at once instead of after filling them
@@ -88,9 +127,13 @@ struct Tables {
     }
     memo.emplace(key, base);
     maxv.emplace(base, mx);
-    return base;
+    return IX_TABLE | base;
   }
-  uint32_t max_of(uint32_t base) const { return maxv.at(base); }
+  // largest offset over the group's 2^nb indices
+  uint64_t max_of(uint32_t d, uint32_t n) const {
+    if (d & IX_TABLE) return maxv.at(d & ~IX_TABLE);
+    return n ? ix_host(tabs, d, n - 1) : 0;  // all index bits set
+  }
 };
 
 // Best-fit allocator over element offsets: free blocks indexed both by
@@ -339,17 +382,11 @@ void schedule(Schedule& S, const Network& net, const Path& path, int B, bool gra
           if (!I.needs[x]) continue;
           const int32_t ov = val[other];
           PT d;
-          if (x < nl) {
-            d.legs = T[I.tid[x]].legs;  // leaf order for the gradient dot
-          } else {
-            // natural order of contract(dC, other): dC's free legs then other's
-            const auto& cl = T[adj[c]].legs;
-            const auto& ol = T[ov].legs;
-            for (int32_t l : cl)
-              if (std::find(ol.begin(), ol.end(), l) == ol.end()) d.legs.push_back(l);
-            for (int32_t l : ol)
-              if (std::find(cl.begin(), cl.end(), l) == cl.end()) d.legs.push_back(l);
-          }
+          // the adjoint keeps its tensor's leg order (a leaf's for the
+          // gradient dot): later adjoint ops then meet operands whose shared
+          // legs sit in the same order, which keeps their index groups in a
+          // few bit-field runs
+          d.legs = T[I.tid[x]].legs;
           d.elems = 1ull << d.legs.size();
           d.term = (int32_t)t;
           d.batched = T[adj[c]].batched || T[ov].batched;
@@ -424,6 +461,7 @@ WorkspaceLayout workspace_layout(const Plan& p) {
   w.roots = o; o = al(o + p.roots.size() * sizeof(DevRoot));
   w.terms = o; o = al(o + p.terms.size() * sizeof(DevTerm));
   w.groups = o; o = al(o + p.groups.size() * sizeof(DevGroup));
+  w.ranges = o; o = al(o + p.ranges.size() * sizeof(DevRange));
   w.split = o; o = al(o + p.split_floats * sizeof(float));
   w.splitcnt = o; o = al(o + p.split_counters * sizeof(uint32_t));
   w.params = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(float));
@@ -479,48 +517,68 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
            N >= (uint32_t)plan.gemm_min_mn && (uint64_t)rows * M * N * K >= plan.gemm_min_macs;
   };
 
-  // ---- execution mode.  Term mode runs each term's whole tree in one
-  // workgroup (workgroup barriers between its steps, one kernel for all
-  // terms): it needs every node on the gather path and gives each term its
-  // own arena region, since terms no longer advance in step.  A workgroup
-  // is one CU, so term mode only pays off for light trees: automatically it
-  // is chosen when no step of any term has more gather items than two per
-  // thread of the workgroup.
-  bool term_mode = plan.exec_mode == 2;
-  if (plan.exec_mode == 0 && B == 1) {
-    term_mode = true;
-    std::map<std::pair<int32_t, int32_t>, uint64_t> items;  // (term, step) -> items
+  // ---- execution mode, step by step.  A step runs either as a level
+  // launch (all terms' nodes at that step, k_gemm + k_gather over the whole
+  // chip) or inside a term launch: one workgroup per term runs the term's
+  // nodes of a run of consecutive steps with workgroup barriers in between,
+  // so a run of k steps costs one kernel instead of k.  A workgroup is one
+  // CU, so only light steps go to term launches: at batch 1, no node for the
+  // GEMM path and no term with more gather items than two per thread; and
+  // only runs of at least two such steps (one step gains nothing).  Terms
+  // then advance independently, so each term gets its own arena region.
+  std::map<int32_t, bool> light;  // step -> light
+  {
+    std::map<std::pair<int32_t, int32_t>, uint64_t> items;  // (step, term) -> items
     for (const PendingOp& q : S.pend) {
+      bool& l = light.emplace(q.step, true).first->second;
       const PT& A = S.T[q.a];
       const PT& Bt = S.T[q.b];
       mark(pb, Bt.legs, true);
       uint32_t sh = 0;
-      for (int32_t l : A.legs) sh += pb[l] >= 0;
+      for (int32_t x : A.legs) sh += pb[x] >= 0;
       mark(pb, Bt.legs, false);
       const uint32_t K = 1u << sh, M = 1u << (A.legs.size() - sh), N = 1u << (Bt.legs.size() - sh);
-      uint64_t& n_items = items[{q.term, q.step}];
+      uint64_t& n_items = items[{q.step, q.term}];
       uint32_t ls, lv;
       gather_shape(M, N, K, 1, TERM_LANES, ls, lv);
       if (ls) n_items = (n_items + 63) & ~uint64_t(63);  // k-split ops start on a wavefront
       n_items += gather_items(M, N, K, 1, TERM_LANES);
-      if (gemm_node(M, N, K, 1) || n_items > TERM_MODE_MAX_ITEMS) {
-        term_mode = false;
-        break;
-      }
+      // one CU walks the term's sums: light means few items and short sums
+      if (B != 1 || gemm_node(M, N, K, 1) || n_items > TERM_MODE_MAX_ITEMS ||
+          (K >> ls) > TERM_MODE_MAX_KSTEPS)
+        l = false;
     }
   }
-  if (term_mode) {
+  std::map<int32_t, bool> term_step;  // step -> runs inside a term launch
+  for (auto it = light.begin(); it != light.end(); ++it) {
+    bool t = plan.exec_mode == 2;
+    if (plan.exec_mode == 0 && it->second) {
+      auto nx = std::next(it);
+      const bool prev_light = it != light.begin() && std::prev(it)->first == it->first - 1 &&
+                              std::prev(it)->second;
+      const bool next_light = nx != light.end() && nx->first == it->first + 1 && nx->second;
+      t = prev_light || next_light;
+    }
+    term_step[it->first] = t;
+  }
+  bool any_term = false, any_level = false;
+  for (const auto& ts : term_step) (ts.second ? any_term : any_level) = true;
+  if (any_term) {
     Schedule St;
     schedule(St, net, path, B, grad, ckpt, true);
     // automatic choice: only while the separate regions stay modest
     const bool fits = !plan.budget || St.arena_elems * 8 <= plan.budget;
     const bool modest = St.arena_elems <= std::max<uint64_t>(4 * S.arena_elems, uint64_t(1) << 25);
-    if (plan.exec_mode == 2 || (fits && modest))
+    if (plan.exec_mode == 2 || (fits && modest)) {
       S = std::move(St);
-    else
-      term_mode = false;
+    } else {
+      for (auto& ts : term_step) ts.second = false;
+      any_term = false;
+      any_level = true;
+    }
   }
-  plan.term_mode = term_mode;
+  plan.term_mode = any_term;
+  plan.exec_used = any_term ? (any_level ? 3 : 2) : 1;
 
   plan.checkpoint_used = grad ? ckpt : 0;
   plan.arena_elems = S.arena_elems;
@@ -539,26 +597,72 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   }
   Tables tables(plan.tabs);
 
-  // ---- contraction ops, grouped into launches by step (term mode: into
-  // groups by term, then step)
-  if (term_mode)
-    std::stable_sort(pend.begin(), pend.end(), [](const PendingOp& x, const PendingOp& y) {
-      return x.term != y.term ? x.term < y.term : x.step < y.step;
-    });
-  else
-    std::stable_sort(pend.begin(), pend.end(),
-                     [](const PendingOp& x, const PendingOp& y) { return x.step < y.step; });
+  // ---- contraction ops: a level launch per level step; for a term step,
+  // one group per term, collected into the open term launch
+  std::stable_sort(pend.begin(), pend.end(), [](const PendingOp& x, const PendingOp& y) {
+    return x.step != y.step ? x.step < y.step : x.term < y.term;
+  });
   double flops = 0, bytes = 0, gflops = 0, gbytes = 0;
-  double term_flops[2] = {0, 0}, term_bytes[2] = {0, 0};
   int32_t n_gemm_nodes = 0;
   plan.terms.assign(net.terms.size(), DevTerm{});
+  const uint32_t n_terms = (uint32_t)net.terms.size();
+  // the open term launch: its groups start at seg_begin (each tagged with
+  // its term in group_term), its phase and algorithmic totals
+  bool seg_open = false, seg_bwd = false;
+  int32_t seg_first_step = 0;
+  size_t seg_begin = 0;
+  double seg_flops = 0, seg_bytes = 0;
+  std::vector<uint32_t> group_term;
+  auto close_segment = [&]() {
+    if (!seg_open) return;
+    // groups by term (stable: each term's steps stay in order), then one
+    // [begin, end) range per term
+    std::vector<size_t> ord(plan.groups.size() - seg_begin);
+    for (size_t x = 0; x < ord.size(); ++x) ord[x] = seg_begin + x;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](size_t x, size_t y) { return group_term[x] < group_term[y]; });
+    std::vector<DevGroup> gs;
+    std::vector<uint32_t> gt;
+    for (size_t x : ord) {
+      gs.push_back(plan.groups[x]);
+      gt.push_back(group_term[x]);
+    }
+    std::copy(gs.begin(), gs.end(), plan.groups.begin() + seg_begin);
+    std::copy(gt.begin(), gt.end(), group_term.begin() + seg_begin);
+    Launch L;
+    L.kind = L_TERM;
+    L.begin = (uint32_t)plan.ranges.size();
+    L.with_leaves = seg_first_step == 1;  // the first term launch also materialises the leaves
+    L.flops = seg_flops;
+    L.bytes = seg_bytes;
+    size_t g = seg_begin;
+    for (uint32_t t = 0; t < n_terms; ++t) {
+      DevRange R{(uint32_t)g, (uint32_t)g};
+      while (g < plan.groups.size() && group_term[g] == t) ++g;
+      R.g_end = (uint32_t)g;
+      plan.ranges.push_back(R);
+    }
+    (seg_bwd ? plan.bwd : plan.fwd).push_back(L);
+    seg_open = false;
+  };
   std::vector<int32_t> Sh, FA, FB;
   size_t i = 0;
   while (i < pend.size()) {
+    const bool tstep = term_step.at(pend[i].step);
+    if (!tstep || (seg_open && seg_bwd != pend[i].bwd)) close_segment();
+    if (tstep && !seg_open) {
+      seg_open = true;
+      seg_bwd = pend[i].bwd;
+      seg_first_step = pend[i].step;
+      seg_begin = plan.groups.size();
+      seg_flops = seg_bytes = 0;
+    }
+    // a level step takes every term's ops at the step, a term step one term's
     size_t j = i;
     while (j < pend.size() && pend[j].step == pend[i].step &&
-           (!term_mode || pend[j].term == pend[i].term))
+           (!tstep || pend[j].term == pend[i].term))
       ++j;
+    const bool term_mode = tstep;
     std::vector<DevOp> gc, gm, wv;
     double lf = 0, lb = 0, gf = 0, gb = 0;
     for (size_t k = i; k < j; ++k) {
@@ -615,8 +719,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         gb += by;
       }
       // k-contiguity of the operands picks the GEMM's load pattern
-      if (op.K > 1 && plan.tabs[op.a_k + 1] == 1) op.flags |= 1u;
-      if (op.K > 1 && plan.tabs[op.b_k + 1] == 1) op.flags |= 2u;
+      if (op.K > 1 && ix_host(plan.tabs, op.a_k, 1) == 1) op.flags |= 1u;
+      if (op.K > 1 && ix_host(plan.tabs, op.b_k, 1) == 1) op.flags |= 2u;
       const bool block_tile = op.M >= (uint32_t)plan.block_tile_min_mn &&
                               op.N >= (uint32_t)plan.block_tile_min_mn &&
                               op.K >= (uint32_t)plan.block_tile_min_k;
@@ -717,39 +821,26 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     if (term_mode) {
       // one group of the term: its ops at this step
-      const int32_t t = pend[i].term;
-      const int ph = pend[i].bwd ? 1 : 0;
       DevGroup G{};
       G.op_begin = L.begin;
       G.op_end = L.end;
       G.items = L.work;
       G.item_base = L.item_begin;
-      DevTerm& D = plan.terms[t];
-      const uint32_t g = (uint32_t)plan.groups.size();
-      if (ph == 0) {
-        if (D.fwd_end == 0) D.fwd_begin = g;
-        D.fwd_end = g + 1;
-      } else {
-        if (D.bwd_end == 0) D.bwd_begin = g;
-        D.bwd_end = g + 1;
-      }
       plan.groups.push_back(G);
-      term_flops[ph] += lf;
-      term_bytes[ph] += lb;
+      group_term.push_back((uint32_t)pend[i].term);
+      seg_flops += lf;
+      seg_bytes += lb;
     } else {
       (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
     }
     i = j;
   }
-  for (DevTerm& D : plan.terms) {  // terms without groups: empty ranges
-    if (D.fwd_end == 0) D.fwd_begin = 0;
-    if (D.bwd_end == 0) D.bwd_begin = 0;
-  }
-  {
+  close_segment();
+  // leaves: inside the first term launch when it starts at the first level,
+  // else a launch of their own
+  if (plan.fwd.empty() || plan.fwd[0].kind != L_TERM || !plan.fwd[0].with_leaves) {
     Launch L;
-    L.kind = term_mode ? L_TERM : L_LEAF;
-    L.flops = term_flops[0];
-    L.bytes = term_bytes[0];
+    L.kind = L_LEAF;
     plan.fwd.insert(plan.fwd.begin(), L);  // leaf work filled below
   }
 
@@ -791,7 +882,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     plan.terms[t].leaf_end = (uint32_t)plan.leaves.size();
     plan.terms[t].leaf_work_end = lw;
   }
-  if (!term_mode) plan.terms.clear();
+  if (!plan.term_mode) plan.terms.clear();
   plan.leaf_work = lw;
   plan.fwd[0].work = lw;
   if (lw > 0 && lw <= ITEM_TABLE_MAX) {  // leaf entry -> leaf index
@@ -858,23 +949,16 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       L.work = (uint64_t)B * net.n_params;
       plan.bwd.push_back(L);
     }
-    if (term_mode) {  // the reverse sweep of every term, before the gradient sum
-      Launch L;
-      L.kind = L_TERM;
-      L.phase = 1;
-      L.flops = term_flops[1];
-      L.bytes = term_bytes[1];
-      plan.bwd.insert(plan.bwd.begin(), L);
-    }
   }
 
   // ---- every device access in bounds (checked here, before any launch)
   {
     const uint64_t AE = plan.arena_elems;
     const uint64_t NT = plan.tabs.size();
-    auto tmax = [&](uint32_t base, uint32_t n) {
-      if ((uint64_t)base + n > NT) fail(TC_ERR_INVALID_ARG, "internal: table out of range");
-      return (uint64_t)tables.max_of(base);  // a table of n = 2^b entries
+    auto tmax = [&](uint32_t d, uint32_t n) {
+      if ((d & IX_TABLE) && (uint64_t)(d & ~IX_TABLE) + n > NT)
+        fail(TC_ERR_INVALID_ARG, "internal: table out of range");
+      return tables.max_of(d, n);  // a group of n = 2^b indices
     };
     for (const DevOp& op : plan.ops) {
       uint64_t r1 = op.rows - 1;
@@ -940,11 +1024,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       }
     }
     for (const DevTerm& D : plan.terms)
-      if (D.fwd_begin > D.fwd_end || D.fwd_end > plan.groups.size() ||
-          D.bwd_begin > D.bwd_end || D.bwd_end > plan.groups.size() ||
-          D.leaf_begin > D.leaf_end || D.leaf_end > plan.leaves.size() ||
+      if (D.leaf_begin > D.leaf_end || D.leaf_end > plan.leaves.size() ||
           D.leaf_work_end > plan.leaf_work || D.leaf_work0 > D.leaf_work_end)
-        fail(TC_ERR_INVALID_ARG, "internal: bad term range");
+        fail(TC_ERR_INVALID_ARG, "internal: bad term leaf range");
+    for (const DevRange& R : plan.ranges)
+      if (R.g_begin > R.g_end || R.g_end > plan.groups.size())
+        fail(TC_ERR_INVALID_ARG, "internal: bad term group range");
+    for (const auto* seq : {&plan.fwd, &plan.bwd})
+      for (const Launch& L : *seq)
+        if (L.kind == L_TERM &&
+            ((uint64_t)L.begin + plan.terms.size() > plan.ranges.size() || plan.terms.empty()))
+          fail(TC_ERR_INVALID_ARG, "internal: term launch without ranges");
     // per-item tables: one entry per work item, naming an item of the launch
     for (const auto* seq : {&plan.fwd, &plan.bwd})
       for (const Launch& L : *seq) {
@@ -980,7 +1070,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   info.n_params = net.n_params;
   info.n_terms = plan.n_terms;
   info.checkpoint_every = plan.checkpoint_used;
-  info.exec_mode = plan.term_mode ? 2 : 1;
+  info.exec_mode = plan.exec_used;
   for (const DevOp& op : plan.ops) info.n_split_nodes += op.ksplit > 1;
   if (plan.budget && info.workspace_bytes > plan.budget)
     fail(TC_ERR_TOO_LARGE, "workspace of " + std::to_string(info.workspace_bytes) +

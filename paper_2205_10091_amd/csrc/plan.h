@@ -15,7 +15,7 @@ enum LaunchKind : int32_t {
   L_LEVEL = 1,  // one contraction level: MFMA GEMM tiles + gather contractions
   L_ROOT = 4,   // FP64 weighted sum of the term roots
   L_GRAD = 5,   // FP64 leaf-gradient reduction
-  L_TERM = 6    // term mode: one workgroup per term runs its leaves and levels
+  L_TERM = 6    // one workgroup per term runs the term's nodes of a run of steps
 };
 // kernel kinds reported by profiling: a level's two kernels
 constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3;
@@ -23,9 +23,11 @@ constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3;
 constexpr uint64_t NO_ITEMS = ~uint64_t(0);
 // levels with at most this many gather items get a per-item op index table
 constexpr uint64_t ITEM_TABLE_MAX = uint64_t(1) << 18;
-// automatic term mode: at most this many gather items per term and step
+// automatic term launches: at most this many gather items per term and step
 // (two per thread of the 1024-thread workgroup)
 constexpr uint64_t TERM_MODE_MAX_ITEMS = 2048;
+// ... and at most this many k-steps per lane in any of its sums
+constexpr uint32_t TERM_MODE_MAX_KSTEPS = 8;
 // lanes a gather node may spread its k-split over: a level launch, a term's
 // workgroup
 constexpr uint64_t LEVEL_LANES = 65536, TERM_LANES = 1024;
@@ -41,7 +43,7 @@ struct Launch {
   uint32_t wbegin = 0, wend = 0;  // GEMM ops in wave tiles, in Plan::ops
   uint64_t wtiles = 0;            // wave tiles
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
-  int32_t phase = 0;              // L_TERM: 0 leaves + forward groups, 1 reverse sweep
+  bool with_leaves = false;       // L_TERM: materialise the leaves first
   double flops = 0;               // algorithmic flops (8 per complex MAC)
   double bytes = 0;               // algorithmic bytes: operands read + results written
   double gemm_flops = 0;          // the part of flops / bytes in GEMM tiles
@@ -67,7 +69,8 @@ struct Plan {
   // execution: 0 = term mode when every node is a gather and batch is 1,
   // 1 = level-synchronous launches, 2 = term mode (all nodes as gathers)
   int32_t exec_mode = 0;
-  bool term_mode = false;
+  bool term_mode = false;   // some steps run in term launches
+  int32_t exec_used = 1;    // 1 level launches only, 2 term launches only, 3 both
   // checkpoint segment length: 0 = only when the budget requires it,
   // >= 2 = always with that length, -1 = never
   int32_t checkpoint = 0;
@@ -82,8 +85,9 @@ struct Plan {
   std::vector<DevGradUse> uses;       // sorted by slot
   std::vector<uint32_t> slot_begin;   // n_params + 1
   std::vector<DevRoot> roots;
-  std::vector<DevTerm> terms;         // term mode
-  std::vector<DevGroup> groups;       // term mode
+  std::vector<DevTerm> terms;         // term launches: each term's leaves
+  std::vector<DevGroup> groups;       // term launches: a term's nodes at one step
+  std::vector<DevRange> ranges;       // term launches: each term's groups, per launch
   std::vector<float> seeds;           // (re, im) per term, arena offset 0
   uint64_t leaf_work = 0;
 
@@ -105,7 +109,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path);
 
 // Byte layout of the workspace: [tables][params][values][grad][arena]
 struct WorkspaceLayout {
-  uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots, terms, groups;
+  uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots, terms, groups, ranges;
   uint64_t split, splitcnt;  // split-K partial tiles (float), arrival counters (uint32)
   uint64_t params, value, grad, arena, total;
 };
