@@ -64,7 +64,10 @@ struct LevelSeg {
   const uint32_t* tab;
   const uint32_t* item_op;  // gather item -> op index, or null (search)
   float2* arena;
-  SplitK split;             // split-K partial tiles and counters
+  SplitK split;             // split-K partial tiles
+  const DevSplitUnit* sunits;  // split-K output tiles of this level
+  uint64_t split_start;     // first split-K output tile of this segment
+  uint32_t n_split;
   uint64_t gemm_start;  // first GEMM tile of this segment
   uint64_t wave_start;  // first wave tile of this segment
   uint64_t gc_start;    // first gather item (a multiple of 64)
@@ -78,6 +81,7 @@ struct LevelArgs {
   uint32_t tile_blocks;  // k_gemm blocks [0, tile_blocks) run 64 x 64 tiles
   uint64_t gemm_tiles;
   uint64_t wave_tiles;
+  uint64_t split_units;  // split-K output tiles over all segments
   uint64_t gc_work;
 };
 
@@ -251,7 +255,7 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
 // each keeps its own register budget (the GEMM tiles' accumulators would
 // otherwise cap the gather waves' occupancy).
 template <int PREC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gemm(LevelArgs a) {
+__global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
   if (blockIdx.x >= a.tile_blocks) {
     // wave tiles: one unit per wavefront, grid-stride over the units
     const int lane = threadIdx.x & 63;
@@ -261,12 +265,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
          u < a.wave_tiles; u += waves) {
       const LevelSeg& S = a.seg[find_seg(a, u, [](const LevelSeg& s) { return s.wave_start; })];
       const uint64_t lu = u - S.wave_start;
-      const DevOp& op = S.wave_ops[find_item(S.wave_ops, S.n_wave, lu)];
-      switch ((op.flags >> 12) & 3u) {
-        case 0: wave_tile_f32<1, 1>(op, lu, S.tab, S.arena, lane, S.split); break;
-        case 1: wave_tile_f32<2, 1>(op, lu, S.tab, S.arena, lane, S.split); break;
-        case 2: wave_tile_f32<1, 2>(op, lu, S.tab, S.arena, lane, S.split); break;
-        default: wave_tile_f32<2, 2>(op, lu, S.tab, S.arena, lane, S.split); break;
+      // the unit is the same for the whole wavefront: its op index is uniform
+      const uint32_t oi = __builtin_amdgcn_readfirstlane(find_item(S.wave_ops, S.n_wave, lu));
+      const DevOp op = S.wave_ops[oi];
+      const uint32_t shape = ((op.flags >> 12) & 3u) | (op_has_tables(op) ? 4u : 0u);
+      switch (shape) {
+        case 0: wave_tile_f32<1, 1, false>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 1: wave_tile_f32<2, 1, false>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 2: wave_tile_f32<1, 2, false>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 3: wave_tile_f32<2, 2, false>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 4: wave_tile_f32<1, 1, true>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 5: wave_tile_f32<2, 1, true>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 6: wave_tile_f32<1, 2, true>(op, lu, S.tab, S.arena, lane, S.split); break;
+        default: wave_tile_f32<2, 2, true>(op, lu, S.tab, S.arena, lane, S.split); break;
       }
     }
     return;
@@ -277,8 +288,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       const LevelSeg& S =
           a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
       const uint64_t lt = tile - S.gemm_start;
-      const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
-      gemm_tile_bf16x3(op, lt, S.tab, S.arena, smem, S.split);
+      const uint32_t oi = __builtin_amdgcn_readfirstlane(find_item(S.gemm_ops, S.n_gemm, lt));
+      const DevOp op = S.gemm_ops[oi];
+      if (op_has_tables(op))
+        gemm_tile_bf16x3<true>(op, lt, S.tab, S.arena, smem, S.split);
+      else
+        gemm_tile_bf16x3<false>(op, lt, S.tab, S.arena, smem, S.split);
     }
   } else {
     __shared__ SmemF32 smem;
@@ -286,8 +301,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       const LevelSeg& S =
           a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.gemm_start; })];
       const uint64_t lt = tile - S.gemm_start;
-      const DevOp& op = S.gemm_ops[find_item(S.gemm_ops, S.n_gemm, lt)];
-      gemm_tile_f32(op, lt, S.tab, S.arena, smem, S.split);
+      const uint32_t oi = __builtin_amdgcn_readfirstlane(find_item(S.gemm_ops, S.n_gemm, lt));
+      const DevOp op = S.gemm_ops[oi];
+      if (op_has_tables(op))
+        gemm_tile_f32<true>(op, lt, S.tab, S.arena, smem, S.split);
+      else
+        gemm_tile_f32<false>(op, lt, S.tab, S.arena, smem, S.split);
+    }
+  }
+}
+
+// Split-K reduction of a level: workgroup u adds the slices of split-K
+// output tile u in slice order and stores C (a block tile with all 256
+// threads, a wave tile with the first wavefront).
+__global__ void __launch_bounds__(256) k_reduce(LevelArgs a) {
+  const uint64_t u = blockIdx.x;
+  const LevelSeg& S = a.seg[find_seg(a, u, [](const LevelSeg& s) { return s.split_start; })];
+  const DevSplitUnit su = S.sunits[u - S.split_start];
+  const DevOp op = S.gemm_ops[su.op];
+  if (su.op < S.n_gemm) {
+    f4 cr[2][2], ci[2][2];
+    sum_part_block(op, su.tile, S.split, cr, ci);
+    const TileCtx c = unit_ctx(op, (uint64_t)su.tile * op.ksplit, S.arena, BM, BN);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    store_tile(op, c, S.tab, S.arena, cr, ci, wave >> 1, wave & 1, lane);
+  } else if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    switch ((op.flags >> 12) & 3u) {
+      case 0: reduce_wave<1, 1>(op, su.tile, S.tab, S.arena, lane, S.split); break;
+      case 1: reduce_wave<2, 1>(op, su.tile, S.tab, S.arena, lane, S.split); break;
+      case 2: reduce_wave<1, 2>(op, su.tile, S.tab, S.arena, lane, S.split); break;
+      default: reduce_wave<2, 2>(op, su.tile, S.tab, S.arena, lane, S.split); break;
     }
   }
 }
@@ -614,7 +658,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
     }
     case L_LEVEL: {
       LevelArgs a{};
-      uint64_t tiles = 0, wtiles = 0, work = 0;
+      uint64_t tiles = 0, wtiles = 0, work = 0, sunits = 0;
       for (int i = 0; i < nseg; ++i) {
         const SegRef& s = segs[i];
         const WorkspaceLayout& L = *s.lay;
@@ -631,7 +675,11 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
                         ? (const uint32_t*)(s.ws + L.item_op) + s.launch->item_begin
                         : nullptr;
         g.arena = (float2*)(s.ws + L.arena);
-        g.split = SplitK{(float*)(s.ws + L.split), (uint32_t*)(s.ws + L.splitcnt)};
+        g.split = SplitK{(float*)(s.ws + L.split)};
+        g.sunits = (const DevSplitUnit*)(s.ws + L.sunits) + s.launch->sbegin;
+        g.n_split = s.launch->send - s.launch->sbegin;
+        g.split_start = sunits;
+        sunits += g.n_split;
         g.gemm_start = tiles;
         g.wave_start = wtiles;
         g.gc_start = work;
@@ -642,6 +690,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.nseg = (uint32_t)nseg;
       a.gemm_tiles = tiles;
       a.wave_tiles = wtiles;
+      a.split_units = sunits;
       a.gc_work = work;
       a.tile_blocks = (unsigned)std::min<uint64_t>(tiles, (uint64_t)n_cu * 8);
       const unsigned wvb = (unsigned)std::min<uint64_t>((wtiles + 3) / 4, (uint64_t)n_cu * 16);
@@ -652,6 +701,9 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
           hipLaunchKernelGGL(k_gemm<TC_PREC_BF16X3>, dim3(gmb), dim3(256), 0, st, a);
         else
           hipLaunchKernelGGL(k_gemm<TC_PREC_C64>, dim3(gmb), dim3(256), 0, st, a);
+        // split-K tiles: their slices are all written once k_gemm is done
+        if (a.split_units)
+          hipLaunchKernelGGL(k_reduce, dim3((unsigned)a.split_units), dim3(256), 0, st, a);
       };
       if (gmb && gcb && fork) {
         // GEMM tiles on the side stream, concurrent with the gather kernel
@@ -770,10 +822,7 @@ void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStrea
   upload(ws, lay.terms, P.terms, stream);
   upload(ws, lay.groups, P.groups, stream);
   upload(ws, lay.ranges, P.ranges, stream);
-  // split-K arrival counters start at zero; each tile's last slice resets
-  // its counter, so they are zero again after every launch
-  if (P.split_counters)
-    HIP_CHECK(hipMemsetAsync(ws + lay.splitcnt, 0, P.split_counters * sizeof(uint32_t), stream));
+  upload(ws, lay.sunits, P.split_units, stream);
   upload(ws, lay.arena, P.seeds, stream);  // seeds sit at arena offset 0
 }
 

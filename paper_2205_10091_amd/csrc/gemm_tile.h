@@ -40,6 +40,33 @@ __device__ __forceinline__ uint32_t ix(const uint32_t* __restrict__ tab, uint32_
   return off;
 }
 
+// The same without the table case: branch-free, for ops whose descriptors
+// are all runs (a branch around a table load in an unrolled loop splits it
+// into blocks, and the compiler then waits for every load at each join).
+__device__ __forceinline__ uint32_t ix_runs(uint32_t d, uint32_t i) {
+  uint32_t off = 0, src = 0;
+#pragma unroll
+  for (int r = 0; r < IX_RUNS; ++r) {
+    const uint32_t len = (d >> (10 * r)) & 31u, dst = (d >> (10 * r + 5)) & 31u;
+    off |= ((i >> src) & ((1u << len) - 1u)) << dst;
+    src += len;
+  }
+  return off;
+}
+
+// ix<TABLES>: TABLES = false for ops without table descriptors
+template <bool TABLES>
+__device__ __forceinline__ uint32_t ixt(const uint32_t* __restrict__ tab, uint32_t d, uint32_t i) {
+  if constexpr (TABLES)
+    return ix(tab, d, i);
+  else
+    return ix_runs(d, i);
+}
+
+__device__ __forceinline__ bool op_has_tables(const DevOp& op) {
+  return ((op.a_m | op.a_k | op.b_k | op.b_n | op.c_m | op.c_n) & IX_TABLE) != 0;
+}
+
 constexpr int BM = 64, BN = 64;
 constexpr int BK32 = 16;   // k per LDS stage, FP32 path
 constexpr int BK16 = 32;   // k per LDS stage, split-BF16 path
@@ -84,64 +111,6 @@ __device__ __forceinline__ TileCtx tile_ctx(const DevOp& op, uint64_t tile,
   return unit_ctx(op, tile - op.work0, arena, BM, BN);
 }
 
-// Split-K scratch of one launch: partial tiles and per-tile arrival counters.
-struct SplitK {
-  float* part;
-  uint32_t* cnt;
-};
-
-// Split-K epilogue of a 64 x 64 block tile (all 256 threads): the slice's
-// accumulators go to its partial tile (element j of thread t at j * 256 + t,
-// so every store is coalesced); the last slice of the tile to arrive adds
-// all slices in slice order (a fixed order: the result does not depend on
-// which slice came last), leaves the sum in cr / ci, resets the counter and
-// returns true.
-__device__ __forceinline__ bool split_block(const DevOp& op, const TileCtx& c, const SplitK& sk,
-                                            f4 (&cr)[2][2], f4 (&ci)[2][2], uint32_t& flag) {
-  const int t = threadIdx.x;
-  const uint32_t P = op.ksplit;
-  float* tile_part = sk.part + op.part + c.tile * P * (32 * 256);
-  float* mine = tile_part + (uint64_t)c.slice * (32 * 256);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        mine[((i * 2 + j) * 8 + v) * 256 + t] = cr[i][j][v];
-        mine[((i * 2 + j) * 8 + 4 + v) * 256 + t] = ci[i][j][v];
-      }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) flag = atomicAdd(sk.cnt + op.cnt + c.tile, 1u) == P - 1 ? 1u : 0u;
-  __syncthreads();
-  const bool last = flag != 0;
-  __syncthreads();  // every thread has read the flag before it is reused
-  if (!last) return false;
-  __threadfence();
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-      ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-  for (uint32_t q = 0; q < P; ++q) {
-    const float* src = tile_part + (uint64_t)q * (32 * 256);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          cr[i][j][v] += src[((i * 2 + j) * 8 + v) * 256 + t];
-          ci[i][j][v] += src[((i * 2 + j) * 8 + 4 + v) * 256 + t];
-        }
-  }
-  if (t == 0) sk.cnt[op.cnt + c.tile] = 0;
-  return true;
-}
-
 __device__ __forceinline__ void store_tile(const DevOp& op, const TileCtx& t,
                                            const uint32_t* __restrict__ tab,
                                            float2* __restrict__ arena, const f4 (&cr)[2][2],
@@ -160,17 +129,72 @@ __device__ __forceinline__ void store_tile(const DevOp& op, const TileCtx& t,
       }
 }
 
+// Split-K partial tiles of one launch (floats).  A slice of a tile writes
+// its accumulators there with plain stores; the level's k_reduce kernel,
+// launched after the GEMM kernel, adds the slices of every tile in slice
+// order and stores C.  The kernel boundary between them makes the partial
+// tiles visible, so no slice waits, fences or counts arrivals.
+struct SplitK {
+  float* part;
+};
+
+// Block tile: element j of thread t at j * 256 + t of the slice's partial
+// tile (coalesced), j = (block * 2 + re/im) * 4 + v over the 2 x 2 blocks.
+__device__ __forceinline__ void write_part_block(const DevOp& op, const TileCtx& c,
+                                                 const SplitK& sk, const f4 (&cr)[2][2],
+                                                 const f4 (&ci)[2][2]) {
+  const int t = threadIdx.x;
+  float* mine = sk.part + op.part + (c.tile * op.ksplit + c.slice) * (32 * 256);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        mine[((i * 2 + j) * 8 + v) * 256 + t] = cr[i][j][v];
+        mine[((i * 2 + j) * 8 + 4 + v) * 256 + t] = ci[i][j][v];
+      }
+}
+
+// the sum over slices 0, 1, ... of a block tile's partials (same layout)
+__device__ __forceinline__ void sum_part_block(const DevOp& op, uint64_t tile, const SplitK& sk,
+                                               f4 (&cr)[2][2], f4 (&ci)[2][2]) {
+  const int t = threadIdx.x;
+  const float* base = sk.part + op.part + tile * op.ksplit * (32 * 256);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (uint32_t q = 0; q < op.ksplit; ++q) {
+    const float* src = base + (uint64_t)q * (32 * 256);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cr[i][j][v] += src[((i * 2 + j) * 8 + v) * 256 + t];
+          ci[i][j][v] += src[((i * 2 + j) * 8 + 4 + v) * 256 + t];
+        }
+  }
+}
+
 // ------------------------------------------------------------------ FP32
 
 struct SmemF32 {
   float A[2][BK32][BM + PAD];  // [re/im][k][m]
   float B[2][BK32][BN + PAD];  // [re/im][k][n]
-  uint32_t flag;               // split-K: this block holds the tile's last slice
 };
 
 // One 64 x 64 tile of C (or one K slice of it) for the FP32 path; called by
-// all 256 threads.
-__device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
+// all 256 threads.  The op record is taken by value: held in registers, it
+// is not reloaded from memory after every barrier of the k loop (a reload
+// would wait for the prefetched operands too).
+template <bool TABLES>
+__device__ __forceinline__ void gemm_tile_f32(const DevOp op, uint64_t tile,
                                               const uint32_t* __restrict__ tab,
                                               float2* __restrict__ arena, SmemF32& S,
                                               const SplitK& sk) {
@@ -206,13 +230,27 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
     // the current tile's MFMAs run
     float2 pa[4], pb[4];
     auto fetch = [&](uint32_t k0) {
+      // every index first, then every load: a wait for an index-table entry
+      // must not also wait for operand loads already in flight
+      uint32_t ka[4], kb[4];
+      bool va[4], vb[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         // A element (m, k): k fastest across threads when A is k-contiguous
-        uint32_t k = k0 + (akf ? (t & 15) : (t >> 6) + 4 * p);
-        pa[p] = (aok[p] && k < c.ke) ? c.A[aoff[p] + ix(tab, op.a_k, k)] : make_float2(0.f, 0.f);
-        k = k0 + (bkf ? (t & 15) : (t >> 6) + 4 * p);
-        pb[p] = (bok[p] && k < c.ke) ? c.B[boff[p] + ix(tab, op.b_k, k)] : make_float2(0.f, 0.f);
+        const uint32_t k = k0 + (akf ? (t & 15) : (t >> 6) + 4 * p);
+        va[p] = aok[p] && k < c.ke;
+        ka[p] = va[p] ? aoff[p] + ixt<TABLES>(tab, op.a_k, k) : 0u;
+        const uint32_t kk = k0 + (bkf ? (t & 15) : (t >> 6) + 4 * p);
+        vb[p] = bok[p] && kk < c.ke;
+        kb[p] = vb[p] ? boff[p] + ixt<TABLES>(tab, op.b_k, kk) : 0u;
+      }
+      // unconditional loads (an invalid element reads the operand's first
+      // entry and is zeroed), so that the loads issue back to back
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const float2 x = c.A[ka[p]], y = c.B[kb[p]];
+        pa[p] = va[p] ? x : make_float2(0.f, 0.f);
+        pb[p] = vb[p] ? y : make_float2(0.f, 0.f);
       }
     };
     fetch(c.kb);
@@ -254,7 +292,10 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
       }
       __syncthreads();
     }
-    if (op.ksplit > 1 && !split_block(op, c, sk, cr, ci, S.flag)) return;
+    if (op.ksplit > 1) {
+      write_part_block(op, c, sk, cr, ci);
+      return;
+    }
     store_tile(op, c, tab, arena, cr, ci, wm, wn, lane);
   }
 }
@@ -268,8 +309,27 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp& op, uint64_t tile,
 // barrier.  This is the form for nodes too narrow for 64 x 64 tiles (M or
 // N below 64, as in per-row batched contractions), where a block tile
 // would mostly multiply padding.  K is a power of two >= 4.
+// C of a wave tile: lane l holds C[m0 + 16 bi + 4 (l / 16) + v][n0 + 16 bj + l % 16]
 template <int BI, int BJ>
-__device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
+__device__ __forceinline__ void store_wave(const DevOp& op, const TileCtx& c,
+                                           const uint32_t* __restrict__ tab,
+                                           float2* __restrict__ arena, const f4 (&cr)[BI][BJ],
+                                           const f4 (&ci)[BI][BJ], int lane) {
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t cm = ix(tab, op.c_m, c.m0 + bi * 16 + 4 * kq + v);
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj)
+        arena[c.cbase + cm + ix(tab, op.c_n, c.n0 + bj * 16 + i)] =
+            make_float2(cr[bi][bj][v], ci[bi][bj][v]);
+    }
+}
+
+template <int BI, int BJ, bool TABLES>
+__device__ __forceinline__ void wave_tile_f32(const DevOp op, uint64_t unit,
                                               const uint32_t* __restrict__ tab,
                                               float2* __restrict__ arena, int lane,
                                               const SplitK& sk) {
@@ -310,8 +370,8 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
     uint32_t ka[U], kb[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ka[u] = ix(tab, op.a_k, 4 * (s + u) + kq);
-      kb[u] = ix(tab, op.b_k, 4 * (s + u) + kq);
+      ka[u] = ixt<TABLES>(tab, op.a_k, 4 * (s + u) + kq);
+      kb[u] = ixt<TABLES>(tab, op.b_k, 4 * (s + u) + kq);
     }
     float2 av[U][BI], bv[U][BJ];
 #pragma unroll
@@ -325,7 +385,7 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
     for (int u = 0; u < U; ++u) step(av[u], bv[u]);
   }
   for (; s < steps; ++s) {
-    const uint32_t ka = ix(tab, op.a_k, 4 * s + kq), kb = ix(tab, op.b_k, 4 * s + kq);
+    const uint32_t ka = ixt<TABLES>(tab, op.a_k, 4 * s + kq), kb = ixt<TABLES>(tab, op.b_k, 4 * s + kq);
     float2 av[BI], bv[BJ];
 #pragma unroll
     for (int bi = 0; bi < BI; ++bi) av[bi] = A[am[bi] + ka];
@@ -334,13 +394,9 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
     step(av, bv);
   }
   if (op.ksplit > 1) {
-    // split-K epilogue of one wavefront: element j of lane l at j * 64 + l
-    // of the slice's partial tile; the last slice of the tile to arrive adds
-    // all slices in slice order and stores
+    // element j of lane l at j * 64 + l of the slice's partial tile
     constexpr int NF = 8 * BI * BJ;
-    const uint32_t P = op.ksplit;
-    float* tile_part = sk.part + op.part + c.tile * P * (NF * 64);
-    float* mine = tile_part + (uint64_t)c.slice * (NF * 64);
+    float* mine = sk.part + op.part + (c.tile * op.ksplit + c.slice) * (NF * 64);
 #pragma unroll
     for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
@@ -350,44 +406,42 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp& op, uint64_t unit,
           mine[((bi * BJ + bj) * 8 + v) * 64 + lane] = cr[bi][bj][v];
           mine[((bi * BJ + bj) * 8 + 4 + v) * 64 + lane] = ci[bi][bj][v];
         }
-    __threadfence();
-    uint32_t prev = 0;
-    if (lane == 0) prev = atomicAdd(sk.cnt + op.cnt + c.tile, 1u);
-    prev = __shfl(prev, 0, 64);
-    if (prev != P - 1) return;
-    __threadfence();
-#pragma unroll
-    for (int bi = 0; bi < BI; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < BJ; ++bj) {
-        cr[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
-        ci[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
-      }
-    for (uint32_t q = 0; q < P; ++q) {
-      const float* src = tile_part + (uint64_t)q * (NF * 64);
-#pragma unroll
-      for (int bi = 0; bi < BI; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < BJ; ++bj)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            cr[bi][bj][v] += src[((bi * BJ + bj) * 8 + v) * 64 + lane];
-            ci[bi][bj][v] += src[((bi * BJ + bj) * 8 + 4 + v) * 64 + lane];
-          }
-    }
-    if (lane == 0) sk.cnt[op.cnt + c.tile] = 0;
+    return;
   }
-  const uint64_t cb = c.cbase;
+  store_wave<BI, BJ>(op, c, tab, arena, cr, ci, lane);
+}
+
+// the sum over slices 0, 1, ... of a wave tile's partials (layout as written
+// by wave_tile_f32), then the store
+template <int BI, int BJ>
+__device__ __forceinline__ void reduce_wave(const DevOp op, uint64_t tile,
+                                            const uint32_t* __restrict__ tab,
+                                            float2* __restrict__ arena, int lane,
+                                            const SplitK& sk) {
+  constexpr int NF = 8 * BI * BJ;
+  const TileCtx c = unit_ctx(op, tile * op.ksplit, arena, 16 * BI, 16 * BJ);
+  f4 cr[BI][BJ], ci[BI][BJ];
 #pragma unroll
   for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const uint32_t cm = ix(tab, op.c_m, m0 + bi * 16 + 4 * kq + v);
+    for (int bj = 0; bj < BJ; ++bj) {
+      cr[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+      ci[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  const float* base = sk.part + op.part + tile * op.ksplit * (NF * 64);
+  for (uint32_t q = 0; q < op.ksplit; ++q) {
+    const float* src = base + (uint64_t)q * (NF * 64);
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
       for (int bj = 0; bj < BJ; ++bj)
-        arena[cb + cm + ix(tab, op.c_n, n0 + bj * 16 + i)] =
-            make_float2(cr[bi][bj][v], ci[bi][bj][v]);
-    }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cr[bi][bj][v] += src[((bi * BJ + bj) * 8 + v) * 64 + lane];
+          ci[bi][bj][v] += src[((bi * BJ + bj) * 8 + 4 + v) * 64 + lane];
+        }
+  }
+  store_wave<BI, BJ>(op, c, tab, arena, cr, ci, lane);
 }
 
 // ------------------------------------------------------------------ BF16X3
@@ -401,12 +455,12 @@ struct SmemBF16 {
   // [re/im][hi/lo][row][k], k contiguous so that a lane reads 8 k at once
   __attribute__((aligned(16))) __bf16 A[2][2][BM][BK16 + 8];
   __attribute__((aligned(16))) __bf16 B[2][2][BN][BK16 + 8];
-  uint32_t flag;  // split-K: this block holds the tile's last slice
 };
 
 // One 64 x 64 tile of C (or one K slice of it) for the split-BF16 path;
 // called by all 256 threads.
-__device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
+template <bool TABLES>
+__device__ __forceinline__ void gemm_tile_bf16x3(const DevOp op, uint64_t tile,
                                                  const uint32_t* __restrict__ tab,
                                                  float2* __restrict__ arena, SmemBF16& S,
                                                  const SplitK& sk) {
@@ -439,22 +493,35 @@ __device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
         ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       }
     for (uint32_t k0 = c.kb; k0 < c.ke; k0 += BK16) {
+      // every index, then every load, then the LDS stores (as in the FP32 tile)
+      uint32_t ka[8], kb[8];
+      bool va[8], vb[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const uint32_t k = k0 + (akf ? (t & 31) : (t >> 6) + 4 * p);
+        va[p] = aok[p] && k < c.ke;
+        ka[p] = va[p] ? aoff[p] + ixt<TABLES>(tab, op.a_k, k) : 0u;
+        const uint32_t kk = k0 + (bkf ? (t & 31) : (t >> 6) + 4 * p);
+        vb[p] = bok[p] && kk < c.ke;
+        kb[p] = vb[p] ? boff[p] + ixt<TABLES>(tab, op.b_k, kk) : 0u;
+      }
+      float2 av[8], bv[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const float2 x = c.A[ka[p]], y = c.B[kb[p]];
+        av[p] = va[p] ? x : make_float2(0.f, 0.f);
+        bv[p] = vb[p] ? y : make_float2(0.f, 0.f);
+      }
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         int kk = akf ? (t & 31) : (t >> 6) + 4 * p;
         int mm = akf ? (t >> 5) + 8 * p : (t & 63);
-        uint32_t k = k0 + kk;
-        float2 v = make_float2(0.f, 0.f);
-        if (aok[p] && k < c.ke) v = c.A[aoff[p] + ix(tab, op.a_k, k)];
-        split_bf16(v.x, As[0][0][mm][kk], As[0][1][mm][kk]);
-        split_bf16(v.y, As[1][0][mm][kk], As[1][1][mm][kk]);
+        split_bf16(av[p].x, As[0][0][mm][kk], As[0][1][mm][kk]);
+        split_bf16(av[p].y, As[1][0][mm][kk], As[1][1][mm][kk]);
         kk = bkf ? (t & 31) : (t >> 6) + 4 * p;
         int nn = bkf ? (t >> 5) + 8 * p : (t & 63);
-        k = k0 + kk;
-        v = make_float2(0.f, 0.f);
-        if (bok[p] && k < c.ke) v = c.B[boff[p] + ix(tab, op.b_k, k)];
-        split_bf16(v.x, Bs[0][0][nn][kk], Bs[0][1][nn][kk]);
-        split_bf16(v.y, Bs[1][0][nn][kk], Bs[1][1][nn][kk]);
+        split_bf16(bv[p].x, Bs[0][0][nn][kk], Bs[0][1][nn][kk]);
+        split_bf16(bv[p].y, Bs[1][0][nn][kk], Bs[1][1][nn][kk]);
       }
       __syncthreads();
       const int kr = 8 * (lane >> 4);
@@ -495,7 +562,10 @@ __device__ __forceinline__ void gemm_tile_bf16x3(const DevOp& op, uint64_t tile,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) cr[i][j] = pr[i][j] - pq[i][j];
-    if (op.ksplit > 1 && !split_block(op, c, sk, cr, ci, S.flag)) return;
+    if (op.ksplit > 1) {
+      write_part_block(op, c, sk, cr, ci);
+      return;
+    }
     store_tile(op, c, tab, arena, cr, ci, wm, wn, lane);
   }
 }

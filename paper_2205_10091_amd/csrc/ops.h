@@ -42,11 +42,17 @@ struct DevOp {
   uint32_t tiles_m, tiles_n;  // GEMM path: tile grid per batch row
   uint32_t flags;          // bit 0: A is k-contiguous; bit 1: B is k-contiguous
   // GEMM split-K: K is cut into ksplit slices (1 = none); slice results go
-  // to partial tiles from float `part` of the split region, and the tiles'
-  // arrival counters start at `cnt` in the counter region
+  // to partial tiles from float `part` of the split region
   uint64_t part;
-  uint32_t cnt;
   uint32_t ksplit;
+};
+
+// One output tile of a split-K GEMM op for the reduction kernel: the op
+// (index among the level's GEMM ops, block tiles first, then wave tiles)
+// and the tile within it.
+struct DevSplitUnit {
+  uint32_t op;
+  uint32_t tile;
 };
 
 // Term launches: one workgroup runs one term's nodes over a run of steps.

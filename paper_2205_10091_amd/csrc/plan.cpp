@@ -463,7 +463,7 @@ WorkspaceLayout workspace_layout(const Plan& p) {
   w.groups = o; o = al(o + p.groups.size() * sizeof(DevGroup));
   w.ranges = o; o = al(o + p.ranges.size() * sizeof(DevRange));
   w.split = o; o = al(o + p.split_floats * sizeof(float));
-  w.splitcnt = o; o = al(o + p.split_counters * sizeof(uint32_t));
+  w.sunits = o; o = al(o + p.split_units.size() * sizeof(DevSplitUnit));
   w.params = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(float));
   w.value = o; o = al(o + (uint64_t)p.batch * 2 * sizeof(double));
   w.grad = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(double));
@@ -678,6 +678,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       for (int32_t l : A.legs) (pb[l] >= 0 ? Sh : FA).push_back(l);
       for (int32_t l : Bt.legs)
         if (pa[l] < 0) FB.push_back(l);
+      // Coalescing: an operand reads contiguously along m (n) when its
+      // fastest leg is free and along k when its fastest leg is the last
+      // contracted index.  A's fastest leg is one or the other; when it is
+      // free, the contracted legs follow B's order so that B's fastest leg,
+      // if contracted, becomes the last contracted index.
+      if (!A.legs.empty() && pb[A.legs.back()] < 0)
+        std::sort(Sh.begin(), Sh.end(), [&](int32_t x, int32_t y) { return pb[x] < pb[y]; });
       DevOp op{};
       op.ksplit = 1;
       op.a = (uint64_t)A.off;
@@ -754,10 +761,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.gemm_bytes = gb;
     // split-K: a GEMM node with too few output tiles to fill the chip (256
     // CUs) cuts K into slices of at least 64; each slice writes a partial
-    // tile and the last slice of a tile to arrive sums them in slice order.
-    // The partial tiles and counters of one level reuse the same regions as
-    // every other level's (levels never overlap).
-    uint64_t part = 0, cnt = 0;
+    // tile and the level's reduction kernel adds them in slice order.  The
+    // partial tiles of one level reuse the region of every other level's
+    // (levels never overlap).
+    uint64_t part = 0;
+    L.gbegin = (uint32_t)plan.ops.size();
+    L.sbegin = (uint32_t)plan.split_units.size();
     auto split = [&](DevOp& op, uint64_t target_units, uint64_t floats_per_tile) {
       const uint64_t base = (uint64_t)op.rows * op.tiles_m * op.tiles_n;
       uint32_t P = 1;
@@ -765,13 +774,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       op.ksplit = P;
       if (P > 1) {
         op.part = part;
-        op.cnt = (uint32_t)cnt;
         part += base * P * floats_per_tile;
-        cnt += base;
+        const uint32_t rel = (uint32_t)(plan.ops.size() - L.gbegin);  // op's index in the level
+        for (uint64_t t = 0; t < base; ++t) plan.split_units.push_back({rel, (uint32_t)t});
       }
       return base * P;
     };
-    L.gbegin = (uint32_t)plan.ops.size();
     uint64_t tiles = 0;
     for (DevOp& op : gm) {
       op.work0 = tiles;
@@ -788,9 +796,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       wtiles += split(op, 2048, 8 * blocks * 64);  // 8 accumulators per 16x16 block and lane
       plan.ops.push_back(op);
     }
-    if (cnt > 0xFFFFFFFFull) fail(TC_ERR_TOO_LARGE, "too many split-K tiles in one level");
     plan.split_floats = std::max(plan.split_floats, part);
-    plan.split_counters = std::max(plan.split_counters, cnt);
+    L.send = (uint32_t)plan.split_units.size();
     L.wend = (uint32_t)plan.ops.size();
     L.wtiles = wtiles;
     L.begin = (uint32_t)plan.ops.size();
@@ -997,10 +1004,18 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
             fail(TC_ERR_INVALID_ARG, "internal: GEMM tile grid does not match the node");
           if (op.ksplit == 1) continue;
           const uint64_t base = (uint64_t)op.rows * op.tiles_m * op.tiles_n;
-          if (op.cnt + base > plan.split_counters ||
-              op.part + base * op.ksplit * fpt > plan.split_floats ||
+          if (op.part + base * op.ksplit * fpt > plan.split_floats ||
               (wave && (op.K / op.ksplit) % 4 != 0))
             fail(TC_ERR_INVALID_ARG, "internal: split-K tiles out of range");
+        }
+        if (L.sbegin > L.send || L.send > plan.split_units.size())
+          fail(TC_ERR_INVALID_ARG, "internal: split-K units out of range");
+        for (uint32_t u = L.sbegin; u < L.send; ++u) {
+          const DevSplitUnit su = plan.split_units[u];
+          if (su.op >= L.wend - L.gbegin) fail(TC_ERR_INVALID_ARG, "internal: split unit op");
+          const DevOp& op = plan.ops[L.gbegin + su.op];
+          if (op.ksplit < 2 || su.tile >= (uint64_t)op.rows * op.tiles_m * op.tiles_n)
+            fail(TC_ERR_INVALID_ARG, "internal: split unit tile");
         }
       }
     // term mode: groups name contiguous op ranges whose items cover the ops,

@@ -42,6 +42,7 @@ struct Launch {
   uint64_t tiles = 0;             // 64 x 64 GEMM tiles
   uint32_t wbegin = 0, wend = 0;  // GEMM ops in wave tiles, in Plan::ops
   uint64_t wtiles = 0;            // wave tiles
+  uint32_t sbegin = 0, send = 0;  // split-K output tiles, in Plan::split_units
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
   bool with_leaves = false;       // L_TERM: materialise the leaves first
   double flops = 0;               // algorithmic flops (8 per complex MAC)
@@ -88,6 +89,7 @@ struct Plan {
   std::vector<DevTerm> terms;         // term launches: each term's leaves
   std::vector<DevGroup> groups;       // term launches: a term's nodes at one step
   std::vector<DevRange> ranges;       // term launches: each term's groups, per launch
+  std::vector<DevSplitUnit> split_units;  // split-K output tiles, per level
   std::vector<float> seeds;           // (re, im) per term, arena offset 0
   uint64_t leaf_work = 0;
 
@@ -95,7 +97,6 @@ struct Plan {
   std::vector<Launch> bwd;            // adjoint levels, grad
   uint64_t arena_elems = 0;           // complex64 elements
   uint64_t split_floats = 0;          // split-K partial tiles of the largest level
-  uint64_t split_counters = 0;        // split-K output tiles of the largest level
   uint64_t peak_tensor_elems = 0;
 
   tc_plan_info info{};
@@ -110,7 +111,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path);
 // Byte layout of the workspace: [tables][params][values][grad][arena]
 struct WorkspaceLayout {
   uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots, terms, groups, ranges;
-  uint64_t split, splitcnt;  // split-K partial tiles (float), arrival counters (uint32)
+  uint64_t split, sunits;  // split-K partial tiles (float), output tiles to reduce
   uint64_t params, value, grad, arena, total;
 };
 WorkspaceLayout workspace_layout(const Plan& p);
