@@ -168,7 +168,7 @@ __device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
 // j < V, accumulated in increasing k.  U steps are issued together so that
 // their table and operand loads overlap instead of forming one dependent
 // chain per step.
-template <int V>
+template <int V, bool TABLES>
 __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restrict__ A,
                                            const float2* __restrict__ Bp,
                                            const uint32_t* __restrict__ tab, uint32_t ak,
@@ -181,8 +181,8 @@ __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restri
     uint32_t ia[U], ib[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ia[u] = ix(tab, ak, k + u * S);
-      ib[u] = ix(tab, bk, k + u * S);
+      ia[u] = ixt<TABLES>(tab, ak, k + u * S);
+      ib[u] = ixt<TABLES>(tab, bk, k + u * S);
     }
     float2 av[U], bv[U][V];
 #pragma unroll
@@ -197,8 +197,8 @@ __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restri
       for (int j = 0; j < V; ++j) cfma(acc[j], av[u], bv[u][j]);
   }
   for (; k < K; k += S) {
-    const float2 av = A[ix(tab, ak, k)];
-    const float2* __restrict__ bb = Bp + ix(tab, bk, k);
+    const float2 av = A[ixt<TABLES>(tab, ak, k)];
+    const float2* __restrict__ bb = Bp + ixt<TABLES>(tab, bk, k);
 #pragma unroll
     for (int j = 0; j < V; ++j) cfma(acc[j], av, bb[bn[j]]);
   }
@@ -344,10 +344,12 @@ __global__ void __launch_bounds__(256) k_reduce(LevelArgs a) {
 // of such a wave runs the same shuffles.
 // Gather item l of op (item layout above).  All lanes of a wavefront call
 // this together (the k-split combines across lanes); `has` = false makes
-// the call a no-op that still joins the shuffles.
-__device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool has,
-                                            const uint32_t* __restrict__ tab,
-                                            float2* __restrict__ arena) {
+// the call a no-op that still joins the shuffles.  TABLES: the op has an
+// index table (else every index is computed, branch-free).
+template <bool TABLES>
+__device__ __forceinline__ void gather_item_t(const DevOp& op, uint64_t l, bool has,
+                                              const uint32_t* __restrict__ tab,
+                                              float2* __restrict__ arena) {
   const uint32_t ls = has ? (op.flags >> 4) & 7u : 0u;
   const uint32_t lv = has ? (op.flags >> 8) & 3u : 0u;
   const uint32_t S = 1u << ls, V = 1u << lv;
@@ -368,17 +370,17 @@ __device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool ha
     n0 = (uint32_t)(e & ((1u << ln) - 1)) << lv;
     m = (uint32_t)((e >> ln) & (op.M - 1));
     r = e >> (ln + lm);
-    const float2* __restrict__ A = arena + op.a + r * op.a_bs + ix(tab, op.a_m, m);
+    const float2* __restrict__ A = arena + op.a + r * op.a_bs + ixt<TABLES>(tab, op.a_m, m);
     const float2* __restrict__ Bp = arena + op.b + r * op.b_bs;
     uint32_t bn[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? ix(tab, op.b_n, n0 + j) : 0u;
+    for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? ixt<TABLES>(tab, op.b_n, n0 + j) : 0u;
     if (V == 4)
-      gather_dot<4>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
+      gather_dot<4, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
     else if (V == 2)
-      gather_dot<2>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
+      gather_dot<2, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
     else
-      gather_dot<1>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
+      gather_dot<1, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
   }
   if (S > 1) {
     // V == 1 whenever S > 1
@@ -388,11 +390,20 @@ __device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool ha
     }
   }
   if (valid && sub == 0) {
-    const uint64_t cb = op.c + r * op.c_bs + ix(tab, op.c_m, m);
+    const uint64_t cb = op.c + r * op.c_bs + ixt<TABLES>(tab, op.c_m, m);
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j)
-      if (j < V) arena[cb + ix(tab, op.c_n, n0 + j)] = make_float2(acc[j].re, acc[j].im);
+      if (j < V) arena[cb + ixt<TABLES>(tab, op.c_n, n0 + j)] = make_float2(acc[j].re, acc[j].im);
   }
+}
+
+__device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool has,
+                                            const uint32_t* __restrict__ tab,
+                                            float2* __restrict__ arena) {
+  if (has && op_has_tables(op))
+    gather_item_t<true>(op, l, has, tab, arena);
+  else
+    gather_item_t<false>(op, l, has, tab, arena);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_gather(LevelArgs a) {
