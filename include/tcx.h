@@ -323,6 +323,8 @@ typedef struct {
   int32_t exec_mode;         /* 1 level launches only, 2 term launches
                                 only, 3 both                             */
   int32_t n_split_nodes;     /* GEMM nodes whose K is cut into slices    */
+  int32_t n_split_sums;      /* gather nodes (long sums, few outputs)
+                                whose K is cut into slices               */
 } tc_plan_info;
 
 tc_status tc_plan_info_get(const tc_plan* plan, tc_plan_info* out);

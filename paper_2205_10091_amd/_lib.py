@@ -83,7 +83,7 @@ class PlanInfo(C.Structure):
                 ("n_grad_launches", C.c_int32), ("batch", C.c_int32),
                 ("n_params", C.c_int32), ("n_terms", C.c_int32),
                 ("checkpoint_every", C.c_int32), ("exec_mode", C.c_int32),
-                ("n_split_nodes", C.c_int32)]
+                ("n_split_nodes", C.c_int32), ("n_split_sums", C.c_int32)]
 
 
 class ServeOpts(C.Structure):

@@ -68,6 +68,12 @@ struct LevelSeg {
   const DevSplitUnit* sunits;  // split-K output tiles of this level
   uint64_t split_start;     // first split-K output tile of this segment
   uint32_t n_split;
+  const DevOp* gs_ops;      // split gather ops (V == 1), in their own work space
+  uint64_t gs_start;        // first split gather item of this segment
+  uint32_t n_gs;
+  const DevSplitUnit* gsunits;  // their outputs, 256 a unit (op relative to gs_ops)
+  uint64_t gsplit_start;
+  uint32_t n_gsplit;
   uint64_t gemm_start;  // first GEMM tile of this segment
   uint64_t wave_start;  // first wave tile of this segment
   uint64_t gc_start;    // first gather item (a multiple of 64)
@@ -82,7 +88,9 @@ struct LevelArgs {
   uint64_t gemm_tiles;
   uint64_t wave_tiles;
   uint64_t split_units;  // split-K output tiles over all segments
+  uint64_t gsplit_units;  // split gather units over all segments
   uint64_t gc_work;
+  uint64_t gs_work;       // split gather items over all segments
 };
 
 struct RootSeg {
@@ -164,19 +172,19 @@ __device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
   acc.im = fmaf(a.y, b.x, acc.im);
 }
 
-// acc[j] += sum over k = sub, sub + S, ... < K of A[ak(k)] * B[bk(k) + bn[j]],
-// j < V, accumulated in increasing k.  U steps are issued together so that
-// their table and operand loads overlap instead of forming one dependent
-// chain per step.
+// acc[j] += sum over k = kb + sub, kb + sub + S, ... < K of
+// A[ak(k)] * B[bk(k) + bn[j]], j < V, accumulated in increasing k.  U steps
+// are issued together so that their table and operand loads overlap instead
+// of forming one dependent chain per step.
 template <int V, bool TABLES>
 __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restrict__ A,
                                            const float2* __restrict__ Bp,
                                            const uint32_t* __restrict__ tab, uint32_t ak,
                                            uint32_t bk,
                                            const uint32_t (&bn)[4], uint32_t sub, uint32_t S,
-                                           uint32_t K) {
+                                           uint32_t kb, uint32_t K) {
   constexpr int U = V == 4 ? 2 : (V == 2 ? 4 : 8);  // about 90 VGPRs: 5 waves per SIMD
-  uint32_t k = sub;
+  uint32_t k = kb + sub;
   for (; k + (U - 1) * S < K; k += U * S) {
     uint32_t ia[U], ib[U];
 #pragma unroll
@@ -346,41 +354,59 @@ __global__ void __launch_bounds__(256) k_reduce(LevelArgs a) {
 // this together (the k-split combines across lanes); `has` = false makes
 // the call a no-op that still joins the shuffles.  TABLES: the op has an
 // index table (else every index is computed, branch-free).
-template <bool TABLES>
+template <bool TABLES, bool SPLIT>
 __device__ __forceinline__ void gather_item_t(const DevOp& op, uint64_t l, bool has,
                                               const uint32_t* __restrict__ tab,
-                                              float2* __restrict__ arena) {
+                                              float2* __restrict__ arena,
+                                              float* __restrict__ part) {
   const uint32_t ls = has ? (op.flags >> 4) & 7u : 0u;
   const uint32_t lv = has ? (op.flags >> 8) & 3u : 0u;
   const uint32_t S = 1u << ls, V = 1u << lv;
   bool valid = false;
   uint64_t e = 0;
   uint32_t sub = 0, ln = 0, lm = 0;
+  // split sums (ksplit > 1): item group e covers slice e / G of output
+  // group e % G, over k in [slice K / P, (slice + 1) K / P); its partial
+  // sum is entry e of the op's partials ([slice][output group])
+  uint32_t kb = 0, ke = 0;
+  uint64_t eo = 0;  // output group
   if (has) {
     ln = __builtin_ctz(op.N) - lv;
     lm = __builtin_ctz(op.M);
     e = l >> ls;
     sub = (uint32_t)(l & (S - 1));
-    valid = e < ((uint64_t)op.rows << (ln + lm));
+    const uint64_t G = (uint64_t)op.rows << (ln + lm);
+    valid = e < (SPLIT ? G * op.ksplit : G);
+    ke = op.K;
+    eo = e;
+    if (SPLIT && valid) {
+      const uint32_t slice = (uint32_t)(e / G);
+      eo = e - (uint64_t)slice * G;
+      const uint32_t ks = op.K / op.ksplit;
+      kb = slice * ks;
+      ke = kb + ks;
+    }
   }
   c32 acc[4] = {cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f)};
   uint32_t m = 0, n0 = 0;
   uint64_t r = 0;
   if (valid) {
-    n0 = (uint32_t)(e & ((1u << ln) - 1)) << lv;
-    m = (uint32_t)((e >> ln) & (op.M - 1));
-    r = e >> (ln + lm);
+    n0 = (uint32_t)(eo & ((1u << ln) - 1)) << lv;
+    m = (uint32_t)((eo >> ln) & (op.M - 1));
+    r = eo >> (ln + lm);
     const float2* __restrict__ A = arena + op.a + r * op.a_bs + ixt<TABLES>(tab, op.a_m, m);
     const float2* __restrict__ Bp = arena + op.b + r * op.b_bs;
     uint32_t bn[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? ixt<TABLES>(tab, op.b_n, n0 + j) : 0u;
-    if (V == 4)
-      gather_dot<4, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
+    if (SPLIT)  // split ops have V == 1
+      gather_dot<1, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
+    else if (V == 4)
+      gather_dot<4, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
     else if (V == 2)
-      gather_dot<2, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
+      gather_dot<2, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
     else
-      gather_dot<1, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, op.K);
+      gather_dot<1, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
   }
   if (S > 1) {
     // V == 1 whenever S > 1
@@ -389,7 +415,9 @@ __device__ __forceinline__ void gather_item_t(const DevOp& op, uint64_t l, bool 
       acc[0].im += __shfl_xor(acc[0].im, (int)off, 64);
     }
   }
-  if (valid && sub == 0) {
+  if (SPLIT && valid && sub == 0) {
+    reinterpret_cast<float2*>(part + op.part)[e] = make_float2(acc[0].re, acc[0].im);
+  } else if (valid && sub == 0) {
     const uint64_t cb = op.c + r * op.c_bs + ixt<TABLES>(tab, op.c_m, m);
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j)
@@ -397,49 +425,89 @@ __device__ __forceinline__ void gather_item_t(const DevOp& op, uint64_t l, bool 
   }
 }
 
+// An unsplit gather op's item.
 __device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool has,
                                             const uint32_t* __restrict__ tab,
                                             float2* __restrict__ arena) {
   if (has && op_has_tables(op))
-    gather_item_t<true>(op, l, has, tab, arena);
+    gather_item_t<true, false>(op, l, has, tab, arena, nullptr);
   else
-    gather_item_t<false>(op, l, has, tab, arena);
+    gather_item_t<false, false>(op, l, has, tab, arena, nullptr);
 }
 
+// Split gather sums of a level: workgroup u adds, for up to 256 output
+// groups of one split op, its slices in slice order and stores C.
+__global__ void __launch_bounds__(256) k_reduce_g(LevelArgs a) {
+  const uint64_t u = blockIdx.x;
+  const LevelSeg& S = a.seg[find_seg(a, u, [](const LevelSeg& s) { return s.gsplit_start; })];
+  const DevSplitUnit su = S.gsunits[u - S.gsplit_start];
+  const DevOp& op = S.gs_ops[su.op];
+  const uint32_t ln = __builtin_ctz(op.N), lm = __builtin_ctz(op.M);  // V == 1
+  const uint64_t G = (uint64_t)op.rows << (ln + lm);
+  const uint64_t e = (uint64_t)su.tile * 256 + threadIdx.x;
+  if (e >= G) return;
+  const float2* src = reinterpret_cast<const float2*>(S.split.part + op.part) + e;
+  c32 acc = cx(0.f, 0.f);
+  for (uint32_t q = 0; q < op.ksplit; ++q) {
+    const float2 v = src[q * G];
+    acc.re += v.x;
+    acc.im += v.y;
+  }
+  const uint32_t n = (uint32_t)(e & (op.N - 1));
+  const uint32_t m = (uint32_t)((e >> ln) & (op.M - 1));
+  const uint64_t r = e >> (ln + lm);
+  S.arena[op.c + r * op.c_bs + ix(S.tab, op.c_m, m) + ix(S.tab, op.c_n, n)] =
+      make_float2(acc.re, acc.im);
+}
+
+// Gather ops of a level; SPLIT: the split ones (their own kernel, so that
+// the split bookkeeping takes no registers from the others).
+template <bool SPLIT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_gather(LevelArgs a) {
   // each block takes one contiguous chunk (a multiple of 256 items, so
   // wavefronts never straddle its end); a thread finds its segment and op
   // once (or reads it from the per-item table) and then only walks forward
+  const uint64_t total = SPLIT ? a.gs_work : a.gc_work;
   const uint64_t nblk = gridDim.x;
-  const uint64_t chunk = (((a.gc_work + nblk - 1) / nblk) + 255) & ~uint64_t(255);
+  const uint64_t chunk = (((total + nblk - 1) / nblk) + 255) & ~uint64_t(255);
   const uint64_t begin = (uint64_t)blockIdx.x * chunk;
-  const uint64_t end = begin + chunk < a.gc_work ? begin + chunk : a.gc_work;
+  const uint64_t end = begin + chunk < total ? begin + chunk : total;
   uint32_t si = 0xffffffffu, oi = 0xffffffffu;
   for (uint64_t w = begin + threadIdx.x; w < end; w += blockDim.x) {
     if (si == 0xffffffffu) {
-      si = find_seg(a, w, [](const LevelSeg& s) { return s.gc_start; });
+      si = SPLIT ? find_seg(a, w, [](const LevelSeg& s) { return s.gs_start; })
+                 : find_seg(a, w, [](const LevelSeg& s) { return s.gc_start; });
     } else {
-      while (si + 1 < a.nseg && a.seg[si + 1].gc_start <= w) {
+      while (si + 1 < a.nseg && (SPLIT ? a.seg[si + 1].gs_start : a.seg[si + 1].gc_start) <= w) {
         ++si;
         oi = 0xffffffffu;
       }
     }
     const LevelSeg& Sg = a.seg[si];
-    const uint64_t ws = w - Sg.gc_start;
-    const bool has = Sg.n_gc > 0;
+    const DevOp* ops = SPLIT ? Sg.gs_ops : Sg.gc_ops;
+    const uint32_t n = SPLIT ? Sg.n_gs : Sg.n_gc;
+    const uint64_t ws = w - (SPLIT ? Sg.gs_start : Sg.gc_start);
+    const bool has = n > 0;
     if (has) {
-      if (Sg.item_op) {
+      if (!SPLIT && Sg.item_op) {
         oi = Sg.item_op[ws];
       } else if (oi == 0xffffffffu) {
-        oi = find_item(Sg.gc_ops, Sg.n_gc, ws);
+        oi = find_item(ops, n, ws);
       } else {
-        while (oi + 1 < Sg.n_gc && Sg.gc_ops[oi + 1].work0 <= ws) ++oi;
+        while (oi + 1 < n && ops[oi + 1].work0 <= ws) ++oi;
       }
     } else {
       oi = 0;
     }
-    const DevOp& op = Sg.gc_ops[oi];
-    gather_item(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena);
+    const DevOp& op = ops[oi];
+    if (SPLIT) {
+      if (has && op_has_tables(op))
+        gather_item_t<true, true>(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena, Sg.split.part);
+      else
+        gather_item_t<false, true>(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena, Sg.split.part);
+    } else {
+      gather_item(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena);
+    }
   }
 }
 
@@ -669,7 +737,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
     }
     case L_LEVEL: {
       LevelArgs a{};
-      uint64_t tiles = 0, wtiles = 0, work = 0, sunits = 0;
+      uint64_t tiles = 0, wtiles = 0, work = 0, sunits = 0, gsunits = 0, gswork = 0;
       for (int i = 0; i < nseg; ++i) {
         const SegRef& s = segs[i];
         const WorkspaceLayout& L = *s.lay;
@@ -680,7 +748,11 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.wave_ops = ops + s.launch->wbegin;
         g.n_wave = s.launch->wend - s.launch->wbegin;
         g.gc_ops = ops + s.launch->begin;
-        g.n_gc = s.launch->end - s.launch->begin;
+        g.n_gc = s.launch->xbegin - s.launch->begin;
+        g.gs_ops = ops + s.launch->xbegin;
+        g.n_gs = s.launch->end - s.launch->xbegin;
+        g.gs_start = gswork;
+        gswork += s.launch->xwork;
         g.tab = (const uint32_t*)(s.ws + L.tabs);
         g.item_op = s.launch->item_begin != NO_ITEMS
                         ? (const uint32_t*)(s.ws + L.item_op) + s.launch->item_begin
@@ -691,6 +763,10 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.n_split = s.launch->send - s.launch->sbegin;
         g.split_start = sunits;
         sunits += g.n_split;
+        g.gsunits = (const DevSplitUnit*)(s.ws + L.gsunits) + s.launch->gsbegin;
+        g.n_gsplit = s.launch->gsend - s.launch->gsbegin;
+        g.gsplit_start = gsunits;
+        gsunits += g.n_gsplit;
         g.gemm_start = tiles;
         g.wave_start = wtiles;
         g.gc_start = work;
@@ -702,11 +778,14 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.gemm_tiles = tiles;
       a.wave_tiles = wtiles;
       a.split_units = sunits;
+      a.gsplit_units = gsunits;
       a.gc_work = work;
+      a.gs_work = gswork;
       a.tile_blocks = (unsigned)std::min<uint64_t>(tiles, (uint64_t)n_cu * 8);
       const unsigned wvb = (unsigned)std::min<uint64_t>((wtiles + 3) / 4, (uint64_t)n_cu * 16);
       const unsigned gmb = (parts & PART_GEMM) ? a.tile_blocks + wvb : 0u;
       const unsigned gcb = (parts & PART_GATHER) && work ? grid_for(work, 256, n_cu) : 0u;
+      const unsigned gsb = (parts & PART_GATHER) && gswork ? grid_for(gswork, 256, n_cu) : 0u;
       auto gemm = [&](hipStream_t st) {
         if (precision == TC_PREC_BF16X3)
           hipLaunchKernelGGL(k_gemm<TC_PREC_BF16X3>, dim3(gmb), dim3(256), 0, st, a);
@@ -716,17 +795,25 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         if (a.split_units)
           hipLaunchKernelGGL(k_reduce, dim3((unsigned)a.split_units), dim3(256), 0, st, a);
       };
-      if (gmb && gcb && fork) {
+      auto gather = [&](hipStream_t st) {
+        if (gcb) hipLaunchKernelGGL(k_gather<false>, dim3(gcb), dim3(256), 0, st, a);
+        if (gsb) {
+          hipLaunchKernelGGL(k_gather<true>, dim3(gsb), dim3(256), 0, st, a);
+          // split sums: their slices are all written once k_gather is done
+          hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)a.gsplit_units), dim3(256), 0, st, a);
+        }
+      };
+      if (gmb && (gcb || gsb) && fork) {
         // GEMM tiles on the side stream, concurrent with the gather kernel
         HIP_CHECK(hipEventRecord(fork->start, stream));
         HIP_CHECK(hipStreamWaitEvent(fork->side, fork->start, 0));
         gemm(fork->side);
-        hipLaunchKernelGGL(k_gather, dim3(gcb), dim3(256), 0, stream, a);
+        gather(stream);
         HIP_CHECK(hipEventRecord(fork->done, fork->side));
         HIP_CHECK(hipStreamWaitEvent(stream, fork->done, 0));
       } else {
         if (gmb) gemm(stream);
-        if (gcb) hipLaunchKernelGGL(k_gather, dim3(gcb), dim3(256), 0, stream, a);
+        if (gcb || gsb) gather(stream);
       }
       break;
     }
@@ -834,6 +921,7 @@ void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStrea
   upload(ws, lay.groups, P.groups, stream);
   upload(ws, lay.ranges, P.ranges, stream);
   upload(ws, lay.sunits, P.split_units, stream);
+  upload(ws, lay.gsunits, P.gsplit_units, stream);
   upload(ws, lay.arena, P.seeds, stream);  // seeds sit at arena offset 0
 }
 

@@ -464,6 +464,7 @@ WorkspaceLayout workspace_layout(const Plan& p) {
   w.ranges = o; o = al(o + p.ranges.size() * sizeof(DevRange));
   w.split = o; o = al(o + p.split_floats * sizeof(float));
   w.sunits = o; o = al(o + p.split_units.size() * sizeof(DevSplitUnit));
+  w.gsunits = o; o = al(o + p.gsplit_units.size() * sizeof(DevSplitUnit));
   w.params = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(float));
   w.value = o; o = al(o + (uint64_t)p.batch * 2 * sizeof(double));
   w.grad = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(double));
@@ -750,6 +751,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         uint32_t ls, lv;
         gather_shape(op.M, op.N, op.K, op.rows, term_mode ? TERM_LANES : LEVEL_LANES, ls, lv);
         op.flags |= (ls << 4) | (lv << 8);
+        // a sum too long even for 64 lanes (few outputs, huge K: a final
+        // inner product) is cut into slices reduced afterwards, as split-K
+        if (!term_mode && (op.K >> ls) > 256) {
+          uint32_t P = 1;
+          while (P < 65536 && (op.K >> ls) / P > 256) P *= 2;
+          op.ksplit = P;
+        }
         gc.push_back(op);
       }
     }
@@ -800,29 +808,56 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.send = (uint32_t)plan.split_units.size();
     L.wend = (uint32_t)plan.ops.size();
     L.wtiles = wtiles;
+    // gather ops: the split ones last, in a work space and a kernel of
+    // their own (their partial sums go to the split region, slice-major,
+    // and a reduction over 256-output chunks adds them)
+    std::stable_partition(gc.begin(), gc.end(), [](const DevOp& op) { return op.ksplit == 1; });
     L.begin = (uint32_t)plan.ops.size();
     uint64_t w = 0;
+    L.gsbegin = (uint32_t)plan.gsplit_units.size();
+    bool in_split = false;
     for (DevOp& op : gc) {
       const uint32_t ls = (op.flags >> 4) & 7u, lv = (op.flags >> 8) & 3u;
-      uint64_t items = ((uint64_t)op.rows * op.M * (op.N >> lv)) << ls;
+      const uint64_t groups = (uint64_t)op.rows * op.M * (op.N >> lv);
+      if (op.ksplit > 1 && !in_split) {  // first split op
+        in_split = true;
+        L.xbegin = (uint32_t)plan.ops.size();
+        L.work = (w + 63) & ~uint64_t(63);
+        w = 0;
+      }
+      uint64_t items = (groups * op.ksplit) << ls;
       if (ls) {  // whole wavefronts: aligned start, padded length
         w = (w + 63) & ~uint64_t(63);
         items = (items + 63) & ~uint64_t(63);
       }
       op.work0 = w;
       w += items;
+      if (op.ksplit > 1) {
+        op.part = part;
+        part += groups * op.ksplit * 2;
+        const uint32_t rel = (uint32_t)(plan.ops.size() - L.xbegin);
+        for (uint64_t ch = 0; ch < (groups + 255) / 256; ++ch)
+          plan.gsplit_units.push_back({rel, (uint32_t)ch});
+      }
       plan.ops.push_back(op);
     }
+    L.gsend = (uint32_t)plan.gsplit_units.size();
+    plan.split_floats = std::max(plan.split_floats, part);
     L.end = (uint32_t)plan.ops.size();
-    L.work = (w + 63) & ~uint64_t(63);
-    if (L.end > L.begin && L.work <= ITEM_TABLE_MAX) {
+    if (!in_split) {
+      L.xbegin = L.end;
+      L.work = (w + 63) & ~uint64_t(63);
+    } else {
+      L.xwork = (w + 63) & ~uint64_t(63);
+    }
+    if (L.xbegin > L.begin && L.work <= ITEM_TABLE_MAX) {
       // item -> op (relative to L.begin); pad items map to the op before them
       L.item_begin = plan.item_op.size();
       plan.item_op.resize(plan.item_op.size() + L.work);
       uint32_t* it = plan.item_op.data() + L.item_begin;
-      for (uint32_t o = L.begin; o < L.end; ++o) {
+      for (uint32_t o = L.begin; o < L.xbegin; ++o) {
         const uint64_t lo = plan.ops[o].work0;
-        const uint64_t hi = o + 1 < L.end ? plan.ops[o + 1].work0 : L.work;
+        const uint64_t hi = o + 1 < L.xbegin ? plan.ops[o + 1].work0 : L.work;
         for (uint64_t x = lo; x < hi; ++x) it[x] = o - L.begin;
       }
     }
@@ -1008,8 +1043,33 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
               (wave && (op.K / op.ksplit) % 4 != 0))
             fail(TC_ERR_INVALID_ARG, "internal: split-K tiles out of range");
         }
-        if (L.sbegin > L.send || L.send > plan.split_units.size())
+        if (L.sbegin > L.send || L.send > plan.split_units.size() || L.gsbegin > L.gsend ||
+            L.gsend > plan.gsplit_units.size())
           fail(TC_ERR_INVALID_ARG, "internal: split-K units out of range");
+        // gather ops: unsplit in [begin, xbegin) over `work` items, split
+        // (V == 1, K a multiple of the slices) in [xbegin, end) over `xwork`
+        if (L.xbegin < L.begin || L.xbegin > L.end)
+          fail(TC_ERR_INVALID_ARG, "internal: split gather range");
+        for (uint32_t o = L.begin; o < L.end; ++o) {
+          const DevOp& op = plan.ops[o];
+          const bool sp = o >= L.xbegin;
+          const uint32_t ls = (op.flags >> 4) & 7u, lv = (op.flags >> 8) & 3u;
+          const uint64_t groups = (uint64_t)op.rows * op.M * (op.N >> lv);
+          const uint64_t items = (groups * op.ksplit) << ls;
+          if ((sp ? op.ksplit < 2 || lv != 0 : op.ksplit != 1) || op.work0 + items > (sp ? L.xwork : L.work) ||
+              (o > L.begin && o != L.xbegin && op.work0 < plan.ops[o - 1].work0))
+            fail(TC_ERR_INVALID_ARG, "internal: gather items do not cover the ops");
+          if (sp && (op.K % op.ksplit != 0 || op.part + groups * op.ksplit * 2 > plan.split_floats))
+            fail(TC_ERR_INVALID_ARG, "internal: gather split out of range");
+        }
+        for (uint32_t u = L.gsbegin; u < L.gsend; ++u) {
+          const DevSplitUnit su = plan.gsplit_units[u];
+          if (su.op >= L.end - L.xbegin) fail(TC_ERR_INVALID_ARG, "internal: gather split unit op");
+          const DevOp& op = plan.ops[L.xbegin + su.op];
+          const uint64_t groups = (uint64_t)op.rows * op.M * (op.N >> ((op.flags >> 8) & 3u));
+          if (op.ksplit < 2 || (uint64_t)su.tile * 256 >= groups)
+            fail(TC_ERR_INVALID_ARG, "internal: gather split unit chunk");
+        }
         for (uint32_t u = L.sbegin; u < L.send; ++u) {
           const DevSplitUnit su = plan.split_units[u];
           if (su.op >= L.wend - L.gbegin) fail(TC_ERR_INVALID_ARG, "internal: split unit op");
@@ -1055,7 +1115,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       for (const Launch& L : *seq) {
         if (L.item_begin == NO_ITEMS) continue;
         const uint64_t n_items =
-            (L.kind == L_LEAF || L.kind == L_TERM) ? plan.leaves.size() : L.end - L.begin;
+            (L.kind == L_LEAF || L.kind == L_TERM) ? plan.leaves.size() : L.xbegin - L.begin;
         if (L.item_begin + L.work > plan.item_op.size())
           fail(TC_ERR_INVALID_ARG, "internal: item table out of range");
         for (uint64_t x = 0; x < L.work; ++x)
@@ -1086,7 +1146,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   info.n_terms = plan.n_terms;
   info.checkpoint_every = plan.checkpoint_used;
   info.exec_mode = plan.exec_used;
-  for (const DevOp& op : plan.ops) info.n_split_nodes += op.ksplit > 1;
+  for (const auto* seq : {&plan.fwd, &plan.bwd})
+    for (const Launch& L : *seq)
+      if (L.kind == L_LEVEL) {
+        for (uint32_t o = L.gbegin; o < L.wend; ++o) info.n_split_nodes += plan.ops[o].ksplit > 1;
+        info.n_split_sums += (int32_t)(L.end - L.xbegin);
+      }
   if (plan.budget && info.workspace_bytes > plan.budget)
     fail(TC_ERR_TOO_LARGE, "workspace of " + std::to_string(info.workspace_bytes) +
                                " bytes exceeds the memory budget");

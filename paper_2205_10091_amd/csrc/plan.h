@@ -38,11 +38,14 @@ struct Launch {
   int32_t kind;
   uint32_t begin = 0, end = 0;    // gather ops in Plan::ops
   uint64_t work = 0;              // gather work items / leaf, root, grad items
+  uint32_t xbegin = 0;            // L_LEVEL: split gather ops are [xbegin, end)
+  uint64_t xwork = 0;             // their work items (a space of their own)
   uint32_t gbegin = 0, gend = 0;  // GEMM ops in 64 x 64 tiles, in Plan::ops
   uint64_t tiles = 0;             // 64 x 64 GEMM tiles
   uint32_t wbegin = 0, wend = 0;  // GEMM ops in wave tiles, in Plan::ops
   uint64_t wtiles = 0;            // wave tiles
   uint32_t sbegin = 0, send = 0;  // split-K output tiles, in Plan::split_units
+  uint32_t gsbegin = 0, gsend = 0;  // split gather outputs (256 a unit), in Plan::gsplit_units
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
   bool with_leaves = false;       // L_TERM: materialise the leaves first
   double flops = 0;               // algorithmic flops (8 per complex MAC)
@@ -90,6 +93,7 @@ struct Plan {
   std::vector<DevGroup> groups;       // term launches: a term's nodes at one step
   std::vector<DevRange> ranges;       // term launches: each term's groups, per launch
   std::vector<DevSplitUnit> split_units;  // split-K output tiles, per level
+  std::vector<DevSplitUnit> gsplit_units; // split gather outputs, per level
   std::vector<float> seeds;           // (re, im) per term, arena offset 0
   uint64_t leaf_work = 0;
 
@@ -111,7 +115,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path);
 // Byte layout of the workspace: [tables][params][values][grad][arena]
 struct WorkspaceLayout {
   uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots, terms, groups, ranges;
-  uint64_t split, sunits;  // split-K partial tiles (float), output tiles to reduce
+  uint64_t split, sunits, gsunits;  // split-K partials (float), units to reduce
   uint64_t params, value, grad, arena, total;
 };
 WorkspaceLayout workspace_layout(const Plan& p);

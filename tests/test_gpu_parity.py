@@ -164,9 +164,9 @@ def test_grid_amplitude_full_size_against_golden():
 
 def test_split_k_wide_nodes_fp32_and_bf16x3():
     """The 6x6 grid's widest nodes have few output tiles and deep K, so
-    their K is cut into slices; the slices' partial tiles are added in slice
-    order by whichever slice finishes last.  Both precisions against the
-    oracle's amplitude, and repeated calls bit-identical."""
+    their K is cut into slices; a reduction kernel adds the slices' partial
+    tiles in slice order.  Both precisions against the oracle's amplitude,
+    and repeated calls bit-identical."""
     from gpu_common import TOL_BF16X3
     path = os.path.join(GOLDEN, "grid6x6_d8_amplitude.json")
     if not os.path.exists(path):
@@ -181,6 +181,27 @@ def test_split_k_wide_nodes_fp32_and_bf16x3():
         a2 = plan.contract(device_params(p))[0]
         assert a1 == a2, prec
         assert rel_err(a1, r, 2 ** (-18)) < tol, prec
+
+
+def test_split_sums_deep_grid_fp32_and_bf16x3():
+    """The 4x6 depth-12 grid ends in a long sum with few outputs; its K is
+    cut into slices summed by the split gather kernel and added in slice
+    order by the reduction.  Both precisions against the oracle's amplitude
+    (state vector and time-order sweep, stored), repeats bit-identical."""
+    from gpu_common import TOL_BF16X3
+    path = os.path.join(GOLDEN, "grid4x6_d12_amplitude.json")
+    if not os.path.exists(path):
+        pytest.skip("reference amplitude not generated")
+    ref = json.load(open(path))
+    r = complex(ref["values"]["statevector"]["re"], ref["values"]["statevector"]["im"])
+    circ, p, amp = tcgen.workload_grid_amplitude(4, 6, 12)
+    for prec, tol in ((0, TOL_C64), (1, TOL_BF16X3)):
+        plan = api.compile(circ, amp, n_trials=32, seed=1, precision=prec)
+        assert plan.info().n_split_sums > 0
+        a1 = plan.contract(device_params(p))[0]
+        a2 = plan.contract(device_params(p))[0]
+        assert a1 == a2, prec
+        assert rel_err(a1, r, 2 ** (-12)) < tol, prec
 
 
 # ------------------------------------------------------------ edge cases
