@@ -238,8 +238,16 @@ struct Schedule {
 // Builds tensors, ops with their steps, lifetimes and arena offsets.
 // ckpt = 0: keep every intermediate for the reverse sweep; ckpt >= 2:
 // checkpoint segments of that many levels.
-void schedule(Schedule& S, const Network& net, const Path& path, int B, bool grad, int ckpt,
-              bool per_term_arena) {
+// A node that runs as 64 x 64 GEMM tiles (the level launch's block tiles).
+bool block_gemm_node(const Plan& plan, uint32_t M, uint32_t N, uint32_t K, uint32_t rows) {
+  return K >= (uint32_t)plan.gemm_min_k && M >= (uint32_t)plan.gemm_min_mn &&
+         N >= (uint32_t)plan.gemm_min_mn && (uint64_t)rows * M * N * K >= plan.gemm_min_macs &&
+         M >= (uint32_t)plan.block_tile_min_mn && N >= (uint32_t)plan.block_tile_min_mn &&
+         K >= (uint32_t)plan.block_tile_min_k;
+}
+
+void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& path, int B,
+              bool grad, int ckpt, bool per_term_arena) {
   std::vector<PT>& T = S.T;
   S.ti.assign(net.terms.size(), TermInfo{});
 
@@ -291,6 +299,42 @@ void schedule(Schedule& S, const Network& net, const Path& path, int B, bool gra
       I.tid[c] = (int32_t)T.size();
       T.push_back(x);
       S.max_level = std::max(S.max_level, I.level[c]);
+    }
+    // Storage order of intermediates.  The leg order of an intermediate is
+    // free (its node writes it through index descriptors), and each has one
+    // consumer; one that feeds a GEMM-tile node is stored the way that node
+    // reads contiguously: as operand A its free legs, then the contracted
+    // ones (k fastest); as operand B the contracted legs, then its free ones
+    // (n fastest); the contracted legs in the same order on both sides (a
+    // leaf operand's order, whose layout is fixed).  Every other tensor
+    // keeps its legs in contraction order.
+    for (size_t s = 0; s < tp.pairs.size(); ++s) {
+      const int32_t a = tp.pairs[s].first, b = tp.pairs[s].second;
+      if (a < nl && b < nl) continue;
+      PT& A = T[I.tid[a]];
+      PT& Bt = T[I.tid[b]];
+      auto in = [](const std::vector<int32_t>& v, int32_t l) {
+        return std::find(v.begin(), v.end(), l) != v.end();
+      };
+      std::vector<int32_t> sh, fa, fb;
+      for (int32_t l : A.legs) (in(Bt.legs, l) ? sh : fa).push_back(l);
+      for (int32_t l : Bt.legs)
+        if (!in(A.legs, l)) fb.push_back(l);
+      const uint32_t rows = (A.batched || Bt.batched) && B > 1 ? (uint32_t)B : 1u;
+      if (!block_gemm_node(plan, 1u << fa.size(), 1u << fb.size(), 1u << sh.size(), rows)) continue;
+      if (a >= nl && b < nl) {  // B's order of the contracted legs
+        sh.clear();
+        for (int32_t l : Bt.legs)
+          if (in(A.legs, l)) sh.push_back(l);
+      }
+      if (a >= nl) {
+        A.legs = fa;
+        A.legs.insert(A.legs.end(), sh.begin(), sh.end());
+      }
+      if (b >= nl) {
+        Bt.legs = sh;
+        Bt.legs.insert(Bt.legs.end(), fb.begin(), fb.end());
+      }
     }
     if (ns > 0) {
       I.root = ns - 1;
@@ -483,7 +527,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   // ---- schedule, with checkpointing when the budget asks for it
   Schedule S;
   int ckpt = plan.checkpoint > 0 ? plan.checkpoint : 0;
-  schedule(S, net, path, B, grad, ckpt, false);
+  schedule(S, plan, net, path, B, grad, ckpt, false);
   if (grad && plan.checkpoint == 0 && plan.budget && S.arena_elems * 8 > plan.budget &&
       S.max_level >= 4) {
     // smallest arena over a few segment lengths
@@ -492,7 +536,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     for (int c : {2, 3, 4, 6, 8, 12}) {
       if (c > std::max(2, S.max_level / 2)) break;
       Schedule t;
-      schedule(t, net, path, B, grad, c, false);
+      schedule(t, plan, net, path, B, grad, c, false);
       if (!best_c || t.arena_elems < best.arena_elems) {
         best = std::move(t);
         best_c = c;
@@ -566,7 +610,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   for (const auto& ts : term_step) (ts.second ? any_term : any_level) = true;
   if (any_term) {
     Schedule St;
-    schedule(St, net, path, B, grad, ckpt, true);
+    schedule(St, plan, net, path, B, grad, ckpt, true);
     // automatic choice: only while the separate regions stay modest
     const bool fits = !plan.budget || St.arena_elems * 8 <= plan.budget;
     const bool modest = St.arena_elems <= std::max<uint64_t>(4 * S.arena_elems, uint64_t(1) << 25);
