@@ -269,10 +269,18 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *               node for the GEMM path, at most two gather items per
  *               thread of each term's workgroup), level launches for the
  *               other steps.
+ *   tile_mode   0 = GEMM nodes whose operands are stored dense, A as
+ *               [m][k] and B as [k][n] (the planner stores intermediates
+ *               that feed GEMM nodes so), with at least 256 tiles of
+ *               128 x 128 run such tiles, the others 64 x 64 tiles; 1 =
+ *               64 x 64 tiles only; 2 = 128 x 128 tiles for every such
+ *               node whatever its tile count (for tests).
  * GEMM nodes whose output tiles cannot fill the chip have K cut into
  * slices (split-K): every slice writes a partial tile to the workspace and
- * the last slice of a tile to arrive adds the slices in slice order, so
- * results do not depend on the order in which slices finish.
+ * a reduction kernel adds the slices in slice order, so results do not
+ * depend on the order in which slices finish.  Gather nodes with a sum too
+ * long for one wavefront and few outputs (a final inner product) have
+ * their sum cut into slices the same way.
  *   checkpoint_every  with want_grad: 0 = keep every intermediate for the
  *               reverse sweep unless mem_budget_bytes is exceeded, in which
  *               case the segment length with the smallest workspace is
@@ -296,6 +304,7 @@ typedef struct {
   int32_t checkpoint_every;
   uint64_t gemm_min_macs;
   int32_t exec_mode;
+  int32_t tile_mode;
 } tc_plan_opts;
 
 tc_status tc_plan_create(const tc_network* net, const tc_path* path,
@@ -325,6 +334,7 @@ typedef struct {
   int32_t n_split_nodes;     /* GEMM nodes whose K is cut into slices    */
   int32_t n_split_sums;      /* gather nodes (long sums, few outputs)
                                 whose K is cut into slices               */
+  int32_t n_wide_nodes;      /* GEMM nodes in 128 x 128 tiles            */
 } tc_plan_info;
 
 tc_status tc_plan_info_get(const tc_plan* plan, tc_plan_info* out);

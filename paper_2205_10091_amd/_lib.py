@@ -70,7 +70,8 @@ class PlanOpts(C.Structure):
                 ("want_grad", C.c_int32), ("device", C.c_int32),
                 ("mem_budget_bytes", C.c_uint64), ("stream", C.c_void_p),
                 ("gemm_min_k", C.c_int32), ("checkpoint_every", C.c_int32),
-                ("gemm_min_macs", C.c_uint64), ("exec_mode", C.c_int32)]
+                ("gemm_min_macs", C.c_uint64), ("exec_mode", C.c_int32),
+                ("tile_mode", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -83,7 +84,8 @@ class PlanInfo(C.Structure):
                 ("n_grad_launches", C.c_int32), ("batch", C.c_int32),
                 ("n_params", C.c_int32), ("n_terms", C.c_int32),
                 ("checkpoint_every", C.c_int32), ("exec_mode", C.c_int32),
-                ("n_split_nodes", C.c_int32), ("n_split_sums", C.c_int32)]
+                ("n_split_nodes", C.c_int32), ("n_split_sums", C.c_int32),
+                ("n_wide_nodes", C.c_int32)]
 
 
 class ServeOpts(C.Structure):

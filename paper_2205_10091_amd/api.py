@@ -148,13 +148,13 @@ class Plan:
 
     def __init__(self, net: Network, path: Path, batch=1, want_grad=False,
                  precision=0, device=0, mem_budget_bytes=0, stream=None, gemm_min_k=0,
-                 checkpoint_every=0, gemm_min_macs=0, exec_mode=0):
+                 checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0):
         self.net, self.path = net, path
         self.batch = batch
         self.want_grad = want_grad
         opts = L.PlanOpts(precision, batch, int(want_grad), device,
                           mem_budget_bytes, stream, gemm_min_k, checkpoint_every,
-                          gemm_min_macs, exec_mode)
+                          gemm_min_macs, exec_mode, tile_mode)
         h = C.c_void_p()
         L.check(lib().tc_plan_create(net.h, path.h, C.byref(opts), C.byref(h)))
         self.h = h
@@ -253,7 +253,7 @@ class Plan:
 def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
             lightcone=True, absorb_1q=True, seed=0, n_trials=8,
             mem_budget_bytes=0, device=0, bind=True, gemm_min_k=0, stream=None,
-            checkpoint_every=0, gemm_min_macs=0, exec_mode=0) -> Plan:
+            checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0) -> Plan:
     """Network + greedy path + plan (+ bind with a torch workspace)."""
     net = Network(circ, obs, split_2q, lightcone, absorb_1q)
     path = Path(net, seed=seed, n_trials=n_trials)
@@ -266,7 +266,7 @@ def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
         torch_stream = torch.cuda.Stream(device=f"cuda:{device}")
         stream = torch_stream.cuda_stream
     plan = Plan(net, path, batch, want_grad, precision, device, mem_budget_bytes,
-                stream, gemm_min_k, checkpoint_every, gemm_min_macs, exec_mode)
+                stream, gemm_min_k, checkpoint_every, gemm_min_macs, exec_mode, tile_mode)
     plan.torch_stream = torch_stream
     if bind:
         plan.bind_torch(f"cuda:{device}")

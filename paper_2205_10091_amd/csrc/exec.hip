@@ -68,6 +68,9 @@ struct LevelSeg {
   const DevSplitUnit* sunits;  // split-K output tiles of this level
   uint64_t split_start;     // first split-K output tile of this segment
   uint32_t n_split;
+  const DevOp* wide_ops;    // GEMM ops in 128 x 128 tiles
+  uint64_t wide_start;      // first wide tile of this segment
+  uint32_t n_wide;
   const DevOp* gs_ops;      // split gather ops (V == 1), in their own work space
   uint64_t gs_start;        // first split gather item of this segment
   uint32_t n_gs;
@@ -89,6 +92,7 @@ struct LevelArgs {
   uint64_t wave_tiles;
   uint64_t split_units;  // split-K output tiles over all segments
   uint64_t gsplit_units;  // split gather units over all segments
+  uint64_t wide_tiles;    // 128 x 128 tiles over all segments
   uint64_t gc_work;
   uint64_t gs_work;       // split gather items over all segments
 };
@@ -316,6 +320,23 @@ __global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
       else
         gemm_tile_f32<false>(op, lt, S.tab, S.arena, smem, S.split);
     }
+  }
+}
+
+// 128 x 128 tiles of a level's wide GEMM ops: one workgroup per CU walks
+// the tiles (the grid is a multiple of 8, which the tile order relies on
+// for its XCD placement; any grid is correct).
+template <int PREC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_gemm_wide(LevelArgs a) {
+  using Smem = typename std::conditional<PREC == TC_PREC_BF16X3, SmemWideBF16, SmemWideF32>::type;
+  __shared__ Smem smem;
+  for (uint64_t tile = blockIdx.x; tile < a.wide_tiles; tile += gridDim.x) {
+    const LevelSeg& S = a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.wide_start; })];
+    const uint64_t lt = tile - S.wide_start;
+    const uint32_t oi = __builtin_amdgcn_readfirstlane(find_item(S.wide_ops, S.n_wide, lt));
+    const DevOp op = S.wide_ops[oi];
+    gemm_wide<PREC == TC_PREC_BF16X3 ? 1 : 0>(op, lt - op.work0, S.tab, S.arena, smem);
   }
 }
 
@@ -737,7 +758,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
     }
     case L_LEVEL: {
       LevelArgs a{};
-      uint64_t tiles = 0, wtiles = 0, work = 0, sunits = 0, gsunits = 0, gswork = 0;
+      uint64_t tiles = 0, wtiles = 0, work = 0, sunits = 0, gsunits = 0, gswork = 0, htiles = 0;
       for (int i = 0; i < nseg; ++i) {
         const SegRef& s = segs[i];
         const WorkspaceLayout& L = *s.lay;
@@ -747,6 +768,10 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.n_gemm = s.launch->gend - s.launch->gbegin;
         g.wave_ops = ops + s.launch->wbegin;
         g.n_wave = s.launch->wend - s.launch->wbegin;
+        g.wide_ops = ops + s.launch->hbegin;
+        g.n_wide = s.launch->hend - s.launch->hbegin;
+        g.wide_start = htiles;
+        htiles += s.launch->htiles;
         g.gc_ops = ops + s.launch->begin;
         g.n_gc = s.launch->xbegin - s.launch->begin;
         g.gs_ops = ops + s.launch->xbegin;
@@ -781,12 +806,21 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.gsplit_units = gsunits;
       a.gc_work = work;
       a.gs_work = gswork;
+      a.wide_tiles = htiles;
       a.tile_blocks = (unsigned)std::min<uint64_t>(tiles, (uint64_t)n_cu * 8);
       const unsigned wvb = (unsigned)std::min<uint64_t>((wtiles + 3) / 4, (uint64_t)n_cu * 16);
       const unsigned gmb = (parts & PART_GEMM) ? a.tile_blocks + wvb : 0u;
+      const unsigned whb = (parts & PART_GEMM) ? (unsigned)std::min<uint64_t>(htiles, (uint64_t)n_cu) : 0u;
       const unsigned gcb = (parts & PART_GATHER) && work ? grid_for(work, 256, n_cu) : 0u;
       const unsigned gsb = (parts & PART_GATHER) && gswork ? grid_for(gswork, 256, n_cu) : 0u;
       auto gemm = [&](hipStream_t st) {
+        if (whb) {
+          if (precision == TC_PREC_BF16X3)
+            hipLaunchKernelGGL(k_gemm_wide<TC_PREC_BF16X3>, dim3(whb), dim3(256), 0, st, a);
+          else
+            hipLaunchKernelGGL(k_gemm_wide<TC_PREC_C64>, dim3(whb), dim3(256), 0, st, a);
+        }
+        if (!gmb) return;
         if (precision == TC_PREC_BF16X3)
           hipLaunchKernelGGL(k_gemm<TC_PREC_BF16X3>, dim3(gmb), dim3(256), 0, st, a);
         else
@@ -803,7 +837,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
           hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)a.gsplit_units), dim3(256), 0, st, a);
         }
       };
-      if (gmb && (gcb || gsb) && fork) {
+      if ((gmb || whb) && (gcb || gsb) && fork) {
         // GEMM tiles on the side stream, concurrent with the gather kernel
         HIP_CHECK(hipEventRecord(fork->start, stream));
         HIP_CHECK(hipStreamWaitEvent(fork->side, fork->start, 0));
@@ -812,7 +846,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         HIP_CHECK(hipEventRecord(fork->done, fork->side));
         HIP_CHECK(hipStreamWaitEvent(stream, fork->done, 0));
       } else {
-        if (gmb) gemm(stream);
+        if (gmb || whb) gemm(stream);
         if (gcb || gsb) gather(stream);
       }
       break;
@@ -1073,8 +1107,9 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
       seq.push_back({L, L.kind, PART_GEMM | PART_GATHER, L.flops, L.bytes});
       continue;
     }
-    if (L.tiles || L.wtiles) seq.push_back({L, PROF_GEMM, PART_GEMM, L.gemm_flops, L.gemm_bytes});
-    if (L.work)
+    if (L.tiles || L.wtiles || L.htiles)
+      seq.push_back({L, PROF_GEMM, PART_GEMM, L.gemm_flops, L.gemm_bytes});
+    if (L.work || L.xwork)
       seq.push_back({L, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops, L.bytes - L.gemm_bytes});
   }
   std::vector<hipEvent_t> ev(seq.size() + 1, nullptr);
@@ -1140,10 +1175,11 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
                          const tc_plan_opts* opts, tc_plan** out) {
   TC_GUARD_BEGIN
   if (!net || !path || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
-  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0, 0, 0};
+  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.gemm_min_k < 0) tcx::fail(TC_ERR_INVALID_ARG, "gemm_min_k must be >= 0");
   if (o.exec_mode < 0 || o.exec_mode > 2) tcx::fail(TC_ERR_INVALID_ARG, "exec_mode must be 0, 1 or 2");
+  if (o.tile_mode < 0 || o.tile_mode > 2) tcx::fail(TC_ERR_INVALID_ARG, "tile_mode must be 0, 1 or 2");
   if (o.checkpoint_every < -1 || o.checkpoint_every == 1)
     tcx::fail(TC_ERR_INVALID_ARG, "checkpoint_every must be -1, 0 or >= 2");
   if (o.batch < 1 || o.batch > (1 << 20)) tcx::fail(TC_ERR_INVALID_ARG, "batch must be in 1..2^20");
@@ -1159,6 +1195,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
   if (o.gemm_min_k > 0) p->p.gemm_min_k = o.gemm_min_k;
   if (o.gemm_min_macs > 0) p->p.gemm_min_macs = o.gemm_min_macs;
   p->p.exec_mode = o.exec_mode;
+  p->p.wide_tiles = o.tile_mode == 0 ? 1 : (o.tile_mode == 1 ? 0 : 2);
   p->p.checkpoint = o.checkpoint_every;
   try {
     tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));

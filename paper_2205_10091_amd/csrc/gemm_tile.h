@@ -571,3 +571,244 @@ __device__ __forceinline__ void gemm_tile_bf16x3(const DevOp op, uint64_t tile,
 }
 
 }  // namespace tcx
+
+namespace tcx {
+
+// ------------------------------------------------------------------ wide tiles
+//
+// Nodes with dense operands, A stored as [m][k] and B as [k][n] (the
+// planner stores intermediates that feed GEMM-tile nodes this way) and a
+// grid of at least one 128 x 128 tile per CU run 128 x 128 tiles: four
+// wavefronts of 64 x 64 each, one workgroup per CU, K in stages of 32
+// through LDS with the next stage's operands prefetched into registers.
+// Per unit of work a tile reads half the operand bytes of 64 x 64 tiles,
+// which the split-BF16 form needs to stay off the L2 bandwidth limit.
+constexpr int HM = 128, HN = 128, HK = 32;  // tile edges, k per stage
+
+struct SmemWideF32 {
+  float A[2][HK][HM + 16];  // [re/im][k][m]
+  float B[2][HK][HN + 16];  // [re/im][k][n]
+};
+struct SmemWideBF16 {
+  // [re/im][hi/lo][row][k], k contiguous: a lane reads 8 k at once
+  __attribute__((aligned(16))) __bf16 A[2][2][HM][HK + 8];
+  __attribute__((aligned(16))) __bf16 B[2][2][HN][HK + 8];
+};
+
+// x = hi + lo into element e of two bfloat16 vectors
+__device__ __forceinline__ void split_into(float x, bf8& hi, bf8& lo, int e) {
+  __bf16 h, l;
+  split_bf16(x, h, l);
+  hi[e] = h;
+  lo[e] = l;
+}
+
+// Tile u of a wide op (0 .. rows tiles_m tiles_n - 1).  Inside a batch row
+// the order is XCD-aware: the persistent grid is a multiple of the 8 XCDs,
+// so tile u runs on XCD u % 8; XCD x takes column stripe x of the tile grid
+// in groups of 4 tile rows, so that its 32 CUs share 4 row slabs of A and 8
+// column slabs of B in its L2 at any time.
+__device__ __forceinline__ void wide_tile(const DevOp& op, uint64_t u, uint64_t& r, uint32_t& tm,
+                                          uint32_t& tn) {
+  const uint32_t TM = op.tiles_m, TN = op.tiles_n;
+  const uint64_t per_row = (uint64_t)TM * TN;
+  r = u / per_row;
+  const uint32_t l = (uint32_t)(u - r * per_row);
+  if (TN % 8 == 0 && TM % 4 == 0) {
+    const uint32_t x = l % 8, q = l / 8, TNx = TN / 8;
+    const uint32_t g = q / (4 * TNx), w = q % (4 * TNx);
+    tm = g * 4 + w % 4;
+    tn = x * TNx + w / 4;
+  } else {
+    tm = l / TN;
+    tn = l % TN;
+  }
+}
+
+// One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA,
+// 1: split BF16.
+template <int PREC, typename Smem>
+__device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
+                                          const uint32_t* __restrict__ tab,
+                                          float2* __restrict__ arena, Smem& S) {
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  uint64_t r;
+  uint32_t tm, tn;
+  wide_tile(op, u, r, tm, tn);
+  const uint32_t m0 = tm * HM, n0 = tn * HN, K = op.K, N = op.N;
+  // operand loads: A row (t / 2), k half (t % 2) * 16: 16 complex; B k rows
+  // 8 (t / 64) .. + 7, columns 2 (t % 64) and + 1
+  const float4* pA = reinterpret_cast<const float4*>(
+      arena + op.a + r * op.a_bs + (uint64_t)(m0 + (t >> 1)) * K + (t & 1) * 16);
+  const float2* pB0 = arena + op.b + r * op.b_bs + (uint64_t)(8 * (t >> 6)) * N + n0 + 2 * (t & 63);
+  float4 ra[8], rb[8];
+  auto fetch = [&](uint32_t k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = pA[k0 / 2 + q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      rb[q] = *reinterpret_cast<const float4*>(pB0 + (uint64_t)(k0 + q) * N);
+  };
+  f4 cr[4][4], ci[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  fetch(0);
+  for (uint32_t k0 = 0; k0 < K; k0 += HK) {
+    // registers -> LDS
+    if constexpr (PREC == 0) {
+      const int row = t >> 1, kh = (t & 1) * 16;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        S.A[0][kh + 2 * q][row] = ra[q].x;
+        S.A[1][kh + 2 * q][row] = ra[q].y;
+        S.A[0][kh + 2 * q + 1][row] = ra[q].z;
+        S.A[1][kh + 2 * q + 1][row] = ra[q].w;
+      }
+      const int kg = 8 * (t >> 6), n = 2 * (t & 63);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        *reinterpret_cast<float2*>(&S.B[0][kg + q][n]) = make_float2(rb[q].x, rb[q].z);
+        *reinterpret_cast<float2*>(&S.B[1][kg + q][n]) = make_float2(rb[q].y, rb[q].w);
+      }
+    } else {
+      const int row = t >> 1, kh = (t & 1) * 16;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        bf8 rh, rl, ih, il;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = ra[4 * half + q];
+          split_into(v.x, rh, rl, 2 * q);
+          split_into(v.y, ih, il, 2 * q);
+          split_into(v.z, rh, rl, 2 * q + 1);
+          split_into(v.w, ih, il, 2 * q + 1);
+        }
+        *reinterpret_cast<bf8*>(&S.A[0][0][row][kh + 8 * half]) = rh;
+        *reinterpret_cast<bf8*>(&S.A[0][1][row][kh + 8 * half]) = rl;
+        *reinterpret_cast<bf8*>(&S.A[1][0][row][kh + 8 * half]) = ih;
+        *reinterpret_cast<bf8*>(&S.A[1][1][row][kh + 8 * half]) = il;
+      }
+      const int kg = 8 * (t >> 6), n = 2 * (t & 63);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {  // column n + c
+        bf8 rh, rl, ih, il;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          split_into(c ? rb[q].z : rb[q].x, rh, rl, q);
+          split_into(c ? rb[q].w : rb[q].y, ih, il, q);
+        }
+        *reinterpret_cast<bf8*>(&S.B[0][0][n + c][kg]) = rh;
+        *reinterpret_cast<bf8*>(&S.B[0][1][n + c][kg]) = rl;
+        *reinterpret_cast<bf8*>(&S.B[1][0][n + c][kg]) = ih;
+        *reinterpret_cast<bf8*>(&S.B[1][1][n + c][kg]) = il;
+      }
+    }
+    __syncthreads();
+    if (k0 + HK < K) fetch(k0 + HK);
+    if constexpr (PREC == 0) {
+#pragma unroll
+      for (int kk = 0; kk < HK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        float br[4], bi[4], nbi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          br[j] = S.B[0][kr][wn * 64 + j * 16 + (lane & 15)];
+          bi[j] = S.B[1][kr][wn * 64 + j * 16 + (lane & 15)];
+          nbi[j] = -bi[j];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float ar = S.A[0][kr][wm * 64 + i * 16 + (lane & 15)];
+          const float ai = S.A[1][kr][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi[j], ci[i][j], 0, 0, 0);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, nbi[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br[j], ci[i][j], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      const int kr = 8 * (lane >> 4);
+      bf8 b[4][2][2];  // [block][re/im][hi/lo]
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            b[j][c][h] = *reinterpret_cast<const bf8*>(&S.B[c][h][wn * 64 + j * 16 + (lane & 15)][kr]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        bf8 a[2][2], na[2];  // [re/im][hi/lo]; na = -(imaginary part)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            a[c][h] = *reinterpret_cast<const bf8*>(&S.A[c][h][wm * 64 + i * 16 + (lane & 15)][kr]);
+        na[0] = -a[1][0];
+        na[1] = -a[1][1];
+        // Cr += Ar Br - Ai Bi and Ci += Ar Bi + Ai Br, each real product
+        // as hi hi + hi lo + lo hi
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][0], b[j][0][0], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][0], b[j][1][0], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][0], b[j][0][1], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][0], b[j][1][1], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][1], b[j][0][0], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][1], b[j][1][0], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(na[0], b[j][1][0], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][0], b[j][0][0], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(na[0], b[j][1][1], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][0], b[j][0][1], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(na[1], b[j][1][0], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][1], b[j][0][0], ci[i][j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // C: lane l holds, per block (i, j), rows 4 (l / 16) + v and column l % 16
+  const uint64_t cb = op.c + r * op.c_bs;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+      const uint64_t cm = cb + ix(tab, op.c_m, m);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t n = n0 + wn * 64 + j * 16 + (lane & 15);
+        arena[cm + ix(tab, op.c_n, n)] = make_float2(cr[i][j][v], ci[i][j][v]);
+      }
+    }
+}
+
+}  // namespace tcx

@@ -30,6 +30,7 @@ namespace tcx {
 // when a gate meets a state) and no memory at all; tables remain for the
 // more permuted ones.
 constexpr int IX_RUNS = 3;
+constexpr uint32_t OPF_WIDE = 1u << 14;  // op flag: 128 x 128 GEMM tiles
 constexpr uint32_t IX_TABLE = 0x80000000u;
 
 struct DevOp {
@@ -40,7 +41,9 @@ struct DevOp {
   uint32_t a_m, a_k, b_k, b_n, c_m, c_n;  // index descriptors
   uint32_t rows;           // batch rows covered (1 if nothing is batched)
   uint32_t tiles_m, tiles_n;  // GEMM path: tile grid per batch row
-  uint32_t flags;          // bit 0: A is k-contiguous; bit 1: B is k-contiguous
+  uint32_t flags;          // bit 0: A is k-contiguous; bit 1: B is k-contiguous;
+                           // gather k-split (bits 4-6) and n-vector (8-9);
+                           // wave-tile blocks (12, 13); 128 x 128 tiles (14)
   // GEMM split-K: K is cut into ksplit slices (1 = none); slice results go
   // to partial tiles from float `part` of the split region
   uint64_t part;

@@ -708,7 +708,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
            (!tstep || pend[j].term == pend[i].term))
       ++j;
     const bool term_mode = tstep;
-    std::vector<DevOp> gc, gm, wv;
+    std::vector<DevOp> gc, gm, wv, wd;
     double lf = 0, lb = 0, gf = 0, gb = 0;
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
@@ -776,7 +776,23 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       const bool block_tile = op.M >= (uint32_t)plan.block_tile_min_mn &&
                               op.N >= (uint32_t)plan.block_tile_min_mn &&
                               op.K >= (uint32_t)plan.block_tile_min_k;
-      if (to_gemm && block_tile) {
+      // wide tiles: dense operands, A as [m][k] and B as [k][n] (element
+      // offsets even, for 16-byte loads), and at least one 128 x 128 tile
+      // per CU of the 256
+      const uint32_t lm = __builtin_ctz(op.M), ln = __builtin_ctz(op.N), lk = __builtin_ctz(op.K);
+      const bool dense = op.a_k == lk && op.a_m == (lm | (lk << 5)) && op.b_n == ln &&
+                         op.b_k == (lk | (ln << 5)) && op.a % 2 == 0 && op.b % 2 == 0 &&
+                         op.a_bs % 2 == 0 && op.b_bs % 2 == 0;
+      const bool wide = to_gemm && block_tile && plan.wide_tiles && dense && op.M >= 128 &&
+                        op.N >= 128 && op.K >= 32 &&
+                        (plan.wide_tiles == 2 || (uint64_t)op.rows * (op.M / 128) * (op.N / 128) >= 256);
+      if (wide) {
+        op.tiles_m = op.M / 128;
+        op.tiles_n = op.N / 128;
+        op.flags |= OPF_WIDE;
+        wd.push_back(op);
+        if (!pend[k].bwd) ++n_gemm_nodes;
+      } else if (to_gemm && block_tile) {
         op.tiles_m = (op.M + 63) / 64;
         op.tiles_n = (op.N + 63) / 64;
         gm.push_back(op);
@@ -852,6 +868,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.send = (uint32_t)plan.split_units.size();
     L.wend = (uint32_t)plan.ops.size();
     L.wtiles = wtiles;
+    L.hbegin = (uint32_t)plan.ops.size();
+    for (DevOp& op : wd) {
+      op.work0 = L.htiles;
+      L.htiles += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+      plan.ops.push_back(op);
+    }
+    L.hend = (uint32_t)plan.ops.size();
     // gather ops: the split ones last, in a work space and a kernel of
     // their own (their partial sums go to the split region, slice-major,
     // and a reduction over 256-output chunks adds them)
@@ -1087,6 +1110,20 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
               (wave && (op.K / op.ksplit) % 4 != 0))
             fail(TC_ERR_INVALID_ARG, "internal: split-K tiles out of range");
         }
+        // wide tiles: dense operands, whole 128 x 128 tiles, no split
+        if (L.hbegin != L.wend || L.hend < L.hbegin || L.begin != L.hend)
+          fail(TC_ERR_INVALID_ARG, "internal: wide op range");
+        for (uint32_t o = L.hbegin; o < L.hend; ++o) {
+          const DevOp& op = plan.ops[o];
+          const uint32_t lm = __builtin_ctz(op.M), ln = __builtin_ctz(op.N), lk = __builtin_ctz(op.K);
+          if (!(op.flags & OPF_WIDE) || op.ksplit != 1 || op.M % 128 || op.N % 128 || op.K % 32 ||
+              op.tiles_m * 128 != op.M || op.tiles_n * 128 != op.N || op.a_k != lk ||
+              op.a_m != (lm | (lk << 5)) || op.b_n != ln || op.b_k != (lk | (ln << 5)) ||
+              op.a % 2 || op.b % 2 || op.a_bs % 2 || op.b_bs % 2 ||
+              (o > L.hbegin && op.work0 != plan.ops[o - 1].work0 + (uint64_t)plan.ops[o - 1].rows *
+                                                              plan.ops[o - 1].tiles_m * plan.ops[o - 1].tiles_n))
+            fail(TC_ERR_INVALID_ARG, "internal: wide GEMM op");
+        }
         if (L.sbegin > L.send || L.send > plan.split_units.size() || L.gsbegin > L.gsend ||
             L.gsend > plan.gsplit_units.size())
           fail(TC_ERR_INVALID_ARG, "internal: split-K units out of range");
@@ -1195,6 +1232,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       if (L.kind == L_LEVEL) {
         for (uint32_t o = L.gbegin; o < L.wend; ++o) info.n_split_nodes += plan.ops[o].ksplit > 1;
         info.n_split_sums += (int32_t)(L.end - L.xbegin);
+        info.n_wide_nodes += (int32_t)(L.hend - L.hbegin);
       }
   if (plan.budget && info.workspace_bytes > plan.budget)
     fail(TC_ERR_TOO_LARGE, "workspace of " + std::to_string(info.workspace_bytes) +

@@ -44,6 +44,8 @@ struct Launch {
   uint64_t tiles = 0;             // 64 x 64 GEMM tiles
   uint32_t wbegin = 0, wend = 0;  // GEMM ops in wave tiles, in Plan::ops
   uint64_t wtiles = 0;            // wave tiles
+  uint32_t hbegin = 0, hend = 0;  // GEMM ops in 128 x 128 tiles (dense operands)
+  uint64_t htiles = 0;            // 128 x 128 tiles
   uint32_t sbegin = 0, send = 0;  // split-K output tiles, in Plan::split_units
   uint32_t gsbegin = 0, gsend = 0;  // split gather outputs (256 a unit), in Plan::gsplit_units
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
@@ -70,6 +72,9 @@ struct Plan {
   // GEMM nodes with M, N >= 64 and K >= 16 use 64 x 64 LDS tiles; the
   // narrower ones run as one-wavefront MFMA tiles
   int32_t block_tile_min_mn = 64, block_tile_min_k = 16;
+  // 128 x 128 tiles for GEMM nodes with dense operands: 0 never, 1 when
+  // they give at least one tile per CU, 2 always
+  int32_t wide_tiles = 1;
   // execution: 0 = term mode when every node is a gather and batch is 1,
   // 1 = level-synchronous launches, 2 = term mode (all nodes as gathers)
   int32_t exec_mode = 0;

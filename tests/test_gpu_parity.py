@@ -204,6 +204,56 @@ def test_split_sums_deep_grid_fp32_and_bf16x3():
         assert rel_err(a1, r, 2 ** (-12)) < tol, prec
 
 
+def test_wide_tiles_against_golden_and_64_tiles():
+    """128 x 128 tiles (dense operands, FP32 and split BF16) on the 6x6
+    depth-8 and 4x6 depth-12 grids, forced onto every node whose operands
+    allow them, against the oracle's amplitudes; repeats bit-identical."""
+    from gpu_common import TOL_BF16X3
+    cases = []
+    for (rows, cols, depth, key) in ((6, 6, 8, "col2"), (4, 6, 12, "statevector")):
+        path = os.path.join(GOLDEN, f"grid{rows}x{cols}_d{depth}_amplitude.json")
+        if not os.path.exists(path):
+            pytest.skip("reference amplitude not generated")
+        ref = json.load(open(path))
+        cases.append((rows, cols, depth, complex(ref["values"][key]["re"], ref["values"][key]["im"])))
+    for rows, cols, depth, r in cases:
+        circ, p, amp = tcgen.workload_grid_amplitude(rows, cols, depth)
+        floor = 2 ** (-rows * cols / 2)
+        for prec, tol in ((0, TOL_C64), (1, TOL_BF16X3)):
+            plan = api.compile(circ, amp, n_trials=32, seed=1, precision=prec, tile_mode=2)
+            assert plan.info().n_wide_nodes > 0
+            a1 = plan.contract(device_params(p))[0]
+            a2 = plan.contract(device_params(p))[0]
+            assert a1 == a2, (rows, cols, prec)
+            assert rel_err(a1, r, floor) < tol, (rows, cols, prec)
+            ref64 = api.compile(circ, amp, n_trials=32, seed=1, precision=prec, tile_mode=1)
+            assert ref64.info().n_wide_nodes == 0
+            assert rel_err(a1, ref64.contract(device_params(p))[0], floor) < tol
+
+
+def test_wide_tiles_full_size_deep_grid():
+    """The 6x6 depth-12 grid's 16384 x 65536 x 4096 node runs 128 x 128
+    tiles by default: FP32 against the 64 x 64 tiles of the same tree, and
+    split BF16 against FP32 (no oracle amplitude at this depth: 2^36
+    entries)."""
+    from gpu_common import TOL_BF16X3
+    circ, p, amp = tcgen.workload_grid_amplitude(6, 6, 12)
+    floor = 2 ** -18
+    wide = api.compile(circ, amp, n_trials=32, seed=1)
+    assert wide.info().n_wide_nodes > 0
+    a = wide.contract(device_params(p))[0]
+    del wide
+    narrow = api.compile(circ, amp, n_trials=32, seed=1, tile_mode=1)
+    assert narrow.info().n_wide_nodes == 0
+    b = narrow.contract(device_params(p))[0]
+    del narrow
+    assert rel_err(a, b, floor) < TOL_C64
+    w16 = api.compile(circ, amp, n_trials=32, seed=1, precision=1)
+    c = w16.contract(device_params(p))[0]
+    del w16
+    assert rel_err(c, a, floor) < TOL_BF16X3
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_all_gate_kinds_random_circuits():
