@@ -12,7 +12,10 @@ as the paper excludes JIT staging from its timings.
 
 Other workloads: --workload batched (the same chain, 1024 parameter vectors
 per launch), forward (10-qubit brickwork: amplitude and <Z0 Z1>), grid (6x6
-fSim grid amplitude, depth 8).
+fSim grid amplitude, depth 8), wide (the 6x6 grid at depth 12, whose tree
+holds wide GEMM nodes: 16384 x 65536 x 4096 and others; FP32 and split
+BF16).  The default run also reports the batched sweep, the forward chain's
+latency and the wide-node grid beside the main line.
 
 Prints one JSON line.  --copy-calibration BYTES also runs one plain device
 copy of that many bytes (used to scale HBM byte counters).
@@ -30,8 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
-KIND_NAMES = {0: "k_leaf", 2: "k_gemm", 3: "k_gather", 4: "k_root", 5: "k_grad", 6: "k_term"}
+PEAK_FP32_TFLOPS = 157.3   # dense FP32 MFMA
+PEAK_BF16_TFLOPS = 2500.0  # dense BF16 MFMA
+KIND_NAMES = {0: "k_leaf", 2: "k_gemm", 3: "k_gather", 4: "k_root", 5: "k_grad", 6: "k_term",
+              7: "k_gemm_wide"}
 KERNEL_SOURCES = ["paper_2205_10091_amd/csrc/exec.hip", "paper_2205_10091_amd/csrc/gemm_tile.h",
                   "paper_2205_10091_amd/csrc/gates.h", "paper_2205_10091_amd/csrc/ops.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -59,9 +64,11 @@ def measured_traffic(workload, kernel):
     return e["hbm_bytes_per_launch"]
 
 
-def roofline(profile, workload):
+def roofline(profile, workload, precision=0):
     """Dominant kernel (most time over a step) with its algorithmic bytes /
-    flops per launch over its mean launch duration."""
+    flops per launch over its mean launch duration.  Split-BF16 GEMM tiles
+    (precision 1) are priced against the BF16 MFMA peak with the flops the
+    matrix cores execute: three BF16 products per real product."""
     kinds, ms, flops, by = profile
     agg = {}
     for k, t, f, b in zip(kinds, ms, flops, by):
@@ -76,12 +83,18 @@ def roofline(profile, workload):
     name = KIND_NAMES[k]
     if ai > PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
         # above the ridge: FP32 MFMA for the GEMM tiles, FP32 vector ALU else
-        rl = {"bound": "mfma" if name == "k_gemm" else "alu",
+        gemm = name in ("k_gemm", "k_gemm_wide")
+        rl = {"bound": "mfma" if gemm else "alu",
               "achieved": f / secs / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
+        if gemm and precision == 1:
+            rl.update({"achieved": 3 * f / secs / 1e12, "peak": PEAK_BF16_TFLOPS,
+                       "dtype": "bf16 (hi/lo split, 3 products per real product)",
+                       "algorithmic_tflops": f / secs / 1e12})
     else:
         rl = {"bound": "hbm", "achieved": b / secs / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     rl["frac"] = rl["achieved"] / rl["peak"]
-    rl["traffic"] = measured_traffic(workload, name)
+    rl["traffic"] = measured_traffic(workload, name + ("_bf16x3" if precision == 1 and
+                                                       name.startswith("k_gemm") else ""))
     rl.update({"kernel": name, "launches_per_step": n, "mean_launch_us": t / n * 1e3,
                "alg_bytes_per_launch": b / n, "alg_flops_per_launch": f / n})
     tot = sum(x[0] for x in agg.values())
@@ -171,6 +184,36 @@ def serve_workload(args, out):
                 "serving": runs})
 
 
+def wide_workload(trials, steps=3):
+    """6x6 fSim grid amplitude at depth 12 in FP32 and split BF16: an
+    evaluation is dominated by GEMM nodes in 128 x 128 tiles.  No oracle
+    value exists at this size (the state has 2^36 entries), so the two
+    precisions are compared with each other; the 4x6 depth-12 and 6x6
+    depth-8 grids pin the same tiles to the oracle in the GPU tests."""
+    import torch
+    import tcgen
+    from paper_2205_10091_amd import api
+    circ, p, amp = tcgen.workload_grid_amplitude(6, 6, 12)
+    params = torch.from_numpy(p).to("cuda:0")
+    res, vals = {"workload": "grid6x6_d12_amplitude"}, {}
+    for prec, key in ((0, "fp32"), (1, "bf16x3")):
+        plan = api.compile(circ, amp, n_trials=trials, seed=1, precision=prec)
+        info = plan.info()
+        out = torch.empty(2, dtype=torch.float64, device="cuda:0")
+        dt, _ = timed(lambda: plan.contract_device(params, out), steps, 1)
+        vals[key] = complex(*out.cpu().numpy())
+        rl, share = roofline(plan.profile(params, which=0, reps=1), "wide", precision=prec)
+        res[key] = {"evals_per_s": steps / dt, "ms_per_step": dt / steps * 1e3,
+                    "achieved_tflops": info.flops / (dt / steps) / 1e12,
+                    "roofline": rl, "time_share_by_kernel": share,
+                    "wide_nodes": info.n_wide_nodes, "gemm_nodes": info.n_gemm_nodes,
+                    "flops": info.flops, "workspace_bytes": int(info.workspace_bytes)}
+        del plan
+        torch.cuda.empty_cache()
+    res["rel_diff_bf16x3_vs_fp32"] = abs(vals["bf16x3"] - vals["fp32"]) / max(abs(vals["fp32"]), 2 ** -18)
+    return res
+
+
 def timed(step, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -189,7 +232,7 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="vqe",
-                    choices=["vqe", "batched", "forward", "grid", "serve"])
+                    choices=["vqe", "batched", "forward", "grid", "wide", "serve"])
     ap.add_argument("--trials", type=int, default=32, help="greedy path trials")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -276,6 +319,19 @@ def main():
         out["rel_err_zz"] = abs(z - sv.energy(circ, p, zz))
     elif args.workload == "serve":
         pass  # handled below
+    elif args.workload == "wide":
+        # an evaluation takes about 0.3 s: at most 10 timed steps
+        out["steps"], out["warmup"] = min(args.steps, 10), 1
+        w = wide_workload(args.trials, steps=out["steps"])
+        f = w["fp32"]
+        out.update({"metric": "circuit evals/s (6x6 fSim grid amplitude, depth 12)",
+                    "value": f["evals_per_s"], "unit": "evals/s",
+                    "ms_per_step": f["ms_per_step"], "dtype": "c64 (fp32)",
+                    "config": {"workload": "grid6x6_d12_amplitude", "batch": 1},
+                    "achieved_tflops": f["achieved_tflops"], "roofline": f["roofline"],
+                    "time_share_by_kernel": f["time_share_by_kernel"],
+                    "bf16x3": w["bf16x3"],
+                    "rel_diff_bf16x3_vs_fp32": w["rel_diff_bf16x3_vs_fp32"]})
     else:
         circ, p, amp = tcgen.workload_grid_amplitude()
         t0 = time.perf_counter()
@@ -305,7 +361,7 @@ def main():
     if args.workload == "serve":
         serve_workload(args, out)
         out["roofline"] = None   # a mix of plans: see the per-workload runs
-    else:
+    elif args.workload != "wide":
         out["plan"] = {"flops": info.flops, "grad_flops": info.grad_flops,
                        "alg_bytes": info.alg_bytes + info.grad_alg_bytes,
                        "workspace_bytes": int(info.workspace_bytes), "nodes": info.n_nodes,
@@ -349,6 +405,9 @@ def main():
         out["forward_chain_latency_us"] = {"p50": float(np.percentile(lat, 50)),
                                            "p99": float(np.percentile(lat, 99)),
                                            "evals_per_s": 1e6 / float(np.mean(lat))}
+
+    if args.workload == "vqe" and not args.no_extras:
+        out["wide_nodes"] = wide_workload(args.trials)
 
     if args.copy_calibration:
         n = args.copy_calibration // 4

@@ -375,7 +375,8 @@ tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
  * kinds[i] (0 leaf materialisation, 2 MFMA GEMM tiles of one tree level,
  * 3 gather contractions of one tree level, 4 FP64 root sum, 5 FP64
  * gradient sum, 6 term mode: all terms' trees, forward pass with the leaves
- * or reverse sweep), the mean duration ms[i], and the kernel's algorithmic
+ * or reverse sweep, 7 MFMA GEMM nodes of one tree level in 128 x 128
+ * tiles), the mean duration ms[i], and the kernel's algorithmic
  * flops[i] and bytes[i] (operands read once plus results written once).
  * which: 0 the forward sequence, 1 forward plus reverse sweep (needs
  * want_grad).  In contractions the two kernels of a level may overlap. */

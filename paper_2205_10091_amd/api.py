@@ -227,7 +227,7 @@ class Plan:
         eager replay with HIP events around each kernel (a level has a GEMM
         and a gather kernel)."""
         info = self.info()
-        cap = 2 * (info.n_launches + info.n_grad_launches) + 8
+        cap = 3 * (info.n_launches + info.n_grad_launches) + 8
         kinds = np.zeros(cap, np.int32)
         ms, fl, by = (np.zeros(cap, np.float64) for _ in range(3))
         n = C.c_int32()

@@ -52,14 +52,14 @@ struct Fork {
 };
 
 // Launch parts of a level: GEMM tiles, gather items.
-constexpr int PART_GEMM = 1, PART_GATHER = 2;
+constexpr int PART_GEMM = 1, PART_GATHER = 2, PART_WIDE = 4;
 
 // Enqueue one launch of `kind` covering all `segs` (at most MAX_SEG, all of
 // that kind) on `stream`; for levels, only the kernels named in `parts`,
 // forked as above when `fork` is given.
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
                      int precision, const Fork* fork = nullptr,
-                     int parts = PART_GEMM | PART_GATHER);
+                     int parts = PART_GEMM | PART_GATHER | PART_WIDE);
 
 // Asynchronous upload of a plan's tables and seeds into a workspace.
 void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStream_t stream);

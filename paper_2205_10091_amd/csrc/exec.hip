@@ -93,6 +93,7 @@ struct LevelArgs {
   uint64_t split_units;  // split-K output tiles over all segments
   uint64_t gsplit_units;  // split gather units over all segments
   uint64_t wide_tiles;    // 128 x 128 tiles over all segments
+  uint64_t wide_chunks;   // split BF16: operand chunks of the split pass
   uint64_t gc_work;
   uint64_t gs_work;       // split gather items over all segments
 };
@@ -330,13 +331,60 @@ template <int PREC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_gemm_wide(LevelArgs a) {
   using Smem = typename std::conditional<PREC == TC_PREC_BF16X3, SmemWideBF16, SmemWideF32>::type;
-  __shared__ Smem smem;
+  __shared__ Smem smem[PREC == TC_PREC_BF16X3 ? 2 : 1];
   for (uint64_t tile = blockIdx.x; tile < a.wide_tiles; tile += gridDim.x) {
     const LevelSeg& S = a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.wide_start; })];
     const uint64_t lt = tile - S.wide_start;
     const uint32_t oi = __builtin_amdgcn_readfirstlane(find_item(S.wide_ops, S.n_wide, lt));
     const DevOp op = S.wide_ops[oi];
-    gemm_wide<PREC == TC_PREC_BF16X3 ? 1 : 0>(op, lt - op.work0, S.tab, S.arena, smem);
+    gemm_wide<PREC == TC_PREC_BF16X3 ? 1 : 0>(
+        op, lt - op.work0, S.tab, S.arena,
+        reinterpret_cast<const uint4*>(S.split.part + op.part), smem);
+  }
+}
+
+// Split pass of a level's wide ops in split BF16: every operand element as
+// hi + lo bfloat16 numbers, in 64-byte chunks of 8 k (layout at
+// split_chunk).  Thread w writes chunk w of the level: per op, A's chunks
+// (k fastest: contiguous reads) then B's (n fastest: coalesced reads of
+// B's k rows).
+__global__ void __launch_bounds__(256) k_split_wide(LevelArgs a) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.wide_chunks; w += stride) {
+    uint64_t e = w;
+    for (uint32_t s = 0; s < a.nseg; ++s) {
+      const LevelSeg& S = a.seg[s];
+      for (uint32_t o = 0; o < S.n_wide; ++o) {
+        const DevOp& op = S.wide_ops[o];
+        const uint64_t kc = op.K / 8, ra = op.a_bs ? op.rows : 1, rb = op.b_bs ? op.rows : 1;
+        const uint64_t na = ra * op.M * kc, nb = rb * op.N * kc;
+        if (e >= na + nb) {
+          e -= na + nb;
+          continue;
+        }
+        uint4* dst = reinterpret_cast<uint4*>(S.split.part + op.part) + 4 * e;
+        float2 x[8];
+        if (e < na) {
+          const uint64_t row = e / kc, k = (e % kc) * 8;  // row = r M + m
+          const float2* src = S.arena + op.a + (row / op.M) * op.a_bs + (row % op.M) * op.K + k;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) x[q] = src[q];
+          split_chunk(x, dst);
+        } else {
+          const uint64_t f = e - na;
+          const uint64_t n = f % op.N, k = ((f / op.N) % kc) * 8, r = f / (op.N * kc);
+          const float2* src = S.arena + op.b + r * op.b_bs + k * op.N + n;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) x[q] = src[(uint64_t)q * op.N];
+          // B's chunks are stored by (r, n, kc)
+          split_chunk(x, reinterpret_cast<uint4*>(S.split.part + op.part) +
+                             4 * (na + (r * op.N + n) * kc + k / 8));
+        }
+        e = ~uint64_t(0);  // done
+        break;
+      }
+      if (e == ~uint64_t(0)) break;
+    }
   }
 }
 
@@ -758,7 +806,8 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
     }
     case L_LEVEL: {
       LevelArgs a{};
-      uint64_t tiles = 0, wtiles = 0, work = 0, sunits = 0, gsunits = 0, gswork = 0, htiles = 0;
+      uint64_t tiles = 0, wtiles = 0, work = 0, sunits = 0, gsunits = 0, gswork = 0, htiles = 0,
+               wchunks = 0;
       for (int i = 0; i < nseg; ++i) {
         const SegRef& s = segs[i];
         const WorkspaceLayout& L = *s.lay;
@@ -772,6 +821,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.n_wide = s.launch->hend - s.launch->hbegin;
         g.wide_start = htiles;
         htiles += s.launch->htiles;
+        wchunks += s.launch->wchunks;
         g.gc_ops = ops + s.launch->begin;
         g.n_gc = s.launch->xbegin - s.launch->begin;
         g.gs_ops = ops + s.launch->xbegin;
@@ -807,17 +857,20 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.gc_work = work;
       a.gs_work = gswork;
       a.wide_tiles = htiles;
+      a.wide_chunks = wchunks;
       a.tile_blocks = (unsigned)std::min<uint64_t>(tiles, (uint64_t)n_cu * 8);
       const unsigned wvb = (unsigned)std::min<uint64_t>((wtiles + 3) / 4, (uint64_t)n_cu * 16);
       const unsigned gmb = (parts & PART_GEMM) ? a.tile_blocks + wvb : 0u;
-      const unsigned whb = (parts & PART_GEMM) ? (unsigned)std::min<uint64_t>(htiles, (uint64_t)n_cu) : 0u;
+      const unsigned whb = (parts & PART_WIDE) ? (unsigned)std::min<uint64_t>(htiles, (uint64_t)n_cu) : 0u;
       const unsigned gcb = (parts & PART_GATHER) && work ? grid_for(work, 256, n_cu) : 0u;
       const unsigned gsb = (parts & PART_GATHER) && gswork ? grid_for(gswork, 256, n_cu) : 0u;
       auto gemm = [&](hipStream_t st) {
         if (whb) {
-          if (precision == TC_PREC_BF16X3)
+          if (precision == TC_PREC_BF16X3) {
+            // the operands' BF16 planes first
+            hipLaunchKernelGGL(k_split_wide, dim3(grid_for(wchunks, 256, n_cu)), dim3(256), 0, st, a);
             hipLaunchKernelGGL(k_gemm_wide<TC_PREC_BF16X3>, dim3(whb), dim3(256), 0, st, a);
-          else
+          } else
             hipLaunchKernelGGL(k_gemm_wide<TC_PREC_C64>, dim3(whb), dim3(256), 0, st, a);
         }
         if (!gmb) return;
@@ -927,7 +980,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
 }
 
 static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& seq,
-                    int parts = PART_GEMM | PART_GATHER) {
+                    int parts = PART_GEMM | PART_GATHER | PART_WIDE) {
   const Fork fork{D.side, D.fork_start, D.fork_done};
   for (const Launch& x : seq) {
     SegRef s{&P, D.ws, &D.lay, &x};
@@ -1104,11 +1157,13 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
   std::vector<Entry> seq;
   for (const Launch& L : all) {
     if (L.kind != L_LEVEL) {
-      seq.push_back({L, L.kind, PART_GEMM | PART_GATHER, L.flops, L.bytes});
+      seq.push_back({L, L.kind, PART_GEMM | PART_GATHER | PART_WIDE, L.flops, L.bytes});
       continue;
     }
-    if (L.tiles || L.wtiles || L.htiles)
-      seq.push_back({L, PROF_GEMM, PART_GEMM, L.gemm_flops, L.gemm_bytes});
+    if (L.htiles) seq.push_back({L, PROF_WIDE, PART_WIDE, L.wide_flops, L.wide_bytes});
+    if (L.tiles || L.wtiles)
+      seq.push_back({L, PROF_GEMM, PART_GEMM, L.gemm_flops - L.wide_flops,
+                     L.gemm_bytes - L.wide_bytes});
     if (L.work || L.xwork)
       seq.push_back({L, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops, L.bytes - L.gemm_bytes});
   }

@@ -625,12 +625,35 @@ __device__ __forceinline__ void wide_tile(const DevOp& op, uint64_t u, uint64_t&
   }
 }
 
-// One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA,
-// 1: split BF16.
-template <int PREC, typename Smem>
+// Split-BF16 operand planes (written by the level's split pass): a chunk
+// of 64 bytes per row (A row m, B column n) and 8 k, holding re hi, re lo,
+// im hi, im lo of the 8 elements; chunk (r, row, kc) at index
+// (r rows + row) K / 8 + kc, A's chunks first, B's after them.
+__device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restrict__ dst) {
+  bf8 rh, rl, ih, il;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    split_into(x[q].x, rh, rl, q);
+    split_into(x[q].y, ih, il, q);
+  }
+  dst[0] = *reinterpret_cast<const uint4*>(&rh);
+  dst[1] = *reinterpret_cast<const uint4*>(&rl);
+  dst[2] = *reinterpret_cast<const uint4*>(&ih);
+  dst[3] = *reinterpret_cast<const uint4*>(&il);
+}
+
+// One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA
+// on the complex64 operands, 1: split BF16 on the operands' BF16 planes
+// (`planes`: the op's chunks).  Split BF16 runs two LDS stages: while the
+// MFMAs consume stage s, stage s + 1 goes from registers into the other
+// buffer and the global loads of stage s + 2 are in flight, with one
+// barrier per stage; FP32 one stage with the next stage's loads in flight.
+template <int PREC, typename Smem, int NB>
 __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
                                           const uint32_t* __restrict__ tab,
-                                          float2* __restrict__ arena, Smem& S) {
+                                          float2* __restrict__ arena,
+                                          const uint4* __restrict__ planes, Smem (&S)[NB]) {
+  static_assert(NB == (PREC == 1 ? 2 : 1), "LDS stages");
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -638,18 +661,61 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
   uint32_t tm, tn;
   wide_tile(op, u, r, tm, tn);
   const uint32_t m0 = tm * HM, n0 = tn * HN, K = op.K, N = op.N;
-  // operand loads: A row (t / 2), k half (t % 2) * 16: 16 complex; B k rows
-  // 8 (t / 64) .. + 7, columns 2 (t % 64) and + 1
+  // FP32 operand loads: A row (t / 2), k half (t % 2) * 16: 16 complex; B
+  // k rows 8 (t / 64) .. + 7, columns 2 (t % 64) and + 1.  Split BF16: the
+  // chunks of A row (t / 2) and B column (t / 2), k half (t % 2) * 16: two
+  // chunks (128 bytes) each.
   const float4* pA = reinterpret_cast<const float4*>(
       arena + op.a + r * op.a_bs + (uint64_t)(m0 + (t >> 1)) * K + (t & 1) * 16);
   const float2* pB0 = arena + op.b + r * op.b_bs + (uint64_t)(8 * (t >> 6)) * N + n0 + 2 * (t & 63);
+  const uint64_t kc = K / 8;
+  const uint4* qA = planes + 4 * (((op.a_bs ? r * op.M : 0) + m0 + (t >> 1)) * kc + (t & 1) * 2);
+  const uint4* qB = planes + 4 * ((op.a_bs ? op.rows : 1) * (uint64_t)op.M * kc +
+                                  ((op.b_bs ? r * op.N : 0) + n0 + (t >> 1)) * kc + (t & 1) * 2);
   float4 ra[8], rb[8];
   auto fetch = [&](uint32_t k0) {
+    if constexpr (PREC == 0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) ra[q] = pA[k0 / 2 + q];
+      for (int q = 0; q < 8; ++q) ra[q] = pA[k0 / 2 + q];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      rb[q] = *reinterpret_cast<const float4*>(pB0 + (uint64_t)(k0 + q) * N);
+      for (int q = 0; q < 8; ++q)
+        rb[q] = *reinterpret_cast<const float4*>(pB0 + (uint64_t)(k0 + q) * N);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint4 x = qA[k0 / 2 + q], y = qB[k0 / 2 + q];  // 4 uint4 a chunk of 8 k
+        ra[q] = *reinterpret_cast<const float4*>(&x);
+        rb[q] = *reinterpret_cast<const float4*>(&y);
+      }
+    }
+  };
+  // registers -> LDS stage
+  auto stage = [&](Smem& D) {
+    if constexpr (PREC == 0) {
+      const int row = t >> 1, kh = (t & 1) * 16;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        D.A[0][kh + 2 * q][row] = ra[q].x;
+        D.A[1][kh + 2 * q][row] = ra[q].y;
+        D.A[0][kh + 2 * q + 1][row] = ra[q].z;
+        D.A[1][kh + 2 * q + 1][row] = ra[q].w;
+      }
+      const int kg = 8 * (t >> 6), n = 2 * (t & 63);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        *reinterpret_cast<float2*>(&D.B[0][kg + q][n]) = make_float2(rb[q].x, rb[q].z);
+        *reinterpret_cast<float2*>(&D.B[1][kg + q][n]) = make_float2(rb[q].y, rb[q].w);
+      }
+    } else {
+      // plane p = 2 re/im + hi/lo of chunk q / 4 (k half + 8 (q / 4))
+      const int row = t >> 1, kh = (t & 1) * 16;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int p = q & 3, k = kh + 8 * (q >> 2);
+        *reinterpret_cast<float4*>(&D.A[p >> 1][p & 1][row][k]) = ra[q];
+        *reinterpret_cast<float4*>(&D.B[p >> 1][p & 1][row][k]) = rb[q];
+      }
+    }
   };
   f4 cr[4][4], ci[4][4];
 #pragma unroll
@@ -659,74 +725,28 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
       cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
-  fetch(0);
-  for (uint32_t k0 = 0; k0 < K; k0 += HK) {
-    // registers -> LDS
-    if constexpr (PREC == 0) {
-      const int row = t >> 1, kh = (t & 1) * 16;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        S.A[0][kh + 2 * q][row] = ra[q].x;
-        S.A[1][kh + 2 * q][row] = ra[q].y;
-        S.A[0][kh + 2 * q + 1][row] = ra[q].z;
-        S.A[1][kh + 2 * q + 1][row] = ra[q].w;
-      }
-      const int kg = 8 * (t >> 6), n = 2 * (t & 63);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        *reinterpret_cast<float2*>(&S.B[0][kg + q][n]) = make_float2(rb[q].x, rb[q].z);
-        *reinterpret_cast<float2*>(&S.B[1][kg + q][n]) = make_float2(rb[q].y, rb[q].w);
-      }
-    } else {
-      const int row = t >> 1, kh = (t & 1) * 16;
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        bf8 rh, rl, ih, il;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 v = ra[4 * half + q];
-          split_into(v.x, rh, rl, 2 * q);
-          split_into(v.y, ih, il, 2 * q);
-          split_into(v.z, rh, rl, 2 * q + 1);
-          split_into(v.w, ih, il, 2 * q + 1);
-        }
-        *reinterpret_cast<bf8*>(&S.A[0][0][row][kh + 8 * half]) = rh;
-        *reinterpret_cast<bf8*>(&S.A[0][1][row][kh + 8 * half]) = rl;
-        *reinterpret_cast<bf8*>(&S.A[1][0][row][kh + 8 * half]) = ih;
-        *reinterpret_cast<bf8*>(&S.A[1][1][row][kh + 8 * half]) = il;
-      }
-      const int kg = 8 * (t >> 6), n = 2 * (t & 63);
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {  // column n + c
-        bf8 rh, rl, ih, il;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          split_into(c ? rb[q].z : rb[q].x, rh, rl, q);
-          split_into(c ? rb[q].w : rb[q].y, ih, il, q);
-        }
-        *reinterpret_cast<bf8*>(&S.B[0][0][n + c][kg]) = rh;
-        *reinterpret_cast<bf8*>(&S.B[0][1][n + c][kg]) = rl;
-        *reinterpret_cast<bf8*>(&S.B[1][0][n + c][kg]) = ih;
-        *reinterpret_cast<bf8*>(&S.B[1][1][n + c][kg]) = il;
-      }
-    }
-    __syncthreads();
-    if (k0 + HK < K) fetch(k0 + HK);
+  // MFMAs over one LDS stage
+  auto compute = [&](const Smem& D) {
     if constexpr (PREC == 0) {
 #pragma unroll
       for (int kk = 0; kk < HK; kk += 4) {
         const int kr = kk + (lane >> 4);
-        float br[4], bi[4], nbi[4];
+        float br[4], bi[4], nbi[4], ar4[4], ai4[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          br[j] = S.B[0][kr][wn * 64 + j * 16 + (lane & 15)];
-          bi[j] = S.B[1][kr][wn * 64 + j * 16 + (lane & 15)];
-          nbi[j] = -bi[j];
+          br[j] = D.B[0][kr][wn * 64 + j * 16 + (lane & 15)];
+          bi[j] = D.B[1][kr][wn * 64 + j * 16 + (lane & 15)];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float ar = S.A[0][kr][wm * 64 + i * 16 + (lane & 15)];
-          const float ai = S.A[1][kr][wm * 64 + i * 16 + (lane & 15)];
+          ar4[i] = D.A[0][kr][wm * 64 + i * 16 + (lane & 15)];
+          ai4[i] = D.A[1][kr][wm * 64 + i * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) nbi[j] = -bi[j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float ar = ar4[i], ai = ai4[i];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[j], cr[i][j], 0, 0, 0);
@@ -741,22 +761,28 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
       }
     } else {
       const int kr = 8 * (lane >> 4);
-      bf8 b[4][2][2];  // [block][re/im][hi/lo]
+      // every fragment of the stage first (B's, then A's block by block):
+      // the MFMAs of block i then wait only for the reads they use, and the
+      // reads of the later blocks land while they run
+      bf8 b[4][2][2], aa[4][2][2];  // [block][re/im][hi/lo]
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int h = 0; h < 2; ++h)
-            b[j][c][h] = *reinterpret_cast<const bf8*>(&S.B[c][h][wn * 64 + j * 16 + (lane & 15)][kr]);
+            b[j][c][h] = *reinterpret_cast<const bf8*>(&D.B[c][h][wn * 64 + j * 16 + (lane & 15)][kr]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        bf8 a[2][2], na[2];  // [re/im][hi/lo]; na = -(imaginary part)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int h = 0; h < 2; ++h)
-            a[c][h] = *reinterpret_cast<const bf8*>(&S.A[c][h][wm * 64 + i * 16 + (lane & 15)][kr]);
+            aa[i][c][h] = *reinterpret_cast<const bf8*>(&D.A[c][h][wm * 64 + i * 16 + (lane & 15)][kr]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bf8(&a)[2][2] = aa[i];
+        bf8 na[2];  // -(imaginary part)
         na[0] = -a[1][0];
         na[1] = -a[1][1];
         // Cr += Ar Br - Ai Bi and Ci += Ar Bi + Ai Br, each real product
@@ -793,7 +819,30 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
         }
       }
     }
+  };
+  const uint32_t ns = K / HK;  // stages (K is a multiple of HK)
+  fetch(0);
+  if constexpr (PREC == 1) {
+    stage(S[0]);
     __syncthreads();
+    if (ns > 1) fetch(HK);
+    for (uint32_t s = 0; s < ns; ++s) {
+      // buffer s & 1 holds stage s; the other one was last read in stage
+      // s - 1, which ended with the barrier
+      if (s + 1 < ns) stage(S[(s + 1) & 1]);
+      if (s + 2 < ns) fetch((s + 2) * HK);
+      compute(S[s & 1]);
+      __syncthreads();
+    }
+  } else {
+    // FP32: one LDS stage (measured faster here than two)
+    for (uint32_t s = 0; s < ns; ++s) {
+      stage(S[0]);
+      __syncthreads();
+      if (s + 1 < ns) fetch((s + 1) * HK);
+      compute(S[0]);
+      __syncthreads();
+    }
   }
   // C: lane l holds, per block (i, j), rows 4 (l / 16) + v and column l % 16
   const uint64_t cb = op.c + r * op.c_bs;

@@ -709,7 +709,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       ++j;
     const bool term_mode = tstep;
     std::vector<DevOp> gc, gm, wv, wd;
-    double lf = 0, lb = 0, gf = 0, gb = 0;
+    double lf = 0, lb = 0, gf = 0, gb = 0, wf = 0, wb = 0;
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
       const PT& Bt = T[pend[k].b];
@@ -783,10 +783,19 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       const bool dense = op.a_k == lk && op.a_m == (lm | (lk << 5)) && op.b_n == ln &&
                          op.b_k == (lk | (ln << 5)) && op.a % 2 == 0 && op.b % 2 == 0 &&
                          op.a_bs % 2 == 0 && op.b_bs % 2 == 0;
+      // (split BF16: the operands' BF16 planes take 8 bytes per element of
+      // workspace, which must fit the memory budget)
+      const uint64_t planes_bytes =
+          8 * ((A.batched && B > 1 ? op.rows : 1) * (uint64_t)op.M * op.K +
+               (Bt.batched && B > 1 ? op.rows : 1) * (uint64_t)op.N * op.K);
+      const bool planes_fit = plan.precision != TC_PREC_BF16X3 || !plan.budget ||
+                              plan.arena_elems * 8 + planes_bytes <= plan.budget;
       const bool wide = to_gemm && block_tile && plan.wide_tiles && dense && op.M >= 128 &&
-                        op.N >= 128 && op.K >= 32 &&
+                        op.N >= 128 && op.K >= 32 && planes_fit &&
                         (plan.wide_tiles == 2 || (uint64_t)op.rows * (op.M / 128) * (op.N / 128) >= 256);
       if (wide) {
+        wf += f;
+        wb += by;
         op.tiles_m = op.M / 128;
         op.tiles_n = op.N / 128;
         op.flags |= OPF_WIDE;
@@ -827,6 +836,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.bytes = lb;
     L.gemm_flops = gf;
     L.gemm_bytes = gb;
+    L.wide_flops = wf;
+    L.wide_bytes = wb;
     // split-K: a GEMM node with too few output tiles to fill the chip (256
     // CUs) cuts K into slices of at least 64; each slice writes a partial
     // tile and the level's reduction kernel adds them in slice order.  The
@@ -868,10 +879,22 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.send = (uint32_t)plan.split_units.size();
     L.wend = (uint32_t)plan.ops.size();
     L.wtiles = wtiles;
+    // wide tiles in split BF16 read their operands as BF16 planes written
+    // by the level's split pass into the split region: chunks of 8 k of one
+    // row (A row m, B column n) holding the 4 planes (re/im, hi/lo) of 8
+    // bfloat16 numbers each, 64 bytes; A's chunks then B's from op.part.
     L.hbegin = (uint32_t)plan.ops.size();
     for (DevOp& op : wd) {
       op.work0 = L.htiles;
       L.htiles += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
+      if (plan.precision == TC_PREC_BF16X3) {
+        part = (part + 63) & ~uint64_t(63);
+        op.part = part;
+        const uint64_t ra = op.a_bs ? op.rows : 1, rb = op.b_bs ? op.rows : 1;
+        const uint64_t chunks = (ra * op.M + rb * op.N) * (op.K / 8);
+        part += chunks * 16;  // 64 bytes a chunk
+        L.wchunks += chunks;
+      }
       plan.ops.push_back(op);
     }
     L.hend = (uint32_t)plan.ops.size();
@@ -1116,6 +1139,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         for (uint32_t o = L.hbegin; o < L.hend; ++o) {
           const DevOp& op = plan.ops[o];
           const uint32_t lm = __builtin_ctz(op.M), ln = __builtin_ctz(op.N), lk = __builtin_ctz(op.K);
+          const uint64_t chunks =
+              ((op.a_bs ? op.rows : 1) * (uint64_t)op.M + (op.b_bs ? op.rows : 1) * (uint64_t)op.N) *
+              (op.K / 8);
+          if (plan.precision == TC_PREC_BF16X3 &&
+              (op.part % 64 || op.part + chunks * 16 > plan.split_floats))
+            fail(TC_ERR_INVALID_ARG, "internal: wide op BF16 planes out of range");
           if (!(op.flags & OPF_WIDE) || op.ksplit != 1 || op.M % 128 || op.N % 128 || op.K % 32 ||
               op.tiles_m * 128 != op.M || op.tiles_n * 128 != op.N || op.a_k != lk ||
               op.a_m != (lm | (lk << 5)) || op.b_n != ln || op.b_k != (lk | (ln << 5)) ||

@@ -17,8 +17,9 @@ enum LaunchKind : int32_t {
   L_GRAD = 5,   // FP64 leaf-gradient reduction
   L_TERM = 6    // one workgroup per term runs the term's nodes of a run of steps
 };
-// kernel kinds reported by profiling: a level's two kernels
-constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3;
+// kernel kinds reported by profiling: a level's GEMM tiles (64 x 64 and
+// wave tiles), gathers, and 128 x 128 GEMM tiles
+constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3, PROF_WIDE = 7;
 
 constexpr uint64_t NO_ITEMS = ~uint64_t(0);
 // levels with at most this many gather items get a per-item op index table
@@ -46,6 +47,7 @@ struct Launch {
   uint64_t wtiles = 0;            // wave tiles
   uint32_t hbegin = 0, hend = 0;  // GEMM ops in 128 x 128 tiles (dense operands)
   uint64_t htiles = 0;            // 128 x 128 tiles
+  uint64_t wchunks = 0;           // split BF16: operand chunks of the split pass
   uint32_t sbegin = 0, send = 0;  // split-K output tiles, in Plan::split_units
   uint32_t gsbegin = 0, gsend = 0;  // split gather outputs (256 a unit), in Plan::gsplit_units
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
@@ -54,6 +56,8 @@ struct Launch {
   double bytes = 0;               // algorithmic bytes: operands read + results written
   double gemm_flops = 0;          // the part of flops / bytes in GEMM tiles
   double gemm_bytes = 0;
+  double wide_flops = 0;          // ... of which in 128 x 128 tiles
+  double wide_bytes = 0;
 };
 
 struct DeviceState;  // defined by the executor
