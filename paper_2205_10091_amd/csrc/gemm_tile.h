@@ -308,7 +308,9 @@ __device__ __forceinline__ void gemm_tile_f32(const DevOp op, uint64_t tile,
 // and B[k + l / 16][n0 + l % 16]), so there is no LDS staging and no
 // barrier.  This is the form for nodes too narrow for 64 x 64 tiles (M or
 // N below 64, as in per-row batched contractions), where a block tile
-// would mostly multiply padding.  K is a power of two >= 4.
+// would mostly multiply padding, and for batched nodes with M or N below
+// 16 (one block, the rows and columns past the edge masked).  K is a power
+// of two >= 4.
 // C of a wave tile: lane l holds C[m0 + 16 bi + 4 (l / 16) + v][n0 + 16 bj + l % 16]
 template <int BI, int BJ>
 __device__ __forceinline__ void store_wave(const DevOp& op, const TileCtx& c,
@@ -320,11 +322,15 @@ __device__ __forceinline__ void store_wave(const DevOp& op, const TileCtx& c,
   for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const uint32_t cm = ix(tab, op.c_m, c.m0 + bi * 16 + 4 * kq + v);
+      const uint32_t m = c.m0 + bi * 16 + 4 * kq + v;
+      if (m >= op.M) continue;  // M < 16: rows past the edge
+      const uint32_t cm = ix(tab, op.c_m, m);
 #pragma unroll
-      for (int bj = 0; bj < BJ; ++bj)
-        arena[c.cbase + cm + ix(tab, op.c_n, c.n0 + bj * 16 + i)] =
-            make_float2(cr[bi][bj][v], ci[bi][bj][v]);
+      for (int bj = 0; bj < BJ; ++bj) {
+        const uint32_t n = c.n0 + bj * 16 + i;
+        if (n < op.N)
+          arena[c.cbase + cm + ix(tab, op.c_n, n)] = make_float2(cr[bi][bj][v], ci[bi][bj][v]);
+      }
     }
 }
 
@@ -338,11 +344,13 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp op, uint64_t unit,
   const float2* __restrict__ B = c.B;
   const uint32_t m0 = c.m0, n0 = c.n0;
   const int i = lane & 15, kq = lane >> 4;
+  // M or N below 16: lanes past the edge read the last row / column (their
+  // products only reach outputs that are not stored)
   uint32_t am[BI], bn[BJ];
 #pragma unroll
-  for (int bi = 0; bi < BI; ++bi) am[bi] = ix(tab, op.a_m, m0 + bi * 16 + i);
+  for (int bi = 0; bi < BI; ++bi) am[bi] = ix(tab, op.a_m, min(m0 + bi * 16 + i, op.M - 1));
 #pragma unroll
-  for (int bj = 0; bj < BJ; ++bj) bn[bj] = ix(tab, op.b_n, n0 + bj * 16 + i);
+  for (int bj = 0; bj < BJ; ++bj) bn[bj] = ix(tab, op.b_n, min(n0 + bj * 16 + i, op.N - 1));
   f4 cr[BI][BJ], ci[BI][BJ];
 #pragma unroll
   for (int bi = 0; bi < BI; ++bi)

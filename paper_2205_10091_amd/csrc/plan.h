@@ -32,6 +32,8 @@ constexpr uint32_t TERM_MODE_MAX_KSTEPS = 8;
 // lanes a gather node may spread its k-split over: a level launch, a term's
 // workgroup
 constexpr uint64_t LEVEL_LANES = 65536, TERM_LANES = 1024;
+// batched nodes below the GEMM rule take masked wave tiles from this many rows
+constexpr uint32_t SMALL_WAVE_MIN_ROWS = 64;
 // index tables of one plan (uint32 entries)
 constexpr uint64_t TABLE_MAX_ENTRIES = uint64_t(1) << 27;
 
