@@ -60,6 +60,7 @@ struct LeafArgs {
 struct LevelSeg {
   const DevOp* gemm_ops;
   const DevOp* wave_ops;
+  const uint32_t* wave_unit_op;  // wave tile -> op index, or null (search)
   const DevOp* gc_ops;
   const uint32_t* tab;
   const uint32_t* item_op;  // gather item -> op index, or null (search)
@@ -263,12 +264,16 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
 }
 
 // One contraction level is two kernels over the same arguments: k_gemm runs
-// the level's wide nodes as 64 x 64 MFMA GEMM tiles, k_gather its other
-// nodes.  They touch disjoint outputs, so they may run concurrently, and
-// each keeps its own register budget (the GEMM tiles' accumulators would
-// otherwise cap the gather waves' occupancy).
+// the level's GEMM nodes as 64 x 64 MFMA tiles and wave tiles, k_gather its
+// other nodes.  They touch disjoint outputs, so they may run concurrently,
+// and each keeps its own register budget (the GEMM tiles' accumulators
+// would otherwise cap the gather waves' occupancy).  FP32 is held to 128
+// registers for 4 waves per SIMD: the batched per-row wave tiles are
+// latency bound, and 4 waves beat 3 without the cap (22.5 against 23.2 ms
+// for the 1024-row VQE sweep) despite a 12-byte spill.
 template <int PREC>
-__global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(PREC == TC_PREC_C64 ? 4 : 2))) k_gemm(LevelArgs a) {
   if (blockIdx.x >= a.tile_blocks) {
     // wave tiles: one unit per wavefront, grid-stride over the units
     const int lane = threadIdx.x & 63;
@@ -279,7 +284,8 @@ __global__ void __launch_bounds__(256) k_gemm(LevelArgs a) {
       const LevelSeg& S = a.seg[find_seg(a, u, [](const LevelSeg& s) { return s.wave_start; })];
       const uint64_t lu = u - S.wave_start;
       // the unit is the same for the whole wavefront: its op index is uniform
-      const uint32_t oi = __builtin_amdgcn_readfirstlane(find_item(S.wave_ops, S.n_wave, lu));
+      const uint32_t oi = __builtin_amdgcn_readfirstlane(
+          S.wave_unit_op ? S.wave_unit_op[lu] : find_item(S.wave_ops, S.n_wave, lu));
       const DevOp op = S.wave_ops[oi];
       const uint32_t shape = ((op.flags >> 12) & 3u) | (op_has_tables(op) ? 4u : 0u);
       switch (shape) {
@@ -816,6 +822,9 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.gemm_ops = ops + s.launch->gbegin;
         g.n_gemm = s.launch->gend - s.launch->gbegin;
         g.wave_ops = ops + s.launch->wbegin;
+        g.wave_unit_op = s.launch->wunit_begin != NO_ITEMS
+                             ? (const uint32_t*)(s.ws + L.item_op) + s.launch->wunit_begin
+                             : nullptr;
         g.n_wave = s.launch->wend - s.launch->wbegin;
         g.wide_ops = ops + s.launch->hbegin;
         g.n_wide = s.launch->hend - s.launch->hbegin;

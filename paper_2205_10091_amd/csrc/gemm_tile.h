@@ -86,21 +86,23 @@ struct TileCtx {
 // (n fastest, then m, then batch row); tile edges tm x tn in elements.
 __device__ __forceinline__ TileCtx unit_ctx(const DevOp& op, uint64_t u, const float2* arena,
                                             uint32_t tm_size, uint32_t tn_size) {
+  // P, tiles_n and tiles_m are powers of two (checked by the planner)
   const uint32_t P = op.ksplit;
+  const uint32_t lp = __builtin_ctz(P), ln = __builtin_ctz(op.tiles_n), lm = __builtin_ctz(op.tiles_m);
   TileCtx t;
-  t.slice = (uint32_t)(u % P);
-  uint64_t l = u / P;
+  t.slice = (uint32_t)(u & (P - 1));
+  uint64_t l = u >> lp;
   t.tile = l;
-  const uint32_t tn = (uint32_t)(l % op.tiles_n);
-  l /= op.tiles_n;
-  const uint32_t tm = (uint32_t)(l % op.tiles_m);
-  const uint64_t r = l / op.tiles_m;
+  const uint32_t tn = (uint32_t)(l & (op.tiles_n - 1));
+  l >>= ln;
+  const uint32_t tm = (uint32_t)(l & (op.tiles_m - 1));
+  const uint64_t r = l >> lm;
   t.A = arena + op.a + r * op.a_bs;
   t.B = arena + op.b + r * op.b_bs;
   t.cbase = op.c + r * op.c_bs;
   t.m0 = tm * tm_size;
   t.n0 = tn * tn_size;
-  const uint32_t ks = op.K / P;
+  const uint32_t ks = op.K >> lp;
   t.kb = t.slice * ks;
   t.ke = t.kb + ks;
   return t;

@@ -889,6 +889,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.send = (uint32_t)plan.split_units.size();
     L.wend = (uint32_t)plan.ops.size();
     L.wtiles = wtiles;
+    if (wtiles && wtiles <= WAVE_TABLE_MAX) {
+      // wave tile -> op (relative to L.wbegin): one load instead of a search
+      L.wunit_begin = plan.item_op.size();
+      plan.item_op.resize(plan.item_op.size() + wtiles);
+      uint32_t* it = plan.item_op.data() + L.wunit_begin;
+      for (uint32_t o = L.wbegin; o < L.wend; ++o) {
+        const uint64_t lo = plan.ops[o].work0;
+        const uint64_t hi = o + 1 < L.wend ? plan.ops[o + 1].work0 : wtiles;
+        for (uint64_t x = lo; x < hi; ++x) it[x] = o - L.wbegin;
+      }
+    }
     // wide tiles in split BF16 read their operands as BF16 planes written
     // by the level's split pass into the split region: chunks of 8 k of one
     // row (A row m, B column n) holding the 4 planes (re/im, hi/lo) of 8
@@ -1233,6 +1244,28 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         if (L.kind == L_TERM &&
             ((uint64_t)L.begin + plan.terms.size() > plan.ranges.size() || plan.terms.empty()))
           fail(TC_ERR_INVALID_ARG, "internal: term launch without ranges");
+    // per-wave-tile tables, and tile grids and slices in powers of two (the
+    // kernels decode tiles with shifts)
+    for (const auto* seq : {&plan.fwd, &plan.bwd})
+      for (const Launch& L : *seq) {
+        if (L.kind != L_LEVEL) continue;
+        for (uint32_t o = L.gbegin; o < L.hend; ++o) {
+          const DevOp& op = plan.ops[o];
+          auto pow2 = [](uint64_t v) { return v && !(v & (v - 1)); };
+          if (!pow2(op.tiles_m) || !pow2(op.tiles_n) || !pow2(op.ksplit))
+            fail(TC_ERR_INVALID_ARG, "internal: tile grid not in powers of two");
+        }
+        if (L.wunit_begin == NO_ITEMS) continue;
+        if (L.wunit_begin + L.wtiles > plan.item_op.size())
+          fail(TC_ERR_INVALID_ARG, "internal: wave tile table out of range");
+        for (uint64_t x = 0; x < L.wtiles; ++x) {
+          const uint32_t o = plan.item_op[L.wunit_begin + x];
+          if (o >= L.wend - L.wbegin) fail(TC_ERR_INVALID_ARG, "internal: wave tile table names a missing op");
+          const DevOp& op = plan.ops[L.wbegin + o];
+          if (x < op.work0 || x >= op.work0 + (uint64_t)op.rows * op.tiles_m * op.tiles_n * op.ksplit)
+            fail(TC_ERR_INVALID_ARG, "internal: wave tile table entry outside its op");
+        }
+      }
     // per-item tables: one entry per work item, naming an item of the launch
     for (const auto* seq : {&plan.fwd, &plan.bwd})
       for (const Launch& L : *seq) {

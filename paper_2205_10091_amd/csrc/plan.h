@@ -32,6 +32,8 @@ constexpr uint32_t TERM_MODE_MAX_KSTEPS = 8;
 // lanes a gather node may spread its k-split over: a level launch, a term's
 // workgroup
 constexpr uint64_t LEVEL_LANES = 65536, TERM_LANES = 1024;
+// levels with at most this many wave tiles get a per-tile op index table
+constexpr uint64_t WAVE_TABLE_MAX = uint64_t(1) << 20;
 // batched nodes below the GEMM rule take masked wave tiles from this many rows
 constexpr uint32_t SMALL_WAVE_MIN_ROWS = 64;
 // index tables of one plan (uint32 entries)
@@ -53,6 +55,7 @@ struct Launch {
   uint32_t sbegin = 0, send = 0;  // split-K output tiles, in Plan::split_units
   uint32_t gsbegin = 0, gsend = 0;  // split gather outputs (256 a unit), in Plan::gsplit_units
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
+  uint64_t wunit_begin = NO_ITEMS;  // per-wave-tile op index table in Plan::item_op
   bool with_leaves = false;       // L_TERM: materialise the leaves first
   double flops = 0;               // algorithmic flops (8 per complex MAC)
   double bytes = 0;               // algorithmic bytes: operands read + results written
