@@ -369,8 +369,10 @@ tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
                                   double* value_dev, double* grad_dev);
 
 /* Profiling.  Runs the plan's kernels eagerly (not as a graph), one after
- * another on the plan's stream, `reps` times with HIP events around every
- * kernel; params is a DEVICE pointer as for tc_contract.  For kernel i <
+ * another on the plan's stream, `reps` times; every kernel's start and end
+ * are stamped by its own dispatch (hipExtLaunchKernel events), so a
+ * duration holds no queueing gap.  params is a DEVICE pointer as for
+ * tc_contract.  For kernel i <
  * *n_launches (at most `cap` are written) it reports the kernel class
  * kinds[i] (0 leaf materialisation, 2 MFMA GEMM tiles of one tree level,
  * 3 gather contractions of one tree level, 4 FP64 root sum, 5 FP64
@@ -379,7 +381,9 @@ tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
  * tiles), the mean duration ms[i], and the kernel's algorithmic
  * flops[i] and bytes[i] (operands read once plus results written once).
  * which: 0 the forward sequence, 1 forward plus reverse sweep (needs
- * want_grad).  In contractions the two kernels of a level may overlap. */
+ * want_grad).  A level's GEMM and gather parts run one after the other
+ * here (in the graph they overlap); a part of several kernels (split-K and
+ * its reduction) is timed from its first kernel's start to its last's end. */
 tc_status tc_plan_profile(tc_plan* plan, const float* params, int32_t which,
                           int32_t reps, int32_t cap, int32_t* n_launches,
                           int32_t* kinds, double* ms, double* flops,

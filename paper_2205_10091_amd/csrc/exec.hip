@@ -13,6 +13,7 @@
 // plan, each pointing at that plan's own tables and workspace.  A single
 // plan is one segment; the serving engine merges the current launch of
 // every live request into one launch per kernel class.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -780,6 +781,27 @@ int device_cu_count(int device) {
   return prop.multiProcessorCount;
 }
 
+// Profiling: while set, every kernel launch records its start (the first
+// launch) and end (each launch, so the last one's remains) on these events,
+// stamped by the kernel dispatch itself rather than queued beside it.
+struct ProfEvents {
+  hipEvent_t start, stop;
+  bool started;
+};
+static thread_local ProfEvents* t_prof = nullptr;
+
+template <typename... Args>
+static void launch(void (*kernel)(Args...), dim3 grid, dim3 block, hipStream_t st,
+                   Args... args) {
+  if (t_prof) {
+    hipEvent_t s = t_prof->started ? nullptr : t_prof->start;
+    t_prof->started = true;
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, s, t_prof->stop, 0, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+  }
+}
+
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
                      int precision, const Fork* fork, int parts) {
   if (nseg <= 0) return;
@@ -807,7 +829,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.nseg = (uint32_t)nseg;
       a.total = w;
       if (w == 0) return;
-      hipLaunchKernelGGL(k_leaf, dim3(grid_for(w, 256, n_cu)), dim3(256), 0, stream, a);
+      launch(k_leaf, dim3(grid_for(w, 256, n_cu)), dim3(256), stream, a);
       break;
     }
     case L_LEVEL: {
@@ -877,26 +899,26 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         if (whb) {
           if (precision == TC_PREC_BF16X3) {
             // the operands' BF16 planes first
-            hipLaunchKernelGGL(k_split_wide, dim3(grid_for(wchunks, 256, n_cu)), dim3(256), 0, st, a);
-            hipLaunchKernelGGL(k_gemm_wide<TC_PREC_BF16X3>, dim3(whb), dim3(256), 0, st, a);
+            launch(k_split_wide, dim3(grid_for(wchunks, 256, n_cu)), dim3(256), st, a);
+            launch(k_gemm_wide<TC_PREC_BF16X3>, dim3(whb), dim3(256), st, a);
           } else
-            hipLaunchKernelGGL(k_gemm_wide<TC_PREC_C64>, dim3(whb), dim3(256), 0, st, a);
+            launch(k_gemm_wide<TC_PREC_C64>, dim3(whb), dim3(256), st, a);
         }
         if (!gmb) return;
         if (precision == TC_PREC_BF16X3)
-          hipLaunchKernelGGL(k_gemm<TC_PREC_BF16X3>, dim3(gmb), dim3(256), 0, st, a);
+          launch(k_gemm<TC_PREC_BF16X3>, dim3(gmb), dim3(256), st, a);
         else
-          hipLaunchKernelGGL(k_gemm<TC_PREC_C64>, dim3(gmb), dim3(256), 0, st, a);
+          launch(k_gemm<TC_PREC_C64>, dim3(gmb), dim3(256), st, a);
         // split-K tiles: their slices are all written once k_gemm is done
         if (a.split_units)
-          hipLaunchKernelGGL(k_reduce, dim3((unsigned)a.split_units), dim3(256), 0, st, a);
+          launch(k_reduce, dim3((unsigned)a.split_units), dim3(256), st, a);
       };
       auto gather = [&](hipStream_t st) {
-        if (gcb) hipLaunchKernelGGL(k_gather<false>, dim3(gcb), dim3(256), 0, st, a);
+        if (gcb) launch(k_gather<false>, dim3(gcb), dim3(256), st, a);
         if (gsb) {
-          hipLaunchKernelGGL(k_gather<true>, dim3(gsb), dim3(256), 0, st, a);
+          launch(k_gather<true>, dim3(gsb), dim3(256), st, a);
           // split sums: their slices are all written once k_gather is done
-          hipLaunchKernelGGL(k_reduce_g, dim3((unsigned)a.gsplit_units), dim3(256), 0, st, a);
+          launch(k_reduce_g, dim3((unsigned)a.gsplit_units), dim3(256), st, a);
         }
       };
       if ((gmb || whb) && (gcb || gsb) && fork) {
@@ -935,7 +957,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.arena = (float2*)(s.ws + L.arena);
       a.n_params = P.n_params;
       a.with_leaves = s.launch->with_leaves ? 1 : 0;
-      hipLaunchKernelGGL(k_term, dim3((unsigned)P.terms.size()), dim3(1024), 0, stream, a);
+      launch(k_term, dim3((unsigned)P.terms.size()), dim3(1024), stream, a);
       break;
     }
     case L_ROOT: {
@@ -955,7 +977,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       }
       a.nseg = (uint32_t)nseg;
       a.total = w;
-      hipLaunchKernelGGL(k_root, dim3((unsigned)((w * 64 + 255) / 256)), dim3(256), 0, stream,
+      launch(k_root, dim3((unsigned)((w * 64 + 255) / 256)), dim3(256), stream,
                          a);
       break;
     }
@@ -979,7 +1001,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.nseg = (uint32_t)nseg;
       a.total = w;
       if (w == 0) return;
-      hipLaunchKernelGGL(k_grad, dim3(grid_for(w * 64, 256, n_cu)), dim3(256), 0, stream, a);
+      launch(k_grad, dim3(grid_for(w * 64, 256, n_cu)), dim3(256), stream, a);
       break;
     }
     default:
@@ -1176,20 +1198,31 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
     if (L.work || L.xwork)
       seq.push_back({L, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops, L.bytes - L.gemm_bytes});
   }
-  std::vector<hipEvent_t> ev(seq.size() + 1, nullptr);
+  // per entry: the start of its first kernel to the end of its last, as
+  // stamped by the kernel dispatches (no queueing gap between launches)
+  std::vector<hipEvent_t> ev(2 * seq.size(), nullptr);
   std::vector<double> acc(seq.size(), 0.0);
+  std::vector<char> ran(seq.size(), 0);
   try {
     for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
     for (int r = 0; r < reps; ++r) {
-      HIP_CHECK(hipEventRecord(ev[0], D.stream));
       for (size_t i = 0; i < seq.size(); ++i) {
-        enqueue(P, D, std::vector<Launch>{seq[i].L}, seq[i].parts);
-        HIP_CHECK(hipEventRecord(ev[i + 1], D.stream));
+        ProfEvents pe{ev[2 * i], ev[2 * i + 1], false};
+        t_prof = &pe;
+        try {
+          enqueue(P, D, std::vector<Launch>{seq[i].L}, seq[i].parts);
+        } catch (...) {
+          t_prof = nullptr;
+          throw;
+        }
+        t_prof = nullptr;
+        ran[i] = pe.started;
       }
       HIP_CHECK(hipStreamSynchronize(D.stream));
       for (size_t i = 0; i < seq.size(); ++i) {
+        if (!ran[i]) continue;
         float t = 0;
-        HIP_CHECK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+        HIP_CHECK(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
         acc[i] += t;
       }
     }
