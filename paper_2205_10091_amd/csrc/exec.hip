@@ -1282,25 +1282,38 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
   if (o.batch < 1 || o.batch > (1 << 20)) tcx::fail(TC_ERR_INVALID_ARG, "batch must be in 1..2^20");
   if (o.precision != TC_PREC_C64 && o.precision != TC_PREC_BF16X3)
     tcx::fail(TC_ERR_UNSUPPORTED, "unknown precision");
-  auto* p = new tc_plan;
-  p->p.precision = o.precision;
-  p->p.batch = o.batch;
-  p->p.want_grad = o.want_grad ? 1 : 0;
-  p->p.device = o.device;
-  p->p.budget = o.mem_budget_bytes;
-  p->p.user_stream = o.stream;
-  if (o.gemm_min_k > 0) p->p.gemm_min_k = o.gemm_min_k;
-  if (o.gemm_min_macs > 0) p->p.gemm_min_macs = o.gemm_min_macs;
-  p->p.exec_mode = o.exec_mode;
-  p->p.wide_tiles = o.tile_mode == 0 ? 1 : (o.tile_mode == 1 ? 0 : 2);
-  p->p.checkpoint = o.checkpoint_every;
+  auto make = [&](int32_t wide_tiles) {
+    auto* p = new tc_plan;
+    p->p.precision = o.precision;
+    p->p.batch = o.batch;
+    p->p.want_grad = o.want_grad ? 1 : 0;
+    p->p.device = o.device;
+    p->p.budget = o.mem_budget_bytes;
+    p->p.user_stream = o.stream;
+    if (o.gemm_min_k > 0) p->p.gemm_min_k = o.gemm_min_k;
+    if (o.gemm_min_macs > 0) p->p.gemm_min_macs = o.gemm_min_macs;
+    p->p.exec_mode = o.exec_mode;
+    p->p.wide_tiles = wide_tiles;
+    p->p.checkpoint = o.checkpoint_every;
+    try {
+      tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    return p;
+  };
+  const int32_t wide = o.tile_mode == 0 ? 1 : (o.tile_mode == 1 ? 0 : 2);
   try {
-    tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));
-  } catch (...) {
-    delete p;
-    throw;
+    *out = make(wide);
+  } catch (const tcx::Error& e) {
+    // split BF16 under a memory budget: the wide tiles' BF16 planes may be
+    // what does not fit; the 64 x 64 tiles need none
+    if (e.status != TC_ERR_TOO_LARGE || o.precision != TC_PREC_BF16X3 || wide != 1 ||
+        !o.mem_budget_bytes)
+      throw;
+    *out = make(0);
   }
-  *out = p;
   return TC_OK;
   TC_GUARD_END
 }

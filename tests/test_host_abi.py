@@ -130,3 +130,47 @@ def test_plan_is_host_only_and_reports_sizes():
     with pytest.raises(L.TcxError) as e:
         api.Plan(net, path, batch=1024, want_grad=True, mem_budget_bytes=1 << 20)
     assert e.value.status == L.TC_ERR_TOO_LARGE
+
+
+def test_tile_mode_wide_nodes_and_split_sums_on_host():
+    # the 6x6 depth-12 grid's widest nodes take 128 x 128 tiles by default
+    # (the planner stores their operands dense), none with tile_mode 1
+    circ, p, amp = tcgen.workload_grid_amplitude(6, 6, 12)
+    net = api.Network(circ, amp)
+    path = api.Path(net, n_trials=32, seed=1)
+    auto = api.Plan(net, path).info()
+    assert auto.n_wide_nodes > 0
+    assert api.Plan(net, path, tile_mode=1).info().n_wide_nodes == 0
+    # split BF16 adds the operands' BF16 planes (8 bytes per element) to
+    # the workspace; under a budget that leaves no room for them the wide
+    # nodes fall back to 64 x 64 tiles instead of failing
+    b16 = api.Plan(net, path, precision=1).info()
+    assert b16.n_wide_nodes > 0 and b16.workspace_bytes > auto.workspace_bytes
+    ws64 = api.Plan(net, path, precision=1, tile_mode=1).info().workspace_bytes
+    budget = ws64 + (64 << 20)
+    assert budget < b16.workspace_bytes
+    tight = api.Plan(net, path, precision=1, mem_budget_bytes=budget).info()
+    assert tight.n_wide_nodes == 0 and tight.workspace_bytes <= budget
+    for bad in (-1, 3):
+        with pytest.raises(L.TcxError) as e:
+            api.Plan(net, path, tile_mode=bad)
+        assert e.value.status == L.TC_ERR_INVALID_ARG
+    # the 4x6 depth-12 grid ends in a long inner product: split sums
+    circ, p, amp = tcgen.workload_grid_amplitude(4, 6, 12)
+    net = api.Network(circ, amp)
+    path = api.Path(net, n_trials=32, seed=1)
+    info = api.Plan(net, path).info()
+    assert info.n_split_sums >= 1
+    # forced wide tiles on a small tree (used by the GPU tests) are valid plans
+    assert api.Plan(net, path, tile_mode=2).info().n_wide_nodes >= 0
+
+
+def test_batched_plan_uses_masked_wave_tiles():
+    # at 1024 rows, nodes with M, N, K >= 8 below the GEMM rule go to the
+    # GEMM branch (masked wave tiles): many more GEMM nodes than at 1 row
+    circ, P, obs = tcgen.workload_batched_vqe(batch=1024)
+    net = api.Network(circ, obs)
+    path = api.Path(net, n_trials=4, seed=1)
+    many = api.Plan(net, path, batch=1024, want_grad=True).info().n_gemm_nodes
+    few = api.Plan(net, path, batch=32, want_grad=True).info().n_gemm_nodes
+    assert many > 2 * max(few, 1)
