@@ -600,10 +600,16 @@ struct SmemWideF32 {
   float B[2][HK][HN + 16];  // [re/im][k][n]
 };
 struct SmemWideBF16 {
-  // [re/im][hi/lo][row][k], k contiguous: a lane reads 8 k at once
-  __attribute__((aligned(16))) __bf16 A[2][2][HM][HK + 8];
-  __attribute__((aligned(16))) __bf16 B[2][2][HN][HK + 8];
+  // [re/im][hi/lo][row][k], k contiguous in 16-byte chunks of 8 (a lane
+  // reads one chunk at once); chunk c of a row sits at c ^ ((row / 2) % 4),
+  // so that 8 lanes reading one chunk of 8 consecutive rows, or writing
+  // two chunks of 4 rows, touch all 32 banks once
+  __attribute__((aligned(16))) __bf16 A[2][2][HM][HK];
+  __attribute__((aligned(16))) __bf16 B[2][2][HN][HK];
 };
+__device__ __forceinline__ int wide_chunk(int row, int k) {
+  return (((k >> 3) ^ ((row >> 1) & 3)) << 3);
+}
 
 // x = hi + lo into element e of two bfloat16 vectors
 __device__ __forceinline__ void split_into(float x, bf8& hi, bf8& lo, int e) {
@@ -722,8 +728,8 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int p = q & 3, k = kh + 8 * (q >> 2);
-        *reinterpret_cast<float4*>(&D.A[p >> 1][p & 1][row][k]) = ra[q];
-        *reinterpret_cast<float4*>(&D.B[p >> 1][p & 1][row][k]) = rb[q];
+        *reinterpret_cast<float4*>(&D.A[p >> 1][p & 1][row][wide_chunk(row, k)]) = ra[q];
+        *reinterpret_cast<float4*>(&D.B[p >> 1][p & 1][row][wide_chunk(row, k)]) = rb[q];
       }
     }
   };
@@ -781,14 +787,16 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int h = 0; h < 2; ++h)
-            b[j][c][h] = *reinterpret_cast<const bf8*>(&D.B[c][h][wn * 64 + j * 16 + (lane & 15)][kr]);
+            b[j][c][h] = *reinterpret_cast<const bf8*>(
+                &D.B[c][h][wn * 64 + j * 16 + (lane & 15)][wide_chunk(lane & 15, kr)]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int h = 0; h < 2; ++h)
-            aa[i][c][h] = *reinterpret_cast<const bf8*>(&D.A[c][h][wm * 64 + i * 16 + (lane & 15)][kr]);
+            aa[i][c][h] = *reinterpret_cast<const bf8*>(
+                &D.A[c][h][wm * 64 + i * 16 + (lane & 15)][wide_chunk(lane & 15, kr)]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const bf8(&a)[2][2] = aa[i];
