@@ -73,6 +73,9 @@ struct LevelSeg {
   const DevOp* wide_ops;    // GEMM ops in 128 x 128 tiles
   uint64_t wide_start;      // first wide tile of this segment
   uint32_t n_wide;
+  const DevOp* rt_ops;      // row-tile ops (batched small nodes)
+  uint64_t rt_start;        // first row-tile workgroup of this segment
+  uint32_t n_rt;
   const DevOp* gs_ops;      // split gather ops (V == 1), in their own work space
   uint64_t gs_start;        // first split gather item of this segment
   uint32_t n_gs;
@@ -96,6 +99,7 @@ struct LevelArgs {
   uint64_t gsplit_units;  // split gather units over all segments
   uint64_t wide_tiles;    // 128 x 128 tiles over all segments
   uint64_t wide_chunks;   // split BF16: operand chunks of the split pass
+  uint64_t rt_blocks;     // row-tile workgroups over all segments
   uint64_t gc_work;
   uint64_t gs_work;       // split gather items over all segments
 };
@@ -536,6 +540,50 @@ __global__ void __launch_bounds__(256) k_reduce_g(LevelArgs a) {
       make_float2(acc.re, acc.im);
 }
 
+// Row tiles: workgroup b copies RPB (= op.tiles_m) whole batch rows of both
+// operands of one small batched node into LDS (a batched tensor's row is
+// one block of M K or K N elements, so the copy is coalesced; a shared
+// operand is copied once), then computes the rows' M N outputs each from
+// LDS, k in increasing order, and stores them.
+__global__ void __launch_bounds__(256) k_rowtile(LevelArgs a) {
+  __shared__ float2 buf[ROW_TILE_ELEMS];
+  const uint64_t b = blockIdx.x;
+  const LevelSeg& S = a.seg[find_seg(a, b, [](const LevelSeg& s) { return s.rt_start; })];
+  const uint64_t lb = b - S.rt_start;
+  const uint32_t oi = __builtin_amdgcn_readfirstlane(find_item(S.rt_ops, S.n_rt, lb));
+  const DevOp op = S.rt_ops[oi];
+  const uint32_t rpb = op.tiles_m;
+  const uint64_t r0 = (lb - op.work0) * rpb;
+  const uint32_t nr = (uint32_t)min((uint64_t)rpb, op.rows - r0);
+  const uint32_t MK = op.M * op.K, KN = op.K * op.N, MN = op.M * op.N;
+  const uint32_t ra = op.a_bs ? nr : 1, rb = op.b_bs ? nr : 1;
+  const int t = threadIdx.x;
+  const float2* __restrict__ A = S.arena + op.a + r0 * op.a_bs;
+  const float2* __restrict__ B = S.arena + op.b + r0 * op.b_bs;
+  // rows r0 .. r0 + nr - 1 of A, then of B (row stride a_bs, b_bs)
+  const uint32_t lmk = __builtin_ctz(MK), lkn = __builtin_ctz(KN);
+  for (uint32_t e = t; e < ra * MK; e += 256)
+    buf[e] = A[(uint64_t)(e >> lmk) * op.a_bs + (e & (MK - 1))];
+  for (uint32_t e = t; e < rb * KN; e += 256)
+    buf[ra * MK + e] = B[(uint64_t)(e >> lkn) * op.b_bs + (e & (KN - 1))];
+  __syncthreads();
+  const uint32_t lmn = __builtin_ctz(MN), ln = __builtin_ctz(op.N);
+  for (uint32_t o = t; o < nr * MN; o += 256) {
+    const uint32_t rr = o >> lmn, y = o & (MN - 1);
+    const uint32_t m = y >> ln, n = y & (op.N - 1);
+    const float2* Ar = buf + (op.a_bs ? rr * MK : 0) + ix(S.tab, op.a_m, m);
+    const float2* Br = buf + ra * MK + (op.b_bs ? rr * KN : 0) + ix(S.tab, op.b_n, n);
+    float re = 0.f, im = 0.f;
+    for (uint32_t k = 0; k < op.K; ++k) {
+      const float2 x = Ar[ix(S.tab, op.a_k, k)], w = Br[ix(S.tab, op.b_k, k)];
+      re += x.x * w.x - x.y * w.y;
+      im += x.x * w.y + x.y * w.x;
+    }
+    S.arena[op.c + (r0 + rr) * op.c_bs + ix(S.tab, op.c_m, m) + ix(S.tab, op.c_n, n)] =
+        make_float2(re, im);
+  }
+}
+
 // Gather ops of a level; SPLIT: the split ones (their own kernel, so that
 // the split bookkeeping takes no registers from the others).
 template <bool SPLIT>
@@ -835,7 +883,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
     case L_LEVEL: {
       LevelArgs a{};
       uint64_t tiles = 0, wtiles = 0, work = 0, sunits = 0, gsunits = 0, gswork = 0, htiles = 0,
-               wchunks = 0;
+               wchunks = 0, rtblocks = 0;
       for (int i = 0; i < nseg; ++i) {
         const SegRef& s = segs[i];
         const WorkspaceLayout& L = *s.lay;
@@ -855,6 +903,10 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         wchunks += s.launch->wchunks;
         g.gc_ops = ops + s.launch->begin;
         g.n_gc = s.launch->xbegin - s.launch->begin;
+        g.rt_ops = ops + s.launch->rbegin;
+        g.n_rt = s.launch->rend - s.launch->rbegin;
+        g.rt_start = rtblocks;
+        rtblocks += s.launch->rblocks;
         g.gs_ops = ops + s.launch->xbegin;
         g.n_gs = s.launch->end - s.launch->xbegin;
         g.gs_start = gswork;
@@ -889,12 +941,14 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.gs_work = gswork;
       a.wide_tiles = htiles;
       a.wide_chunks = wchunks;
+      a.rt_blocks = rtblocks;
       a.tile_blocks = (unsigned)std::min<uint64_t>(tiles, (uint64_t)n_cu * 8);
       const unsigned wvb = (unsigned)std::min<uint64_t>((wtiles + 3) / 4, (uint64_t)n_cu * 16);
       const unsigned gmb = (parts & PART_GEMM) ? a.tile_blocks + wvb : 0u;
       const unsigned whb = (parts & PART_WIDE) ? (unsigned)std::min<uint64_t>(htiles, (uint64_t)n_cu) : 0u;
       const unsigned gcb = (parts & PART_GATHER) && work ? grid_for(work, 256, n_cu) : 0u;
       const unsigned gsb = (parts & PART_GATHER) && gswork ? grid_for(gswork, 256, n_cu) : 0u;
+      const unsigned rtb = (parts & PART_GATHER) ? (unsigned)rtblocks : 0u;
       auto gemm = [&](hipStream_t st) {
         if (whb) {
           if (precision == TC_PREC_BF16X3) {
@@ -915,13 +969,14 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       };
       auto gather = [&](hipStream_t st) {
         if (gcb) launch(k_gather<false>, dim3(gcb), dim3(256), st, a);
+        if (rtb) launch(k_rowtile, dim3(rtb), dim3(256), st, a);
         if (gsb) {
           launch(k_gather<true>, dim3(gsb), dim3(256), st, a);
           // split sums: their slices are all written once k_gather is done
           launch(k_reduce_g, dim3((unsigned)a.gsplit_units), dim3(256), st, a);
         }
       };
-      if ((gmb || whb) && (gcb || gsb) && fork) {
+      if ((gmb || whb) && (gcb || gsb || rtb) && fork) {
         // GEMM tiles on the side stream, concurrent with the gather kernel
         HIP_CHECK(hipEventRecord(fork->start, stream));
         HIP_CHECK(hipStreamWaitEvent(fork->side, fork->start, 0));
@@ -931,7 +986,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         HIP_CHECK(hipStreamWaitEvent(stream, fork->done, 0));
       } else {
         if (gmb || whb) gemm(stream);
-        if (gcb || gsb) gather(stream);
+        if (gcb || gsb || rtb) gather(stream);
       }
       break;
     }
@@ -1195,7 +1250,7 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
     if (L.tiles || L.wtiles)
       seq.push_back({L, PROF_GEMM, PART_GEMM, L.gemm_flops - L.wide_flops,
                      L.gemm_bytes - L.wide_bytes});
-    if (L.work || L.xwork)
+    if (L.work || L.xwork || L.rblocks)
       seq.push_back({L, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops, L.bytes - L.gemm_bytes});
   }
   // per entry: the start of its first kernel to the end of its last, as

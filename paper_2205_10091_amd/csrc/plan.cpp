@@ -708,7 +708,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
            (!tstep || pend[j].term == pend[i].term))
       ++j;
     const bool term_mode = tstep;
-    std::vector<DevOp> gc, gm, wv, wd;
+    std::vector<DevOp> gc, gm, wv, wd, rt;
     double lf = 0, lb = 0, gf = 0, gb = 0, wf = 0, wb = 0;
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
@@ -824,6 +824,20 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         op.flags |= ((bi - 1) << 12) | ((bj - 1) << 13);
         wv.push_back(op);
         if (!pend[k].bwd) ++n_gemm_nodes;
+      } else if (!term_mode && op.rows >= SMALL_WAVE_MIN_ROWS &&
+                 (uint64_t)op.M * op.K + (uint64_t)op.K * op.N <= ROW_TILE_ELEMS) {
+        // row tiles: a batched node small per row (a gate absorbed into
+        // every row): a workgroup copies RPB whole rows of both operands
+        // into LDS once (coalesced: a row of a batched tensor is one block)
+        // and computes their outputs from there, where gather items would
+        // re-read the shared operand once per output group.  RPB (in
+        // tiles_m) is the largest power of two <= 64 whose rows fit.
+        const uint64_t per_row = (uint64_t)op.M * op.K + (uint64_t)op.K * op.N;
+        uint32_t rpb = 1;
+        while (rpb < 64 && 2 * rpb * per_row <= ROW_TILE_ELEMS) rpb *= 2;
+        op.tiles_m = rpb;
+        op.tiles_n = (op.rows + rpb - 1) / rpb;
+        rt.push_back(op);
       } else {
         // gather: split long sums over up to 64 lanes while the op is small,
         // else 4 outputs per thread along n
@@ -955,6 +969,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.gsend = (uint32_t)plan.gsplit_units.size();
     plan.split_floats = std::max(plan.split_floats, part);
     L.end = (uint32_t)plan.ops.size();
+    L.rbegin = L.end;
+    for (DevOp& op : rt) {
+      op.work0 = L.rblocks;
+      L.rblocks += op.tiles_n;
+      plan.ops.push_back(op);
+    }
+    L.rend = (uint32_t)plan.ops.size();
     if (!in_split) {
       L.xbegin = L.end;
       L.work = (w + 63) & ~uint64_t(63);
@@ -1160,6 +1181,18 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         // wide tiles: dense operands, whole 128 x 128 tiles, no split
         if (L.hbegin != L.wend || L.hend < L.hbegin || L.begin != L.hend)
           fail(TC_ERR_INVALID_ARG, "internal: wide op range");
+        // row tiles: whole rows of both operands within the LDS budget
+        if (L.rbegin != L.end || L.rend < L.rbegin)
+          fail(TC_ERR_INVALID_ARG, "internal: row-tile op range");
+        for (uint32_t o = L.rbegin; o < L.rend; ++o) {
+          const DevOp& op = plan.ops[o];
+          const uint64_t rpb = op.tiles_m;
+          if (rpb < 1 || rpb > 64 || (rpb & (rpb - 1)) || op.rows < 1 ||
+              rpb * ((uint64_t)op.M * op.K + (uint64_t)op.K * op.N) > ROW_TILE_ELEMS ||
+              op.tiles_n != (op.rows + rpb - 1) / rpb || op.ksplit != 1 ||
+              op.work0 != (o == L.rbegin ? 0 : plan.ops[o - 1].work0 + plan.ops[o - 1].tiles_n))
+            fail(TC_ERR_INVALID_ARG, "internal: row-tile op");
+        }
         for (uint32_t o = L.hbegin; o < L.hend; ++o) {
           const DevOp& op = plan.ops[o];
           const uint32_t lm = __builtin_ctz(op.M), ln = __builtin_ctz(op.N), lk = __builtin_ctz(op.K);

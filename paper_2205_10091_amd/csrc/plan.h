@@ -36,6 +36,9 @@ constexpr uint64_t LEVEL_LANES = 65536, TERM_LANES = 1024;
 constexpr uint64_t WAVE_TABLE_MAX = uint64_t(1) << 20;
 // batched nodes below the GEMM rule take masked wave tiles from this many rows
 constexpr uint32_t SMALL_WAVE_MIN_ROWS = 64;
+// row tiles: a workgroup stages whole batch rows of both operands in LDS,
+// at most this many complex elements (16 KB)
+constexpr uint32_t ROW_TILE_ELEMS = 2048;
 // index tables of one plan (uint32 entries)
 constexpr uint64_t TABLE_MAX_ENTRIES = uint64_t(1) << 27;
 
@@ -45,6 +48,8 @@ struct Launch {
   uint64_t work = 0;              // gather work items / leaf, root, grad items
   uint32_t xbegin = 0;            // L_LEVEL: split gather ops are [xbegin, end)
   uint64_t xwork = 0;             // their work items (a space of their own)
+  uint32_t rbegin = 0, rend = 0;  // L_LEVEL: row-tile ops (batched small nodes)
+  uint64_t rblocks = 0;           // their workgroups
   uint32_t gbegin = 0, gend = 0;  // GEMM ops in 64 x 64 tiles, in Plan::ops
   uint64_t tiles = 0;             // 64 x 64 GEMM tiles
   uint32_t wbegin = 0, wend = 0;  // GEMM ops in wave tiles, in Plan::ops
