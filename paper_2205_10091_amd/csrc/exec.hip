@@ -355,10 +355,9 @@ k_gemm_wide(LevelArgs a) {
 }
 
 // Split pass of a level's wide ops in split BF16: every operand element as
-// hi + lo bfloat16 numbers, in 64-byte chunks of 8 k (layout at
-// split_chunk).  Thread w writes chunk w of the level: per op, A's chunks
-// (k fastest: contiguous reads) then B's (n fastest: coalesced reads of
-// B's k rows).
+// hi + lo bfloat16 numbers in four planes (layout at split_chunk).  Thread
+// w converts 8 k of one row of the level: per op, A's (k fastest:
+// contiguous reads) then B's (n fastest: coalesced reads of B's k rows).
 __global__ void __launch_bounds__(256) k_split_wide(LevelArgs a) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.wide_chunks; w += stride) {
@@ -373,23 +372,22 @@ __global__ void __launch_bounds__(256) k_split_wide(LevelArgs a) {
           e -= na + nb;
           continue;
         }
-        uint4* dst = reinterpret_cast<uint4*>(S.split.part + op.part) + 4 * e;
+        uint4* planes = reinterpret_cast<uint4*>(S.split.part + op.part);
         float2 x[8];
         if (e < na) {
           const uint64_t row = e / kc, k = (e % kc) * 8;  // row = r M + m
           const float2* src = S.arena + op.a + (row / op.M) * op.a_bs + (row % op.M) * op.K + k;
 #pragma unroll
           for (int q = 0; q < 8; ++q) x[q] = src[q];
-          split_chunk(x, dst);
+          split_chunk(x, planes + e, na);  // e = row K / 8 + k / 8
         } else {
           const uint64_t f = e - na;
           const uint64_t n = f % op.N, k = ((f / op.N) % kc) * 8, r = f / (op.N * kc);
           const float2* src = S.arena + op.b + r * op.b_bs + k * op.N + n;
 #pragma unroll
           for (int q = 0; q < 8; ++q) x[q] = src[(uint64_t)q * op.N];
-          // B's chunks are stored by (r, n, kc)
-          split_chunk(x, reinterpret_cast<uint4*>(S.split.part + op.part) +
-                             4 * (na + (r * op.N + n) * kc + k / 8));
+          // B's planes follow A's 4 planes; B's rows are (r, n)
+          split_chunk(x, planes + 4 * na + (r * op.N + n) * kc + k / 8, nb);
         }
         e = ~uint64_t(0);  // done
         break;

@@ -641,11 +641,13 @@ __device__ __forceinline__ void wide_tile(const DevOp& op, uint64_t u, uint64_t&
   }
 }
 
-// Split-BF16 operand planes (written by the level's split pass): a chunk
-// of 64 bytes per row (A row m, B column n) and 8 k, holding re hi, re lo,
-// im hi, im lo of the 8 elements; chunk (r, row, kc) at index
-// (r rows + row) K / 8 + kc, A's chunks first, B's after them.
-__device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restrict__ dst) {
+// Split-BF16 operand planes (written by the level's split pass): plane p
+// = 2 re/im + hi/lo; in a plane, 16 bytes (8 k) per row (A row m, B column
+// n) and chunk of 8 k: uint4 (p R + row) K / 8 + kc for an operand of R
+// rows in all (A's rows over its batch rows, then B's planes after A's).
+// `stride` = R K / 8, the distance between two planes.
+__device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restrict__ dst,
+                                            uint64_t stride) {
   bf8 rh, rl, ih, il;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -653,9 +655,9 @@ __device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restr
     split_into(x[q].y, ih, il, q);
   }
   dst[0] = *reinterpret_cast<const uint4*>(&rh);
-  dst[1] = *reinterpret_cast<const uint4*>(&rl);
-  dst[2] = *reinterpret_cast<const uint4*>(&ih);
-  dst[3] = *reinterpret_cast<const uint4*>(&il);
+  dst[stride] = *reinterpret_cast<const uint4*>(&rl);
+  dst[2 * stride] = *reinterpret_cast<const uint4*>(&ih);
+  dst[3 * stride] = *reinterpret_cast<const uint4*>(&il);
 }
 
 // One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA
@@ -684,10 +686,12 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
   const float4* pA = reinterpret_cast<const float4*>(
       arena + op.a + r * op.a_bs + (uint64_t)(m0 + (t >> 1)) * K + (t & 1) * 16);
   const float2* pB0 = arena + op.b + r * op.b_bs + (uint64_t)(8 * (t >> 6)) * N + n0 + 2 * (t & 63);
-  const uint64_t kc = K / 8;
-  const uint4* qA = planes + 4 * (((op.a_bs ? r * op.M : 0) + m0 + (t >> 1)) * kc + (t & 1) * 2);
-  const uint4* qB = planes + 4 * ((op.a_bs ? op.rows : 1) * (uint64_t)op.M * kc +
-                                  ((op.b_bs ? r * op.N : 0) + n0 + (t >> 1)) * kc + (t & 1) * 2);
+  // split BF16: the planes' rows of this tile (A rows m0.., B columns n0..)
+  const uint64_t kcT = K / 8;
+  const uint64_t RA = (op.a_bs ? op.rows : 1) * (uint64_t)op.M;
+  const uint64_t RB = (op.b_bs ? op.rows : 1) * (uint64_t)op.N;
+  const uint4* qA = planes + ((op.a_bs ? r * op.M : 0) + m0) * kcT;
+  const uint4* qB = planes + 4 * RA * kcT + ((op.b_bs ? r * op.N : 0) + n0) * kcT;
   float4 ra[8], rb[8];
   auto fetch = [&](uint32_t k0) {
     if constexpr (PREC == 0) {
@@ -696,12 +700,24 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         rb[q] = *reinterpret_cast<const float4*>(pB0 + (uint64_t)(k0 + q) * N);
-    } else {
+    }
+  };
+  // split BF16: one stage straight from the planes into LDS buffer D with
+  // 16-byte direct loads (lane l of a load lands at its base + 16 l, a base
+  // being 16 rows of one plane: row 16 rb + l / 4, stored chunk l % 4, which
+  // holds logical chunk (l % 4) ^ ((row / 2) % 4) of the swizzle)
+  auto issue = [&](uint32_t k0, Smem& Dst) {
+    if constexpr (PREC == 1) {
+      const uint32_t kcs = k0 / 8;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const uint4 x = qA[k0 / 2 + q], y = qB[k0 / 2 + q];  // 4 uint4 a chunk of 8 k
-        ra[q] = *reinterpret_cast<const float4*>(&x);
-        rb[q] = *reinterpret_cast<const float4*>(&y);
+      for (int j = 0; j < 8; ++j) {
+        const int g = wave * 8 + j, p = g >> 3, rb16 = g & 7;
+        const int row = rb16 * 16 + (lane >> 2);
+        const int c = (lane & 3) ^ ((row >> 1) & 3);
+        __builtin_amdgcn_global_load_lds(qA + ((uint64_t)p * RA + row) * kcT + kcs + c,
+                                         &Dst.A[p >> 1][p & 1][rb16 * 16][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(qB + ((uint64_t)p * RB + row) * kcT + kcs + c,
+                                         &Dst.B[p >> 1][p & 1][rb16 * 16][0], 16, 0, 0);
       }
     }
   };
@@ -721,15 +737,6 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
       for (int q = 0; q < 8; ++q) {
         *reinterpret_cast<float2*>(&D.B[0][kg + q][n]) = make_float2(rb[q].x, rb[q].z);
         *reinterpret_cast<float2*>(&D.B[1][kg + q][n]) = make_float2(rb[q].y, rb[q].w);
-      }
-    } else {
-      // plane p = 2 re/im + hi/lo of chunk q / 4 (k half + 8 (q / 4))
-      const int row = t >> 1, kh = (t & 1) * 16;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int p = q & 3, k = kh + 8 * (q >> 2);
-        *reinterpret_cast<float4*>(&D.A[p >> 1][p & 1][row][wide_chunk(row, k)]) = ra[q];
-        *reinterpret_cast<float4*>(&D.B[p >> 1][p & 1][row][wide_chunk(row, k)]) = rb[q];
       }
     }
   };
@@ -839,21 +846,21 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
     }
   };
   const uint32_t ns = K / HK;  // stages (K is a multiple of HK)
-  fetch(0);
   if constexpr (PREC == 1) {
-    stage(S[0]);
+    issue(0, S[0]);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
     __syncthreads();
-    if (ns > 1) fetch(HK);
     for (uint32_t s = 0; s < ns; ++s) {
       // buffer s & 1 holds stage s; the other one was last read in stage
       // s - 1, which ended with the barrier
-      if (s + 1 < ns) stage(S[(s + 1) & 1]);
-      if (s + 2 < ns) fetch((s + 2) * HK);
+      if (s + 1 < ns) issue((s + 1) * HK, S[(s + 1) & 1]);
       compute(S[s & 1]);
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
   } else {
     // FP32: one LDS stage (measured faster here than two)
+    fetch(0);
     for (uint32_t s = 0; s < ns; ++s) {
       stage(S[0]);
       __syncthreads();
