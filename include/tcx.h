@@ -274,10 +274,11 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *               that feed GEMM nodes so), with at least 256 tiles of
  *               128 x 128 run such tiles, the others 64 x 64 tiles; 1 =
  *               64 x 64 tiles only; 2 = 128 x 128 tiles for every such
- *               node whatever its tile count (for tests).  In split BF16
- *               the wide tiles read the operands as BF16 planes (8 bytes
- *               per element of workspace); under mem_budget_bytes a plan
- *               that fits only without them is built with 64 x 64 tiles.
+ *               node whatever its tile count (for tests).  The wide tiles
+ *               read the operands as planes written once per evaluation
+ *               (FP32 re/im, or split-BF16 hi/lo: 8 bytes per element of
+ *               workspace); under mem_budget_bytes a plan that fits only
+ *               without them is built with 64 x 64 tiles.
  * GEMM nodes whose output tiles cannot fill the chip have K cut into
  * slices (split-K): every slice writes a partial tile to the workspace and
  * a reduction kernel adds the slices in slice order, so results do not

@@ -342,7 +342,7 @@ template <int PREC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_gemm_wide(LevelArgs a) {
   using Smem = typename std::conditional<PREC == TC_PREC_BF16X3, SmemWideBF16, SmemWideF32>::type;
-  __shared__ Smem smem[PREC == TC_PREC_BF16X3 ? 2 : 1];
+  __shared__ Smem smem[2];
   for (uint64_t tile = blockIdx.x; tile < a.wide_tiles; tile += gridDim.x) {
     const LevelSeg& S = a.seg[find_seg(a, tile, [](const LevelSeg& s) { return s.wide_start; })];
     const uint64_t lt = tile - S.wide_start;
@@ -354,10 +354,13 @@ k_gemm_wide(LevelArgs a) {
   }
 }
 
-// Split pass of a level's wide ops in split BF16: every operand element as
-// hi + lo bfloat16 numbers in four planes (layout at split_chunk).  Thread
-// w converts 8 k of one row of the level: per op, A's (k fastest:
-// contiguous reads) then B's (n fastest: coalesced reads of B's k rows).
+// Split pass of a level's wide ops: every operand element once into the
+// planes the tiles load from (layout at split_chunk).  Thread w converts 8
+// k of one row of the level's operands, per op A's rows then B's.  FP32
+// (k-major planes): rows fastest, so that neighbouring threads write
+// neighbouring floats; split BF16 (row-major planes): A's k fastest
+// (contiguous reads), B's columns fastest (coalesced reads of B's k rows).
+template <int PREC>
 __global__ void __launch_bounds__(256) k_split_wide(LevelArgs a) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.wide_chunks; w += stride) {
@@ -366,28 +369,57 @@ __global__ void __launch_bounds__(256) k_split_wide(LevelArgs a) {
       const LevelSeg& S = a.seg[s];
       for (uint32_t o = 0; o < S.n_wide; ++o) {
         const DevOp& op = S.wide_ops[o];
-        const uint64_t kc = op.K / 8, ra = op.a_bs ? op.rows : 1, rb = op.b_bs ? op.rows : 1;
-        const uint64_t na = ra * op.M * kc, nb = rb * op.N * kc;
+        const uint64_t kc = op.K / 8;
+        const uint64_t RA = (op.a_bs ? op.rows : 1) * (uint64_t)op.M;
+        const uint64_t RB = (op.b_bs ? op.rows : 1) * (uint64_t)op.N;
+        const uint64_t na = RA * kc, nb = RB * kc;
         if (e >= na + nb) {
           e -= na + nb;
           continue;
         }
-        uint4* planes = reinterpret_cast<uint4*>(S.split.part + op.part);
         float2 x[8];
-        if (e < na) {
-          const uint64_t row = e / kc, k = (e % kc) * 8;  // row = r M + m
-          const float2* src = S.arena + op.a + (row / op.M) * op.a_bs + (row % op.M) * op.K + k;
+        if (PREC == TC_PREC_C64) {
+          float* pl = S.split.part + op.part;
+          const uint64_t K = op.K;
+          if (e < na) {  // A row `row` (= r M + m), k .. k + 7
+            const uint64_t row = e % RA, k = (e / RA) * 8;
+            const float2* src = S.arena + op.a + (row / op.M) * op.a_bs + (row % op.M) * K + k;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) x[q] = src[q];
-          split_chunk(x, planes + e, na);  // e = row K / 8 + k / 8
+            for (int q = 0; q < 8; ++q) x[q] = src[q];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              pl[(k + q) * RA + row] = x[q].x;
+              pl[K * RA + (k + q) * RA + row] = x[q].y;
+            }
+          } else {  // B column `col` (= r N + n), k .. k + 7
+            const uint64_t f = e - na, col = f % RB, k = (f / RB) * 8;
+            const float2* src = S.arena + op.b + (col / op.N) * op.b_bs + k * op.N + col % op.N;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = src[(uint64_t)q * op.N];
+            float* pb = pl + 2 * K * RA;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              pb[(k + q) * RB + col] = x[q].x;
+              pb[K * RB + (k + q) * RB + col] = x[q].y;
+            }
+          }
         } else {
-          const uint64_t f = e - na;
-          const uint64_t n = f % op.N, k = ((f / op.N) % kc) * 8, r = f / (op.N * kc);
-          const float2* src = S.arena + op.b + r * op.b_bs + k * op.N + n;
+          uint4* planes = reinterpret_cast<uint4*>(S.split.part + op.part);
+          if (e < na) {
+            const uint64_t row = e / kc, k = (e % kc) * 8;  // row = r M + m
+            const float2* src = S.arena + op.a + (row / op.M) * op.a_bs + (row % op.M) * op.K + k;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) x[q] = src[(uint64_t)q * op.N];
-          // B's planes follow A's 4 planes; B's rows are (r, n)
-          split_chunk(x, planes + 4 * na + (r * op.N + n) * kc + k / 8, nb);
+            for (int q = 0; q < 8; ++q) x[q] = src[q];
+            split_chunk(x, planes + e, na);  // e = row K / 8 + k / 8
+          } else {
+            const uint64_t f = e - na;
+            const uint64_t n = f % op.N, k = ((f / op.N) % kc) * 8, r = f / (op.N * kc);
+            const float2* src = S.arena + op.b + r * op.b_bs + k * op.N + n;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = src[(uint64_t)q * op.N];
+            // B's planes follow A's 4 planes; B's rows are (r, n)
+            split_chunk(x, planes + 4 * na + (r * op.N + n) * kc + k / 8, nb);
+          }
         }
         e = ~uint64_t(0);  // done
         break;
@@ -949,12 +981,14 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       const unsigned rtb = (parts & PART_GATHER) ? (unsigned)rtblocks : 0u;
       auto gemm = [&](hipStream_t st) {
         if (whb) {
+          // the operands' planes first
           if (precision == TC_PREC_BF16X3) {
-            // the operands' BF16 planes first
-            launch(k_split_wide, dim3(grid_for(wchunks, 256, n_cu)), dim3(256), st, a);
+            launch(k_split_wide<TC_PREC_BF16X3>, dim3(grid_for(wchunks, 256, n_cu)), dim3(256), st, a);
             launch(k_gemm_wide<TC_PREC_BF16X3>, dim3(whb), dim3(256), st, a);
-          } else
+          } else {
+            launch(k_split_wide<TC_PREC_C64>, dim3(grid_for(wchunks, 256, n_cu)), dim3(256), st, a);
             launch(k_gemm_wide<TC_PREC_C64>, dim3(whb), dim3(256), st, a);
+          }
         }
         if (!gmb) return;
         if (precision == TC_PREC_BF16X3)
@@ -1360,11 +1394,9 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
   try {
     *out = make(wide);
   } catch (const tcx::Error& e) {
-    // split BF16 under a memory budget: the wide tiles' BF16 planes may be
-    // what does not fit; the 64 x 64 tiles need none
-    if (e.status != TC_ERR_TOO_LARGE || o.precision != TC_PREC_BF16X3 || wide != 1 ||
-        !o.mem_budget_bytes)
-      throw;
+    // under a memory budget the wide tiles' operand planes may be what does
+    // not fit; the 64 x 64 tiles need none
+    if (e.status != TC_ERR_TOO_LARGE || wide != 1 || !o.mem_budget_bytes) throw;
     *out = make(0);
   }
   return TC_OK;

@@ -590,15 +590,22 @@ namespace tcx {
 // planner stores intermediates that feed GEMM-tile nodes this way) and a
 // grid of at least one 128 x 128 tile per CU run 128 x 128 tiles: four
 // wavefronts of 64 x 64 each, one workgroup per CU, K in stages of 32
-// through LDS with the next stage's operands prefetched into registers.
-// Per unit of work a tile reads half the operand bytes of 64 x 64 tiles,
-// which the split-BF16 form needs to stay off the L2 bandwidth limit.
+// through LDS.  A split pass first writes each operand once as planes laid
+// out like the LDS stages, so that a stage is a set of 16-byte direct
+// global-to-LDS loads (no registers, no LDS writes by the waves).  Per unit
+// of work a tile reads half the operand bytes of 64 x 64 tiles.
 constexpr int HM = 128, HN = 128, HK = 32;  // tile edges, k per stage
 
 struct SmemWideF32 {
-  float A[2][HK][HM + 16];  // [re/im][k][m]
-  float B[2][HK][HN + 16];  // [re/im][k][n]
+  // [re/im][k][m] (and [k][n]), m contiguous in 16-byte chunks of 4; chunk
+  // q of k row k sits at q ^ (4 (k % 2)), so that the 32 lanes of half a
+  // fragment read (16 m of two k rows) touch all 32 banks once
+  __attribute__((aligned(16))) float A[2][HK][HM];
+  __attribute__((aligned(16))) float B[2][HK][HN];
 };
+__device__ __forceinline__ int wide_m(int k, int m) {
+  return ((((m >> 2) ^ ((k & 1) << 2))) << 2) | (m & 3);
+}
 struct SmemWideBF16 {
   // [re/im][hi/lo][row][k], k contiguous in 16-byte chunks of 8 (a lane
   // reads one chunk at once); chunk c of a row sits at c ^ ((row / 2) % 4),
@@ -641,11 +648,12 @@ __device__ __forceinline__ void wide_tile(const DevOp& op, uint64_t u, uint64_t&
   }
 }
 
-// Split-BF16 operand planes (written by the level's split pass): plane p
-// = 2 re/im + hi/lo; in a plane, 16 bytes (8 k) per row (A row m, B column
-// n) and chunk of 8 k: uint4 (p R + row) K / 8 + kc for an operand of R
-// rows in all (A's rows over its batch rows, then B's planes after A's).
-// `stride` = R K / 8, the distance between two planes.
+// Operand planes (written by the level's split pass; A's, then B's).
+// FP32: re and im planes, k-major: element (k, row) of an operand of R
+// rows in all (over its batch rows) at float k R + row; A's re, A's im,
+// B's re, B's im.  Split BF16: plane p = 2 re/im + hi/lo, row-major in
+// 16-byte chunks of 8 k: uint4 (p R + row) K / 8 + kc; A's 4 planes, then
+// B's.  `stride` = R K / 8, the distance between two BF16 planes.
 __device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restrict__ dst,
                                             uint64_t stride) {
   bf8 rh, rl, ih, il;
@@ -660,18 +668,15 @@ __device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restr
   dst[3 * stride] = *reinterpret_cast<const uint4*>(&il);
 }
 
-// One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA
-// on the complex64 operands, 1: split BF16 on the operands' BF16 planes
-// (`planes`: the op's chunks).  Split BF16 runs two LDS stages: while the
-// MFMAs consume stage s, stage s + 1 goes from registers into the other
-// buffer and the global loads of stage s + 2 are in flight, with one
-// barrier per stage; FP32 one stage with the next stage's loads in flight.
-template <int PREC, typename Smem, int NB>
+// One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA,
+// 1: split BF16; the operands come from their planes (`planes`: the op's).
+// Two LDS stages: while the MFMAs consume stage s, the direct loads of
+// stage s + 1 fill the other buffer, with one barrier per stage.
+template <int PREC, typename Smem>
 __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
                                           const uint32_t* __restrict__ tab,
                                           float2* __restrict__ arena,
-                                          const uint4* __restrict__ planes, Smem (&S)[NB]) {
-  static_assert(NB == (PREC == 1 ? 2 : 1), "LDS stages");
+                                          const uint4* __restrict__ planes, Smem (&S)[2]) {
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -679,35 +684,35 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
   uint32_t tm, tn;
   wide_tile(op, u, r, tm, tn);
   const uint32_t m0 = tm * HM, n0 = tn * HN, K = op.K, N = op.N;
-  // FP32 operand loads: A row (t / 2), k half (t % 2) * 16: 16 complex; B
-  // k rows 8 (t / 64) .. + 7, columns 2 (t % 64) and + 1.  Split BF16: the
-  // chunks of A row (t / 2) and B column (t / 2), k half (t % 2) * 16: two
-  // chunks (128 bytes) each.
-  const float4* pA = reinterpret_cast<const float4*>(
-      arena + op.a + r * op.a_bs + (uint64_t)(m0 + (t >> 1)) * K + (t & 1) * 16);
-  const float2* pB0 = arena + op.b + r * op.b_bs + (uint64_t)(8 * (t >> 6)) * N + n0 + 2 * (t & 63);
-  // split BF16: the planes' rows of this tile (A rows m0.., B columns n0..)
-  const uint64_t kcT = K / 8;
+  // the planes' rows of this tile (A rows m0.., B columns n0..)
   const uint64_t RA = (op.a_bs ? op.rows : 1) * (uint64_t)op.M;
   const uint64_t RB = (op.b_bs ? op.rows : 1) * (uint64_t)op.N;
-  const uint4* qA = planes + ((op.a_bs ? r * op.M : 0) + m0) * kcT;
-  const uint4* qB = planes + 4 * RA * kcT + ((op.b_bs ? r * op.N : 0) + n0) * kcT;
-  float4 ra[8], rb[8];
-  auto fetch = [&](uint32_t k0) {
-    if constexpr (PREC == 0) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) ra[q] = pA[k0 / 2 + q];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        rb[q] = *reinterpret_cast<const float4*>(pB0 + (uint64_t)(k0 + q) * N);
-    }
-  };
-  // split BF16: one stage straight from the planes into LDS buffer D with
-  // 16-byte direct loads (lane l of a load lands at its base + 16 l, a base
-  // being 16 rows of one plane: row 16 rb + l / 4, stored chunk l % 4, which
-  // holds logical chunk (l % 4) ^ ((row / 2) % 4) of the swizzle)
+  const uint64_t arow = (op.a_bs ? r * op.M : 0) + m0, brow = (op.b_bs ? r * op.N : 0) + n0;
+  // one stage straight from the planes into LDS buffer Dst with 16-byte
+  // direct loads: lane l of a load lands at the load's base + 16 l, so each
+  // lane fetches the 16 bytes that belong at that slot of the swizzle
   auto issue = [&](uint32_t k0, Smem& Dst) {
-    if constexpr (PREC == 1) {
+    if constexpr (PREC == 0) {
+      // 1 KB = two k rows of one plane; load g of 32 per operand
+      const float* pl = reinterpret_cast<const float*>(planes);
+      const float* Ap[2] = {pl, pl + (uint64_t)K * RA};
+      const float* Bp[2] = {pl + 2 * (uint64_t)K * RA, pl + 2 * (uint64_t)K * RA + (uint64_t)K * RB};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int g = wave * 8 + j, c = g >> 4, kp = g & 15;
+        const int kr = 2 * kp + (lane >> 5);
+        const int q = (lane & 31) ^ ((kr & 1) << 2);
+        __builtin_amdgcn_global_load_lds(Ap[c] + (uint64_t)(k0 + kr) * RA + arow + 4 * q,
+                                         &Dst.A[c][2 * kp][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(Bp[c] + (uint64_t)(k0 + kr) * RB + brow + 4 * q,
+                                         &Dst.B[c][2 * kp][0], 16, 0, 0);
+      }
+    } else {
+      // 1 KB = 16 rows of one plane: row 16 rb + l / 4, stored chunk l % 4,
+      // which holds logical chunk (l % 4) ^ ((row / 2) % 4)
+      const uint64_t kcT = K / 8;
+      const uint4* qA = planes + arow * kcT;
+      const uint4* qB = planes + 4 * RA * kcT + brow * kcT;
       const uint32_t kcs = k0 / 8;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -718,25 +723,6 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
                                          &Dst.A[p >> 1][p & 1][rb16 * 16][0], 16, 0, 0);
         __builtin_amdgcn_global_load_lds(qB + ((uint64_t)p * RB + row) * kcT + kcs + c,
                                          &Dst.B[p >> 1][p & 1][rb16 * 16][0], 16, 0, 0);
-      }
-    }
-  };
-  // registers -> LDS stage
-  auto stage = [&](Smem& D) {
-    if constexpr (PREC == 0) {
-      const int row = t >> 1, kh = (t & 1) * 16;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        D.A[0][kh + 2 * q][row] = ra[q].x;
-        D.A[1][kh + 2 * q][row] = ra[q].y;
-        D.A[0][kh + 2 * q + 1][row] = ra[q].z;
-        D.A[1][kh + 2 * q + 1][row] = ra[q].w;
-      }
-      const int kg = 8 * (t >> 6), n = 2 * (t & 63);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        *reinterpret_cast<float2*>(&D.B[0][kg + q][n]) = make_float2(rb[q].x, rb[q].z);
-        *reinterpret_cast<float2*>(&D.B[1][kg + q][n]) = make_float2(rb[q].y, rb[q].w);
       }
     }
   };
@@ -757,13 +743,13 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
         float br[4], bi[4], nbi[4], ar4[4], ai4[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          br[j] = D.B[0][kr][wn * 64 + j * 16 + (lane & 15)];
-          bi[j] = D.B[1][kr][wn * 64 + j * 16 + (lane & 15)];
+          br[j] = D.B[0][kr][wide_m(kr, wn * 64 + j * 16 + (lane & 15))];
+          bi[j] = D.B[1][kr][wide_m(kr, wn * 64 + j * 16 + (lane & 15))];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          ar4[i] = D.A[0][kr][wm * 64 + i * 16 + (lane & 15)];
-          ai4[i] = D.A[1][kr][wm * 64 + i * 16 + (lane & 15)];
+          ar4[i] = D.A[0][kr][wide_m(kr, wm * 64 + i * 16 + (lane & 15))];
+          ai4[i] = D.A[1][kr][wide_m(kr, wm * 64 + i * 16 + (lane & 15))];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) nbi[j] = -bi[j];
@@ -846,28 +832,16 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
     }
   };
   const uint32_t ns = K / HK;  // stages (K is a multiple of HK)
-  if constexpr (PREC == 1) {
-    issue(0, S[0]);
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
+  issue(0, S[0]);
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
+  __syncthreads();
+  for (uint32_t s = 0; s < ns; ++s) {
+    // buffer s & 1 holds stage s; the other one was last read in stage
+    // s - 1, which ended with the barrier
+    if (s + 1 < ns) issue((s + 1) * HK, S[(s + 1) & 1]);
+    compute(S[s & 1]);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (uint32_t s = 0; s < ns; ++s) {
-      // buffer s & 1 holds stage s; the other one was last read in stage
-      // s - 1, which ended with the barrier
-      if (s + 1 < ns) issue((s + 1) * HK, S[(s + 1) & 1]);
-      compute(S[s & 1]);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    }
-  } else {
-    // FP32: one LDS stage (measured faster here than two)
-    fetch(0);
-    for (uint32_t s = 0; s < ns; ++s) {
-      stage(S[0]);
-      __syncthreads();
-      if (s + 1 < ns) fetch((s + 1) * HK);
-      compute(S[0]);
-      __syncthreads();
-    }
   }
   // C: lane l holds, per block (i, j), rows 4 (l / 16) + v and column l % 16
   const uint64_t cb = op.c + r * op.c_bs;

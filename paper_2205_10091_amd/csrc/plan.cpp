@@ -797,7 +797,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       const uint64_t planes_bytes =
           8 * ((A.batched && B > 1 ? op.rows : 1) * (uint64_t)op.M * op.K +
                (Bt.batched && B > 1 ? op.rows : 1) * (uint64_t)op.N * op.K);
-      const bool planes_fit = plan.precision != TC_PREC_BF16X3 || !plan.budget ||
+      const bool planes_fit = !plan.budget ||
                               plan.arena_elems * 8 + planes_bytes <= plan.budget;
       const bool wide = to_gemm && block_tile && plan.wide_tiles && dense && op.M >= 128 &&
                         op.N >= 128 && op.K >= 32 && planes_fit &&
@@ -914,20 +914,20 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         for (uint64_t x = lo; x < hi; ++x) it[x] = o - L.wbegin;
       }
     }
-    // wide tiles in split BF16 read their operands as BF16 planes written
-    // by the level's split pass into the split region: chunks of 8 k of one
-    // row (A row m, B column n) holding the 4 planes (re/im, hi/lo) of 8
-    // bfloat16 numbers each, 64 bytes; A's chunks then B's from op.part.
+    // wide tiles read their operands as planes written by the level's split
+    // pass into the split region (FP32: re and im planes, k-major; split
+    // BF16: re-hi, re-lo, im-hi, im-lo planes, row-major; 8 bytes per
+    // element either way), A's planes then B's from op.part.
     L.hbegin = (uint32_t)plan.ops.size();
     for (DevOp& op : wd) {
       op.work0 = L.htiles;
       L.htiles += (uint64_t)op.rows * op.tiles_m * op.tiles_n;
-      if (plan.precision == TC_PREC_BF16X3) {
+      {
         part = (part + 63) & ~uint64_t(63);
         op.part = part;
         const uint64_t ra = op.a_bs ? op.rows : 1, rb = op.b_bs ? op.rows : 1;
         const uint64_t chunks = (ra * op.M + rb * op.N) * (op.K / 8);
-        part += chunks * 16;  // 64 bytes a chunk
+        part += chunks * 16;  // 64 bytes per 8 elements, in either precision
         L.wchunks += chunks;
       }
       plan.ops.push_back(op);
@@ -1199,8 +1199,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           const uint64_t chunks =
               ((op.a_bs ? op.rows : 1) * (uint64_t)op.M + (op.b_bs ? op.rows : 1) * (uint64_t)op.N) *
               (op.K / 8);
-          if (plan.precision == TC_PREC_BF16X3 &&
-              (op.part % 64 || op.part + chunks * 16 > plan.split_floats))
+          if (op.part % 64 || op.part + chunks * 16 > plan.split_floats)
             fail(TC_ERR_INVALID_ARG, "internal: wide op BF16 planes out of range");
           if (!(op.flags & OPF_WIDE) || op.ksplit != 1 || op.M % 128 || op.N % 128 || op.K % 32 ||
               op.tiles_m * 128 != op.M || op.tiles_n * 128 != op.N || op.a_k != lk ||

@@ -141,16 +141,18 @@ def test_tile_mode_wide_nodes_and_split_sums_on_host():
     auto = api.Plan(net, path).info()
     assert auto.n_wide_nodes > 0
     assert api.Plan(net, path, tile_mode=1).info().n_wide_nodes == 0
-    # split BF16 adds the operands' BF16 planes (8 bytes per element) to
-    # the workspace; under a budget that leaves no room for them the wide
-    # nodes fall back to 64 x 64 tiles instead of failing
-    b16 = api.Plan(net, path, precision=1).info()
-    assert b16.n_wide_nodes > 0 and b16.workspace_bytes > auto.workspace_bytes
-    ws64 = api.Plan(net, path, precision=1, tile_mode=1).info().workspace_bytes
-    budget = ws64 + (64 << 20)
-    assert budget < b16.workspace_bytes
-    tight = api.Plan(net, path, precision=1, mem_budget_bytes=budget).info()
-    assert tight.n_wide_nodes == 0 and tight.workspace_bytes <= budget
+    # the wide tiles read their operands as planes (8 bytes per element of
+    # workspace, FP32 and split BF16 alike); under a budget that leaves no
+    # room for them the wide nodes fall back to 64 x 64 tiles instead of
+    # failing
+    for prec in (0, 1):
+        wide = api.Plan(net, path, precision=prec).info()
+        ws64 = api.Plan(net, path, precision=prec, tile_mode=1).info().workspace_bytes
+        assert wide.n_wide_nodes > 0 and wide.workspace_bytes > ws64
+        budget = ws64 + (64 << 20)
+        assert budget < wide.workspace_bytes
+        tight = api.Plan(net, path, precision=prec, mem_budget_bytes=budget).info()
+        assert tight.n_wide_nodes == 0 and tight.workspace_bytes <= budget
     for bad in (-1, 3):
         with pytest.raises(L.TcxError) as e:
             api.Plan(net, path, tile_mode=bad)
