@@ -174,6 +174,16 @@ def serve_workload(args, out):
         s["rate_frac_of_plain"] = frac
         s["rejected_frac"] = len(rep.rejected) / n_req
         runs.append(s)
+    # the engine's capacity: every request submitted at once
+    srv = serve.Server(pool_bytes=64 << 30, max_request_bytes=4 << 30, max_active=64,
+                       path_trials=1)
+    print("[serve] engine saturated (all requests at t = 0)", file=sys.stderr, flush=True)
+    rep = serve.run(srv, tcgen.serving_requests(n_req, 1.0, seed=6), realtime=False,
+                    progress=lambda t, d, r, p: print(
+                        f"[serve]   t={t:.1f}s done={d} rejected={r} pending={p}",
+                        file=sys.stderr, flush=True))
+    srv.close()
+    out["saturated"] = rep.summary()
     best = runs[-1]
     out.update({"metric": "circuit evals/s under Poisson arrivals (serving mix), p50/p99 latency",
                 "value": best["evals_per_s"], "unit": "evals/s",
