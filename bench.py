@@ -243,11 +243,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="vqe",
                     choices=["vqe", "batched", "forward", "grid", "wide", "serve"])
-    ap.add_argument("--trials", type=int, default=32, help="greedy path trials")
+    ap.add_argument("--trials", type=int, default=0,
+                    help="greedy path trials (default: 512 for the chain workloads, whose "
+                         "launches are latency bound and gain from the fewest flops; 32 for "
+                         "the grids)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
+    chain_trials = args.trials or 512
+    grid_trials = args.trials or 32
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the contraction path is built and "
               "measured per GPU; multi-GPU sharding is a design note, not a run.",
@@ -272,7 +277,7 @@ def main():
         else:
             circ, P, obs = tcgen.workload_batched_vqe(batch=B)
         t0 = time.perf_counter()
-        plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=args.trials, seed=1)
+        plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=chain_trials, seed=1)
         plan_s = time.perf_counter() - t0
         params = torch.from_numpy(np.ascontiguousarray(P.reshape(-1))).to(dev)
         info = plan.info()
@@ -298,7 +303,7 @@ def main():
             "dtype": "c64 (fp32) + fp64 sums",
             "config": {"workload": f"vqe_chain_n20_L6_tfim_energy_grad_batch{B}",
                        "n_qubits": 20, "layers": 6, "n_params": 240, "n_terms": 39,
-                       "batch": B, "path_trials": args.trials},
+                       "batch": B, "path_trials": chain_trials},
             "achieved_tflops": (info.flops + info.grad_flops) / (dt / args.steps) / 1e12,
             "outputs": "E and dE/dtheta left in HBM (device-side optimiser form)"})
         prof = plan.profile(params, which=1, reps=20 if B == 1 else 2)
@@ -311,8 +316,8 @@ def main():
     elif args.workload == "forward":
         circ, p, zz, amp = tcgen.workload_forward_chain()
         t0 = time.perf_counter()
-        pa = api.compile(circ, amp, n_trials=args.trials, seed=1)
-        pz = api.compile(circ, zz, n_trials=args.trials, seed=1)
+        pa = api.compile(circ, amp, n_trials=chain_trials, seed=1)
+        pz = api.compile(circ, zz, n_trials=chain_trials, seed=1)
         plan_s = time.perf_counter() - t0
         params = torch.from_numpy(p).to(dev)
         dt, _ = timed(lambda: (pa.contract(params), pz.contract(params)), args.steps,
@@ -332,7 +337,7 @@ def main():
     elif args.workload == "wide":
         # an evaluation takes about 0.3 s: at most 10 timed steps
         out["steps"], out["warmup"] = min(args.steps, 10), 1
-        w = wide_workload(args.trials, steps=out["steps"])
+        w = wide_workload(grid_trials, steps=out["steps"])
         f = w["fp32"]
         out.update({"metric": "circuit evals/s (6x6 fSim grid amplitude, depth 12)",
                     "value": f["evals_per_s"], "unit": "evals/s",
@@ -345,7 +350,7 @@ def main():
     else:
         circ, p, amp = tcgen.workload_grid_amplitude()
         t0 = time.perf_counter()
-        plan = api.compile(circ, amp, n_trials=args.trials, seed=1)
+        plan = api.compile(circ, amp, n_trials=grid_trials, seed=1)
         plan_s = time.perf_counter() - t0
         params = torch.from_numpy(p).to(dev)
         dt, v = timed(lambda: plan.contract(params), args.steps, args.warmup)
@@ -361,7 +366,7 @@ def main():
         r = complex(ref["values"]["col2"]["re"], ref["values"]["col2"]["im"])
         out["rel_err_amplitude"] = abs(v[0] - r) / max(abs(r), 2 ** -18)
         # the same tree with the wide nodes in split-BF16 (hi + lo) MFMA
-        plan16 = api.compile(circ, amp, n_trials=args.trials, seed=1, precision=1)
+        plan16 = api.compile(circ, amp, n_trials=grid_trials, seed=1, precision=1)
         dt16, v16 = timed(lambda: plan16.contract(params), args.steps, args.warmup)
         rl16, _ = roofline(plan16.profile(params, which=0, reps=5), args.workload)
         out["bf16x3"] = {"evals_per_s": args.steps / dt16, "ms_per_step": dt16 / args.steps * 1e3,
@@ -386,7 +391,7 @@ def main():
         # batched sweep: 1024 parameter vectors per launch vs the plain form
         B = 1024
         circ4, P4, obs4 = tcgen.workload_batched_vqe(batch=B)
-        plan4 = api.compile(circ4, obs4, batch=B, want_grad=True, n_trials=args.trials, seed=1)
+        plan4 = api.compile(circ4, obs4, batch=B, want_grad=True, n_trials=chain_trials, seed=1)
         par4 = torch.from_numpy(P4.reshape(-1)).to(dev)
         i4 = plan4.info()
         # results left in HBM, as for the main line; then with the 1024
@@ -424,7 +429,7 @@ def main():
                                            "evals_per_s": 1e6 / float(np.mean(lat))}
 
     if args.workload == "vqe" and not args.no_extras:
-        out["wide_nodes"] = wide_workload(args.trials)
+        out["wide_nodes"] = wide_workload(grid_trials)
 
     if args.copy_calibration:
         n = args.copy_calibration // 4

@@ -11,6 +11,10 @@
 // engine"): contract the connected pair minimising
 // size(out) - size(a) - size(b).
 #include <algorithm>
+#include <atomic>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <queue>
 #include <random>
@@ -263,9 +267,13 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
   int trials = std::max(1, opts.n_trials);
   for (size_t t = 0; t < net.terms.size(); ++t) {
     const Term& term = net.terms[t];
-    TermPath best;
-    double best_score = 0;
-    for (int trial = 0; trial < trials; ++trial) {
+    // the trials are independent (each seeds its own generator from the
+    // seed, the term and the trial number): they run on up to 16 host
+    // threads, and the best score wins, ties to the lowest trial number, so
+    // the result does not depend on the thread count
+    std::vector<TermPath> found(trials);
+    std::vector<double> score(trials, 0.0);
+    auto run_trial = [&](int trial) {
       Search s;
       s.init(term);
       if (net.opts.absorb_1q) s.absorb_small();
@@ -280,15 +288,39 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
         s.costmod = std::exp2(u(rng));
         s.greedy(&rng, opts.temperature > 0 ? opts.temperature : 0.1);
       }
-      TermPath tp;
+      TermPath& tp = found[trial];
       tp.n_leaves = (int32_t)term.leaves.size();
       tp.pairs = std::move(s.pairs);
-      double sc = score_of(tree_stats(term, tp), opts.score);
-      if (trial == 0 || sc < best_score) {
-        best_score = sc;
-        best = std::move(tp);
-      }
+      score[trial] = score_of(tree_stats(term, tp), opts.score);
+    };
+    const int n_threads =
+        std::min(trials, std::max(1, std::min(16, (int)std::thread::hardware_concurrency())));
+    if (n_threads <= 1 || trials < 4) {
+      for (int trial = 0; trial < trials; ++trial) run_trial(trial);
+    } else {
+      std::atomic<int> next{0};
+      std::vector<std::thread> pool;
+      std::exception_ptr err;
+      std::mutex err_mu;
+      for (int w = 0; w < n_threads; ++w)
+        pool.emplace_back([&]() {
+          for (int trial = next++; trial < trials; trial = next++) {
+            try {
+              run_trial(trial);
+            } catch (...) {
+              std::lock_guard<std::mutex> g(err_mu);
+              if (!err) err = std::current_exception();
+            }
+          }
+        });
+      for (auto& th : pool) th.join();
+      if (err) std::rethrow_exception(err);
     }
+    int best_trial = 0;
+    for (int trial = 1; trial < trials; ++trial)
+      if (score[trial] < score[best_trial]) best_trial = trial;
+    TermPath best = std::move(found[best_trial]);
+    const double best_score = score[best_trial];
     // One more candidate: the time-ordered sweep of a state-vector
     // simulation, kept when it scores better.  The unconjugated leaves
     // (boundary vectors, gates in circuit order, Pauli matrices or output
