@@ -244,14 +244,14 @@ def main():
     ap.add_argument("--workload", default="vqe",
                     choices=["vqe", "batched", "forward", "grid", "wide", "serve"])
     ap.add_argument("--trials", type=int, default=0,
-                    help="greedy path trials (default: 512 for the chain workloads, whose "
+                    help="greedy path trials (default: 1024 for the chain workloads, whose "
                          "launches are latency bound and gain from the fewest flops; 32 for "
                          "the grids)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
-    chain_trials = args.trials or 512
+    chain_trials = args.trials or 1024
     grid_trials = args.trials or 32
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the contraction path is built and "
