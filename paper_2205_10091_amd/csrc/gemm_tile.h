@@ -19,12 +19,15 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ops.h"
 
 namespace tcx {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f16 __attribute__((ext_vector_type(16)));
 
 // Offset of index i of an index group under its descriptor d (layout in
 // ops.h): a table lookup, or the OR of up to IX_RUNS shifted bit fields.
@@ -626,6 +629,16 @@ __device__ __forceinline__ void split_into(float x, bf8& hi, bf8& lo, int e) {
   lo[e] = l;
 }
 
+// -x for eight bfloat16 numbers: flip the sign bits
+__device__ __forceinline__ bf8 neg_bf8(const bf8& x) {
+  uint4 u = __builtin_bit_cast(uint4, x);
+  u.x ^= 0x80008000u;
+  u.y ^= 0x80008000u;
+  u.z ^= 0x80008000u;
+  u.w ^= 0x80008000u;
+  return __builtin_bit_cast(bf8, u);
+}
+
 // Tile u of a wide op (0 .. rows tiles_m tiles_n - 1).  Inside a batch row
 // the order is XCD-aware: the persistent grid is a multiple of the 8 XCDs,
 // so tile u runs on XCD u % 8; XCD x takes column stripe x of the tile grid
@@ -668,10 +681,11 @@ __device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restr
   dst[3 * stride] = *reinterpret_cast<const uint4*>(&il);
 }
 
-// One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA,
-// 1: split BF16; the operands come from their planes (`planes`: the op's).
-// Two LDS stages: while the MFMAs consume stage s, the direct loads of
-// stage s + 1 fill the other buffer, with one barrier per stage.
+// One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA
+// (16 x 16 x 4 f32), 1: split BF16 (32 x 32 x 16 bf16); the operands come
+// from their planes (`planes`: the op's).  Two LDS stages: while the MFMAs
+// consume stage s, the direct loads of stage s + 1 fill the other buffer,
+// with one barrier per stage.
 template <int PREC, typename Smem>
 __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
                                           const uint32_t* __restrict__ tab,
@@ -726,17 +740,19 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
       }
     }
   };
-  f4 cr[4][4], ci[4][4];
+  const uint64_t cb = op.c + r * op.c_bs;
+  const uint32_t ns = K / HK;  // stages (K is a multiple of HK)
+  if constexpr (PREC == 0) {
+    f4 cr[4][4], ci[4][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-      ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-  // MFMAs over one LDS stage
-  auto compute = [&](const Smem& D) {
-    if constexpr (PREC == 0) {
+      for (int j = 0; j < 4; ++j) {
+        cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    // MFMAs over one LDS stage (16 x 16 x 4 blocks, 4 x 4 per wave)
+    auto compute = [&](const Smem& D) {
 #pragma unroll
       for (int kk = 0; kk < HK; kk += 4) {
         const int kr = kk + (lane >> 4);
@@ -768,95 +784,158 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
           }
         }
       }
-    } else {
-      const int kr = 8 * (lane >> 4);
-      // every fragment of the stage first (B's, then A's block by block):
-      // the MFMAs of block i then wait only for the reads they use, and the
-      // reads of the later blocks land while they run
-      bf8 b[4][2][2], aa[4][2][2];  // [block][re/im][hi/lo]
+    };
+    issue(0, S[0]);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
+    __syncthreads();
+    for (uint32_t s = 0; s < ns; ++s) {
+      // buffer s & 1 holds stage s; the other one was last read in stage
+      // s - 1, which ended with the barrier
+      if (s + 1 < ns) issue((s + 1) * HK, S[(s + 1) & 1]);
+      compute(S[s & 1]);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    // C: lane l holds, per block (i, j), rows 4 (l / 16) + v and column l % 16
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            b[j][c][h] = *reinterpret_cast<const bf8*>(
-                &D.B[c][h][wn * 64 + j * 16 + (lane & 15)][wide_chunk(lane & 15, kr)]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            aa[i][c][h] = *reinterpret_cast<const bf8*>(
-                &D.A[c][h][wm * 64 + i * 16 + (lane & 15)][wide_chunk(lane & 15, kr)]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bf8(&a)[2][2] = aa[i];
-        bf8 na[2];  // -(imaginary part)
-        na[0] = -a[1][0];
-        na[1] = -a[1][1];
-        // Cr += Ar Br - Ai Bi and Ci += Ar Bi + Ai Br, each real product
-        // as hi hi + hi lo + lo hi
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const uint64_t cm = cb + ix(tab, op.c_m, m);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][0], b[j][0][0], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][0], b[j][1][0], ci[i][j], 0, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][0], b[j][0][1], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][0], b[j][1][1], ci[i][j], 0, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][1], b[j][0][0], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][1], b[j][1][0], ci[i][j], 0, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(na[0], b[j][1][0], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][0], b[j][0][0], ci[i][j], 0, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(na[0], b[j][1][1], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][0], b[j][0][1], ci[i][j], 0, 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(na[1], b[j][1][0], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][1], b[j][0][0], ci[i][j], 0, 0, 0);
+          const uint32_t n = n0 + wn * 64 + j * 16 + (lane & 15);
+          arena[cm + ix(tab, op.c_n, n)] = make_float2(cr[i][j][v], ci[i][j][v]);
         }
       }
-    }
-  };
-  const uint32_t ns = K / HK;  // stages (K is a multiple of HK)
-  issue(0, S[0]);
-  __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
-  __syncthreads();
-  for (uint32_t s = 0; s < ns; ++s) {
-    // buffer s & 1 holds stage s; the other one was last read in stage
-    // s - 1, which ended with the barrier
-    if (s + 1 < ns) issue((s + 1) * HK, S[(s + 1) & 1]);
-    compute(S[s & 1]);
+  } else {
+    // 32 x 32 x 16 blocks, 2 x 2 per wave; a stage is two k steps of 16.
+    // Fragment of a block at k step q: lane l holds row (A) or column (B)
+    // l % 32 and k 16 q + 8 (l / 32) .. + 7, one 16-byte LDS chunk.
+    f16 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          cr[i][j][v] = 0.f;
+          ci[i][j][v] = 0.f;
+        }
+    typedef bf8 Frag[2][2][2][2];  // [A/B][block][re/im][hi/lo]
+    const int fr = lane & 31;
+    auto load = [&](const Smem& D, int q, Frag& F) {
+      const int kc = wide_chunk(fr, 16 * q + 8 * (lane >> 5));
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            F[0][b][c][h] = *reinterpret_cast<const bf8*>(&D.A[c][h][wm * 64 + b * 32 + fr][kc]);
+            F[1][b][c][h] = *reinterpret_cast<const bf8*>(&D.B[c][h][wn * 64 + b * 32 + fr][kc]);
+          }
+    };
+    // Cr += Ar Br - Ai Bi and Ci += Ar Bi + Ai Br, each real product as
+    // hi hi + hi lo + lo hi; the term loop is outermost, so that eight
+    // independent accumulations separate two into the same register block
+    auto mma = [&](const Frag& F) {
+      bf8 na[2][2];  // -(A's imaginary part) [block][hi/lo]
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        na[i][0] = neg_bf8(F[0][i][1][0]);
+        na[i][1] = neg_bf8(F[0][i][1][1]);
+      }
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        // terms 0..2 take A's real part (Cr: Ar Br, Ci: Ar Bi), terms
+        // 3..5 its imaginary part (Cr: -Ai Bi, Ci: Ai Br); within each
+        // three, (hi, hi), (hi, lo), (lo, hi)
+        const int ah = (t % 3 == 2) ? 1 : 0;
+        const int bh = (t % 3 == 1) ? 1 : 0;
+        const bool imag = t >= 3;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const bf8& xr = imag ? na[i][ah] : F[0][i][0][ah];
+            const bf8& xi = imag ? F[0][i][1][ah] : F[0][i][0][ah];
+            const bf8& yr = imag ? F[1][j][1][bh] : F[1][j][0][bh];
+            const bf8& yi = imag ? F[1][j][0][bh] : F[1][j][1][bh];
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xr, yr, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xi, yi, ci[i][j], 0, 0, 0);
+          }
+      }
+    };
+    // F0 and F1 hold the two k steps of the current stage.  The barrier in
+    // the middle of stage s (after the MFMAs of k step 0) is the one point
+    // where a wave waits: for the direct loads of stage s + 1, issued a
+    // whole stage earlier, and for its reads of stage s, after which no
+    // wave reads that buffer again, so the loads of stage s + 2 go into it
+    // at once.  The reads of a k step's fragments are spread over the MFMAs
+    // of the k step before it (sched_group_barrier: mask 8 = MFMA, 0x100 =
+    // LDS read, 0x20 = global load); the last two stages are peeled so that
+    // every step is straight-line code.
+    Frag F0, F1;
+    auto step = [&](uint32_t s, auto issue_ahead, auto read_next) {
+      load(S[s & 1], 1, F1);
+      mma(F0);
+#pragma unroll
+      for (int g = 0; g < 16; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 32, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_waitcnt(0);  // direct loads of stage s + 1, reads of stage s
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (decltype(read_next)::value) load(S[(s + 1) & 1], 0, F0);
+      if constexpr (decltype(issue_ahead)::value) issue((s + 2) * HK, S[s & 1]);
+      mma(F1);
+      if constexpr (decltype(read_next)::value) {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+      }
+      if constexpr (decltype(issue_ahead)::value) {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    issue(0, S[0]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-  }
-  // C: lane l holds, per block (i, j), rows 4 (l / 16) + v and column l % 16
-  const uint64_t cb = op.c + r * op.c_bs;
+    load(S[0], 0, F0);
+    if (ns > 1) issue(HK, S[1]);
+    uint32_t s = 0;
+    for (; s + 2 < ns; ++s) step(s, yes{}, yes{});
+    if (s + 1 < ns) step(s++, no{}, yes{});
+    step(s, no{}, no{});
+    // C: lane l holds, per block (i, j), rows 8 (v / 4) + 4 (l / 32) + v % 4
+    // and column l % 32
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const uint32_t m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
-      const uint64_t cm = cb + ix(tab, op.c_m, m);
+      for (int v = 0; v < 16; ++v) {
+        const uint32_t m = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const uint64_t cm = cb + ix(tab, op.c_m, m);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t n = n0 + wn * 64 + j * 16 + (lane & 15);
-        arena[cm + ix(tab, op.c_n, n)] = make_float2(cr[i][j][v], ci[i][j][v]);
+        for (int j = 0; j < 2; ++j) {
+          const uint32_t n = n0 + wn * 64 + j * 32 + fr;
+          arena[cm + ix(tab, op.c_n, n)] = make_float2(cr[i][j][v], ci[i][j][v]);
+        }
       }
-    }
+  }
 }
 
 }  // namespace tcx
