@@ -616,6 +616,15 @@ __global__ void __launch_bounds__(256) k_rowtile(LevelArgs a) {
 
 // Gather ops of a level; SPLIT: the split ones (their own kernel, so that
 // the split bookkeeping takes no registers from the others).
+// Op records read at wave-uniform addresses through the constant address
+// space, so that the loads are scalar (the compiler's host pass, which
+// only parses device code, sees a plain pointer).
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) DevOp* ScalarOpPtr;
+#else
+typedef const DevOp* ScalarOpPtr;
+#endif
+
 template <bool SPLIT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_gather(LevelArgs a) {
   // each block takes one contiguous chunk (a multiple of 256 items, so
@@ -660,7 +669,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
       else
         gather_item_t<false, true>(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena, Sg.split.part);
     } else {
-      gather_item(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena);
+      // Segments start at multiples of 64 items, so a wavefront's lanes
+      // share the segment; when they share the op too (all but the
+      // wavefronts that straddle two ops), the op record is read once
+      // through the constant address space (scalar loads) and its
+      // descriptor arithmetic stays scalar.
+      const uint32_t siu = __builtin_amdgcn_readfirstlane(si);
+      const uint32_t oiu = __builtin_amdgcn_readfirstlane(oi);
+      if (has && __builtin_amdgcn_ballot_w64(oi != oiu) == 0) {
+        const LevelSeg& Su = a.seg[siu];
+        const DevOp opu = ((ScalarOpPtr)Su.gc_ops)[oiu];
+        gather_item(opu, ws - opu.work0, true, Su.tab, Su.arena);
+      } else {
+        gather_item(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena);
+      }
     }
   }
 }
