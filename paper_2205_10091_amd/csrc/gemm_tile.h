@@ -683,9 +683,10 @@ __device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restr
 
 // One 128 x 128 tile of C; called by all 256 threads.  PREC 0: FP32 MFMA
 // (16 x 16 x 4 f32), 1: split BF16 (32 x 32 x 16 bf16); the operands come
-// from their planes (`planes`: the op's).  Two LDS stages: while the MFMAs
-// consume stage s, the direct loads of stage s + 1 fill the other buffer,
-// with one barrier per stage.
+// from their planes (`planes`: the op's).  Two LDS buffers of one stage
+// (32 k) each, filled by direct loads two stages ahead, with one barrier
+// per stage in its middle (the schedule is described at the split-BF16
+// path).
 template <int PREC, typename Smem>
 __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
                                           const uint32_t* __restrict__ tab,
@@ -751,51 +752,90 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
         cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         ci[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       }
-    // MFMAs over one LDS stage (16 x 16 x 4 blocks, 4 x 4 per wave)
-    auto compute = [&](const Smem& D) {
+    // 16 x 16 x 4 blocks, 4 x 4 per wave; a stage is two halves of four k
+    // steps.  Fragments of half h: [k step][A re, A im, B re, B im][block],
+    // lane l holding row (A) or column (B) l % 16 at k 4 t + l / 16.
+    typedef float FragF[4][4][4];
+    auto load = [&](const Smem& D, int h, FragF& F) {
 #pragma unroll
-      for (int kk = 0; kk < HK; kk += 4) {
-        const int kr = kk + (lane >> 4);
-        float br[4], bi[4], nbi[4], ar4[4], ai4[4];
+      for (int t = 0; t < 4; ++t) {
+        const int kr = 16 * h + 4 * t + (lane >> 4);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          br[j] = D.B[0][kr][wide_m(kr, wn * 64 + j * 16 + (lane & 15))];
-          bi[j] = D.B[1][kr][wide_m(kr, wn * 64 + j * 16 + (lane & 15))];
+        for (int b = 0; b < 4; ++b) {
+          F[t][0][b] = D.A[0][kr][wide_m(kr, wm * 64 + b * 16 + (lane & 15))];
+          F[t][1][b] = D.A[1][kr][wide_m(kr, wm * 64 + b * 16 + (lane & 15))];
+          F[t][2][b] = D.B[0][kr][wide_m(kr, wn * 64 + b * 16 + (lane & 15))];
+          F[t][3][b] = D.B[1][kr][wide_m(kr, wn * 64 + b * 16 + (lane & 15))];
         }
+      }
+    };
+    auto mma = [&](const FragF& F) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float nbi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) nbi[j] = -F[t][3][j];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          ar4[i] = D.A[0][kr][wide_m(kr, wm * 64 + i * 16 + (lane & 15))];
-          ai4[i] = D.A[1][kr][wide_m(kr, wm * 64 + i * 16 + (lane & 15))];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) nbi[j] = -bi[j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float ar = ar4[i], ai = ai4[i];
+          const float ar = F[t][0][i], ai = F[t][1][i];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi[j], ci[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, F[t][2][j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, F[t][3][j], ci[i][j], 0, 0, 0);
           }
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, nbi[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br[j], ci[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, F[t][2][j], ci[i][j], 0, 0, 0);
           }
         }
       }
     };
-    issue(0, S[0]);
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
-    __syncthreads();
-    for (uint32_t s = 0; s < ns; ++s) {
-      // buffer s & 1 holds stage s; the other one was last read in stage
-      // s - 1, which ended with the barrier
-      if (s + 1 < ns) issue((s + 1) * HK, S[(s + 1) & 1]);
-      compute(S[s & 1]);
+    // the stage schedule of the split-BF16 path below, in halves of 16 k
+    FragF F0, F1;
+    auto step = [&](uint32_t s, auto issue_ahead, auto read_next) {
+      load(S[s & 1], 1, F1);
+      mma(F0);
+#pragma unroll
+      for (int g = 0; g < 64; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 128, 0);
+      __builtin_amdgcn_sched_barrier(0);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-    }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (decltype(read_next)::value) load(S[(s + 1) & 1], 0, F0);
+      if constexpr (decltype(issue_ahead)::value) issue((s + 2) * HK, S[s & 1]);
+      mma(F1);
+      if constexpr (decltype(read_next)::value) {
+#pragma unroll
+        for (int g = 0; g < 64; ++g) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+      }
+      if constexpr (decltype(issue_ahead)::value) {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    issue(0, S[0]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    load(S[0], 0, F0);
+    if (ns > 1) issue(HK, S[1]);
+    uint32_t s = 0;
+    for (; s + 2 < ns; ++s) step(s, yes{}, yes{});
+    if (s + 1 < ns) step(s++, no{}, yes{});
+    step(s, no{}, no{});
     // C: lane l holds, per block (i, j), rows 4 (l / 16) + v and column l % 16
 #pragma unroll
     for (int i = 0; i < 4; ++i)
