@@ -410,15 +410,15 @@ __global__ void __launch_bounds__(256) k_split_wide(LevelArgs a) {
             const float2* src = S.arena + op.a + (row / op.M) * op.a_bs + (row % op.M) * op.K + k;
 #pragma unroll
             for (int q = 0; q < 8; ++q) x[q] = src[q];
-            split_chunk(x, planes + e, na);  // e = row K / 8 + k / 8
+            split_chunk(x, planes + wide_plane_chunk(row, k / 8, kc), 4);
           } else {
             const uint64_t f = e - na;
             const uint64_t n = f % op.N, k = ((f / op.N) % kc) * 8, r = f / (op.N * kc);
             const float2* src = S.arena + op.b + r * op.b_bs + k * op.N + n;
 #pragma unroll
             for (int q = 0; q < 8; ++q) x[q] = src[(uint64_t)q * op.N];
-            // B's planes follow A's 4 planes; B's rows are (r, n)
-            split_chunk(x, planes + 4 * na + (r * op.N + n) * kc + k / 8, nb);
+            // B's planes follow A's; B's rows are (r, n)
+            split_chunk(x, planes + 4 * na + wide_plane_chunk(r * op.N + n, k / 8, kc), 4);
           }
         }
         e = ~uint64_t(0);  // done

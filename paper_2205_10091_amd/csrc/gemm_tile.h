@@ -664,9 +664,15 @@ __device__ __forceinline__ void wide_tile(const DevOp& op, uint64_t u, uint64_t&
 // Operand planes (written by the level's split pass; A's, then B's).
 // FP32: re and im planes, k-major: element (k, row) of an operand of R
 // rows in all (over its batch rows) at float k R + row; A's re, A's im,
-// B's re, B's im.  Split BF16: plane p = 2 re/im + hi/lo, row-major in
-// 16-byte chunks of 8 k: uint4 (p R + row) K / 8 + kc; A's 4 planes, then
-// B's.  `stride` = R K / 8, the distance between two BF16 planes.
+// B's re, B's im.  Split BF16: four planes p = 2 re/im + hi/lo in 16-byte
+// chunks of 8 k, interleaved by LDS stage: row by row, each stage (32 k)
+// of a row is one 256-byte block of the 4 planes' 64 bytes, so a stage
+// reads whole cache lines; chunk kc of plane p of row `row` is uint4
+// wide_plane_chunk(row, kc, K / 8) + 4 p.  A's R_A K / 2 uint4, then B's.
+__host__ __device__ __forceinline__ uint64_t wide_plane_chunk(uint64_t row, uint64_t kc,
+                                                            uint64_t kc_total) {
+  return row * kc_total * 4 + (kc >> 2) * 16 + (kc & 3);
+}
 __device__ __forceinline__ void split_chunk(const float2 (&x)[8], uint4* __restrict__ dst,
                                             uint64_t stride) {
   bf8 rh, rl, ih, il;
@@ -726,18 +732,16 @@ __device__ __forceinline__ void gemm_wide(const DevOp& op, uint64_t u,
       // 1 KB = 16 rows of one plane: row 16 rb + l / 4, stored chunk l % 4,
       // which holds logical chunk (l % 4) ^ ((row / 2) % 4)
       const uint64_t kcT = K / 8;
-      const uint4* qA = planes + arow * kcT;
-      const uint4* qB = planes + 4 * RA * kcT + brow * kcT;
-      const uint32_t kcs = k0 / 8;
+      const uint4* qA = planes + wide_plane_chunk(arow, k0 / 8, kcT);
+      const uint4* qB = planes + 4 * RA * kcT + wide_plane_chunk(brow, k0 / 8, kcT);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int g = wave * 8 + j, p = g >> 3, rb16 = g & 7;
         const int row = rb16 * 16 + (lane >> 2);
         const int c = (lane & 3) ^ ((row >> 1) & 3);
-        __builtin_amdgcn_global_load_lds(qA + ((uint64_t)p * RA + row) * kcT + kcs + c,
-                                         &Dst.A[p >> 1][p & 1][rb16 * 16][0], 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(qB + ((uint64_t)p * RB + row) * kcT + kcs + c,
-                                         &Dst.B[p >> 1][p & 1][rb16 * 16][0], 16, 0, 0);
+        const uint64_t off = (uint64_t)row * kcT * 4 + 4 * p + c;
+        __builtin_amdgcn_global_load_lds(qA + off, &Dst.A[p >> 1][p & 1][rb16 * 16][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(qB + off, &Dst.B[p >> 1][p & 1][rb16 * 16][0], 16, 0, 0);
       }
     }
   };
