@@ -12,10 +12,13 @@ as the paper excludes JIT staging from its timings.
 
 Other workloads: --workload batched (the same chain, 1024 parameter vectors
 per launch), forward (10-qubit brickwork: amplitude and <Z0 Z1>), grid (6x6
-fSim grid amplitude, depth 8), wide (the 6x6 grid at depth 12, whose tree
-holds wide GEMM nodes: 16384 x 65536 x 4096 and others; FP32 and split
-BF16).  The default run also reports the batched sweep, the forward chain's
-latency and the wide-node grid beside the main line.
+fSim grid amplitude, depth 8, FP32 and split BF16 against the stored oracle
+amplitude), wide (the 4x7 grid at depth 16, whose default tree holds six
+GEMM nodes in 128 x 128 tiles, up to 1024 x 65536 x 16384, against its stored
+oracle amplitude; --wide-grid 6x6x12 takes the 6x6 grid at depth 12, which
+has no oracle value), serve (the serving mix).  The default run also
+reports the batched sweep, the forward chain's latency, the 6x6 depth-8 grid
+and the 4x7 depth-16 grid beside the main line.
 
 Prints one JSON line.  --copy-calibration BYTES also runs one plain device
 copy of that many bytes (used to scale HBM byte counters).
@@ -36,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3   # dense FP32 MFMA
 PEAK_BF16_TFLOPS = 2500.0  # dense BF16 MFMA
 KIND_NAMES = {0: "k_leaf", 2: "k_gemm", 3: "k_gather", 4: "k_root", 5: "k_grad", 6: "k_term",
-              7: "k_gemm_wide"}
+              7: "k_gemm_wide", 8: "k_rowtile", 9: "k_gather_split"}
 KERNEL_SOURCES = ["paper_2205_10091_amd/csrc/exec.hip", "paper_2205_10091_amd/csrc/gemm_tile.h",
                   "paper_2205_10091_amd/csrc/gates.h", "paper_2205_10091_amd/csrc/ops.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -102,22 +105,34 @@ def roofline(profile, workload, precision=0):
     return rl, share
 
 
-def cpu_baseline(circ, p, obs, budget_s=15.0):
-    from threadpoolctl import threadpool_info
+def cpu_baseline(circ, p, obs, budget_s=12.0):
+    """The oracle's energy + gradient rate on this host: once with one BLAS
+    thread, once with the BLAS pool as configured (its thread count is
+    reported; os.cpu_count() beside it)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import statevector as sv
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        sv.energy_grad(circ, p, obs)
-        n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 50:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+
+    def run(limit):
+        with threadpool_limits(limits=limit):
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+            t0 = time.perf_counter()
+            n = 0
+            while True:
+                sv.energy_grad(circ, p, obs)
+                n += 1
+                if time.perf_counter() - t0 > budget_s or n >= 50:
+                    break
+            return n, time.perf_counter() - t0, int(threads)
+
+    n, dt, threads = run(None)
+    n1, dt1, _ = run(1)
+    return {"value": n / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} energy+gradient evaluations of the 20-qubit chain by the "
                       f"complex128 state-vector oracle with the adjoint method "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s, {threads} BLAS threads)",
+            "single_thread": {"value": n1 / dt1, "unit": "evals/s", "cores": 1,
+                              "sample": f"{n1} evaluations ({dt1:.1f} s)"},
+            "host_cpu_count": os.cpu_count()}
 
 
 def serve_workload(args, out):
@@ -194,33 +209,56 @@ def serve_workload(args, out):
                 "serving": runs})
 
 
-def wide_workload(trials, steps=3):
-    """6x6 fSim grid amplitude at depth 12 in FP32 and split BF16: an
-    evaluation is dominated by GEMM nodes in 128 x 128 tiles.  No oracle
-    value exists at this size (the state has 2^36 entries), so the two
-    precisions are compared with each other; the 4x6 depth-12 and 6x6
-    depth-8 grids pin the same tiles to the oracle in the GPU tests."""
+def golden_amplitude(rows, cols, depth):
+    """The stored oracle amplitude of a seeded fSim grid (two independent
+    oracle methods, tests/golden/), its methods' seconds, or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"grid{rows}x{cols}_d{depth}_amplitude.json")
+    if not os.path.exists(path):
+        return None, {}
+    ref = json.load(open(path))
+    key = "statevector" if "statevector" in ref["values"] else sorted(ref["values"])[0]
+    v = ref["values"][key]
+    return complex(v["re"], v["im"]), {k: x.get("seconds") for k, x in ref["values"].items()}
+
+
+def grid_leg(rows, cols, depth, trials, steps, warmup, workload):
+    """A seeded fSim grid amplitude in FP32 and in split BF16 (wide nodes):
+    evaluations/s, achieved TFLOP/s, the dominant kernel's roofline and the
+    error against the stored oracle amplitude, floored at 2^(-n/2) (the RMS
+    amplitude) and unfloored."""
     import torch
     import tcgen
     from paper_2205_10091_amd import api
-    circ, p, amp = tcgen.workload_grid_amplitude(6, 6, 12)
+    circ, p, amp = tcgen.workload_grid_amplitude(rows, cols, depth)
+    n = rows * cols
+    ref, oracle_s = golden_amplitude(rows, cols, depth)
     params = torch.from_numpy(p).to("cuda:0")
-    res, vals = {"workload": "grid6x6_d12_amplitude"}, {}
+    res, vals = {"workload": f"grid{rows}x{cols}_d{depth}_amplitude", "n_qubits": n}, {}
     for prec, key in ((0, "fp32"), (1, "bf16x3")):
+        t0 = time.perf_counter()
         plan = api.compile(circ, amp, n_trials=trials, seed=1, precision=prec)
+        plan_s = time.perf_counter() - t0
         info = plan.info()
         out = torch.empty(2, dtype=torch.float64, device="cuda:0")
-        dt, _ = timed(lambda: plan.contract_device(params, out), steps, 1)
+        dt, _ = timed(lambda: plan.contract_device(params, out), steps, warmup)
         vals[key] = complex(*out.cpu().numpy())
-        rl, share = roofline(plan.profile(params, which=0, reps=1), "wide", precision=prec)
-        res[key] = {"evals_per_s": steps / dt, "ms_per_step": dt / steps * 1e3,
-                    "achieved_tflops": info.flops / (dt / steps) / 1e12,
-                    "roofline": rl, "time_share_by_kernel": share,
-                    "wide_nodes": info.n_wide_nodes, "gemm_nodes": info.n_gemm_nodes,
-                    "flops": info.flops, "workspace_bytes": int(info.workspace_bytes)}
+        rl, share = roofline(plan.profile(params, which=0, reps=2 if info.flops > 1e12 else 10),
+                             workload, precision=prec)
+        r = {"evals_per_s": steps / dt, "ms_per_step": dt / steps * 1e3,
+             "achieved_tflops": info.flops / (dt / steps) / 1e12,
+             "roofline": rl, "time_share_by_kernel": share,
+             "wide_nodes": info.n_wide_nodes, "gemm_nodes": info.n_gemm_nodes,
+             "flops": info.flops, "workspace_bytes": int(info.workspace_bytes),
+             "largest_intermediate_bytes": int(info.peak_tensor_bytes), "plan_seconds": plan_s}
+        if ref is not None:
+            r["rel_err"] = abs(vals[key] - ref) / max(abs(ref), 2 ** (-n / 2))
+            r["true_rel_err"] = abs(vals[key] - ref) / abs(ref)
+        res[key] = r
         del plan
         torch.cuda.empty_cache()
-    res["rel_diff_bf16x3_vs_fp32"] = abs(vals["bf16x3"] - vals["fp32"]) / max(abs(vals["fp32"]), 2 ** -18)
+    res["oracle_amplitude"] = None if ref is None else [ref.real, ref.imag]
+    res["oracle_seconds"] = oracle_s
+    res["rel_diff_bf16x3_vs_fp32"] = abs(vals["bf16x3"] - vals["fp32"]) / max(abs(vals["fp32"]), 2 ** (-n / 2))
     return res
 
 
@@ -250,6 +288,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--wide-grid", default="4x7x16", metavar="RxCxD",
+                    help="grid of --workload wide (4x7x16: oracle-pinned; 6x6x12: larger, "
+                         "no oracle value)")
     args = ap.parse_args()
     chain_trials = args.trials or 1024
     grid_trials = args.trials or 32
@@ -313,6 +354,7 @@ def main():
         out["rel_err_energy"] = abs(e[b0] - e_ref) / max(abs(e_ref), 1.0)
         out["rel_err_grad"] = float(np.linalg.norm(g[b0] - g_ref) /
                                     max(np.linalg.norm(g_ref), 1.0))
+        out["max_abs_err_grad"] = float(np.max(np.abs(g[b0] - g_ref)))
     elif args.workload == "forward":
         circ, p, zz, amp = tcgen.workload_forward_chain()
         t0 = time.perf_counter()
@@ -335,48 +377,38 @@ def main():
     elif args.workload == "serve":
         pass  # handled below
     elif args.workload == "wide":
-        # an evaluation takes about 0.3 s: at most 10 timed steps
+        # 4x7 grid at depth 16 (oracle-pinned; 1.8e13 flops) or, with
+        # --wide-grid 6x6x12, the 6x6 grid at depth 12 (no oracle value)
+        rows, cols, depth = (int(x) for x in args.wide_grid.split("x"))
         out["steps"], out["warmup"] = min(args.steps, 10), 1
-        w = wide_workload(grid_trials, steps=out["steps"])
+        w = grid_leg(rows, cols, depth, grid_trials, out["steps"], 1, "wide")
         f = w["fp32"]
-        out.update({"metric": "circuit evals/s (6x6 fSim grid amplitude, depth 12)",
+        out.update({"metric": f"circuit evals/s ({rows}x{cols} fSim grid amplitude, depth {depth})",
                     "value": f["evals_per_s"], "unit": "evals/s",
                     "ms_per_step": f["ms_per_step"], "dtype": "c64 (fp32)",
-                    "config": {"workload": "grid6x6_d12_amplitude", "batch": 1},
+                    "config": {"workload": w["workload"], "batch": 1},
                     "achieved_tflops": f["achieved_tflops"], "roofline": f["roofline"],
                     "time_share_by_kernel": f["time_share_by_kernel"],
+                    "rel_err": f.get("rel_err"), "true_rel_err": f.get("true_rel_err"),
                     "bf16x3": w["bf16x3"],
                     "rel_diff_bf16x3_vs_fp32": w["rel_diff_bf16x3_vs_fp32"]})
     else:
-        circ, p, amp = tcgen.workload_grid_amplitude()
-        t0 = time.perf_counter()
-        plan = api.compile(circ, amp, n_trials=grid_trials, seed=1)
-        plan_s = time.perf_counter() - t0
-        params = torch.from_numpy(p).to(dev)
-        dt, v = timed(lambda: plan.contract(params), args.steps, args.warmup)
-        info = plan.info()
+        # 6x6 grid, depth 8: FP32 and split BF16 against the oracle amplitude
+        g = grid_leg(6, 6, 8, grid_trials, args.steps, args.warmup, "grid")
+        f = g["fp32"]
         out.update({"metric": "circuit evals/s (6x6 fSim grid amplitude, depth 8)",
-                    "value": args.steps / dt, "unit": "evals/s",
-                    "ms_per_step": dt / args.steps * 1e3, "dtype": "c64 (fp32)",
+                    "value": f["evals_per_s"], "unit": "evals/s",
+                    "ms_per_step": f["ms_per_step"], "dtype": "c64 (fp32)",
                     "config": {"workload": "grid6x6_d8_amplitude", "batch": 1},
-                    "achieved_tflops": info.flops / (dt / args.steps) / 1e12})
-        prof = plan.profile(params, which=0, reps=20)
-        rl, share = roofline(prof, args.workload)
-        ref = json.load(open(os.path.join(ROOT, "tests/golden/grid6x6_d8_amplitude.json")))
-        r = complex(ref["values"]["col2"]["re"], ref["values"]["col2"]["im"])
-        out["rel_err_amplitude"] = abs(v[0] - r) / max(abs(r), 2 ** -18)
-        # the same tree with the wide nodes in split-BF16 (hi + lo) MFMA
-        plan16 = api.compile(circ, amp, n_trials=grid_trials, seed=1, precision=1)
-        dt16, v16 = timed(lambda: plan16.contract(params), args.steps, args.warmup)
-        rl16, _ = roofline(plan16.profile(params, which=0, reps=5), args.workload)
-        out["bf16x3"] = {"evals_per_s": args.steps / dt16, "ms_per_step": dt16 / args.steps * 1e3,
-                         "rel_err_amplitude": abs(v16[0] - r) / max(abs(r), 2 ** -18),
-                         "dominant_kernel": rl16}
+                    "achieved_tflops": f["achieved_tflops"], "roofline": f["roofline"],
+                    "time_share_by_kernel": f["time_share_by_kernel"],
+                    "rel_err": f.get("rel_err"), "true_rel_err": f.get("true_rel_err"),
+                    "bf16x3": g["bf16x3"], "oracle_seconds": g["oracle_seconds"]})
 
     if args.workload == "serve":
         serve_workload(args, out)
         out["roofline"] = None   # a mix of plans: see the per-workload runs
-    elif args.workload != "wide":
+    elif args.workload in ("vqe", "batched", "forward"):
         out["plan"] = {"flops": info.flops, "grad_flops": info.grad_flops,
                        "alg_bytes": info.alg_bytes + info.grad_alg_bytes,
                        "workspace_bytes": int(info.workspace_bytes), "nodes": info.n_nodes,
@@ -429,7 +461,12 @@ def main():
                                            "evals_per_s": 1e6 / float(np.mean(lat))}
 
     if args.workload == "vqe" and not args.no_extras:
-        out["wide_nodes"] = wide_workload(grid_trials)
+        # the 36-qubit precision-stress grid (depth 8) and the oracle-pinned
+        # wide-node grid (4x7, depth 16), each in FP32 and split BF16
+        print("[bench] grid 6x6 depth 8", file=sys.stderr, flush=True)
+        out["grid_amplitude"] = grid_leg(6, 6, 8, grid_trials, 50, 5, "grid")
+        print("[bench] grid 4x7 depth 16 (wide nodes)", file=sys.stderr, flush=True)
+        out["wide_nodes"] = grid_leg(4, 7, 16, grid_trials, 5, 1, "wide")
 
     if args.copy_calibration:
         n = args.copy_calibration // 4

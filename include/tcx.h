@@ -382,7 +382,9 @@ tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
  * 3 gather contractions of one tree level, 4 FP64 root sum, 5 FP64
  * gradient sum, 6 term mode: all terms' trees, forward pass with the leaves
  * or reverse sweep, 7 MFMA GEMM nodes of one tree level in 128 x 128
- * tiles), the mean duration ms[i], and the kernel's algorithmic
+ * tiles with their split pass, 8 row tiles of one tree level (batched small
+ * nodes), 9 split sums of one tree level with their reduction), the mean
+ * duration ms[i], and the kernel's algorithmic
  * flops[i] and bytes[i] (operands read once plus results written once).
  * which: 0 the forward sequence, 1 forward plus reverse sweep (needs
  * want_grad).  A level's GEMM and gather parts run one after the other

@@ -51,15 +51,18 @@ struct Fork {
   hipEvent_t start, done;
 };
 
-// Launch parts of a level: GEMM tiles, gather items.
-constexpr int PART_GEMM = 1, PART_GATHER = 2, PART_WIDE = 4;
+// Launch parts of a level: GEMM tiles (64 x 64 and wave tiles), gather
+// items, 128 x 128 tiles with their split pass, row tiles, split sums with
+// their reduction.
+constexpr int PART_GEMM = 1, PART_GATHER = 2, PART_WIDE = 4, PART_ROWTILE = 8, PART_GSPLIT = 16;
+constexpr int PART_ALL = PART_GEMM | PART_GATHER | PART_WIDE | PART_ROWTILE | PART_GSPLIT;
 
 // Enqueue one launch of `kind` covering all `segs` (at most MAX_SEG, all of
 // that kind) on `stream`; for levels, only the kernels named in `parts`,
 // forked as above when `fork` is given.
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
                      int precision, const Fork* fork = nullptr,
-                     int parts = PART_GEMM | PART_GATHER | PART_WIDE);
+                     int parts = PART_ALL);
 
 // Asynchronous upload of a plan's tables and seeds into a workspace.
 void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStream_t stream);

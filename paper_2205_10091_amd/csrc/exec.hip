@@ -358,7 +358,8 @@ k_gemm_wide(LevelArgs a) {
 // planes the tiles load from (layout at split_chunk).  Thread w converts 8
 // k of one row of the level's operands, per op A's rows then B's.  FP32
 // (k-major planes): rows fastest, so that neighbouring threads write
-// neighbouring floats; split BF16 (row-major planes): A's k fastest
+// neighbouring floats; split BF16 (per row, each 32-k stage is one 256-byte
+// block holding the four planes' 64 bytes, wide_plane_chunk): A's k fastest
 // (contiguous reads), B's columns fastest (coalesced reads of B's k rows).
 template <int PREC>
 __global__ void __launch_bounds__(256) k_split_wide(LevelArgs a) {
@@ -999,8 +1000,8 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       const unsigned gmb = (parts & PART_GEMM) ? a.tile_blocks + wvb : 0u;
       const unsigned whb = (parts & PART_WIDE) ? (unsigned)std::min<uint64_t>(htiles, (uint64_t)n_cu) : 0u;
       const unsigned gcb = (parts & PART_GATHER) && work ? grid_for(work, 256, n_cu) : 0u;
-      const unsigned gsb = (parts & PART_GATHER) && gswork ? grid_for(gswork, 256, n_cu) : 0u;
-      const unsigned rtb = (parts & PART_GATHER) ? (unsigned)rtblocks : 0u;
+      const unsigned gsb = (parts & PART_GSPLIT) && gswork ? grid_for(gswork, 256, n_cu) : 0u;
+      const unsigned rtb = (parts & PART_ROWTILE) ? (unsigned)rtblocks : 0u;
       auto gemm = [&](hipStream_t st) {
         if (whb) {
           // the operands' planes first
@@ -1120,7 +1121,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
 }
 
 static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& seq,
-                    int parts = PART_GEMM | PART_GATHER | PART_WIDE) {
+                    int parts = PART_ALL) {
   const Fork fork{D.side, D.fork_start, D.fork_done};
   for (const Launch& x : seq) {
     SegRef s{&P, D.ws, &D.lay, &x};
@@ -1297,15 +1298,18 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
   std::vector<Entry> seq;
   for (const Launch& L : all) {
     if (L.kind != L_LEVEL) {
-      seq.push_back({L, L.kind, PART_GEMM | PART_GATHER | PART_WIDE, L.flops, L.bytes});
+      seq.push_back({L, L.kind, PART_ALL, L.flops, L.bytes});
       continue;
     }
     if (L.htiles) seq.push_back({L, PROF_WIDE, PART_WIDE, L.wide_flops, L.wide_bytes});
     if (L.tiles || L.wtiles)
       seq.push_back({L, PROF_GEMM, PART_GEMM, L.gemm_flops - L.wide_flops,
                      L.gemm_bytes - L.wide_bytes});
-    if (L.work || L.xwork || L.rblocks)
-      seq.push_back({L, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops, L.bytes - L.gemm_bytes});
+    if (L.work)
+      seq.push_back({L, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops - L.rt_flops - L.gs_flops,
+                     L.bytes - L.gemm_bytes - L.rt_bytes - L.gs_bytes});
+    if (L.rblocks) seq.push_back({L, PROF_ROWTILE, PART_ROWTILE, L.rt_flops, L.rt_bytes});
+    if (L.xwork) seq.push_back({L, PROF_GSPLIT, PART_GSPLIT, L.gs_flops, L.gs_bytes});
   }
   // per entry: the start of its first kernel to the end of its last, as
   // stamped by the kernel dispatches (no queueing gap between launches)

@@ -709,7 +709,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       ++j;
     const bool term_mode = tstep;
     std::vector<DevOp> gc, gm, wv, wd, rt;
-    double lf = 0, lb = 0, gf = 0, gb = 0, wf = 0, wb = 0;
+    double lf = 0, lb = 0, gf = 0, gb = 0, wf = 0, wb = 0, rtf = 0, rtby = 0, sgf = 0, sgby = 0;
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
       const PT& Bt = T[pend[k].b];
@@ -838,6 +838,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         op.tiles_m = rpb;
         op.tiles_n = (op.rows + rpb - 1) / rpb;
         rt.push_back(op);
+        rtf += f;
+        rtby += by;
       } else {
         // gather: split long sums over up to 64 lanes while the op is small,
         // else 4 outputs per thread along n
@@ -850,6 +852,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           uint32_t P = 1;
           while (P < 65536 && (op.K >> ls) / P > 256) P *= 2;
           op.ksplit = P;
+          sgf += f;
+          sgby += by;
         }
         gc.push_back(op);
       }
@@ -862,6 +866,10 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.gemm_bytes = gb;
     L.wide_flops = wf;
     L.wide_bytes = wb;
+    L.rt_flops = rtf;
+    L.rt_bytes = rtby;
+    L.gs_flops = sgf;
+    L.gs_bytes = sgby;
     // split-K: a GEMM node with too few output tiles to fill the chip (256
     // CUs) cuts K into slices of at least 64; each slice writes a partial
     // tile and the level's reduction kernel adds them in slice order.  The
@@ -916,8 +924,9 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     // wide tiles read their operands as planes written by the level's split
     // pass into the split region (FP32: re and im planes, k-major; split
-    // BF16: re-hi, re-lo, im-hi, im-lo planes, row-major; 8 bytes per
-    // element either way), A's planes then B's from op.part.
+    // BF16: re-hi, re-lo, im-hi, im-lo planes interleaved by stage, each
+    // row's 32-k stage one 256-byte block of the four planes' 64 bytes;
+    // 8 bytes per element either way), A's planes then B's from op.part.
     L.hbegin = (uint32_t)plan.ops.size();
     for (DevOp& op : wd) {
       op.work0 = L.htiles;

@@ -19,7 +19,8 @@ enum LaunchKind : int32_t {
 };
 // kernel kinds reported by profiling: a level's GEMM tiles (64 x 64 and
 // wave tiles), gathers, and 128 x 128 GEMM tiles
-constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3, PROF_WIDE = 7;
+constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3, PROF_WIDE = 7, PROF_ROWTILE = 8,
+                  PROF_GSPLIT = 9;
 
 constexpr uint64_t NO_ITEMS = ~uint64_t(0);
 // levels with at most this many gather items get a per-item op index table
@@ -68,6 +69,10 @@ struct Launch {
   double gemm_bytes = 0;
   double wide_flops = 0;          // ... of which in 128 x 128 tiles
   double wide_bytes = 0;
+  double rt_flops = 0;            // the part in row tiles
+  double rt_bytes = 0;
+  double gs_flops = 0;            // the part in split sums
+  double gs_bytes = 0;
 };
 
 struct DeviceState;  // defined by the executor

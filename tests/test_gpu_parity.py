@@ -15,7 +15,7 @@ import tcgen
 from oracle import statevector as sv
 from paper_2205_10091_amd import _lib as L
 from paper_2205_10091_amd import api
-from gpu_common import TOL_C64, device_params, grad_err, rel_err
+from gpu_common import TOL_C64, assert_grad, device_params, grad_err, rel_err, true_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -70,7 +70,7 @@ def test_vqe_chain_energy_and_gradient():
     e, g = plan.contract_grad(device_params(p))
     e_ref, g_ref = sv.energy_grad(circ, p, obs)
     assert rel_err(e[0], e_ref, 1.0) < TOL_C64
-    assert grad_err(g[0], g_ref) < TOL_C64
+    assert_grad(g[0], g_ref, TOL_C64)
     # slots no gate reaches are exactly zero; the first RZZ layer has zero
     # gradient up to rounding
     gg = g[0].reshape(6, 2, 20)
@@ -121,13 +121,19 @@ def test_batched_sweep_matches_oracle_and_single_calls():
     for b in (0, 17, 63):
         e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
         assert rel_err(e[b], e_ref, 1.0) < TOL_C64
-        assert grad_err(g[b], g_ref) < TOL_C64
+        assert_grad(g[b], g_ref, TOL_C64)
         e1, g1 = single.contract_grad(device_params(P[b]))
         assert abs(e1[0] - e[b]) < 1e-6
         assert np.max(np.abs(g1[0] - g[b])) < 1e-6
 
 
-def test_batched_sweep_full_size_sampled_rows():
+def test_batched_sweep_full_size_every_row():
+    """1024 parameter vectors in one launch: every row's energy and every
+    gradient component against a batch-1 plan of the same network called
+    row by row, and sampled rows against the oracle.  E = sum_j a_j T_j is
+    summed in FP64 from complex64 terms, so |dE| <= sum_j |a_j| |dT_j|: the
+    differences are divided by sum_j |a_j| (39 here), which leaves the
+    per-term contraction difference, required below 1e-6."""
     B = 1024
     circ, P, obs = tcgen.workload_batched_vqe(batch=B)
     plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=8, seed=1)
@@ -136,7 +142,21 @@ def test_batched_sweep_full_size_sampled_rows():
     for b in (0, 511, 1023):
         e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
         assert rel_err(e[b], e_ref, 1.0) < TOL_C64
-        assert grad_err(g[b], g_ref) < TOL_C64
+        assert_grad(g[b], g_ref, TOL_C64)
+    del plan
+    single = api.compile(circ, obs, want_grad=True, n_trials=8, seed=1)
+    pd = device_params(P, B)
+    scale = float(np.sum(np.abs(obs.weights)))
+    worst_e = worst_g = worst_rel = 0.0
+    for b in range(B):
+        e1, g1 = single.contract_grad(pd[b].contiguous())
+        worst_e = max(worst_e, abs(e1[0] - e[b]))
+        worst_rel = max(worst_rel, abs(e1[0] - e[b]) / max(1.0, abs(e1[0])))
+        worst_g = max(worst_g, float(np.max(np.abs(g1[0] - g[b]))))
+    print(f"batch 1024 vs batch 1 over {B} rows: max |dE| {worst_e:.2e} "
+          f"(relative to |E|: {worst_rel:.2e}), max gradient component diff {worst_g:.2e}; "
+          f"sum |a_j| = {scale}")
+    assert worst_e / scale < 1e-6 and worst_g / scale < 1e-6
 
 
 # ------------------------------------------------------------ grid amplitudes
@@ -159,7 +179,12 @@ def test_grid_amplitude_full_size_against_golden():
     assert abs(vals[0] - vals[1]) <= 1e-12 * abs(vals[0])
     circ, p, amp = tcgen.workload_grid_amplitude()
     _, a = one(circ, amp, p, n_trials=32, seed=1)
+    # the amplitude (|ref| = 3.8e-7) is far below the 2^-18 floor, so the
+    # unfloored relative error is checked as well
+    print(f"6x6 depth 8, c64: rel_err {rel_err(a, vals[0], 2 ** (-18)):.2e}, "
+          f"true relative error {true_rel_err(a, vals[0]):.2e}")
     assert rel_err(a, vals[0], 2 ** (-18)) < TOL_C64
+    assert true_rel_err(a, vals[0]) < TOL_C64
 
 
 def test_split_k_wide_nodes_fp32_and_bf16x3():
@@ -180,7 +205,10 @@ def test_split_k_wide_nodes_fp32_and_bf16x3():
         a1 = plan.contract(device_params(p))[0]
         a2 = plan.contract(device_params(p))[0]
         assert a1 == a2, prec
+        print(f"6x6 depth 8, precision {prec}: rel_err {rel_err(a1, r, 2 ** (-18)):.2e}, "
+              f"true relative error {true_rel_err(a1, r):.2e}")
         assert rel_err(a1, r, 2 ** (-18)) < tol, prec
+        assert true_rel_err(a1, r) < tol, prec
 
 
 def test_split_sums_deep_grid_fp32_and_bf16x3():
@@ -201,7 +229,10 @@ def test_split_sums_deep_grid_fp32_and_bf16x3():
         a1 = plan.contract(device_params(p))[0]
         a2 = plan.contract(device_params(p))[0]
         assert a1 == a2, prec
+        print(f"4x6 depth 12, precision {prec}: rel_err {rel_err(a1, r, 2 ** (-12)):.2e}, "
+              f"true relative error {true_rel_err(a1, r):.2e}")
         assert rel_err(a1, r, 2 ** (-12)) < tol, prec
+        assert true_rel_err(a1, r) < tol, prec
 
 
 def test_wide_tiles_against_golden_and_64_tiles():
@@ -225,10 +256,44 @@ def test_wide_tiles_against_golden_and_64_tiles():
             a1 = plan.contract(device_params(p))[0]
             a2 = plan.contract(device_params(p))[0]
             assert a1 == a2, (rows, cols, prec)
+            print(f"{rows}x{cols} depth {depth}, forced 128x128 tiles, precision {prec}: "
+                  f"rel_err {rel_err(a1, r, floor):.2e}, true relative error {true_rel_err(a1, r):.2e}")
             assert rel_err(a1, r, floor) < tol, (rows, cols, prec)
+            assert true_rel_err(a1, r) < tol, (rows, cols, prec)
             ref64 = api.compile(circ, amp, n_trials=32, seed=1, precision=prec, tile_mode=1)
             assert ref64.info().n_wide_nodes == 0
             assert rel_err(a1, ref64.contract(device_params(p))[0], floor) < tol
+
+
+@pytest.mark.parametrize("rows,cols", [(5, 5), (4, 7)])
+def test_wide_tiles_default_plan_against_golden(rows, cols):
+    """Depth-16 grids whose default plan (no tile forcing, 32 greedy trials)
+    puts its widest nodes on 128 x 128 tiles: launches of 256 to 65536
+    tiles, both tile orders (XCD-striped where the tile grid allows it,
+    row-major otherwise), K from 32 to 16384.  FP32 and split BF16 against
+    the stored oracle amplitude (state vector and time-order sweep, which
+    agree to ~1e-15); repeats bit-identical."""
+    from gpu_common import TOL_BF16X3
+    path = os.path.join(GOLDEN, f"grid{rows}x{cols}_d16_amplitude.json")
+    if not os.path.exists(path):
+        pytest.skip("reference amplitude not generated")
+    ref = json.load(open(path))
+    r = complex(ref["values"]["statevector"]["re"], ref["values"]["statevector"]["im"])
+    r2 = complex(ref["values"]["time"]["re"], ref["values"]["time"]["im"])
+    assert abs(r - r2) <= 1e-12 * abs(r)
+    circ, p, amp = tcgen.workload_grid_amplitude(rows, cols, 16)
+    floor = 2 ** (-rows * cols / 2)
+    for prec, tol in ((0, TOL_C64), (1, TOL_BF16X3)):
+        plan = api.compile(circ, amp, n_trials=32, seed=1, precision=prec)
+        assert plan.info().n_wide_nodes > 0
+        a1 = plan.contract(device_params(p))[0]
+        a2 = plan.contract(device_params(p))[0]
+        del plan
+        assert a1 == a2, prec
+        print(f"{rows}x{cols} depth 16, default plan, precision {prec}: "
+              f"rel_err {rel_err(a1, r, floor):.2e}, true relative error {true_rel_err(a1, r):.2e}")
+        assert rel_err(a1, r, floor) < tol, prec
+        assert true_rel_err(a1, r) < tol, prec
 
 
 def test_wide_tiles_full_size_deep_grid():
@@ -325,7 +390,7 @@ def test_gemm_path_matches_gather_path():
     e_ref, g_ref = sv.energy_grad(circ, p, obs)
     for e, g in ((e1, g1), (e2, g2)):
         assert rel_err(e[0], e_ref, 1.0) < TOL_C64
-        assert grad_err(g[0], g_ref) < TOL_C64
+        assert_grad(g[0], g_ref, TOL_C64)
     # batched rows through the GEMM tiles
     B = 16
     circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=14, layers=5)
@@ -334,7 +399,7 @@ def test_gemm_path_matches_gather_path():
     for b in (0, 9):
         e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
         assert rel_err(e[b], e_ref, 1.0) < TOL_C64
-        assert grad_err(g[b], g_ref) < TOL_C64
+        assert_grad(g[b], g_ref, TOL_C64)
 
 
 def test_grid_gemm_nodes_fp32_and_bf16x3():
@@ -364,7 +429,7 @@ def test_checkpointed_gradient_matches(ckpt):
     assert np.max(np.abs(e1 - e2)) < 1e-6
     assert np.max(np.abs(g1 - g2)) < 1e-6
     e_ref, g_ref = sv.energy_grad(circ, P[3], obs)
-    assert grad_err(g2[3], g_ref) < TOL_C64
+    assert_grad(g2[3], g_ref, TOL_C64)
 
 
 def test_term_mode_matches_level_mode_and_oracle():
@@ -384,7 +449,7 @@ def test_term_mode_matches_level_mode_and_oracle():
     results = [pl.contract_grad(device_params(p)) for pl in (tm, lev, ck)]
     for e, g in results:
         assert rel_err(e[0], e_ref, 1.0) < TOL_C64
-        assert grad_err(g[0], g_ref) < TOL_C64
+        assert_grad(g[0], g_ref, TOL_C64)
     # repeated calls reuse the same per-term regions
     e2, g2 = tm.contract_grad(device_params(p))
     assert e2[0] == results[0][0][0] and np.array_equal(g2, results[0][1])
@@ -397,7 +462,7 @@ def test_term_mode_matches_level_mode_and_oracle():
     for b in (0, 5):
         e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
         assert rel_err(e[b], e_ref, 1.0) < TOL_C64
-        assert grad_err(g[b], g_ref) < TOL_C64
+        assert_grad(g[b], g_ref, TOL_C64)
     # forward only, amplitude: a light tree, term mode chosen automatically
     circ, p, zz, amp = tcgen.workload_forward_chain()
     pa, a = one(circ, amp, p)
@@ -418,7 +483,7 @@ def test_autograd_function_matches_oracle():
     for b in range(B):
         e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
         assert abs(e[b].item() - e_ref) < TOL_C64
-        assert grad_err(gx[b].cpu().numpy() / w[b].item(), g_ref) < TOL_C64
+        assert_grad(gx[b].cpu().numpy() / w[b].item(), g_ref, TOL_C64)
 
 
 def test_state_errors():

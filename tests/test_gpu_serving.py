@@ -11,7 +11,7 @@ import tcgen
 from oracle import statevector as sv
 from paper_2205_10091_amd import _lib as L
 from paper_2205_10091_amd import serve
-from gpu_common import TOL_C64, grad_err, rel_err
+from gpu_common import TOL_C64, assert_grad, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_mix_matches_alone_and_oracle():
         if rq.circuit.n_qubits <= 16:
             if rq.want_grad:
                 e_ref, g_ref = sv.energy_grad(rq.circuit, rq.params, rq.observable)
-                assert grad_err(r.grad, g_ref) < TOL_C64
+                assert_grad(r.grad, g_ref, TOL_C64)
             else:
                 e_ref = sv.energy(rq.circuit, rq.params, rq.observable).real
             assert rel_err(r.value, e_ref, 1.0) < TOL_C64
