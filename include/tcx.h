@@ -372,6 +372,27 @@ tc_status tc_contract_device(tc_plan* plan, const float* params,
 tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
                                   double* value_dev, double* grad_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * tc_contract_grad_device computation run in a static device array of
+ * TC_NOALLOC_MAX_BYTES per GPU, reserved when the library is loaded and
+ * held until the process ends, instead of the plan's bound workspace.  It
+ * calls no hipMalloc/hipFree and never binds the plan (the plan may also be
+ * bound; its workspace is not touched).  Each call uploads the plan's tables
+ * and params into the array, enqueues the forward and reverse sweeps
+ * kernel by kernel (no graph) on the plan's stream (opts.stream; NULL = the
+ * null stream), and copies value (B doubles) and grad (B*n_params doubles)
+ * to the caller's DEVICE buffers; either may be NULL.  Does not
+ * synchronise.  The array is shared by every plan on that GPU and keeps
+ * the last call's contents: calls that overlap on one GPU (two streams,
+ * two threads) race and give wrong results.
+ * Errors: STATE without want_grad; TOO_LARGE when the plan's
+ * workspace_bytes exceed TC_NOALLOC_MAX_BYTES; BUSY as for the other
+ * contraction calls; DEVICE on HIP errors. */
+#define TC_NOALLOC_MAX_BYTES (64ull << 20)
+tc_status tc_contract_grad_device_noalloc(tc_plan* plan, const float* params,
+                                          double* value_dev, double* grad_dev);
+
 /* Profiling.  Runs the plan's kernels eagerly (not as a graph), one after
  * another on the plan's stream, `reps` times; every kernel's start and end
  * are stamped by its own dispatch (hipExtLaunchKernel events), so a

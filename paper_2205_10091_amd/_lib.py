@@ -131,6 +131,7 @@ SIGNATURES = [
     ("tc_contract_grad", C.c_int, [VP, VP, F64P, F64P]),
     ("tc_contract_device", C.c_int, [VP, VP, VP]),
     ("tc_contract_grad_device", C.c_int, [VP, VP, VP, VP]),
+    ("tc_contract_grad_device_noalloc", C.c_int, [VP, VP, VP, VP]),
     ("tc_plan_profile", C.c_int, [VP, VP, C.c_int32, C.c_int32, C.c_int32, I32P,
                                   I32P, F64P, F64P, F64P]),
     ("tc_serve_create", C.c_int, [C.POINTER(ServeOpts), PVP]),

@@ -249,6 +249,13 @@ class Plan:
             self.h, self._params_ptr(params), C.c_void_p(value_dev.data_ptr()),
             C.c_void_p(grad_dev.data_ptr())))
 
+    def contract_grad_device_noalloc(self, params, value_dev, grad_dev):
+        """tc_contract_grad_device_noalloc: the same outputs, computed in the
+        library's static per-GPU scratch array (no device allocation)."""
+        L.check(lib().tc_contract_grad_device_noalloc(
+            self.h, self._params_ptr(params), C.c_void_p(value_dev.data_ptr()),
+            C.c_void_p(grad_dev.data_ptr())))
+
 
 def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
             lightcone=True, absorb_1q=True, seed=0, n_trials=8,

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1359,6 +1360,74 @@ void free_device(Plan& P) {
   P.dev = nullptr;
 }
 
+// ------------------------------------------------------------------ static scratch
+//
+// Workspace for callers that cannot allocate device memory: one array per
+// GPU, reserved when the code object is loaded and held until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy (on
+// the host it names a stand-in, not the device copy); it uses the device
+// address that hipGetSymbolAddress returns for the current device.
+
+static __device__ __align__(256) char scratch[TC_NOALLOC_MAX_BYTES];
+
+struct ScratchSlot {
+  char* ptr = nullptr;
+  int n_cu = 0;
+};
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static ScratchSlot g_scratch[MAX_DEVICES];
+
+// The calling thread's current device must be `device`.
+static ScratchSlot scratch_slot(int device) {
+  if (device < 0 || device >= MAX_DEVICES) fail(TC_ERR_INVALID_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  ScratchSlot& s = g_scratch[device];
+  if (!s.ptr) {
+    void* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255) != 0) fail(TC_ERR_DEVICE, "scratch array has no usable address");
+    int cu = 0;
+    HIP_CHECK(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device));
+    s.n_cu = cu > 0 ? cu : 256;
+    s.ptr = (char*)p;
+  }
+  return s;
+}
+
+void contract_grad_noalloc(Plan& P, const float* params, double* value_dev, double* grad_dev) {
+  if (!P.want_grad) fail(TC_ERR_STATE, "plan was compiled without want_grad");
+  if (!params) fail(TC_ERR_INVALID_ARG, "params is NULL");
+  const WorkspaceLayout lay = workspace_layout(P);
+  if (lay.total > TC_NOALLOC_MAX_BYTES)
+    fail(TC_ERR_TOO_LARGE, "plan needs " + std::to_string(lay.total) +
+                               " bytes of workspace, more than the static scratch holds (" +
+                               std::to_string((uint64_t)TC_NOALLOC_MAX_BYTES) + ")");
+  BusyGuard g(P.busy);
+  HIP_CHECK(hipSetDevice(P.device));
+  const ScratchSlot s = scratch_slot(P.device);
+  hipStream_t st = (hipStream_t)P.user_stream;
+  // the tables of whichever plan ran here last are replaced; every value
+  // the kernels read is either uploaded here or written by an earlier
+  // kernel of this call, so nothing needs clearing
+  upload_tables(P, s.ptr, lay, st);
+  const uint64_t pbytes = (uint64_t)P.batch * P.n_params * sizeof(float);
+  if (pbytes)
+    HIP_CHECK(hipMemcpyAsync(s.ptr + lay.params, params, pbytes, hipMemcpyDeviceToDevice, st));
+  for (const std::vector<Launch>* seq : {&P.fwd, &P.bwd})
+    for (const Launch& x : *seq) {
+      SegRef r{&P, s.ptr, &lay, &x};
+      launch_segments(x.kind, &r, 1, st, s.n_cu, P.precision);
+    }
+  if (value_dev)
+    HIP_CHECK(hipMemcpy2DAsync(value_dev, sizeof(double), s.ptr + lay.value, 2 * sizeof(double),
+                               sizeof(double), (size_t)P.batch, hipMemcpyDeviceToDevice, st));
+  if (grad_dev && P.n_params)
+    HIP_CHECK(hipMemcpyAsync(grad_dev, s.ptr + lay.grad,
+                             (uint64_t)P.batch * P.n_params * sizeof(double),
+                             hipMemcpyDeviceToDevice, st));
+}
+
 }  // namespace tcx
 
 // ------------------------------------------------------------------ C ABI
@@ -1480,6 +1549,15 @@ tc_status tc_contract_grad_device(tc_plan* plan, const float* params, double* va
   TC_GUARD_BEGIN
   if (!plan) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
   tcx::contract_grad(plan->p, params, value_dev, grad_dev, true);
+  return TC_OK;
+  TC_GUARD_END
+}
+
+tc_status tc_contract_grad_device_noalloc(tc_plan* plan, const float* params,
+                                          double* value_dev, double* grad_dev) {
+  TC_GUARD_BEGIN
+  if (!plan) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tcx::contract_grad_noalloc(plan->p, params, value_dev, grad_dev);
   return TC_OK;
   TC_GUARD_END
 }
