@@ -135,29 +135,28 @@ def cpu_baseline(circ, p, obs, budget_s=12.0):
             "host_cpu_count": os.cpu_count()}
 
 
-def serve_workload(args, out):
-    """Serving mix: chains and grids of 8-64 qubits (chains up to 600 at
-    depth 2), depth 2-10, TFIM energy (g ~ U[0.5, 1.5]) with gradient for
-    half of them, Poisson arrivals.  The plain per-circuit form (plan +
-    contract each request alone, one after another) sets the saturated
-    rate; the engine is then driven at 0.5, 0.8 and 0.95 of it."""
+def serving_leg(n_req=60, fracs=(0.8,), n_plain=30, path_trials=4):
+    """Serving mix (seed 6): chains and grids of 8-64 qubits (chains up to
+    600 at depth 2), depth 2-10, TFIM energy (g ~ U[0.5, 1.5]) with gradient
+    for half of them, Poisson arrivals, 4 GiB per request.  The plain
+    per-circuit form (plan + contract each request alone, one after
+    another, same per-request cap) sets the saturated rate; the engine is
+    driven at the given fractions of it, and once with every request
+    submitted at t = 0 (its capacity)."""
+    import torch
     import tcgen
     from paper_2205_10091_amd import _lib as L
     from paper_2205_10091_amd import api, serve
-    import torch
-    n_req = max(args.steps, 20)
     reqs = tcgen.serving_requests(n_req, 1.0, seed=6)
-    # plain per-circuit form on the first requests
     t0 = time.perf_counter()
     done = rejected = 0
-    n_plain = min(40, n_req)
     for k, rq in enumerate(reqs[:n_plain]):
         if k % 10 == 0:
             print(f"[serve] plain per-circuit {k}/{n_plain} t={time.perf_counter() - t0:.1f}s",
                   file=sys.stderr, flush=True)
         try:
-            plan = api.compile(rq.circuit, rq.observable, want_grad=rq.want_grad, n_trials=1,
-                               mem_budget_bytes=4 << 30)
+            plan = api.compile(rq.circuit, rq.observable, want_grad=rq.want_grad,
+                               n_trials=path_trials, seed=0x5eed, mem_budget_bytes=4 << 30)
         except L.TcxError as e:
             if e.status != L.TC_ERR_TOO_LARGE:
                 raise
@@ -168,45 +167,54 @@ def serve_workload(args, out):
             plan.contract_grad(par)
         else:
             plan.contract(par)
+        del plan
         done += 1
+    torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
-    lam_sat = (done + rejected) / plain_s
-    out["plain_per_circuit"] = {"requests": done + rejected, "rejected": rejected,
-                                "requests_per_s": lam_sat}
-    runs = []
-    for frac in (0.5, 0.8, 0.95):
-        rate = frac * lam_sat
-        rs = tcgen.serving_requests(n_req, rate, seed=6)
+    lam = (done + rejected) / plain_s
+    res = {"workload": "serving_mix_chain_grid_8_64_depth_2_10", "requests": n_req,
+           "max_request_bytes": 4 << 30, "path_trials": path_trials,
+           "plain_per_circuit": {"requests": done + rejected, "rejected": rejected,
+                                 "requests_per_s": lam}}
+
+    def engine(rate, realtime):
         srv = serve.Server(pool_bytes=64 << 30, max_request_bytes=4 << 30, max_active=64,
-                           path_trials=1)
-        print(f"[serve] engine at {frac:.2f} of plain rate ({rate:.2f} req/s)",
-              file=sys.stderr, flush=True)
-        rep = serve.run(srv, rs, realtime=True, progress=lambda t, d, r, p: print(
-            f"[serve]   t={t:.1f}s done={d} rejected={r} pending={p}", file=sys.stderr, flush=True))
+                           path_trials=path_trials)
+        rep = serve.run(srv, tcgen.serving_requests(n_req, rate, seed=6), realtime=realtime,
+                        progress=lambda t, d, r, p: print(
+                            f"[serve]   t={t:.1f}s done={d} rejected={r} pending={p}",
+                            file=sys.stderr, flush=True))
         srv.close()
-        s = rep.summary()
-        s["rate_per_s"] = rate
-        s["rate_frac_of_plain"] = frac
-        s["rejected_frac"] = len(rep.rejected) / n_req
-        runs.append(s)
-    # the engine's capacity: every request submitted at once
-    srv = serve.Server(pool_bytes=64 << 30, max_request_bytes=4 << 30, max_active=64,
-                       path_trials=1)
+        x = rep.summary()
+        x["rejected_frac"] = len(rep.rejected) / n_req
+        return x
+
+    runs = []
+    for frac in fracs:
+        print(f"[serve] engine at {frac:.2f} of the plain rate ({frac * lam:.2f} req/s)",
+              file=sys.stderr, flush=True)
+        x = engine(frac * lam, True)
+        x.update({"rate_per_s": frac * lam, "rate_frac_of_plain": frac})
+        runs.append(x)
     print("[serve] engine saturated (all requests at t = 0)", file=sys.stderr, flush=True)
-    rep = serve.run(srv, tcgen.serving_requests(n_req, 1.0, seed=6), realtime=False,
-                    progress=lambda t, d, r, p: print(
-                        f"[serve]   t={t:.1f}s done={d} rejected={r} pending={p}",
-                        file=sys.stderr, flush=True))
-    srv.close()
-    out["saturated"] = rep.summary()
-    best = runs[-1]
+    res["poisson"] = runs
+    res["saturated"] = engine(1.0, False)
+    res["saturated"]["vs_plain_per_circuit"] = res["saturated"]["evals_per_s"] / lam if lam else None
+    return res
+
+
+def serve_workload(args, out):
+    """--workload serve: the serving leg at 0.5, 0.8 and 0.95 of the plain
+    rate; value = evaluations/s at 0.95."""
+    res = serving_leg(n_req=max(args.steps, 20), fracs=(0.5, 0.8, 0.95))
+    best = res["poisson"][-1]
     out.update({"metric": "circuit evals/s under Poisson arrivals (serving mix), p50/p99 latency",
                 "value": best["evals_per_s"], "unit": "evals/s",
                 "ms_per_step": 1e3 / best["evals_per_s"] if best["evals_per_s"] else None,
                 "dtype": "c64 (fp32) + fp64 sums",
-                "config": {"workload": "serving_mix_chain_grid_8_64_depth_2_10", "requests": n_req,
-                           "max_active": 64, "path_trials": 1},
-                "serving": runs})
+                "config": {"workload": res["workload"], "requests": res["requests"],
+                           "max_active": 64, "path_trials": res["path_trials"]},
+                "serving": res})
 
 
 def golden_amplitude(rows, cols, depth):
@@ -467,6 +475,10 @@ def main():
         out["grid_amplitude"] = grid_leg(6, 6, 8, grid_trials, 50, 5, "grid")
         print("[bench] grid 4x7 depth 16 (wide nodes)", file=sys.stderr, flush=True)
         out["wide_nodes"] = grid_leg(4, 7, 16, grid_trials, 5, 1, "wide")
+        # the first 20 requests of the serving stream (the full 60-request
+        # run at three rates is --workload serve, about ten minutes)
+        print("[bench] serving mix", file=sys.stderr, flush=True)
+        out["serving"] = serving_leg(n_req=20, n_plain=20)
 
     if args.copy_calibration:
         n = args.copy_calibration // 4

@@ -246,8 +246,13 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *               wide nodes, complex64 elsewhere;
  *   batch       number of parameter vectors B evaluated per call (>= 1);
  *   want_grad   keep intermediates and compile the reverse sweep;
- *   mem_budget_bytes  0 = no limit; otherwise TOO_LARGE if the workspace
- *               exceeds it;
+ *   mem_budget_bytes  0 = no limit; otherwise the plan is made to fit it:
+ *               when the terms' intermediates, all live at once under
+ *               level-by-level execution, would exceed it, the terms run
+ *               in groups (level by level within a group, one group after
+ *               another, sized to about 80 % of the budget), and with
+ *               want_grad, if that is not enough, with checkpointed
+ *               segments; TOO_LARGE if the workspace still exceeds it;
  *   stream      hipStream_t to run on (NULL = the library's own stream);
  *   gemm_min_k  nodes with K >= gemm_min_k contracted indices (K = product
  *               of their dimensions) and M, N >= 16 run on the MFMA GEMM,
@@ -339,6 +344,10 @@ typedef struct {
   int32_t n_split_sums;      /* gather nodes (long sums, few outputs)
                                 whose K is cut into slices               */
   int32_t n_wide_nodes;      /* GEMM nodes in 128 x 128 tiles            */
+  int32_t n_term_groups;     /* terms run in this many groups, one group's
+                                forward pass and reverse sweep after the
+                                other's, so that the live intermediates
+                                fit mem_budget_bytes (1 = all together)  */
 } tc_plan_info;
 
 tc_status tc_plan_info_get(const tc_plan* plan, tc_plan_info* out);
@@ -454,6 +463,10 @@ typedef struct {
   double submit_to_done_s;    /* library-measured latency                 */
   int32_t want_grad;
   int32_t status;             /* tc_status of the request                 */
+  double plan_s;              /* of which host planning (network, path,
+                                 plan; ~0 on a plan-cache hit)            */
+  double admit_to_done_s;     /* of which from admission (pool memory and
+                                 a slot granted) to the result            */
 } tc_serve_result;
 
 tc_status tc_serve_create(const tc_serve_opts* opts, tc_server** out);

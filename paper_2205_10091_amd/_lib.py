@@ -85,7 +85,7 @@ class PlanInfo(C.Structure):
                 ("n_params", C.c_int32), ("n_terms", C.c_int32),
                 ("checkpoint_every", C.c_int32), ("exec_mode", C.c_int32),
                 ("n_split_nodes", C.c_int32), ("n_split_sums", C.c_int32),
-                ("n_wide_nodes", C.c_int32)]
+                ("n_wide_nodes", C.c_int32), ("n_term_groups", C.c_int32)]
 
 
 class ServeOpts(C.Structure):
@@ -97,7 +97,8 @@ class ServeOpts(C.Structure):
 class ServeResult(C.Structure):
     _fields_ = [("id", C.c_int64), ("value", C.c_double),
                 ("value_im", C.c_double), ("submit_to_done_s", C.c_double),
-                ("want_grad", C.c_int32), ("status", C.c_int32)]
+                ("want_grad", C.c_int32), ("status", C.c_int32),
+                ("plan_s", C.c_double), ("admit_to_done_s", C.c_double)]
 
 
 VP = C.c_void_p

@@ -1121,12 +1121,12 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
   HIP_CHECK(hipGetLastError());
 }
 
-static void enqueue(const Plan& P, DeviceState& D, const std::vector<Launch>& seq,
+static void enqueue(const Plan& P, DeviceState& D, const std::vector<const Launch*>& seq,
                     int parts = PART_ALL) {
   const Fork fork{D.side, D.fork_start, D.fork_done};
-  for (const Launch& x : seq) {
-    SegRef s{&P, D.ws, &D.lay, &x};
-    launch_segments(x.kind, &s, 1, D.stream, D.n_cu, P.precision, &fork, parts);
+  for (const Launch* x : seq) {
+    SegRef s{&P, D.ws, &D.lay, x};
+    launch_segments(x->kind, &s, 1, D.stream, D.n_cu, P.precision, &fork, parts);
   }
 }
 
@@ -1175,8 +1175,7 @@ static void release(DeviceState* D) {
 }
 
 static void capture(const Plan& P, DeviceState& D, int which) {
-  std::vector<Launch> seq = P.fwd;
-  if (which == 1) seq.insert(seq.end(), P.bwd.begin(), P.bwd.end());
+  const std::vector<const Launch*> seq = launch_order(P, which == 1);
   HIP_CHECK(hipStreamBeginCapture(D.stream, hipStreamCaptureModeThreadLocal));
   try {
     enqueue(P, D, seq);
@@ -1288,29 +1287,29 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
   BusyGuard g(P.busy);
   stage_params(P, params);
   DeviceState& D = *P.dev;
-  std::vector<Launch> all = P.fwd;
-  if (which == 1) all.insert(all.end(), P.bwd.begin(), P.bwd.end());
+  const std::vector<const Launch*> all = launch_order(P, which == 1);
   // one entry per kernel: a level contributes its GEMM and gather kernels
   struct Entry {
-    Launch L;
+    const Launch* Lp;
     int kind, parts;
     double flops, bytes;
   };
   std::vector<Entry> seq;
-  for (const Launch& L : all) {
+  for (const Launch* Lp : all) {
+    const Launch& L = *Lp;
     if (L.kind != L_LEVEL) {
-      seq.push_back({L, L.kind, PART_ALL, L.flops, L.bytes});
+      seq.push_back({Lp, L.kind, PART_ALL, L.flops, L.bytes});
       continue;
     }
-    if (L.htiles) seq.push_back({L, PROF_WIDE, PART_WIDE, L.wide_flops, L.wide_bytes});
+    if (L.htiles) seq.push_back({Lp, PROF_WIDE, PART_WIDE, L.wide_flops, L.wide_bytes});
     if (L.tiles || L.wtiles)
-      seq.push_back({L, PROF_GEMM, PART_GEMM, L.gemm_flops - L.wide_flops,
+      seq.push_back({Lp, PROF_GEMM, PART_GEMM, L.gemm_flops - L.wide_flops,
                      L.gemm_bytes - L.wide_bytes});
     if (L.work)
-      seq.push_back({L, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops - L.rt_flops - L.gs_flops,
+      seq.push_back({Lp, PROF_GATHER, PART_GATHER, L.flops - L.gemm_flops - L.rt_flops - L.gs_flops,
                      L.bytes - L.gemm_bytes - L.rt_bytes - L.gs_bytes});
-    if (L.rblocks) seq.push_back({L, PROF_ROWTILE, PART_ROWTILE, L.rt_flops, L.rt_bytes});
-    if (L.xwork) seq.push_back({L, PROF_GSPLIT, PART_GSPLIT, L.gs_flops, L.gs_bytes});
+    if (L.rblocks) seq.push_back({Lp, PROF_ROWTILE, PART_ROWTILE, L.rt_flops, L.rt_bytes});
+    if (L.xwork) seq.push_back({Lp, PROF_GSPLIT, PART_GSPLIT, L.gs_flops, L.gs_bytes});
   }
   // per entry: the start of its first kernel to the end of its last, as
   // stamped by the kernel dispatches (no queueing gap between launches)
@@ -1324,7 +1323,7 @@ void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_
         ProfEvents pe{ev[2 * i], ev[2 * i + 1], false};
         t_prof = &pe;
         try {
-          enqueue(P, D, std::vector<Launch>{seq[i].L}, seq[i].parts);
+          enqueue(P, D, std::vector<const Launch*>{seq[i].Lp}, seq[i].parts);
         } catch (...) {
           t_prof = nullptr;
           throw;
@@ -1414,11 +1413,10 @@ void contract_grad_noalloc(Plan& P, const float* params, double* value_dev, doub
   const uint64_t pbytes = (uint64_t)P.batch * P.n_params * sizeof(float);
   if (pbytes)
     HIP_CHECK(hipMemcpyAsync(s.ptr + lay.params, params, pbytes, hipMemcpyDeviceToDevice, st));
-  for (const std::vector<Launch>* seq : {&P.fwd, &P.bwd})
-    for (const Launch& x : *seq) {
-      SegRef r{&P, s.ptr, &lay, &x};
-      launch_segments(x.kind, &r, 1, st, s.n_cu, P.precision);
-    }
+  for (const Launch* x : launch_order(P, true)) {
+    SegRef r{&P, s.ptr, &lay, x};
+    launch_segments(x->kind, &r, 1, st, s.n_cu, P.precision);
+  }
   if (value_dev)
     HIP_CHECK(hipMemcpy2DAsync(value_dev, sizeof(double), s.ptr + lay.value, 2 * sizeof(double),
                                sizeof(double), (size_t)P.batch, hipMemcpyDeviceToDevice, st));

@@ -233,6 +233,11 @@ struct Schedule {
   std::vector<std::pair<size_t, int32_t>> leaf_adj_term;  // (term, leaf index)
   int32_t max_level = 0, root_step = 0, grad_step = 0;
   uint64_t seed_elems = 0, arena_elems = 0, peak_tensor_elems = 0;
+  // term groups: group g's steps are (g span, (g + 1) span]; live elements
+  // at the busiest step of each group, and after the leaves are placed
+  int32_t span = 0;
+  std::vector<uint64_t> group_peak;
+  uint64_t base_live = 0;
 };
 
 // Builds tensors, ops with their steps, lifetimes and arena offsets.
@@ -246,8 +251,14 @@ bool block_gemm_node(const Plan& plan, uint32_t M, uint32_t N, uint32_t K, uint3
          K >= (uint32_t)plan.block_tile_min_k;
 }
 
+// Term groups (grp: term -> group, G groups; nullptr = one group): the
+// terms of a group advance level by level together, and group g runs its
+// whole forward pass and reverse sweep before group g + 1 starts, so only
+// one group's intermediates are live at a time.  The root sum and the
+// gradient sum follow the last group.
 void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& path, int B,
-              bool grad, int ckpt, bool per_term_arena) {
+              bool grad, int ckpt, bool per_term_arena,
+              const std::vector<int32_t>* grp = nullptr, int32_t G = 1) {
   std::vector<PT>& T = S.T;
   S.ti.assign(net.terms.size(), TermInfo{});
 
@@ -342,9 +353,32 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
     }
   }
   const int32_t Lf = S.max_level;
-  S.root_step = Lf + 1;
   const bool ck = grad && ckpt >= 2;
   auto seg_of = [&](int32_t level) { return level <= 0 ? -1 : (level - 1) / ckpt; };
+
+  // ---- timeline of one group: forward levels 1..Lf, one empty step, then
+  // for each checkpoint segment from the top its recompute steps (ascending
+  // levels) and its adjoint steps (descending); groups follow each other,
+  // then the root sum and the gradient sum
+  const int32_t nseg = ck ? seg_of(Lf) + 1 : 1;
+  std::vector<int32_t> recompute_step(Lf + 2, -1), adjoint_step(Lf + 2, -1);
+  S.span = Lf;
+  if (grad) {
+    int32_t st = Lf + 2;
+    for (int32_t sg = nseg - 1; sg >= 0; --sg) {
+      const int32_t lo = ck ? sg * ckpt + 1 : 1;
+      const int32_t hi = ck ? std::min((sg + 1) * ckpt, Lf) : Lf;
+      if (ck)
+        for (int32_t l = lo; l < hi; ++l) recompute_step[l] = st++;
+      for (int32_t l = hi; l >= lo; --l) adjoint_step[l] = st++;
+    }
+    S.span = st - 1;
+  }
+  if (G < 1 || (G > 1 && (!grp || grp->size() != net.terms.size())))
+    fail(TC_ERR_INVALID_ARG, "internal: term groups");
+  S.root_step = G * S.span + 1;
+  S.grad_step = S.root_step + 1;
+  auto goff = [&](size_t t) { return G > 1 ? (*grp)[t] * S.span : 0; };
 
   // ---- forward ops and last uses
   for (size_t t = 0; t < net.terms.size(); ++t) {
@@ -353,29 +387,13 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
     const int32_t nl = (int32_t)net.terms[t].leaves.size();
     for (size_t s = 0; s < tp.pairs.size(); ++s) {
       int32_t a = tp.pairs[s].first, b = tp.pairs[s].second, c = nl + (int32_t)s;
-      int32_t step = I.level[c];
+      int32_t step = goff(t) + I.level[c];
+      T[I.tid[c]].first = step;
       S.pend.push_back({I.tid[a], I.tid[b], I.tid[c], step, (int32_t)t, false, false});
       T[I.tid[a]].last = std::max(T[I.tid[a]].last, step);
       T[I.tid[b]].last = std::max(T[I.tid[b]].last, step);
     }
     if (I.root >= 0) T[I.tid[I.root]].last = S.root_step;
-  }
-
-  // ---- reverse sweep (and recomputation under checkpointing)
-  // Timeline after the root step: for each segment from the top, its
-  // recompute steps (ascending levels), then its adjoint steps (descending).
-  const int32_t nseg = ck ? seg_of(Lf) + 1 : 1;
-  std::vector<int32_t> recompute_step(Lf + 2, -1), adjoint_step(Lf + 2, -1);
-  {
-    int32_t st = S.root_step + 1;
-    for (int32_t sg = nseg - 1; sg >= 0; --sg) {
-      const int32_t lo = ck ? sg * ckpt + 1 : 1;
-      const int32_t hi = ck ? std::min((sg + 1) * ckpt, Lf) : Lf;
-      if (ck)
-        for (int32_t l = lo; l < hi; ++l) recompute_step[l] = st++;
-      for (int32_t l = hi; l >= lo; --l) adjoint_step[l] = st++;
-    }
-    S.grad_step = st;
   }
   if (grad) {
     for (size_t t = 0; t < net.terms.size(); ++t) {
@@ -402,7 +420,7 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
                          [&](int32_t u, int32_t v) { return I.level[u] < I.level[v]; });
         for (int32_t x : order) {
           int32_t a = tp.pairs[x - nl].first, b = tp.pairs[x - nl].second;
-          int32_t step = recompute_step[I.level[x]];
+          int32_t step = goff(t) + recompute_step[I.level[x]];
           PT r = T[I.tid[x]];
           r.off = -1;
           r.first = step;
@@ -420,7 +438,7 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
       for (int32_t c = ns - 1; c >= nl; --c) {
         if (adj[c] < 0) continue;
         int32_t a = tp.pairs[c - nl].first, b = tp.pairs[c - nl].second;
-        int32_t step = adjoint_step[I.level[c]];
+        int32_t step = goff(t) + adjoint_step[I.level[c]];
         for (int side = 0; side < 2; ++side) {
           int32_t x = side == 0 ? a : b, other = side == 0 ? b : a;
           if (!I.needs[x]) continue;
@@ -460,10 +478,12 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
   for (int32_t i = 0; i < (int32_t)T.size(); ++i)
     if (!T[i].fixed) members[per_term_arena ? T[i].term : 0].push_back(i);
   uint64_t base = S.seed_elems;
+  S.group_peak.assign(G, 0);
   for (const auto& mem : members) {
     Arena ar;
     ar.top = base;
     uint64_t top = base;
+    uint64_t live = 0;
     std::vector<std::vector<int32_t>> born(n_steps + 1), dies(n_steps + 2);
     for (int32_t i : mem) {
       born[T[i].first].push_back(i);
@@ -473,6 +493,7 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
       for (int32_t i : dies[s]) {
         uint64_t n = T[i].elems * (T[i].batched ? (uint64_t)B : 1);
         ar.release((uint64_t)T[i].off, n);
+        live -= Arena::align(std::max<uint64_t>(n, 1));
       }
       // big tensors first keeps the best-fit layout compact
       std::sort(born[s].begin(), born[s].end(),
@@ -482,6 +503,12 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
         T[i].off = (int64_t)ar.alloc(n);
         top = std::max(top, ar.top);
         S.peak_tensor_elems = std::max(S.peak_tensor_elems, n);
+        live += Arena::align(std::max<uint64_t>(n, 1));
+      }
+      if (s == 0) S.base_live = std::max(S.base_live, live);
+      if (!per_term_arena && s >= 1 && s <= G * S.span) {
+        uint64_t& gp = S.group_peak[(s - 1) / S.span];
+        gp = std::max(gp, live);
       }
     }
     base = Arena::align(top);
@@ -517,6 +544,18 @@ WorkspaceLayout workspace_layout(const Plan& p) {
   return w;
 }
 
+std::vector<const Launch*> launch_order(const Plan& p, bool with_grad) {
+  std::vector<const Launch*> seq;
+  seq.reserve(p.fwd.size() + (with_grad ? p.bwd.size() : 0));
+  size_t i = 0, j = 0;
+  while (i < p.fwd.size() || (with_grad && j < p.bwd.size())) {
+    const bool take_fwd = i < p.fwd.size() &&
+                          (!with_grad || j >= p.bwd.size() || p.fwd[i].step <= p.bwd[j].step);
+    seq.push_back(take_fwd ? &p.fwd[i++] : &p.bwd[j++]);
+  }
+  return seq;
+}
+
 void build_plan(Plan& plan, const Network& net, const Path& path) {
   const int B = plan.batch;
   const bool grad = plan.want_grad != 0;
@@ -524,12 +563,91 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   plan.n_terms = (int32_t)net.terms.size();
   if (path.terms.size() != net.terms.size()) fail(TC_ERR_INVALID_ARG, "path does not match network");
 
-  // ---- schedule, with checkpointing when the budget asks for it
+  // ---- schedule under the memory budget: all terms level by level; if
+  // their live intermediates do not fit, terms in groups run one group
+  // after another; with a gradient, then checkpointed segments (which
+  // recompute forward values), alone or with groups
   Schedule S;
   int ckpt = plan.checkpoint > 0 ? plan.checkpoint : 0;
+  std::vector<int32_t> grp;
+  int32_t G = 1;
   schedule(S, plan, net, path, B, grad, ckpt, false);
-  if (grad && plan.checkpoint == 0 && plan.budget && S.arena_elems * 8 > plan.budget &&
-      S.max_level >= 4) {
+  // bytes of the op records and per-item op tables (an upper estimate:
+  // every gather item of every op), which share the budget with the arena
+  uint64_t tab_est = 0;
+  if (plan.budget) {
+    int32_t nlab = 0;
+    for (const Term& term : net.terms) nlab = std::max(nlab, term.n_labels);
+    std::vector<char> inb(nlab, 0);
+    double items = 0;
+    for (const PendingOp& q : S.pend) {
+      const PT& A = S.T[q.a];
+      const PT& Bt = S.T[q.b];
+      for (int32_t l : Bt.legs) inb[l] = 1;
+      uint32_t sh = 0;
+      for (int32_t l : A.legs) sh += inb[l];
+      for (int32_t l : Bt.legs) inb[l] = 0;
+      const uint32_t K = 1u << sh, M = 1u << (A.legs.size() - sh), N = 1u << (Bt.legs.size() - sh);
+      const uint32_t rows = (A.batched || Bt.batched) && B > 1 ? (uint32_t)B : 1u;
+      items += (double)std::min<uint64_t>(gather_items(M, N, K, rows, LEVEL_LANES), ITEM_TABLE_MAX);
+    }
+    const double b = (double)S.pend.size() * sizeof(DevOp) +
+                     4.0 * std::min(items, (double)ITEM_TABLES_TOTAL_MAX);
+    // plus the split-K partial tiles, held to a sixteenth of the budget
+    tab_est = (uint64_t)(1.25 * b) + (uint64_t(1) << 16) + plan.budget / 16;
+  }
+  auto over = [&](const Schedule& x) {
+    return plan.budget && x.arena_elems * 8 + tab_est > plan.budget;
+  };
+  const size_t nt = net.terms.size();
+  // groups of consecutive terms whose live intermediates (estimated from
+  // each term's peak when run alone) fit 80 % of the budget, the rest
+  // being left for tables and split regions; fewer terms per group until
+  // the arena fits
+  uint64_t single_term_bytes = ~uint64_t(0);  // arena with one term at a time, if tried
+  auto try_groups = [&](int c) {
+    if (nt < 2 || plan.exec_mode == 2) return false;
+    std::vector<int32_t> one(nt);
+    for (size_t t = 0; t < nt; ++t) one[t] = (int32_t)t;
+    Schedule s1;
+    schedule(s1, plan, net, path, B, grad, c, false, &one, (int32_t)nt);
+    single_term_bytes = std::min(single_term_bytes, s1.arena_elems * 8);
+    if (over(s1)) return false;
+    const double cap = 0.9 * (double)(plan.budget - std::min(tab_est, plan.budget)) / 8.0;
+    for (double f : {1.0, 0.6, 0.35, 0.0}) {
+      std::vector<int32_t> g(nt);
+      int32_t ng = 0;
+      double acc = 0;
+      for (size_t t = 0; t < nt; ++t) {
+        const double need = (double)(s1.group_peak[t] > s1.base_live ? s1.group_peak[t] - s1.base_live : 0);
+        if (t > 0 && (f == 0.0 || s1.base_live + acc + need > f * cap)) {
+          ++ng;
+          acc = 0;
+        }
+        g[t] = ng;
+        acc += need;
+      }
+      ++ng;
+      if (ng == (int32_t)nt) {
+        S = std::move(s1);
+        grp = std::move(one);
+        G = ng;
+        ckpt = c;
+        return true;
+      }
+      Schedule sg;
+      schedule(sg, plan, net, path, B, grad, c, false, &g, ng);
+      if (!over(sg)) {
+        S = std::move(sg);
+        grp = std::move(g);
+        G = ng;
+        ckpt = c;
+        return true;
+      }
+    }
+    return false;
+  };
+  if (over(S) && !try_groups(ckpt) && grad && plan.checkpoint == 0 && S.max_level >= 4) {
     // smallest arena over a few segment lengths
     Schedule best;
     int best_c = 0;
@@ -542,11 +660,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         best_c = c;
       }
     }
-    if (best.arena_elems < S.arena_elems) {
+    if (best_c && !over(best)) {
       S = std::move(best);
       ckpt = best_c;
+    } else if (best_c) {
+      if (!try_groups(best_c) && best.arena_elems < S.arena_elems) {
+        S = std::move(best);
+        ckpt = best_c;
+      }
     }
   }
+  plan.term_groups = G;
   // leg label -> position in one operand's storage order (-1: absent)
   int32_t n_labels = 0;
   for (const Term& term : net.terms) n_labels = std::max(n_labels, term.n_labels);
@@ -606,6 +730,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     term_step[it->first] = t;
   }
+  if (G > 1)  // groups run level launches only
+    for (auto& ts : term_step) ts.second = false;
   bool any_term = false, any_level = false;
   for (const auto& ts : term_step) (ts.second ? any_term : any_level) = true;
   if (any_term) {
@@ -629,9 +755,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   plan.arena_elems = S.arena_elems;
   plan.peak_tensor_elems = S.peak_tensor_elems;
   // the arena alone already exceeds the budget: stop before building tables
-  if (plan.budget && plan.arena_elems * 8 > plan.budget)
+  if (plan.budget && plan.arena_elems * 8 > plan.budget) {
+    if (single_term_bytes != ~uint64_t(0) && single_term_bytes > plan.budget)
+      fail(TC_ERR_TOO_LARGE, "live intermediates need " + std::to_string(single_term_bytes) +
+                                 " bytes even with one term at a time, more than the memory budget");
     fail(TC_ERR_TOO_LARGE, "live intermediates need " + std::to_string(plan.arena_elems * 8) +
                                " bytes, more than the memory budget");
+  }
   std::vector<PT>& T = S.T;
   std::vector<PendingOp>& pend = S.pend;
   std::vector<TermInfo>& ti = S.ti;
@@ -676,6 +806,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     std::copy(gt.begin(), gt.end(), group_term.begin() + seg_begin);
     Launch L;
     L.kind = L_TERM;
+    L.step = seg_first_step;
     L.begin = (uint32_t)plan.ranges.size();
     L.with_leaves = seg_first_step == 1;  // the first term launch also materialises the leaves
     L.flops = seg_flops;
@@ -849,17 +980,24 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         // a sum too long even for 64 lanes (few outputs, huge K: a final
         // inner product) is cut into slices reduced afterwards, as split-K
         if (!term_mode && (op.K >> ls) > 256) {
+          // (partial sums of one op: at most a sixteenth of a memory budget)
+          const uint64_t outs = (uint64_t)op.rows * op.M * (op.N >> lv);
           uint32_t P = 1;
-          while (P < 65536 && (op.K >> ls) / P > 256) P *= 2;
+          while (P < 65536 && (op.K >> ls) / P > 256 &&
+                 (!plan.budget || outs * 2 * P * 2 * 4 <= plan.budget / 16))
+            P *= 2;
           op.ksplit = P;
-          sgf += f;
-          sgby += by;
+          if (P > 1) {
+            sgf += f;
+            sgby += by;
+          }
         }
         gc.push_back(op);
       }
     }
     Launch L;
     L.kind = L_LEVEL;
+    L.step = pend[i].step;
     L.flops = lf;
     L.bytes = lb;
     L.gemm_flops = gf;
@@ -875,13 +1013,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     // tile and the level's reduction kernel adds them in slice order.  The
     // partial tiles of one level reuse the region of every other level's
     // (levels never overlap).
+    // Under a memory budget the partial tiles of a level get at most a
+    // sixteenth of it (fewer slices; the result does not change).
     uint64_t part = 0;
     L.gbegin = (uint32_t)plan.ops.size();
     L.sbegin = (uint32_t)plan.split_units.size();
     auto split = [&](DevOp& op, uint64_t target_units, uint64_t floats_per_tile) {
       const uint64_t base = (uint64_t)op.rows * op.tiles_m * op.tiles_n;
       uint32_t P = 1;
-      while (P < 64 && base * P < target_units && op.K / (2 * P) >= 64) P *= 2;
+      while (P < 64 && base * P < target_units && op.K / (2 * P) >= 64 &&
+             (!plan.budget || (part + base * 2 * P * floats_per_tile) * 4 <= plan.budget / 16))
+        P *= 2;
       op.ksplit = P;
       if (P > 1) {
         op.part = part;
@@ -911,7 +1053,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     L.send = (uint32_t)plan.split_units.size();
     L.wend = (uint32_t)plan.ops.size();
     L.wtiles = wtiles;
-    if (wtiles && wtiles <= WAVE_TABLE_MAX) {
+    if (wtiles && wtiles <= WAVE_TABLE_MAX &&
+        plan.item_op.size() + wtiles <= ITEM_TABLES_TOTAL_MAX) {
       // wave tile -> op (relative to L.wbegin): one load instead of a search
       L.wunit_begin = plan.item_op.size();
       plan.item_op.resize(plan.item_op.size() + wtiles);
@@ -991,7 +1134,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     } else {
       L.xwork = (w + 63) & ~uint64_t(63);
     }
-    if (L.xbegin > L.begin && L.work <= ITEM_TABLE_MAX) {
+    if (L.xbegin > L.begin && L.work <= ITEM_TABLE_MAX &&
+        plan.item_op.size() + L.work <= ITEM_TABLES_TOTAL_MAX) {
       // item -> op (relative to L.begin); pad items map to the op before them
       L.item_begin = plan.item_op.size();
       plan.item_op.resize(plan.item_op.size() + L.work);
@@ -1093,6 +1237,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   {
     Launch L;
     L.kind = L_ROOT;
+    L.step = S.root_step;
     L.work = (uint64_t)B;
     plan.fwd.push_back(L);
   }
@@ -1129,6 +1274,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     if (net.n_params > 0) {
       Launch L;
       L.kind = L_GRAD;
+      L.step = S.grad_step;
       L.work = (uint64_t)B * net.n_params;
       plan.bwd.push_back(L);
     }
@@ -1342,6 +1488,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   info.n_params = net.n_params;
   info.n_terms = plan.n_terms;
   info.checkpoint_every = plan.checkpoint_used;
+  info.n_term_groups = plan.term_groups;
   info.exec_mode = plan.exec_used;
   for (const auto* seq : {&plan.fwd, &plan.bwd})
     for (const Launch& L : *seq)
@@ -1350,9 +1497,15 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         info.n_split_sums += (int32_t)(L.end - L.xbegin);
         info.n_wide_nodes += (int32_t)(L.hend - L.hbegin);
       }
-  if (plan.budget && info.workspace_bytes > plan.budget)
+  if (plan.budget && info.workspace_bytes > plan.budget) {
+    const WorkspaceLayout w = workspace_layout(plan);
     fail(TC_ERR_TOO_LARGE, "workspace of " + std::to_string(info.workspace_bytes) +
-                               " bytes exceeds the memory budget");
+                               " bytes (intermediates " + std::to_string(w.total - w.arena) +
+                               ", split partial sums and operand planes " +
+                               std::to_string(w.sunits - w.split) + ", tables and the rest " +
+                               std::to_string(w.arena - (w.sunits - w.split)) +
+                               ") exceeds the memory budget");
+  }
 }
 
 }  // namespace tcx

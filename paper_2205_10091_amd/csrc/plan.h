@@ -25,6 +25,8 @@ constexpr int32_t PROF_GEMM = 2, PROF_GATHER = 3, PROF_WIDE = 7, PROF_ROWTILE = 
 constexpr uint64_t NO_ITEMS = ~uint64_t(0);
 // levels with at most this many gather items get a per-item op index table
 constexpr uint64_t ITEM_TABLE_MAX = uint64_t(1) << 18;
+// all per-item tables of a plan together (levels past it search instead)
+constexpr uint64_t ITEM_TABLES_TOTAL_MAX = uint64_t(1) << 24;
 // automatic term launches: at most this many gather items per term and step
 // (two per thread of the 1024-thread workgroup)
 constexpr uint64_t TERM_MODE_MAX_ITEMS = 2048;
@@ -45,6 +47,7 @@ constexpr uint64_t TABLE_MAX_ENTRIES = uint64_t(1) << 27;
 
 struct Launch {
   int32_t kind;
+  int32_t step = 0;               // timeline step (the first one of a term launch)
   uint32_t begin = 0, end = 0;    // gather ops in Plan::ops
   uint64_t work = 0;              // gather work items / leaf, root, grad items
   uint32_t xbegin = 0;            // L_LEVEL: split gather ops are [xbegin, end)
@@ -103,6 +106,8 @@ struct Plan {
   // >= 2 = always with that length, -1 = never
   int32_t checkpoint = 0;
   int32_t checkpoint_used = 0;
+  // terms run in this many groups, one after another (1 = all together)
+  int32_t term_groups = 1;
 
   // tables uploaded once
   std::vector<DevOp> ops;
@@ -135,6 +140,11 @@ struct Plan {
 };
 
 void build_plan(Plan& plan, const Network& net, const Path& path);
+
+// The launches of one call in timeline order: the forward list alone, or
+// the forward and reverse lists merged by step (with term groups each
+// group's reverse sweep runs before the next group's forward pass).
+std::vector<const Launch*> launch_order(const Plan& p, bool with_grad);
 
 // Byte layout of the workspace: [tables][params][values][grad][arena]
 struct WorkspaceLayout {

@@ -85,7 +85,7 @@ struct Slot {
 
 struct Request {
   int64_t id = 0;
-  double t_submit = 0, t_done = 0;
+  double t_submit = 0, t_planned = 0, t_admit = 0, t_done = 0;
   int want_grad = 0;
   std::shared_ptr<Plan> plan;
   std::vector<float> params;
@@ -193,6 +193,7 @@ struct Server {
       ensure_slot(s, 2 + (uint64_t)r.plan->n_params, std::max<uint64_t>(1, r.params.size()));
       s.busy = true;
       r.slot = si;
+      r.t_admit = now_s();
       r.off = off;
       r.ws = pool_base + off;
       upload_tables(*r.plan, r.ws, r.lay, stream);
@@ -202,9 +203,7 @@ struct Server {
                                  r.params.size() * sizeof(float), hipMemcpyHostToDevice,
                                  stream));
       }
-      for (const Launch& x : r.plan->fwd) r.seq.push_back(&x);
-      if (r.want_grad)
-        for (const Launch& x : r.plan->bwd) r.seq.push_back(&x);
+      r.seq = launch_order(*r.plan, r.want_grad != 0);
       r.cursor = 0;
       active.push_back(std::move(queue.front()));
       queue.pop_front();
@@ -329,13 +328,25 @@ tc_status tc_serve_submit(tc_server* srv, const tc_circuit* circuit,
   if (!plan) {
     tc_path_opts po{0x5eed, S.opts.path_trials, TC_SCORE_COMBO, 0.1};
     tcx::Path path = tcx::greedy_path(net, po);
-    plan = std::make_shared<tcx::Plan>();
-    plan->batch = 1;
-    plan->want_grad = req->want_grad;
-    plan->device = S.opts.device;
-    plan->budget = S.opts.max_request_bytes;
-    plan->exec_mode = 1;  // requests advance one level per engine step
-    tcx::build_plan(*plan, net, path);  // TOO_LARGE when over the per-request cap
+    auto make = [&](int32_t wide_tiles) {
+      auto p = std::make_shared<tcx::Plan>();
+      p->batch = 1;
+      p->want_grad = req->want_grad;
+      p->device = S.opts.device;
+      p->budget = S.opts.max_request_bytes;
+      p->exec_mode = 1;  // requests advance one level per engine step
+      p->wide_tiles = wide_tiles;
+      tcx::build_plan(*p, net, path);  // TOO_LARGE when over the per-request cap
+      return p;
+    };
+    try {
+      plan = make(1);
+    } catch (const tcx::Error& e) {
+      // the wide tiles' operand planes may be what does not fit; the
+      // 64 x 64 tiles need none
+      if (e.status != TC_ERR_TOO_LARGE) throw;
+      plan = make(0);
+    }
     std::lock_guard<std::mutex> g(S.mu);
     if (S.cache.size() >= 512) S.cache.clear();
     S.cache.emplace(key, plan);
@@ -344,6 +355,7 @@ tc_status tc_serve_submit(tc_server* srv, const tc_circuit* circuit,
   req->params.assign(params, params + circuit->n_params);
   req->plan = plan;
   req->lay = tcx::workspace_layout(*plan);
+  req->t_planned = tcx::now_s();
   std::lock_guard<std::mutex> g(S.mu);
   req->id = S.next_id++;
   *id = req->id;
@@ -384,6 +396,8 @@ tc_status tc_serve_result_get(tc_server* srv, int64_t id, tc_serve_result* out,
   out->submit_to_done_s = r.t_done - r.t_submit;
   out->want_grad = r.want_grad;
   out->status = r.status;
+  out->plan_s = r.t_planned - r.t_submit;
+  out->admit_to_done_s = r.t_done - r.t_admit;
   if (grad && r.want_grad)
     for (size_t k = 0; k < r.grad.size(); ++k) grad[k] = r.grad[k];
   S.done.erase(it);

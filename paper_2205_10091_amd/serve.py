@@ -27,6 +27,8 @@ class Result:
     latency_s: float
     grad: Optional[np.ndarray]
     status: int
+    plan_s: float = 0.0           # host planning inside latency_s
+    device_s: float = 0.0         # admission to result inside latency_s
 
 
 class Server:
@@ -75,13 +77,15 @@ class Server:
         L.check(st)
         npar = self.n_params.pop(rid, 0)
         return Result(rid, out.value, out.value_im, out.submit_to_done_s,
-                      g[:npar].copy() if out.want_grad else None, out.status)
+                      g[:npar].copy() if out.want_grad else None, out.status,
+                      out.plan_s, out.admit_to_done_s)
 
 
 @dataclass
 class ServeReport:
     results: Dict[int, Result] = field(default_factory=dict)   # keyed by request index
     rejected: List[int] = field(default_factory=list)
+    reasons: Dict[int, str] = field(default_factory=dict)      # request index -> why rejected
     wall_s: float = 0.0
 
     def latencies(self):
@@ -90,43 +94,68 @@ class ServeReport:
     def summary(self):
         lat = self.latencies()
         n = len(lat)
+        pct = lambda a, q: float(np.percentile(a, q) * 1e3) if len(a) else None  # noqa: E731
+        plan = np.array([r.plan_s for r in self.results.values()])
+        dev = np.array([r.device_s for r in self.results.values()])
+        why = {}
+        for msg in self.reasons.values():
+            if "rank > 31" in msg:
+                k = "an intermediate above 2^31 elements"
+            elif "one term at a time" in msg:
+                k = "one term's intermediates above the per-request cap"
+            else:
+                k = "workspace above the per-request cap"
+            why[k] = why.get(k, 0) + 1
         return {"completed": n, "rejected": len(self.rejected), "wall_s": self.wall_s,
                 "evals_per_s": n / self.wall_s if self.wall_s else 0.0,
-                "p50_ms": float(np.percentile(lat, 50) * 1e3) if n else None,
-                "p99_ms": float(np.percentile(lat, 99) * 1e3) if n else None}
+                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                "plan_p50_ms": pct(plan, 50), "plan_p99_ms": pct(plan, 99),
+                "admitted_to_done_p50_ms": pct(dev, 50), "admitted_to_done_p99_ms": pct(dev, 99),
+                "rejected_reasons": why}
 
 
 def run(server: Server, requests, realtime: bool = True, poll_sleep: float = 0.0,
-        progress=None, progress_every_s: float = 10.0) -> ServeReport:
+        progress=None, progress_every_s: float = 10.0, planners: int = 8) -> ServeReport:
     """Submit `requests` (objects with circuit, observable, params,
     want_grad, arrival_s) at their arrival times (realtime) or all at once,
-    and step the engine until every accepted request finished.  If given,
-    `progress(elapsed_s, n_done, n_rejected, n_pending)` is called about
-    every `progress_every_s` seconds."""
+    and step the engine until every accepted request finished.  Each
+    submission (which plans the request on the host, or finds its plan in
+    the engine's cache) runs on one of `planners` threads, so that host
+    planning of one request overlaps others' planning and the device work.
+    If given, `progress(elapsed_s, n_done, n_rejected, n_pending)` is called
+    about every `progress_every_s` seconds."""
+    from concurrent.futures import ThreadPoolExecutor
     rep = ServeReport()
     ids: Dict[int, int] = {}
     lock = threading.Lock()
     done_submitting = threading.Event()
     errors = []
 
+    def submit_one(i, rq):
+        try:
+            rid = server.submit(rq.circuit, rq.observable, rq.params, rq.want_grad)
+            with lock:
+                ids[rid] = i
+        except L.TcxError as e:
+            if e.status == L.TC_ERR_TOO_LARGE:
+                with lock:
+                    rep.rejected.append(i)
+                    rep.reasons[i] = str(e)
+            else:
+                errors.append(e)
+        except Exception as e:  # surfaced in the engine thread
+            errors.append(e)
+
     def submitter():
         t0 = time.perf_counter()
         try:
-            for i, rq in enumerate(requests):
-                if realtime:
-                    dt = rq.arrival_s - (time.perf_counter() - t0)
-                    if dt > 0:
-                        time.sleep(dt)
-                try:
-                    rid = server.submit(rq.circuit, rq.observable, rq.params, rq.want_grad)
-                    with lock:
-                        ids[rid] = i
-                except L.TcxError as e:
-                    if e.status == L.TC_ERR_TOO_LARGE:
-                        with lock:
-                            rep.rejected.append(i)
-                    else:
-                        raise
+            with ThreadPoolExecutor(max_workers=max(1, planners)) as pool:
+                for i, rq in enumerate(requests):
+                    if realtime:
+                        dt = rq.arrival_s - (time.perf_counter() - t0)
+                        if dt > 0:
+                            time.sleep(dt)
+                    pool.submit(submit_one, i, rq)
         except Exception as e:  # surfaced in the engine thread
             errors.append(e)
         finally:

@@ -319,6 +319,33 @@ def test_wide_tiles_full_size_deep_grid():
     assert rel_err(c, a, floor) < TOL_BF16X3
 
 
+# ------------------------------------------------------------ term groups
+
+@pytest.mark.parametrize("rows,cols,depth,grad,budget_mb", [
+    (4, 5, 5, False, 512), (4, 5, 5, True, 4096), (3, 6, 6, True, 4096)])
+def test_term_groups_match_oracle(rows, cols, depth, grad, budget_mb):
+    """Plans whose terms run in groups under a memory budget (each group's
+    forward pass and reverse sweep before the next group's; with the 4x5
+    gradient also checkpointed segments) against the state-vector oracle."""
+    circ = tcgen.grid_ladder(rows, cols, depth)
+    obs = tcgen.tfim_zz_x_grid(rows, cols, 0.8)
+    p = tcgen.draw_angles(21, (circ.n_params,))
+    plan = api.compile(circ, obs, want_grad=grad, n_trials=1, mem_budget_bytes=budget_mb << 20)
+    info = plan.info()
+    assert info.n_term_groups > 1 and info.workspace_bytes <= budget_mb << 20
+    if grad:
+        e, g = plan.contract_grad(device_params(p))
+        e_ref, g_ref = sv.energy_grad(circ, p, obs)
+        assert rel_err(e[0], e_ref, 1.0) < TOL_C64
+        assert_grad(g[0], g_ref, TOL_C64)
+        # the forward sequence alone of the same plan
+        v = plan.contract(device_params(p))[0]
+        assert abs(v.real - e[0]) < 1e-6
+    else:
+        v = plan.contract(device_params(p))[0]
+        assert rel_err(v, sv.energy(circ, p, obs), 1.0) < TOL_C64
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_all_gate_kinds_random_circuits():

@@ -105,7 +105,20 @@ def test_checkpointing_shrinks_the_workspace_under_a_budget():
     assert forced.flops == full.flops
     budget = (full.workspace_bytes + forced.workspace_bytes) // 2
     auto = api.Plan(net, path, batch=256, want_grad=True, mem_budget_bytes=budget).info()
-    assert auto.checkpoint_every >= 2 and auto.workspace_bytes <= budget
+    # 39 terms: the planner first runs them in groups (no recomputation)
+    assert auto.n_term_groups > 1 and auto.checkpoint_every == 0
+    assert auto.workspace_bytes <= budget and auto.grad_flops == full.grad_flops
+    # one term: only checkpointed segments can shrink the workspace
+    one = tcgen.Observable("pauli_sum", structures=obs.structures[:1], weights=obs.weights[:1])
+    net1 = api.Network(circ, one)
+    path1 = api.Path(net1, n_trials=8, seed=1)
+    full1 = api.Plan(net1, path1, batch=256, want_grad=True, checkpoint_every=-1).info()
+    forced1 = api.Plan(net1, path1, batch=256, want_grad=True, checkpoint_every=3).info()
+    assert forced1.workspace_bytes < full1.workspace_bytes
+    budget1 = (full1.workspace_bytes + forced1.workspace_bytes) // 2
+    auto1 = api.Plan(net1, path1, batch=256, want_grad=True, mem_budget_bytes=budget1).info()
+    assert auto1.checkpoint_every >= 2 and auto1.n_term_groups == 1
+    assert auto1.workspace_bytes <= budget1
     with pytest.raises(L.TcxError) as e:
         api.Plan(net, path, batch=256, want_grad=True, checkpoint_every=1)
     assert e.value.status == L.TC_ERR_INVALID_ARG

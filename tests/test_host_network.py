@@ -14,6 +14,7 @@ import pytest
 import tcgen
 from oracle import gates as G
 from oracle import statevector as sv
+from paper_2205_10091_amd import _lib as L
 from paper_2205_10091_amd import api
 
 
@@ -169,3 +170,34 @@ def test_path_stats_are_recomputed_independently():
     assert math.isclose(st.flops, fl) and math.isclose(st.write, wr)
     assert st.log2_size == mx
     assert len(used) == 2 * len(lv["rank"]) - 2
+
+
+@pytest.mark.parametrize("rows,cols,depth,grad,budget_mb", [
+    (4, 5, 5, False, 512), (4, 5, 5, True, 4096), (3, 6, 6, True, 4096)])
+def test_term_groups_fit_the_memory_budget(rows, cols, depth, grad, budget_mb):
+    """With every term's intermediates live at once these plans need 1.3 to
+    137 GB; under the budget the planner runs the terms in groups (and with
+    a gradient, if needed, checkpointed segments) so that the whole
+    workspace fits.  Host only: no device memory is touched."""
+    circ = tcgen.grid_ladder(rows, cols, depth)
+    obs = tcgen.tfim_zz_x_grid(rows, cols, 1.0)
+    free = api.compile(circ, obs, want_grad=grad, bind=False, n_trials=1)
+    assert free.info().n_term_groups == 1
+    budget = budget_mb << 20
+    assert free.info().workspace_bytes > budget
+    plan = api.compile(circ, obs, want_grad=grad, bind=False, n_trials=1, mem_budget_bytes=budget)
+    info = plan.info()
+    assert info.n_term_groups > 1
+    assert info.workspace_bytes <= budget
+    # the same contraction work (recomputation aside)
+    assert info.flops == free.info().flops
+    assert info.n_nodes == free.info().n_nodes
+
+
+def test_term_groups_reject_what_one_term_cannot_fit():
+    circ = tcgen.grid_ladder(4, 5, 5)
+    obs = tcgen.tfim_zz_x_grid(4, 5, 1.0)
+    with pytest.raises(L.TcxError) as e:
+        api.compile(circ, obs, want_grad=True, bind=False, n_trials=1, mem_budget_bytes=256 << 20)
+    assert e.value.status == L.TC_ERR_TOO_LARGE
+    assert "one term at a time" in str(e.value)
