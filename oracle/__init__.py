@@ -14,6 +14,8 @@ Parts (each module cites the passage of the paper it follows):
                    central finite differences;
 * ``brute``        O3: the full 2^n x 2^n unitary, n <= 8;
 * ``tn``           O2: an einsum-style pairwise tensor-network contraction
-                   with its own network builder and sweep orders.
+                   with its own network builder and sweep orders;
+* ``mpo``          operators given as matrix product operators: the dense
+                   matrix and the application to a state vector.
 """
-from . import gates, statevector, brute, tn  # noqa: F401
+from . import gates, statevector, brute, tn, mpo  # noqa: F401

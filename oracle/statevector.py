@@ -8,6 +8,8 @@ Follows the paper's definitions directly:
 * section "Pauli string expectation / Pauli structures and weights" and the
   Hamiltonian written as a weighted sum of Pauli strings in the introduction:
   E = sum_j alpha_j <psi|P_j|psi>, summed here in float64 in term order;
+* section "Expectations of Hamiltonians via operator_expectation": an
+  operator given as an MPO is applied to the state by ``oracle.mpo``;
 * section "Gradients, optimization and variational algorithms": dE/dtheta,
   computed here with the adjoint method (Jones & Gacon, arXiv:2009.02823):
   with psi_g = U_g psi_{g-1} and lambda_g = (U_G ... U_{g+1})^dagger H psi_G,
@@ -22,6 +24,7 @@ import math
 import numpy as np
 
 from . import gates as G
+from . import mpo
 
 
 def zero_state(n: int) -> np.ndarray:
@@ -79,7 +82,10 @@ def term_values(circ, params, obs) -> np.ndarray:
 
 
 def energy(circ, params, obs) -> complex:
-    """sum_j alpha_j <P_j>, accumulated in float64 in term order."""
+    """sum_j alpha_j <P_j>, accumulated in float64 in term order; for an
+    operator given as an MPO, <psi|M|psi>."""
+    if obs.kind == "mpo":
+        return mpo.expectation(run(circ, params), obs.mpo)
     vals = term_values(circ, params, obs)
     re = 0.0
     im = 0.0
@@ -90,6 +96,8 @@ def energy(circ, params, obs) -> complex:
 
 
 def apply_hamiltonian(psi: np.ndarray, obs) -> np.ndarray:
+    if obs.kind == "mpo":
+        return mpo.apply(psi, obs.mpo)
     out = np.zeros_like(psi)
     for a, s in zip(obs.weights, obs.structures):
         out = out + float(a) * apply_pauli(psi, s)

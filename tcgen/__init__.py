@@ -83,11 +83,14 @@ class Circuit:
 
 @dataclass
 class Observable:
-    """Either an amplitude <bits|U|0...0> or a weighted Pauli sum."""
-    kind: str                          # "amplitude" or "pauli_sum"
+    """An amplitude <bits|U|0...0>, a weighted Pauli sum, or an operator
+    given as a matrix product operator (site tensors of shape
+    (D_left, D_right, 2, 2): bond in, bond out, row index, column index)."""
+    kind: str                          # "amplitude", "pauli_sum" or "mpo"
     bits: Optional[Tuple[int, ...]] = None
     structures: Optional[np.ndarray] = None   # (n_terms, n_qubits) uint8
     weights: Optional[np.ndarray] = None      # (n_terms,) float64
+    mpo: Optional[List[np.ndarray]] = None    # n site tensors, complex128
 
 
 def draw_angles(seed: int, shape, high: float = TWO_PI) -> np.ndarray:
@@ -142,6 +145,26 @@ def tfim_zz_x(n: int, g: float = 1.0) -> Observable:
         s[n - 1 + i, i] = 1
         w[n - 1 + i] = g
     return Observable("pauli_sum", structures=s, weights=w)
+
+
+def tfim_mpo(n: int, g: float = 1.0, j: float = 1.0) -> Observable:
+    """The open-chain TFIM operator j sum_i Z_i Z_{i+1} + g sum_i X_i as a
+    matrix product operator of bond dimension 3 (the input the section
+    "Expectations of Hamiltonians via operator_expectation" feeds to
+    operator_expectation; the oracle checks it against the Pauli sum).  Bond
+    values: 2 = no term placed yet, 1 = the first Z of a bond placed,
+    0 = a term completed; site k maps left value l to right value r with
+    2->2: I, 2->1: j Z, 1->0: Z, 2->0: g X, 0->0: I.  The first site starts
+    from 2, the last ends in 0."""
+    eye = np.eye(2, dtype=np.complex128)
+    zz = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+    xx = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    w = np.zeros((3, 3, 2, 2), dtype=np.complex128)
+    w[2, 2], w[2, 1], w[1, 0], w[2, 0], w[0, 0] = eye, j * zz, zz, g * xx, eye
+    if n == 1:
+        return Observable("mpo", mpo=[(g * xx)[None, None]])
+    sites = [w[2:3, :, :, :].copy()] + [w.copy() for _ in range(n - 2)] + [w[:, 0:1, :, :].copy()]
+    return Observable("mpo", mpo=sites)
 
 
 def tfim_zz_x_grid(rows: int, cols: int, g: float = 1.0) -> Observable:
