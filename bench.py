@@ -217,6 +217,47 @@ def serve_workload(args, out):
                 "serving": res})
 
 
+def mpo_leg(trials, steps=20):
+    """TFIM energy + gradient with the operator as one MPO network (bond 3)
+    against the same operator as a sum of light-coned Pauli-term networks,
+    both planned under the time score: the 20-qubit chain at depth 6 (39
+    terms) and 10, and a 600-qubit chain at depth 2 (1199 terms)."""
+    import torch
+    import tcgen
+    from oracle import statevector as sv
+    from paper_2205_10091_amd import api
+    res = {}
+    for n, layers, label in ((20, 6, "vqe_chain_n20_L6"), (20, 10, "chain_n20_L10"),
+                             (600, 2, "chain_n600_L2")):
+        circ = tcgen.chain_ladder(n, layers)
+        p = tcgen.draw_angles(2, (circ.n_params,))
+        params = torch.from_numpy(p).to("cuda:0")
+        r = {}
+        vals = {}
+        for form, obs in (("mpo", tcgen.tfim_mpo(n, 1.0)), ("pauli_sum", tcgen.tfim_zz_x(n, 1.0))):
+            t0 = time.perf_counter()
+            plan = api.compile(circ, obs, want_grad=True, n_trials=trials, seed=1, score=4)
+            plan_s = time.perf_counter() - t0
+            info = plan.info()
+            e_dev = torch.empty(1, dtype=torch.float64, device="cuda:0")
+            g_dev = torch.empty(info.n_params, dtype=torch.float64, device="cuda:0")
+            dt, _ = timed(lambda: plan.contract_grad_device(params, e_dev, g_dev), steps, 2)
+            vals[form] = (e_dev.item(), g_dev.cpu().numpy())
+            r[form] = {"evals_per_s": steps / dt, "ms_per_step": dt / steps * 1e3,
+                       "networks": info.n_terms, "flops": info.flops + info.grad_flops,
+                       "launches_per_step": info.n_launches + info.n_grad_launches,
+                       "workspace_bytes": int(info.workspace_bytes), "plan_seconds": plan_s}
+            del plan
+        r["mpo_vs_pauli_sum"] = r["mpo"]["evals_per_s"] / r["pauli_sum"]["evals_per_s"]
+        r["energy_diff_mpo_vs_pauli"] = abs(vals["mpo"][0] - vals["pauli_sum"][0])
+        if n <= 20:
+            e_ref, g_ref = sv.energy_grad(circ, p, tcgen.tfim_mpo(n, 1.0))
+            r["mpo"]["rel_err_energy"] = abs(vals["mpo"][0] - e_ref) / max(abs(e_ref), 1.0)
+            r["mpo"]["max_abs_err_grad"] = float(np.max(np.abs(vals["mpo"][1] - g_ref)))
+        res[label] = r
+    return res
+
+
 def golden_amplitude(rows, cols, depth):
     """The stored oracle amplitude of a seeded fSim grid (two independent
     oracle methods, tests/golden/), its methods' seconds, or None."""
@@ -288,7 +329,7 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="vqe",
-                    choices=["vqe", "batched", "forward", "grid", "wide", "serve"])
+                    choices=["vqe", "batched", "forward", "grid", "wide", "serve", "mpo"])
     ap.add_argument("--trials", type=int, default=0,
                     help="greedy path trials (default: 1024 for the chain workloads, whose "
                          "launches are latency bound and gain from the fewest flops; 32 for "
@@ -384,6 +425,17 @@ def main():
         out["rel_err_zz"] = abs(z - sv.energy(circ, p, zz))
     elif args.workload == "serve":
         pass  # handled below
+    elif args.workload == "mpo":
+        # the TFIM energy + gradient as one MPO network vs the Pauli sum;
+        # value = MPO evaluations/s on the 20-qubit chain at depth 10
+        res = mpo_leg(chain_trials if args.trials else 16, steps=min(args.steps, 20))
+        r = res["chain_n20_L10"]["mpo"]
+        out.update({"metric": "circuit evals/s (TFIM energy + gradient, operator as one MPO "
+                              "network, 20-qubit chain at depth 10)",
+                    "value": r["evals_per_s"], "unit": "evals/s", "ms_per_step": r["ms_per_step"],
+                    "dtype": "c64 (fp32) + fp64 sums",
+                    "config": {"workload": "chain_n20_L10_tfim_mpo_energy_grad", "batch": 1},
+                    "mpo": res, "roofline": None})
     elif args.workload == "wide":
         # 4x7 grid at depth 16 (oracle-pinned; 1.8e13 flops) or, with
         # --wide-grid 6x6x12, the 6x6 grid at depth 12 (no oracle value)
@@ -475,6 +527,8 @@ def main():
         out["grid_amplitude"] = grid_leg(6, 6, 8, grid_trials, 50, 5, "grid")
         print("[bench] grid 4x7 depth 16 (wide nodes)", file=sys.stderr, flush=True)
         out["wide_nodes"] = grid_leg(4, 7, 16, grid_trials, 5, 1, "wide")
+        print("[bench] MPO vs Pauli-sum energy", file=sys.stderr, flush=True)
+        out["mpo"] = mpo_leg(16)
         # the first 20 requests of the serving stream (the full 60-request
         # run at three rates is --workload serve, about ten minutes)
         print("[bench] serving mix", file=sys.stderr, flush=True)

@@ -104,8 +104,19 @@ typedef struct {
  * PAULI_SUM: sum_j weights[j] <psi|P_j|psi> with structure vectors
  * structures[j*n_qubits + q] in {0=I,1=X,2=Y,3=Z} (section "Pauli structures
  * and weights").  The weighted sum is reduced in FP64 in a fixed order.
+ * MPO: <psi|M|psi> for an operator given as a matrix product operator
+ * (sections "Expectations of Hamiltonians via operator_expectation", MPO
+ * input, and "QuOperator as the operator to be measured"):
+ *   M[i_1..i_n; j_1..j_n] = sum over bonds of prod_k T_k[b_{k-1}, b_k, i_k, j_k]
+ * contracted as ONE network (ket, the n site tensors, conjugated ket)
+ * instead of one network per Pauli term.  Site k is a D_{k-1} x D_k x 2 x 2
+ * array (left bond, right bond, row = out index, column = in index) of
+ * (re, im) doubles, row-major; the sites are concatenated in `mpo`;
+ * mpo_bonds[k-1] = D_k for the n-1 inner bonds, each in 1..8 (D_0 = D_n = 1).
+ * A bond of dimension D becomes ceil(log2 D) legs of dimension 2, the
+ * padded entries zero.  No light cone applies (M acts on every qubit).
  */
-typedef enum { TC_OBS_AMPLITUDE = 0, TC_OBS_PAULI_SUM = 1 } tc_obs_kind;
+typedef enum { TC_OBS_AMPLITUDE = 0, TC_OBS_PAULI_SUM = 1, TC_OBS_MPO = 2 } tc_obs_kind;
 
 typedef struct {
   int32_t kind;               /* tc_obs_kind                               */
@@ -114,6 +125,8 @@ typedef struct {
   int32_t n_terms;            /* PAULI_SUM: number of terms (>= 1)         */
   const uint8_t* structures;  /* PAULI_SUM: n_terms * n_qubits             */
   const double* weights;      /* PAULI_SUM: n_terms                        */
+  const int32_t* mpo_bonds;   /* MPO: n_qubits - 1 inner bond dimensions   */
+  const double* mpo;          /* MPO: the site tensors (copied at build)   */
 } tc_observable;
 
 /* ------------------------------------------------------------------ network
@@ -165,16 +178,18 @@ typedef struct {
 tc_status tc_network_info_get(const tc_network* net, tc_network_info* out);
 
 /* Leaf tensors of one term, for inspection and host-side checks.  For leaf
- * i: kind[i] (0 gate, 1 |0> vector, 2 <bit| vector, 3 Pauli matrix),
- * gate[i] (gate index, or the bit / Pauli value for kinds 1-3), part[i]
+ * i: kind[i] (0 gate, 1 |0> vector, 2 <bit| vector, 3 Pauli matrix, 4 MPO
+ * site), gate[i] (gate index, the bit / Pauli value for kinds 1-3, the site
+ * for kind 4), part[i]
  * (0 whole gate, 1 first split factor, 2 second split factor), conj[i] (1
  * for bra copies), rank[i] and legs[4*i + r] (leg labels, most significant
  * first).  Element e of a leaf is the entry whose r-th leg has value
  * (e >> (rank-1-r)) & 1.  Whole gates have legs (out..., in...); split
  * factors have legs (bond, out, in) and equal P_k (first) and c_k P_k
  * (second) with P_0 = I, P_1 = the gate's Pauli (Z for CZ, X for CNOT's
- * target) and c_k from the gate.  Arrays have max_leaves entries (legs:
- * 4*max_leaves); *n_leaves receives the count. */
+ * target) and c_k from the gate; MPO sites have legs (left bond bits...,
+ * right bond bits..., out, in).  Arrays have max_leaves entries (legs:
+ * 8*max_leaves, unused entries -1); *n_leaves receives the count. */
 tc_status tc_network_term_leaves(const tc_network* net, int32_t term,
                                  int32_t* n_leaves, int32_t* kind,
                                  int32_t* gate, int32_t* part, int32_t* conj,
@@ -190,13 +205,19 @@ tc_status tc_network_term_leaves(const tc_network* net, int32_t term,
  * score is kept.  Deterministic for a fixed seed.
  *
  * score: 0 flops, 1 write, 2 size, 3 combo = flops + 64 * write (the
- * default combination named in the contractor table of that section).
+ * default combination named in the contractor table of that section),
+ * 4 time = an execution-time estimate on this executor: flops at
+ * 10 TFLOP/s, written elements at 2 TB/s and 6 us per tree level (levels
+ * are dependent launches).  Beside the greedy trials two candidates are
+ * scored: a sweep in time order (ket gates, observable, conjugated gates)
+ * and, for networks whose leaves sit on wires, per-wire column tensors
+ * merged left to right or as a balanced binary tree over wires.
  * flops count 8 real operations per complex multiply-add.
  */
 typedef struct tc_path tc_path;
 
 typedef enum { TC_SCORE_FLOPS = 0, TC_SCORE_WRITE = 1, TC_SCORE_SIZE = 2,
-               TC_SCORE_COMBO = 3 } tc_score;
+               TC_SCORE_COMBO = 3, TC_SCORE_TIME = 4 } tc_score;
 
 typedef struct {
   uint64_t seed;

@@ -39,7 +39,8 @@ class Circuit(C.Structure):
 class Observable(C.Structure):
     _fields_ = [("kind", C.c_int32), ("bits", C.POINTER(C.c_uint8)),
                 ("n_terms", C.c_int32), ("structures", C.POINTER(C.c_uint8)),
-                ("weights", C.POINTER(C.c_double))]
+                ("weights", C.POINTER(C.c_double)), ("mpo_bonds", C.POINTER(C.c_int32)),
+                ("mpo", C.POINTER(C.c_double))]
 
 
 class BuildOpts(C.Structure):

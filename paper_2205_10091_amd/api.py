@@ -54,7 +54,15 @@ class _CObservable:
             bits = obs.bits if obs.bits is not None else (0,) * n_qubits
             b = (C.c_uint8 * n_qubits)(*bits)
             self.keep.append(b)
-            self.o = L.Observable(0, C.cast(b, C.POINTER(C.c_uint8)), 0, None, None)
+            self.o = L.Observable(0, C.cast(b, C.POINTER(C.c_uint8)), 0, None, None, None, None)
+        elif obs.kind == "mpo":
+            ts = [np.asarray(t, np.complex128) for t in obs.mpo]
+            bonds = np.ascontiguousarray([t.shape[1] for t in ts[:-1]], dtype=np.int32)
+            flat = np.ascontiguousarray(
+                np.concatenate([t.reshape(-1) for t in ts]).view(np.float64))
+            self.keep += [bonds, flat]
+            self.o = L.Observable(2, None, 0, None, None, bonds.ctypes.data_as(L.I32P),
+                                  flat.ctypes.data_as(L.F64P))
         else:
             s = np.ascontiguousarray(obs.structures, dtype=np.uint8)
             w = np.ascontiguousarray(obs.weights, dtype=np.float64)
@@ -62,7 +70,7 @@ class _CObservable:
             self.o = L.Observable(
                 1, None, int(s.shape[0]),
                 s.ctypes.data_as(C.POINTER(C.c_uint8)),
-                w.ctypes.data_as(C.POINTER(C.c_double)))
+                w.ctypes.data_as(C.POINTER(C.c_double)), None, None)
 
 
 class Network:
@@ -95,7 +103,7 @@ class Network:
         info = self.info()
         m = max(info.max_leaves, 1)
         arrs = [np.zeros(m, np.int32) for _ in range(5)]
-        legs = np.zeros(4 * m, np.int32)
+        legs = np.zeros(8 * m, np.int32)
         n = C.c_int32()
         ptr = lambda a: a.ctypes.data_as(L.I32P)  # noqa: E731
         L.check(lib().tc_network_term_leaves(self.h, term, C.byref(n),
@@ -103,7 +111,7 @@ class Network:
         k = n.value
         kind, gate, part, conj, rank = (a[:k] for a in arrs)
         return dict(kind=kind, gate=gate, part=part, conj=conj, rank=rank,
-                    legs=legs[:4 * k].reshape(k, 4))
+                    legs=legs[:8 * k].reshape(k, 8))
 
 
 class Path:
@@ -260,10 +268,12 @@ class Plan:
 def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
             lightcone=True, absorb_1q=True, seed=0, n_trials=8,
             mem_budget_bytes=0, device=0, bind=True, gemm_min_k=0, stream=None,
-            checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0) -> Plan:
-    """Network + greedy path + plan (+ bind with a torch workspace)."""
+            checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0,
+            score=3) -> Plan:
+    """Network + greedy path + plan (+ bind with a torch workspace).
+    score: the path score of tc_greedy_path (3 combo, 4 time estimate)."""
     net = Network(circ, obs, split_2q, lightcone, absorb_1q)
-    path = Path(net, seed=seed, n_trials=n_trials)
+    path = Path(net, seed=seed, n_trials=n_trials, score=score)
     torch_stream = None
     if stream is None and bind:
         # a dedicated torch stream (default priority): torch work orders

@@ -109,7 +109,8 @@ tc_status tc_network_term_leaves(const tc_network* net, int32_t term,
     if (conj) conj[i] = lf.conj;
     if (rank) rank[i] = lf.rank;
     if (legs)
-      for (int r = 0; r < 4; ++r) legs[4 * i + r] = lf.legs[r];
+      for (int r = 0; r < tcx::MAX_LEAF_RANK; ++r)
+        legs[tcx::MAX_LEAF_RANK * i + r] = lf.legs[r];
   }
   return TC_OK;
   TC_GUARD_END
@@ -122,7 +123,7 @@ tc_status tc_greedy_path(const tc_network* net, const tc_path_opts* opts,
   tc_path_opts o{0, 1, TC_SCORE_COMBO, 0.1};
   if (opts) o = *opts;
   if (o.n_trials < 1) tcx::fail(TC_ERR_INVALID_ARG, "n_trials must be >= 1");
-  if (o.score < 0 || o.score > 3) tcx::fail(TC_ERR_INVALID_ARG, "unknown score");
+  if (o.score < 0 || o.score > 4) tcx::fail(TC_ERR_INVALID_ARG, "unknown score");
   auto* p = new tc_path;
   p->path = tcx::greedy_path(net->net, o);
   p->terms = net->net.terms;

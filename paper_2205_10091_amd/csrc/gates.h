@@ -226,6 +226,7 @@ __device__ __forceinline__ c32 leaf_entry(const DevLeaf& L, int e, float t0, flo
     case DLEAF_KET0: v = cx(e == 0 ? 1.f : 0.f, 0.f); break;
     case DLEAF_BRA: v = cx(e == L.value ? 1.f : 0.f, 0.f); break;
     case DLEAF_PAULI: v = pauli_entry(L.value, e >> 1, e & 1); break;
+    case DLEAF_MPO: v = cx(ftab[L.mat + 2 * e], ftab[L.mat + 2 * e + 1]); break;
     default:
       if (L.part == 0) {
         if (L.rank == 2)

@@ -35,15 +35,25 @@ bool gate_splittable(int kind);
 bool gate_diagonal(int kind);   // diagonal in the computational basis
 
 // ---------------------------------------------------------------- network
-enum LeafKind : int32_t { LEAF_GATE = 0, LEAF_KET0 = 1, LEAF_BRA = 2, LEAF_PAULI = 3 };
+enum LeafKind : int32_t { LEAF_GATE = 0, LEAF_KET0 = 1, LEAF_BRA = 2, LEAF_PAULI = 3,
+                          LEAF_MPO = 4 };
+constexpr int MAX_LEAF_RANK = 8;
 
 struct Leaf {
   int32_t kind = LEAF_GATE;
-  int32_t gate = 0;   // gate index, or bit / Pauli value for other kinds
+  int32_t gate = 0;   // gate index, bit / Pauli value, or MPO site
   int32_t part = 0;   // 0 whole, 1 / 2 split factors
   int32_t conj = 0;
   int32_t rank = 0;
-  int32_t legs[4] = {-1, -1, -1, -1};
+  int32_t legs[MAX_LEAF_RANK] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int32_t qubit = 0;  // the wire it sits on (a whole two-qubit gate: the later one)
+};
+
+// An MPO site as a leaf tensor: legs (left bond bits, right bond bits, out,
+// in), entries (re, im) with the bonds padded to powers of two.
+struct MpoSite {
+  int32_t lbits = 0, rbits = 0;
+  std::vector<double> entries;   // 2 * 2^(lbits + rbits + 2)
 };
 
 struct Term {
@@ -59,6 +69,7 @@ struct Network {
   tc_build_opts opts{1, 1, 1};
   std::vector<GateRec> gates;
   std::vector<Term> terms;
+  std::vector<MpoSite> mpo;   // MPO observable: one per qubit
   // identifies the circuit + observable structure (for plan caches)
   uint64_t structure_hash = 0;
 };

@@ -11,6 +11,7 @@
 // split here is the exact closed form, no SVD).  Gates outside a Pauli
 // term's backward light cone cancel against their mirror images and are
 // dropped.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -131,12 +132,14 @@ struct TermBuilder {
   explicit TermBuilder(const Network& n) : net(n) {}
   int32_t label() { return next++; }
   void leaf(int32_t kind, int32_t gate, int32_t part, int32_t conj,
-            std::initializer_list<int32_t> legs) {
+            const std::vector<int32_t>& legs, int32_t qubit) {
+    if ((int)legs.size() > MAX_LEAF_RANK) fail(TC_ERR_INVALID_ARG, "internal: leaf rank");
     Leaf lf;
     lf.kind = kind;
     lf.gate = gate;
     lf.part = part;
     lf.conj = conj;
+    lf.qubit = qubit;
     lf.rank = 0;
     for (int32_t l : legs) lf.legs[lf.rank++] = l;
     term.leaves.push_back(lf);
@@ -159,7 +162,7 @@ struct TermBuilder {
     for (int q = 0; q < n; ++q) {
       if (!active[q]) continue;
       cur[q] = (final_labels && last_use[q] < 0) ? (*final_labels)[q] : label();
-      leaf(LEAF_KET0, 0, 0, conj, {cur[q]});
+      leaf(LEAF_KET0, 0, 0, conj, {cur[q]}, q);
     }
     for (size_t gi = 0; gi < net.gates.size(); ++gi) {
       if (!keep[gi]) continue;
@@ -170,14 +173,14 @@ struct TermBuilder {
                      ? (*final_labels)[g.q[k]]
                      : label();
       if (g.nq == 1) {
-        leaf(LEAF_GATE, (int32_t)gi, 0, conj, {out[0], cur[g.q[0]]});
+        leaf(LEAF_GATE, (int32_t)gi, 0, conj, {out[0], cur[g.q[0]]}, g.q[0]);
       } else if (net.opts.split_2q && gate_splittable(g.kind)) {
         int32_t bond = label();
-        leaf(LEAF_GATE, (int32_t)gi, 1, conj, {bond, out[0], cur[g.q[0]]});
-        leaf(LEAF_GATE, (int32_t)gi, 2, conj, {bond, out[1], cur[g.q[1]]});
+        leaf(LEAF_GATE, (int32_t)gi, 1, conj, {bond, out[0], cur[g.q[0]]}, g.q[0]);
+        leaf(LEAF_GATE, (int32_t)gi, 2, conj, {bond, out[1], cur[g.q[1]]}, g.q[1]);
       } else {
         leaf(LEAF_GATE, (int32_t)gi, 0, conj,
-             {out[0], out[1], cur[g.q[0]], cur[g.q[1]]});
+             {out[0], out[1], cur[g.q[0]], cur[g.q[1]]}, std::max(g.q[0], g.q[1]));
       }
       for (int k = 0; k < g.nq; ++k) cur[g.q[k]] = out[k];
     }
@@ -227,7 +230,7 @@ Network build_network(const tc_circuit* c, const tc_observable* o,
     for (int q = 0; q < n; ++q) {
       int32_t b = o->bits ? o->bits[q] : 0;
       if (b != 0 && b != 1) fail(TC_ERR_INVALID_ARG, "bits must be 0 or 1");
-      tb.leaf(LEAF_BRA, b, 0, 0, {fin[q]});
+      tb.leaf(LEAF_BRA, b, 0, 0, {fin[q]}, q);
       h = hash_mix(h, (uint64_t)b);
     }
     tb.term.n_labels = tb.next;
@@ -290,7 +293,7 @@ Network build_network(const tc_circuit* c, const tc_observable* o,
       for (int q = 0; q < n; ++q) {
         if (!active[q] || s[q] == 0) continue;
         int32_t ol = tb.label();
-        tb.leaf(LEAF_PAULI, s[q], 0, 0, {ol, ket_out[q]});
+        tb.leaf(LEAF_PAULI, s[q], 0, 0, {ol, ket_out[q]}, q);
         bra_out[q] = ol;
       }
       tb.ket(active, keep, 1, &bra_out);
@@ -298,6 +301,63 @@ Network build_network(const tc_circuit* c, const tc_observable* o,
       tb.term.weight = w;
       net.terms.push_back(std::move(tb.term));
     }
+  } else if (o->kind == TC_OBS_MPO) {
+    // one network: ket, the MPO sites (out leg to the bra, in leg from the
+    // ket, bond legs between neighbours), conjugated ket
+    if (n > 1 && !o->mpo_bonds) fail(TC_ERR_INVALID_ARG, "mpo_bonds is NULL");
+    if (!o->mpo) fail(TC_ERR_INVALID_ARG, "mpo is NULL");
+    std::vector<int32_t> dim(n + 1, 1);
+    for (int k = 1; k < n; ++k) {
+      dim[k] = o->mpo_bonds[k - 1];
+      if (dim[k] < 1 || dim[k] > 8) fail(TC_ERR_INVALID_ARG, "MPO bond dimensions must be 1..8");
+      h = hash_mix(h, (uint64_t)dim[k]);
+    }
+    auto bits_of = [](int32_t d) {
+      int32_t b = 0;
+      while ((1 << b) < d) ++b;
+      return b;
+    };
+    TermBuilder tb(net);
+    std::vector<int32_t> ket_out = tb.ket(all_active, all_keep, 0, nullptr);
+    std::vector<int32_t> bra_out(n);
+    std::vector<int32_t> left;  // legs of the bond to the left of site k
+    const double* src = o->mpo;
+    net.mpo.resize(n);
+    for (int k = 0; k < n; ++k) {
+      MpoSite& site = net.mpo[k];
+      site.lbits = bits_of(dim[k]);
+      site.rbits = bits_of(dim[k + 1]);
+      std::vector<int32_t> right;
+      for (int b = 0; b < site.rbits; ++b) right.push_back(tb.label());
+      bra_out[k] = tb.label();
+      std::vector<int32_t> legs = left;
+      legs.insert(legs.end(), right.begin(), right.end());
+      legs.push_back(bra_out[k]);
+      legs.push_back(ket_out[k]);
+      const int32_t pr = 1 << site.rbits;
+      site.entries.assign((size_t)2 << (site.lbits + site.rbits + 2), 0.0);
+      for (int32_t l = 0; l < dim[k]; ++l)
+        for (int32_t r = 0; r < dim[k + 1]; ++r)
+          for (int oi = 0; oi < 4; ++oi) {
+            const double re = *src++, im = *src++;
+            if (!std::isfinite(re) || !std::isfinite(im))
+              fail(TC_ERR_INVALID_ARG, "non-finite MPO entry");
+            const size_t e = ((size_t)(l * pr + r) << 2) | (size_t)oi;
+            site.entries[2 * e] = re;
+            site.entries[2 * e + 1] = im;
+            uint64_t b;
+            std::memcpy(&b, &re, 8);
+            h = hash_mix(h, b);
+            std::memcpy(&b, &im, 8);
+            h = hash_mix(h, b);
+          }
+      tb.leaf(LEAF_MPO, k, 0, 0, legs, k);
+      left = right;
+    }
+    tb.ket(all_active, all_keep, 1, &bra_out);
+    tb.term.n_labels = tb.next;
+    tb.term.weight = 1.0;
+    net.terms.push_back(std::move(tb.term));
   } else {
     fail(TC_ERR_INVALID_ARG, "unknown observable kind");
   }

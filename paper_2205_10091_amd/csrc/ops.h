@@ -77,7 +77,7 @@ struct DevTerm {
 };
 
 enum : int32_t {
-  DLEAF_GATE = 0, DLEAF_KET0 = 1, DLEAF_BRA = 2, DLEAF_PAULI = 3
+  DLEAF_GATE = 0, DLEAF_KET0 = 1, DLEAF_BRA = 2, DLEAF_PAULI = 3, DLEAF_MPO = 4
 };
 
 struct DevLeaf {
@@ -92,7 +92,8 @@ struct DevLeaf {
   int32_t param[2];        // parameter slots, -1 = fixed
   float fixed[2];
   uint32_t rows;           // batch rows written (1 = shared)
-  uint32_t mat;            // offset of 32 floats (U1/U2) in the float table
+  uint32_t mat;            // offset in the float table: 32 floats (U1/U2), or
+                           // 2^(rank+1) (the entries of an MPO site)
 };
 
 // d(term root)/d(angle) for one leaf use: sum_e adj[e] * dleaf[e]/dangle

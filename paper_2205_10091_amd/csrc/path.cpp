@@ -210,6 +210,10 @@ double score_of(const TreeStats& s, int score) {
     case TC_SCORE_FLOPS: return s.flops;
     case TC_SCORE_WRITE: return s.write;
     case TC_SCORE_SIZE: return s.size * 1e6 + s.flops * 1e-12;
+    case TC_SCORE_TIME:
+      // seconds: flops at 10 TFLOP/s, written elements (8 B) at 2 TB/s,
+      // and one dependent launch of about 6 us per tree level
+      return s.flops * 1e-13 + s.write * 8.0 / 2e12 + s.depth * 6e-6;
     default: return s.flops / 8.0 + 64.0 * s.write;
   }
 }
@@ -320,7 +324,7 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
     for (int trial = 1; trial < trials; ++trial)
       if (score[trial] < score[best_trial]) best_trial = trial;
     TermPath best = std::move(found[best_trial]);
-    const double best_score = score[best_trial];
+    double best_score = score[best_trial];
     // One more candidate: the time-ordered sweep of a state-vector
     // simulation, kept when it scores better.  The unconjugated leaves
     // (boundary vectors, gates in circuit order, Pauli matrices or output
@@ -344,7 +348,89 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
         cur = tp.n_leaves + (int32_t)tp.pairs.size() - 1;
       }
       const double sc = score_of(tree_stats(term, tp), opts.score);
-      if (sc < best_score) best = std::move(tp);
+      if (sc < best_score) {
+        best = std::move(tp);
+        best_score = sc;
+      }
+    }
+    // Two spatial candidates, wire by wire (on each wire: ket gates in time
+    // order, the observable's leaves, the conjugated gates from the last
+    // back): (a) every leaf absorbed in that order into one growing tensor,
+    // which holds one boundary of open bonds; (b) each wire's leaves folded
+    // into a column tensor, all wires independently, then the columns
+    // merged as a balanced binary tree over wire order, whose blocks hold
+    // two boundaries but whose depth is log2 of the wire count (for wide
+    // shallow circuits: far fewer dependent launches).
+    // They are scored under the time score, or when the best path so far
+    // has an intermediate above 2^28 elements (other plans stay as found).
+    if (term.leaves.size() > 2 &&
+        (opts.score == TC_SCORE_TIME || tree_stats(term, best).size > std::ldexp(1.0, 28))) {
+      const int32_t nl = (int32_t)term.leaves.size();
+      int32_t max_q = 0;
+      for (const Leaf& lf : term.leaves) max_q = std::max(max_q, lf.qubit);
+      std::vector<std::vector<int32_t>> col(max_q + 1);
+      std::vector<int32_t> ord(nl);
+      for (int32_t i = 0; i < nl; ++i) ord[i] = i;
+      auto side = [&](const Leaf& lf) {
+        if (lf.conj) return 2;
+        return (lf.kind == LEAF_KET0 || lf.kind == LEAF_GATE) ? 0 : 1;
+      };
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+        const Leaf &a = term.leaves[x], &b = term.leaves[y];
+        const int sa = side(a), sb = side(b);
+        if (sa != sb) return sa < sb;
+        return sa == 2 ? x > y : x < y;  // conjugated gates from the last back
+      });
+      for (int32_t i : ord) col[term.leaves[i].qubit].push_back(i);
+      TermPath base;
+      base.n_leaves = nl;
+      std::vector<int32_t> heads;  // one tensor per non-empty wire, in wire order
+      for (const auto& c : col) {
+        if (c.empty()) continue;
+        int32_t cur = c[0];
+        for (size_t k = 1; k < c.size(); ++k) {
+          base.pairs.push_back({cur, c[k]});
+          cur = nl + (int32_t)base.pairs.size() - 1;
+        }
+        heads.push_back(cur);
+      }
+      for (int variant = 0; variant < 2; ++variant) {
+        TermPath tp;
+        std::vector<int32_t> level = heads;
+        if (variant == 0) {
+          // every leaf straight into one growing tensor, wire by wire
+          tp.n_leaves = nl;
+          int32_t cur = -1;
+          for (const auto& c : col)
+            for (int32_t i : c) {
+              if (cur < 0) {
+                cur = i;
+                continue;
+              }
+              tp.pairs.push_back({cur, i});
+              cur = nl + (int32_t)tp.pairs.size() - 1;
+            }
+        } else {
+          tp = base;
+          while (level.size() > 1) {
+            std::vector<int32_t> next;
+            for (size_t k = 0; k + 1 < level.size(); k += 2) {
+              tp.pairs.push_back({level[k], level[k + 1]});
+              next.push_back(nl + (int32_t)tp.pairs.size() - 1);
+            }
+            if (level.size() % 2) next.push_back(level.back());
+            level = std::move(next);
+          }
+        }
+        const TreeStats st = tree_stats(term, tp);
+        const double sc = score_of(st, opts.score);
+        // (a candidate whose largest intermediate the executor cannot hold
+        // is never kept)
+        if (st.size <= std::ldexp(1.0, 31) && sc < best_score) {
+          best = std::move(tp);
+          best_score = sc;
+        }
+      }
     }
     path.terms.push_back(std::move(best));
   }

@@ -1200,6 +1200,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           d.mat = (uint32_t)plan.ftab.size();
           for (int k = 0; k < 32; ++k) plan.ftab.push_back((float)g.mat[k]);
         }
+      } else if (lf.kind == LEAF_MPO) {
+        // a constant tensor: its (padded) entries in the float table
+        const MpoSite& site = net.mpo.at((size_t)lf.gate);
+        if (site.entries.size() != (size_t)2 << lf.rank)
+          fail(TC_ERR_INVALID_ARG, "internal: MPO site size");
+        d.mat = (uint32_t)plan.ftab.size();
+        for (double x : site.entries) plan.ftab.push_back((float)x);
       } else {
         d.value = lf.gate;
       }
@@ -1298,10 +1305,16 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         fail(TC_ERR_INVALID_ARG, "internal: contraction op out of the arena");
       if (op.c < seed_elems) fail(TC_ERR_INVALID_ARG, "internal: op writes over the seeds");
     }
-    for (const DevLeaf& d : plan.leaves)
+    for (const DevLeaf& d : plan.leaves) {
       if (d.out + ((uint64_t)d.rows << d.rank) > AE || d.out < seed_elems ||
-          (d.param[0] >= plan.n_params) || (d.param[1] >= plan.n_params))
+          (d.param[0] >= plan.n_params) || (d.param[1] >= plan.n_params) ||
+          d.rank > MAX_LEAF_RANK)
         fail(TC_ERR_INVALID_ARG, "internal: leaf out of range");
+      const uint64_t nf = d.kind == DLEAF_MPO ? (uint64_t)2 << d.rank
+                          : (d.kind == DLEAF_GATE && (d.gkind == TC_GATE_U1 || d.gkind == TC_GATE_U2)) ? 32 : 0;
+      if (nf && (uint64_t)d.mat + nf > plan.ftab.size())
+        fail(TC_ERR_INVALID_ARG, "internal: leaf table out of range");
+    }
     for (const DevGradUse& u : plan.uses)
       if (u.leaf >= plan.leaves.size() ||
           u.adj + (uint64_t)(B - 1) * u.adj_bs + (1ull << plan.leaves[u.leaf].rank) > AE)

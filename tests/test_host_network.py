@@ -54,11 +54,26 @@ def leaf_tensor(circ, params, kind, gate, part, conj, rank):
     return t.conj() if conj else t
 
 
-def contract_along_path(net, path, circ, params, term):
+def padded_site(t):
+    """An MPO site (Dl, Dr, 2, 2) padded to power-of-two bonds and split
+    into legs of dimension 2: (left bits..., right bits..., out, in)."""
+    dl, dr = t.shape[:2]
+    bl, br = (dl - 1).bit_length(), (dr - 1).bit_length()
+    p = np.zeros((1 << bl, 1 << br, 2, 2), complex)
+    p[:dl, :dr] = t
+    return p.reshape((2,) * (bl + br + 2))
+
+
+def contract_along_path(net, path, circ, params, term, mpo=None):
     lv = net.term_leaves(term)
     tensors = []
     for i in range(len(lv["kind"])):
         r = int(lv["rank"][i])
+        if int(lv["kind"][i]) == 4:
+            t = padded_site(np.asarray(mpo[int(lv["gate"][i])], complex))
+            assert t.ndim == r
+            tensors.append((t, [int(x) for x in lv["legs"][i][:r]]))
+            continue
         t = leaf_tensor(circ, params, int(lv["kind"][i]), int(lv["gate"][i]),
                         int(lv["part"][i]), int(lv["conj"][i]), r)
         tensors.append((t, [int(x) for x in lv["legs"][i][:r]]))
@@ -85,6 +100,47 @@ def test_vqe_chain_terms_through_exported_network(split, lightcone, absorb):
     for j in range(len(want)):
         got = contract_along_path(net, path, circ, params, j)
         assert abs(got - want[j]) < 1e-12, j
+
+
+@pytest.mark.parametrize("split,absorb", [(1, 1), (0, 1), (1, 0)])
+def test_mpo_network_through_exported_leaves(split, absorb):
+    """The one-network form of an MPO observable (section "QuOperator as the
+    operator to be measured"): its exported leaves, contracted in numpy
+    along the library's path, give the oracle's <psi|M|psi>."""
+    n = 7
+    circ = tcgen.chain_ladder(n, 3)
+    params = tcgen.draw_angles(9, (circ.n_params,)).astype(np.float64)
+    obs = tcgen.tfim_mpo(n, 0.8)
+    net = api.Network(circ, obs, split_2q=split, absorb_1q=absorb)
+    assert net.info().n_terms == 1
+    path = api.Path(net, n_trials=3, seed=5)
+    got = contract_along_path(net, path, circ, params, 0, mpo=obs.mpo)
+    assert abs(got - sv.energy(circ, params, obs)) < 1e-12
+    # bonds of several dimensions, complex entries, a non-Hermitian M
+    rng = np.random.default_rng(4)
+    dims = [1, 2, 3, 8, 5, 1, 4, 1]
+    ts = [rng.normal(size=(dims[k], dims[k + 1], 2, 2)) + 1j * rng.normal(size=(dims[k], dims[k + 1], 2, 2))
+          for k in range(n)]
+    m = tcgen.Observable("mpo", mpo=ts)
+    net = api.Network(circ, m, split_2q=split, absorb_1q=absorb)
+    path = api.Path(net, n_trials=2, seed=1)
+    got = contract_along_path(net, path, circ, params, 0, mpo=ts)
+    assert abs(got - sv.energy(circ, params, m)) < 1e-12 * max(1.0, abs(got))
+
+
+def test_mpo_observable_errors():
+    circ = tcgen.chain_ladder(4, 1)
+    ok = tcgen.tfim_mpo(4, 1.0)
+    bad = [t.copy() for t in ok.mpo]
+    bad[1] = np.zeros((3, 9, 2, 2))
+    bad[2] = np.zeros((9, 3, 2, 2))
+    with pytest.raises(L.TcxError) as e:
+        api.Network(circ, tcgen.Observable("mpo", mpo=bad))
+    assert e.value.status == L.TC_ERR_INVALID_ARG
+    nan = [t.copy() for t in ok.mpo]
+    nan[0][0, 0, 0, 0] = np.nan
+    with pytest.raises(L.TcxError):
+        api.Network(circ, tcgen.Observable("mpo", mpo=nan))
 
 
 @pytest.mark.parametrize("seed", range(4))
