@@ -168,3 +168,34 @@ def finite_diff_grad(circ, params, obs, h: float = 1e-3) -> np.ndarray:
         em = energy(circ, p, obs).real
         grad[s] = (ep - em) / (2 * h)
     return grad
+
+
+def jacobian(circ, params) -> np.ndarray:
+    """J[:, j] = d psi / d theta_j as a (2^n, n_params) matrix: for every
+    use of slot j (a gate angle reading it), the circuit run with that gate
+    replaced by its derivative, summed over the slot's uses (the product
+    rule written out).  Section "Advanced automatic differentiation":
+    the Jacobian of the output state."""
+    params = np.asarray(params, dtype=np.float64)
+    n = circ.n_qubits
+    jac = np.zeros((1 << n, circ.n_params), dtype=np.complex128)
+    for gi, g in enumerate(circ.gates):
+        for which, s in enumerate(g.params):
+            if s < 0:
+                continue
+            psi = zero_state(n)
+            for gk, h in enumerate(circ.gates):
+                m = G.dmatrix(h, params, which) if gk == gi else G.matrix(h, params)
+                psi = apply(psi, m, h.qubits)
+            jac[:, s] += psi.reshape(-1)
+    return jac
+
+
+def geometric_tensor(circ, params) -> np.ndarray:
+    """G_ij = <d_i psi|d_j psi> - <d_i psi|psi><psi|d_j psi> (section
+    "Advanced automatic differentiation", the quantity behind the QFI and
+    the quantum natural gradient; the QFI is 4 Re G)."""
+    psi = state(circ, params)
+    jac = jacobian(circ, params)
+    overlap = jac.conj().T @ psi          # <d_i psi|psi>
+    return jac.conj().T @ jac - np.outer(overlap, overlap.conj())
