@@ -258,6 +258,31 @@ def mpo_leg(trials, steps=20):
     return res
 
 
+def qgt_leg(trials=8, steps=20):
+    """The geometric tensor (QFI = 4 Re G) of the paper's gradient-benchmark
+    circuit: 12 qubits, 4 blocks of [CNOT ladder, RX, RZ, RX], 144 slots;
+    the oracle (state Jacobian in complex128, numpy) timed beside it."""
+    import torch
+    import tcgen
+    from oracle import statevector as sv
+    from paper_2205_10091_amd import api
+    circ = tcgen.qfi_blocks(12, 4)
+    p = tcgen.draw_angles(3, (circ.n_params,))
+    params = torch.from_numpy(p).to("cuda:0")
+    plan = api.compile(circ, tcgen.Observable("state"), qgt=True, n_trials=trials, seed=1)
+    info = plan.info()
+    dt, g = timed(lambda: plan.geometric_tensor(params), steps, 2)
+    t0 = time.perf_counter()
+    ref = sv.geometric_tensor(circ, p.astype(np.float64))
+    oracle_s = time.perf_counter() - t0
+    return {"workload": "qfi_blocks_n12_b4", "n_params": circ.n_params,
+            "rows": info.n_qgt_rows, "evals_per_s": steps / dt, "ms_per_eval": dt / steps * 1e3,
+            "flops": info.flops + info.grad_flops,
+            "launches": info.n_launches + info.n_grad_launches,
+            "max_abs_err": float(np.max(np.abs(g - ref))),
+            "oracle_seconds": oracle_s}
+
+
 def golden_amplitude(rows, cols, depth):
     """The stored oracle amplitude of a seeded fSim grid (two independent
     oracle methods, tests/golden/), its methods' seconds, or None."""
@@ -527,6 +552,8 @@ def main():
         out["grid_amplitude"] = grid_leg(6, 6, 8, grid_trials, 50, 5, "grid")
         print("[bench] grid 4x7 depth 16 (wide nodes)", file=sys.stderr, flush=True)
         out["wide_nodes"] = grid_leg(4, 7, 16, grid_trials, 5, 1, "wide")
+        print("[bench] geometric tensor", file=sys.stderr, flush=True)
+        out["qgt"] = qgt_leg()
         print("[bench] MPO vs Pauli-sum energy", file=sys.stderr, flush=True)
         out["mpo"] = mpo_leg(16)
         # the first 20 requests of the serving stream (the full 60-request

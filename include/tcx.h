@@ -115,8 +115,12 @@ typedef struct {
  * mpo_bonds[k-1] = D_k for the n-1 inner bonds, each in 1..8 (D_0 = D_n = 1).
  * A bond of dimension D becomes ceil(log2 D) legs of dimension 2, the
  * padded entries zero.  No light cone applies (M acts on every qubit).
+ * STATE: the network <psi|psi> (ket and conjugated ket joined on every
+ * wire); contracted it gives the squared norm, and it is the network of
+ * the geometric tensor (tc_plan_opts.qgt, tc_contract_qgt).
  */
-typedef enum { TC_OBS_AMPLITUDE = 0, TC_OBS_PAULI_SUM = 1, TC_OBS_MPO = 2 } tc_obs_kind;
+typedef enum { TC_OBS_AMPLITUDE = 0, TC_OBS_PAULI_SUM = 1, TC_OBS_MPO = 2,
+               TC_OBS_STATE = 3 } tc_obs_kind;
 
 typedef struct {
   int32_t kind;               /* tc_obs_kind                               */
@@ -318,6 +322,16 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *               levels (values consumed inside their own segment are freed
  *               after the forward pass and recomputed segment by segment
  *               during the reverse sweep); -1 = never.
+ *   qgt         geometric tensor (section "Advanced automatic
+ *               differentiation": the quantity <d_i psi|d_j psi> -
+ *               <d_i psi|psi><psi|d_j psi> behind the QFI and the quantum
+ *               natural gradient).  The plan contracts the <psi|psi>
+ *               network once per gate use u of a parameter (batch row u
+ *               takes that gate's derivative on the ket side), which gives
+ *               <psi|d_u psi>; its reverse sweep toward the bra leaves
+ *               gives <d_i psi|d_u psi> for every slot i in the same pass;
+ *               a last kernel sums the uses of each slot and subtracts the
+ *               product term.
  */
 typedef struct tc_plan tc_plan;
 
@@ -335,6 +349,9 @@ typedef struct {
   uint64_t gemm_min_macs;
   int32_t exec_mode;
   int32_t tile_mode;
+  int32_t qgt;               /* 1: the plan computes the geometric tensor
+                                (tc_contract_qgt) of the circuit's state;
+                                needs a TC_OBS_STATE network and batch 1   */
 } tc_plan_opts;
 
 tc_status tc_plan_create(const tc_network* net, const tc_path* path,
@@ -369,6 +386,8 @@ typedef struct {
                                 forward pass and reverse sweep after the
                                 other's, so that the live intermediates
                                 fit mem_budget_bytes (1 = all together)  */
+  int32_t n_qgt_rows;        /* qgt plans: gate uses of parameters, one
+                                contraction row each (0 otherwise)        */
 } tc_plan_info;
 
 tc_status tc_plan_info_get(const tc_plan* plan, tc_plan_info* out);
@@ -401,6 +420,15 @@ tc_status tc_contract_device(tc_plan* plan, const float* params,
                              double* out_dev);
 tc_status tc_contract_grad_device(tc_plan* plan, const float* params,
                                   double* value_dev, double* grad_dev);
+
+/* tc_contract_qgt: for a plan made with qgt = 1.  params is a DEVICE
+ * pointer to n_params floats (one vector); qgt is a HOST pointer to
+ * 2 * n_params * n_params doubles receiving G[i][j] = <d_i psi|d_j psi> -
+ * <d_i psi|psi><psi|d_j psi> as (re, im), row-major (i the bra slot, j the
+ * ket slot); slots no gate uses give zero rows and columns.  The QFI is
+ * 4 Re G.  Synchronous.  STATE for plans without qgt (and the other
+ * contraction calls return STATE for qgt plans). */
+tc_status tc_contract_qgt(tc_plan* plan, const float* params, double* qgt);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -72,7 +72,7 @@ class PlanOpts(C.Structure):
                 ("mem_budget_bytes", C.c_uint64), ("stream", C.c_void_p),
                 ("gemm_min_k", C.c_int32), ("checkpoint_every", C.c_int32),
                 ("gemm_min_macs", C.c_uint64), ("exec_mode", C.c_int32),
-                ("tile_mode", C.c_int32)]
+                ("tile_mode", C.c_int32), ("qgt", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -86,7 +86,8 @@ class PlanInfo(C.Structure):
                 ("n_params", C.c_int32), ("n_terms", C.c_int32),
                 ("checkpoint_every", C.c_int32), ("exec_mode", C.c_int32),
                 ("n_split_nodes", C.c_int32), ("n_split_sums", C.c_int32),
-                ("n_wide_nodes", C.c_int32), ("n_term_groups", C.c_int32)]
+                ("n_wide_nodes", C.c_int32), ("n_term_groups", C.c_int32),
+                ("n_qgt_rows", C.c_int32)]
 
 
 class ServeOpts(C.Structure):
@@ -134,6 +135,7 @@ SIGNATURES = [
     ("tc_contract_device", C.c_int, [VP, VP, VP]),
     ("tc_contract_grad_device", C.c_int, [VP, VP, VP, VP]),
     ("tc_contract_grad_device_noalloc", C.c_int, [VP, VP, VP, VP]),
+    ("tc_contract_qgt", C.c_int, [VP, VP, F64P]),
     ("tc_plan_profile", C.c_int, [VP, VP, C.c_int32, C.c_int32, C.c_int32, I32P,
                                   I32P, F64P, F64P, F64P]),
     ("tc_serve_create", C.c_int, [C.POINTER(ServeOpts), PVP]),

@@ -55,6 +55,8 @@ class _CObservable:
             b = (C.c_uint8 * n_qubits)(*bits)
             self.keep.append(b)
             self.o = L.Observable(0, C.cast(b, C.POINTER(C.c_uint8)), 0, None, None, None, None)
+        elif obs.kind == "state":
+            self.o = L.Observable(3, None, 0, None, None, None, None)
         elif obs.kind == "mpo":
             ts = [np.asarray(t, np.complex128) for t in obs.mpo]
             bonds = np.ascontiguousarray([t.shape[1] for t in ts[:-1]], dtype=np.int32)
@@ -156,13 +158,14 @@ class Plan:
 
     def __init__(self, net: Network, path: Path, batch=1, want_grad=False,
                  precision=0, device=0, mem_budget_bytes=0, stream=None, gemm_min_k=0,
-                 checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0):
+                 checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0, qgt=False):
         self.net, self.path = net, path
         self.batch = batch
         self.want_grad = want_grad
+        self.qgt = bool(qgt)
         opts = L.PlanOpts(precision, batch, int(want_grad), device,
                           mem_budget_bytes, stream, gemm_min_k, checkpoint_every,
-                          gemm_min_macs, exec_mode, tile_mode)
+                          gemm_min_macs, exec_mode, tile_mode, int(qgt))
         h = C.c_void_p()
         L.check(lib().tc_plan_create(net.h, path.h, C.byref(opts), C.byref(h)))
         self.h = h
@@ -213,6 +216,15 @@ class Plan:
             # parameters written on torch's current stream are visible to the plan
             self.torch_stream.wait_stream(torch.cuda.current_stream(params.device))
         return C.c_void_p(params.data_ptr())
+
+    def geometric_tensor(self, params) -> np.ndarray:
+        """G[i, j] = <d_i psi|d_j psi> - <d_i psi|psi><psi|d_j psi> as a
+        complex128 (n_params, n_params) array (plans made with qgt=True)."""
+        n = self.n_params
+        out = np.zeros(2 * max(n * n, 1), np.float64)
+        L.check(lib().tc_contract_qgt(self.h, self._params_ptr(params),
+                                      out.ctypes.data_as(L.F64P)))
+        return (out[0::2] + 1j * out[1::2])[:n * n].reshape(n, n)
 
     def contract(self, params) -> np.ndarray:
         """Complex values (numpy complex128, shape [batch])."""
@@ -269,7 +281,7 @@ def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
             lightcone=True, absorb_1q=True, seed=0, n_trials=8,
             mem_budget_bytes=0, device=0, bind=True, gemm_min_k=0, stream=None,
             checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0,
-            score=3) -> Plan:
+            score=3, qgt=False) -> Plan:
     """Network + greedy path + plan (+ bind with a torch workspace).
     score: the path score of tc_greedy_path (3 combo, 4 time estimate)."""
     net = Network(circ, obs, split_2q, lightcone, absorb_1q)
@@ -283,7 +295,8 @@ def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
         torch_stream = torch.cuda.Stream(device=f"cuda:{device}")
         stream = torch_stream.cuda_stream
     plan = Plan(net, path, batch, want_grad, precision, device, mem_budget_bytes,
-                stream, gemm_min_k, checkpoint_every, gemm_min_macs, exec_mode, tile_mode)
+                stream, gemm_min_k, checkpoint_every, gemm_min_macs, exec_mode, tile_mode,
+                qgt)
     plan.torch_stream = torch_stream
     if bind:
         plan.bind_torch(f"cuda:{device}")

@@ -51,7 +51,7 @@ struct LeafSeg {
   float2* arena;
   uint64_t start;  // first work item of this segment in the launch
   uint32_t n;
-  int32_t n_params;
+  uint32_t param_stride;  // floats between rows' parameter vectors (0: shared)
 };
 struct LeafArgs {
   LeafSeg seg[MAX_SEG];
@@ -131,7 +131,7 @@ struct TermArgs {
   const float* ftab;
   const float* params;
   float2* arena;
-  int32_t n_params;
+  uint32_t param_stride;      // floats between rows' parameter vectors
   int32_t with_leaves;        // materialise the term's leaves first
 };
 
@@ -143,6 +143,20 @@ struct GradSeg {
   const float2* arena;
   double* grad;
   uint64_t start;  // first wavefront (row, slot) of this segment
+  int32_t n_params;
+  uint32_t param_stride;  // floats between rows' parameter vectors
+  int32_t cplx;           // 1: complex sums, (re, im) per (row, slot)
+};
+
+// Geometric tensor: G[i][j] = sum over the rows u of slot j of
+// S[u][i] - conj(v_i) v_j with v_j = sum over the rows u of slot j of
+// value[u] (value[u] = <psi|d_u psi>, S[u][i] = <d_i psi|d_u psi>).
+struct QgtArgs {
+  const double* value;       // (re, im) per row
+  const double* sums;        // (re, im) per (row, slot)
+  const uint32_t* slot_begin;  // n_params + 1
+  const uint32_t* rows;        // rows by slot
+  double* out;                 // (re, im) per (i, j)
   int32_t n_params;
 };
 struct GradArgs {
@@ -227,16 +241,19 @@ __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restri
 // Leaf work item w (row-major over the leaf's rows and entries): one entry
 // of one leaf tensor for one batch row.
 __device__ __forceinline__ void leaf_item(const DevLeaf& L, uint64_t w,
-                                          const float* __restrict__ params, int32_t n_params,
+                                          const float* __restrict__ params, uint32_t param_stride,
                                           const float* __restrict__ ftab,
                                           float2* __restrict__ arena) {
   const uint64_t l = w - L.work0;
   const int e = (int)(l & ((1u << L.rank) - 1));
   const uint64_t r = l >> L.rank;
-  const float* pr = params + r * (uint64_t)n_params;
+  const float* pr = params + r * (uint64_t)param_stride;
   const float t0 = L.param[0] >= 0 ? pr[L.param[0]] : L.fixed[0];
   const float t1 = L.param[1] >= 0 ? pr[L.param[1]] : L.fixed[1];
-  const c32 v = leaf_entry(L, e, t0, t1, ftab);
+  // (geometric tensor plans: the row of a gate use holds its derivative)
+  const c32 v = (int64_t)r == L.dsel[0]   ? dleaf_entry(L, e, t0, t1, 0)
+                : (int64_t)r == L.dsel[1] ? dleaf_entry(L, e, t0, t1, 1)
+                                          : leaf_entry(L, e, t0, t1, ftab);
   arena[L.out + (r << L.rank) + e] = make_float2(v.re, v.im);
 }
 
@@ -265,7 +282,7 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
       li = find_item(S.leaves, S.n, ws);
     else
       while (li + 1 < S.n && S.leaves[li + 1].work0 <= ws) ++li;
-    leaf_item(S.leaves[li], ws, S.params, S.n_params, S.ftab, S.arena);
+    leaf_item(S.leaves[li], ws, S.params, S.param_stride, S.ftab, S.arena);
   }
 }
 
@@ -762,7 +779,7 @@ __global__ void __launch_bounds__(1024) k_term(TermArgs a) {
     for (uint64_t w = T.leaf_work0 + threadIdx.x; w < T.leaf_work_end; w += blockDim.x) {
       const uint32_t li =
           a.item_leaf ? a.item_leaf[w] : find_in(a.leaves, T.leaf_begin, T.leaf_end, w);
-      leaf_item(a.leaves[li], w, a.params, a.n_params, a.ftab, a.arena);
+      leaf_item(a.leaves[li], w, a.params, a.param_stride, a.ftab, a.arena);
     }
   }
   commit(R.g_begin, 0);
@@ -849,8 +866,8 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs a) {
     const uint64_t w = wv - S.start;
     const uint64_t b = w / (uint32_t)S.n_params;
     const uint32_t slot = (uint32_t)(w - b * (uint32_t)S.n_params);
-    const float* pr = S.params + b * (uint64_t)S.n_params;
-    double acc = 0.0;
+    const float* pr = S.params + b * (uint64_t)S.param_stride;
+    double acc = 0.0, acc_im = 0.0;
     for (uint32_t u = S.slot_begin[slot] + lane; u < S.slot_begin[slot + 1]; u += 64) {
       const DevGradUse& U = S.uses[u];
       const DevLeaf& L = S.leaves[U.leaf];
@@ -862,10 +879,58 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs a) {
         const c32 d = dleaf_entry(L, e, t0, t1, U.which);
         const float2 x = ad[e];
         acc += (double)x.x * d.re - (double)x.y * d.im;
+        acc_im += (double)x.x * d.im + (double)x.y * d.re;
       }
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) S.grad[w] = acc;
+    for (int off = 32; off > 0; off >>= 1) {
+      acc += __shfl_xor(acc, off, 64);
+      acc_im += __shfl_xor(acc_im, off, 64);
+    }
+    if (lane == 0) {
+      if (S.cplx) {
+        S.grad[2 * w] = acc;
+        S.grad[2 * w + 1] = acc_im;
+      } else {
+        S.grad[w] = acc;
+      }
+    }
+  }
+}
+
+// One wavefront per (i, j): lanes over the rows of slot j (sums and v_j)
+// and of slot i (v_i), fixed-order butterflies, FP64.
+__global__ void __launch_bounds__(256) k_qgt(QgtArgs a) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wv = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t np = (uint64_t)a.n_params;
+  if (wv >= np * np) return;  // whole wavefronts leave together
+  const uint32_t i = (uint32_t)(wv / np), j = (uint32_t)(wv - (uint64_t)i * np);
+  double sr = 0.0, si = 0.0, vjr = 0.0, vji = 0.0, vir = 0.0, vii = 0.0;
+  for (uint32_t k = a.slot_begin[j] + lane; k < a.slot_begin[j + 1]; k += 64) {
+    const uint64_t u = a.rows[k];
+    sr += a.sums[2 * (u * np + i)];
+    si += a.sums[2 * (u * np + i) + 1];
+    vjr += a.value[2 * u];
+    vji += a.value[2 * u + 1];
+  }
+  for (uint32_t k = a.slot_begin[i] + lane; k < a.slot_begin[i + 1]; k += 64) {
+    const uint64_t u = a.rows[k];
+    vir += a.value[2 * u];
+    vii += a.value[2 * u + 1];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
+    vjr += __shfl_xor(vjr, off, 64);
+    vji += __shfl_xor(vji, off, 64);
+    vir += __shfl_xor(vir, off, 64);
+    vii += __shfl_xor(vii, off, 64);
+  }
+  if (lane == 0) {
+    // conj(v_i) v_j
+    const double pr = vir * vjr + vii * vji, pi = vir * vji - vii * vjr;
+    a.out[2 * wv] = sr - pr;
+    a.out[2 * wv + 1] = si - pi;
   }
 }
 
@@ -924,7 +989,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.params = (const float*)(s.ws + L.params);
         g.arena = (float2*)(s.ws + L.arena);
         g.n = (uint32_t)s.plan->leaves.size();
-        g.n_params = s.plan->n_params;
+        g.param_stride = s.plan->param_stride();
         g.start = w;
         w += s.launch->work;
       }
@@ -1066,7 +1131,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.ftab = (const float*)(s.ws + L.ftab);
       a.params = (const float*)(s.ws + L.params);
       a.arena = (float2*)(s.ws + L.arena);
-      a.n_params = P.n_params;
+      a.param_stride = P.param_stride();
       a.with_leaves = s.launch->with_leaves ? 1 : 0;
       launch(k_term, dim3((unsigned)P.terms.size()), dim3(1024), stream, a);
       break;
@@ -1106,6 +1171,8 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.arena = (const float2*)(s.ws + L.arena);
         g.grad = (double*)(s.ws + L.grad);
         g.n_params = s.plan->n_params;
+        g.param_stride = s.plan->param_stride();
+        g.cplx = s.plan->qgt ? 1 : 0;
         g.start = w;
         w += s.launch->work;
       }
@@ -1113,6 +1180,22 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.total = w;
       if (w == 0) return;
       launch(k_grad, dim3(grid_for(w * 64, 256, n_cu)), dim3(256), stream, a);
+      break;
+    }
+    case L_QGT: {
+      if (nseg != 1) fail(TC_ERR_INVALID_ARG, "internal: one plan per geometric tensor launch");
+      const SegRef& s = segs[0];
+      const WorkspaceLayout& L = *s.lay;
+      QgtArgs a{};
+      a.value = (const double*)(s.ws + L.value);
+      a.sums = (const double*)(s.ws + L.grad);
+      a.slot_begin = (const uint32_t*)(s.ws + L.qslot);
+      a.rows = (const uint32_t*)(s.ws + L.qrows);
+      a.out = (double*)(s.ws + L.qgt);
+      a.n_params = s.plan->n_params;
+      const uint64_t waves = (uint64_t)a.n_params * a.n_params;
+      if (!waves) return;
+      launch(k_qgt, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), stream, a);
       break;
     }
     default:
@@ -1151,6 +1234,8 @@ void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStrea
   upload(ws, lay.ranges, P.ranges, stream);
   upload(ws, lay.sunits, P.split_units, stream);
   upload(ws, lay.gsunits, P.gsplit_units, stream);
+  upload(ws, lay.qslot, P.qslot_begin, stream);
+  upload(ws, lay.qrows, P.qrows, stream);
   upload(ws, lay.arena, P.seeds, stream);  // seeds sit at arena offset 0
 }
 
@@ -1246,13 +1331,14 @@ static void stage_params(Plan& P, const float* params) {
   if (!P.dev) bind_plan(P, nullptr, 0);
   DeviceState& D = *P.dev;
   HIP_CHECK(hipSetDevice(D.device));
-  uint64_t pbytes = (uint64_t)P.batch * P.n_params * sizeof(float);
+  uint64_t pbytes = (P.qgt ? 1 : (uint64_t)P.batch) * P.n_params * sizeof(float);
   if (pbytes)
     HIP_CHECK(hipMemcpyAsync(D.ws + D.lay.params, params, pbytes, hipMemcpyDeviceToDevice,
                              D.stream));
 }
 
 void contract(Plan& P, const float* params, double* out, bool device_out) {
+  if (P.qgt) fail(TC_ERR_STATE, "a geometric tensor plan runs through tc_contract_qgt");
   BusyGuard g(P.busy);
   stage_params(P, params);
   DeviceState& D = *P.dev;
@@ -1266,6 +1352,7 @@ void contract(Plan& P, const float* params, double* out, bool device_out) {
 void contract_grad(Plan& P, const float* params, double* value, double* grad,
                    bool device_out) {
   if (!P.want_grad) fail(TC_ERR_STATE, "plan was compiled without want_grad");
+  if (P.qgt) fail(TC_ERR_STATE, "a geometric tensor plan runs through tc_contract_qgt");
   BusyGuard g(P.busy);
   stage_params(P, params);
   DeviceState& D = *P.dev;
@@ -1278,6 +1365,19 @@ void contract_grad(Plan& P, const float* params, double* value, double* grad,
     HIP_CHECK(hipMemcpyAsync(grad, D.ws + D.lay.grad,
                              (uint64_t)P.batch * P.n_params * sizeof(double), kind, D.stream));
   if (!device_out) HIP_CHECK(hipStreamSynchronize(D.stream));
+}
+
+void contract_qgt(Plan& P, const float* params, double* out) {
+  if (!P.qgt) fail(TC_ERR_STATE, "plan was compiled without qgt");
+  BusyGuard g(P.busy);
+  stage_params(P, params);
+  DeviceState& D = *P.dev;
+  HIP_CHECK(hipGraphLaunch(D.exec[1], D.stream));
+  const uint64_t n = 2 * (uint64_t)P.n_params * P.n_params;
+  if (n)
+    HIP_CHECK(hipMemcpyAsync(out, D.ws + D.lay.qgt, n * sizeof(double), hipMemcpyDeviceToHost,
+                             D.stream));
+  HIP_CHECK(hipStreamSynchronize(D.stream));
 }
 
 void profile(Plan& P, const float* params, int which, int reps, int cap, int* n_out,
@@ -1396,6 +1496,7 @@ static ScratchSlot scratch_slot(int device) {
 
 void contract_grad_noalloc(Plan& P, const float* params, double* value_dev, double* grad_dev) {
   if (!P.want_grad) fail(TC_ERR_STATE, "plan was compiled without want_grad");
+  if (P.qgt) fail(TC_ERR_STATE, "a geometric tensor plan runs through tc_contract_qgt");
   if (!params) fail(TC_ERR_INVALID_ARG, "params is NULL");
   const WorkspaceLayout lay = workspace_layout(P);
   if (lay.total > TC_NOALLOC_MAX_BYTES)
@@ -1452,7 +1553,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
                          const tc_plan_opts* opts, tc_plan** out) {
   TC_GUARD_BEGIN
   if (!net || !path || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
-  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0, 0, 0, 0};
+  tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.gemm_min_k < 0) tcx::fail(TC_ERR_INVALID_ARG, "gemm_min_k must be >= 0");
   if (o.exec_mode < 0 || o.exec_mode > 2) tcx::fail(TC_ERR_INVALID_ARG, "exec_mode must be 0, 1 or 2");
@@ -1475,6 +1576,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
     p->p.exec_mode = o.exec_mode;
     p->p.wide_tiles = wide_tiles;
     p->p.checkpoint = o.checkpoint_every;
+    p->p.qgt = o.qgt ? 1 : 0;
     try {
       tcx::build_plan(p->p, tcx::network_of(net), tcx::path_of(path));
     } catch (...) {
@@ -1547,6 +1649,14 @@ tc_status tc_contract_grad_device(tc_plan* plan, const float* params, double* va
   TC_GUARD_BEGIN
   if (!plan) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
   tcx::contract_grad(plan->p, params, value_dev, grad_dev, true);
+  return TC_OK;
+  TC_GUARD_END
+}
+
+tc_status tc_contract_qgt(tc_plan* plan, const float* params, double* qgt) {
+  TC_GUARD_BEGIN
+  if (!plan || !params || !qgt) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  tcx::contract_qgt(plan->p, params, qgt);
   return TC_OK;
   TC_GUARD_END
 }

@@ -301,6 +301,14 @@ Network build_network(const tc_circuit* c, const tc_observable* o,
       tb.term.weight = w;
       net.terms.push_back(std::move(tb.term));
     }
+  } else if (o->kind == TC_OBS_STATE) {
+    // <psi|psi>: the conjugated ket's wires end on the ket's open legs
+    TermBuilder tb(net);
+    std::vector<int32_t> ket_out = tb.ket(all_active, all_keep, 0, nullptr);
+    tb.ket(all_active, all_keep, 1, &ket_out);
+    tb.term.n_labels = tb.next;
+    tb.term.weight = 1.0;
+    net.terms.push_back(std::move(tb.term));
   } else if (o->kind == TC_OBS_MPO) {
     // one network: ket, the MPO sites (out leg to the bra, in leg from the
     // ket, bond legs between neighbours), conjugated ket

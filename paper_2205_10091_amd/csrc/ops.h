@@ -94,6 +94,8 @@ struct DevLeaf {
   uint32_t rows;           // batch rows written (1 = shared)
   uint32_t mat;            // offset in the float table: 32 floats (U1/U2), or
                            // 2^(rank+1) (the entries of an MPO site)
+  int32_t dsel[2];         // batch row that takes d/d(angle a) instead of the
+                           // gate (geometric tensor plans), -1 none
 };
 
 // d(term root)/d(angle) for one leaf use: sum_e adj[e] * dleaf[e]/dangle

@@ -288,9 +288,13 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
       PT x;
       x.legs = legs[i];
       x.elems = 1ull << x.legs.size();
-      x.batched = leaf_param_dependent(net, term.leaves[i]);
+      const bool pd = leaf_param_dependent(net, term.leaves[i]);
+      // geometric tensor: the ket's parameter leaves differ per row (each
+      // row differentiates one gate use); the reverse sweep runs toward
+      // the bra's parameter leaves only
+      x.batched = plan.qgt ? pd && !term.leaves[i].conj : pd;
       x.term = (int32_t)t;
-      I.needs[i] = x.batched;
+      I.needs[i] = plan.qgt ? pd && term.leaves[i].conj : pd;
       x.first = 0;
       I.tid[i] = (int32_t)T.size();
       T.push_back(x);
@@ -536,9 +540,14 @@ WorkspaceLayout workspace_layout(const Plan& p) {
   w.split = o; o = al(o + p.split_floats * sizeof(float));
   w.sunits = o; o = al(o + p.split_units.size() * sizeof(DevSplitUnit));
   w.gsunits = o; o = al(o + p.gsplit_units.size() * sizeof(DevSplitUnit));
-  w.params = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(float));
+  w.qslot = o; o = al(o + p.qslot_begin.size() * sizeof(uint32_t));
+  w.qrows = o; o = al(o + p.qrows.size() * sizeof(uint32_t));
+  const uint64_t np = (uint64_t)std::max(p.n_params, 1);
+  w.params = o; o = al(o + (p.qgt ? 1 : (uint64_t)p.batch) * np * sizeof(float));
   w.value = o; o = al(o + (uint64_t)p.batch * 2 * sizeof(double));
-  w.grad = o; o = al(o + (uint64_t)p.batch * std::max(p.n_params, 1) * sizeof(double));
+  // (geometric tensor: complex adjoint sums per row and slot)
+  w.grad = o; o = al(o + (uint64_t)p.batch * np * (p.qgt ? 2 : 1) * sizeof(double));
+  w.qgt = o; o = al(o + (p.qgt ? 2 * np * np : 0) * sizeof(double));
   w.arena = o; o = al(o + p.arena_elems * 8);
   w.total = o;
   return w;
@@ -557,6 +566,23 @@ std::vector<const Launch*> launch_order(const Plan& p, bool with_grad) {
 }
 
 void build_plan(Plan& plan, const Network& net, const Path& path) {
+  if (plan.qgt) {
+    // one row per gate use of a parameter on the ket side
+    if (net.obs_kind != TC_OBS_STATE)
+      fail(TC_ERR_INVALID_ARG, "the geometric tensor needs a network built for TC_OBS_STATE");
+    if (plan.batch != 1)
+      fail(TC_ERR_INVALID_ARG, "geometric tensor plans take one parameter vector (batch 1)");
+    int32_t u = 0;
+    for (const Term& term : net.terms)
+      for (const Leaf& lf : term.leaves)
+        if (lf.kind == LEAF_GATE && !lf.conj && leaf_param_dependent(net, lf)) {
+          const GateRec& g = net.gates[lf.gate];
+          for (int a = 0; a < g.n_angles; ++a) u += g.param[a] >= 0;
+        }
+    plan.qgt_rows = u;
+    plan.batch = std::max(u, 1);
+    plan.want_grad = 1;
+  }
   const int B = plan.batch;
   const bool grad = plan.want_grad != 0;
   plan.n_params = net.n_params;
@@ -1173,6 +1199,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
 
   // ---- leaves
   uint64_t lw = 0;
+  std::vector<int32_t> qrow_slot;  // geometric tensor: the slot of each row
   for (size_t t = 0; t < net.terms.size(); ++t) {
     const Term& term = net.terms[t];
     plan.terms[t].leaf_begin = (uint32_t)plan.leaves.size();
@@ -1189,12 +1216,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       d.rank = lf.rank;
       d.rows = (x.batched && B > 1) ? (uint32_t)B : 1u;
       d.param[0] = d.param[1] = -1;
+      d.dsel[0] = d.dsel[1] = -1;
       if (lf.kind == LEAF_GATE) {
         const GateRec& g = net.gates[lf.gate];
         d.gkind = g.kind;
         for (int a = 0; a < g.n_angles; ++a) {
           d.param[a] = g.param[a];
           d.fixed[a] = (float)g.fixed[a];
+          if (plan.qgt && !lf.conj && leaf_param_dependent(net, lf) && g.param[a] >= 0) {
+            d.dsel[a] = (int32_t)qrow_slot.size();  // this use's row
+            qrow_slot.push_back(g.param[a]);
+          }
         }
         if (g.kind == TC_GATE_U1 || g.kind == TC_GATE_U2) {
           d.mat = (uint32_t)plan.ftab.size();
@@ -1218,6 +1250,15 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   }
   if (!plan.term_mode) plan.terms.clear();
   plan.leaf_work = lw;
+  if (plan.qgt) {
+    if ((int32_t)qrow_slot.size() != plan.qgt_rows) fail(TC_ERR_INVALID_ARG, "internal: qgt rows");
+    plan.qslot_begin.assign(net.n_params + 1, 0);
+    for (int32_t s : qrow_slot) plan.qslot_begin[s + 1]++;
+    for (int p2 = 0; p2 < net.n_params; ++p2) plan.qslot_begin[p2 + 1] += plan.qslot_begin[p2];
+    plan.qrows.assign(qrow_slot.size(), 0);
+    std::vector<uint32_t> fill(plan.qslot_begin.begin(), plan.qslot_begin.end() - 1);
+    for (size_t r = 0; r < qrow_slot.size(); ++r) plan.qrows[fill[qrow_slot[r]]++] = (uint32_t)r;
+  }
   plan.fwd[0].work = lw;
   if (lw > 0 && lw <= ITEM_TABLE_MAX) {  // leaf entry -> leaf index
     plan.fwd[0].item_begin = plan.item_op.size();
@@ -1285,6 +1326,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       L.work = (uint64_t)B * net.n_params;
       plan.bwd.push_back(L);
     }
+    if (plan.qgt && net.n_params > 0) {
+      Launch L;
+      L.kind = L_QGT;
+      L.step = S.grad_step + 1;
+      L.work = (uint64_t)net.n_params * net.n_params;
+      plan.bwd.push_back(L);
+    }
   }
 
   // ---- every device access in bounds (checked here, before any launch)
@@ -1319,6 +1367,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       if (u.leaf >= plan.leaves.size() ||
           u.adj + (uint64_t)(B - 1) * u.adj_bs + (1ull << plan.leaves[u.leaf].rank) > AE)
         fail(TC_ERR_INVALID_ARG, "internal: gradient use out of range");
+    for (uint32_t r : plan.qrows)
+      if (r >= (uint32_t)B) fail(TC_ERR_INVALID_ARG, "internal: qgt row out of range");
+    for (const DevLeaf& d : plan.leaves)
+      for (int a = 0; a < 2; ++a)
+        if (d.dsel[a] >= B || (d.dsel[a] >= 0 && d.rows != (uint32_t)B))
+          fail(TC_ERR_INVALID_ARG, "internal: derivative row out of range");
     for (const DevRoot& r : plan.roots)
       if (r.present && r.val + (uint64_t)(B - 1) * r.bs >= AE)
         fail(TC_ERR_INVALID_ARG, "internal: root out of range");
@@ -1497,8 +1551,9 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   info.n_levels = S.max_level;
   info.n_launches = (int32_t)plan.fwd.size();
   info.n_grad_launches = (int32_t)plan.bwd.size();
-  info.batch = B;
+  info.batch = plan.qgt ? 1 : B;   // the caller's parameter vectors
   info.n_params = net.n_params;
+  info.n_qgt_rows = plan.qgt_rows;
   info.n_terms = plan.n_terms;
   info.checkpoint_every = plan.checkpoint_used;
   info.n_term_groups = plan.term_groups;

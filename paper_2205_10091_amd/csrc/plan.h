@@ -15,7 +15,8 @@ enum LaunchKind : int32_t {
   L_LEVEL = 1,  // one contraction level: MFMA GEMM tiles + gather contractions
   L_ROOT = 4,   // FP64 weighted sum of the term roots
   L_GRAD = 5,   // FP64 leaf-gradient reduction
-  L_TERM = 6    // one workgroup per term runs the term's nodes of a run of steps
+  L_TERM = 6,   // one workgroup per term runs the term's nodes of a run of steps
+  L_QGT = 7     // geometric tensor from the per-use values and adjoint sums
 };
 // kernel kinds reported by profiling: a level's GEMM tiles (64 x 64 and
 // wave tiles), gathers, and 128 x 128 GEMM tiles
@@ -108,6 +109,11 @@ struct Plan {
   int32_t checkpoint_used = 0;
   // terms run in this many groups, one after another (1 = all together)
   int32_t term_groups = 1;
+  // geometric tensor: batch rows are the ket's gate uses, all reading one
+  // parameter vector
+  int32_t qgt = 0;
+  int32_t qgt_rows = 0;
+  uint32_t param_stride() const { return qgt ? 0u : (uint32_t)n_params; }
 
   // tables uploaded once
   std::vector<DevOp> ops;
@@ -124,6 +130,8 @@ struct Plan {
   std::vector<DevSplitUnit> split_units;  // split-K output tiles, per level
   std::vector<DevSplitUnit> gsplit_units; // split gather outputs, per level
   std::vector<float> seeds;           // (re, im) per term, arena offset 0
+  std::vector<uint32_t> qslot_begin;  // qgt: n_params + 1, rows of each slot in qrows
+  std::vector<uint32_t> qrows;        // qgt: batch rows (ket gate uses) by slot
   uint64_t leaf_work = 0;
 
   std::vector<Launch> fwd;            // leaf, levels, root
@@ -150,7 +158,8 @@ std::vector<const Launch*> launch_order(const Plan& p, bool with_grad);
 struct WorkspaceLayout {
   uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots, terms, groups, ranges;
   uint64_t split, sunits, gsunits;  // split-K partials (float), units to reduce
-  uint64_t params, value, grad, arena, total;
+  uint64_t qslot, qrows;             // qgt: slot -> rows tables
+  uint64_t params, value, grad, qgt, arena, total;
 };
 WorkspaceLayout workspace_layout(const Plan& p);
 

@@ -83,10 +83,11 @@ class Circuit:
 
 @dataclass
 class Observable:
-    """An amplitude <bits|U|0...0>, a weighted Pauli sum, or an operator
+    """An amplitude <bits|U|0...0>, a weighted Pauli sum, an operator
     given as a matrix product operator (site tensors of shape
-    (D_left, D_right, 2, 2): bond in, bond out, row index, column index)."""
-    kind: str                          # "amplitude", "pauli_sum" or "mpo"
+    (D_left, D_right, 2, 2): bond in, bond out, row index, column index),
+    or the state itself ("state": the network <psi|psi>)."""
+    kind: str                          # "amplitude", "pauli_sum", "mpo" or "state"
     bits: Optional[Tuple[int, ...]] = None
     structures: Optional[np.ndarray] = None   # (n_terms, n_qubits) uint8
     weights: Optional[np.ndarray] = None      # (n_terms,) float64
@@ -145,6 +146,23 @@ def tfim_zz_x(n: int, g: float = 1.0) -> Observable:
         s[n - 1 + i, i] = 1
         w[n - 1 + i] = g
     return Observable("pauli_sum", structures=s, weights=w)
+
+
+def qfi_blocks(n: int, blocks: int) -> Circuit:
+    """The parameterised circuit of the paper's QFI / Hessian benchmark
+    (section "Advanced automatic differentiation", gradient benchmark
+    figure): blocks of [CNOT ladder, RX, RZ, RX on every qubit], one slot
+    per gate."""
+    c = Circuit(n, 3 * n * blocks)
+    s = 0
+    for _ in range(blocks):
+        for i in range(n - 1):
+            c.add("cnot", (i, i + 1))
+        for kind in ("rx", "rz", "rx"):
+            for i in range(n):
+                c.add(kind, (i,), (s,))
+                s += 1
+    return c
 
 
 def tfim_mpo(n: int, g: float = 1.0, j: float = 1.0) -> Observable:
