@@ -14,6 +14,22 @@ Gates absent from the paper follow their usual published definitions:
   ((1+i)/2) I + ((1-i)/2) G, with W = (X + Y)/sqrt(2);
 * fSim(theta, phi) (Foxen et al., PRL 125, 120504 (2020)):
   [[1,0,0,0],[0,cos t,-i sin t,0],[0,-i sin t,cos t,0],[0,0,0,e^{-i phi}]].
+
+Channels with externalised randomness (sections "Externalizing the
+randomness", "Batched Monte Carlo trajectory noise simulation",
+"Demonstration of barren plateaus"): a status x in [0,1) is cut into
+contiguous intervals whose lengths are the outcome probabilities, in the
+listed order, and the operator of the interval holding x is applied:
+
+* "depol" (probabilities (px, py, pz) in ``matrix``; status = angle 0):
+  I, X, Y, Z with probabilities 1 - px - py - pz, px, py, pz;
+* "rswitch" (angle 0 = t, angle 1 = status): RX(t), RY(t), RZ(t), a third
+  each.
+
+The cut points are computed and compared in float32 (the status arrives as
+a float32 parameter), in the order written in ``_choice``, so that a
+status next to a cut falls on the same side as in any float32
+implementation of the same rule.  The status itself has no derivative.
 """
 from __future__ import annotations
 
@@ -81,6 +97,28 @@ _FIXED = {
 _ROT_GEN = {"rx": X, "ry": Y, "rz": Z, "rzz": ZZ, "rxx": XX, "ryy": YY}
 
 
+def _choice(status: float, cuts) -> int:
+    """Index of the interval of [0,1) holding the status, for the interval
+    ends `cuts` (float32; the last interval runs to 1)."""
+    x = np.float32(status)
+    for i, c in enumerate(cuts):
+        if x < c:
+            return i
+    return len(cuts)
+
+
+def _depol_cuts(g):
+    # p0 = ((1 - px) - py) - pz, then p0 + px, then (p0 + px) + py, in float32
+    px, py, pz = (np.float32(v) for v in g.matrix)
+    p0 = np.float32(np.float32(np.float32(np.float32(1.0) - px) - py) - pz)
+    c1 = np.float32(p0 + px)
+    return [p0, c1, np.float32(c1 + py)]
+
+
+_RSWITCH = [X, Y, Z]
+_RSWITCH_CUTS = [np.float32(1.0) / np.float32(3.0), np.float32(2.0) / np.float32(3.0)]
+
+
 def gate_angles(g, params) -> list:
     """Angles of gate g: params[slot] where slot >= 0, else the fixed value."""
     return [float(params[s]) if s >= 0 else float(f)
@@ -102,6 +140,12 @@ def matrix(g, params) -> np.ndarray:
         d = 2 if k == "u1" else 4
         return np.array([complex(a, b) for a, b in g.matrix],
                         dtype=np.complex128).reshape(d, d)
+    if k == "depol":
+        (x,) = gate_angles(g, params)
+        return PAULI[_choice(x, _depol_cuts(g))].copy()
+    if k == "rswitch":
+        t, x = gate_angles(g, params)
+        return _rot(_RSWITCH[_choice(x, _RSWITCH_CUTS)], t)
     raise ValueError(f"unknown gate kind {k!r}")
 
 
@@ -114,6 +158,13 @@ def dmatrix(g, params, which: int) -> np.ndarray:
     if k == "fsim":
         t, p = gate_angles(g, params)
         return _dfsim(t, p, which)
+    if k == "depol":
+        return np.zeros((2, 2), dtype=np.complex128)
+    if k == "rswitch":
+        t, x = gate_angles(g, params)
+        if which == 1:
+            return np.zeros((2, 2), dtype=np.complex128)
+        return _drot(_RSWITCH[_choice(x, _RSWITCH_CUTS)], t)
     raise ValueError(f"gate kind {k!r} has no angle")
 
 

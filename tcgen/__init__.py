@@ -37,7 +37,12 @@ GATE_ARITY = {
     "rzz": (2, 1), "rxx": (2, 1), "ryy": (2, 1),
     "fsim": (2, 2),
     "u2": (2, 0),
+    "depol": (1, 1),      # angle: the status; matrix: (px, py, pz)
+    "rswitch": (1, 2),    # angles: t, the status
 }
+# kinds drawn by random_circuit unless told otherwise (the channels need
+# probabilities or statuses of their own)
+UNITARY_KINDS = [k for k in GATE_ARITY if k not in ("depol", "rswitch")]
 
 
 @dataclass(frozen=True)
@@ -50,8 +55,9 @@ class Gate:
     params  : one entry per angle argument: a slot of the caller's parameter
               vector, or -1 to use the matching entry of ``fixed``.
     fixed   : fixed angles used where ``params`` is -1.
-    matrix  : for "u1"/"u2" only, a complex 2x2 / 4x4 row-major matrix given
-              as a tuple of (re, im) pairs.
+    matrix  : for "u1"/"u2", a complex 2x2 / 4x4 row-major matrix given
+              as a tuple of (re, im) pairs; for "depol", the probabilities
+              (px, py, pz).
     """
     kind: str
     qubits: Tuple[int, ...]
@@ -382,7 +388,7 @@ def random_circuit(n: int, n_gates: int, seed: int,
     Every parameterised angle gets its own slot; u1/u2 get random complex
     matrices (not necessarily unitary)."""
     rng = np.random.default_rng(seed)
-    kinds = list(kinds) if kinds is not None else list(GATE_ARITY)
+    kinds = list(kinds) if kinds is not None else list(UNITARY_KINDS)
     c = Circuit(n, 0)
     p = 0
     for _ in range(n_gates):
