@@ -283,6 +283,37 @@ def qgt_leg(trials=8, steps=20):
             "oracle_seconds": oracle_s}
 
 
+def structures_leg(trials=8, steps=20):
+    """Batched circuit structures (section "Demonstration of barren
+    plateaus", table "bpbench": 10 qubits, 10 layers, 100 circuits, each
+    gate of a layer RX/RY/RZ by a status): the energy <Z0 Z1> and its
+    gradient for all 100 circuits in one launch, and the gradient variance
+    the benchmark is about; the oracle timed on the same 100 rows."""
+    import torch
+    import tcgen
+    from oracle import statevector as sv
+    from paper_2205_10091_amd import api
+    B = 100
+    circ, P, obs = tcgen.workload_barren_plateau(batch=B)
+    plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=trials, seed=1)
+    info = plan.info()
+    par = torch.from_numpy(P.reshape(-1)).to("cuda:0")
+    e_dev = torch.empty(B, dtype=torch.float64, device="cuda:0")
+    g_dev = torch.empty(B * info.n_params, dtype=torch.float64, device="cuda:0")
+    dt, _ = timed(lambda: plan.contract_grad_device(par, e_dev, g_dev), steps, 3)
+    g = g_dev.cpu().numpy().reshape(B, -1)
+    t0 = time.perf_counter()
+    refs = [sv.energy_grad(circ, P[b], obs)[1] for b in range(B)]
+    oracle_s = time.perf_counter() - t0
+    return {"workload": "barren_plateau_n10_L10_100_structures", "batch": B,
+            "seconds_per_launch": dt / steps, "circuits_per_s": B * steps / dt,
+            "grad_variance_theta0": float(np.var(g[:, 0])),
+            "max_abs_err_grad": float(np.max(np.abs(g - np.array(refs)))),
+            "oracle_seconds_100_circuits": oracle_s,
+            "launches": info.n_launches + info.n_grad_launches,
+            "flops": info.flops + info.grad_flops}
+
+
 def golden_amplitude(rows, cols, depth):
     """The stored oracle amplitude of a seeded fSim grid (two independent
     oracle methods, tests/golden/), its methods' seconds, or None."""
@@ -552,6 +583,8 @@ def main():
         out["grid_amplitude"] = grid_leg(6, 6, 8, grid_trials, 50, 5, "grid")
         print("[bench] grid 4x7 depth 16 (wide nodes)", file=sys.stderr, flush=True)
         out["wide_nodes"] = grid_leg(4, 7, 16, grid_trials, 5, 1, "wide")
+        print("[bench] batched circuit structures", file=sys.stderr, flush=True)
+        out["structures"] = structures_leg()
         print("[bench] geometric tensor", file=sys.stderr, flush=True)
         out["qgt"] = qgt_leg()
         print("[bench] MPO vs Pauli-sum energy", file=sys.stderr, flush=True)

@@ -71,6 +71,21 @@ int32_t tc_version(void);
  *   SQRT_X/Y/W = ((1+i)/2) I + ((1-i)/2) G with W = (X+Y)/sqrt 2;
  *   FSIM(t, p) = [[1,0,0,0],[0,cos t,-i sin t,0],[0,-i sin t,cos t,0],
  *                 [0,0,0,exp(-i p)]].
+ * Channels with externalised randomness (sections "Externalizing the
+ * randomness", "Batched Monte Carlo trajectory noise simulation" and
+ * "Demonstration of barren plateaus"): the random number ("status", in
+ * [0,1)) is an angle argument, so a parameter slot per batch row makes each
+ * row one trajectory or one circuit structure.  [0,1) is cut into intervals
+ * in the listed order, and the operator of the interval holding the status
+ * is applied (a unitary: the channel's Kraus operators are multiples of
+ * unitaries).  The cuts are computed and compared in float32.
+ *   DEPOL   angle 0 = status; matrix = 3 doubles (px, py, pz), each >= 0,
+ *           sum <= 1; applies I, X, Y, Z with probabilities
+ *           1 - px - py - pz, px, py, pz (cuts p0 = ((1 - px) - py) - pz,
+ *           p0 + px, (p0 + px) + py).
+ *   RSWITCH angle 0 = t, angle 1 = status; applies RX(t), RY(t), RZ(t) for
+ *           status < 1/3, < 2/3, else.
+ * The gradient of a status is 0 (the choice is piecewise constant).
  */
 typedef enum {
   TC_GATE_H = 0, TC_GATE_X = 1, TC_GATE_Y = 2, TC_GATE_Z = 3, TC_GATE_S = 4,
@@ -80,7 +95,9 @@ typedef enum {
   TC_GATE_CNOT = 12, TC_GATE_CZ = 13,
   TC_GATE_RZZ = 14, TC_GATE_RXX = 15, TC_GATE_RYY = 16,
   TC_GATE_FSIM = 17,                     /* two angles (theta, phi)       */
-  TC_GATE_U2 = 18                        /* caller 4x4 matrix             */
+  TC_GATE_U2 = 18,                       /* caller 4x4 matrix             */
+  TC_GATE_DEPOL = 19,                    /* Monte Carlo depolarizing      */
+  TC_GATE_RSWITCH = 20                   /* RX / RY / RZ chosen per row   */
 } tc_gate_kind;
 
 typedef struct {

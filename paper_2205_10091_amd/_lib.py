@@ -22,7 +22,8 @@ TC_OK, TC_ERR_INVALID_ARG, TC_ERR_UNSUPPORTED, TC_ERR_OUT_OF_MEMORY, \
 
 GATE_KIND = {"h": 0, "x": 1, "y": 2, "z": 3, "s": 4, "sqrt_x": 5, "sqrt_y": 6,
              "sqrt_w": 7, "rx": 8, "ry": 9, "rz": 10, "u1": 11, "cnot": 12,
-             "cz": 13, "rzz": 14, "rxx": 15, "ryy": 16, "fsim": 17, "u2": 18}
+             "cz": 13, "rzz": 14, "rxx": 15, "ryy": 16, "fsim": 17, "u2": 18,
+             "depol": 19, "rswitch": 20}
 
 
 class Gate(C.Structure):

@@ -42,9 +42,22 @@ __device__ __forceinline__ c32 pauli_entry(int g, int o, int i) {
   }
 }
 
-// one-qubit gate entry G[o][i]
-__device__ __forceinline__ c32 gate1(int kind, int o, int i, float t,
+// The operator a status selects (float32 cuts, in the order the header
+// gives): DEPOL -> Pauli 0..3, RSWITCH -> TC_GATE_RX / RY / RZ.
+__device__ __forceinline__ int depol_choice(float status, const float* p) {
+  const float p0 = ((1.f - p[0]) - p[1]) - p[2];
+  const float c1 = p0 + p[0], c2 = c1 + p[1];
+  return status < p0 ? 0 : status < c1 ? 1 : status < c2 ? 2 : 3;
+}
+__device__ __forceinline__ int rswitch_choice(float status) {
+  return status < 1.f / 3.f ? TC_GATE_RX : status < 2.f / 3.f ? TC_GATE_RY : TC_GATE_RZ;
+}
+
+// one-qubit gate entry G[o][i] (t, t1: the gate's angles)
+__device__ __forceinline__ c32 gate1(int kind, int o, int i, float t, float t1,
                                      const float* mat) {
+  if (kind == TC_GATE_DEPOL) return pauli_entry(depol_choice(t, mat), o, i);
+  if (kind == TC_GATE_RSWITCH) kind = rswitch_choice(t1);
   switch (kind) {
     case TC_GATE_H: return cx((o & i) ? -TCX_RSQRT2 : TCX_RSQRT2, 0.f);
     case TC_GATE_X: return pauli_entry(1, o, i);
@@ -88,7 +101,8 @@ __device__ __forceinline__ c32 gate1(int kind, int o, int i, float t,
   return cx(0.f, 0.f);
 }
 
-__device__ __forceinline__ c32 dgate1(int kind, int o, int i, float t) {
+__device__ __forceinline__ c32 dgate1(int kind, int o, int i, float t, float t1) {
+  if (kind == TC_GATE_RSWITCH) kind = rswitch_choice(t1);  // (a DEPOL status: 0)
   float s, c;
   sincosf(0.5f * t, &s, &c);
   switch (kind) {
@@ -230,7 +244,7 @@ __device__ __forceinline__ c32 leaf_entry(const DevLeaf& L, int e, float t0, flo
     default:
       if (L.part == 0) {
         if (L.rank == 2)
-          v = gate1(L.gkind, e >> 1, e & 1, t0, ftab + L.mat);
+          v = gate1(L.gkind, e >> 1, e & 1, t0, t1, ftab + L.mat);
         else
           v = gate2(L.gkind, e >> 2, e & 3, t0, t1, ftab + L.mat);
       } else {
@@ -246,7 +260,7 @@ __device__ __forceinline__ c32 dleaf_entry(const DevLeaf& L, int e, float t0, fl
   c32 v;
   if (L.part == 0) {
     if (L.rank == 2)
-      v = dgate1(L.gkind, e >> 1, e & 1, t0);
+      v = which == 0 ? dgate1(L.gkind, e >> 1, e & 1, t0, t1) : cx(0.f, 0.f);
     else
       v = dgate2(L.gkind, e >> 2, e & 3, t0, t1, which);
   } else {

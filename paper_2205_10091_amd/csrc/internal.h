@@ -32,6 +32,7 @@ struct GateRec {
 int gate_qubits(int kind);   // 1 or 2; 0 for unknown kinds
 int gate_angles(int kind);   // number of angle arguments
 bool gate_splittable(int kind);
+bool gate_angle_differentiable(int kind, int angle);
 bool gate_diagonal(int kind);   // diagonal in the computational basis
 
 // ---------------------------------------------------------------- network

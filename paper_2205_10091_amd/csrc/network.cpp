@@ -24,7 +24,7 @@ int gate_qubits(int kind) {
     case TC_GATE_H: case TC_GATE_X: case TC_GATE_Y: case TC_GATE_Z:
     case TC_GATE_S: case TC_GATE_SQRT_X: case TC_GATE_SQRT_Y:
     case TC_GATE_SQRT_W: case TC_GATE_RX: case TC_GATE_RY: case TC_GATE_RZ:
-    case TC_GATE_U1:
+    case TC_GATE_U1: case TC_GATE_DEPOL: case TC_GATE_RSWITCH:
       return 1;
     case TC_GATE_CNOT: case TC_GATE_CZ: case TC_GATE_RZZ: case TC_GATE_RXX:
     case TC_GATE_RYY: case TC_GATE_FSIM: case TC_GATE_U2:
@@ -37,13 +37,18 @@ int gate_qubits(int kind) {
 int gate_angles(int kind) {
   switch (kind) {
     case TC_GATE_RX: case TC_GATE_RY: case TC_GATE_RZ: case TC_GATE_RZZ:
-    case TC_GATE_RXX: case TC_GATE_RYY:
+    case TC_GATE_RXX: case TC_GATE_RYY: case TC_GATE_DEPOL:
       return 1;
-    case TC_GATE_FSIM:
+    case TC_GATE_FSIM: case TC_GATE_RSWITCH:
       return 2;
     default:
       return 0;
   }
+}
+
+bool gate_angle_differentiable(int kind, int a) {
+  // a status chooses an operator: piecewise constant
+  return !(kind == TC_GATE_DEPOL && a == 0) && !(kind == TC_GATE_RSWITCH && a == 1);
 }
 
 bool gate_diagonal(int kind) {
@@ -110,6 +115,17 @@ std::vector<GateRec> intake(const tc_circuit* c) {
       r.fixed[a] = g.fixed[a];
       if (r.param[a] < 0 && !std::isfinite(r.fixed[a]))
         fail(TC_ERR_INVALID_ARG, "gate " + std::to_string(i) + ": non-finite angle");
+    }
+    if (g.kind == TC_GATE_DEPOL) {
+      if (!g.matrix) fail(TC_ERR_INVALID_ARG, "gate " + std::to_string(i) + ": probabilities are NULL");
+      double sum = 0;
+      for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(g.matrix[k]) || g.matrix[k] < 0)
+          fail(TC_ERR_INVALID_ARG, "gate " + std::to_string(i) + ": bad probability");
+        r.mat[k] = g.matrix[k];
+        sum += g.matrix[k];
+      }
+      if (sum > 1.0) fail(TC_ERR_INVALID_ARG, "gate " + std::to_string(i) + ": probabilities exceed 1");
     }
     if (g.kind == TC_GATE_U1 || g.kind == TC_GATE_U2) {
       if (!g.matrix) fail(TC_ERR_INVALID_ARG, "gate " + std::to_string(i) + ": matrix is NULL");
@@ -215,7 +231,7 @@ Network build_network(const tc_circuit* c, const tc_observable* o,
       std::memcpy(&bits, &g.fixed[a], 8);
       if (g.param[a] < 0) h = hash_mix(h, bits);
     }
-    if (g.kind == TC_GATE_U1 || g.kind == TC_GATE_U2)
+    if (g.kind == TC_GATE_U1 || g.kind == TC_GATE_U2 || g.kind == TC_GATE_DEPOL)
       for (int k = 0; k < 32; ++k) {
         uint64_t bits;
         std::memcpy(&bits, &g.mat[k], 8);

@@ -577,7 +577,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       for (const Leaf& lf : term.leaves)
         if (lf.kind == LEAF_GATE && !lf.conj && leaf_param_dependent(net, lf)) {
           const GateRec& g = net.gates[lf.gate];
-          for (int a = 0; a < g.n_angles; ++a) u += g.param[a] >= 0;
+          for (int a = 0; a < g.n_angles; ++a)
+            u += g.param[a] >= 0 && gate_angle_differentiable(g.kind, a);
         }
     plan.qgt_rows = u;
     plan.batch = std::max(u, 1);
@@ -1223,7 +1224,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         for (int a = 0; a < g.n_angles; ++a) {
           d.param[a] = g.param[a];
           d.fixed[a] = (float)g.fixed[a];
-          if (plan.qgt && !lf.conj && leaf_param_dependent(net, lf) && g.param[a] >= 0) {
+          if (plan.qgt && !lf.conj && leaf_param_dependent(net, lf) && g.param[a] >= 0 &&
+              gate_angle_differentiable(g.kind, a)) {
             d.dsel[a] = (int32_t)qrow_slot.size();  // this use's row
             qrow_slot.push_back(g.param[a]);
           }
@@ -1231,6 +1233,9 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         if (g.kind == TC_GATE_U1 || g.kind == TC_GATE_U2) {
           d.mat = (uint32_t)plan.ftab.size();
           for (int k = 0; k < 32; ++k) plan.ftab.push_back((float)g.mat[k]);
+        } else if (g.kind == TC_GATE_DEPOL) {
+          d.mat = (uint32_t)plan.ftab.size();  // px, py, pz
+          for (int k = 0; k < 3; ++k) plan.ftab.push_back((float)g.mat[k]);
         }
       } else if (lf.kind == LEAF_MPO) {
         // a constant tensor: its (padded) entries in the float table
@@ -1303,7 +1308,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       const GateRec& g = net.gates[lf.gate];
       const PT& d = T[S.leaf_adj[u].second];
       for (int a = 0; a < g.n_angles; ++a) {
-        if (g.param[a] < 0) continue;
+        if (g.param[a] < 0 || !gate_angle_differentiable(g.kind, a)) continue;
         DevGradUse gu{};
         gu.adj = (uint64_t)d.off;
         gu.adj_bs = (d.batched && B > 1) ? (uint32_t)d.elems : 0u;
@@ -1359,7 +1364,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           d.rank > MAX_LEAF_RANK)
         fail(TC_ERR_INVALID_ARG, "internal: leaf out of range");
       const uint64_t nf = d.kind == DLEAF_MPO ? (uint64_t)2 << d.rank
-                          : (d.kind == DLEAF_GATE && (d.gkind == TC_GATE_U1 || d.gkind == TC_GATE_U2)) ? 32 : 0;
+                          : (d.kind == DLEAF_GATE && (d.gkind == TC_GATE_U1 || d.gkind == TC_GATE_U2)) ? 32
+                          : (d.kind == DLEAF_GATE && d.gkind == TC_GATE_DEPOL) ? 3 : 0;
       if (nf && (uint64_t)d.mat + nf > plan.ftab.size())
         fail(TC_ERR_INVALID_ARG, "internal: leaf table out of range");
     }

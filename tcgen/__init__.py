@@ -171,6 +171,53 @@ def qfi_blocks(n: int, blocks: int) -> Circuit:
     return c
 
 
+def noisy_ladder(n: int, layers: int, probs=(0.2, 0.2, 0.2)):
+    """The RZZ-ladder + RX ansatz with a depolarizing channel on every qubit
+    after each layer (section "Batched Monte Carlo trajectory noise
+    simulation").  Slots: the ansatz's params[L][2][n], then one status per
+    channel (layer-major).  Returns (circuit, index of the first status)."""
+    c = chain_ladder(n, layers)
+    first = c.n_params
+    gates = []
+    per_layer = (n - 1) + n
+    for l in range(layers):
+        gates += c.gates[l * per_layer:(l + 1) * per_layer]
+        for q in range(n):
+            gates.append(Gate("depol", (q,), (first + l * n + q,), (0.0,), tuple(probs)))
+    return Circuit(n, first + layers * n, gates), first
+
+
+def workload_trajectories(batch: int = 64, n: int = 6, layers: int = 2, seed: int = 8):
+    """`batch` Monte Carlo trajectories of the noisy ladder: every row the
+    same circuit weights and its own statuses ~ U[0,1); observable X on the
+    middle qubit (the paper's example loss)."""
+    circ, first = noisy_ladder(n, layers)
+    w = draw_angles(seed, (first,))
+    st = np.random.default_rng(seed + 1).uniform(0.0, 1.0, size=(batch, circ.n_params - first))
+    P = np.concatenate([np.tile(w, (batch, 1)), st.astype(np.float32)], axis=1)
+    return circ, np.ascontiguousarray(P, np.float32), pauli_string(n, x=(n // 2,))
+
+
+def workload_barren_plateau(batch: int = 100, n: int = 10, layers: int = 10, seed: int = 9):
+    """The barren-plateau benchmark of section "Demonstration of barren
+    plateaus" (table "bpbench": 10 qubits, 10 layers, 100 circuits): each
+    layer applies on every qubit one of RX, RY, RZ chosen by a status, then
+    CZ on the chain; every row has its own weights ~ U[0, 2 pi) and
+    statuses ~ U[0,1).  Slots: weights[q][l] then statuses[q][l].
+    Observable Z0 Z1."""
+    c = Circuit(n, 2 * n * layers)
+    for l in range(layers):
+        for q in range(n):
+            c.add("rswitch", (q,), (q * layers + l, n * layers + q * layers + l))
+        for q in range(n - 1):
+            c.add("cz", (q, q + 1))
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.0, TWO_PI, size=(batch, n * layers))
+    st = rng.uniform(0.0, 1.0, size=(batch, n * layers))
+    P = np.concatenate([w, st], axis=1).astype(np.float32)
+    return c, np.ascontiguousarray(P), pauli_string(n, z=(0, 1))
+
+
 def tfim_mpo(n: int, g: float = 1.0, j: float = 1.0) -> Observable:
     """The open-chain TFIM operator j sum_i Z_i Z_{i+1} + g sum_i X_i as a
     matrix product operator of bond dimension 3 (the input the section

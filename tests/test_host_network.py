@@ -128,6 +128,22 @@ def test_mpo_network_through_exported_leaves(split, absorb):
     assert abs(got - sv.energy(circ, params, m)) < 1e-12 * max(1.0, abs(got))
 
 
+def test_channel_gates_through_exported_network():
+    """Depolarizing and RX/RY/RZ-choice gates, statuses as parameters: the
+    exported leaves, contracted in numpy, give the oracle's values."""
+    circ, first = tcgen.noisy_ladder(5, 2)
+    circ.add("rswitch", (2,), (0, first + 1))
+    obs = tcgen.tfim_zz_x(5, 0.6)
+    for seed in range(3):
+        p = tcgen.draw_angles(seed, (circ.n_params,)).astype(np.float64)
+        p[first:] = np.random.default_rng(seed).uniform(0, 1, circ.n_params - first)
+        net = api.Network(circ, obs)
+        path = api.Path(net, n_trials=2, seed=seed)
+        want = sv.term_values(circ, p, obs)
+        for j in range(len(want)):
+            assert abs(contract_along_path(net, path, circ, p, j) - want[j]) < 1e-12
+
+
 def test_mpo_observable_errors():
     circ = tcgen.chain_ladder(4, 1)
     ok = tcgen.tfim_mpo(4, 1.0)

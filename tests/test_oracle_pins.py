@@ -149,7 +149,7 @@ def test_hadamard_layer_amplitudes(n):
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_unit_norm_through_identity_observable(seed):
     c = tcgen.random_circuit(6, 40, seed,
-                             kinds=[k for k in tcgen.GATE_ARITY if k not in ("u1", "u2")])
+                             kinds=[k for k in tcgen.UNITARY_KINDS if k not in ("u1", "u2")])
     p = np.random.default_rng(seed).uniform(0, 2 * math.pi, c.n_params)
     ident = tcgen.pauli_string(6)
     assert close(sv.energy(c, p, ident), 1.0, 1e-13)
