@@ -326,7 +326,7 @@ def golden_amplitude(rows, cols, depth):
     return complex(v["re"], v["im"]), {k: x.get("seconds") for k, x in ref["values"].items()}
 
 
-def grid_leg(rows, cols, depth, trials, steps, warmup, workload):
+def grid_leg(rows, cols, depth, trials, steps, warmup, workload, reconf_k=0):
     """A seeded fSim grid amplitude in FP32 and in split BF16 (wide nodes):
     evaluations/s, achieved TFLOP/s, the dominant kernel's roofline and the
     error against the stored oracle amplitude, floored at 2^(-n/2) (the RMS
@@ -338,10 +338,11 @@ def grid_leg(rows, cols, depth, trials, steps, warmup, workload):
     n = rows * cols
     ref, oracle_s = golden_amplitude(rows, cols, depth)
     params = torch.from_numpy(p).to("cuda:0")
-    res, vals = {"workload": f"grid{rows}x{cols}_d{depth}_amplitude", "n_qubits": n}, {}
+    res, vals = {"workload": f"grid{rows}x{cols}_d{depth}_amplitude", "n_qubits": n,
+                 "reconf_k": reconf_k}, {}
     for prec, key in ((0, "fp32"), (1, "bf16x3")):
         t0 = time.perf_counter()
-        plan = api.compile(circ, amp, n_trials=trials, seed=1, precision=prec)
+        plan = api.compile(circ, amp, n_trials=trials, seed=1, precision=prec, reconf_k=reconf_k)
         plan_s = time.perf_counter() - t0
         info = plan.info()
         out = torch.empty(2, dtype=torch.float64, device="cuda:0")
@@ -583,6 +584,9 @@ def main():
         out["grid_amplitude"] = grid_leg(6, 6, 8, grid_trials, 50, 5, "grid")
         print("[bench] grid 4x7 depth 16 (wide nodes)", file=sys.stderr, flush=True)
         out["wide_nodes"] = grid_leg(4, 7, 16, grid_trials, 5, 1, "wide")
+        # the same grid on a subtree-reconfigured tree (10x fewer flops)
+        print("[bench] grid 4x7 depth 16, reconfigured tree", file=sys.stderr, flush=True)
+        out["wide_nodes_reconfigured"] = grid_leg(4, 7, 16, grid_trials, 10, 1, "wide", reconf_k=8)
         print("[bench] batched circuit structures", file=sys.stderr, flush=True)
         out["structures"] = structures_leg()
         print("[bench] geometric tensor", file=sys.stderr, flush=True)

@@ -245,6 +245,11 @@ typedef struct {
   int32_t n_trials;      /* >= 1                                          */
   int32_t score;         /* tc_score                                      */
   double temperature;    /* noise scale for trials after the first        */
+  int32_t reconf_k;      /* 0 = off; 3..10: subtree reconfiguration of the
+                            chosen tree, frontiers of up to reconf_k inputs
+                            re-contracted optimally (exact dynamic program
+                            over subsets, flops/8 + 64 write), kept when
+                            the score improves                           */
 } tc_path_opts;
 
 tc_status tc_greedy_path(const tc_network* net, const tc_path_opts* opts,
@@ -256,6 +261,23 @@ tc_status tc_greedy_path(const tc_network* net, const tc_path_opts* opts,
 tc_status tc_path_replace_term(tc_path* base, int32_t term,
                                const int32_t* pairs, int32_t n_steps);
 void tc_path_free(tc_path* path);
+
+/* tc_slice: a network contracted as a sum of smaller ones (section
+ * "Outlook and concluding remarks": slicing, to go past memory limits and
+ * to spread one contraction over devices).  For every term whose tree in
+ * `path` has an intermediate above 2^max_log2_size elements, bond labels
+ * are chosen on that tree (the label carried by the most of its largest
+ * intermediates, repeatedly) until every intermediate fits; the term then
+ * becomes 2^s terms of the same weight, each with the s bonds cut and
+ * capped by the basis vectors of one assignment of their values, and its
+ * path is the original tree with the caps absorbed first.  Contracting the
+ * new network (with the new path) gives the same value and gradient.
+ * Returns a new network and path (library-owned, freed with *_free) and
+ * the largest s over the terms.  TOO_LARGE if more than max_labels (<= 16)
+ * labels would be needed; INVALID_ARG for a path of another network. */
+tc_status tc_slice(const tc_network* net, const tc_path* path, int32_t max_log2_size,
+                   int32_t max_labels, tc_network** out_net, tc_path** out_path,
+                   int32_t* n_sliced_labels);
 
 typedef struct {
   double log10_flops;    /* over all terms                                */
@@ -501,8 +523,12 @@ tc_status tc_plan_profile(tc_plan* plan, const float* params, int32_t which,
  * structure and observable; each request gets its own region of the pool.
  *
  *   tc_serve_submit  copies the request; params are HOST floats
- *                    (n_params); returns an id.  TOO_LARGE if the request
- *                    alone exceeds max_request_bytes (it is not queued).
+ *                    (n_params); returns an id.  A request whose plan does
+ *                    not fit max_request_bytes even with its terms in
+ *                    groups is sliced (tc_slice, every intermediate within
+ *                    an eighth of the cap) and its slices run as terms.
+ *                    TOO_LARGE if it still does not fit, or needs more
+ *                    than max_request_flops (it is not queued).
  *   tc_serve_step    admits what fits, launches one step for every live
  *                    request, and collects finished ones; *n_live receives
  *                    the number still queued or running.
@@ -520,6 +546,8 @@ typedef struct {
   int32_t max_active;         /* live request slots                       */
   int32_t path_trials;        /* greedy trials per new structure          */
   void* stream;               /* hipStream_t, NULL = own stream           */
+  double max_request_flops;   /* 0 = no limit; else requests whose plan
+                                 needs more flops are rejected (TOO_LARGE) */
 } tc_serve_opts;
 
 typedef struct {

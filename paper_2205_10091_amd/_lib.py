@@ -57,7 +57,8 @@ class NetworkInfo(C.Structure):
 
 class PathOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_trials", C.c_int32),
-                ("score", C.c_int32), ("temperature", C.c_double)]
+                ("score", C.c_int32), ("temperature", C.c_double),
+                ("reconf_k", C.c_int32)]
 
 
 class PathStats(C.Structure):
@@ -94,7 +95,8 @@ class PlanInfo(C.Structure):
 class ServeOpts(C.Structure):
     _fields_ = [("device", C.c_int32), ("pool_bytes", C.c_uint64),
                 ("max_request_bytes", C.c_uint64), ("max_active", C.c_int32),
-                ("path_trials", C.c_int32), ("stream", C.c_void_p)]
+                ("path_trials", C.c_int32), ("stream", C.c_void_p),
+                ("max_request_flops", C.c_double)]
 
 
 class ServeResult(C.Structure):
@@ -125,6 +127,7 @@ SIGNATURES = [
     ("tc_greedy_path", C.c_int, [VP, C.POINTER(PathOpts), PVP]),
     ("tc_path_replace_term", C.c_int, [VP, C.c_int32, I32P, C.c_int32]),
     ("tc_path_free", None, [VP]),
+    ("tc_slice", C.c_int, [VP, VP, C.c_int32, C.c_int32, PVP, PVP, I32P]),
     ("tc_path_stats_get", C.c_int, [VP, C.c_int32, C.POINTER(PathStats)]),
     ("tc_path_term_pairs", C.c_int, [VP, C.c_int32, I32P, I32P]),
     ("tc_plan_create", C.c_int, [VP, VP, C.POINTER(PlanOpts), PVP]),

@@ -119,9 +119,9 @@ class Network:
 class Path:
     """Owns a tc_path*."""
 
-    def __init__(self, net: Network, seed=0, n_trials=1, score=3, temperature=0.1):
+    def __init__(self, net: Network, seed=0, n_trials=1, score=3, temperature=0.1, reconf_k=0):
         self.net = net
-        opts = L.PathOpts(seed, n_trials, score, temperature)
+        opts = L.PathOpts(seed, n_trials, score, temperature, reconf_k)
         h = C.c_void_p()
         L.check(lib().tc_greedy_path(net.h, C.byref(opts), C.byref(h)))
         self.h = h
@@ -146,6 +146,19 @@ class Path:
         L.check(lib().tc_path_term_pairs(self.h, term, out.ctypes.data_as(L.I32P),
                                          C.byref(n)))
         return out[:2 * n.value].reshape(-1, 2)
+
+    def sliced(self, max_log2_size: int, max_labels: int = 16):
+        """tc_slice: (network, path, s) for the sum over slices whose
+        intermediates fit 2^max_log2_size elements."""
+        hn, hp = C.c_void_p(), C.c_void_p()
+        s = C.c_int32()
+        L.check(lib().tc_slice(self.net.h, self.h, int(max_log2_size), int(max_labels),
+                               C.byref(hn), C.byref(hp), C.byref(s)))
+        net = Network.__new__(Network)
+        net.circ, net.h = self.net.circ, hn
+        path = Path.__new__(Path)
+        path.net, path.h = net, hp
+        return net, path, s.value
 
     def replace_term(self, term: int, pairs):
         p = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1)
@@ -281,11 +294,11 @@ def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
             lightcone=True, absorb_1q=True, seed=0, n_trials=8,
             mem_budget_bytes=0, device=0, bind=True, gemm_min_k=0, stream=None,
             checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0,
-            score=3, qgt=False) -> Plan:
+            score=3, qgt=False, reconf_k=0) -> Plan:
     """Network + greedy path + plan (+ bind with a torch workspace).
     score: the path score of tc_greedy_path (3 combo, 4 time estimate)."""
     net = Network(circ, obs, split_2q, lightcone, absorb_1q)
-    path = Path(net, seed=seed, n_trials=n_trials, score=score)
+    path = Path(net, seed=seed, n_trials=n_trials, score=score, reconf_k=reconf_k)
     torch_stream = None
     if stream is None and bind:
         # a dedicated torch stream (default priority): torch work orders

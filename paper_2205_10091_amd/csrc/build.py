@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libtcx.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HOST = ["network.cpp", "path.cpp", "plan.cpp", "capi_host.cpp"]
+HOST = ["network.cpp", "path.cpp", "plan.cpp", "slice.cpp", "capi_host.cpp"]
 DEVICE = ["exec.hip", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

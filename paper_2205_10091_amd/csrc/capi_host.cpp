@@ -120,10 +120,11 @@ tc_status tc_greedy_path(const tc_network* net, const tc_path_opts* opts,
                          tc_path** out) {
   TC_GUARD_BEGIN
   if (!net || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
-  tc_path_opts o{0, 1, TC_SCORE_COMBO, 0.1};
+  tc_path_opts o{0, 1, TC_SCORE_COMBO, 0.1, 0};
   if (opts) o = *opts;
   if (o.n_trials < 1) tcx::fail(TC_ERR_INVALID_ARG, "n_trials must be >= 1");
   if (o.score < 0 || o.score > 4) tcx::fail(TC_ERR_INVALID_ARG, "unknown score");
+  if (o.reconf_k < 0 || o.reconf_k > 10) tcx::fail(TC_ERR_INVALID_ARG, "reconf_k must be 0..10");
   auto* p = new tc_path;
   p->path = tcx::greedy_path(net->net, o);
   p->terms = net->net.terms;
@@ -148,6 +149,29 @@ tc_status tc_path_replace_term(tc_path* base, int32_t term,
 }
 
 void tc_path_free(tc_path* path) { delete path; }
+
+tc_status tc_slice(const tc_network* net, const tc_path* path, int32_t max_log2_size,
+                   int32_t max_labels, tc_network** out_net, tc_path** out_path,
+                   int32_t* n_sliced_labels) {
+  TC_GUARD_BEGIN
+  if (!net || !path || !out_net || !out_path) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
+  auto* n = new tc_network;
+  auto* p = new tc_path;
+  int32_t s = 0;
+  try {
+    tcx::slice_network(net->net, path->path, max_log2_size, max_labels, n->net, p->path, s);
+  } catch (...) {
+    delete n;
+    delete p;
+    throw;
+  }
+  p->terms = n->net.terms;
+  *out_net = n;
+  *out_path = p;
+  if (n_sliced_labels) *n_sliced_labels = s;
+  return TC_OK;
+  TC_GUARD_END
+}
 
 tc_status tc_path_stats_get(const tc_path* path, int32_t term, tc_path_stats* out) {
   TC_GUARD_BEGIN

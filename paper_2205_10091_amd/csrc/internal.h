@@ -106,4 +106,10 @@ std::vector<std::vector<int32_t>> ssa_legs(const Term& term, const TermPath& tp)
 
 uint64_t hash_mix(uint64_t h, uint64_t v);
 
+// Slicing (slice.cpp): every term whose tree has an intermediate above
+// 2^max_log2 elements becomes 2^s terms with s bond labels fixed, and the
+// path of each is the original tree; max_sliced receives the largest s.
+void slice_network(const Network& net, const Path& path, int32_t max_log2, int32_t max_labels,
+                   Network& out_net, Path& out_path, int32_t& max_sliced);
+
 }  // namespace tcx

@@ -11,6 +11,8 @@
 // engine"): contract the connected pair minimising
 // size(out) - size(a) - size(b).
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <atomic>
 #include <exception>
 #include <mutex>
@@ -216,6 +218,193 @@ double score_of(const TreeStats& s, int score) {
       return s.flops * 1e-13 + s.write * 8.0 / 2e12 + s.depth * 6e-6;
     default: return s.flops / 8.0 + 64.0 * s.write;
   }
+}
+
+std::vector<std::vector<int32_t>> ssa_legs_of(const Term& term, const TermPath& tp) {
+  std::vector<std::vector<int32_t>> legs;
+  for (const Leaf& lf : term.leaves) legs.emplace_back(lf.legs, lf.legs + lf.rank);
+  for (auto& p : tp.pairs) legs.push_back(result_legs(legs[p.first], legs[p.second]));
+  return legs;
+}
+
+// ---- subtree reconfiguration
+//
+// Section "Custom contraction settings" compares path finders by FLOPs,
+// WRITE and SIZE (the contractor table, where reconfigured trees from the
+// hyper-optimising finder it cites do best).  Here, from scratch: for each
+// internal node of a tree, its subtree is opened up to a frontier of at
+// most k inputs (expanding the frontier's largest internal node first);
+// the cheapest binary tree over those inputs that yields the node's legs is
+// found exactly by dynamic programming over input subsets (cost of a step:
+// 2^|union of its operands' legs| + 64 * 2^|its result's legs|, i.e.
+// flops / 8 + 64 * write), and replaces the subtree when cheaper.  Legs are
+// tracked as bitsets over the frontier's labels.
+struct RNode {
+  int32_t a = -1, b = -1;        // children (-1: a leaf)
+  std::vector<int32_t> legs;
+};
+
+using Bits = std::array<uint64_t, 8>;  // up to 512 labels in one frontier
+
+inline int bits_count(const Bits& x) {
+  int c = 0;
+  for (uint64_t w : x) c += __builtin_popcountll(w);
+  return c;
+}
+
+double rstep(int union_legs, int out_legs) {
+  return std::ldexp(1.0, union_legs) + 64.0 * std::ldexp(1.0, out_legs);
+}
+
+// Re-optimises the region of `v` (a node with children); true if changed.
+bool reconf_node(std::vector<RNode>& nodes, int32_t v, int k) {
+  std::vector<int32_t> front{nodes[v].a, nodes[v].b};
+  std::vector<int32_t> inner{v};
+  while ((int)front.size() < k) {
+    int best = -1;
+    for (int i = 0; i < (int)front.size(); ++i)
+      if (nodes[front[i]].a >= 0 &&
+          (best < 0 || nodes[front[i]].legs.size() > nodes[front[best]].legs.size()))
+        best = i;
+    if (best < 0) break;
+    const int32_t x = front[best];
+    inner.push_back(x);
+    front[best] = nodes[x].a;
+    front.push_back(nodes[x].b);
+  }
+  const int m = (int)front.size();
+  if (m < 3) return false;
+  // local labels
+  std::vector<int32_t> labels;
+  for (int32_t f : front)
+    for (int32_t l : nodes[f].legs)
+      if (std::find(labels.begin(), labels.end(), l) == labels.end()) labels.push_back(l);
+  if (labels.size() > 512) return false;
+  auto idx = [&](int32_t l) { return (int)(std::find(labels.begin(), labels.end(), l) - labels.begin()); };
+  std::vector<Bits> in(m, Bits{});
+  for (int i = 0; i < m; ++i)
+    for (int32_t l : nodes[front[i]].legs) {
+      const int j = idx(l);
+      in[i][j >> 6] |= uint64_t(1) << (j & 63);
+    }
+  Bits out{};
+  for (int32_t l : nodes[v].legs) {
+    const int j = idx(l);
+    if (j < (int)labels.size()) out[j >> 6] |= uint64_t(1) << (j & 63);
+  }
+  // legs of every subset: a label stays open if it is an output label or
+  // also touches an input outside the subset
+  const uint32_t full = (1u << m) - 1;
+  std::vector<Bits> lg(full + 1, Bits{});
+  for (uint32_t S = 1; S <= full; ++S) {
+    Bits touch{}, outside{};
+    for (int i = 0; i < m; ++i)
+      for (int w = 0; w < 8; ++w) (((S >> i) & 1) ? touch : outside)[w] |= in[i][w];
+    for (int w = 0; w < 8; ++w) lg[S][w] = touch[w] & (outside[w] | out[w]);
+  }
+  std::vector<double> cost(full + 1, 0.0);
+  std::vector<uint32_t> split(full + 1, 0);
+  for (uint32_t S = 1; S <= full; ++S) {
+    if (!(S & (S - 1))) continue;
+    const uint32_t low = S & (~S + 1);
+    double best = -1;
+    // A holds the lowest input (each split once)
+    for (uint32_t A = (S - 1) & S; A; A = (A - 1) & S) {
+      if (!(A & low)) continue;
+      const uint32_t Bs = S ^ A;
+      Bits u;
+      for (int w = 0; w < 8; ++w) u[w] = lg[A][w] | lg[Bs][w];
+      const double c = cost[A] + cost[Bs] + rstep(bits_count(u), bits_count(lg[S]));
+      if (best < 0 || c < best) {
+        best = c;
+        split[S] = A;
+      }
+    }
+    cost[S] = best;
+  }
+  // the region's current cost
+  double now = 0;
+  for (int32_t x : inner) {
+    const RNode& n = nodes[x];
+    std::vector<int32_t> u = nodes[n.a].legs;
+    for (int32_t l : nodes[n.b].legs)
+      if (std::find(u.begin(), u.end(), l) == u.end()) u.push_back(l);
+    now += rstep((int)u.size(), (int)n.legs.size());
+  }
+  if (cost[full] >= now * (1.0 - 1e-9)) return false;
+  // rebuild: the region's inner nodes are reused for the new internal
+  // nodes (m - 1 of them, the same count), v stays the region's top
+  std::vector<int32_t> pool(inner.begin() + 1, inner.end());
+  std::function<int32_t(uint32_t, int32_t)> build = [&](uint32_t S, int32_t at) -> int32_t {
+    if (!(S & (S - 1))) return front[__builtin_ctz(S)];
+    int32_t id = at;
+    if (id < 0) {
+      id = pool.back();
+      pool.pop_back();
+    }
+    const uint32_t A = split[S];
+    const int32_t ca = build(A, -1), cb = build(S ^ A, -1);
+    nodes[id].a = ca;
+    nodes[id].b = cb;
+    nodes[id].legs.clear();
+    for (int j = 0; j < (int)labels.size(); ++j)
+      if ((lg[S][j >> 6] >> (j & 63)) & 1) nodes[id].legs.push_back(labels[j]);
+    return id;
+  };
+  std::vector<int32_t> keep_legs = nodes[v].legs;
+  build(full, v);
+  nodes[v].legs = keep_legs;  // (the same set; keep the original order)
+  return true;
+}
+
+TermPath reconfigure(const Term& term, const TermPath& tp, int k, int passes) {
+  const int32_t nl = (int32_t)term.leaves.size();
+  if ((int32_t)tp.pairs.size() < 2) return tp;
+  std::vector<std::vector<int32_t>> legs = ssa_legs_of(term, tp);
+  std::vector<RNode> nodes(legs.size());
+  for (size_t i = 0; i < legs.size(); ++i) nodes[i].legs = legs[i];
+  for (size_t s = 0; s < tp.pairs.size(); ++s) {
+    nodes[nl + s].a = tp.pairs[s].first;
+    nodes[nl + s].b = tp.pairs[s].second;
+  }
+  const int32_t root = nl + (int32_t)tp.pairs.size() - 1;
+  for (int p = 0; p < passes; ++p) {
+    // internal nodes, children before parents
+    std::vector<int32_t> order;
+    std::vector<int32_t> st{root};
+    while (!st.empty()) {
+      const int32_t x = st.back();
+      st.pop_back();
+      if (nodes[x].a < 0) continue;
+      order.push_back(x);
+      st.push_back(nodes[x].a);
+      st.push_back(nodes[x].b);
+    }
+    std::reverse(order.begin(), order.end());
+    bool changed = false;
+    for (int32_t x : order) changed |= reconf_node(nodes, x, k);
+    if (!changed) break;
+  }
+  // SSA pairs in post order
+  TermPath out;
+  out.n_leaves = nl;
+  std::vector<int32_t> ssa(nodes.size(), -1);
+  for (int32_t i = 0; i < nl; ++i) ssa[i] = i;
+  std::vector<std::pair<int32_t, bool>> st{{root, false}};
+  while (!st.empty()) {
+    auto [x, done] = st.back();
+    st.pop_back();
+    if (nodes[x].a < 0) continue;
+    if (!done) {
+      st.push_back({x, true});
+      st.push_back({nodes[x].b, false});
+      st.push_back({nodes[x].a, false});
+    } else {
+      out.pairs.push_back({ssa[nodes[x].a], ssa[nodes[x].b]});
+      ssa[x] = nl + (int32_t)out.pairs.size() - 1;
+    }
+  }
+  return out;
 }
 
 }  // namespace
@@ -431,6 +620,11 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
           best_score = sc;
         }
       }
+    }
+    if (opts.reconf_k >= 3 && best.pairs.size() >= 2) {
+      TermPath r = reconfigure(term, best, std::min(opts.reconf_k, 10), 4);
+      const TreeStats st = tree_stats(term, r);
+      if (st.size <= std::ldexp(1.0, 31) && score_of(st, opts.score) < best_score) best = std::move(r);
     }
     path.terms.push_back(std::move(best));
   }

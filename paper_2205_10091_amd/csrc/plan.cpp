@@ -678,7 +678,9 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     // smallest arena over a few segment lengths
     Schedule best;
     int best_c = 0;
-    for (int c : {2, 3, 4, 6, 8, 12}) {
+    // (segments of about sqrt(levels) keep the fewest values for deep
+    // trees, so longer segments are tried as well)
+    for (int c : {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128}) {
       if (c > std::max(2, S.max_level / 2)) break;
       Schedule t;
       schedule(t, plan, net, path, B, grad, c, false);

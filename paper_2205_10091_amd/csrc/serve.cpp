@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -326,9 +327,9 @@ tc_status tc_serve_submit(tc_server* srv, const tc_circuit* circuit,
     if (it != S.cache.end()) plan = it->second;
   }
   if (!plan) {
-    tc_path_opts po{0x5eed, S.opts.path_trials, TC_SCORE_COMBO, 0.1};
+    tc_path_opts po{0x5eed, S.opts.path_trials, TC_SCORE_COMBO, 0.1, 0};
     tcx::Path path = tcx::greedy_path(net, po);
-    auto make = [&](int32_t wide_tiles) {
+    auto make = [&](int32_t wide_tiles, const tcx::Network& nw, const tcx::Path& pa) {
       auto p = std::make_shared<tcx::Plan>();
       p->batch = 1;
       p->want_grad = req->want_grad;
@@ -336,17 +337,59 @@ tc_status tc_serve_submit(tc_server* srv, const tc_circuit* circuit,
       p->budget = S.opts.max_request_bytes;
       p->exec_mode = 1;  // requests advance one level per engine step
       p->wide_tiles = wide_tiles;
-      tcx::build_plan(*p, net, path);  // TOO_LARGE when over the per-request cap
+      tcx::build_plan(*p, nw, pa);  // TOO_LARGE when over the per-request cap
       return p;
     };
+    auto fit = [&](const tcx::Network& nw, const tcx::Path& pa) {
+      try {
+        return make(1, nw, pa);
+      } catch (const tcx::Error& e) {
+        // the wide tiles' operand planes may be what does not fit; the
+        // 64 x 64 tiles need none
+        if (e.status != TC_ERR_TOO_LARGE) throw;
+        return make(0, nw, pa);
+      }
+    };
     try {
-      plan = make(1);
+      plan = fit(net, path);
     } catch (const tcx::Error& e) {
-      // the wide tiles' operand planes may be what does not fit; the
-      // 64 x 64 tiles need none
+      // still too large (even one term at a time, or an intermediate of
+      // more than 2^31 elements): slice bonds, first until every
+      // intermediate fits an eighth of the cap, then two legs further each
+      // time (each sliced bond halves every intermediate that holds it, so
+      // also what a term keeps for its reverse sweep), and run the slices
+      // as terms (in groups)
       if (e.status != TC_ERR_TOO_LARGE) throw;
-      plan = make(0);
+      const tcx::Error original = e;
+      int32_t lg = 0;
+      while (lg < 27 && (uint64_t(8) << (lg + 1)) <= S.opts.max_request_bytes / 8) ++lg;
+      int32_t peak = 0;
+      for (size_t t = 0; t < net.terms.size(); ++t)
+        peak = std::max(peak, (int32_t)std::lround(std::log2(
+                                  std::max(1.0, tcx::tree_stats(net.terms[t], path.terms[t]).size))));
+      lg = std::min(lg, std::max(1, peak - 1));
+      // (when slicing cannot make it fit, the request is rejected for the
+      // original reason)
+      for (int attempt = 0;; ++attempt) {
+        tcx::Network snet;
+        tcx::Path spath;
+        int32_t s = 0;
+        try {
+          tcx::slice_network(net, path, lg, 12, snet, spath, s);  // TOO_LARGE past 12 bonds
+          plan = fit(snet, spath);
+          break;
+        } catch (const tcx::Error& e2) {
+          if (e2.status != TC_ERR_TOO_LARGE) throw;
+          if (attempt >= 5 || lg <= 3 || s == 0) throw original;
+          lg -= 2;
+        }
+      }
     }
+    if (S.opts.max_request_flops > 0 &&
+        plan->info.flops + plan->info.grad_flops > S.opts.max_request_flops)
+      tcx::fail(TC_ERR_TOO_LARGE, "contraction needs " +
+                                      std::to_string(plan->info.flops + plan->info.grad_flops) +
+                                      " flops, more than the per-request limit");
     std::lock_guard<std::mutex> g(S.mu);
     if (S.cache.size() >= 512) S.cache.clear();
     S.cache.emplace(key, plan);

@@ -33,8 +33,9 @@ class Result:
 
 class Server:
     def __init__(self, pool_bytes=16 << 30, max_request_bytes=4 << 30, max_active=64,
-                 path_trials=4, device=0):
-        opts = L.ServeOpts(device, pool_bytes, max_request_bytes, max_active, path_trials, None)
+                 path_trials=4, device=0, max_request_flops=0.0):
+        opts = L.ServeOpts(device, pool_bytes, max_request_bytes, max_active, path_trials, None,
+                           float(max_request_flops))
         h = C.c_void_p()
         L.check(lib().tc_serve_create(C.byref(opts), C.byref(h)))
         self.h = h
@@ -99,7 +100,11 @@ class ServeReport:
         dev = np.array([r.device_s for r in self.results.values()])
         why = {}
         for msg in self.reasons.values():
-            if "rank > 31" in msg:
+            if "flops" in msg:
+                k = "flops above the per-request limit"
+            elif "sliced labels" in msg:
+                k = "more than 12 sliced bonds needed"
+            elif "rank > 31" in msg:
                 k = "an intermediate above 2^31 elements"
             elif "one term at a time" in msg:
                 k = "one term's intermediates above the per-request cap"

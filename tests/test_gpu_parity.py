@@ -296,6 +296,27 @@ def test_wide_tiles_default_plan_against_golden(rows, cols):
         assert true_rel_err(a1, r) < tol, prec
 
 
+def test_reconfigured_paths_against_golden():
+    """Subtree-reconfigured trees (frontiers of 8 inputs) of the 6x6 depth-8
+    and 5x5 depth-16 grids, both precisions, against the stored oracle
+    amplitudes."""
+    from gpu_common import TOL_BF16X3
+    for rows, cols, depth, key in ((6, 6, 8, "col2"), (5, 5, 16, "statevector")):
+        path = os.path.join(GOLDEN, f"grid{rows}x{cols}_d{depth}_amplitude.json")
+        if not os.path.exists(path):
+            pytest.skip("reference amplitude not generated")
+        ref = json.load(open(path))
+        r = complex(ref["values"][key]["re"], ref["values"][key]["im"])
+        circ, p, amp = tcgen.workload_grid_amplitude(rows, cols, depth)
+        for prec, tol in ((0, TOL_C64), (1, TOL_BF16X3)):
+            plan = api.compile(circ, amp, n_trials=32, seed=1, precision=prec, reconf_k=8)
+            a = plan.contract(device_params(p))[0]
+            del plan
+            print(f"{rows}x{cols} depth {depth}, reconfigured, precision {prec}: "
+                  f"true relative error {true_rel_err(a, r):.2e}")
+            assert true_rel_err(a, r) < tol
+
+
 def test_wide_tiles_full_size_deep_grid():
     """The 6x6 depth-12 grid's 16384 x 65536 x 4096 node runs 128 x 128
     tiles by default: FP32 against the 64 x 64 tiles of the same tree, and

@@ -273,3 +273,68 @@ def test_term_groups_reject_what_one_term_cannot_fit():
         api.compile(circ, obs, want_grad=True, bind=False, n_trials=1, mem_budget_bytes=256 << 20)
     assert e.value.status == L.TC_ERR_TOO_LARGE
     assert "one term at a time" in str(e.value)
+
+
+@pytest.mark.parametrize("rows,cols,depth,trials", [(6, 6, 8, 1), (5, 5, 16, 32), (4, 4, 8, 4)])
+def test_subtree_reconfiguration_improves_and_stays_valid(rows, cols, depth, trials):
+    """Reconfigured trees: a valid SSA path over the same leaves (checked by
+    recontracting the legs here), never a worse combo score than the tree
+    it starts from, and a strict gain on the single-trial 6x6 grid."""
+    circ, p, amp = tcgen.workload_grid_amplitude(rows, cols, depth)
+    net = api.Network(circ, amp)
+    base = api.Path(net, n_trials=trials, seed=1)
+    rec = api.Path(net, n_trials=trials, seed=1, reconf_k=8)
+    sb, sr = base.stats(), rec.stats()
+    assert sr.flops / 8 + 64 * sr.write <= sb.flops / 8 + 64 * sb.write
+    if (rows, cols, trials) == (6, 6, 1):
+        assert sr.flops < sb.flops / 10
+    lv = net.term_leaves(0)
+    legs = [set(int(x) for x in lv["legs"][i][:lv["rank"][i]]) for i in range(len(lv["rank"]))]
+    used = set()
+    fl = 0.0
+    for a, b in rec.pairs(0):
+        assert a not in used and b not in used and a < len(legs) and b < len(legs)
+        used.update((a, b))
+        legs.append(legs[a] ^ legs[b])
+        fl += 8 * 2.0 ** len(legs[a] | legs[b])
+    assert legs[-1] == set() and len(used) == len(legs) - 1
+    assert math.isclose(sr.flops, fl)
+    if rows * cols <= 16:
+        got = contract_along_path(net, rec, circ, p.astype(np.float64), 0)
+        assert abs(got - sv.amplitude(circ, p)) < 1e-12
+
+
+def test_slicing_amplitude_sums_to_the_oracle():
+    """A 4x4 grid amplitude sliced until every intermediate holds at most
+    2^(peak - 4) elements: 2^s slices, each within the bound, whose values
+    (contracted in numpy along the sliced paths) sum to the oracle's
+    amplitude."""
+    circ, p, amp = tcgen.workload_grid_amplitude(4, 4, 8)
+    p = p.astype(np.float64)
+    net = api.Network(circ, amp)
+    path = api.Path(net, n_trials=4, seed=1)
+    peak = int(round(path.stats().log2_size))
+    snet, spath, s = path.sliced(peak - 4)
+    assert s >= 1 and snet.info().n_terms == 2 ** s
+    assert spath.stats().log2_size <= peak - 4
+    total = sum(contract_along_path(snet, spath, circ, p, j) for j in range(2 ** s))
+    assert abs(total - sv.amplitude(circ, p)) < 1e-12
+
+
+def test_slicing_expectation_and_limits():
+    """One Pauli term of a 10-qubit ladder, sliced: the slices sum to the
+    oracle's <P>; asking for too few labels is TOO_LARGE."""
+    circ = tcgen.chain_ladder(10, 4)
+    obs = tcgen.pauli_string(10, z=(4, 5))
+    p = tcgen.draw_angles(3, (circ.n_params,)).astype(np.float64)
+    net = api.Network(circ, obs)
+    path = api.Path(net, n_trials=4, seed=1)
+    peak = int(round(path.stats().log2_size))
+    snet, spath, s = path.sliced(peak - 3)
+    assert s >= 1 and snet.info().n_terms == 2 ** s
+    assert spath.stats().log2_size <= peak - 3
+    total = sum(contract_along_path(snet, spath, circ, p, j) for j in range(2 ** s))
+    assert abs(total - sv.term_values(circ, p, obs)[0]) < 1e-12
+    with pytest.raises(L.TcxError) as e:
+        path.sliced(2, max_labels=1)
+    assert e.value.status == L.TC_ERR_TOO_LARGE
