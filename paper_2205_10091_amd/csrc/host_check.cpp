@@ -1,0 +1,282 @@
+// Host-side check driver for sanitizer builds (no GPU): runs the network
+// builder, the path finder (trials, reconfiguration, spatial candidates),
+// slicing and the planner (budgets, term groups, checkpointing, batches,
+// MPO and state observables, geometric tensor plans, channel gates) over a
+// spread of circuits, plus the error paths, so that AddressSanitizer and
+// UndefinedBehaviorSanitizer see every host code path the library takes
+// before a kernel is launched.  Prints "host check ok" and exits 0 when
+// every call behaves as documented.
+//
+//   g++ -std=c++17 -g -O1 -fsanitize=address,undefined -fno-omit-frame-pointer \
+//       -I include paper_2205_10091_amd/csrc/{network,path,plan,slice,capi_host,host_check}.cpp
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+struct tc_network;
+struct tc_path;
+namespace tcx {
+const Network& network_of(const tc_network* n);
+const Path& path_of(const tc_path* p);
+}  // namespace tcx
+
+namespace {
+
+int failures = 0;
+
+void expect(bool ok, const std::string& what) {
+  if (!ok) {
+    std::fprintf(stderr, "FAILED: %s (%s)\n", what.c_str(), tc_last_error());
+    ++failures;
+  }
+}
+
+struct Circ {
+  int n = 0, n_params = 0;
+  std::vector<tc_gate> gates;
+  std::vector<std::vector<double>> mats;  // caller matrices / probabilities
+  std::vector<int> mat_of;                // per gate: index into mats, or -1
+  void add(int kind, int q0, int q1 = -1, int p0 = -1, int p1 = -1,
+           const std::vector<double>& m = {}) {
+    tc_gate g{};
+    g.kind = kind;
+    g.q[0] = q0;
+    g.q[1] = q1 < 0 ? 0 : q1;
+    g.param[0] = p0;
+    g.param[1] = p1;
+    g.fixed[0] = 0.3;
+    g.fixed[1] = 0.7;
+    gates.push_back(g);
+    mat_of.push_back(m.empty() ? -1 : (int)mats.size());
+    if (!m.empty()) mats.push_back(m);
+  }
+  tc_circuit c() {
+    for (size_t i = 0; i < gates.size(); ++i)
+      gates[i].matrix = mat_of[i] < 0 ? nullptr : mats[mat_of[i]].data();
+    return tc_circuit{n, n_params, (int32_t)gates.size(), gates.data()};
+  }
+};
+
+Circ ladder(int n, int layers) {
+  Circ c;
+  c.n = n;
+  c.n_params = layers * 2 * n;
+  for (int l = 0; l < layers; ++l) {
+    for (int i = 0; i + 1 < n; ++i) c.add(TC_GATE_RZZ, i, i + 1, (l * 2) * n + i);
+    for (int i = 0; i < n; ++i) c.add(TC_GATE_RX, i, -1, (l * 2 + 1) * n + i);
+  }
+  return c;
+}
+
+Circ grid(int r, int cols, int layers) {
+  Circ c;
+  c.n = r * cols;
+  int s = 0;
+  for (int l = 0; l < layers; ++l) {
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b + 1 < cols; ++b) c.add(TC_GATE_RZZ, a * cols + b, a * cols + b + 1, s++);
+    for (int a = 0; a + 1 < r; ++a)
+      for (int b = 0; b < cols; ++b) c.add(TC_GATE_RZZ, a * cols + b, (a + 1) * cols + b, s++);
+    for (int q = 0; q < c.n; ++q) c.add(TC_GATE_FSIM, q, (q + 1) % c.n, s, s + 1), s += 2;
+  }
+  c.n_params = s;
+  return c;
+}
+
+Circ all_kinds(int n, int seed) {
+  Circ c;
+  c.n = n;
+  std::srand(seed);
+  int s = 0;
+  for (int k = 0; k < 60; ++k) {
+    int kind = std::rand() % 21;
+    int q0 = std::rand() % n, q1 = (q0 + 1 + std::rand() % (n - 1)) % n;
+    switch (kind) {
+      case TC_GATE_U1: c.add(kind, q0, -1, -1, -1, std::vector<double>(8, 0.25)); break;
+      case TC_GATE_U2: c.add(kind, q0, q1, -1, -1, std::vector<double>(32, 0.1)); break;
+      case TC_GATE_DEPOL: c.add(kind, q0, -1, s++, -1, {0.1, 0.2, 0.3}); break;
+      case TC_GATE_RSWITCH: c.add(kind, q0, -1, s, s + 1), s += 2; break;
+      case TC_GATE_FSIM: c.add(kind, q0, q1, s, s + 1), s += 2; break;
+      case TC_GATE_RX: case TC_GATE_RY: case TC_GATE_RZ: c.add(kind, q0, -1, s++); break;
+      case TC_GATE_RZZ: case TC_GATE_RXX: case TC_GATE_RYY: c.add(kind, q0, q1, s++); break;
+      case TC_GATE_CNOT: case TC_GATE_CZ: c.add(kind, q0, q1); break;
+      default: c.add(kind, q0); break;
+    }
+  }
+  c.n_params = s;
+  return c;
+}
+
+struct Obs {
+  std::vector<uint8_t> st;
+  std::vector<double> w;
+  std::vector<int32_t> bonds;
+  std::vector<double> mpo;
+  tc_observable o{};
+};
+
+Obs tfim(int n) {
+  Obs x;
+  for (int i = 0; i + 1 < n; ++i) {
+    std::vector<uint8_t> s(n, 0);
+    s[i] = s[i + 1] = 3;
+    x.st.insert(x.st.end(), s.begin(), s.end());
+    x.w.push_back(1.0);
+  }
+  for (int i = 0; i < n; ++i) {
+    std::vector<uint8_t> s(n, 0);
+    s[i] = 1;
+    x.st.insert(x.st.end(), s.begin(), s.end());
+    x.w.push_back(0.8);
+  }
+  x.o = tc_observable{TC_OBS_PAULI_SUM, nullptr, (int32_t)x.w.size(), x.st.data(), x.w.data(),
+                      nullptr, nullptr};
+  return x;
+}
+
+Obs mpo_random(int n) {
+  Obs x;
+  std::vector<int32_t> d(n + 1, 1);
+  for (int k = 1; k < n; ++k) d[k] = 1 + (k * 3) % 8;
+  for (int k = 1; k < n; ++k) x.bonds.push_back(d[k]);
+  for (int k = 0; k < n; ++k)
+    for (int e = 0; e < d[k] * d[k + 1] * 4; ++e) {
+      x.mpo.push_back(std::sin(0.3 * e + k));
+      x.mpo.push_back(std::cos(0.7 * e - k));
+    }
+  x.o = tc_observable{TC_OBS_MPO, nullptr, 0, nullptr, nullptr, x.bonds.data(), x.mpo.data()};
+  return x;
+}
+
+void run_plans(const tc_network* net, const tc_path* path, bool grad, const char* what) {
+  tc_path_stats st{};
+  expect(tc_path_stats_get(path, -1, &st) == TC_OK, std::string(what) + ": stats");
+  for (int batch : {1, 8})
+    for (uint64_t budget : {uint64_t(0), uint64_t(1) << 22})
+      for (int exec : {0, 1}) {
+        tcx::Plan p;
+        p.batch = batch;
+        p.want_grad = grad ? 1 : 0;
+        p.budget = budget;
+        p.exec_mode = exec;
+        try {
+          tcx::build_plan(p, tcx::network_of(net), tcx::path_of(path));
+          const tcx::WorkspaceLayout w = tcx::workspace_layout(p);
+          expect(!budget || w.total <= budget, std::string(what) + ": within budget");
+          expect(!tcx::launch_order(p, grad).empty(), std::string(what) + ": launches");
+        } catch (const tcx::Error& e) {
+          expect(e.status == TC_ERR_TOO_LARGE && budget, std::string(what) + ": plan " + e.msg);
+        }
+      }
+}
+
+void one(Circ& c, tc_observable* o, bool grad, const char* what, int reconf, int score) {
+  tc_circuit cc = c.c();
+  tc_network* net = nullptr;
+  if (tc_build_network(&cc, o, nullptr, &net) != TC_OK) {
+    expect(false, std::string(what) + ": network");
+    return;
+  }
+  tc_path_opts po{7, 4, score, 0.1, reconf};
+  tc_path* path = nullptr;
+  expect(tc_greedy_path(net, &po, &path) == TC_OK, std::string(what) + ": path");
+  if (path) {
+    run_plans(net, path, grad, what);
+    tc_path_stats st{};
+    tc_path_stats_get(path, -1, &st);
+    tc_network* snet = nullptr;
+    tc_path* spath = nullptr;
+    int32_t s = 0;
+    const int target = std::max(2, (int)std::lround(st.log2_size) - 2);
+    const tc_status rs = tc_slice(net, path, target, 16, &snet, &spath, &s);
+    expect(rs == TC_OK || rs == TC_ERR_TOO_LARGE, std::string(what) + ": slice");
+    if (rs == TC_OK) {
+      tc_path_stats ss{};
+      expect(tc_path_stats_get(spath, -1, &ss) == TC_OK && ss.log2_size <= target + 1e-9,
+             std::string(what) + ": sliced size");
+      run_plans(snet, spath, grad, what);
+      tc_path_free(spath);
+      tc_network_free(snet);
+    }
+    tc_path_free(path);
+  }
+  tc_network_free(net);
+}
+
+}  // namespace
+
+int main() {
+  {
+    Circ c = ladder(10, 3);
+    Obs o = tfim(10);
+    one(c, &o.o, true, "ladder tfim", 0, TC_SCORE_COMBO);
+    one(c, &o.o, true, "ladder tfim reconf", 8, TC_SCORE_TIME);
+    Obs m = mpo_random(10);
+    one(c, &m.o, true, "ladder mpo", 6, TC_SCORE_TIME);
+  }
+  {
+    Circ c = grid(3, 3, 2);
+    Obs o = tfim(9);
+    one(c, &o.o, true, "grid fsim tfim", 8, TC_SCORE_COMBO);
+    std::vector<uint8_t> bits(9, 1);
+    tc_observable amp{TC_OBS_AMPLITUDE, bits.data(), 0, nullptr, nullptr, nullptr, nullptr};
+    one(c, &amp, false, "grid amplitude", 8, TC_SCORE_COMBO);
+  }
+  for (int seed = 0; seed < 3; ++seed) {
+    Circ c = all_kinds(6, seed);
+    Obs o = tfim(6);
+    one(c, &o.o, true, "all kinds", seed % 2 ? 6 : 0, seed % 2 ? TC_SCORE_TIME : TC_SCORE_COMBO);
+  }
+  {
+    // geometric tensor plan on the state network
+    Circ c = all_kinds(6, 9);
+    tc_circuit cc = c.c();
+    tc_observable st{TC_OBS_STATE, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+    tc_network* net = nullptr;
+    expect(tc_build_network(&cc, &st, nullptr, &net) == TC_OK, "state network");
+    tc_path_opts po{3, 2, TC_SCORE_COMBO, 0.1, 0};
+    tc_path* path = nullptr;
+    expect(tc_greedy_path(net, &po, &path) == TC_OK, "state path");
+    tcx::Plan p;
+    p.qgt = 1;
+    try {
+      tcx::build_plan(p, tcx::network_of(net), tcx::path_of(path));
+      expect(p.qgt_rows > 0 && p.batch == p.qgt_rows, "qgt rows");
+    } catch (const tcx::Error& e) {
+      expect(false, "qgt plan: " + e.msg);
+    }
+    tc_path_free(path);
+    tc_network_free(net);
+  }
+  {
+    // documented errors
+    Circ c = ladder(4, 1);
+    c.gates[0].q[1] = 9;  // qubit out of range
+    tc_circuit cc = c.c();
+    Obs o = tfim(4);
+    tc_network* net = nullptr;
+    expect(tc_build_network(&cc, &o.o, nullptr, &net) == TC_ERR_INVALID_ARG, "bad qubit");
+    Circ d;
+    d.n = 1;
+    d.n_params = 1;
+    d.add(TC_GATE_DEPOL, 0, -1, 0, -1, {0.5, 0.4, 0.3});  // sum > 1
+    tc_circuit dc = d.c();
+    Obs one_q = tfim(1);
+    expect(tc_build_network(&dc, &one_q.o, nullptr, &net) == TC_ERR_INVALID_ARG, "bad probabilities");
+    Obs bad = tfim(4);
+    bad.st[0] = 7;
+    Circ e = ladder(4, 1);
+    tc_circuit ec = e.c();
+    expect(tc_build_network(&ec, &bad.o, nullptr, &net) == TC_ERR_INVALID_ARG, "bad structure");
+  }
+  if (failures) {
+    std::fprintf(stderr, "%d failures\n", failures);
+    return 1;
+  }
+  std::printf("host check ok\n");
+  return 0;
+}
