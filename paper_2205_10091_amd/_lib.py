@@ -58,7 +58,7 @@ class NetworkInfo(C.Structure):
 class PathOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_trials", C.c_int32),
                 ("score", C.c_int32), ("temperature", C.c_double),
-                ("reconf_k", C.c_int32)]
+                ("reconf_k", C.c_int32), ("max_depth", C.c_int32)]
 
 
 class PathStats(C.Structure):

@@ -119,9 +119,10 @@ class Network:
 class Path:
     """Owns a tc_path*."""
 
-    def __init__(self, net: Network, seed=0, n_trials=1, score=3, temperature=0.1, reconf_k=0):
+    def __init__(self, net: Network, seed=0, n_trials=1, score=3, temperature=0.1, reconf_k=0,
+                 max_depth=0):
         self.net = net
-        opts = L.PathOpts(seed, n_trials, score, temperature, reconf_k)
+        opts = L.PathOpts(seed, n_trials, score, temperature, reconf_k, max_depth)
         h = C.c_void_p()
         L.check(lib().tc_greedy_path(net.h, C.byref(opts), C.byref(h)))
         self.h = h
@@ -294,11 +295,13 @@ def compile(circ, obs, batch=1, want_grad=False, precision=0, split_2q=True,
             lightcone=True, absorb_1q=True, seed=0, n_trials=8,
             mem_budget_bytes=0, device=0, bind=True, gemm_min_k=0, stream=None,
             checkpoint_every=0, gemm_min_macs=0, exec_mode=0, tile_mode=0,
-            score=3, qgt=False, reconf_k=0) -> Plan:
+            score=3, qgt=False, reconf_k=0, max_depth=0) -> Plan:
     """Network + greedy path + plan (+ bind with a torch workspace).
-    score: the path score of tc_greedy_path (3 combo, 4 time estimate)."""
+    score: the path score of tc_greedy_path (3 combo, 4 time estimate);
+    max_depth: cap on each term's tree levels (0 = none)."""
     net = Network(circ, obs, split_2q, lightcone, absorb_1q)
-    path = Path(net, seed=seed, n_trials=n_trials, score=score, reconf_k=reconf_k)
+    path = Path(net, seed=seed, n_trials=n_trials, score=score, reconf_k=reconf_k,
+                max_depth=max_depth)
     torch_stream = None
     if stream is None and bind:
         # a dedicated torch stream (default priority): torch work orders

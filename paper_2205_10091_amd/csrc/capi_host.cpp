@@ -120,11 +120,12 @@ tc_status tc_greedy_path(const tc_network* net, const tc_path_opts* opts,
                          tc_path** out) {
   TC_GUARD_BEGIN
   if (!net || !out) tcx::fail(TC_ERR_INVALID_ARG, "NULL argument");
-  tc_path_opts o{0, 1, TC_SCORE_COMBO, 0.1, 0};
+  tc_path_opts o{0, 1, TC_SCORE_COMBO, 0.1, 0, 0};
   if (opts) o = *opts;
   if (o.n_trials < 1) tcx::fail(TC_ERR_INVALID_ARG, "n_trials must be >= 1");
   if (o.score < 0 || o.score > 4) tcx::fail(TC_ERR_INVALID_ARG, "unknown score");
   if (o.reconf_k < 0 || o.reconf_k > 10) tcx::fail(TC_ERR_INVALID_ARG, "reconf_k must be 0..10");
+  if (o.max_depth < 0) tcx::fail(TC_ERR_INVALID_ARG, "max_depth must be >= 0");
   auto* p = new tc_path;
   p->path = tcx::greedy_path(net->net, o);
   p->terms = net->net.terms;

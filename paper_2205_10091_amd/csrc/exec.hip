@@ -133,6 +133,7 @@ struct TermArgs {
   float2* arena;
   uint32_t param_stride;      // floats between rows' parameter vectors
   int32_t with_leaves;        // materialise the term's leaves first
+  const DevROp* rops;         // resident launches: the node records
 };
 
 struct GradSeg {
@@ -823,6 +824,160 @@ __global__ void __launch_bounds__(1024) k_term(TermArgs a) {
   }
 }
 
+// Resident term launch: workgroup t runs term t's whole evaluation, its
+// leaves, every forward step and (with the gradient) every reverse-sweep
+// step, with a workgroup barrier after each step.  Each node reads its
+// operands from the LDS arena (extern shared memory, sized by the plan) or
+// the global arena, as its record says, and writes its result to one or
+// both; the planner placed the tensors so that a step's reads never meet a
+// region written in the same step.  Operand pointers are generic (flat)
+// so that one code path serves either memory.  Op records of a step are
+// double-buffered in LDS as in k_term.
+constexpr uint32_t RES_LDS_OPS = 160;
+constexpr uint32_t ROP_WORDS = sizeof(DevROp) / 4;
+static_assert(sizeof(DevROp) % 4 == 0, "resident op records are copied as 32-bit words");
+constexpr uint32_t RES_PRE = (RES_LDS_OPS * ROP_WORDS + 1023) / 1024;  // words per thread
+
+// Item l of a resident node (the item layout of gather_item_t, batch 1).
+// All lanes of a wavefront whose node splits its sums (S > 1) call this
+// together: such nodes start and end on wavefront boundaries.
+template <bool TABLES>
+__device__ __forceinline__ void res_item_t(const DevROp& op, uint32_t l,
+                                           const uint32_t* __restrict__ tab,
+                                           float2* __restrict__ arena, float2* lds) {
+  const uint32_t sh = op.shape;
+  const uint32_t lm = sh & 31u, lk = (sh >> 10) & 31u, ls = (sh >> 15) & 7u, lv = (sh >> 18) & 3u;
+  const uint32_t ln = ((sh >> 5) & 31u) - lv;
+  const uint32_t S = 1u << ls, V = 1u << lv;
+  const uint32_t e = l >> ls, sub = l & (S - 1);
+  const bool valid = e < (1u << (ln + lm));
+  c32 acc[4] = {cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f), cx(0.f, 0.f)};
+  uint32_t m = 0, n0 = 0;
+  if (valid) {
+    n0 = (e & ((1u << ln) - 1)) << lv;
+    m = e >> ln;
+    const float2* A = ((sh & RES_A_LDS) ? lds : arena) + op.a + ixt<TABLES>(tab, op.a_m, m);
+    const float2* Bp = ((sh & RES_B_LDS) ? lds : arena) + op.b;
+    uint32_t bn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? ixt<TABLES>(tab, op.b_n, n0 + j) : 0u;
+    const uint32_t K = 1u << lk;
+    if (V == 4)
+      gather_dot<4, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
+    else if (V == 2)
+      gather_dot<2, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
+    else
+      gather_dot<1, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
+  }
+  if (S > 1) {
+    // V == 1 whenever S > 1
+    for (uint32_t off = S >> 1; off > 0; off >>= 1) {
+      acc[0].re += __shfl_xor(acc[0].re, (int)off, 64);
+      acc[0].im += __shfl_xor(acc[0].im, (int)off, 64);
+    }
+  }
+  if (valid && sub == 0) {
+    float2* C = ((sh & RES_C_LDS) ? lds : arena) + op.c + ixt<TABLES>(tab, op.c_m, m);
+    float2* C2 = arena + op.c2 + ixt<TABLES>(tab, op.c_m, m);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j < V) {
+        const uint32_t o = ixt<TABLES>(tab, op.c_n, n0 + j);
+        const float2 v = make_float2(acc[j].re, acc[j].im);
+        C[o] = v;
+        if (sh & RES_C2) C2[o] = v;
+      }
+  }
+}
+
+__device__ __forceinline__ void res_item(const DevROp& op, uint32_t l,
+                                         const uint32_t* __restrict__ tab,
+                                         float2* __restrict__ arena, float2* lds) {
+  if (op.shape & RES_TABLES)
+    res_item_t<true>(op, l, tab, arena, lds);
+  else
+    res_item_t<false>(op, l, tab, arena, lds);
+}
+
+__global__ void __launch_bounds__(1024) k_term_res(TermArgs a) {
+  extern __shared__ float2 lds[];
+  __shared__ DevROp sops[2][RES_LDS_OPS];
+  __shared__ DevGroup sgroups[TERM_LDS_GROUPS];
+  const DevTerm T = a.terms[blockIdx.x];
+  const DevRange R = a.ranges[blockIdx.x];
+  const uint32_t ng = R.g_end - R.g_begin;
+  const bool groups_staged = ng <= TERM_LDS_GROUPS;
+  if (groups_staged && threadIdx.x < ng) sgroups[threadIdx.x] = a.groups[R.g_begin + threadIdx.x];
+  uint32_t pre[RES_PRE];
+  auto fetch = [&](uint32_t g) {  // the op records of group g, into registers
+    if (g >= R.g_end) return;
+    const DevGroup G = a.groups[g];
+    const uint32_t n = G.op_end - G.op_begin;
+    if (n > RES_LDS_OPS) return;
+    const uint32_t* src = (const uint32_t*)(a.rops + G.op_begin);
+#pragma unroll
+    for (uint32_t q = 0; q < RES_PRE; ++q) {
+      const uint32_t x = threadIdx.x + q * 1024;
+      pre[q] = x < n * ROP_WORDS ? src[x] : 0u;
+    }
+  };
+  auto commit = [&](uint32_t g, int buf) {  // registers -> LDS buffer
+    if (g >= R.g_end) return;
+    const DevGroup G = a.groups[g];
+    const uint32_t n = G.op_end - G.op_begin;
+    if (n > RES_LDS_OPS) return;
+    uint32_t* dst = (uint32_t*)&sops[buf][0];
+#pragma unroll
+    for (uint32_t q = 0; q < RES_PRE; ++q) {
+      const uint32_t x = threadIdx.x + q * 1024;
+      if (x < n * ROP_WORDS) dst[x] = pre[q];
+    }
+  };
+  fetch(R.g_begin);
+  // the term's leaves, at batch row 0, into LDS and / or the global arena
+  for (uint64_t w = T.leaf_work0 + threadIdx.x; w < T.leaf_work_end; w += blockDim.x) {
+    const uint32_t li =
+        a.item_leaf ? a.item_leaf[w] : find_in(a.leaves, T.leaf_begin, T.leaf_end, w);
+    const DevLeaf& L = a.leaves[li];
+    const int e = (int)(w - L.work0);
+    const float t0 = L.param[0] >= 0 ? a.params[L.param[0]] : L.fixed[0];
+    const float t1 = L.param[1] >= 0 ? a.params[L.param[1]] : L.fixed[1];
+    const c32 v = leaf_entry(L, e, t0, t1, a.ftab);
+    if (L.where & 1u) a.arena[L.out + e] = make_float2(v.re, v.im);
+    if (L.where & 2u) lds[L.lds_out + e] = make_float2(v.re, v.im);
+  }
+  commit(R.g_begin, 0);
+  __syncthreads();
+  for (uint32_t g = R.g_begin; g < R.g_end; ++g) {
+    const int buf = (int)((g - R.g_begin) & 1u);
+    const DevGroup G = groups_staged ? sgroups[g - R.g_begin] : a.groups[g];
+    const uint32_t n = G.op_end - G.op_begin;
+    fetch(g + 1);  // in flight while this group computes
+    const DevROp* ops = n <= RES_LDS_OPS ? sops[buf] : a.rops + G.op_begin;
+    uint32_t oi = 0xffffffffu;
+    for (uint32_t w = threadIdx.x; w < (uint32_t)G.items; w += blockDim.x) {
+      if (oi == 0xffffffffu) {
+        // largest op with work0 <= w
+        uint32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (ops[mid].work0 <= w)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        oi = lo;
+      } else {
+        while (oi + 1 < n && ops[oi + 1].work0 <= w) ++oi;
+      }
+      const DevROp op = ops[oi];
+      res_item(op, w - op.work0, a.tab, a.arena, lds);
+    }
+    commit(g + 1, buf ^ 1);
+    __syncthreads();
+  }
+}
+
 // E[b] = sum_j alpha_j T_j[b] in FP64: one wavefront per batch row, lane l
 // takes terms l, l + 64, ...; the 64 partial sums combine in a fixed
 // butterfly order (deterministic).
@@ -958,15 +1113,49 @@ struct ProfEvents {
 static thread_local ProfEvents* t_prof = nullptr;
 
 template <typename... Args>
-static void launch(void (*kernel)(Args...), dim3 grid, dim3 block, hipStream_t st,
-                   Args... args) {
+static void launch_shm(void (*kernel)(Args...), dim3 grid, dim3 block, size_t shm, hipStream_t st,
+                       Args... args) {
   if (t_prof) {
     hipEvent_t s = t_prof->started ? nullptr : t_prof->start;
     t_prof->started = true;
-    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, s, t_prof->stop, 0, args...);
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, st, s, t_prof->stop, 0, args...);
   } else {
-    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
   }
+}
+
+template <typename... Args>
+static void launch(void (*kernel)(Args...), dim3 grid, dim3 block, hipStream_t st,
+                   Args... args) {
+  launch_shm(kernel, grid, block, 0, st, args...);
+}
+
+// Elements of the LDS arena a resident term launch can have on `device`:
+// the device's shared memory per workgroup less k_term_res's own, in whole
+// 256-element blocks; 0 when the device cannot be queried.
+uint32_t resident_lds_elems(int device) {
+  int max_shared = 0;
+  if (hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_term_res)) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const int64_t avail = (int64_t)max_shared - (int64_t)fa.sharedSizeBytes - 1024;
+  if (avail < 8 * 4096) return 0;
+  const uint32_t elems = (uint32_t)((avail / 8) & ~int64_t(255));
+  // (the launch asks for this much dynamic shared memory)
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_term_res),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(elems * sizeof(float2))) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return elems;
 }
 
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
@@ -1133,7 +1322,13 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.arena = (float2*)(s.ws + L.arena);
       a.param_stride = P.param_stride();
       a.with_leaves = s.launch->with_leaves ? 1 : 0;
-      launch(k_term, dim3((unsigned)P.terms.size()), dim3(1024), stream, a);
+      if (P.resident) {
+        a.rops = (const DevROp*)(s.ws + L.rops);
+        launch_shm(k_term_res, dim3((unsigned)P.terms.size()), dim3(1024),
+                   (size_t)P.lds_elems * sizeof(float2), stream, a);
+      } else {
+        launch(k_term, dim3((unsigned)P.terms.size()), dim3(1024), stream, a);
+      }
       break;
     }
     case L_ROOT: {
@@ -1232,6 +1427,7 @@ void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStrea
   upload(ws, lay.terms, P.terms, stream);
   upload(ws, lay.groups, P.groups, stream);
   upload(ws, lay.ranges, P.ranges, stream);
+  upload(ws, lay.rops, P.rops, stream);
   upload(ws, lay.sunits, P.split_units, stream);
   upload(ws, lay.gsunits, P.gsplit_units, stream);
   upload(ws, lay.qslot, P.qslot_begin, stream);
@@ -1556,7 +1752,10 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
   tc_plan_opts o{0, 1, 0, 0, 0, nullptr, 0, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.gemm_min_k < 0) tcx::fail(TC_ERR_INVALID_ARG, "gemm_min_k must be >= 0");
-  if (o.exec_mode < 0 || o.exec_mode > 2) tcx::fail(TC_ERR_INVALID_ARG, "exec_mode must be 0, 1 or 2");
+  if (o.exec_mode < 0 || o.exec_mode > 3) tcx::fail(TC_ERR_INVALID_ARG, "exec_mode must be 0, 1, 2 or 3");
+  // resident term launches size their LDS arena from the device
+  const uint32_t lds_elems =
+      (o.exec_mode == 0 || o.exec_mode == 3) && o.batch == 1 && !o.qgt ? tcx::resident_lds_elems(o.device) : 0;
   if (o.tile_mode < 0 || o.tile_mode > 2) tcx::fail(TC_ERR_INVALID_ARG, "tile_mode must be 0, 1 or 2");
   if (o.checkpoint_every < -1 || o.checkpoint_every == 1)
     tcx::fail(TC_ERR_INVALID_ARG, "checkpoint_every must be -1, 0 or >= 2");
@@ -1574,6 +1773,7 @@ tc_status tc_plan_create(const tc_network* net, const tc_path* path,
     if (o.gemm_min_k > 0) p->p.gemm_min_k = o.gemm_min_k;
     if (o.gemm_min_macs > 0) p->p.gemm_min_macs = o.gemm_min_macs;
     p->p.exec_mode = o.exec_mode;
+    p->p.lds_elems = lds_elems;
     p->p.wide_tiles = wide_tiles;
     p->p.checkpoint = o.checkpoint_every;
     p->p.qgt = o.qgt ? 1 : 0;

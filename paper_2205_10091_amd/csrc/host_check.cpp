@@ -10,6 +10,7 @@
 //   g++ -std=c++17 -g -O1 -fsanitize=address,undefined -fno-omit-frame-pointer \
 //       -I include paper_2205_10091_amd/csrc/{network,path,plan,slice,capi_host,host_check}.cpp
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -27,6 +28,7 @@ const Path& path_of(const tc_path* p);
 namespace {
 
 int failures = 0;
+int resident_checked = 0;
 
 void expect(bool ok, const std::string& what) {
   if (!ok) {
@@ -152,6 +154,98 @@ Obs mpo_random(int n) {
   return x;
 }
 
+// Resident term launches, executed on the host: every term's leaves and
+// nodes in step order, operands taken from a per-term LDS arena or the
+// global arena as the resident records say (`res`), or from the global
+// arena through the plain op records (the reference).  Memory starts as
+// NaN, so a read of anything not yet written shows in the results; the
+// nodes of a step run first to last or last to first (`rev`), so a node
+// that overwrote another's operand within one step would change them.
+// Returns the term roots and the leaf adjoints the gradient reads.
+using cd = std::complex<double>;
+
+uint64_t ix_of(const std::vector<uint32_t>& tabs, uint32_t d, uint64_t i) {
+  if (d & 0x80000000u) return tabs.at((d & 0x7fffffffu) + i);
+  uint64_t off = 0;
+  uint32_t src = 0;
+  for (int r = 0; r < 3; ++r) {
+    const uint32_t f = (d >> (10 * r)) & 0x3ffu, len = f & 31u, dst = f >> 5;
+    off |= ((i >> src) & ((uint64_t(1) << len) - 1)) << dst;
+    src += len;
+  }
+  return off;
+}
+
+std::vector<cd> run_resident(const tcx::Plan& p, bool res, bool grad, bool rev) {
+  const double nan = std::nan("");
+  std::vector<cd> G(p.arena_elems, cd(nan, nan)), L;
+  for (size_t t = 0; t < p.seeds.size() / 2; ++t) G.at(t) = cd(p.seeds[2 * t], p.seeds[2 * t + 1]);
+  const tcx::Launch* term_launch = nullptr;
+  for (const tcx::Launch* x : tcx::launch_order(p, grad))
+    if (x->kind == tcx::L_TERM) term_launch = x;
+  if (!term_launch) return {};
+  for (size_t t = 0; t < p.terms.size(); ++t) {
+    L.assign(p.lds_elems, cd(nan, nan));
+    for (uint32_t li = p.terms[t].leaf_begin; li < p.terms[t].leaf_end; ++li) {
+      const tcx::DevLeaf& d = p.leaves[li];
+      for (uint64_t e = 0; e < (uint64_t(1) << d.rank); ++e) {
+        const cd v(std::sin(0.7 * li + 0.3 * e), std::cos(0.11 * li - 0.5 * e));
+        if (!res || (d.where & 1u)) G.at(d.out + e) = v;
+        if (res && (d.where & 2u)) L.at(d.lds_out + e) = v;
+      }
+    }
+    const tcx::DevRange R = p.ranges.at(term_launch->begin + t);
+    for (uint32_t g = R.g_begin; g < R.g_end; ++g) {
+      const tcx::DevGroup& grp = p.groups.at(g);
+      for (uint32_t q = 0; q < grp.op_end - grp.op_begin; ++q) {
+        const uint32_t o = rev ? grp.op_end - 1 - q : grp.op_begin + q;
+        const tcx::DevOp& op = p.ops.at(o);
+        uint64_t a = op.a, b = op.b, c = op.c, c2 = 0;
+        bool al = false, bl = false, cl = false, two = false;
+        if (res) {
+          const tcx::DevROp& r = p.rops.at(o);
+          a = r.a, b = r.b, c = r.c, c2 = r.c2;
+          al = r.shape & tcx::RES_A_LDS, bl = r.shape & tcx::RES_B_LDS;
+          cl = r.shape & tcx::RES_C_LDS, two = r.shape & tcx::RES_C2;
+        }
+        std::vector<cd>& MA = al ? L : G;
+        std::vector<cd>& MB = bl ? L : G;
+        std::vector<cd>& MC = cl ? L : G;
+        auto offs = [&](uint32_t d, uint64_t n) {
+          std::vector<uint64_t> v(n);
+          for (uint64_t i = 0; i < n; ++i) v[i] = ix_of(p.tabs, d, i);
+          return v;
+        };
+        const std::vector<uint64_t> am = offs(op.a_m, op.M), ak = offs(op.a_k, op.K),
+                                    bk = offs(op.b_k, op.K), bn = offs(op.b_n, op.N),
+                                    cm = offs(op.c_m, op.M), cn = offs(op.c_n, op.N);
+        for (uint64_t m = 0; m < op.M; ++m)
+          for (uint64_t n = 0; n < op.N; ++n) {
+            cd acc = 0;
+            for (uint64_t k = 0; k < op.K; ++k) acc += MA.at(a + am[m] + ak[k]) * MB.at(b + bk[k] + bn[n]);
+            MC.at(c + cm[m] + cn[n]) = acc;
+            if (two) G.at(c2 + cm[m] + cn[n]) = acc;
+          }
+      }
+    }
+  }
+  std::vector<cd> out;
+  for (const tcx::DevRoot& r : p.roots)
+    if (r.present) out.push_back(G.at(r.val));
+  if (grad)
+    for (const tcx::DevGradUse& u : p.uses)
+      for (uint64_t e = 0; e < (uint64_t(1) << p.leaves.at(u.leaf).rank); ++e)
+        out.push_back(G.at(u.adj + e));
+  return out;
+}
+
+bool same(const std::vector<cd>& x, const std::vector<cd>& y) {
+  if (x.size() != y.size() || x.empty()) return false;
+  for (size_t i = 0; i < x.size(); ++i)
+    if (!(x[i] == y[i])) return false;  // NaN never compares equal
+  return true;
+}
+
 void run_plans(const tc_network* net, const tc_path* path, bool grad, const char* what) {
   tc_path_stats st{};
   expect(tc_path_stats_get(path, -1, &st) == TC_OK, std::string(what) + ": stats");
@@ -172,6 +266,42 @@ void run_plans(const tc_network* net, const tc_path* path, bool grad, const char
           expect(e.status == TC_ERR_TOO_LARGE && budget, std::string(what) + ": plan " + e.msg);
         }
       }
+  // resident term launches: a small LDS arena (most tensors global) and a
+  // large one, each against the same plan's plain records
+  for (uint32_t lds : {1024u, 16384u}) {
+    tcx::Plan p;
+    p.want_grad = grad ? 1 : 0;
+    p.exec_mode = 3;
+    p.lds_elems = lds;
+    try {
+      tcx::build_plan(p, tcx::network_of(net), tcx::path_of(path));
+    } catch (const tcx::Error& e) {
+      // (nodes for the GEMM path rule the mode out)
+      expect(e.status == TC_ERR_UNSUPPORTED, std::string(what) + ": resident plan " + e.msg);
+      continue;
+    }
+    expect(p.resident && p.exec_used == 4, std::string(what) + ": resident mode");
+    ++resident_checked;
+    const std::vector<cd> want = run_resident(p, false, grad, false);
+    expect(same(run_resident(p, true, grad, false), want), std::string(what) + ": resident values");
+    expect(same(run_resident(p, true, grad, true), want), std::string(what) + ": resident values, nodes reversed");
+    // a planted misplacement must show: the first node that reads an LDS
+    // operand reads it from the wrong place
+    if (lds == 16384u)
+      for (tcx::DevROp& r : p.rops)
+        if (r.shape & tcx::RES_A_LDS) {
+          const uint32_t keep = r.a;
+          r.a = keep >= 8 ? keep - 8 : keep + 8;
+          expect(!same(run_resident(p, true, grad, false), want), std::string(what) + ": planted misplacement seen");
+          r.a = keep;
+          break;
+        }
+    if (grad) {
+      // the forward-only launch gives the same roots
+      std::vector<cd> fw = run_resident(p, true, false, false), ref = run_resident(p, false, false, false);
+      expect(same(fw, ref), std::string(what) + ": resident forward launch");
+    }
+  }
 }
 
 void one(Circ& c, tc_observable* o, bool grad, const char* what, int reconf, int score) {
@@ -181,7 +311,7 @@ void one(Circ& c, tc_observable* o, bool grad, const char* what, int reconf, int
     expect(false, std::string(what) + ": network");
     return;
   }
-  tc_path_opts po{7, 4, score, 0.1, reconf};
+  tc_path_opts po{7, 4, score, 0.1, reconf, reconf ? 12 : 0};
   tc_path* path = nullptr;
   expect(tc_greedy_path(net, &po, &path) == TC_OK, std::string(what) + ": path");
   if (path) {
@@ -238,7 +368,7 @@ int main() {
     tc_observable st{TC_OBS_STATE, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
     tc_network* net = nullptr;
     expect(tc_build_network(&cc, &st, nullptr, &net) == TC_OK, "state network");
-    tc_path_opts po{3, 2, TC_SCORE_COMBO, 0.1, 0};
+    tc_path_opts po{3, 2, TC_SCORE_COMBO, 0.1, 0, 0};
     tc_path* path = nullptr;
     expect(tc_greedy_path(net, &po, &path) == TC_OK, "state path");
     tcx::Plan p;
@@ -277,6 +407,7 @@ int main() {
     std::fprintf(stderr, "%d failures\n", failures);
     return 1;
   }
-  std::printf("host check ok\n");
+  expect(resident_checked >= 8, "resident plans checked");
+  std::printf("host check ok (%d resident plans simulated)\n", resident_checked);
   return 0;
 }

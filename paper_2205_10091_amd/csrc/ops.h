@@ -71,6 +71,26 @@ struct DevRange {
   uint32_t g_begin, g_end;
 };
 
+// Resident term launch: one workgroup runs a term's whole forward pass and
+// reverse sweep, with the tensors the planner places there in the
+// workgroup's LDS arena and the rest in the global arena.  A node of such
+// a launch (no batch axis; M = 2^lm, N = 2^ln, K = 2^lk):
+//   a, b, c   element offsets, each in the LDS arena when its RES_*_LDS
+//             flag is set, else in the global arena;
+//   c2        global arena offset of a second copy of C (RES_C2): a value
+//             that later steps read from global memory once its LDS copy
+//             is released;
+//   work0     first gather item within its group;
+//   shape     lm | ln << 5 | lk << 10 | ls << 15 | lv << 18 | flags.
+constexpr uint32_t RES_A_LDS = 1u << 21, RES_B_LDS = 1u << 22, RES_C_LDS = 1u << 23,
+                   RES_C2 = 1u << 24, RES_TABLES = 1u << 25;
+struct DevROp {
+  uint32_t a, b, c, c2;
+  uint32_t work0;
+  uint32_t a_m, a_k, b_k, b_n, c_m, c_n;
+  uint32_t shape;
+};
+
 struct DevTerm {
   uint64_t leaf_work0, leaf_work_end;  // the term's leaf entries (leaf work items)
   uint32_t leaf_begin, leaf_end;       // the term's leaves
@@ -96,6 +116,9 @@ struct DevLeaf {
                            // 2^(rank+1) (the entries of an MPO site)
   int32_t dsel[2];         // batch row that takes d/d(angle a) instead of the
                            // gate (geometric tensor plans), -1 none
+  uint32_t lds_out;        // resident term launches: LDS arena offset
+  uint32_t where;          // resident term launches: bit 0 written at `out`
+                           // (global arena), bit 1 at `lds_out` (LDS)
 };
 
 // d(term root)/d(angle) for one leaf use: sum_e adj[e] * dleaf[e]/dangle

@@ -466,6 +466,17 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
     // the result does not depend on the thread count
     std::vector<TermPath> found(trials);
     std::vector<double> score(trials, 0.0);
+    std::vector<int32_t> tdepth(trials, 0);
+    // candidate (score sc, depth d) beats the current best (bsc, bd): under
+    // a depth cap, within the cap first, then the shallower, then the score
+    const int32_t cap = opts.max_depth;
+    auto better = [cap](double sc, int32_t d, double bsc, int32_t bd) {
+      if (cap <= 0) return sc < bsc;
+      const bool ok = d <= cap, bok = bd <= cap;
+      if (ok != bok) return ok;
+      if (!ok && d != bd) return d < bd;
+      return sc < bsc;
+    };
     auto run_trial = [&](int trial) {
       Search s;
       s.init(term);
@@ -484,7 +495,9 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
       TermPath& tp = found[trial];
       tp.n_leaves = (int32_t)term.leaves.size();
       tp.pairs = std::move(s.pairs);
-      score[trial] = score_of(tree_stats(term, tp), opts.score);
+      const TreeStats ts = tree_stats(term, tp);
+      score[trial] = score_of(ts, opts.score);
+      tdepth[trial] = ts.depth;
     };
     const int n_threads =
         std::min(trials, std::max(1, std::min(16, (int)std::thread::hardware_concurrency())));
@@ -511,9 +524,10 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
     }
     int best_trial = 0;
     for (int trial = 1; trial < trials; ++trial)
-      if (score[trial] < score[best_trial]) best_trial = trial;
+      if (better(score[trial], tdepth[trial], score[best_trial], tdepth[best_trial])) best_trial = trial;
     TermPath best = std::move(found[best_trial]);
     double best_score = score[best_trial];
+    int32_t best_depth = tdepth[best_trial];
     // One more candidate: the time-ordered sweep of a state-vector
     // simulation, kept when it scores better.  The unconjugated leaves
     // (boundary vectors, gates in circuit order, Pauli matrices or output
@@ -536,10 +550,12 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
         tp.pairs.push_back({cur, order[k]});
         cur = tp.n_leaves + (int32_t)tp.pairs.size() - 1;
       }
-      const double sc = score_of(tree_stats(term, tp), opts.score);
-      if (sc < best_score) {
+      const TreeStats ts = tree_stats(term, tp);
+      const double sc = score_of(ts, opts.score);
+      if (better(sc, ts.depth, best_score, best_depth)) {
         best = std::move(tp);
         best_score = sc;
+        best_depth = ts.depth;
       }
     }
     // Two spatial candidates, wire by wire (on each wire: ket gates in time
@@ -615,16 +631,19 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
         const double sc = score_of(st, opts.score);
         // (a candidate whose largest intermediate the executor cannot hold
         // is never kept)
-        if (st.size <= std::ldexp(1.0, 31) && sc < best_score) {
+        if (st.size <= std::ldexp(1.0, 31) && better(sc, st.depth, best_score, best_depth)) {
           best = std::move(tp);
           best_score = sc;
+          best_depth = st.depth;
         }
       }
     }
     if (opts.reconf_k >= 3 && best.pairs.size() >= 2) {
       TermPath r = reconfigure(term, best, std::min(opts.reconf_k, 10), 4);
       const TreeStats st = tree_stats(term, r);
-      if (st.size <= std::ldexp(1.0, 31) && score_of(st, opts.score) < best_score) best = std::move(r);
+      if (st.size <= std::ldexp(1.0, 31) &&
+          better(score_of(st, opts.score), st.depth, best_score, best_depth))
+        best = std::move(r);
     }
     path.terms.push_back(std::move(best));
   }

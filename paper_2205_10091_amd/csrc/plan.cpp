@@ -46,6 +46,12 @@ struct PT {                       // a tensor of the plan
   int32_t first = 0, last = 0;    // timeline steps of production / last use
   bool fixed = false;             // preallocated constant (seeds)
   int32_t term = -1;              // owning term
+  // resident term launches: an LDS copy at lds_off serves the reads up to
+  // step lds_last; `global` says whether the global copy at off is kept
+  // (read later, or by the root and gradient kernels)
+  int64_t lds_off = -1;
+  int32_t lds_last = -1;
+  bool global = true;
 };
 
 // offset of index i under descriptor d (see ops.h)
@@ -520,6 +526,75 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
   S.arena_elems = std::max(base, S.seed_elems);
 }
 
+// LDS placement of a resident plan, term by term (each term's workgroup
+// has the whole LDS arena of `cap` elements to itself).  A tensor whose
+// reads all come within RES_LDS_WINDOW steps of its production (and that
+// neither the root sum nor the gradient sum reads) lives in LDS alone; any
+// other keeps its global copy and, where space allows, gets an LDS copy
+// that serves its first reading step, so a forward value feeds the next
+// node from LDS and the reverse sweep from global memory.  Short LDS
+// lifetimes are placed first (they return their space soonest), each at
+// the lowest offset clear of every placed tensor whose lifetime overlaps
+// its own; lifetimes are inclusive step ranges, so a node's operands and
+// its result never share space.
+constexpr int32_t RES_LDS_WINDOW = 6;
+
+void place_lds(std::vector<PT>& T, const std::vector<PendingOp>& pend, int32_t root_step,
+               uint64_t cap, size_t n_terms) {
+  std::vector<int32_t> u1(T.size(), INT32_MAX);
+  for (const PendingOp& q : pend) {
+    u1[q.a] = std::min(u1[q.a], q.step);
+    u1[q.b] = std::min(u1[q.b], q.step);
+  }
+  std::vector<std::vector<int32_t>> by_term(n_terms);
+  for (int32_t i = 0; i < (int32_t)T.size(); ++i)
+    if (!T[i].fixed && T[i].term >= 0 && (size_t)T[i].term < n_terms) by_term[T[i].term].push_back(i);
+  struct Cand {
+    int32_t id, lo, hi;
+    uint64_t size;
+    bool keep;  // the global copy stays
+  };
+  struct Placed {
+    uint64_t off, size;
+    int32_t lo, hi;
+  };
+  std::vector<Cand> cs;
+  std::vector<Placed> pl;
+  std::vector<std::pair<uint64_t, uint64_t>> busy;
+  for (const auto& ids : by_term) {
+    cs.clear();
+    pl.clear();
+    for (int32_t id : ids) {
+      const PT& x = T[id];
+      if (x.elems > cap || u1[id] == INT32_MAX) continue;
+      const bool keep = x.last >= root_step || x.last - x.first > RES_LDS_WINDOW;
+      cs.push_back({id, x.first, keep ? u1[id] : x.last, (x.elems + 7) & ~uint64_t(7), keep});
+    }
+    std::sort(cs.begin(), cs.end(), [](const Cand& p, const Cand& q) {
+      if (p.hi - p.lo != q.hi - q.lo) return p.hi - p.lo < q.hi - q.lo;
+      if (p.size != q.size) return p.size > q.size;
+      return p.id < q.id;
+    });
+    for (const Cand& c : cs) {
+      busy.clear();
+      for (const Placed& p : pl)
+        if (p.lo <= c.hi && c.lo <= p.hi) busy.push_back({p.off, p.off + p.size});
+      std::sort(busy.begin(), busy.end());
+      uint64_t off = 0;
+      for (const auto& b : busy) {
+        if (b.first >= off + c.size) break;
+        off = std::max(off, b.second);
+      }
+      if (off + c.size > cap) continue;
+      pl.push_back({off, c.size, c.lo, c.hi});
+      PT& x = T[c.id];
+      x.lds_off = (int64_t)off;
+      x.lds_last = c.hi;
+      x.global = c.keep;
+    }
+  }
+}
+
 }  // namespace
 
 WorkspaceLayout workspace_layout(const Plan& p) {
@@ -537,6 +612,7 @@ WorkspaceLayout workspace_layout(const Plan& p) {
   w.terms = o; o = al(o + p.terms.size() * sizeof(DevTerm));
   w.groups = o; o = al(o + p.groups.size() * sizeof(DevGroup));
   w.ranges = o; o = al(o + p.ranges.size() * sizeof(DevRange));
+  w.rops = o; o = al(o + p.rops.size() * sizeof(DevROp));
   w.split = o; o = al(o + p.split_floats * sizeof(float));
   w.sunits = o; o = al(o + p.split_units.size() * sizeof(DevSplitUnit));
   w.gsunits = o; o = al(o + p.gsplit_units.size() * sizeof(DevSplitUnit));
@@ -560,7 +636,11 @@ std::vector<const Launch*> launch_order(const Plan& p, bool with_grad) {
   while (i < p.fwd.size() || (with_grad && j < p.bwd.size())) {
     const bool take_fwd = i < p.fwd.size() &&
                           (!with_grad || j >= p.bwd.size() || p.fwd[i].step <= p.bwd[j].step);
-    seq.push_back(take_fwd ? &p.fwd[i++] : &p.bwd[j++]);
+    const Launch* L = take_fwd ? &p.fwd[i++] : &p.bwd[j++];
+    // a resident plan's forward-only launch gives way to the launch that
+    // runs both the forward pass and the reverse sweep
+    if (with_grad && L->resident == 1) continue;
+    seq.push_back(L);
   }
   return seq;
 }
@@ -761,6 +841,32 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   }
   if (G > 1)  // groups run level launches only
     for (auto& ts : term_step) ts.second = false;
+  // Resident term launches: one workgroup per term runs every step, the
+  // leaves first and the reverse sweep after the forward pass, in a single
+  // kernel; tensors placed in the workgroup's LDS arena are read and
+  // written there, so a step costs a workgroup barrier and LDS traffic
+  // instead of a kernel launch and dependent global-memory round trips.
+  // Batch 1, one term group, every node on the gather path, and an LDS
+  // arena from the device.
+  plan.resident = false;
+  if (plan.exec_mode == 3 || plan.exec_mode == 0) {
+    bool ok = B == 1 && G == 1 && !plan.qgt && plan.lds_elems >= 1024;
+    for (size_t k = 0; ok && k < S.pend.size(); ++k) {
+      const PT& A = S.T[S.pend[k].a];
+      const PT& Bt = S.T[S.pend[k].b];
+      mark(pb, Bt.legs, true);
+      uint32_t sh = 0;
+      for (int32_t x : A.legs) sh += pb[x] >= 0;
+      mark(pb, Bt.legs, false);
+      if (gemm_node(1u << (A.legs.size() - sh), 1u << (Bt.legs.size() - sh), 1u << sh, 1)) ok = false;
+    }
+    if (plan.exec_mode == 3 && !ok)
+      fail(TC_ERR_UNSUPPORTED, "resident term launches need batch 1, one term group, no node for "
+                               "the GEMM path and a device LDS arena");
+    plan.resident = ok && plan.exec_mode == 3;
+  }
+  if (plan.resident)
+    for (auto& ts : term_step) ts.second = true;
   bool any_term = false, any_level = false;
   for (const auto& ts : term_step) (ts.second ? any_term : any_level) = true;
   if (any_term) {
@@ -769,16 +875,22 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     // automatic choice: only while the separate regions stay modest
     const bool fits = !plan.budget || St.arena_elems * 8 <= plan.budget;
     const bool modest = St.arena_elems <= std::max<uint64_t>(4 * S.arena_elems, uint64_t(1) << 25);
-    if (plan.exec_mode == 2 || (fits && modest)) {
+    if (plan.exec_mode == 2 || plan.exec_mode == 3 || (fits && modest)) {
       S = std::move(St);
     } else {
       for (auto& ts : term_step) ts.second = false;
       any_term = false;
       any_level = true;
+      plan.resident = false;
     }
   }
   plan.term_mode = any_term;
-  plan.exec_used = any_term ? (any_level ? 3 : 2) : 1;
+  plan.exec_used = plan.resident ? 4 : any_term ? (any_level ? 3 : 2) : 1;
+  if (plan.resident) {
+    if (S.arena_elems >= (uint64_t(1) << 32))
+      fail(TC_ERR_TOO_LARGE, "resident term launches address the global arena with 32-bit offsets");
+    place_lds(S.T, S.pend, S.root_step, plan.lds_elems, net.terms.size());
+  }
 
   plan.checkpoint_used = grad ? ckpt : 0;
   plan.arena_elems = S.arena_elems;
@@ -815,8 +927,9 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   bool seg_open = false, seg_bwd = false;
   int32_t seg_first_step = 0;
   size_t seg_begin = 0;
-  double seg_flops = 0, seg_bytes = 0;
+  double seg_flops = 0, seg_bytes = 0, seg_fflops = 0, seg_fbytes = 0;
   std::vector<uint32_t> group_term;
+  std::vector<char> group_bwd;
   auto close_segment = [&]() {
     if (!seg_open) return;
     // groups by term (stable: each term's steps stay in order), then one
@@ -827,12 +940,15 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
                      [&](size_t x, size_t y) { return group_term[x] < group_term[y]; });
     std::vector<DevGroup> gs;
     std::vector<uint32_t> gt;
+    std::vector<char> gb;
     for (size_t x : ord) {
       gs.push_back(plan.groups[x]);
       gt.push_back(group_term[x]);
+      gb.push_back(group_bwd[x]);
     }
     std::copy(gs.begin(), gs.end(), plan.groups.begin() + seg_begin);
     std::copy(gt.begin(), gt.end(), group_term.begin() + seg_begin);
+    std::copy(gb.begin(), gb.end(), group_bwd.begin() + seg_begin);
     Launch L;
     L.kind = L_TERM;
     L.step = seg_first_step;
@@ -847,20 +963,44 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       R.g_end = (uint32_t)g;
       plan.ranges.push_back(R);
     }
-    (seg_bwd ? plan.bwd : plan.fwd).push_back(L);
+    if (plan.resident) {
+      // one launch holds every step; calls without the gradient run each
+      // term's forward groups only (they precede its reverse-sweep groups)
+      Launch F = L;
+      F.resident = 1;
+      F.begin = (uint32_t)plan.ranges.size();
+      F.flops = seg_fflops;
+      F.bytes = seg_fbytes;
+      for (uint32_t t = 0; t < n_terms; ++t) {
+        DevRange R = plan.ranges[L.begin + t];
+        uint32_t e = R.g_begin;
+        while (e < R.g_end && !group_bwd[e]) ++e;
+        for (uint32_t x = e; x < R.g_end; ++x)
+          if (!group_bwd[x]) fail(TC_ERR_INVALID_ARG, "internal: forward group after the reverse sweep");
+        R.g_end = e;
+        plan.ranges.push_back(R);
+      }
+      plan.fwd.push_back(F);
+      if (grad) {
+        L.resident = 2;
+        plan.bwd.push_back(L);
+      }
+    } else {
+      (seg_bwd ? plan.bwd : plan.fwd).push_back(L);
+    }
     seg_open = false;
   };
   std::vector<int32_t> Sh, FA, FB;
   size_t i = 0;
   while (i < pend.size()) {
     const bool tstep = term_step.at(pend[i].step);
-    if (!tstep || (seg_open && seg_bwd != pend[i].bwd)) close_segment();
+    if (!tstep || (seg_open && !plan.resident && seg_bwd != pend[i].bwd)) close_segment();
     if (tstep && !seg_open) {
       seg_open = true;
       seg_bwd = pend[i].bwd;
       seg_first_step = pend[i].step;
       seg_begin = plan.groups.size();
-      seg_flops = seg_bytes = 0;
+      seg_flops = seg_bytes = seg_fflops = seg_fbytes = 0;
     }
     // a level step takes every term's ops at the step, a term step one term's
     size_t j = i;
@@ -869,6 +1009,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       ++j;
     const bool term_mode = tstep;
     std::vector<DevOp> gc, gm, wv, wd, rt;
+    std::vector<DevROp> gcr;  // resident plans: gc's nodes as resident records
     double lf = 0, lb = 0, gf = 0, gb = 0, wf = 0, wb = 0, rtf = 0, rtby = 0, sgf = 0, sgby = 0;
     for (size_t k = i; k < j; ++k) {
       const PT& A = T[pend[k].a];
@@ -1022,6 +1163,43 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           }
         }
         gc.push_back(op);
+        if (plan.resident) {
+          // where each operand is read at this step, and where C goes
+          const int32_t st = pend[k].step;
+          DevROp r{};
+          uint32_t shape = (uint32_t)__builtin_ctz(op.M) | ((uint32_t)__builtin_ctz(op.N) << 5) |
+                           ((uint32_t)__builtin_ctz(op.K) << 10) | (ls << 15) | (lv << 18);
+          auto src = [&](const PT& x, uint32_t flag) -> uint32_t {
+            if (x.lds_off >= 0 && st <= x.lds_last) {
+              shape |= flag;
+              return (uint32_t)x.lds_off;
+            }
+            if (!x.global || x.off < 0) fail(TC_ERR_INVALID_ARG, "internal: resident operand has no copy");
+            return (uint32_t)x.off;
+          };
+          r.a = src(A, RES_A_LDS);
+          r.b = src(Bt, RES_B_LDS);
+          if (C.lds_off >= 0) {
+            shape |= RES_C_LDS;
+            r.c = (uint32_t)C.lds_off;
+            if (C.global) {
+              shape |= RES_C2;
+              r.c2 = (uint32_t)C.off;
+            }
+          } else {
+            r.c = (uint32_t)C.off;
+          }
+          r.a_m = op.a_m;
+          r.a_k = op.a_k;
+          r.b_k = op.b_k;
+          r.b_n = op.b_n;
+          r.c_m = op.c_m;
+          r.c_n = op.c_n;
+          for (uint32_t d : {op.a_m, op.a_k, op.b_k, op.b_n, op.c_m, op.c_n})
+            if (d & IX_TABLE) shape |= RES_TABLES;
+          r.shape = shape;
+          gcr.push_back(r);
+        }
       }
     }
     Launch L;
@@ -1118,6 +1296,9 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     // their own (their partial sums go to the split region, slice-major,
     // and a reduction over 256-output chunks adds them)
     std::stable_partition(gc.begin(), gc.end(), [](const DevOp& op) { return op.ksplit == 1; });
+    if (plan.resident && (gcr.size() != gc.size() || !gm.empty() || !wv.empty() || !wd.empty() ||
+                          !rt.empty()))
+      fail(TC_ERR_INVALID_ARG, "internal: resident step with non-gather nodes");
     L.begin = (uint32_t)plan.ops.size();
     uint64_t w = 0;
     L.gsbegin = (uint32_t)plan.gsplit_units.size();
@@ -1138,6 +1319,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       }
       op.work0 = w;
       w += items;
+      if (plan.resident) {
+        if (op.ksplit != 1 || w >= (uint64_t(1) << 32))
+          fail(TC_ERR_INVALID_ARG, "internal: resident node items");
+        DevROp r = gcr[plan.ops.size() - L.begin];
+        r.work0 = (uint32_t)op.work0;
+        plan.rops.push_back(r);
+      }
       if (op.ksplit > 1) {
         op.part = part;
         part += groups * op.ksplit * 2;
@@ -1184,8 +1372,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       G.item_base = L.item_begin;
       plan.groups.push_back(G);
       group_term.push_back((uint32_t)pend[i].term);
+      group_bwd.push_back(pend[i].bwd ? 1 : 0);
       seg_flops += lf;
       seg_bytes += lb;
+      if (!pend[i].bwd) {
+        seg_fflops += lf;
+        seg_fbytes += lb;
+      }
     } else {
       (pend[i].bwd ? plan.bwd : plan.fwd).push_back(L);
     }
@@ -1212,6 +1405,11 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       const PT& x = T[ti[t].tid[li]];
       DevLeaf d{};
       d.out = (uint64_t)x.off;
+      d.where = 1;
+      if (plan.resident && x.lds_off >= 0) {
+        d.lds_out = (uint32_t)x.lds_off;
+        d.where = (x.global ? 1u : 0u) | 2u;
+      }
       d.work0 = lw;
       d.kind = lf.kind;
       d.part = lf.part;
@@ -1276,6 +1474,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
   }
   plan.fwd[0].bytes += 8.0 * (double)lw;  // every leaf entry written once
+  for (Launch& L : plan.bwd)  // a resident plan's launch with the reverse sweep
+    if (L.resident == 2) {
+      L.work = plan.fwd[0].work;
+      L.item_begin = plan.fwd[0].item_begin;
+      L.bytes += 8.0 * (double)lw;
+    }
 
   // ---- roots
   for (size_t t = 0; t < net.terms.size(); ++t) {
@@ -1493,6 +1697,38 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           if (plan.item_op[G.item_base + x] >= G.op_end - G.op_begin)
             fail(TC_ERR_INVALID_ARG, "internal: item table names a missing op");
       }
+    }
+    // resident plans: one record per gather op with the same shape, every
+    // operand inside the LDS arena or the global arena it names
+    if (plan.resident) {
+      const uint64_t LE = plan.lds_elems;
+      if (plan.rops.size() != plan.ops.size() || !LE)
+        fail(TC_ERR_INVALID_ARG, "internal: resident op records");
+      for (size_t o = 0; o < plan.rops.size(); ++o) {
+        const DevROp& r = plan.rops[o];
+        const DevOp& op = plan.ops[o];
+        const uint32_t sh = r.shape;
+        if ((1u << (sh & 31)) != op.M || (1u << ((sh >> 5) & 31)) != op.N ||
+            (1u << ((sh >> 10) & 31)) != op.K || ((sh >> 15) & 7) != ((op.flags >> 4) & 7u) ||
+            ((sh >> 18) & 3) != ((op.flags >> 8) & 3u) || r.work0 != op.work0 || op.rows != 1 ||
+            op.ksplit != 1 || r.a_m != op.a_m || r.a_k != op.a_k || r.b_k != op.b_k ||
+            r.b_n != op.b_n || r.c_m != op.c_m || r.c_n != op.c_n)
+          fail(TC_ERR_INVALID_ARG, "internal: resident record does not match its op");
+        const uint64_t a_end = (uint64_t)r.a + tmax(r.a_m, op.M) + tmax(r.a_k, op.K);
+        const uint64_t b_end = (uint64_t)r.b + tmax(r.b_k, op.K) + tmax(r.b_n, op.N);
+        const uint64_t c_ext = tmax(r.c_m, op.M) + tmax(r.c_n, op.N);
+        if (a_end >= ((sh & RES_A_LDS) ? LE : AE) || b_end >= ((sh & RES_B_LDS) ? LE : AE) ||
+            (uint64_t)r.c + c_ext >= ((sh & RES_C_LDS) ? LE : AE) ||
+            ((sh & RES_C2) && (!(sh & RES_C_LDS) || (uint64_t)r.c2 + c_ext >= AE)) ||
+            (!(sh & RES_C_LDS) && r.c < seed_elems) || ((sh & RES_C2) && r.c2 < seed_elems))
+          fail(TC_ERR_INVALID_ARG, "internal: resident op out of its arena");
+      }
+      for (const DevLeaf& d : plan.leaves)
+        if (!(d.where & 3u) || d.where > 3u ||
+            ((d.where & 2u) && (uint64_t)d.lds_out + (1ull << d.rank) > LE) || d.rows != 1)
+          fail(TC_ERR_INVALID_ARG, "internal: resident leaf out of the LDS arena");
+    } else if (!plan.rops.empty()) {
+      fail(TC_ERR_INVALID_ARG, "internal: resident records in a plan without resident launches");
     }
     for (const DevTerm& D : plan.terms)
       if (D.leaf_begin > D.leaf_end || D.leaf_end > plan.leaves.size() ||

@@ -67,6 +67,9 @@ struct Launch {
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
   uint64_t wunit_begin = NO_ITEMS;  // per-wave-tile op index table in Plan::item_op
   bool with_leaves = false;       // L_TERM: materialise the leaves first
+  // resident term launches: 1 the forward pass alone (calls without the
+  // gradient), 2 the forward pass and reverse sweep (calls with it)
+  int32_t resident = 0;
   double flops = 0;               // algorithmic flops (8 per complex MAC)
   double bytes = 0;               // algorithmic bytes: operands read + results written
   double gemm_flops = 0;          // the part of flops / bytes in GEMM tiles
@@ -98,11 +101,16 @@ struct Plan {
   // 128 x 128 tiles for GEMM nodes with dense operands: 0 never, 1 when
   // they give at least one tile per CU, 2 always
   int32_t wide_tiles = 1;
-  // execution: 0 = term mode when every node is a gather and batch is 1,
-  // 1 = level-synchronous launches, 2 = term mode (all nodes as gathers)
+  // execution: 0 = automatic, 1 = level-synchronous launches, 2 = term
+  // mode (all nodes as gathers), 3 = resident term launches
   int32_t exec_mode = 0;
+  // complex elements of one workgroup's LDS arena for resident term
+  // launches (set by the executor from the device; 0 = none)
+  uint32_t lds_elems = 0;
+  bool resident = false;    // resident term launches (batch 1, gathers only)
   bool term_mode = false;   // some steps run in term launches
-  int32_t exec_used = 1;    // 1 level launches only, 2 term launches only, 3 both
+  int32_t exec_used = 1;    // 1 level launches only, 2 term launches only, 3 both,
+                            // 4 resident term launches
   // checkpoint segment length: 0 = only when the budget requires it,
   // >= 2 = always with that length, -1 = never
   int32_t checkpoint = 0;
@@ -127,6 +135,7 @@ struct Plan {
   std::vector<DevTerm> terms;         // term launches: each term's leaves
   std::vector<DevGroup> groups;       // term launches: a term's nodes at one step
   std::vector<DevRange> ranges;       // term launches: each term's groups, per launch
+  std::vector<DevROp> rops;           // resident term launches: the nodes (groups index them)
   std::vector<DevSplitUnit> split_units;  // split-K output tiles, per level
   std::vector<DevSplitUnit> gsplit_units; // split gather outputs, per level
   std::vector<float> seeds;           // (re, im) per term, arena offset 0
@@ -156,7 +165,7 @@ std::vector<const Launch*> launch_order(const Plan& p, bool with_grad);
 
 // Byte layout of the workspace: [tables][params][values][grad][arena]
 struct WorkspaceLayout {
-  uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots, terms, groups, ranges;
+  uint64_t ops, tabs, item_op, leaves, ftab, uses, slot_begin, roots, terms, groups, ranges, rops;
   uint64_t split, sunits, gsunits;  // split-K partials (float), units to reduce
   uint64_t qslot, qrows;             // qgt: slot -> rows tables
   uint64_t params, value, grad, qgt, arena, total;

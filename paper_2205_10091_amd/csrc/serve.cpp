@@ -327,7 +327,7 @@ tc_status tc_serve_submit(tc_server* srv, const tc_circuit* circuit,
     if (it != S.cache.end()) plan = it->second;
   }
   if (!plan) {
-    tc_path_opts po{0x5eed, S.opts.path_trials, TC_SCORE_COMBO, 0.1, 0};
+    tc_path_opts po{0x5eed, S.opts.path_trials, TC_SCORE_COMBO, 0.1, 0, 0};
     tcx::Path path = tcx::greedy_path(net, po);
     auto make = [&](int32_t wide_tiles, const tcx::Network& nw, const tcx::Path& pa) {
       auto p = std::make_shared<tcx::Plan>();
