@@ -424,7 +424,13 @@ def main():
         else:
             circ, P, obs = tcgen.workload_batched_vqe(batch=B)
         t0 = time.perf_counter()
-        plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=chain_trials, seed=1)
+        # batch 1 is launch bound: the depth cap that the path finder's time
+        # model prefers trades a few flops of the deepest terms for fewer
+        # dependent launches; a batched sweep is flop bound and keeps the
+        # cheapest trees
+        depth = -1 if B == 1 else 0
+        plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=chain_trials, seed=1,
+                           max_depth=depth)
         plan_s = time.perf_counter() - t0
         params = torch.from_numpy(np.ascontiguousarray(P.reshape(-1))).to(dev)
         info = plan.info()
@@ -450,7 +456,8 @@ def main():
             "dtype": "c64 (fp32) + fp64 sums",
             "config": {"workload": f"vqe_chain_n20_L6_tfim_energy_grad_batch{B}",
                        "n_qubits": 20, "layers": 6, "n_params": 240, "n_terms": 39,
-                       "batch": B, "path_trials": chain_trials},
+                       "batch": B, "path_trials": chain_trials,
+                       "path_depth_cap": "auto (time model)" if depth < 0 else "none"},
             "achieved_tflops": (info.flops + info.grad_flops) / (dt / args.steps) / 1e12,
             "outputs": "E and dE/dtheta left in HBM (device-side optimiser form)"})
         prof = plan.profile(params, which=1, reps=20 if B == 1 else 2)

@@ -125,7 +125,7 @@ tc_status tc_greedy_path(const tc_network* net, const tc_path_opts* opts,
   if (o.n_trials < 1) tcx::fail(TC_ERR_INVALID_ARG, "n_trials must be >= 1");
   if (o.score < 0 || o.score > 4) tcx::fail(TC_ERR_INVALID_ARG, "unknown score");
   if (o.reconf_k < 0 || o.reconf_k > 10) tcx::fail(TC_ERR_INVALID_ARG, "reconf_k must be 0..10");
-  if (o.max_depth < 0) tcx::fail(TC_ERR_INVALID_ARG, "max_depth must be >= 0");
+  if (o.max_depth < -1) tcx::fail(TC_ERR_INVALID_ARG, "max_depth must be -1, 0 or a depth");
   auto* p = new tc_path;
   p->path = tcx::greedy_path(net->net, o);
   p->terms = net->net.terms;

@@ -90,6 +90,7 @@ struct TermPath {
 struct Path {
   std::vector<TermPath> terms;
   tc_path_opts opts{};
+  int32_t depth_cap = 0;  // the tree depth cap used (0 = none)
 };
 
 struct TreeStats {

@@ -454,29 +454,82 @@ TreeStats tree_stats(const Term& term, const TermPath& tp) {
   return st;
 }
 
+// Depth choice (tc_path_opts.max_depth = -1).  A plan runs one dependent
+// launch per tree level of its deepest term (twice with the reverse
+// sweep), and each costs about LEVEL_SECONDS whatever its size, while the
+// small gather nodes of such trees run at about 1 / FLOP_SECONDS flop/s:
+// the cap D minimises D LEVEL_SECONDS + flops(D) FLOP_SECONDS over the
+// depths the candidates offer (measured on the 20-qubit chain of the VQE
+// workload: removing a level saved about 4 us per pass, extra flops cost
+// about 0.45 ps each).
+constexpr double LEVEL_SECONDS = 4e-6, FLOP_SECONDS = 4.5e-13;
+
+namespace {
+
+// One term's candidates: the best tree found at each depth, with the offer
+// order (ties go to the earlier offer, as with a single running best).
+struct TreeCand {
+  double score = 0, flops = 0, size = 0;
+  int32_t depth = 0;
+  int64_t seq = 0;
+  TermPath tp;
+};
+
+// candidate x beats y under the cap (cap <= 0: no cap): within the cap
+// first, then the shallower, then the score, then the earlier offer
+bool beats(const TreeCand& x, const TreeCand& y, int32_t cap) {
+  if (cap > 0) {
+    const bool ok = x.depth <= cap, yok = y.depth <= cap;
+    if (ok != yok) return ok;
+    if (!ok && x.depth != y.depth) return x.depth < y.depth;
+  }
+  if (x.score != y.score) return x.score < y.score;
+  return x.seq < y.seq;
+}
+
+const TreeCand& pick(const std::vector<TreeCand>& front, int32_t cap) {
+  size_t b = 0;
+  for (size_t i = 1; i < front.size(); ++i)
+    if (beats(front[i], front[b], cap)) b = i;
+  return front[b];
+}
+
+}  // namespace
+
 Path greedy_path(const Network& net, const tc_path_opts& opts) {
   Path path;
   path.opts = opts;
   int trials = std::max(1, opts.n_trials);
+  std::vector<std::vector<TreeCand>> fronts(net.terms.size());
   for (size_t t = 0; t < net.terms.size(); ++t) {
     const Term& term = net.terms[t];
+    std::vector<TreeCand>& front = fronts[t];
+    int64_t seq = 0;
+    // keeps tp if it is the best so far at its depth
+    auto offer = [&](TermPath&& tp, const TreeStats& st, double sc) {
+      TreeCand c;
+      c.score = sc;
+      c.flops = st.flops;
+      c.size = st.size;
+      c.depth = st.depth;
+      c.seq = seq++;
+      for (TreeCand& f : front)
+        if (f.depth == c.depth) {
+          if (c.score < f.score) {
+            c.tp = std::move(tp);
+            f = std::move(c);
+          }
+          return;
+        }
+      c.tp = std::move(tp);
+      front.push_back(std::move(c));
+    };
     // the trials are independent (each seeds its own generator from the
     // seed, the term and the trial number): they run on up to 16 host
-    // threads, and the best score wins, ties to the lowest trial number, so
-    // the result does not depend on the thread count
+    // threads and are offered in trial order, so the result does not
+    // depend on the thread count
     std::vector<TermPath> found(trials);
-    std::vector<double> score(trials, 0.0);
-    std::vector<int32_t> tdepth(trials, 0);
-    // candidate (score sc, depth d) beats the current best (bsc, bd): under
-    // a depth cap, within the cap first, then the shallower, then the score
-    const int32_t cap = opts.max_depth;
-    auto better = [cap](double sc, int32_t d, double bsc, int32_t bd) {
-      if (cap <= 0) return sc < bsc;
-      const bool ok = d <= cap, bok = bd <= cap;
-      if (ok != bok) return ok;
-      if (!ok && d != bd) return d < bd;
-      return sc < bsc;
-    };
+    std::vector<TreeStats> tstat(trials);
     auto run_trial = [&](int trial) {
       Search s;
       s.init(term);
@@ -495,9 +548,7 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
       TermPath& tp = found[trial];
       tp.n_leaves = (int32_t)term.leaves.size();
       tp.pairs = std::move(s.pairs);
-      const TreeStats ts = tree_stats(term, tp);
-      score[trial] = score_of(ts, opts.score);
-      tdepth[trial] = ts.depth;
+      tstat[trial] = tree_stats(term, tp);
     };
     const int n_threads =
         std::min(trials, std::max(1, std::min(16, (int)std::thread::hardware_concurrency())));
@@ -522,21 +573,17 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
       for (auto& th : pool) th.join();
       if (err) std::rethrow_exception(err);
     }
-    int best_trial = 0;
-    for (int trial = 1; trial < trials; ++trial)
-      if (better(score[trial], tdepth[trial], score[best_trial], tdepth[best_trial])) best_trial = trial;
-    TermPath best = std::move(found[best_trial]);
-    double best_score = score[best_trial];
-    int32_t best_depth = tdepth[best_trial];
+    for (int trial = 0; trial < trials; ++trial)
+      offer(std::move(found[trial]), tstat[trial], score_of(tstat[trial], opts.score));
     // One more candidate: the time-ordered sweep of a state-vector
-    // simulation, kept when it scores better.  The unconjugated leaves
-    // (boundary vectors, gates in circuit order, Pauli matrices or output
-    // bras) are absorbed one by one into a single growing tensor, then the
-    // conjugated copy from its last gate back to its boundary vectors, so
-    // the tensor never holds more than the light cone's open wires (plus a
-    // split gate's bond).  On two-dimensional circuits, where greedy merging
-    // of the doubled network can open far more legs, this bounds the largest
-    // intermediate by 2^(qubits in the light cone).
+    // simulation.  The unconjugated leaves (boundary vectors, gates in
+    // circuit order, Pauli matrices or output bras) are absorbed one by one
+    // into a single growing tensor, then the conjugated copy from its last
+    // gate back to its boundary vectors, so the tensor never holds more
+    // than the light cone's open wires (plus a split gate's bond).  On
+    // two-dimensional circuits, where greedy merging of the doubled network
+    // can open far more legs, this bounds the largest intermediate by
+    // 2^(qubits in the light cone).
     if (term.leaves.size() > 1) {
       std::vector<int32_t> order;
       for (int32_t i = 0; i < (int32_t)term.leaves.size(); ++i)
@@ -550,13 +597,8 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
         tp.pairs.push_back({cur, order[k]});
         cur = tp.n_leaves + (int32_t)tp.pairs.size() - 1;
       }
-      const TreeStats ts = tree_stats(term, tp);
-      const double sc = score_of(ts, opts.score);
-      if (better(sc, ts.depth, best_score, best_depth)) {
-        best = std::move(tp);
-        best_score = sc;
-        best_depth = ts.depth;
-      }
+      const TreeStats st = tree_stats(term, tp);
+      offer(std::move(tp), st, score_of(st, opts.score));
     }
     // Two spatial candidates, wire by wire (on each wire: ket gates in time
     // order, the observable's leaves, the conjugated gates from the last
@@ -569,7 +611,7 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
     // They are scored under the time score, or when the best path so far
     // has an intermediate above 2^28 elements (other plans stay as found).
     if (term.leaves.size() > 2 &&
-        (opts.score == TC_SCORE_TIME || tree_stats(term, best).size > std::ldexp(1.0, 28))) {
+        (opts.score == TC_SCORE_TIME || pick(front, 0).size > std::ldexp(1.0, 28))) {
       const int32_t nl = (int32_t)term.leaves.size();
       int32_t max_q = 0;
       for (const Leaf& lf : term.leaves) max_q = std::max(max_q, lf.qubit);
@@ -628,24 +670,61 @@ Path greedy_path(const Network& net, const tc_path_opts& opts) {
           }
         }
         const TreeStats st = tree_stats(term, tp);
-        const double sc = score_of(st, opts.score);
         // (a candidate whose largest intermediate the executor cannot hold
         // is never kept)
-        if (st.size <= std::ldexp(1.0, 31) && better(sc, st.depth, best_score, best_depth)) {
-          best = std::move(tp);
-          best_score = sc;
-          best_depth = st.depth;
-        }
+        if (st.size <= std::ldexp(1.0, 31)) offer(std::move(tp), st, score_of(st, opts.score));
       }
     }
-    if (opts.reconf_k >= 3 && best.pairs.size() >= 2) {
-      TermPath r = reconfigure(term, best, std::min(opts.reconf_k, 10), 4);
-      const TreeStats st = tree_stats(term, r);
-      if (st.size <= std::ldexp(1.0, 31) &&
-          better(score_of(st, opts.score), st.depth, best_score, best_depth))
+  }
+  // the depth cap: as given, or the one the time model prefers
+  int32_t cap = opts.max_depth;
+  if (cap < 0) {
+    std::vector<int32_t> depths;
+    for (const auto& front : fronts)
+      for (const TreeCand& c : front) depths.push_back(c.depth);
+    std::sort(depths.begin(), depths.end());
+    depths.erase(std::unique(depths.begin(), depths.end()), depths.end());
+    double best_t = 0;
+    cap = 0;
+    for (auto it = depths.rbegin(); it != depths.rend(); ++it) {
+      double flops = 0;
+      int32_t levels = 0;
+      for (const auto& front : fronts) {
+        if (front.empty()) continue;
+        const TreeCand& c = pick(front, *it);
+        flops += c.flops;
+        levels = std::max(levels, c.depth);
+      }
+      const double tm = levels * LEVEL_SECONDS + flops * FLOP_SECONDS;
+      if (cap == 0 || tm < best_t) {
+        best_t = tm;
+        cap = *it;
+      }
+    }
+  }
+  path.depth_cap = cap;
+  for (size_t t = 0; t < net.terms.size(); ++t) {
+    const Term& term = net.terms[t];
+    if (fronts[t].empty()) {  // a network without leaves
+      TermPath tp;
+      tp.n_leaves = (int32_t)term.leaves.size();
+      path.terms.push_back(std::move(tp));
+      continue;
+    }
+    TreeCand best = pick(fronts[t], cap);
+    if (opts.reconf_k >= 3 && best.tp.pairs.size() >= 2) {
+      TreeCand r;
+      r.tp = reconfigure(term, best.tp, std::min(opts.reconf_k, 10), 4);
+      const TreeStats st = tree_stats(term, r.tp);
+      r.score = score_of(st, opts.score);
+      r.depth = st.depth;
+      r.seq = -1;  // ties: the reconfigured tree stays out
+      if (st.size <= std::ldexp(1.0, 31) && beats(r, best, cap) && r.score < best.score)
+        best = std::move(r);
+      else if (st.size <= std::ldexp(1.0, 31) && cap > 0 && best.depth > cap && r.depth < best.depth)
         best = std::move(r);
     }
-    path.terms.push_back(std::move(best));
+    path.terms.push_back(std::move(best.tp));
   }
   return path;
 }

@@ -338,3 +338,25 @@ def test_slicing_expectation_and_limits():
     with pytest.raises(L.TcxError) as e:
         path.sliced(2, max_labels=1)
     assert e.value.status == L.TC_ERR_TOO_LARGE
+
+
+def test_depth_cap_trades_flops_for_levels():
+    """tc_path_opts.max_depth: a cap below the free choice's depth gives
+    shallower trees for at least as many flops; -1 picks a cap from the
+    candidates; below -1 is rejected."""
+    circ, _, obs = tcgen.workload_vqe_chain(n=14, layers=5)
+    net = api.Network(circ, obs)
+    free = api.Path(net, seed=1, n_trials=64)
+    d0, f0 = free.stats().max_depth, free.stats().flops
+    capped = api.Path(net, seed=1, n_trials=64, max_depth=d0 - 3)
+    assert capped.stats().max_depth <= d0 - 3
+    assert capped.stats().flops >= f0
+    for t in range(net.info().n_terms):
+        assert capped.stats(t).max_depth <= max(d0 - 3, 1) or capped.stats(t).max_depth <= free.stats(t).max_depth
+    auto = api.Path(net, seed=1, n_trials=64, max_depth=-1)
+    assert auto.stats().max_depth <= d0
+    same = api.Path(net, seed=1, n_trials=64, max_depth=0)
+    for t in range(net.info().n_terms):
+        np.testing.assert_array_equal(same.pairs(t), free.pairs(t))
+    with pytest.raises(L.TcxError):
+        api.Path(net, seed=1, n_trials=4, max_depth=-2)
