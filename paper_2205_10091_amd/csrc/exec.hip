@@ -75,6 +75,7 @@ struct LevelSeg {
   uint64_t wide_start;      // first wide tile of this segment
   uint32_t n_wide;
   const DevOp* rt_ops;      // row-tile ops (batched small nodes)
+  const uint32_t* rt_unit_op;  // row-tile workgroup -> op index, or null (search)
   uint64_t rt_start;        // first row-tile workgroup of this segment
   uint32_t n_rt;
   const DevOp* gs_ops;      // split gather ops (V == 1), in their own work space
@@ -596,11 +597,12 @@ __global__ void __launch_bounds__(256) k_reduce_g(LevelArgs a) {
 // operand is copied once), then computes the rows' M N outputs each from
 // LDS, k in increasing order, and stores them.
 __global__ void __launch_bounds__(256) k_rowtile(LevelArgs a) {
-  __shared__ float2 buf[ROW_TILE_ELEMS];
+  __shared__ float2 buf[ROW_TILE_LDS];
   const uint64_t b = blockIdx.x;
   const LevelSeg& S = a.seg[find_seg(a, b, [](const LevelSeg& s) { return s.rt_start; })];
   const uint64_t lb = b - S.rt_start;
-  const uint32_t oi = __builtin_amdgcn_readfirstlane(find_item(S.rt_ops, S.n_rt, lb));
+  const uint32_t oi = __builtin_amdgcn_readfirstlane(
+      S.rt_unit_op ? S.rt_unit_op[lb] : find_item(S.rt_ops, S.n_rt, lb));
   const DevOp op = S.rt_ops[oi];
   const uint32_t rpb = op.tiles_m;
   const uint64_t r0 = (lb - op.work0) * rpb;
@@ -610,12 +612,26 @@ __global__ void __launch_bounds__(256) k_rowtile(LevelArgs a) {
   const int t = threadIdx.x;
   const float2* __restrict__ A = S.arena + op.a + r0 * op.a_bs;
   const float2* __restrict__ B = S.arena + op.b + r0 * op.b_bs;
-  // rows r0 .. r0 + nr - 1 of A, then of B (row stride a_bs, b_bs)
+  // rows r0 .. r0 + nr - 1 of A, then of B (row stride a_bs, b_bs): all of
+  // a thread's loads (at most ROW_TILE_LDS / 256) are issued before the
+  // first LDS store, so the copy costs one memory round trip
   const uint32_t lmk = __builtin_ctz(MK), lkn = __builtin_ctz(KN);
-  for (uint32_t e = t; e < ra * MK; e += 256)
-    buf[e] = A[(uint64_t)(e >> lmk) * op.a_bs + (e & (MK - 1))];
-  for (uint32_t e = t; e < rb * KN; e += 256)
-    buf[ra * MK + e] = B[(uint64_t)(e >> lkn) * op.b_bs + (e & (KN - 1))];
+  const uint32_t na = ra * MK, ntot = na + rb * KN;
+  constexpr uint32_t PER = ROW_TILE_LDS / 256;
+  float2 v[PER];
+#pragma unroll
+  for (uint32_t q = 0; q < PER; ++q) {
+    const uint32_t e = t + q * 256;
+    if (e < na)
+      v[q] = A[(uint64_t)(e >> lmk) * op.a_bs + (e & (MK - 1))];
+    else if (e < ntot)
+      v[q] = B[(uint64_t)((e - na) >> lkn) * op.b_bs + ((e - na) & (KN - 1))];
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < PER; ++q) {
+    const uint32_t e = t + q * 256;
+    if (e < ntot) buf[e] = v[q];
+  }
   __syncthreads();
   const uint32_t lmn = __builtin_ctz(MN), ln = __builtin_ctz(op.N);
   for (uint32_t o = t; o < nr * MN; o += 256) {
@@ -1212,6 +1228,9 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.gc_ops = ops + s.launch->begin;
         g.n_gc = s.launch->xbegin - s.launch->begin;
         g.rt_ops = ops + s.launch->rbegin;
+        g.rt_unit_op = s.launch->rtunit_begin != NO_ITEMS
+                           ? (const uint32_t*)(s.ws + L.item_op) + s.launch->rtunit_begin
+                           : nullptr;
         g.n_rt = s.launch->rend - s.launch->rbegin;
         g.rt_start = rtblocks;
         rtblocks += s.launch->rblocks;

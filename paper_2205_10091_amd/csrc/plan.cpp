@@ -1132,10 +1132,11 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         // into LDS once (coalesced: a row of a batched tensor is one block)
         // and computes their outputs from there, where gather items would
         // re-read the shared operand once per output group.  RPB (in
-        // tiles_m) is the largest power of two <= 64 whose rows fit.
+        // tiles_m) is the largest power of two <= ROW_TILE_ROWS whose rows
+        // fit ROW_TILE_LDS.
         const uint64_t per_row = (uint64_t)op.M * op.K + (uint64_t)op.K * op.N;
         uint32_t rpb = 1;
-        while (rpb < 64 && 2 * rpb * per_row <= ROW_TILE_ELEMS) rpb *= 2;
+        while (rpb < ROW_TILE_ROWS && 2 * rpb * per_row <= ROW_TILE_LDS) rpb *= 2;
         op.tiles_m = rpb;
         op.tiles_n = (op.rows + rpb - 1) / rpb;
         rt.push_back(op);
@@ -1345,6 +1346,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       plan.ops.push_back(op);
     }
     L.rend = (uint32_t)plan.ops.size();
+    if (L.rblocks && L.rblocks <= WAVE_TABLE_MAX &&
+        plan.item_op.size() + L.rblocks <= ITEM_TABLES_TOTAL_MAX) {
+      // row-tile workgroup -> op (relative to L.rbegin): one load instead of
+      // a search over the level's (often thousands of) row-tile ops
+      L.rtunit_begin = plan.item_op.size();
+      plan.item_op.resize(plan.item_op.size() + L.rblocks);
+      uint32_t* it = plan.item_op.data() + L.rtunit_begin;
+      for (uint32_t o = L.rbegin; o < L.rend; ++o)
+        for (uint64_t x = plan.ops[o].work0; x < plan.ops[o].work0 + plan.ops[o].tiles_n; ++x)
+          it[x] = o - L.rbegin;
+    }
     if (!in_split) {
       L.xbegin = L.end;
       L.work = (w + 63) & ~uint64_t(63);
@@ -1621,8 +1633,8 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         for (uint32_t o = L.rbegin; o < L.rend; ++o) {
           const DevOp& op = plan.ops[o];
           const uint64_t rpb = op.tiles_m;
-          if (rpb < 1 || rpb > 64 || (rpb & (rpb - 1)) || op.rows < 1 ||
-              rpb * ((uint64_t)op.M * op.K + (uint64_t)op.K * op.N) > ROW_TILE_ELEMS ||
+          if (rpb < 1 || rpb > ROW_TILE_ROWS || (rpb & (rpb - 1)) || op.rows < 1 ||
+              rpb * ((uint64_t)op.M * op.K + (uint64_t)op.K * op.N) > ROW_TILE_LDS ||
               op.tiles_n != (op.rows + rpb - 1) / rpb || op.ksplit != 1 ||
               op.work0 != (o == L.rbegin ? 0 : plan.ops[o - 1].work0 + plan.ops[o - 1].tiles_n))
             fail(TC_ERR_INVALID_ARG, "internal: row-tile op");
@@ -1752,6 +1764,17 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           auto pow2 = [](uint64_t v) { return v && !(v & (v - 1)); };
           if (!pow2(op.tiles_m) || !pow2(op.tiles_n) || !pow2(op.ksplit))
             fail(TC_ERR_INVALID_ARG, "internal: tile grid not in powers of two");
+        }
+        if (L.rtunit_begin != NO_ITEMS) {
+          if (L.rtunit_begin + L.rblocks > plan.item_op.size())
+            fail(TC_ERR_INVALID_ARG, "internal: row-tile table out of range");
+          for (uint64_t x = 0; x < L.rblocks; ++x) {
+            const uint32_t o = plan.item_op[L.rtunit_begin + x];
+            if (o >= L.rend - L.rbegin) fail(TC_ERR_INVALID_ARG, "internal: row-tile table names a missing op");
+            const DevOp& op = plan.ops[L.rbegin + o];
+            if (x < op.work0 || x >= op.work0 + op.tiles_n)
+              fail(TC_ERR_INVALID_ARG, "internal: row-tile table entry outside its op");
+          }
         }
         if (L.wunit_begin == NO_ITEMS) continue;
         if (L.wunit_begin + L.wtiles > plan.item_op.size())

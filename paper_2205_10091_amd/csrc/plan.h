@@ -43,6 +43,10 @@ constexpr uint32_t SMALL_WAVE_MIN_ROWS = 64;
 // row tiles: a workgroup stages whole batch rows of both operands in LDS,
 // at most this many complex elements (16 KB)
 constexpr uint32_t ROW_TILE_ELEMS = 2048;
+// ... and a workgroup stages up to this many rows' operands at once, at
+// most ROW_TILE_LDS complex elements (16 KB; measured on the 1024-row VQE
+// sweep, 128 rows in 32 KB ran the row tiles 7 % slower)
+constexpr uint32_t ROW_TILE_ROWS = 64, ROW_TILE_LDS = 2048;
 // index tables of one plan (uint32 entries)
 constexpr uint64_t TABLE_MAX_ENTRIES = uint64_t(1) << 27;
 
@@ -66,6 +70,7 @@ struct Launch {
   uint32_t gsbegin = 0, gsend = 0;  // split gather outputs (256 a unit), in Plan::gsplit_units
   uint64_t item_begin = NO_ITEMS; // per-item op index table in Plan::item_op
   uint64_t wunit_begin = NO_ITEMS;  // per-wave-tile op index table in Plan::item_op
+  uint64_t rtunit_begin = NO_ITEMS; // per-row-tile-workgroup op index table in Plan::item_op
   bool with_leaves = false;       // L_TERM: materialise the leaves first
   // resident term launches: 1 the forward pass alone (calls without the
   // gradient), 2 the forward pass and reverse sweep (calls with it)
