@@ -81,6 +81,23 @@ def test_vqe_chain_energy_and_gradient():
     assert abs(v.real - e[0]) < 1e-6 and abs(v.imag) < TOL_C64
 
 
+def test_vqe_chain_in_the_benchmark_configuration():
+    """The plan the benchmark times: 1024 path trials and the depth cap of
+    the path finder's time model, device-resident outputs."""
+    import torch
+    circ, p, obs = tcgen.workload_vqe_chain()
+    plan = api.compile(circ, obs, want_grad=True, n_trials=1024, seed=1, max_depth=-1)
+    info = plan.info()
+    assert info.n_levels <= 18
+    e_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    g_dev = torch.empty(circ.n_params, dtype=torch.float64, device="cuda")
+    plan.contract_grad_device(device_params(p), e_dev, g_dev)
+    e_ref, g_ref = sv.energy_grad(circ, p, obs)
+    print(f"benchmark plan: {info.n_levels} levels, |dE| {abs(e_dev.item() - e_ref):.2e}")
+    assert rel_err(e_dev.item(), e_ref, 1.0) < TOL_C64
+    assert_grad(g_dev.cpu().numpy(), g_ref, TOL_C64, "benchmark plan")
+
+
 def test_vqe_gradient_vs_parameter_shift_and_fd_on_gpu():
     """The GPU gradient against the GPU's own energies at shifted angles:
     the exact two-point shift rule and central differences (h = 1e-3)."""
