@@ -951,7 +951,10 @@ __global__ void __launch_bounds__(1024) k_term_res(TermArgs a) {
   };
   fetch(R.g_begin);
   // the term's leaves, at batch row 0, into LDS and / or the global arena
-  for (uint64_t w = T.leaf_work0 + threadIdx.x; w < T.leaf_work_end; w += blockDim.x) {
+  // (only in the launch that materialises them: a later run's LDS arena
+  // and the leaves' freed global regions hold other tensors by then)
+  for (uint64_t w = T.leaf_work0 + threadIdx.x; a.with_leaves && w < T.leaf_work_end;
+       w += blockDim.x) {
     const uint32_t li =
         a.item_leaf ? a.item_leaf[w] : find_in(a.leaves, T.leaf_begin, T.leaf_end, w);
     const DevLeaf& L = a.leaves[li];
@@ -1341,7 +1344,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       a.arena = (float2*)(s.ws + L.arena);
       a.param_stride = P.param_stride();
       a.with_leaves = s.launch->with_leaves ? 1 : 0;
-      if (P.resident) {
+      if (s.launch->resident) {
         a.rops = (const DevROp*)(s.ws + L.rops);
         launch_shm(k_term_res, dim3((unsigned)P.terms.size()), dim3(1024),
                    (size_t)P.lds_elems * sizeof(float2), stream, a);

@@ -10,7 +10,6 @@
 //   g++ -std=c++17 -g -O1 -fsanitize=address,undefined -fno-omit-frame-pointer \
 //       -I include paper_2205_10091_amd/csrc/{network,path,plan,slice,capi_host,host_check}.cpp
 #include <cmath>
-#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -29,6 +28,7 @@ namespace {
 
 int failures = 0;
 int resident_checked = 0;
+int runs_checked = 0;
 
 void expect(bool ok, const std::string& what) {
   if (!ok) {
@@ -154,15 +154,40 @@ Obs mpo_random(int n) {
   return x;
 }
 
-// Resident term launches, executed on the host: every term's leaves and
-// nodes in step order, operands taken from a per-term LDS arena or the
-// global arena as the resident records say (`res`), or from the global
-// arena through the plain op records (the reference).  Memory starts as
-// NaN, so a read of anything not yet written shows in the results; the
-// nodes of a step run first to last or last to first (`rev`), so a node
-// that overwrote another's operand within one step would change them.
-// Returns the term roots and the leaf adjoints the gradient reads.
-using cd = std::complex<double>;
+// Resident term launches, executed on the host: every launch of the
+// sequence in order, the nodes of resident term launches with operands
+// taken from a per-workgroup LDS arena or the global arena as their
+// resident records say (`res`), everything else from the global arena
+// through the plain op records (the reference).  The arithmetic is the
+// contraction's sums of products over the integers modulo the prime
+// 2^61 - 1 (exact, no overflow on networks of any length), with leaves and
+// seeds hashed from their indices; memory starts as a poison value that
+// every product with it keeps, so a read of anything not yet written shows
+// in the results.  The nodes of a step run first to last or last to first
+// (`rev`), so a node that overwrote another's operand within one step
+// would change them.  Returns the term roots and the leaf adjoints the
+// gradient reads.
+using val = uint64_t;
+constexpr val MOD = (uint64_t(1) << 61) - 1, POISON = ~uint64_t(0);
+
+val vmul(val a, val b) {
+  if (a == POISON || b == POISON) return POISON;
+  const unsigned __int128 x = (unsigned __int128)a * b;
+  val r = (val)(x & MOD) + (val)(x >> 61);
+  return r >= MOD ? r - MOD : r;
+}
+val vadd(val a, val b) {
+  if (a == POISON || b == POISON) return POISON;
+  const val r = a + b;
+  return r >= MOD ? r - MOD : r;
+}
+val vhash(uint64_t a, uint64_t b) {
+  uint64_t x = a * 0x9E3779B97F4A7C15ull ^ (b + 0x7F4A7C159E3779B9ull);
+  x ^= x >> 31;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 29;
+  return x % MOD;
+}
 
 uint64_t ix_of(const std::vector<uint32_t>& tabs, uint32_t d, uint64_t i) {
   if (d & 0x80000000u) return tabs.at((d & 0x7fffffffu) + i);
@@ -176,60 +201,69 @@ uint64_t ix_of(const std::vector<uint32_t>& tabs, uint32_t d, uint64_t i) {
   return off;
 }
 
-std::vector<cd> run_resident(const tcx::Plan& p, bool res, bool grad, bool rev) {
-  const double nan = std::nan("");
-  std::vector<cd> G(p.arena_elems, cd(nan, nan)), L;
-  for (size_t t = 0; t < p.seeds.size() / 2; ++t) G.at(t) = cd(p.seeds[2 * t], p.seeds[2 * t + 1]);
-  const tcx::Launch* term_launch = nullptr;
-  for (const tcx::Launch* x : tcx::launch_order(p, grad))
-    if (x->kind == tcx::L_TERM) term_launch = x;
-  if (!term_launch) return {};
-  for (size_t t = 0; t < p.terms.size(); ++t) {
-    L.assign(p.lds_elems, cd(nan, nan));
-    for (uint32_t li = p.terms[t].leaf_begin; li < p.terms[t].leaf_end; ++li) {
-      const tcx::DevLeaf& d = p.leaves[li];
-      for (uint64_t e = 0; e < (uint64_t(1) << d.rank); ++e) {
-        const cd v(std::sin(0.7 * li + 0.3 * e), std::cos(0.11 * li - 0.5 * e));
-        if (!res || (d.where & 1u)) G.at(d.out + e) = v;
-        if (res && (d.where & 2u)) L.at(d.lds_out + e) = v;
-      }
+std::vector<val> run_resident(const tcx::Plan& p, bool res, bool grad, bool rev) {
+  std::vector<val> G(p.arena_elems, POISON), L;
+  for (size_t t = 0; t < p.seeds.size() / 2; ++t) G.at(t) = vhash(1000003 + t, 7);
+  auto leaf = [&](uint32_t li, bool use_where) {
+    const tcx::DevLeaf& d = p.leaves[li];
+    for (uint64_t e = 0; e < (uint64_t(1) << d.rank); ++e) {
+      const val v = vhash(li, e);
+      if (!use_where || (d.where & 1u)) G.at(d.out + e) = v;
+      if (use_where && (d.where & 2u)) L.at(d.lds_out + e) = v;
     }
-    const tcx::DevRange R = p.ranges.at(term_launch->begin + t);
-    for (uint32_t g = R.g_begin; g < R.g_end; ++g) {
-      const tcx::DevGroup& grp = p.groups.at(g);
-      for (uint32_t q = 0; q < grp.op_end - grp.op_begin; ++q) {
-        const uint32_t o = rev ? grp.op_end - 1 - q : grp.op_begin + q;
-        const tcx::DevOp& op = p.ops.at(o);
-        uint64_t a = op.a, b = op.b, c = op.c, c2 = 0;
-        bool al = false, bl = false, cl = false, two = false;
-        if (res) {
-          const tcx::DevROp& r = p.rops.at(o);
-          a = r.a, b = r.b, c = r.c, c2 = r.c2;
-          al = r.shape & tcx::RES_A_LDS, bl = r.shape & tcx::RES_B_LDS;
-          cl = r.shape & tcx::RES_C_LDS, two = r.shape & tcx::RES_C2;
+  };
+  auto node = [&](uint32_t o, bool resident) {
+    const tcx::DevOp& op = p.ops.at(o);
+    uint64_t a = op.a, b = op.b, c = op.c, c2 = 0;
+    bool al = false, bl = false, cl = false, two = false;
+    if (resident) {
+      const tcx::DevROp& r = p.rops.at(o);
+      a = r.a, b = r.b, c = r.c, c2 = r.c2;
+      al = r.shape & tcx::RES_A_LDS, bl = r.shape & tcx::RES_B_LDS;
+      cl = r.shape & tcx::RES_C_LDS, two = r.shape & tcx::RES_C2;
+    }
+    std::vector<val>& MA = al ? L : G;
+    std::vector<val>& MB = bl ? L : G;
+    std::vector<val>& MC = cl ? L : G;
+    auto offs = [&](uint32_t d, uint64_t n) {
+      std::vector<uint64_t> v(n);
+      for (uint64_t i = 0; i < n; ++i) v[i] = ix_of(p.tabs, d, i);
+      return v;
+    };
+    const std::vector<uint64_t> am = offs(op.a_m, op.M), ak = offs(op.a_k, op.K),
+                                bk = offs(op.b_k, op.K), bn = offs(op.b_n, op.N),
+                                cm = offs(op.c_m, op.M), cn = offs(op.c_n, op.N);
+    for (uint64_t m = 0; m < op.M; ++m)
+      for (uint64_t n = 0; n < op.N; ++n) {
+        val acc = 0;
+        for (uint64_t k = 0; k < op.K; ++k)
+          acc = vadd(acc, vmul(MA.at(a + am[m] + ak[k]), MB.at(b + bk[k] + bn[n])));
+        MC.at(c + cm[m] + cn[n]) = acc;
+        if (two) G.at(c2 + cm[m] + cn[n]) = acc;
+      }
+  };
+  for (const tcx::Launch* x : tcx::launch_order(p, grad)) {
+    if (x->kind == tcx::L_LEAF) {
+      for (uint32_t li = 0; li < p.leaves.size(); ++li) leaf(li, false);
+    } else if (x->kind == tcx::L_LEVEL) {
+      const uint32_t n = x->rend - x->gbegin;
+      for (uint32_t q = 0; q < n; ++q) node(rev ? x->rend - 1 - q : x->gbegin + q, false);
+    } else if (x->kind == tcx::L_TERM) {
+      const bool resident = res && x->resident;
+      for (size_t t = 0; t < p.terms.size(); ++t) {
+        L.assign(p.lds_elems, POISON);  // each launch's workgroup starts afresh
+        if (x->with_leaves)
+          for (uint32_t li = p.terms[t].leaf_begin; li < p.terms[t].leaf_end; ++li) leaf(li, resident);
+        const tcx::DevRange R = p.ranges.at(x->begin + t);
+        for (uint32_t g = R.g_begin; g < R.g_end; ++g) {
+          const tcx::DevGroup& grp = p.groups.at(g);
+          for (uint32_t q = 0; q < grp.op_end - grp.op_begin; ++q)
+            node(rev ? grp.op_end - 1 - q : grp.op_begin + q, resident);
         }
-        std::vector<cd>& MA = al ? L : G;
-        std::vector<cd>& MB = bl ? L : G;
-        std::vector<cd>& MC = cl ? L : G;
-        auto offs = [&](uint32_t d, uint64_t n) {
-          std::vector<uint64_t> v(n);
-          for (uint64_t i = 0; i < n; ++i) v[i] = ix_of(p.tabs, d, i);
-          return v;
-        };
-        const std::vector<uint64_t> am = offs(op.a_m, op.M), ak = offs(op.a_k, op.K),
-                                    bk = offs(op.b_k, op.K), bn = offs(op.b_n, op.N),
-                                    cm = offs(op.c_m, op.M), cn = offs(op.c_n, op.N);
-        for (uint64_t m = 0; m < op.M; ++m)
-          for (uint64_t n = 0; n < op.N; ++n) {
-            cd acc = 0;
-            for (uint64_t k = 0; k < op.K; ++k) acc += MA.at(a + am[m] + ak[k]) * MB.at(b + bk[k] + bn[n]);
-            MC.at(c + cm[m] + cn[n]) = acc;
-            if (two) G.at(c2 + cm[m] + cn[n]) = acc;
-          }
       }
     }
   }
-  std::vector<cd> out;
+  std::vector<val> out;
   for (const tcx::DevRoot& r : p.roots)
     if (r.present) out.push_back(G.at(r.val));
   if (grad)
@@ -239,10 +273,10 @@ std::vector<cd> run_resident(const tcx::Plan& p, bool res, bool grad, bool rev) 
   return out;
 }
 
-bool same(const std::vector<cd>& x, const std::vector<cd>& y) {
+bool same(const std::vector<val>& x, const std::vector<val>& y) {
   if (x.size() != y.size() || x.empty()) return false;
   for (size_t i = 0; i < x.size(); ++i)
-    if (!(x[i] == y[i])) return false;  // NaN never compares equal
+    if (x[i] != y[i] || x[i] == POISON) return false;
   return true;
 }
 
@@ -266,6 +300,24 @@ void run_plans(const tc_network* net, const tc_path* path, bool grad, const char
           expect(e.status == TC_ERR_TOO_LARGE && budget, std::string(what) + ": plan " + e.msg);
         }
       }
+  // the automatic mode with an LDS arena: its light runs are resident
+  // launches, checked against the same plan's plain records
+  for (uint32_t lds : {1024u, 16384u}) {
+    tcx::Plan p;
+    p.want_grad = grad ? 1 : 0;
+    p.lds_elems = lds;
+    try {
+      tcx::build_plan(p, tcx::network_of(net), tcx::path_of(path));
+    } catch (const tcx::Error& e) {
+      expect(false, std::string(what) + ": automatic plan with LDS " + e.msg);
+      continue;
+    }
+    if (!p.resident_runs) continue;
+    ++runs_checked;
+    const std::vector<val> want = run_resident(p, false, grad, false);
+    expect(same(run_resident(p, true, grad, false), want), std::string(what) + ": resident runs");
+    expect(same(run_resident(p, true, grad, true), want), std::string(what) + ": resident runs, nodes reversed");
+  }
   // resident term launches: a small LDS arena (most tensors global) and a
   // large one, each against the same plan's plain records
   for (uint32_t lds : {1024u, 16384u}) {
@@ -282,7 +334,7 @@ void run_plans(const tc_network* net, const tc_path* path, bool grad, const char
     }
     expect(p.resident && p.exec_used == 4, std::string(what) + ": resident mode");
     ++resident_checked;
-    const std::vector<cd> want = run_resident(p, false, grad, false);
+    const std::vector<val> want = run_resident(p, false, grad, false);
     expect(same(run_resident(p, true, grad, false), want), std::string(what) + ": resident values");
     expect(same(run_resident(p, true, grad, true), want), std::string(what) + ": resident values, nodes reversed");
     // a planted misplacement must show: the first node that reads an LDS
@@ -298,7 +350,7 @@ void run_plans(const tc_network* net, const tc_path* path, bool grad, const char
         }
     if (grad) {
       // the forward-only launch gives the same roots
-      std::vector<cd> fw = run_resident(p, true, false, false), ref = run_resident(p, false, false, false);
+      std::vector<val> fw = run_resident(p, true, false, false), ref = run_resident(p, false, false, false);
       expect(same(fw, ref), std::string(what) + ": resident forward launch");
     }
   }
@@ -408,6 +460,8 @@ int main() {
     return 1;
   }
   expect(resident_checked >= 8, "resident plans checked");
-  std::printf("host check ok (%d resident plans simulated)\n", resident_checked);
+  expect(runs_checked >= 4, "plans with resident runs checked");
+  std::printf("host check ok (%d resident plans, %d plans with resident runs simulated)\n",
+              resident_checked, runs_checked);
   return 0;
 }

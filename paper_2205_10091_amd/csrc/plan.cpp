@@ -537,10 +537,15 @@ void schedule(Schedule& S, const Plan& plan, const Network& net, const Path& pat
 // the lowest offset clear of every placed tensor whose lifetime overlaps
 // its own; lifetimes are inclusive step ranges, so a node's operands and
 // its result never share space.
+// A window [s0, s1] restricts the placement to one run of steps (a light
+// run of the automatic mode): only tensors produced in it (and the leaves,
+// when it materialises them) are candidates, an LDS copy serves only reads
+// inside it, and a tensor read after it keeps its global copy.
 constexpr int32_t RES_LDS_WINDOW = 6;
 
 void place_lds(std::vector<PT>& T, const std::vector<PendingOp>& pend, int32_t root_step,
-               uint64_t cap, size_t n_terms) {
+               uint64_t cap, size_t n_terms, int32_t s0 = 0, int32_t s1 = INT32_MAX,
+               bool leaves = true) {
   std::vector<int32_t> u1(T.size(), INT32_MAX);
   for (const PendingOp& q : pend) {
     u1[q.a] = std::min(u1[q.a], q.step);
@@ -566,8 +571,9 @@ void place_lds(std::vector<PT>& T, const std::vector<PendingOp>& pend, int32_t r
     pl.clear();
     for (int32_t id : ids) {
       const PT& x = T[id];
-      if (x.elems > cap || u1[id] == INT32_MAX) continue;
-      const bool keep = x.last >= root_step || x.last - x.first > RES_LDS_WINDOW;
+      if (x.elems > cap || u1[id] == INT32_MAX || u1[id] > s1) continue;
+      if (x.first == 0 ? !leaves : (x.first < s0 || x.first > s1)) continue;
+      const bool keep = x.last >= root_step || x.last > s1 || x.last - x.first > RES_LDS_WINDOW;
       cs.push_back({id, x.first, keep ? u1[id] : x.last, (x.elems + 7) & ~uint64_t(7), keep});
     }
     std::sort(cs.begin(), cs.end(), [](const Cand& p, const Cand& q) {
@@ -886,10 +892,41 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
   }
   plan.term_mode = any_term;
   plan.exec_used = plan.resident ? 4 : any_term ? (any_level ? 3 : 2) : 1;
+  // automatic mode: the forward runs of light steps become resident runs
+  // (their tensors in LDS where they fit, placed run by run) when the
+  // device has an LDS arena and the global arena fits 32-bit offsets
+  plan.resident_runs = plan.exec_mode == 0 && any_term && B == 1 && !plan.qgt &&
+                       plan.lds_elems >= 1024 && S.arena_elems < (uint64_t(1) << 32);
   if (plan.resident) {
     if (S.arena_elems >= (uint64_t(1) << 32))
       fail(TC_ERR_TOO_LARGE, "resident term launches address the global arena with 32-bit offsets");
     place_lds(S.T, S.pend, S.root_step, plan.lds_elems, net.terms.size());
+  } else if (plan.resident_runs) {
+    // the runs as the op emission below forms them: consecutive term steps
+    // (in step order) of one phase
+    std::map<int32_t, bool> bwd_step;
+    for (const PendingOp& q : S.pend) bwd_step[q.step] = q.bwd;
+    int32_t r0 = -1, r1 = -1;
+    bool rb = false;
+    // (forward runs only: a reverse-sweep run reads mostly forward values
+    // kept in global memory, and measured slower as a resident launch
+    // than as a plain term launch on the 20-qubit chain, 21 against 11 us)
+    auto flush = [&]() {
+      if (r0 >= 0 && !rb)
+        place_lds(S.T, S.pend, S.root_step, plan.lds_elems, net.terms.size(), r0, r1, r0 == 1);
+      r0 = -1;
+    };
+    for (const auto& ts : term_step) {
+      const bool b = bwd_step.at(ts.first);
+      if (!ts.second || (r0 >= 0 && b != rb)) flush();
+      if (!ts.second) continue;
+      if (r0 < 0) {
+        r0 = ts.first;
+        rb = b;
+      }
+      r1 = ts.first;
+    }
+    flush();
   }
 
   plan.checkpoint_used = grad ? ckpt : 0;
@@ -986,6 +1023,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         plan.bwd.push_back(L);
       }
     } else {
+      if (plan.resident_runs && !seg_bwd) L.resident = 3;
       (seg_bwd ? plan.bwd : plan.fwd).push_back(L);
     }
     seg_open = false;
@@ -1164,7 +1202,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           }
         }
         gc.push_back(op);
-        if (plan.resident) {
+        if (plan.resident || (plan.resident_runs && term_mode && !pend[k].bwd)) {
           // where each operand is read at this step, and where C goes
           const int32_t st = pend[k].step;
           DevROp r{};
@@ -1297,8 +1335,9 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     // their own (their partial sums go to the split region, slice-major,
     // and a reduction over 256-output chunks adds them)
     std::stable_partition(gc.begin(), gc.end(), [](const DevOp& op) { return op.ksplit == 1; });
-    if (plan.resident && (gcr.size() != gc.size() || !gm.empty() || !wv.empty() || !wd.empty() ||
-                          !rt.empty()))
+    const bool res_step = plan.resident || (plan.resident_runs && term_mode && !pend[i].bwd);
+    if (res_step && (gcr.size() != gc.size() || !gm.empty() || !wv.empty() || !wd.empty() ||
+                     !rt.empty()))
       fail(TC_ERR_INVALID_ARG, "internal: resident step with non-gather nodes");
     L.begin = (uint32_t)plan.ops.size();
     uint64_t w = 0;
@@ -1320,7 +1359,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       }
       op.work0 = w;
       w += items;
-      if (plan.resident) {
+      if (res_step) {
         if (op.ksplit != 1 || w >= (uint64_t(1) << 32))
           fail(TC_ERR_INVALID_ARG, "internal: resident node items");
         DevROp r = gcr[plan.ops.size() - L.begin];
@@ -1346,6 +1385,13 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       plan.ops.push_back(op);
     }
     L.rend = (uint32_t)plan.ops.size();
+    // (resident runs: the level steps' ops get empty resident records, so
+    // that the records stay indexed like the ops)
+    if (plan.resident_runs) {
+      if (res_step && plan.rops.size() != plan.ops.size())
+        fail(TC_ERR_INVALID_ARG, "internal: resident records out of step with the ops");
+      plan.rops.resize(plan.ops.size());
+    }
     if (L.rblocks && L.rblocks <= WAVE_TABLE_MAX &&
         plan.item_op.size() + L.rblocks <= ITEM_TABLES_TOTAL_MAX) {
       // row-tile workgroup -> op (relative to L.rbegin): one load instead of
@@ -1418,7 +1464,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       DevLeaf d{};
       d.out = (uint64_t)x.off;
       d.where = 1;
-      if (plan.resident && x.lds_off >= 0) {
+      if ((plan.resident || plan.resident_runs) && x.lds_off >= 0) {
         d.lds_out = (uint32_t)x.lds_off;
         d.where = (x.global ? 1u : 0u) | 2u;
       }
@@ -1712,11 +1758,23 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     }
     // resident plans: one record per gather op with the same shape, every
     // operand inside the LDS arena or the global arena it names
-    if (plan.resident) {
+    if (plan.resident || plan.resident_runs) {
       const uint64_t LE = plan.lds_elems;
       if (plan.rops.size() != plan.ops.size() || !LE)
         fail(TC_ERR_INVALID_ARG, "internal: resident op records");
+      // the ops that resident term launches run
+      std::vector<char> used(plan.ops.size(), 0);
+      for (const auto* seq : {&plan.fwd, &plan.bwd})
+        for (const Launch& L : *seq) {
+          if (L.kind != L_TERM || !L.resident) continue;
+          for (size_t t = 0; t < plan.terms.size(); ++t) {
+            const DevRange& R = plan.ranges.at(L.begin + t);
+            for (uint32_t g = R.g_begin; g < R.g_end; ++g)
+              for (uint32_t o = plan.groups.at(g).op_begin; o < plan.groups.at(g).op_end; ++o) used.at(o) = 1;
+          }
+        }
       for (size_t o = 0; o < plan.rops.size(); ++o) {
+        if (!used[o]) continue;
         const DevROp& r = plan.rops[o];
         const DevOp& op = plan.ops[o];
         const uint32_t sh = r.shape;
@@ -1739,9 +1797,19 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         if (!(d.where & 3u) || d.where > 3u ||
             ((d.where & 2u) && (uint64_t)d.lds_out + (1ull << d.rank) > LE) || d.rows != 1)
           fail(TC_ERR_INVALID_ARG, "internal: resident leaf out of the LDS arena");
+      // leaves held in LDS are written by the resident launch that runs first
+      bool lds_leaves = false;
+      for (const DevLeaf& d : plan.leaves) lds_leaves = lds_leaves || d.where != 1u;
+      if (lds_leaves && (plan.fwd.empty() || plan.fwd[0].kind != L_TERM || !plan.fwd[0].with_leaves ||
+                         !plan.fwd[0].resident))
+        fail(TC_ERR_INVALID_ARG, "internal: leaves in LDS without a resident launch writing them");
     } else if (!plan.rops.empty()) {
       fail(TC_ERR_INVALID_ARG, "internal: resident records in a plan without resident launches");
     }
+    for (const auto* seq : {&plan.fwd, &plan.bwd})
+      for (const Launch& L : *seq)
+        if (L.resident && (L.kind != L_TERM || !(plan.resident || plan.resident_runs)))
+          fail(TC_ERR_INVALID_ARG, "internal: resident launch in a plan without resident records");
     for (const DevTerm& D : plan.terms)
       if (D.leaf_begin > D.leaf_end || D.leaf_end > plan.leaves.size() ||
           D.leaf_work_end > plan.leaf_work || D.leaf_work0 > D.leaf_work_end)

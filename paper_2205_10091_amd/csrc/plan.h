@@ -73,7 +73,8 @@ struct Launch {
   uint64_t rtunit_begin = NO_ITEMS; // per-row-tile-workgroup op index table in Plan::item_op
   bool with_leaves = false;       // L_TERM: materialise the leaves first
   // resident term launches: 1 the forward pass alone (calls without the
-  // gradient), 2 the forward pass and reverse sweep (calls with it)
+  // gradient), 2 the forward pass and reverse sweep (calls with it), 3 a
+  // run of light steps of the automatic mode (calls with or without it)
   int32_t resident = 0;
   double flops = 0;               // algorithmic flops (8 per complex MAC)
   double bytes = 0;               // algorithmic bytes: operands read + results written
@@ -113,6 +114,7 @@ struct Plan {
   // launches (set by the executor from the device; 0 = none)
   uint32_t lds_elems = 0;
   bool resident = false;    // resident term launches (batch 1, gathers only)
+  bool resident_runs = false;  // automatic mode: forward light runs as resident term launches
   bool term_mode = false;   // some steps run in term launches
   int32_t exec_used = 1;    // 1 level launches only, 2 term launches only, 3 both,
                             // 4 resident term launches
