@@ -203,7 +203,11 @@ __device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
 // acc[j] += sum over k = kb + sub, kb + sub + S, ... < K of
 // A[ak(k)] * B[bk(k) + bn[j]], j < V, accumulated in increasing k.  U steps
 // are issued together so that their table and operand loads overlap instead
-// of forming one dependent chain per step.
+// of forming one dependent chain per step.  U is small (2 steps at V = 1):
+// the gather kernel then fits 72 VGPRs and 7 wavefronts per SIMD, and more
+// items in flight beat deeper unrolling (20-qubit VQE chain, energy +
+// gradient: 365 us at U = 8 / 4 / 2 and 5 waves, 338 us at 4 / 2 / 1 and 6,
+// 325 us at 2 / 1 / 1 and 7; 8 waves spill).
 template <int V, bool TABLES>
 __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restrict__ A,
                                            const float2* __restrict__ Bp,
@@ -211,7 +215,7 @@ __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restri
                                            uint32_t bk,
                                            const uint32_t (&bn)[4], uint32_t sub, uint32_t S,
                                            uint32_t kb, uint32_t K) {
-  constexpr int U = V == 4 ? 2 : (V == 2 ? 4 : 8);  // about 90 VGPRs: 5 waves per SIMD
+  constexpr int U = V == 4 ? 1 : (V == 2 ? 1 : 2);
   uint32_t k = kb + sub;
   for (; k + (U - 1) * S < K; k += U * S) {
     uint32_t ia[U], ib[U];
@@ -662,7 +666,7 @@ typedef const DevOp* ScalarOpPtr;
 #endif
 
 template <bool SPLIT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_gather(LevelArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_gather(LevelArgs a) {
   // each block takes one contiguous chunk (a multiple of 256 items, so
   // wavefronts never straddle its end); a thread finds its segment and op
   // once (or reads it from the per-item table) and then only walks forward
