@@ -203,19 +203,21 @@ __device__ __forceinline__ void cfma(c32& acc, float2 a, float2 b) {
 // acc[j] += sum over k = kb + sub, kb + sub + S, ... < K of
 // A[ak(k)] * B[bk(k) + bn[j]], j < V, accumulated in increasing k.  U steps
 // are issued together so that their table and operand loads overlap instead
-// of forming one dependent chain per step.  U is small (2 steps at V = 1):
-// the gather kernel then fits 72 VGPRs and 7 wavefronts per SIMD, and more
-// items in flight beat deeper unrolling (20-qubit VQE chain, energy +
-// gradient: 365 us at U = 8 / 4 / 2 and 5 waves, 338 us at 4 / 2 / 1 and 6,
-// 325 us at 2 / 1 / 1 and 7; 8 waves spill).
-template <int V, bool TABLES>
+// of forming one dependent chain per step.  Level launches (DEEP = false)
+// take U small (2 steps at V = 1): the gather kernel then fits 72 VGPRs and
+// 7 wavefronts per SIMD, and more items in flight beat deeper unrolling
+// (20-qubit VQE chain, energy + gradient: 365 us at U = 8 / 4 / 2 and 5
+// waves, 338 us at 4 / 2 / 1 and 6, 325 us at 2 / 1 / 1 and 7; 8 waves
+// spill).  Term launches have one workgroup per term, so their items gain
+// from the deeper unroll (DEEP = true: 8 / 4 / 2).
+template <int V, bool TABLES, bool DEEP = false>
 __device__ __forceinline__ void gather_dot(c32 (&acc)[4], const float2* __restrict__ A,
                                            const float2* __restrict__ Bp,
                                            const uint32_t* __restrict__ tab, uint32_t ak,
                                            uint32_t bk,
                                            const uint32_t (&bn)[4], uint32_t sub, uint32_t S,
                                            uint32_t kb, uint32_t K) {
-  constexpr int U = V == 4 ? 1 : (V == 2 ? 1 : 2);
+  constexpr int U = DEEP ? (V == 4 ? 2 : (V == 2 ? 4 : 8)) : (V == 4 ? 1 : (V == 2 ? 1 : 2));
   uint32_t k = kb + sub;
   for (; k + (U - 1) * S < K; k += U * S) {
     uint32_t ia[U], ib[U];
@@ -489,7 +491,7 @@ __global__ void __launch_bounds__(256) k_reduce(LevelArgs a) {
 // this together (the k-split combines across lanes); `has` = false makes
 // the call a no-op that still joins the shuffles.  TABLES: the op has an
 // index table (else every index is computed, branch-free).
-template <bool TABLES, bool SPLIT>
+template <bool TABLES, bool SPLIT, bool DEEP = false>
 __device__ __forceinline__ void gather_item_t(const DevOp& op, uint64_t l, bool has,
                                               const uint32_t* __restrict__ tab,
                                               float2* __restrict__ arena,
@@ -535,13 +537,13 @@ __device__ __forceinline__ void gather_item_t(const DevOp& op, uint64_t l, bool 
 #pragma unroll
     for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? ixt<TABLES>(tab, op.b_n, n0 + j) : 0u;
     if (SPLIT)  // split ops have V == 1
-      gather_dot<1, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
+      gather_dot<1, TABLES, DEEP>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
     else if (V == 4)
-      gather_dot<4, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
+      gather_dot<4, TABLES, DEEP>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
     else if (V == 2)
-      gather_dot<2, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
+      gather_dot<2, TABLES, DEEP>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
     else
-      gather_dot<1, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
+      gather_dot<1, TABLES, DEEP>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, kb, ke);
   }
   if (S > 1) {
     // V == 1 whenever S > 1
@@ -561,13 +563,14 @@ __device__ __forceinline__ void gather_item_t(const DevOp& op, uint64_t l, bool 
 }
 
 // An unsplit gather op's item.
+template <bool DEEP = false>
 __device__ __forceinline__ void gather_item(const DevOp& op, uint64_t l, bool has,
                                             const uint32_t* __restrict__ tab,
                                             float2* __restrict__ arena) {
   if (has && op_has_tables(op))
-    gather_item_t<true, false>(op, l, has, tab, arena, nullptr);
+    gather_item_t<true, false, DEEP>(op, l, has, tab, arena, nullptr);
   else
-    gather_item_t<false, false>(op, l, has, tab, arena, nullptr);
+    gather_item_t<false, false, DEEP>(op, l, has, tab, arena, nullptr);
 }
 
 // Split gather sums of a level: workgroup u adds, for up to 256 output
@@ -665,8 +668,12 @@ typedef const __attribute__((address_space(4))) DevOp* ScalarOpPtr;
 typedef const DevOp* ScalarOpPtr;
 #endif
 
-template <bool SPLIT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_gather(LevelArgs a) {
+// DEEP: the deep k unroll at 5 wavefronts per SIMD, for levels whose items
+// hold long sums (bandwidth bound: bytes in flight per wavefront matter);
+// else the short unroll at 7 (latency bound: items in flight matter).
+template <bool SPLIT, bool DEEP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEEP ? 5 : 7)))
+k_gather(LevelArgs a) {
   // each block takes one contiguous chunk (a multiple of 256 items, so
   // wavefronts never straddle its end); a thread finds its segment and op
   // once (or reads it from the per-item table) and then only walks forward
@@ -705,9 +712,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     const DevOp& op = ops[oi];
     if (SPLIT) {
       if (has && op_has_tables(op))
-        gather_item_t<true, true>(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena, Sg.split.part);
+        gather_item_t<true, true, DEEP>(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena, Sg.split.part);
       else
-        gather_item_t<false, true>(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena, Sg.split.part);
+        gather_item_t<false, true, DEEP>(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena, Sg.split.part);
     } else {
       // Segments start at multiples of 64 items, so a wavefront's lanes
       // share the segment; when they share the op too (all but the
@@ -719,9 +726,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
       if (has && __builtin_amdgcn_ballot_w64(oi != oiu) == 0) {
         const LevelSeg& Su = a.seg[siu];
         const DevOp opu = ((ScalarOpPtr)Su.gc_ops)[oiu];
-        gather_item(opu, ws - opu.work0, true, Su.tab, Su.arena);
+        gather_item<DEEP>(opu, ws - opu.work0, true, Su.tab, Su.arena);
       } else {
-        gather_item(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena);
+        gather_item<DEEP>(op, has ? ws - op.work0 : 0, has, Sg.tab, Sg.arena);
       }
     }
   }
@@ -823,7 +830,7 @@ __global__ void __launch_bounds__(1024) k_term(TermArgs a) {
             hi = mid;
         }
         const DevOp& op = ops[lo];
-        gather_item(op, w - op.work0, true, a.tab, a.arena);
+        gather_item<true>(op, w - op.work0, true, a.tab, a.arena);
       }
     } else {
       const DevOp* __restrict__ ops = a.ops + G.op_begin;
@@ -836,7 +843,7 @@ __global__ void __launch_bounds__(1024) k_term(TermArgs a) {
         else
           while (oi + 1 < n && ops[oi + 1].work0 <= w) ++oi;
         const DevOp& op = ops[oi];
-        gather_item(op, w - op.work0, true, a.tab, a.arena);
+        gather_item<true>(op, w - op.work0, true, a.tab, a.arena);
       }
     }
     commit(g + 1, buf ^ 1);
@@ -883,11 +890,11 @@ __device__ __forceinline__ void res_item_t(const DevROp& op, uint32_t l,
     for (int j = 0; j < 4; ++j) bn[j] = (uint32_t)j < V ? ixt<TABLES>(tab, op.b_n, n0 + j) : 0u;
     const uint32_t K = 1u << lk;
     if (V == 4)
-      gather_dot<4, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
+      gather_dot<4, TABLES, true>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
     else if (V == 2)
-      gather_dot<2, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
+      gather_dot<2, TABLES, true>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
     else
-      gather_dot<1, TABLES>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
+      gather_dot<1, TABLES, true>(acc, A, Bp, tab, op.a_k, op.b_k, bn, sub, S, 0, K);
   }
   if (S > 1) {
     // V == 1 whenever S > 1
@@ -1281,6 +1288,8 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       const unsigned gmb = (parts & PART_GEMM) ? a.tile_blocks + wvb : 0u;
       const unsigned whb = (parts & PART_WIDE) ? (unsigned)std::min<uint64_t>(htiles, (uint64_t)n_cu) : 0u;
       const unsigned gcb = (parts & PART_GATHER) && work ? grid_for(work, 256, n_cu) : 0u;
+      bool deep = false;  // any merged level asking for the deep unroll
+      for (int i = 0; i < nseg; ++i) deep = deep || segs[i].launch->deep_gather;
       const unsigned gsb = (parts & PART_GSPLIT) && gswork ? grid_for(gswork, 256, n_cu) : 0u;
       const unsigned rtb = (parts & PART_ROWTILE) ? (unsigned)rtblocks : 0u;
       auto gemm = [&](hipStream_t st) {
@@ -1304,10 +1313,13 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
           launch(k_reduce, dim3((unsigned)a.split_units), dim3(256), st, a);
       };
       auto gather = [&](hipStream_t st) {
-        if (gcb) launch(k_gather<false>, dim3(gcb), dim3(256), st, a);
+        if (gcb && deep)
+          launch(k_gather<false, true>, dim3(gcb), dim3(256), st, a);
+        else if (gcb)
+          launch(k_gather<false, false>, dim3(gcb), dim3(256), st, a);
         if (rtb) launch(k_rowtile, dim3(rtb), dim3(256), st, a);
         if (gsb) {
-          launch(k_gather<true>, dim3(gsb), dim3(256), st, a);
+          launch(k_gather<true, true>, dim3(gsb), dim3(256), st, a);
           // split sums: their slices are all written once k_gather is done
           launch(k_reduce_g, dim3((unsigned)a.gsplit_units), dim3(256), st, a);
         }

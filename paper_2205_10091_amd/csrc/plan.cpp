@@ -1376,6 +1376,22 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
       plan.ops.push_back(op);
     }
     L.gsend = (uint32_t)plan.gsplit_units.size();
+    {
+      // k-steps per item, averaged over the level's unsplit gather items:
+      // long sums (8 or more) take the deep unroll (bandwidth bound: the
+      // sweeps of wide chains, 2^22-element boundaries absorbing gates),
+      // short ones the short unroll with more wavefronts (latency bound)
+      double it = 0, ks = 0;
+      for (uint32_t o = L.begin; o < plan.ops.size(); ++o) {
+        const DevOp& op = plan.ops[o];
+        if (op.ksplit != 1) continue;
+        const uint32_t ls = (op.flags >> 4) & 7u, lv = (op.flags >> 8) & 3u;
+        const double items = (double)(((uint64_t)op.rows * op.M * (op.N >> lv)) << ls);
+        it += items;
+        ks += items * (double)(op.K >> ls);
+      }
+      L.deep_gather = it > 0 && ks >= 8.0 * it;
+    }
     plan.split_floats = std::max(plan.split_floats, part);
     L.end = (uint32_t)plan.ops.size();
     L.rbegin = L.end;

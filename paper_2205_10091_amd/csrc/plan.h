@@ -72,6 +72,7 @@ struct Launch {
   uint64_t wunit_begin = NO_ITEMS;  // per-wave-tile op index table in Plan::item_op
   uint64_t rtunit_begin = NO_ITEMS; // per-row-tile-workgroup op index table in Plan::item_op
   bool with_leaves = false;       // L_TERM: materialise the leaves first
+  bool deep_gather = false;       // L_LEVEL: gather items with long sums (deep unroll)
   // resident term launches: 1 the forward pass alone (calls without the
   // gradient), 2 the forward pass and reverse sweep (calls with it), 3 a
   // run of light steps of the automatic mode (calls with or without it)
