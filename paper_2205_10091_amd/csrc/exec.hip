@@ -65,7 +65,7 @@ struct LevelSeg {
   const uint32_t* wave_unit_op;  // wave tile -> op index, or null (search)
   const DevOp* gc_ops;
   const uint32_t* tab;
-  const uint32_t* item_op;  // gather item -> op index, or null (search)
+  const uint32_t* item_op;  // gather wavefront (64 items) -> op index, or null (search)
   float2* arena;
   SplitK split;             // split-K partial tiles
   const DevSplitUnit* sunits;  // split-K output tiles of this level
@@ -664,8 +664,10 @@ __global__ void __launch_bounds__(256) k_rowtile(LevelArgs a) {
 // only parses device code, sees a plain pointer).
 #if defined(__HIP_DEVICE_COMPILE__)
 typedef const __attribute__((address_space(4))) DevOp* ScalarOpPtr;
+typedef const __attribute__((address_space(4))) uint32_t* ScalarU32Ptr;
 #else
 typedef const DevOp* ScalarOpPtr;
+typedef const uint32_t* ScalarU32Ptr;
 #endif
 
 // DEEP: the deep k unroll at 5 wavefronts per SIMD, for levels whose items
@@ -700,7 +702,10 @@ k_gather(LevelArgs a) {
     const bool has = n > 0;
     if (has) {
       if (!SPLIT && Sg.item_op) {
-        oi = Sg.item_op[ws];
+        // a level's ops start on wavefronts: one table entry per wavefront,
+        // read with a scalar load
+        const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)(ws >> 6));
+        oi = ((ScalarU32Ptr)Sg.item_op)[wv];
       } else if (oi == 0xffffffffu) {
         oi = find_item(ops, n, ws);
       } else {

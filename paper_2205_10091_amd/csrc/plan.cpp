@@ -1353,7 +1353,11 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         w = 0;
       }
       uint64_t items = (groups * op.ksplit) << ls;
-      if (ls) {  // whole wavefronts: aligned start, padded length
+      // whole wavefronts (aligned start, padded length): ops that split
+      // their sums over lanes, and every op of a level launch, whose
+      // wavefronts then each hold one op (found through a per-wavefront
+      // table, 4 bytes per 64 items)
+      if (ls || !term_mode) {
         w = (w + 63) & ~uint64_t(63);
         items = (items + 63) & ~uint64_t(63);
       }
@@ -1425,16 +1429,19 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
     } else {
       L.xwork = (w + 63) & ~uint64_t(63);
     }
-    if (L.xbegin > L.begin && L.work <= ITEM_TABLE_MAX &&
-        plan.item_op.size() + L.work <= ITEM_TABLES_TOTAL_MAX) {
-      // item -> op (relative to L.begin); pad items map to the op before them
+    // item -> op (relative to L.begin) for a term step's group, wavefront
+    // -> op for a level launch (its ops start on wavefronts); pad items map
+    // to the op before them
+    const uint64_t per = term_mode ? 1 : 64, n_entries = L.work / per;
+    if (L.xbegin > L.begin && n_entries <= ITEM_TABLE_MAX &&
+        plan.item_op.size() + n_entries <= ITEM_TABLES_TOTAL_MAX) {
       L.item_begin = plan.item_op.size();
-      plan.item_op.resize(plan.item_op.size() + L.work);
+      plan.item_op.resize(plan.item_op.size() + n_entries);
       uint32_t* it = plan.item_op.data() + L.item_begin;
       for (uint32_t o = L.begin; o < L.xbegin; ++o) {
         const uint64_t lo = plan.ops[o].work0;
         const uint64_t hi = o + 1 < L.xbegin ? plan.ops[o + 1].work0 : L.work;
-        for (uint64_t x = lo; x < hi; ++x) it[x] = o - L.begin;
+        for (uint64_t x = lo / per; x < hi / per; ++x) it[x] = o - L.begin;
       }
     }
     if (term_mode) {
@@ -1877,11 +1884,23 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         if (L.item_begin == NO_ITEMS) continue;
         const uint64_t n_items =
             (L.kind == L_LEAF || L.kind == L_TERM) ? plan.leaves.size() : L.xbegin - L.begin;
-        if (L.item_begin + L.work > plan.item_op.size())
+        // a level launch's table has one entry per wavefront of 64 items,
+        // each naming the op whose (padded) items hold that wavefront
+        const uint64_t per = L.kind == L_LEVEL ? 64 : 1;
+        if (L.kind == L_LEVEL && L.work % 64)
+          fail(TC_ERR_INVALID_ARG, "internal: level items not whole wavefronts");
+        if (L.item_begin + L.work / per > plan.item_op.size())
           fail(TC_ERR_INVALID_ARG, "internal: item table out of range");
-        for (uint64_t x = 0; x < L.work; ++x)
-          if (plan.item_op[L.item_begin + x] >= n_items)
-            fail(TC_ERR_INVALID_ARG, "internal: item table names a missing op");
+        for (uint64_t x = 0; x < L.work / per; ++x) {
+          const uint32_t o = plan.item_op[L.item_begin + x];
+          if (o >= n_items) fail(TC_ERR_INVALID_ARG, "internal: item table names a missing op");
+          if (L.kind == L_LEVEL) {
+            const uint64_t lo = plan.ops[L.begin + o].work0;
+            const uint64_t hi = L.begin + o + 1 < L.xbegin ? plan.ops[L.begin + o + 1].work0 : L.work;
+            if (lo % 64 || x * 64 < lo || x * 64 + 64 > hi)
+              fail(TC_ERR_INVALID_ARG, "internal: wavefront table entry outside its op");
+          }
+        }
       }
   }
 
