@@ -682,7 +682,14 @@ k_gather(LevelArgs a) {
   const uint64_t total = SPLIT ? a.gs_work : a.gc_work;
   const uint64_t nblk = gridDim.x;
   const uint64_t chunk = (((total + nblk - 1) / nblk) + 255) & ~uint64_t(255);
-  const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+  // Workgroups are dispatched to the 8 XCDs round robin (block b to XCD
+  // b mod 8), and each XCD has its own L2: each XCD takes a contiguous
+  // range of chunks, so that an op's items, which read the same operands,
+  // mostly share one L2 instead of fetching those operands once per XCD.
+  const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3;
+  const uint32_t q = (uint32_t)(nblk >> 3), r = (uint32_t)(nblk & 7u);
+  const uint64_t cidx = (uint64_t)xcd * q + (xcd < r ? xcd : r) + slot;
+  const uint64_t begin = cidx * chunk;
   const uint64_t end = begin + chunk < total ? begin + chunk : total;
   uint32_t si = 0xffffffffu, oi = 0xffffffffu;
   for (uint64_t w = begin + threadIdx.x; w < end; w += blockDim.x) {
