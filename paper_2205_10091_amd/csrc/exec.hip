@@ -302,6 +302,19 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
 // registers for 4 waves per SIMD: the batched per-row wave tiles are
 // latency bound, and 4 waves beat 3 without the cap (22.5 against 23.2 ms
 // for the 1024-row VQE sweep) despite a 12-byte spill.
+// Block b of a grid of n runs on XCD b mod 8 (round-robin dispatch); the
+// logical block that gives XCD x a contiguous range of [0, n), so that
+// neighbouring work (items of one op, which read the same operands) shares
+// one XCD's L2.  A bijection on [0, n) for any n; blocks at or past n keep
+// their number.  (The 64 x 64 GEMM tiles measured no better in this order
+// on the 6x6 depth-8 grid.)
+__device__ __forceinline__ uint64_t xcd_block(uint64_t n) {
+  const uint64_t b = blockIdx.x;
+  if (b >= n) return b;
+  const uint64_t x = b & 7u, slot = b >> 3, q = n >> 3, r = n & 7u;
+  return x * q + (x < r ? x : r) + slot;
+}
+
 template <int PREC>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(PREC == TC_PREC_C64 ? 4 : 2))) k_gemm(LevelArgs a) {
@@ -686,10 +699,7 @@ k_gather(LevelArgs a) {
   // b mod 8), and each XCD has its own L2: each XCD takes a contiguous
   // range of chunks, so that an op's items, which read the same operands,
   // mostly share one L2 instead of fetching those operands once per XCD.
-  const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3;
-  const uint32_t q = (uint32_t)(nblk >> 3), r = (uint32_t)(nblk & 7u);
-  const uint64_t cidx = (uint64_t)xcd * q + (xcd < r ? xcd : r) + slot;
-  const uint64_t begin = cidx * chunk;
+  const uint64_t begin = xcd_block(nblk) * chunk;
   const uint64_t end = begin + chunk < total ? begin + chunk : total;
   uint32_t si = 0xffffffffu, oi = 0xffffffffu;
   for (uint64_t w = begin + threadIdx.x; w < end; w += blockDim.x) {
