@@ -593,7 +593,9 @@ def main():
         out["wide_nodes"] = grid_leg(4, 7, 16, grid_trials, 5, 1, "wide")
         # the same grid on a subtree-reconfigured tree (10x fewer flops)
         print("[bench] grid 4x7 depth 16, reconfigured tree", file=sys.stderr, flush=True)
-        out["wide_nodes_reconfigured"] = grid_leg(4, 7, 16, grid_trials, 10, 1, "wide", reconf_k=8)
+        # (no counter run covers the reconfigured tree's launches)
+        out["wide_nodes_reconfigured"] = grid_leg(4, 7, 16, grid_trials, 10, 1, "wide_reconfigured",
+                                                  reconf_k=8)
         print("[bench] batched circuit structures", file=sys.stderr, flush=True)
         out["structures"] = structures_leg()
         print("[bench] geometric tensor", file=sys.stderr, flush=True)
