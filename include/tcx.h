@@ -344,11 +344,18 @@ tc_status tc_path_term_pairs(const tc_path* path, int32_t term,
  *               workgroup barriers in between (gather path only; each term
  *               gets its own arena region).  1 = level launches only; 2 =
  *               term launches only (the leaves and all forward steps in
- *               one kernel, the reverse sweep in another); 0 = term
- *               launches for runs of at least two light steps (batch 1, no
- *               node for the GEMM path, at most two gather items per
- *               thread of each term's workgroup), level launches for the
- *               other steps.
+ *               one kernel, the reverse sweep in another); 3 = resident
+ *               term launches: one kernel runs each term's leaves, forward
+ *               pass and reverse sweep in one workgroup, with tensors the
+ *               planner places in the workgroup's LDS arena (sized from
+ *               the device's shared memory) read and written there
+ *               (batch 1, every node on the gather path, one term group;
+ *               TC_ERR_UNSUPPORTED otherwise); 0 = term launches for runs
+ *               of at least two light steps (batch 1, no node for the GEMM
+ *               path, at most two gather items per thread of each term's
+ *               workgroup; the forward runs as resident term launches when
+ *               the device has an LDS arena), level launches for the other
+ *               steps.
  *   tile_mode   0 = GEMM nodes whose operands are stored dense, A as
  *               [m][k] and B as [k][n] (the planner stores intermediates
  *               that feed GEMM nodes so), with at least 256 tiles of
@@ -427,7 +434,7 @@ typedef struct {
   int32_t n_terms;
   int32_t checkpoint_every;  /* segment length used, 0 = none            */
   int32_t exec_mode;         /* 1 level launches only, 2 term launches
-                                only, 3 both                             */
+                                only, 3 both, 4 resident term launches   */
   int32_t n_split_nodes;     /* GEMM nodes whose K is cut into slices    */
   int32_t n_split_sums;      /* gather nodes (long sums, few outputs)
                                 whose K is cut into slices               */
