@@ -104,6 +104,7 @@ struct LevelArgs {
   uint64_t rt_blocks;     // row-tile workgroups over all segments
   uint64_t gc_work;
   uint64_t gs_work;       // split gather items over all segments
+  int32_t xcd_order;      // gather chunks in XCD order (plans at batch 1)
 };
 
 struct RootSeg {
@@ -331,8 +332,14 @@ __attribute__((amdgpu_waves_per_eu(PREC == TC_PREC_C64 ? 4 : 2))) k_gemm(LevelAr
       const uint32_t oi = __builtin_amdgcn_readfirstlane(
           S.wave_unit_op ? S.wave_unit_op[lu] : find_item(S.wave_ops, S.n_wave, lu));
       const DevOp op = S.wave_ops[oi];
-      const uint32_t shape = ((op.flags >> 12) & 3u) | (op_has_tables(op) ? 4u : 0u);
+      const uint32_t shape = op_has_tables(op) ? (((op.flags >> 12) & 3u) | 4u)
+                             : (op.flags & OPF_AVEC) ? (((op.flags >> 12) & 3u) | 8u)
+                                                     : ((op.flags >> 12) & 3u);
       switch (shape) {
+        case 8: wave_tile_f32<1, 1, false, true>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 9: wave_tile_f32<2, 1, false, true>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 10: wave_tile_f32<1, 2, false, true>(op, lu, S.tab, S.arena, lane, S.split); break;
+        case 11: wave_tile_f32<2, 2, false, true>(op, lu, S.tab, S.arena, lane, S.split); break;
         case 0: wave_tile_f32<1, 1, false>(op, lu, S.tab, S.arena, lane, S.split); break;
         case 1: wave_tile_f32<2, 1, false>(op, lu, S.tab, S.arena, lane, S.split); break;
         case 2: wave_tile_f32<1, 2, false>(op, lu, S.tab, S.arena, lane, S.split); break;
@@ -699,7 +706,7 @@ k_gather(LevelArgs a) {
   // b mod 8), and each XCD has its own L2: each XCD takes a contiguous
   // range of chunks, so that an op's items, which read the same operands,
   // mostly share one L2 instead of fetching those operands once per XCD.
-  const uint64_t begin = xcd_block(nblk) * chunk;
+  const uint64_t begin = (a.xcd_order ? xcd_block(nblk) : (uint64_t)blockIdx.x) * chunk;
   const uint64_t end = begin + chunk < total ? begin + chunk : total;
   uint32_t si = 0xffffffffu, oi = 0xffffffffu;
   for (uint64_t w = begin + threadIdx.x; w < end; w += blockDim.x) {
@@ -1312,6 +1319,11 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       const unsigned gcb = (parts & PART_GATHER) && work ? grid_for(work, 256, n_cu) : 0u;
       bool deep = false;  // any merged level asking for the deep unroll
       for (int i = 0; i < nseg; ++i) deep = deep || segs[i].launch->deep_gather;
+      // XCD order pays at batch 1, where an op's items read the same small
+      // operands (batched levels measured slower with it: each row's
+      // operands are its own)
+      a.xcd_order = 1;
+      for (int i = 0; i < nseg; ++i) a.xcd_order = a.xcd_order && segs[i].plan->batch == 1;
       const unsigned gsb = (parts & PART_GSPLIT) && gswork ? grid_for(gswork, 256, n_cu) : 0u;
       const unsigned rtb = (parts & PART_ROWTILE) ? (unsigned)rtblocks : 0u;
       auto gemm = [&](hipStream_t st) {

@@ -339,7 +339,12 @@ __device__ __forceinline__ void store_wave(const DevOp& op, const TileCtx& c,
     }
 }
 
-template <int BI, int BJ, bool TABLES>
+// AVEC (op flag OPF_AVEC, no tables): in each group of U = 4 k-steps over
+// k = base .. base + 15, lane kq takes k = base + 4 kq + u at step u
+// instead of base + 4 u + kq (a sum over k may visit k in any order, the
+// same for A and B), so its four A values of a row are consecutive and
+// come in two 16-byte loads instead of four 8-byte loads.
+template <int BI, int BJ, bool TABLES, bool AVEC = false>
 __device__ __forceinline__ void wave_tile_f32(const DevOp op, uint64_t unit,
                                               const uint32_t* __restrict__ tab,
                                               float2* __restrict__ arena, int lane,
@@ -381,18 +386,37 @@ __device__ __forceinline__ void wave_tile_f32(const DevOp op, uint64_t unit,
   constexpr int U = 4;
   for (; s + U <= steps; s += U) {
     uint32_t ka[U], kb[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      ka[u] = ixt<TABLES>(tab, op.a_k, 4 * (s + u) + kq);
-      kb[u] = ixt<TABLES>(tab, op.b_k, 4 * (s + u) + kq);
-    }
     float2 av[U][BI], bv[U][BJ];
+    if constexpr (AVEC) {
+      const uint32_t k0 = 4 * s + 4 * kq;  // this lane's four consecutive k
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < U; ++u) kb[u] = ixt<TABLES>(tab, op.b_k, k0 + u);
 #pragma unroll
-      for (int bi = 0; bi < BI; ++bi) av[u][bi] = A[am[bi] + ka[u]];
+      for (int bi = 0; bi < BI; ++bi) {
+        const float4* p = reinterpret_cast<const float4*>(A + am[bi] + k0);
+        const float4 lo = p[0], hi = p[1];
+        av[0][bi] = make_float2(lo.x, lo.y);
+        av[1][bi] = make_float2(lo.z, lo.w);
+        av[2][bi] = make_float2(hi.x, hi.y);
+        av[3][bi] = make_float2(hi.z, hi.w);
+      }
 #pragma unroll
-      for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = B[kb[u] + bn[bj]];
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = B[kb[u] + bn[bj]];
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ka[u] = ixt<TABLES>(tab, op.a_k, 4 * (s + u) + kq);
+        kb[u] = ixt<TABLES>(tab, op.b_k, 4 * (s + u) + kq);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int bi = 0; bi < BI; ++bi) av[u][bi] = A[am[bi] + ka[u]];
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = B[kb[u] + bn[bj]];
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) step(av[u], bv[u]);

@@ -31,6 +31,10 @@ namespace tcx {
 // more permuted ones.
 constexpr int IX_RUNS = 3;
 constexpr uint32_t OPF_WIDE = 1u << 14;  // op flag: 128 x 128 GEMM tiles
+// op flag, wave tiles without index tables: A's k index is the lowest bits
+// of A (k contiguous) and A's offsets are even, so a lane reads four
+// consecutive k of a row with two 16-byte loads
+constexpr uint32_t OPF_AVEC = 1u << 15;
 constexpr uint32_t IX_TABLE = 0x80000000u;
 
 struct DevOp {

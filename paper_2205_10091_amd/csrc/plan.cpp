@@ -1161,6 +1161,12 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         op.tiles_m = std::max(1u, op.M / (16 * bi));
         op.tiles_n = std::max(1u, op.N / (16 * bj));
         op.flags |= ((bi - 1) << 12) | ((bj - 1) << 13);
+        {
+          const uint32_t lk2 = __builtin_ctz(op.K);
+          const bool tabs = ((op.a_m | op.a_k | op.b_k | op.b_n | op.c_m | op.c_n) & IX_TABLE) != 0;
+          if (!tabs && op.K >= 16 && op.a_k == lk2 && op.a % 2 == 0 && op.a_bs % 2 == 0)
+            op.flags |= OPF_AVEC;
+        }
         wv.push_back(op);
         if (!pend[k].bwd) ++n_gemm_nodes;
       } else if (!term_mode && op.rows >= SMALL_WAVE_MIN_ROWS &&
