@@ -144,6 +144,33 @@ def test_batched_sweep_matches_oracle_and_single_calls():
         assert np.max(np.abs(g1[0] - g[b])) < 1e-6
 
 
+@pytest.mark.parametrize("B", [100, 200])
+def test_batched_sweep_ragged_rows(B):
+    """Batch sizes that are not a multiple of the 64 rows a row-tile
+    workgroup stages (100 = 64 + 36, 200 = 3 x 64 + 8), so the last row
+    tile of every small batched node is partial and the masked wave tiles
+    run over a ragged row count: every row against a batch-1 plan called
+    row by row, sampled rows (first, last, the first of the partial tile)
+    against the oracle.  As in the full-size test below, the differences
+    between the two plans are divided by sum_j |a_j| (|dE| <= sum_j |a_j|
+    |dT_j| for E summed in FP64 from complex64 terms T_j)."""
+    circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=12, layers=4)
+    plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=4, seed=1)
+    e, g = plan.contract_grad(device_params(P, B))
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
+    for b in (0, 64, B - 1):
+        e_ref, g_ref = sv.energy_grad(circ, P[b], obs)
+        assert rel_err(e[b], e_ref, 1.0) < TOL_C64
+        assert_grad(g[b], g_ref, TOL_C64)
+    single = api.compile(circ, obs, want_grad=True, n_trials=4, seed=1)
+    pd = device_params(P, B)
+    scale = float(np.sum(np.abs(obs.weights)))
+    for b in range(B):
+        e1, g1 = single.contract_grad(pd[b].contiguous())
+        assert abs(e1[0] - e[b]) / scale < 1e-6, b
+        assert np.max(np.abs(g1[0] - g[b])) / scale < 1e-6, b
+
+
 def test_batched_sweep_full_size_every_row():
     """1024 parameter vectors in one launch: every row's energy and every
     gradient component against a batch-1 plan of the same network called
