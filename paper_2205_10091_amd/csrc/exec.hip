@@ -625,6 +625,11 @@ __global__ void __launch_bounds__(256) k_reduce_g(LevelArgs a) {
 // LDS, k in increasing order, and stores them.
 __global__ void __launch_bounds__(256) k_rowtile(LevelArgs a) {
   __shared__ float2 buf[ROW_TILE_LDS];
+  // A's and B's offsets of each k (K <= ROW_TILE_LDS / 2, as a row of both
+  // operands fits the staging buffer), decoded once per workgroup: the sum
+  // over k runs the same k on every lane, so decoding it there kept the
+  // scalar unit busy for every output
+  __shared__ uint32_t koff[2][ROW_TILE_LDS / 2];
   const uint64_t b = blockIdx.x;
   const LevelSeg& S = a.seg[find_seg(a, b, [](const LevelSeg& s) { return s.rt_start; })];
   const uint64_t lb = b - S.rt_start;
@@ -659,6 +664,10 @@ __global__ void __launch_bounds__(256) k_rowtile(LevelArgs a) {
     const uint32_t e = t + q * 256;
     if (e < ntot) buf[e] = v[q];
   }
+  for (uint32_t k = t; k < op.K; k += 256) {
+    koff[0][k] = ix(S.tab, op.a_k, k);
+    koff[1][k] = ix(S.tab, op.b_k, k);
+  }
   __syncthreads();
   const uint32_t lmn = __builtin_ctz(MN), ln = __builtin_ctz(op.N);
   for (uint32_t o = t; o < nr * MN; o += 256) {
@@ -668,7 +677,7 @@ __global__ void __launch_bounds__(256) k_rowtile(LevelArgs a) {
     const float2* Br = buf + ra * MK + (op.b_bs ? rr * KN : 0) + ix(S.tab, op.b_n, n);
     float re = 0.f, im = 0.f;
     for (uint32_t k = 0; k < op.K; ++k) {
-      const float2 x = Ar[ix(S.tab, op.a_k, k)], w = Br[ix(S.tab, op.b_k, k)];
+      const float2 x = Ar[koff[0][k]], w = Br[koff[1][k]];
       re += x.x * w.x - x.y * w.y;
       im += x.x * w.y + x.y * w.x;
     }

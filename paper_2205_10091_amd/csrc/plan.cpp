@@ -1710,6 +1710,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
           const uint64_t rpb = op.tiles_m;
           if (rpb < 1 || rpb > ROW_TILE_ROWS || (rpb & (rpb - 1)) || op.rows < 1 ||
               rpb * ((uint64_t)op.M * op.K + (uint64_t)op.K * op.N) > ROW_TILE_LDS ||
+              op.K > ROW_TILE_LDS / 2 ||
               op.tiles_n != (op.rows + rpb - 1) / rpb || op.ksplit != 1 ||
               op.work0 != (o == L.rbegin ? 0 : plan.ops[o - 1].work0 + plan.ops[o - 1].tiles_n))
             fail(TC_ERR_INVALID_ARG, "internal: row-tile op");
