@@ -195,14 +195,16 @@ struct Arena {
 };
 
 // Gather layout of a node: k-split S = 2^ls lanes per output group (long
-// sums of small nodes, while the node stays within `lanes` lanes), else
-// V = 2^lv outputs per thread along n.  Level launches spread a node over
-// the whole chip (65536 lanes); term mode over one 1024-thread workgroup.
+// sums of small nodes, while a lane keeps more than min_steps k-steps and
+// the node stays within `lanes` lanes; further while a lane would hold more
+// than 256), else V = 2^lv outputs per thread along n.  Level launches
+// spread a node over the whole chip (65536 lanes); term mode over one
+// 1024-thread workgroup.
 void gather_shape(uint32_t M, uint32_t N, uint32_t K, uint32_t rows, uint64_t lanes,
-                  uint32_t& ls, uint32_t& lv) {
+                  uint32_t& ls, uint32_t& lv, uint32_t min_steps = 4) {
   const uint64_t outs = (uint64_t)rows * M * N;
   ls = 0;
-  while (ls < 6 && (K >> ls) > 4 && (outs << (ls + 1)) <= lanes) ++ls;
+  while (ls < 6 && (K >> ls) > min_steps && (outs << (ls + 1)) <= lanes) ++ls;
   while (ls < 6 && (K >> ls) > 256) ++ls;
   lv = 0;
   if (ls == 0) lv = N >= 4 ? 2 : (N == 2 ? 1 : 0);
@@ -1046,6 +1048,24 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
            (!tstep || pend[j].term == pend[i].term))
       ++j;
     const bool term_mode = tstep;
+    // a level with more gather items than two chip-fulls (at 4 k-steps per
+    // lane) splits its sums half as far: fewer, longer items in one pass
+    uint32_t min_steps = 4;
+    if (!term_mode) {
+      uint64_t li = 0;
+      for (size_t k = i; k < j; ++k) {
+        const PT& A = T[pend[k].a];
+        const PT& Bt = T[pend[k].b];
+        mark(pb, Bt.legs, true);
+        uint32_t sh = 0;
+        for (int32_t x : A.legs) sh += pb[x] >= 0;
+        mark(pb, Bt.legs, false);
+        const uint32_t K = 1u << sh, M = 1u << (A.legs.size() - sh), N = 1u << (Bt.legs.size() - sh);
+        const uint32_t rows = (A.batched || Bt.batched) && B > 1 ? (uint32_t)B : 1u;
+        li += gather_items(M, N, K, rows, LEVEL_LANES);
+      }
+      if (li > LEVEL_SHORT_SPLIT_ITEMS) min_steps = 8;
+    }
     std::vector<DevOp> gc, gm, wv, wd, rt;
     std::vector<DevROp> gcr;  // resident plans: gc's nodes as resident records
     double lf = 0, lb = 0, gf = 0, gb = 0, wf = 0, wb = 0, rtf = 0, rtby = 0, sgf = 0, sgby = 0;
@@ -1190,7 +1210,7 @@ void build_plan(Plan& plan, const Network& net, const Path& path) {
         // gather: split long sums over up to 64 lanes while the op is small,
         // else 4 outputs per thread along n
         uint32_t ls, lv;
-        gather_shape(op.M, op.N, op.K, op.rows, term_mode ? TERM_LANES : LEVEL_LANES, ls, lv);
+        gather_shape(op.M, op.N, op.K, op.rows, term_mode ? TERM_LANES : LEVEL_LANES, ls, lv, min_steps);
         op.flags |= (ls << 4) | (lv << 8);
         // a sum too long even for 64 lanes (few outputs, huge K: a final
         // inner product) is cut into slices reduced afterwards, as split-K
