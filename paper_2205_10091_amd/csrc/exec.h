@@ -28,8 +28,6 @@ struct DeviceState {
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   int n_cu = 256;
-  hipStream_t side = nullptr;               // GEMM half of forked level launches
-  hipEvent_t fork_start = nullptr, fork_done = nullptr;
 };
 
 // One plan's launch, located in that plan's workspace.
@@ -43,14 +41,6 @@ struct SegRef {
 // Largest number of plans one merged launch carries (kernel-argument space).
 constexpr int MAX_SEG = 24;
 
-// A level launch with both GEMM tiles and gather work may fork: its GEMM
-// kernel runs on `side` (after `start` is recorded on the main stream) and
-// the main stream waits for `done` before the next launch.
-struct Fork {
-  hipStream_t side;
-  hipEvent_t start, done;
-};
-
 // Launch parts of a level: GEMM tiles (64 x 64 and wave tiles), gather
 // items, 128 x 128 tiles with their split pass, row tiles, split sums with
 // their reduction.
@@ -58,11 +48,11 @@ constexpr int PART_GEMM = 1, PART_GATHER = 2, PART_WIDE = 4, PART_ROWTILE = 8, P
 constexpr int PART_ALL = PART_GEMM | PART_GATHER | PART_WIDE | PART_ROWTILE | PART_GSPLIT;
 
 // Enqueue one launch of `kind` covering all `segs` (at most MAX_SEG, all of
-// that kind) on `stream`; for levels, only the kernels named in `parts`,
-// forked as above when `fork` is given.
+// that kind) on `stream`; for levels, only the kernels named in `parts`
+// (GEMM kernels first, then the gather kernels, in stream order: a second
+// stream for the GEMM half measured slower once captured in a graph).
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
-                     int precision, const Fork* fork = nullptr,
-                     int parts = PART_ALL);
+                     int precision, int parts = PART_ALL);
 
 // Asynchronous upload of a plan's tables and seeds into a workspace.
 void upload_tables(const Plan& P, char* ws, const WorkspaceLayout& lay, hipStream_t stream);

@@ -1227,7 +1227,7 @@ uint32_t resident_lds_elems(int device) {
 }
 
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
-                     int precision, const Fork* fork, int parts) {
+                     int precision, int parts) {
   if (nseg <= 0) return;
   if (nseg > MAX_SEG) fail(TC_ERR_INVALID_ARG, "internal: too many segments");
   switch (kind) {
@@ -1367,18 +1367,8 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
           launch(k_reduce_g, dim3((unsigned)a.gsplit_units), dim3(256), st, a);
         }
       };
-      if ((gmb || whb) && (gcb || gsb || rtb) && fork) {
-        // GEMM tiles on the side stream, concurrent with the gather kernel
-        HIP_CHECK(hipEventRecord(fork->start, stream));
-        HIP_CHECK(hipStreamWaitEvent(fork->side, fork->start, 0));
-        gemm(fork->side);
-        gather(stream);
-        HIP_CHECK(hipEventRecord(fork->done, fork->side));
-        HIP_CHECK(hipStreamWaitEvent(stream, fork->done, 0));
-      } else {
-        if (gmb || whb) gemm(stream);
-        if (gcb || gsb || rtb) gather(stream);
-      }
+      if (gmb || whb) gemm(stream);
+      if (gcb || gsb || rtb) gather(stream);
       break;
     }
     case L_TERM: {
@@ -1482,10 +1472,9 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
 
 static void enqueue(const Plan& P, DeviceState& D, const std::vector<const Launch*>& seq,
                     int parts = PART_ALL) {
-  const Fork fork{D.side, D.fork_start, D.fork_done};
   for (const Launch* x : seq) {
     SegRef s{&P, D.ws, &D.lay, x};
-    launch_segments(x->kind, &s, 1, D.stream, D.n_cu, P.precision, &fork, parts);
+    launch_segments(x->kind, &s, 1, D.stream, D.n_cu, P.precision, parts);
   }
 }
 
@@ -1527,11 +1516,7 @@ static void release(DeviceState* D) {
     if (D->exec[i]) (void)hipGraphExecDestroy(D->exec[i]);
     if (D->graph[i]) (void)hipGraphDestroy(D->graph[i]);
   }
-  if (D->side) (void)hipStreamSynchronize(D->side);
   if (D->ws_owned && D->ws) (void)hipFree(D->ws);
-  if (D->fork_start) (void)hipEventDestroy(D->fork_start);
-  if (D->fork_done) (void)hipEventDestroy(D->fork_done);
-  if (D->side) (void)hipStreamDestroy(D->side);
   if (D->own_stream && D->stream) (void)hipStreamDestroy(D->stream);
   delete D;
 }
@@ -1564,9 +1549,6 @@ void bind_plan(Plan& P, void* workspace, uint64_t bytes) {
       HIP_CHECK(hipStreamCreateWithFlags(&D->stream, hipStreamNonBlocking));
       D->own_stream = true;
     }
-    HIP_CHECK(hipStreamCreateWithFlags(&D->side, hipStreamNonBlocking));
-    HIP_CHECK(hipEventCreateWithFlags(&D->fork_start, hipEventDisableTiming));
-    HIP_CHECK(hipEventCreateWithFlags(&D->fork_done, hipEventDisableTiming));
     D->lay = workspace_layout(P);
     if (workspace) {
       if (bytes < D->lay.total)
