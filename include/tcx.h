@@ -469,6 +469,12 @@ tc_status tc_plan_bind(tc_plan* plan, void* workspace, uint64_t bytes);
  * *_device variants write to DEVICE buffers of the same shapes (out_dev:
  * 2*B doubles; value_dev: B doubles; grad_dev: B*n_params doubles) and do
  * not synchronise; the caller orders later work on the plan's stream.
+ * tc_contract_grad_device with both outputs (and n_params > 0) reads params
+ * and writes value_dev and grad_dev in place: the plan keeps one extra
+ * graph captured for the last (params, value_dev, grad_dev) triple and
+ * captures it again when a call passes other pointers (so a loop over the
+ * same buffers pays no staging copies); the three buffers must not overlap
+ * each other.
  */
 tc_status tc_contract(tc_plan* plan, const float* params, double* out);
 tc_status tc_contract_grad(tc_plan* plan, const float* params, double* value,

@@ -27,6 +27,12 @@ struct DeviceState {
   WorkspaceLayout lay{};
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // the gradient graph captured for one set of caller buffers (parameters
+  // read and E, dE/dtheta written in place), kept while the caller passes
+  // the same three pointers
+  hipGraph_t dgraph = nullptr;
+  hipGraphExec_t dexec = nullptr;
+  const void* dkey[3] = {nullptr, nullptr, nullptr};
   int n_cu = 256;
 };
 
@@ -36,6 +42,12 @@ struct SegRef {
   const char* ws;               // workspace base of this plan
   const WorkspaceLayout* lay;
   const Launch* launch;
+  // caller buffers used in place of the workspace's own (null: the
+  // workspace): the parameter vectors (batch x n_params floats), E's real
+  // parts (batch doubles), the gradient (batch x n_params doubles)
+  const float* params = nullptr;
+  double* value_re = nullptr;
+  double* grad = nullptr;
 };
 
 // Largest number of plans one merged launch carries (kernel-argument space).

@@ -111,6 +111,7 @@ struct RootSeg {
   const DevRoot* roots;
   const float2* arena;
   double* value;
+  double* value_re;  // also E's real part here, one double per row (or null)
   uint64_t start;  // first wavefront (batch row) of this segment
   uint32_t n_terms;
   uint32_t batch;
@@ -1074,6 +1075,7 @@ __global__ void __launch_bounds__(256) k_root(RootArgs a) {
   if (lane == 0) {
     S.value[2 * b] = re;
     S.value[2 * b + 1] = im;
+    if (S.value_re) S.value_re[b] = re;
   }
 }
 
@@ -1243,7 +1245,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
                           ? (const uint32_t*)(s.ws + L.item_op) + s.launch->item_begin
                           : nullptr;
         g.ftab = (const float*)(s.ws + L.ftab);
-        g.params = (const float*)(s.ws + L.params);
+        g.params = s.params ? s.params : (const float*)(s.ws + L.params);
         g.arena = (float2*)(s.ws + L.arena);
         g.n = (uint32_t)s.plan->leaves.size();
         g.param_stride = s.plan->param_stride();
@@ -1389,7 +1391,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
                         : nullptr;
       a.leaves = (const DevLeaf*)(s.ws + L.leaves);
       a.ftab = (const float*)(s.ws + L.ftab);
-      a.params = (const float*)(s.ws + L.params);
+      a.params = s.params ? s.params : (const float*)(s.ws + L.params);
       a.arena = (float2*)(s.ws + L.arena);
       a.param_stride = P.param_stride();
       a.with_leaves = s.launch->with_leaves ? 1 : 0;
@@ -1412,6 +1414,7 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.roots = (const DevRoot*)(s.ws + L.roots);
         g.arena = (const float2*)(s.ws + L.arena);
         g.value = (double*)(s.ws + L.value);
+        g.value_re = s.value_re;
         g.n_terms = (uint32_t)s.plan->roots.size();
         g.batch = (uint32_t)s.plan->batch;
         g.start = w;
@@ -1433,9 +1436,9 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
         g.uses = (const DevGradUse*)(s.ws + L.uses);
         g.slot_begin = (const uint32_t*)(s.ws + L.slot_begin);
         g.leaves = (const DevLeaf*)(s.ws + L.leaves);
-        g.params = (const float*)(s.ws + L.params);
+        g.params = s.params ? s.params : (const float*)(s.ws + L.params);
         g.arena = (const float2*)(s.ws + L.arena);
-        g.grad = (double*)(s.ws + L.grad);
+        g.grad = s.grad ? s.grad : (double*)(s.ws + L.grad);
         g.n_params = s.plan->n_params;
         g.param_stride = s.plan->param_stride();
         g.cplx = s.plan->qgt ? 1 : 0;
@@ -1471,9 +1474,10 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
 }
 
 static void enqueue(const Plan& P, DeviceState& D, const std::vector<const Launch*>& seq,
-                    int parts = PART_ALL) {
+                    int parts = PART_ALL, const float* params = nullptr,
+                    double* value_re = nullptr, double* grad = nullptr) {
   for (const Launch* x : seq) {
-    SegRef s{&P, D.ws, &D.lay, x};
+    SegRef s{&P, D.ws, &D.lay, x, params, value_re, grad};
     launch_segments(x->kind, &s, 1, D.stream, D.n_cu, P.precision, parts);
   }
 }
@@ -1516,6 +1520,8 @@ static void release(DeviceState* D) {
     if (D->exec[i]) (void)hipGraphExecDestroy(D->exec[i]);
     if (D->graph[i]) (void)hipGraphDestroy(D->graph[i]);
   }
+  if (D->dexec) (void)hipGraphExecDestroy(D->dexec);
+  if (D->dgraph) (void)hipGraphDestroy(D->dgraph);
   if (D->ws_owned && D->ws) (void)hipFree(D->ws);
   if (D->own_stream && D->stream) (void)hipStreamDestroy(D->stream);
   delete D;
@@ -1534,6 +1540,35 @@ static void capture(const Plan& P, DeviceState& D, int which) {
   }
   HIP_CHECK(hipStreamEndCapture(D.stream, &D.graph[which]));
   HIP_CHECK(hipGraphInstantiate(&D.exec[which], D.graph[which], nullptr, nullptr, 0));
+}
+
+// The gradient graph for caller buffers: captured again whenever the three
+// pointers differ from the last call's.
+static void run_direct(const Plan& P, DeviceState& D, const float* params, double* value,
+                       double* grad) {
+  if (!D.dexec || D.dkey[0] != params || D.dkey[1] != value || D.dkey[2] != grad) {
+    if (D.dexec) HIP_CHECK(hipGraphExecDestroy(D.dexec));
+    if (D.dgraph) HIP_CHECK(hipGraphDestroy(D.dgraph));
+    D.dexec = nullptr;
+    D.dgraph = nullptr;
+    D.dkey[0] = D.dkey[1] = D.dkey[2] = nullptr;
+    const std::vector<const Launch*> seq = launch_order(P, true);
+    HIP_CHECK(hipStreamBeginCapture(D.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue(P, D, seq, PART_ALL, params, value, grad);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(D.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIP_CHECK(hipStreamEndCapture(D.stream, &D.dgraph));
+    HIP_CHECK(hipGraphInstantiate(&D.dexec, D.dgraph, nullptr, nullptr, 0));
+    D.dkey[0] = params;
+    D.dkey[1] = value;
+    D.dkey[2] = grad;
+  }
+  HIP_CHECK(hipGraphLaunch(D.dexec, D.stream));
 }
 
 void bind_plan(Plan& P, void* workspace, uint64_t bytes) {
@@ -1613,6 +1648,15 @@ void contract_grad(Plan& P, const float* params, double* value, double* grad,
   if (!P.want_grad) fail(TC_ERR_STATE, "plan was compiled without want_grad");
   if (P.qgt) fail(TC_ERR_STATE, "a geometric tensor plan runs through tc_contract_qgt");
   BusyGuard g(P.busy);
+  if (device_out && value && grad && params && P.n_params > 0) {
+    // caller buffers on the device: the graph reads and writes them in
+    // place (no staging copies around it)
+    if (!P.dev) bind_plan(P, nullptr, 0);
+    DeviceState& D = *P.dev;
+    HIP_CHECK(hipSetDevice(D.device));
+    run_direct(P, D, params, value, grad);
+    return;
+  }
   stage_params(P, params);
   DeviceState& D = *P.dev;
   HIP_CHECK(hipGraphLaunch(D.exec[1], D.stream));

@@ -98,6 +98,38 @@ def test_vqe_chain_in_the_benchmark_configuration():
     assert_grad(g_dev.cpu().numpy(), g_ref, TOL_C64, "benchmark plan")
 
 
+def test_device_outputs_in_place_match_staged_outputs():
+    """tc_contract_grad_device reads the parameters and writes E and the
+    gradient in place through a graph captured for those three buffers:
+    the same kernels as the staged path (host outputs), so the results are
+    bit-identical, on a second call with the same buffers holding new
+    parameters, and after a switch to other output buffers (a new capture)."""
+    import torch
+    B = 8
+    circ, P, obs = tcgen.workload_batched_vqe(batch=B, n=12, layers=4)
+    plan = api.compile(circ, obs, batch=B, want_grad=True, n_trials=4, seed=1)
+    npar = circ.n_params
+    rng = np.random.default_rng(5)
+    P2 = (P + rng.normal(0, 0.3, P.shape)).astype(np.float32)
+    pd = device_params(P, B)
+    e_dev = torch.empty(B, dtype=torch.float64, device="cuda")
+    g_dev = torch.empty(B * npar, dtype=torch.float64, device="cuda")
+    for params in (P, P2):
+        pd.copy_(device_params(params, B))
+        e_h, g_h = plan.contract_grad(device_params(params, B))
+        plan.contract_grad_device(pd, e_dev, g_dev)
+        assert np.array_equal(e_dev.cpu().numpy(), e_h)
+        assert np.array_equal(g_dev.cpu().numpy().reshape(B, npar), g_h.reshape(B, npar))
+    e2 = torch.empty(B, dtype=torch.float64, device="cuda")
+    g2 = torch.empty(B * npar, dtype=torch.float64, device="cuda")
+    plan.contract_grad_device(pd, e2, g2)
+    assert np.array_equal(e2.cpu().numpy(), e_dev.cpu().numpy())
+    assert np.array_equal(g2.cpu().numpy(), g_dev.cpu().numpy())
+    e_ref, g_ref = sv.energy_grad(circ, P2[3], obs)
+    assert rel_err(e2[3].item(), e_ref, 1.0) < TOL_C64
+    assert_grad(g2.cpu().numpy().reshape(B, npar)[3], g_ref, TOL_C64)
+
+
 def test_vqe_gradient_vs_parameter_shift_and_fd_on_gpu():
     """The GPU gradient against the GPU's own energies at shifted angles:
     the exact two-point shift rule and central differences (h = 1e-3)."""
