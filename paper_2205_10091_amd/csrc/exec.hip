@@ -1050,9 +1050,10 @@ __global__ void __launch_bounds__(1024) k_term_res(TermArgs a) {
 // E[b] = sum_j alpha_j T_j[b] in FP64: one wavefront per batch row, lane l
 // takes terms l, l + 64, ...; the 64 partial sums combine in a fixed
 // butterfly order (deterministic).
-__global__ void __launch_bounds__(256) k_root(RootArgs a) {
+// Root rows for block `blk` of the root part of a launch.
+__device__ __forceinline__ void root_rows(const RootArgs& a, uint64_t blk) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wv = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t wv = (blk * blockDim.x + threadIdx.x) >> 6;
   if (wv >= a.total) return;  // whole wavefronts leave together
   const RootSeg& S = a.seg[find_seg(a, wv, [](const RootSeg& s) { return s.start; })];
   const uint64_t b = wv - S.start;
@@ -1079,14 +1080,17 @@ __global__ void __launch_bounds__(256) k_root(RootArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_root(RootArgs a) { root_rows(a, blockIdx.x); }
+
 // grad[b][slot] = Re sum_{uses of slot} sum_e adj[e] dleaf[e]/dangle in FP64:
 // one wavefront per (row, slot), lanes over the slot's uses, fixed-order
 // butterfly combination.
-__global__ void __launch_bounds__(256) k_grad(GradArgs a) {
+// Gradient waves for block `blk` of `nblk` blocks of the gradient part of
+// a launch (grid-stride over the (row, slot) waves).
+__device__ __forceinline__ void grad_waves(const GradArgs& a, uint64_t blk, uint64_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t wv = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wv < a.total;
-       wv += waves) {
+  const uint64_t waves = (nblk * blockDim.x) >> 6;
+  for (uint64_t wv = (blk * blockDim.x + threadIdx.x) >> 6; wv < a.total; wv += waves) {
     const GradSeg& S = a.seg[find_seg(a, wv, [](const GradSeg& s) { return s.start; })];
     const uint64_t w = wv - S.start;
     const uint64_t b = w / (uint32_t)S.n_params;
@@ -1120,6 +1124,19 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs a) {
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_grad(GradArgs a) { grad_waves(a, blockIdx.x, gridDim.x); }
+
+// The last two launches of a gradient call in one: blocks [0, root_blocks)
+// sum the roots, the others the gradient (independent: the root sum reads
+// the terms' root values and writes E, the gradient sum reads adjoints and
+// parameters and writes dE/dtheta).
+__global__ void __launch_bounds__(256) k_root_grad(RootArgs r, GradArgs g, uint32_t root_blocks) {
+  if (blockIdx.x < root_blocks)
+    root_rows(r, blockIdx.x);
+  else
+    grad_waves(g, blockIdx.x - root_blocks, gridDim.x - root_blocks);
 }
 
 // One wavefront per (i, j): lanes over the rows of slot j (sums and v_j)
@@ -1226,6 +1243,71 @@ uint32_t resident_lds_elems(int device) {
     return 0;
   }
   return elems;
+}
+
+// Arguments of the root sum over `segs` (one segment per plan).
+static RootArgs root_args(const SegRef* segs, int nseg) {
+  RootArgs a{};
+  uint64_t w = 0;
+  for (int i = 0; i < nseg; ++i) {
+    const SegRef& s = segs[i];
+    const WorkspaceLayout& L = *s.lay;
+    RootSeg& g = a.seg[i];
+    g.roots = (const DevRoot*)(s.ws + L.roots);
+    g.arena = (const float2*)(s.ws + L.arena);
+    g.value = (double*)(s.ws + L.value);
+    g.value_re = s.value_re;
+    g.n_terms = (uint32_t)s.plan->roots.size();
+    g.batch = (uint32_t)s.plan->batch;
+    g.start = w;
+    w += (uint64_t)s.plan->batch;
+  }
+  a.nseg = (uint32_t)nseg;
+  a.total = w;
+  return a;
+}
+
+// Arguments of the gradient sum over `segs`.
+static GradArgs grad_args(const SegRef* segs, int nseg) {
+  GradArgs a{};
+  uint64_t w = 0;
+  for (int i = 0; i < nseg; ++i) {
+    const SegRef& s = segs[i];
+    const WorkspaceLayout& L = *s.lay;
+    GradSeg& g = a.seg[i];
+    g.uses = (const DevGradUse*)(s.ws + L.uses);
+    g.slot_begin = (const uint32_t*)(s.ws + L.slot_begin);
+    g.leaves = (const DevLeaf*)(s.ws + L.leaves);
+    g.params = s.params ? s.params : (const float*)(s.ws + L.params);
+    g.arena = (const float2*)(s.ws + L.arena);
+    g.grad = s.grad ? s.grad : (double*)(s.ws + L.grad);
+    g.n_params = s.plan->n_params;
+    g.param_stride = s.plan->param_stride();
+    g.cplx = s.plan->qgt ? 1 : 0;
+    g.start = w;
+    w += s.launch->work;
+  }
+  a.nseg = (uint32_t)nseg;
+  a.total = w;
+  return a;
+}
+
+// The root sum of plan segment `r` and the gradient sum of `g` as one
+// kernel (k_root_grad), or the root sum alone when there is no gradient
+// work.
+static_assert(sizeof(RootArgs) + sizeof(GradArgs) + 8 <= 4096,
+              "k_root_grad's arguments fit the kernel argument segment");
+static void launch_root_grad(const SegRef& r, const SegRef& g, hipStream_t stream, int n_cu) {
+  const RootArgs ra = root_args(&r, 1);
+  const GradArgs ga = grad_args(&g, 1);
+  const unsigned rb = (unsigned)((ra.total * 64 + 255) / 256);
+  if (ga.total == 0) {
+    launch(k_root, dim3(rb), dim3(256), stream, ra);
+  } else {
+    const unsigned gb = grid_for(ga.total * 64, 256, n_cu);
+    launch(k_root_grad, dim3(rb + gb), dim3(256), stream, ra, ga, (uint32_t)rb);
+  }
+  HIP_CHECK(hipGetLastError());
 }
 
 void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream, int n_cu,
@@ -1405,50 +1487,14 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
       break;
     }
     case L_ROOT: {
-      RootArgs a{};
-      uint64_t w = 0;
-      for (int i = 0; i < nseg; ++i) {
-        const SegRef& s = segs[i];
-        const WorkspaceLayout& L = *s.lay;
-        RootSeg& g = a.seg[i];
-        g.roots = (const DevRoot*)(s.ws + L.roots);
-        g.arena = (const float2*)(s.ws + L.arena);
-        g.value = (double*)(s.ws + L.value);
-        g.value_re = s.value_re;
-        g.n_terms = (uint32_t)s.plan->roots.size();
-        g.batch = (uint32_t)s.plan->batch;
-        g.start = w;
-        w += (uint64_t)s.plan->batch;
-      }
-      a.nseg = (uint32_t)nseg;
-      a.total = w;
-      launch(k_root, dim3((unsigned)((w * 64 + 255) / 256)), dim3(256), stream,
-                         a);
+      const RootArgs a = root_args(segs, nseg);
+      launch(k_root, dim3((unsigned)((a.total * 64 + 255) / 256)), dim3(256), stream, a);
       break;
     }
     case L_GRAD: {
-      GradArgs a{};
-      uint64_t w = 0;
-      for (int i = 0; i < nseg; ++i) {
-        const SegRef& s = segs[i];
-        const WorkspaceLayout& L = *s.lay;
-        GradSeg& g = a.seg[i];
-        g.uses = (const DevGradUse*)(s.ws + L.uses);
-        g.slot_begin = (const uint32_t*)(s.ws + L.slot_begin);
-        g.leaves = (const DevLeaf*)(s.ws + L.leaves);
-        g.params = s.params ? s.params : (const float*)(s.ws + L.params);
-        g.arena = (const float2*)(s.ws + L.arena);
-        g.grad = s.grad ? s.grad : (double*)(s.ws + L.grad);
-        g.n_params = s.plan->n_params;
-        g.param_stride = s.plan->param_stride();
-        g.cplx = s.plan->qgt ? 1 : 0;
-        g.start = w;
-        w += s.launch->work;
-      }
-      a.nseg = (uint32_t)nseg;
-      a.total = w;
-      if (w == 0) return;
-      launch(k_grad, dim3(grid_for(w * 64, 256, n_cu)), dim3(256), stream, a);
+      const GradArgs a = grad_args(segs, nseg);
+      if (a.total == 0) return;
+      launch(k_grad, dim3(grid_for(a.total * 64, 256, n_cu)), dim3(256), stream, a);
       break;
     }
     case L_QGT: {
@@ -1476,8 +1522,16 @@ void launch_segments(int kind, const SegRef* segs, int nseg, hipStream_t stream,
 static void enqueue(const Plan& P, DeviceState& D, const std::vector<const Launch*>& seq,
                     int parts = PART_ALL, const float* params = nullptr,
                     double* value_re = nullptr, double* grad = nullptr) {
-  for (const Launch* x : seq) {
+  for (size_t i = 0; i < seq.size(); ++i) {
+    const Launch* x = seq[i];
     SegRef s{&P, D.ws, &D.lay, x, params, value_re, grad};
+    if (x->kind == L_ROOT && i + 2 == seq.size() && seq[i + 1]->kind == L_GRAD) {
+      // a gradient call ends with the root sum and the gradient sum, which
+      // do not depend on each other: one launch
+      const SegRef sg{&P, D.ws, &D.lay, seq[i + 1], params, value_re, grad};
+      launch_root_grad(s, sg, D.stream, D.n_cu);
+      break;
+    }
     launch_segments(x->kind, &s, 1, D.stream, D.n_cu, P.precision, parts);
   }
 }
