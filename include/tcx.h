@@ -474,7 +474,8 @@ tc_status tc_plan_bind(tc_plan* plan, void* workspace, uint64_t bytes);
  * graph captured for the last (params, value_dev, grad_dev) triple and
  * captures it again when a call passes other pointers (so a loop over the
  * same buffers pays no staging copies); the three buffers must not overlap
- * each other.
+ * each other.  While the plan's stream is being captured by the caller, the
+ * call takes the staging path instead (copies around the plan's graph).
  */
 tc_status tc_contract(tc_plan* plan, const float* params, double* out);
 tc_status tc_contract_grad(tc_plan* plan, const float* params, double* value,

@@ -1704,12 +1704,17 @@ void contract_grad(Plan& P, const float* params, double* value, double* grad,
   BusyGuard g(P.busy);
   if (device_out && value && grad && params && P.n_params > 0) {
     // caller buffers on the device: the graph reads and writes them in
-    // place (no staging copies around it)
+    // place (no staging copies around it), unless the caller is capturing
+    // the plan's stream (a capture cannot be started inside another)
     if (!P.dev) bind_plan(P, nullptr, 0);
     DeviceState& D = *P.dev;
     HIP_CHECK(hipSetDevice(D.device));
-    run_direct(P, D, params, value, grad);
-    return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_CHECK(hipStreamIsCapturing(D.stream, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+      run_direct(P, D, params, value, grad);
+      return;
+    }
   }
   stage_params(P, params);
   DeviceState& D = *P.dev;
