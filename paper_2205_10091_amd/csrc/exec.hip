@@ -1601,6 +1601,8 @@ static void capture(const Plan& P, DeviceState& D, int which) {
 static void run_direct(const Plan& P, DeviceState& D, const float* params, double* value,
                        double* grad) {
   if (!D.dexec || D.dkey[0] != params || D.dkey[1] != value || D.dkey[2] != grad) {
+    // the previous graph may still run on the stream: let it finish first
+    if (D.dexec) HIP_CHECK(hipStreamSynchronize(D.stream));
     if (D.dexec) HIP_CHECK(hipGraphExecDestroy(D.dexec));
     if (D.dgraph) HIP_CHECK(hipGraphDestroy(D.dgraph));
     D.dexec = nullptr;
